@@ -1,0 +1,367 @@
+"""Seeded synthetic workloads for the multi-compartment cell stepper.
+
+This module only draws random model descriptions: morphologies (branch
+topology, lengths, diameters), mechanism placement and densities, synapse
+placement, network connections, external input events and current clamps.
+It holds none of the method's arithmetic (no discretisation, no currents, no
+solves); both the CPU oracle and the GPU library consume its output and do all
+of that themselves, independently.
+
+A model is a dict of flat numpy column arrays:
+
+cells      cell_branch_begin i64, cell_n_branch i32, soma_area f64,
+           soma_mech u32, soma_gna/soma_gk/soma_gl/soma_gpas/soma_epas f64,
+           cm f64 (uF/cm^2), Ra f64 (ohm cm)
+branches   br_parent i32 (-1 = soma), br_n_cv i32, br_length f64 (um),
+           br_diam f64 (um), br_mech u32, br_gna/br_gk/br_gl/br_gpas f64
+           (S/cm^2), br_epas f64 (mV)
+synapses   syn_cell i32, syn_branch i32 (-1 = soma), syn_cv i32 (0-based CV
+           along the branch, proximal first), syn_tau f64 (ms), syn_e f64 (mV)
+conns      con_src u32, con_dst u32, con_syn u32 (global synapse index),
+           con_delay i32 (steps), con_w f64 (uS)
+events     ev_syn u32, ev_step i64, ev_w f64 (uS)
+iclamps    ic_cell i32, ic_branch i32, ic_cv i32, ic_on i64, ic_off i64
+           (active for step_on <= n < step_off), ic_amp f64 (nA, positive
+           depolarises)
+scalars    dt (ms), threshold (mV), v_init (mV), n_steps
+
+Every cell draws from its own generator, SeedSequence(entropy, spawn_key=(i,)),
+so any subset of cells can be regenerated alone and identically (used to build
+the light-cone sub-models the full-size parity checks run on the CPU).
+
+Units and constants follow the textbook Hodgkin-Huxley squid-axon values and
+the passive/synapse readings recorded for this build: hh gNa 0.12, gK 0.036,
+gL 0.0003 S/cm^2; pas 0.001 S/cm^2 at -65 mV; expsyn reversal 0 mV.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+MECH_HH = 1
+MECH_PAS = 2
+
+SEED_BASE = 1901_07454
+DT = 0.025
+THRESHOLD = -10.0
+V_INIT = -65.0
+CM = 1.0
+RA = 100.0
+SOMA_AREA = 500.0
+HH_DEF = (0.12, 0.036, 0.0003)
+PAS_G = 0.001
+PAS_E = -65.0
+
+
+def cell_rng(cfg: int, i: int) -> np.random.Generator:
+    ss = np.random.SeedSequence(SEED_BASE + int(cfg), spawn_key=(int(i),))
+    return np.random.Generator(np.random.PCG64(ss))
+
+
+def steps_of(t_ms, dt=DT):
+    """Map times (ms) to the step grid (ceil), as the Poisson inputs do."""
+    return np.ceil(np.asarray(t_ms) / dt - 1e-9).astype(np.int64)
+
+
+# ----------------------------------------------------------------------------
+# topology helpers (parents listed in topological order, -1 = soma)
+
+def full_binary_parents(depth: int) -> np.ndarray:
+    n = 2 ** (depth + 1) - 1
+    p = np.empty(n, np.int32)
+    p[0] = -1
+    for b in range(1, n):
+        p[b] = (b - 1) // 2
+    return p
+
+
+def yule_parents(rng: np.random.Generator, n_branch_min: int) -> np.ndarray:
+    """Yule tree: start with one root branch, split a uniformly chosen leaf
+    into two children until at least n_branch_min branches exist."""
+    parents = [-1]
+    leaves = [0]
+    while len(parents) < n_branch_min:
+        k = int(rng.integers(len(leaves)))
+        b = leaves[k]
+        c1, c2 = len(parents), len(parents) + 1
+        parents += [b, b]
+        leaves[k] = c1
+        leaves.append(c2)
+    return np.asarray(parents, np.int32)
+
+
+def spread(total: int, parts: int, rng: np.random.Generator) -> np.ndarray:
+    """Split `total` CVs as evenly as possible over `parts` branches."""
+    base = total // parts
+    out = np.full(parts, base, np.int32)
+    extra = total - base * parts
+    if extra:
+        out[rng.choice(parts, size=extra, replace=False)] += 1
+    return out
+
+
+# ----------------------------------------------------------------------------
+# per-cell description
+
+class CellDesc:
+    __slots__ = ("parents", "n_cv", "length", "diam", "mech", "gna", "gk", "gl",
+                 "gpas", "epas", "soma_mech", "soma_g", "syn", "in_conn",
+                 "ext", "clamps")
+
+    def __init__(self):
+        self.syn = []       # (branch, cv, tau, e)
+        self.in_conn = []   # (src gid, local syn, delay_steps, w)
+        self.ext = []       # (local syn, step, w)
+        self.clamps = []    # (branch, cv, on, off, amp)
+
+
+def _geometry(d: CellDesc, rng, n_cv):
+    nb = len(d.parents)
+    d.n_cv = np.asarray(n_cv, np.int32)
+    d.length = rng.uniform(100.0, 300.0, nb)
+    d.diam = rng.uniform(1.0, 3.0, nb)
+
+
+def _dend_pas(d: CellDesc):
+    nb = len(d.parents)
+    d.mech = np.full(nb, MECH_PAS, np.uint32)
+    d.gna = np.zeros(nb)
+    d.gk = np.zeros(nb)
+    d.gl = np.zeros(nb)
+    d.gpas = np.full(nb, PAS_G)
+    d.epas = np.full(nb, PAS_E)
+
+
+def _soma_hh(d: CellDesc):
+    d.soma_mech = MECH_HH
+    d.soma_g = (HH_DEF[0], HH_DEF[1], HH_DEF[2], 0.0, PAS_E)
+
+
+def _random_cv(rng, d: CellDesc):
+    b = int(rng.integers(len(d.parents)))
+    return b, int(rng.integers(int(d.n_cv[b])))
+
+
+def _poisson_steps(rng, rate_hz, t_ms, dt=DT):
+    n = rng.poisson(rate_hz * t_ms * 1e-3)
+    return np.sort(steps_of(rng.uniform(0.0, t_ms, n), dt))
+
+
+def cell_c1(i: int) -> CellDesc:
+    rng = cell_rng(1, i)
+    d = CellDesc()
+    d.parents = np.full(4, -1, np.int32)
+    _geometry(d, rng, [32] * 4)
+    _dend_pas(d)
+    _soma_hh(d)
+    d.syn.append((-1, 0, 2.0, 0.0))
+    t = np.sort(rng.uniform(0.0, 100.0, 10))
+    for s in steps_of(t):
+        d.ext.append((0, int(s), 0.01))
+    return d
+
+
+def cell_c2(i: int, n_cells: int, kick_all: bool = True) -> CellDesc:
+    rng = cell_rng(2, i)
+    d = CellDesc()
+    d.parents = full_binary_parents(6)
+    _geometry(d, rng, [8] * len(d.parents))
+    _dend_pas(d)
+    _soma_hh(d)
+    d.syn.append((-1, 0, 2.0, 0.0))
+    for _ in range(9):
+        b, k = _random_cv(rng, d)
+        d.syn.append((b, k, 2.0, 0.0))
+    d.in_conn.append(((i - 1) % n_cells, 0, 200, 0.05))
+    if kick_all or i == 0:
+        d.ext.append((0, 0, 0.05))
+    return d
+
+
+def cell_c3(i: int, t_ms: float = 200.0) -> CellDesc:
+    rng = cell_rng(3, i)
+    d = CellDesc()
+    n = int(round(math.exp(rng.uniform(math.log(50.0), math.log(5000.0)))))
+    nb_min = -(-(n - 1) // 8)
+    d.parents = yule_parents(rng, nb_min)
+    nb = len(d.parents)
+    _geometry(d, rng, spread(n - 1, nb, rng))
+    _dend_pas(d)
+    hh = rng.uniform(size=nb) < 0.25
+    d.mech[hh] = MECH_HH
+    d.gna[hh], d.gk[hh], d.gl[hh] = HH_DEF
+    d.gpas[hh] = 0.0
+    _soma_hh(d)
+    for s in range(20):
+        b, k = _random_cv(rng, d)
+        d.syn.append((b, k, 2.0, 0.0))
+        for st in _poisson_steps(rng, 10.0, t_ms):
+            d.ext.append((s, int(st), 0.01))
+    return d
+
+
+C4_COUNTS = [16] * 4 + [15] * 9
+
+
+def cell_c4(i: int, hidden: bool) -> CellDesc:
+    """Adjoint workload cell. `hidden` selects the target parameters;
+    otherwise the perturbed starting point theta_0 is returned."""
+    rng = cell_rng(4, i)
+    d = CellDesc()
+    d.parents = yule_parents(rng, 13)
+    nb = len(d.parents)
+    _geometry(d, rng, rng.permutation(np.asarray(C4_COUNTS, np.int32)))
+    nr = nb + 1
+    th = np.stack([rng.uniform(0.08, 0.16, nr), rng.uniform(0.024, 0.048, nr),
+                   rng.uniform(2e-4, 4e-4, nr)], axis=1)
+    pert = rng.uniform(0.8, 1.2, (nr, 3))
+    if not hidden:
+        th = th * pert
+    d.soma_mech = MECH_HH | MECH_PAS
+    d.soma_g = (th[0, 0], th[0, 1], 0.0, th[0, 2], PAS_E)
+    d.mech = np.full(nb, MECH_HH | MECH_PAS, np.uint32)
+    d.gna, d.gk, d.gpas = th[1:, 0].copy(), th[1:, 1].copy(), th[1:, 2].copy()
+    d.gl = np.zeros(nb)
+    d.epas = np.full(nb, PAS_E)
+    d.clamps.append((-1, 0, 200, 2000, 0.2))
+    return d
+
+
+def cell_c5(i: int, n_cells: int, n_in: int = 100, t_ms: float = 200.0,
+            w_bg: float = 0.05) -> CellDesc:
+    rng = cell_rng(5, i)
+    d = CellDesc()
+    d.parents = yule_parents(rng, 187)
+    nb = len(d.parents)
+    _geometry(d, rng, [8] * nb)
+    _dend_pas(d)
+    _soma_hh(d)
+    n_in = min(n_in, n_cells - 1)
+    src = rng.choice(n_cells - 1, size=n_in, replace=False)
+    src = np.where(src >= i, src + 1, src)
+    delays = np.rint(rng.uniform(5.0, 10.0, n_in) / DT).astype(np.int64)
+    for j in range(n_in):
+        b, k = _random_cv(rng, d)
+        d.syn.append((b, k, 2.0, 0.0))
+        d.in_conn.append((int(src[j]), j, int(delays[j]), 0.01))
+    d.syn.append((-1, 0, 2.0, 0.0))
+    for st in _poisson_steps(rng, 5.0, t_ms):
+        d.ext.append((n_in, int(st), w_bg))
+    return d
+
+
+# ----------------------------------------------------------------------------
+# assembly of a model from cell descriptions
+
+def assemble(cells: list[CellDesc], gids=None, n_steps: int = 0,
+             dt: float = DT) -> dict:
+    """Flatten per-cell descriptions into the column model.  `gids` are the
+    global ids the cells had in the full network; connections whose source is
+    not among them are dropped (used for light-cone sub-models)."""
+    if gids is None:
+        gids = list(range(len(cells)))
+    remap = {int(g): k for k, g in enumerate(gids)}
+    C = len(cells)
+    nbs = np.array([len(c.parents) for c in cells], np.int64)
+    bb = np.zeros(C, np.int64)
+    bb[1:] = np.cumsum(nbs)[:-1]
+    cat = lambda f, dt_: np.concatenate([np.asarray(getattr(c, f), dt_) for c in cells]) if C else np.zeros(0, dt_)
+    m = dict(
+        cell_branch_begin=bb, cell_n_branch=nbs.astype(np.int32),
+        soma_area=np.full(C, SOMA_AREA), soma_mech=np.array([c.soma_mech for c in cells], np.uint32),
+        soma_gna=np.array([c.soma_g[0] for c in cells]), soma_gk=np.array([c.soma_g[1] for c in cells]),
+        soma_gl=np.array([c.soma_g[2] for c in cells]), soma_gpas=np.array([c.soma_g[3] for c in cells]),
+        soma_epas=np.array([c.soma_g[4] for c in cells]),
+        cm=np.full(C, CM), Ra=np.full(C, RA),
+        br_parent=cat("parents", np.int32), br_n_cv=cat("n_cv", np.int32),
+        br_length=cat("length", np.float64), br_diam=cat("diam", np.float64),
+        br_mech=cat("mech", np.uint32), br_gna=cat("gna", np.float64), br_gk=cat("gk", np.float64),
+        br_gl=cat("gl", np.float64), br_gpas=cat("gpas", np.float64), br_epas=cat("epas", np.float64),
+    )
+    sb = np.zeros(C + 1, np.int64)
+    sb[1:] = np.cumsum([len(c.syn) for c in cells])
+    syn = [(ci, s) for ci, c in enumerate(cells) for s in c.syn]
+    m["syn_cell"] = np.array([ci for ci, _ in syn], np.int32)
+    m["syn_branch"] = np.array([s[0] for _, s in syn], np.int32)
+    m["syn_cv"] = np.array([s[1] for _, s in syn], np.int32)
+    m["syn_tau"] = np.array([s[2] for _, s in syn], np.float64)
+    m["syn_e"] = np.array([s[3] for _, s in syn], np.float64)
+    con = [(remap[src], ci, int(sb[ci]) + ls, dl, w)
+           for ci, c in enumerate(cells) for (src, ls, dl, w) in c.in_conn if int(src) in remap]
+    m["con_src"] = np.array([x[0] for x in con], np.uint32)
+    m["con_dst"] = np.array([x[1] for x in con], np.uint32)
+    m["con_syn"] = np.array([x[2] for x in con], np.uint32)
+    m["con_delay"] = np.array([x[3] for x in con], np.int32)
+    m["con_w"] = np.array([x[4] for x in con], np.float64)
+    ev = [(int(sb[ci]) + ls, st, w) for ci, c in enumerate(cells) for (ls, st, w) in c.ext]
+    m["ev_syn"] = np.array([x[0] for x in ev], np.uint32)
+    m["ev_step"] = np.array([x[1] for x in ev], np.int64)
+    m["ev_w"] = np.array([x[2] for x in ev], np.float64)
+    ic = [(ci,) + tuple(x) for ci, c in enumerate(cells) for x in c.clamps]
+    m["ic_cell"] = np.array([x[0] for x in ic], np.int32)
+    m["ic_branch"] = np.array([x[1] for x in ic], np.int32)
+    m["ic_cv"] = np.array([x[2] for x in ic], np.int32)
+    m["ic_on"] = np.array([x[3] for x in ic], np.int64)
+    m["ic_off"] = np.array([x[4] for x in ic], np.int64)
+    m["ic_amp"] = np.array([x[5] for x in ic], np.float64)
+    m["dt"], m["threshold"], m["v_init"], m["n_steps"] = dt, THRESHOLD, V_INIT, int(n_steps)
+    m["gids"] = np.asarray(gids, np.int64)
+    return m
+
+
+def n_cvs(m: dict) -> np.ndarray:
+    """CVs per cell: one soma CV plus the branch CV counts (a count, not a
+    discretisation)."""
+    out = np.ones(len(m["cell_n_branch"]), np.int64)
+    np.add.at(out, np.repeat(np.arange(len(out)), m["cell_n_branch"]), m["br_n_cv"])
+    return out
+
+
+# ----------------------------------------------------------------------------
+# the five workloads (and scaled-down variants used by tests)
+
+def config1() -> dict:
+    return assemble([cell_c1(0)], n_steps=4000)
+
+
+def config2(n_cells: int = 8192, cells=None, kick_all: bool = True, n_steps: int = 4000) -> dict:
+    ids = range(n_cells) if cells is None else cells
+    return assemble([cell_c2(i, n_cells, kick_all) for i in ids], gids=list(ids), n_steps=n_steps)
+
+
+def config3(n_cells: int = 4096, cells=None, n_steps: int = 8000) -> dict:
+    ids = range(n_cells) if cells is None else cells
+    t_ms = n_steps * DT
+    return assemble([cell_c3(i, t_ms) for i in ids], gids=list(ids), n_steps=n_steps)
+
+
+def config4(n_cells: int = 256, hidden: bool = False, cells=None, n_steps: int = 2000) -> dict:
+    ids = range(n_cells) if cells is None else cells
+    return assemble([cell_c4(i, hidden) for i in ids], gids=list(ids), n_steps=n_steps)
+
+
+def config4_theta(m: dict) -> np.ndarray:
+    """Per-region (soma, branches...) [gNa, gK, g_pas] of a config-4 model,
+    shape [cells, 14, 3]."""
+    C = len(m["cell_n_branch"])
+    nb = int(m["cell_n_branch"][0])
+    th = np.empty((C, nb + 1, 3))
+    th[:, 0, 0], th[:, 0, 1], th[:, 0, 2] = m["soma_gna"], m["soma_gk"], m["soma_gpas"]
+    th[:, 1:, 0] = m["br_gna"].reshape(C, nb)
+    th[:, 1:, 1] = m["br_gk"].reshape(C, nb)
+    th[:, 1:, 2] = m["br_gpas"].reshape(C, nb)
+    return th
+
+
+def config5(n_cells: int = 65536, cells=None, n_in: int = 100, n_steps: int = 8000) -> dict:
+    ids = range(n_cells) if cells is None else cells
+    t_ms = n_steps * DT
+    return assemble([cell_c5(i, n_cells, n_in, t_ms) for i in ids], gids=list(ids), n_steps=n_steps)
+
+
+def ring_light_cone(n_cells: int, target: int, n_steps: int, delay: int = 200) -> list[int]:
+    """Cells of the config-2 ring whose spikes can reach `target` within
+    n_steps: a spike of cell target-j needs at least j*(delay+1) steps."""
+    hops = n_steps // (delay + 1) + 1
+    return [(target - j) % n_cells for j in range(min(hops, n_cells - 1), -1, -1)]
