@@ -1,0 +1,239 @@
+/*
+ * arbmi.h -- C ABI of the MI355X multi-compartment cell stepper.
+ *
+ * The library advances networks of morphologically detailed cells by the
+ * scheme of the Arbor paper (arXiv:1901.07454), Section II "Model": each
+ * cell is a branching cable discretised into vertex-centred control volumes
+ * (eq. 2a); a time step computes membrane currents at V(t), solves the
+ * implicit-Euler system for V(t+dt) with the Hines (tree Thomas) algorithm,
+ * then integrates channel and synapse states with the new voltage; spikes are
+ * threshold crossings on the soma and reach their targets through
+ * (source, destination, synapse, delay, weight) connections, exchanged once
+ * per epoch no longer than the minimum delay (Sec. II; Sec. IV-A).
+ *
+ * Conventions for every call
+ *   - Units: V mV, t ms (steps of dt), length and diameter um, area um^2,
+ *     capacitance pF, conductance nS, current pA at the interface of the
+ *     numerics; densities in S/cm^2 and uF/cm^2, synaptic weights in uS,
+ *     clamp amplitudes in nA (positive depolarises).
+ *   - All arithmetic is IEEE FP64.
+ *   - Inputs are borrowed for the duration of the call only; the library
+ *     copies what it keeps.  Output buffers are owned by the caller.  A
+ *     pointer documented as "device" must be a device address on the sim's
+ *     GPU; "host" pointers are ordinary host memory.
+ *   - Device memory is obtained through arb_params.alloc (or hipMalloc when
+ *     it is NULL) and returned through arb_params.free at arb_free.
+ *   - Work is enqueued on arb_params.hip_stream (NULL = the null stream).
+ *     arb_step returns once its work is enqueued; every arb_get_* call
+ *     synchronises that stream first.
+ *   - Every call returns ARB_OK (0) or a negative ARB_E* code and never
+ *     aborts or throws.  arb_last_error() gives a text for the last failure
+ *     on the calling thread.  One sim must not be used from two threads at
+ *     once.
+ *   - User CV numbering: cells in order; within a cell the soma CV first,
+ *     then each branch's CVs from proximal to distal, branches in the order
+ *     given.  Voltages and traces are reported in this order even though the
+ *     library stores CVs in its own packed order.
+ */
+#ifndef ARBMI_H
+#define ARBMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ARB_OK = 0,
+    ARB_EINVAL = -1,    /* bad model or argument (topology, sizes, ranges, NaN) */
+    ARB_ENOMEM = -2,    /* the allocator returned NULL */
+    ARB_EHIP = -3,      /* a HIP runtime call failed; text in arb_last_error */
+    ARB_ESTATE = -4,    /* call out of order (e.g. backward before forward) */
+    ARB_EOVERFLOW = -5  /* a fixed-capacity buffer (spikes, events) overflowed */
+};
+
+#define ARB_MECH_HH 1u  /* Hodgkin-Huxley Na, K and leak channels */
+#define ARB_MECH_PAS 2u /* passive leak g_pas (V - e_pas) */
+
+typedef struct arb_sim_ *arb_sim;
+
+/* One unbranched dendritic section (Sec. II: the cell is a branching
+ * one-dimensional cable).  Discretised into n_cv control volumes of equal
+ * length; node k (k = 1..n_cv) sits at k*length/n_cv from the proximal end,
+ * whose node is the parent's last node (or the soma). */
+typedef struct {
+    int32_t parent;        /* parent branch index within the cell, -1 = soma; must be < own index */
+    int32_t n_cv;          /* >= 1 */
+    double length_um;      /* > 0 */
+    double diam_um;        /* > 0 */
+    uint32_t mech;         /* ARB_MECH_HH | ARB_MECH_PAS */
+    uint32_t reserved;
+    double gbar_na, gbar_k, gl_hh; /* hh densities, S/cm^2 */
+    double g_pas, e_pas;           /* pas density S/cm^2, reversal mV */
+} arb_branch;
+
+/* One cell: an isopotential soma node plus branches[branch_begin ..
+ * branch_begin + n_branch) of the flat branch array, in topological order. */
+typedef struct {
+    int64_t branch_begin;
+    int32_t n_branch;      /* >= 0 */
+    uint32_t soma_mech;
+    double soma_area_um2;  /* > 0 */
+    double soma_gbar_na, soma_gbar_k, soma_gl_hh, soma_g_pas, soma_e_pas;
+    double cm_uF_cm2;      /* > 0 */
+    double Ra_ohm_cm;      /* > 0 */
+} arb_cell;
+
+/* Exponential synapse g' = -g/tau, current g (V - e_rev) (point source of
+ * eq. 1a/2a).  branch = -1 places it on the soma (cv must be 0). */
+typedef struct {
+    int32_t cell, branch, cv; /* cv: 0-based CV along the branch, proximal first */
+    int32_t reserved;
+    double tau_ms;            /* > 0 */
+    double e_rev_mV;
+} arb_synapse;
+
+/* Connection tuple (source, destination, synapse, delay, weight) (Sec. II).
+ * syn is an index into the synapse array and must lie on cell dst. */
+typedef struct {
+    uint32_t src, dst, syn;
+    int32_t delay_steps;      /* >= 1 */
+    double w_uS;
+} arb_connection;
+
+/* External input event: at the start of step `step`, g[syn] += 1000 w. */
+typedef struct {
+    uint32_t syn;
+    int32_t reserved;
+    int64_t step;             /* >= 0 */
+    double w_uS;
+} arb_event;
+
+/* Current clamp, active for step_on <= n < step_off. */
+typedef struct {
+    int32_t cell, branch, cv, reserved;
+    int64_t step_on, step_off;
+    double amp_nA;
+} arb_iclamp;
+
+typedef struct {
+    double dt_ms;             /* > 0 */
+    double threshold_mV;      /* soma spike threshold (upward crossing) */
+    double v_init_mV;         /* initial V; gates start at steady state, g = 0 */
+    int32_t epoch_steps;      /* 0 = the minimum connection delay; must not exceed it */
+    int32_t flags;            /* ARB_FLAG_* */
+    void *hip_stream;         /* hipStream_t, NULL = null stream */
+    void *(*alloc)(size_t bytes, void *ctx); /* device allocator, NULL = hipMalloc */
+    void (*free)(void *ptr, void *ctx);
+    void *alloc_ctx;
+    int64_t spike_capacity;   /* spikes kept between arb_get_spikes calls; 0 = default */
+    int64_t event_capacity;   /* network events per (cell pack, epoch); 0 = default */
+    int32_t block_threads;    /* threads per cell pack; 0 = autotuned */
+    int32_t coef_mode;        /* 0 = autotuned, 1 = per-CV coefficients in LDS, 2 = streamed */
+} arb_params;
+
+#define ARB_FLAG_TIME_KERNELS 1 /* record HIP events around every step kernel */
+
+typedef struct {
+    uint32_t gid;
+    int32_t reserved;
+    int64_t step;             /* index of the step whose end value crossed: V^{step-1} < thr <= V^{step} */
+    double t_ms;              /* linearly interpolated crossing time (reported only) */
+} arb_spike;
+
+typedef struct {
+    int32_t n_cells;
+    int32_t n_packs;          /* workgroups of the step kernel */
+    int64_t n_cv;             /* user CVs */
+    int64_t n_slots;          /* packed CV slots incl. padding */
+    int64_t n_hh, n_syn, n_conn;
+    int64_t step;             /* steps completed */
+    int32_t epoch_steps;
+    int32_t block_threads;
+    int32_t coef_mode;        /* 1 = LDS, 2 = streamed */
+    int32_t lds_bytes;        /* dynamic LDS per workgroup */
+    int64_t device_bytes;     /* device memory held by the sim */
+    int64_t bytes_per_step;   /* algorithmic HBM bytes one step must move (SoA model) */
+} arb_info;
+
+/* Build a simulation from a fully enumerated model (Sec. III-A: cells,
+ * their connections; Sec. II: mechanisms, synapses, injections).  Validates
+ * everything on the host first (ARB_EINVAL with a message naming the bad
+ * item), discretises each cell, packs cells into workgroups, uploads.
+ * *out receives the new sim, or NULL on failure. */
+int arb_build_cells(const arb_cell *cells, int32_t n_cells, const arb_branch *branches,
+                    int64_t n_branches, const arb_synapse *syn, int64_t n_syn,
+                    const arb_connection *conn, int64_t n_conn, const arb_event *ev,
+                    int64_t n_ev, const arb_iclamp *stim, int32_t n_stim,
+                    const arb_params *p, arb_sim *out);
+
+/* Advance every cell by n_steps steps of dt (Sec. II operator splitting:
+ * events due at the step start, currents at V(t), implicit Euler + Hines for
+ * V(t+dt), states with the new V, threshold test; spike exchange at each
+ * epoch end, Sec. IV-A).  Asynchronous.  On failure the sim is left at the
+ * last completed epoch.  ARB_EOVERFLOW if a spike or event buffer filled. */
+int arb_step(arb_sim s, int64_t n_steps);
+
+/* Copy all n_cv voltages in user CV order into dst (n >= n_cv doubles),
+ * a device pointer if dst_on_device, else host. */
+int arb_get_voltages(arb_sim s, double *dst, int64_t n, int dst_on_device);
+
+/* Drain the spikes recorded since the last call into host dst, sorted by
+ * (step, gid).  *n_out = number written; ARB_EOVERFLOW if cap was too small
+ * (nothing is drained then) or spikes were lost to a full device buffer. */
+int arb_get_spikes(arb_sim s, arb_spike *dst, int64_t cap, int64_t *n_out);
+
+/* Record V of the given user CVs after every step from now on, for up to
+ * max_steps steps (replaces earlier probes). */
+int arb_set_probes(arb_sim s, const int64_t *cv, int32_t n, int64_t max_steps);
+
+/* Copy the recorded trace, layout [probe][step], into dst (n_probe * cap
+ * doubles, device or host) and restart recording.  *n_steps_out = steps
+ * recorded. */
+int arb_get_trace(arb_sim s, double *dst, int64_t cap, int dst_on_device, int64_t *n_steps_out);
+
+/* Replace per-region channel densities theta[cell][region][3] =
+ * (gbar_na, gbar_k, g_pas), region 0 = soma, 1 + b = branch b (host array of
+ * n = 3 * (n_cells + n_branches) doubles).  Takes effect at the next step. */
+int arb_set_params(arb_sim s, const double *theta, int64_t n);
+
+/* Gradient support (discrete adjoint of the step).  Forward: run n_steps
+ * recording the soma voltage of every cell after each step into trace_dev
+ * (device, [cell][step]), storing a state checkpoint every ckpt_every
+ * steps; input events are recorded and treated as fixed in the backward. */
+int arb_grad_forward(arb_sim s, int64_t n_steps, int32_t ckpt_every, double *trace_dev);
+
+/* Backward: given dL/dtrace (device, [cell][step]), write dL/dtheta (device,
+ * [cell][region][3], layout of arb_set_params).  ARB_ESTATE without a prior
+ * arb_grad_forward.  Leaves the sim's state at the end of the forward. */
+int arb_grad_backward(arb_sim s, const double *dL_dtrace_dev, double *dL_dtheta_dev);
+
+/* Checkpoint: serialise / restore the dynamic state (step, V, gates,
+ * synaptic conductances, pending events, event cursors).  With blob NULL,
+ * arb_get_state writes only the size into *n_out. */
+int arb_get_state(arb_sim s, void *blob, int64_t cap, int64_t *n_out);
+int arb_set_state(arb_sim s, const void *blob, int64_t n);
+
+/* Sizes and the chosen launch configuration. */
+int arb_get_info(arb_sim s, arb_info *info);
+
+/* Step-kernel timing (ARB_FLAG_TIME_KERNELS): total ms and number of
+ * launches since the last call; synchronises the stream. */
+int arb_get_kernel_time(arb_sim s, double *ms_total, int64_t *n_launches);
+
+/* Wait for all enqueued work of the sim. */
+int arb_sync(arb_sim s);
+
+/* Release everything the sim holds.  NULL is accepted. */
+int arb_free(arb_sim s);
+
+/* Text of the last failure on the calling thread ("" if none). */
+const char *arb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARBMI_H */

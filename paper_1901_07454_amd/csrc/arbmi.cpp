@@ -1,0 +1,738 @@
+// arbmi.cpp -- the C ABI: sim lifetime, device memory, the epoch loop.
+#include "../../include/arbmi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "adjoint.hpp"
+#include "kernels.hpp"
+#include "lower.hpp"
+#include "sim.hpp"
+
+using namespace arbmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return ARB_EHIP;
+}
+
+#define HIP_TRY(expr)                                      \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
+    } while (0)
+
+}  // namespace
+
+namespace arbmi {
+
+void* Sim::raw_alloc(size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    bytes = (bytes + 255) & ~size_t(255);
+    void* ptr = nullptr;
+    if (p.alloc) {
+        ptr = p.alloc(bytes, p.alloc_ctx);
+    } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
+        ptr = nullptr;
+    }
+    if (ptr) {
+        allocs.push_back(ptr);
+        device_bytes += int64_t(bytes);
+    }
+    return ptr;
+}
+
+void Sim::release_all() {
+    for (void* q : allocs) {
+        if (p.free)
+            p.free(q, p.alloc_ctx);
+        else
+            (void)hipFree(q);
+    }
+    allocs.clear();
+    device_bytes = 0;
+}
+
+int Sim::upload(void* dst, const void* src, size_t bytes) {
+    if (!bytes) return ARB_OK;
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    return ARB_OK;
+}
+
+int Sim::fill_zero(void* dst, size_t bytes) {
+    if (!bytes) return ARB_OK;
+    HIP_TRY(hipMemsetAsync(dst, 0, bytes, st));
+    return ARB_OK;
+}
+
+StepArgs Sim::step_args() const {
+    StepArgs a{};
+    a.pk = d_pk;
+    a.rd = d_rd;
+    a.tk = d_tk;
+    a.ch_slot = d_ch;
+    a.nl = d_nl;
+    a.pc_gid = d_pc_gid;
+    a.pc_soma = d_pc_soma;
+    a.V = d_V;
+    a.alpha = d_alpha;
+    a.beta = d_beta;
+    a.F = d_F;
+    a.invd = d_invd;
+    a.hh_m = d_hh_m;
+    a.hh_h = d_hh_h;
+    a.hh_n = d_hh_n;
+    a.hh_gna = d_hh_gna;
+    a.hh_gk = d_hh_gk;
+    a.syn_g = d_syn_g;
+    a.syn_e = d_syn_e;
+    a.syn_decay = d_syn_decay;
+    a.ic_on = d_ic_on;
+    a.ic_off = d_ic_off;
+    a.ic_amp = d_ic_amp;
+    a.xe_step = d_xe_step;
+    a.xe_syn = d_xe_syn;
+    a.xe_w = d_xe_w;
+    a.pk_xcur = d_pk_xcur;
+    a.bk_ev = d_bk_ev;
+    a.bk_cnt = d_bk_cnt;
+    a.pk_ncur = d_pk_ncur;
+    a.bk_cap = bk_cap;
+    a.n_packs = int32_t(L.packs.size());
+    a.cr_syn = d_cr_syn;
+    a.cr_w = d_cr_w;
+    a.sp_gid = d_sp_gid;
+    a.sp_step = d_sp_step;
+    a.sp_t = d_sp_t;
+    a.sp_cap = sp_cap;
+    a.ctr = d_ctr;
+    a.pr_slot = d_pr_slot;
+    a.pr_id = d_pr_id;
+    a.trace = d_trace;
+    a.trace_cap = trace_cap;
+    a.trace_step0 = trace_step0;
+    a.n_slots_total = L.n_slots;
+    a.n_hh_total = int64_t(L.hh_cv.size());
+    a.n_syn_total = int64_t(L.syn_global.size());
+    a.dt = L.dt;
+    a.threshold = L.threshold;
+    return a;
+}
+
+// Enqueue steps [step, step + n): epochs of K steps aligned at multiples of
+// K; network events are sorted at each epoch start and spikes exchanged at
+// each epoch end.  `rec` (optional) records the pre-step state of every step
+// for the adjoint; then the steps must lie in one launch.
+int Sim::advance(int64_t n, const RecordArgs* rec) {
+    const bool net = !L.out_rank.empty();
+    const int np = int32_t(L.packs.size());
+    while (n > 0) {
+        const int64_t e = step / K, pos = step % K;
+        const int64_t nthis = std::min<int64_t>(n, K - pos);
+        const int32_t bucket = int32_t(e % n_buckets);
+        if (net && pos == 0)
+            HIP_TRY(launch_sort_buckets(d_bk_ev, d_bk_cnt, d_pk_ncur, bk_cap, bucket, np, d_ctr, st));
+        StepArgs a = step_args();
+        a.bucket = bucket;
+        a.step0 = step;
+        a.nsteps = int32_t(nthis);
+        a.epoch_end = (pos + nthis == K) ? 1 : 0;
+        if (rec) {
+            if (nthis != n) return fail(ARB_EINVAL, "recorded steps must fit one epoch");
+            a.rec_V = rec->V;
+            a.rec_m = rec->m;
+            a.rec_h = rec->h;
+            a.rec_n = rec->n;
+            a.rec_g = rec->g;
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (p.flags & ARB_FLAG_TIME_KERNELS) {
+            if (timer_free.size() < 2) {
+                hipEvent_t x;
+                HIP_TRY(hipEventCreate(&x));
+                timer_free.push_back(x);
+                HIP_TRY(hipEventCreate(&x));
+                timer_free.push_back(x);
+            }
+            e0 = timer_free.back();
+            timer_free.pop_back();
+            e1 = timer_free.back();
+            timer_free.pop_back();
+            HIP_TRY(hipEventRecord(e0, st));
+        }
+        HIP_TRY(launch_step(a, cfg, np, st));
+        if (e0) {
+            HIP_TRY(hipEventRecord(e1, st));
+            timer_pending.push_back({e0, e1});
+        }
+        step += nthis;
+        n -= nthis;
+        if (net && a.epoch_end) {
+            ExchArgs x{};
+            x.sp_gid = d_sp_gid;
+            x.sp_step = d_sp_step;
+            x.out_off = d_out_off;
+            x.out_rank = d_out_rank;
+            x.cr_pack = d_cr_pack;
+            x.cr_delay = d_cr_delay;
+            x.bk_ev = d_bk_ev;
+            x.bk_cnt = d_bk_cnt;
+            x.bk_cap = bk_cap;
+            x.n_buckets = n_buckets;
+            x.n_packs = np;
+            x.epoch_steps = K;
+            x.sp_cap = sp_cap;
+            x.ctr = d_ctr;
+            HIP_TRY(launch_exchange(x, exch_grid, st));
+        }
+    }
+    return ARB_OK;
+}
+
+int Sim::check_flags(bool& spikes_lost, bool& events_lost) {
+    Counters c{};
+    HIP_TRY(hipMemcpyAsync(&c, d_ctr, sizeof c, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    spikes_lost = (c.flags & kFlagSpikeOverflow) != 0;
+    events_lost = (c.flags & kFlagEventOverflow) != 0;
+    return ARB_OK;
+}
+
+}  // namespace arbmi
+
+namespace {
+
+template <class T>
+T* dalloc(Sim* s, size_t n, int& rc) {
+    if (rc != ARB_OK) return nullptr;
+    T* ptr = static_cast<T*>(s->raw_alloc(n * sizeof(T)));
+    if (!ptr) rc = fail(ARB_ENOMEM, "device allocation failed");
+    return ptr;
+}
+
+template <class T>
+T* dupload(Sim* s, const std::vector<T>& v, int& rc) {
+    T* ptr = dalloc<T>(s, std::max<size_t>(v.size(), 1), rc);
+    if (rc == ARB_OK && !v.empty()) rc = s->upload(ptr, v.data(), v.size() * sizeof(T));
+    return ptr;
+}
+
+int build_device(Sim* s) {
+    Lowered& L = s->L;
+    int rc = ARB_OK;
+    const int np = int(L.packs.size());
+    s->d_pk = dupload(s, L.packs, rc);
+    s->d_rd = dupload(s, L.rounds, rc);
+    s->d_tk = dupload(s, L.tasks, rc);
+    s->d_ch = dupload(s, L.ch_slot, rc);
+    s->d_nl = dupload(s, L.nl, rc);
+    s->d_pc_gid = dupload(s, L.pc_gid, rc);
+    s->d_pc_soma = dupload(s, L.pc_soma, rc);
+    std::vector<double> v0(L.n_slots, 0.0);
+    for (int64_t i = 0; i < L.n_cv; ++i) v0[L.perm[i]] = L.v_init;
+    s->d_V = dupload(s, v0, rc);
+    s->d_alpha = dupload(s, L.alpha, rc);
+    s->d_beta = dupload(s, L.beta, rc);
+    s->d_F = dupload(s, L.F, rc);
+    s->d_invd = dupload(s, L.invd, rc);
+    // gates at steady state for v_init (host evaluation of the same rates)
+    const size_t nhh = L.hh_cv.size();
+    {
+        const double v = L.v_init;
+        auto ex = [](double x) { return (1.0 + x == 1.0) ? 1.0 : x / std::expm1(x); };
+        const double am = ex(-(v + 40.0) * 0.1), bm = 4.0 * std::exp(-(v + 65.0) * (1.0 / 18.0));
+        const double ah = 0.07 * std::exp(-(v + 65.0) * 0.05), bh = 1.0 / (std::exp(-(v + 35.0) * 0.1) + 1.0);
+        const double an = 0.1 * ex(-(v + 55.0) * 0.1), bn = 0.125 * std::exp(-(v + 65.0) * (1.0 / 80.0));
+        s->m0 = am / (am + bm);
+        s->h0 = ah / (ah + bh);
+        s->n0 = an / (an + bn);
+    }
+    s->d_hh_m = dupload(s, std::vector<double>(nhh, s->m0), rc);
+    s->d_hh_h = dupload(s, std::vector<double>(nhh, s->h0), rc);
+    s->d_hh_n = dupload(s, std::vector<double>(nhh, s->n0), rc);
+    s->d_hh_gna = dupload(s, L.hh_gna, rc);
+    s->d_hh_gk = dupload(s, L.hh_gk, rc);
+    const size_t nsyn = L.syn_global.size();
+    s->d_syn_g = dupload(s, std::vector<double>(nsyn, 0.0), rc);
+    s->d_syn_e = dupload(s, L.syn_e, rc);
+    s->d_syn_decay = dupload(s, L.syn_decay, rc);
+    s->d_ic_on = dupload(s, L.ic_on, rc);
+    s->d_ic_off = dupload(s, L.ic_off, rc);
+    s->d_ic_amp = dupload(s, L.ic_amp, rc);
+    s->d_xe_step = dupload(s, L.xe_step, rc);
+    s->d_xe_syn = dupload(s, L.xe_syn, rc);
+    s->d_xe_w = dupload(s, L.xe_w, rc);
+    std::vector<int64_t> xcur(np);
+    for (int k = 0; k < np; ++k) xcur[k] = L.packs[k].xe0;
+    s->xcur0 = xcur;
+    s->d_pk_xcur = dupload(s, xcur, rc);
+    s->d_pk_ncur = dupload(s, std::vector<int32_t>(np, 0), rc);
+    s->d_cr_syn = dupload(s, L.cr_syn, rc);
+    s->d_cr_pack = dupload(s, L.cr_pack, rc);
+    s->d_cr_delay = dupload(s, L.cr_delay, rc);
+    s->d_cr_w = dupload(s, L.cr_w, rc);
+    s->d_out_off = dupload(s, L.out_off, rc);
+    s->d_out_rank = dupload(s, L.out_rank, rc);
+    s->d_perm = dupload(s, L.perm, rc);
+    // network event buckets
+    const bool net = !L.out_rank.empty();
+    if (net) {
+        s->n_buckets = int32_t(2 + (L.max_delay + s->K - 1) / s->K);
+        int64_t cap = s->p.event_capacity;
+        if (cap <= 0) cap = std::max<int64_t>(64, 4 * L.max_in_per_pack);
+        // the per-pack sort stages a run in LDS, rounded up to a power of two
+        int64_t lim = 1;
+        while (lim * 2 * 8 <= std::min<int64_t>(s->lds_max - 256, 128 * 1024)) lim *= 2;
+        cap = std::min<int64_t>(cap, lim);
+        s->bk_cap = int32_t(cap);
+    } else {
+        s->n_buckets = 1;
+        s->bk_cap = 0;
+    }
+    const size_t nbk = size_t(s->n_buckets) * size_t(np);
+    s->d_bk_cnt = dalloc<uint32_t>(s, nbk, rc);
+    if (rc == ARB_OK) rc = s->fill_zero(s->d_bk_cnt, nbk * sizeof(uint32_t));
+    s->d_bk_ev = dalloc<uint64_t>(s, std::max<size_t>(1, nbk * size_t(s->bk_cap)), rc);
+    // spikes
+    int64_t spc = s->p.spike_capacity;
+    if (spc <= 0) spc = std::max<int64_t>(1 << 16, int64_t(L.n_cells) * 64);
+    spc = std::min<int64_t>(spc, int64_t(1) << 31);
+    s->sp_cap = uint32_t(spc);
+    s->d_sp_gid = dalloc<uint32_t>(s, s->sp_cap, rc);
+    s->d_sp_step = dalloc<int64_t>(s, s->sp_cap, rc);
+    s->d_sp_t = dalloc<double>(s, s->sp_cap, rc);
+    s->d_ctr = dalloc<Counters>(s, 1, rc);
+    if (rc == ARB_OK) rc = s->fill_zero(s->d_ctr, sizeof(Counters));
+    if (rc != ARB_OK) return rc;
+    return ARB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int arb_build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* branches, int64_t n_branches,
+                    const arb_synapse* syn, int64_t n_syn, const arb_connection* conn, int64_t n_conn,
+                    const arb_event* ev, int64_t n_ev, const arb_iclamp* stim, int32_t n_stim,
+                    const arb_params* p, arb_sim* out) {
+    g_err.clear();
+    if (!out) return fail(ARB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(ARB_EINVAL, "params is NULL");
+    if (p->block_threads != 0 && p->block_threads != 64 && p->block_threads != 128 && p->block_threads != 256)
+        return fail(ARB_EINVAL, "block_threads must be 0, 64, 128 or 256");
+    if (p->coef_mode < 0 || p->coef_mode > 2) return fail(ARB_EINVAL, "coef_mode must be 0, 1 or 2");
+    if ((p->alloc == nullptr) != (p->free == nullptr)) return fail(ARB_EINVAL, "alloc and free must be given together");
+
+    // device limits (validation below runs even without a device)
+    int ndev = 0;
+    const bool have_dev = hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0;
+    int dev = 0;
+    int64_t lds_max = 160 * 1024;
+    int n_cu = 256;
+    if (have_dev) {
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0) lds_max = v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+    }
+
+    Sim* s = new Sim();
+    s->p = *p;
+    s->st = static_cast<hipStream_t>(p->hip_stream);
+    s->device = dev;
+    s->n_cu = n_cu;
+    s->lds_max = lds_max;
+    const Plan plan = choose_plan(cells, n_cells, branches, n_branches, *p, lds_max, n_cu);
+    LowerOptions opt;
+    opt.block_threads = plan.block_threads;
+    opt.coef_mode = plan.coef_mode;
+    opt.lds_budget = plan.lds_budget;
+    opt.lds_hard_max = plan.lds_hard_max;
+    opt.max_cells_per_pack = plan.max_cells_per_pack;
+    std::string err;
+    int rc = lower_model(cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim, *p,
+                         opt, s->L, err);
+    if (rc == ARB_EINVAL && p->coef_mode == 0 && opt.coef_mode == 1 && err.find("LDS") != std::string::npos) {
+        // a cell too large for LDS-resident coefficients: stream them instead
+        opt.coef_mode = 2;
+        s->L = Lowered();
+        rc = lower_model(cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim, *p,
+                         opt, s->L, err);
+    }
+    if (rc != ARB_OK) {
+        delete s;
+        return fail(rc, err);
+    }
+    if (!have_dev) {
+        delete s;
+        return fail(ARB_EHIP, "no HIP device available");
+    }
+    const bool net = !s->L.out_rank.empty();
+    s->K = p->epoch_steps > 0 ? p->epoch_steps : (net ? s->L.min_delay : 1000);
+    s->cfg.block_threads = s->L.block_threads;
+    s->cfg.coef_mode = s->L.coef_mode;
+    int64_t lds = 0;
+    for (const PackDesc& D : s->L.packs) lds = std::max(lds, pack_lds_bytes(D.nslot, D.nsyn, D.nhh, s->L.coef_mode));
+    s->cfg.lds_bytes = int(std::max<int64_t>(lds, 8));
+    s->exch_grid = std::max(1, std::min(4 * n_cu, int((n_cells + 3) / 4)));
+    hipError_t he = prepare_step_kernels(int(lds_max));
+    if (he != hipSuccess) {
+        delete s;
+        return hip_fail(he, "prepare_step_kernels");
+    }
+    rc = build_device(s);
+    if (rc == ARB_OK) {
+        hipError_t e = hipStreamSynchronize(s->st);
+        if (e != hipSuccess) rc = hip_fail(e, "upload");
+    }
+    if (rc != ARB_OK) {
+        s->release_all();
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return ARB_OK;
+}
+
+int arb_step(arb_sim s_, int64_t n_steps) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s) return fail(ARB_EINVAL, "sim is NULL");
+    if (n_steps < 0) return fail(ARB_EINVAL, "n_steps < 0");
+    if (s->step + n_steps >= (int64_t(1) << 31)) return fail(ARB_EINVAL, "step count beyond 2^31");
+    s->grad_valid = false;
+    return s->advance(n_steps, nullptr);
+}
+
+int arb_get_voltages(arb_sim s_, double* dst, int64_t n, int dst_on_device) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s || !dst) return fail(ARB_EINVAL, "null argument");
+    if (n < s->L.n_cv) return fail(ARB_EINVAL, "destination smaller than the CV count");
+    const int64_t ncv = s->L.n_cv;
+    if (dst_on_device) {
+        HIP_TRY(launch_gather(s->d_V, s->d_perm, dst, ncv, s->st));
+        HIP_TRY(hipStreamSynchronize(s->st));
+        return ARB_OK;
+    }
+    int rc = ARB_OK;
+    if (!s->d_tmp || s->tmp_n < ncv) {
+        s->d_tmp = dalloc<double>(s, size_t(ncv), rc);
+        if (rc != ARB_OK) return rc;
+        s->tmp_n = ncv;
+    }
+    HIP_TRY(launch_gather(s->d_V, s->d_perm, s->d_tmp, ncv, s->st));
+    HIP_TRY(hipMemcpyAsync(dst, s->d_tmp, size_t(ncv) * 8, hipMemcpyDeviceToHost, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    return ARB_OK;
+}
+
+int arb_get_spikes(arb_sim s_, arb_spike* dst, int64_t cap, int64_t* n_out) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s || !n_out) return fail(ARB_EINVAL, "null argument");
+    *n_out = 0;
+    Counters c{};
+    HIP_TRY(hipMemcpyAsync(&c, s->d_ctr, sizeof c, hipMemcpyDeviceToHost, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    const uint32_t have = std::min(c.sp_count, s->sp_cap);
+    const int64_t n = int64_t(have) - int64_t(s->sp_user);
+    if (n > cap || (n > 0 && !dst)) return fail(ARB_EOVERFLOW, "destination too small for the pending spikes");
+    if (n > 0) {
+        std::vector<uint32_t> gid(n);
+        std::vector<int64_t> stp(n);
+        std::vector<double> t(n);
+        HIP_TRY(hipMemcpyAsync(gid.data(), s->d_sp_gid + s->sp_user, n * 4, hipMemcpyDeviceToHost, s->st));
+        HIP_TRY(hipMemcpyAsync(stp.data(), s->d_sp_step + s->sp_user, n * 8, hipMemcpyDeviceToHost, s->st));
+        HIP_TRY(hipMemcpyAsync(t.data(), s->d_sp_t + s->sp_user, n * 8, hipMemcpyDeviceToHost, s->st));
+        HIP_TRY(hipStreamSynchronize(s->st));
+        std::vector<int64_t> idx(n);
+        for (int64_t i = 0; i < n; ++i) idx[i] = i;
+        std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+            if (stp[a] != stp[b]) return stp[a] < stp[b];
+            return gid[a] < gid[b];
+        });
+        for (int64_t i = 0; i < n; ++i) {
+            dst[i].gid = gid[idx[i]];
+            dst[i].reserved = 0;
+            dst[i].step = stp[idx[i]];
+            dst[i].t_ms = t[idx[i]];
+        }
+    }
+    *n_out = n;
+    s->sp_user = have;
+    // everything returned and exchanged: start the buffer over
+    if (c.sp_exch == have && have == c.sp_count && (c.flags & kFlagSpikeOverflow) == 0) {
+        Counters z = c;
+        z.sp_count = 0;
+        z.sp_exch = 0;
+        HIP_TRY(hipMemcpyAsync(s->d_ctr, &z, sizeof z, hipMemcpyHostToDevice, s->st));
+        HIP_TRY(hipStreamSynchronize(s->st));
+        s->sp_user = 0;
+    }
+    if (c.flags & (kFlagSpikeOverflow | kFlagEventOverflow))
+        return fail(ARB_EOVERFLOW, (c.flags & kFlagSpikeOverflow) ? "spike buffer overflowed: spikes were lost"
+                                                                  : "event buffer overflowed: events were lost");
+    return ARB_OK;
+}
+
+int arb_set_probes(arb_sim s_, const int64_t* cv, int32_t n, int64_t max_steps) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s) return fail(ARB_EINVAL, "sim is NULL");
+    if (n < 0 || (n > 0 && !cv) || max_steps < 0) return fail(ARB_EINVAL, "bad probe arguments");
+    for (int32_t k = 0; k < n; ++k)
+        if (cv[k] < 0 || cv[k] >= s->L.n_cv) return fail(ARB_EINVAL, "probe CV out of range");
+    Lowered& L = s->L;
+    const int np = int(L.packs.size());
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> per(np);
+    std::vector<int64_t> pack_of_slot_begin(np);
+    for (int32_t k = 0; k < n; ++k) {
+        const int64_t slot = L.perm[cv[k]];
+        const int64_t pk = std::upper_bound(L.packs.begin(), L.packs.end(), slot,
+                                            [](int64_t x, const PackDesc& D) { return x < D.slot0; }) -
+                           L.packs.begin() - 1;
+        per[pk].push_back({int32_t(slot - L.packs[pk].slot0), k});
+    }
+    std::vector<int32_t> ps, pid;
+    for (int k = 0; k < np; ++k) {
+        L.packs[k].pr0 = int32_t(ps.size());
+        L.packs[k].npr = int32_t(per[k].size());
+        for (auto& q : per[k]) {
+            ps.push_back(q.first);
+            pid.push_back(q.second);
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s->st));
+    int rc = ARB_OK;
+    s->d_pr_slot = dupload(s, ps, rc);
+    s->d_pr_id = dupload(s, pid, rc);
+    if (rc == ARB_OK) rc = s->upload(s->d_pk, L.packs.data(), L.packs.size() * sizeof(PackDesc));
+    s->d_trace = (n > 0 && max_steps > 0) ? dalloc<double>(s, size_t(n) * size_t(max_steps), rc) : nullptr;
+    if (rc != ARB_OK) return rc;
+    s->n_probe = n;
+    s->trace_cap = (n > 0) ? max_steps : 0;
+    s->trace_step0 = s->step;
+    HIP_TRY(hipStreamSynchronize(s->st));
+    return ARB_OK;
+}
+
+int arb_get_trace(arb_sim s_, double* dst, int64_t cap, int dst_on_device, int64_t* n_steps_out) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s || !n_steps_out) return fail(ARB_EINVAL, "null argument");
+    *n_steps_out = 0;
+    if (s->n_probe == 0) return ARB_OK;
+    const int64_t rec = std::min(s->step - s->trace_step0, s->trace_cap);
+    if (rec > cap) return fail(ARB_EOVERFLOW, "destination holds fewer steps than were recorded");
+    if (rec > 0) {
+        if (!dst) return fail(ARB_EINVAL, "dst is NULL");
+        HIP_TRY(hipMemcpy2DAsync(dst, size_t(cap) * 8, s->d_trace, size_t(s->trace_cap) * 8, size_t(rec) * 8,
+                                 size_t(s->n_probe), dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                 s->st));
+    }
+    HIP_TRY(hipStreamSynchronize(s->st));
+    *n_steps_out = rec;
+    s->trace_step0 = s->step;
+    return ARB_OK;
+}
+
+int arb_set_params(arb_sim s_, const double* theta, int64_t n) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s || !theta) return fail(ARB_EINVAL, "null argument");
+    Lowered& L = s->L;
+    if (n != 3 * int64_t(L.regions.size())) return fail(ARB_EINVAL, "theta must hold 3 values per region");
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(theta[k])) return fail(ARB_EINVAL, "theta not finite");
+    for (size_t r = 0; r < L.regions.size(); ++r) {
+        L.regions[r].gna = theta[3 * r + 0];
+        L.regions[r].gk = theta[3 * r + 1];
+        L.regions[r].gpas = theta[3 * r + 2];
+    }
+    recompute_coefficients(L);
+    HIP_TRY(hipStreamSynchronize(s->st));
+    int rc = s->upload(s->d_alpha, L.alpha.data(), L.alpha.size() * 8);
+    if (rc == ARB_OK) rc = s->upload(s->d_beta, L.beta.data(), L.beta.size() * 8);
+    if (rc == ARB_OK) rc = s->upload(s->d_hh_gna, L.hh_gna.data(), L.hh_gna.size() * 8);
+    if (rc == ARB_OK) rc = s->upload(s->d_hh_gk, L.hh_gk.data(), L.hh_gk.size() * 8);
+    if (rc != ARB_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s->st));
+    s->grad_valid = false;
+    return ARB_OK;
+}
+
+// blob: header, then V, hh m/h/n, syn g, ext cursors, net cursors, bucket
+// counts and keys, counters, spike buffer
+struct StateHeader {
+    uint64_t magic;
+    int64_t step, n_slots, n_hh, n_syn, n_packs, n_bk, bk_cap, sp_cap, sp_user;
+};
+static const uint64_t kMagic = 0x41524232535441ull;
+
+int arb_get_state(arb_sim s_, void* blob, int64_t cap, int64_t* n_out) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s || !n_out) return fail(ARB_EINVAL, "null argument");
+    const Lowered& L = s->L;
+    const int64_t np = int64_t(L.packs.size()), nbk = int64_t(s->n_buckets) * np;
+    const int64_t nhh = int64_t(L.hh_cv.size()), nsyn = int64_t(L.syn_global.size());
+    struct Part { const void* d; int64_t bytes; };
+    const Part parts[] = {{s->d_V, L.n_slots * 8},   {s->d_hh_m, nhh * 8},  {s->d_hh_h, nhh * 8},
+                          {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
+                          {s->d_pk_ncur, np * 4},    {s->d_bk_cnt, nbk * 4}, {s->d_bk_ev, nbk * s->bk_cap * 8},
+                          {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
+                          {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8}};
+    int64_t total = sizeof(StateHeader);
+    for (const Part& q : parts) total += q.bytes;
+    *n_out = total;
+    if (!blob) return ARB_OK;
+    if (cap < total) return fail(ARB_EOVERFLOW, "state blob capacity too small");
+    StateHeader h{kMagic, s->step, L.n_slots, nhh, nsyn, np, nbk, s->bk_cap, s->sp_cap, s->sp_user};
+    char* out = static_cast<char*>(blob);
+    std::memcpy(out, &h, sizeof h);
+    int64_t at = sizeof h;
+    for (const Part& q : parts) {
+        if (q.bytes) HIP_TRY(hipMemcpyAsync(out + at, q.d, size_t(q.bytes), hipMemcpyDeviceToHost, s->st));
+        at += q.bytes;
+    }
+    HIP_TRY(hipStreamSynchronize(s->st));
+    return ARB_OK;
+}
+
+int arb_set_state(arb_sim s_, const void* blob, int64_t n) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s || !blob) return fail(ARB_EINVAL, "null argument");
+    const Lowered& L = s->L;
+    if (n < int64_t(sizeof(StateHeader))) return fail(ARB_EINVAL, "state blob too small");
+    StateHeader h;
+    std::memcpy(&h, blob, sizeof h);
+    const int64_t np = int64_t(L.packs.size()), nbk = int64_t(s->n_buckets) * np;
+    const int64_t nhh = int64_t(L.hh_cv.size()), nsyn = int64_t(L.syn_global.size());
+    if (h.magic != kMagic || h.n_slots != L.n_slots || h.n_hh != nhh || h.n_syn != nsyn || h.n_packs != np ||
+        h.n_bk != nbk || h.bk_cap != s->bk_cap || h.sp_cap != int64_t(s->sp_cap))
+        return fail(ARB_EINVAL, "state blob does not belong to this model");
+    struct Part { void* d; int64_t bytes; };
+    const Part parts[] = {{s->d_V, L.n_slots * 8},   {s->d_hh_m, nhh * 8},  {s->d_hh_h, nhh * 8},
+                          {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
+                          {s->d_pk_ncur, np * 4},    {s->d_bk_cnt, nbk * 4}, {s->d_bk_ev, nbk * s->bk_cap * 8},
+                          {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
+                          {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8}};
+    int64_t total = sizeof(StateHeader);
+    for (const Part& q : parts) total += q.bytes;
+    if (n < total) return fail(ARB_EINVAL, "state blob truncated");
+    const char* in = static_cast<const char*>(blob);
+    int64_t at = sizeof h;
+    HIP_TRY(hipStreamSynchronize(s->st));
+    for (const Part& q : parts) {
+        if (q.bytes) HIP_TRY(hipMemcpyAsync(q.d, in + at, size_t(q.bytes), hipMemcpyHostToDevice, s->st));
+        at += q.bytes;
+    }
+    HIP_TRY(hipStreamSynchronize(s->st));
+    s->step = h.step;
+    s->sp_user = uint32_t(h.sp_user);
+    s->trace_step0 = s->step;
+    s->grad_valid = false;
+    return ARB_OK;
+}
+
+int arb_get_info(arb_sim s_, arb_info* info) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s || !info) return fail(ARB_EINVAL, "null argument");
+    const Lowered& L = s->L;
+    arb_info I{};
+    I.n_cells = L.n_cells;
+    I.n_packs = int32_t(L.packs.size());
+    I.n_cv = L.n_cv;
+    I.n_slots = L.n_slots;
+    I.n_hh = int64_t(L.hh_cv.size());
+    I.n_syn = int64_t(L.syn_global.size());
+    I.n_conn = int64_t(L.out_rank.size());
+    I.step = s->step;
+    I.epoch_steps = s->K;
+    I.block_threads = s->cfg.block_threads;
+    I.coef_mode = s->cfg.coef_mode;
+    I.lds_bytes = s->cfg.lds_bytes;
+    I.device_bytes = s->device_bytes;
+    // algorithmic bytes of one step in the SoA model: per CV V read+write,
+    // c, sigma, parent index, pas conductance (44 B); per hh instance three
+    // gates read+write plus a weight (56 B); per synapse g read+write plus
+    // its CV index (20 B)
+    I.bytes_per_step = 44 * L.n_cv + 56 * I.n_hh + 20 * I.n_syn;
+    *info = I;
+    return ARB_OK;
+}
+
+int arb_get_kernel_time(arb_sim s_, double* ms_total, int64_t* n_launches) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s || !ms_total || !n_launches) return fail(ARB_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(s->st));
+    double tot = 0.0;
+    for (auto& pr : s->timer_pending) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+        tot += ms;
+        s->timer_free.push_back(pr.first);
+        s->timer_free.push_back(pr.second);
+    }
+    *ms_total = tot;
+    *n_launches = int64_t(s->timer_pending.size());
+    s->timer_pending.clear();
+    return ARB_OK;
+}
+
+int arb_sync(arb_sim s_) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s) return fail(ARB_EINVAL, "sim is NULL");
+    HIP_TRY(hipStreamSynchronize(s->st));
+    bool sl = false, el = false;
+    int rc = s->check_flags(sl, el);
+    if (rc != ARB_OK) return rc;
+    if (sl) return fail(ARB_EOVERFLOW, "spike buffer overflowed: spikes were lost");
+    if (el) return fail(ARB_EOVERFLOW, "event buffer overflowed: events were lost");
+    return ARB_OK;
+}
+
+int arb_free(arb_sim s_) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s) return ARB_OK;
+    (void)hipStreamSynchronize(s->st);
+    for (hipEvent_t e : s->timer_free) (void)hipEventDestroy(e);
+    for (auto& pr : s->timer_pending) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    s->release_all();
+    delete s;
+    return ARB_OK;
+}
+
+const char* arb_last_error(void) { return g_err.c_str(); }
+
+int arb_grad_forward(arb_sim s_, int64_t n_steps, int32_t ckpt_every, double* trace_dev) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s) return fail(ARB_EINVAL, "sim is NULL");
+    return grad_forward(s, n_steps, ckpt_every, trace_dev);
+}
+
+int arb_grad_backward(arb_sim s_, const double* dL_dtrace_dev, double* dL_dtheta_dev) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s) return fail(ARB_EINVAL, "sim is NULL");
+    return grad_backward(s, dL_dtrace_dev, dL_dtheta_dev);
+}
+
+}  // extern "C"
+
+namespace arbmi {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+int set_hip_error(hipError_t e, const char* where) { return hip_fail(e, where); }
+}  // namespace arbmi

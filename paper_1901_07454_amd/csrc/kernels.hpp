@@ -1,0 +1,121 @@
+// kernels.hpp -- launch interface of the HIP kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.hpp"
+
+namespace arbmi {
+
+// Everything the fused step kernel reads or writes.  All pointers are device
+// pointers into the sim's arena.
+struct StepArgs {
+    const PackDesc* pk;
+    const RoundDesc* rd;
+    const TaskDesc* tk;
+    const int32_t* ch_slot;
+    const NlDesc* nl;
+    const int32_t* pc_gid;
+    const int32_t* pc_soma;
+    double* V;                 // [n_slots]
+    const double* alpha;
+    const double* beta;
+    const double* F;
+    const double* invd;
+    double* hh_m;              // [n_hh] gates
+    double* hh_h;
+    double* hh_n;
+    const double* hh_gna;      // nS
+    const double* hh_gk;
+    double* syn_g;             // [n_syn] nS
+    const double* syn_e;
+    const double* syn_decay;   // exp(-dt/tau)
+    const int64_t* ic_on;
+    const int64_t* ic_off;
+    const double* ic_amp;      // pA
+    const int64_t* xe_step;    // external events
+    const int32_t* xe_syn;
+    const double* xe_w;        // nS
+    int64_t* pk_xcur;          // [n_packs] cursor into the external events
+    // network events of the current epoch: per pack a sorted run of keys
+    // (delivery step << 32 | connection rank)
+    const uint64_t* bk_ev;     // [NB][n_packs][bk_cap]
+    uint32_t* bk_cnt;          // [NB][n_packs] (the step kernel clears its run at the epoch end)
+    int32_t* pk_ncur;          // [n_packs] cursor into the current bucket
+    int32_t bk_cap;
+    int32_t bucket;            // bucket of the current epoch
+    int32_t n_packs;
+    int32_t pad0;
+    const int32_t* cr_syn;     // per connection rank: pack-local synapse
+    const double* cr_w;        //   weight nS
+    // spikes
+    uint32_t* sp_gid;
+    int64_t* sp_step;
+    double* sp_t;
+    uint32_t sp_cap;
+    uint32_t pad1;
+    Counters* ctr;
+    // probes
+    const int32_t* pr_slot;    // per pack probe entries (pack-local slot)
+    const int32_t* pr_id;
+    double* trace;             // [n_probe][trace_cap]
+    int64_t trace_cap;
+    int64_t trace_step0;       // step whose end value goes to column 0
+    // gradient checkpoint recording (null when not recording): per step of
+    // the launch, the state before the step
+    double* rec_V;             // [nsteps][n_slots]
+    double* rec_m;             // [nsteps][n_hh] ...
+    double* rec_h;
+    double* rec_n;
+    double* rec_g;             // [nsteps][n_syn] g after the step's events
+    int64_t n_slots_total;
+    int64_t n_hh_total;
+    int64_t n_syn_total;
+    double dt;
+    double threshold;
+    int64_t step0;             // first step of this launch
+    int32_t nsteps;            // steps in this launch
+    int32_t epoch_end;         // 1 if the launch completes an epoch (reset the bucket)
+};
+
+// Per-launch configuration chosen by the host.
+struct LaunchCfg {
+    int block_threads;  // 64, 128, 256
+    int coef_mode;      // 1 LDS, 2 streamed
+    int lds_bytes;      // dynamic LDS per workgroup
+};
+
+hipError_t launch_step(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st);
+hipError_t prepare_step_kernels(int max_lds_bytes);
+
+// Sort each pack's run of network events of `bucket` (keys ascending) and
+// reset the packs' cursors.  Flags an overflow if a run exceeded bk_cap.
+hipError_t launch_sort_buckets(uint64_t* bk_ev, uint32_t* bk_cnt, int32_t* pk_ncur, int32_t bk_cap,
+                               int32_t bucket, int32_t n_packs, Counters* ctr, hipStream_t st);
+
+// Turn the spikes [ctr.sp_exch, ctr.sp_count) into network events.
+struct ExchArgs {
+    const uint32_t* sp_gid;
+    const int64_t* sp_step;
+    const int64_t* out_off;
+    const uint32_t* out_rank;
+    const int32_t* cr_pack;
+    const int32_t* cr_delay;
+    uint64_t* bk_ev;
+    uint32_t* bk_cnt;
+    int32_t bk_cap;
+    int32_t n_buckets;
+    int32_t n_packs;
+    int32_t epoch_steps;
+    uint32_t sp_cap;
+    uint32_t pad;
+    Counters* ctr;
+};
+hipError_t launch_exchange(const ExchArgs& a, int grid, hipStream_t st);
+
+// dst[i] = V[perm[i]] for i < n
+hipError_t launch_gather(const double* V, const int64_t* perm, double* dst, int64_t n, hipStream_t st);
+// V[perm[i]] = src[i]
+hipError_t launch_scatter(double* V, const int64_t* perm, const double* src, int64_t n, hipStream_t st);
+
+}  // namespace arbmi

@@ -1,0 +1,76 @@
+// layout.hpp -- device-side data layout shared by the host lowering and the
+// HIP kernels of the cell stepper.
+//
+// A *pack* is the set of cells one workgroup advances.  Its control volumes
+// (CVs) occupy a contiguous run of *slots*.  Cells' branches are grouped by
+// depth in the branch tree (the soma is depth 0, a branch hanging off the
+// soma depth 1, ...); the branches of one depth in a pack form one or more
+// *rounds* of at most `block_threads` branches.  In a round of width w and
+// length L (its longest branch), CV k (0 = proximal) of the branch handled by
+// thread t sits at slot  round.slot0 + k*w + t, so that the threads of a
+// round touch consecutive slots (coalesced in HBM, conflict-free in LDS).
+// Rounds are stored deepest first: the elimination sweep runs them in order
+// and the substitution sweep in reverse.
+#pragma once
+#include <stdint.h>
+
+namespace arbmi {
+
+// hh reversal potentials (mV): textbook squid-axon values
+constexpr double kENa = 50.0;
+constexpr double kEK = -77.0;
+constexpr double kEL = -54.3;
+
+struct PackDesc {
+    int64_t slot0;   // first global slot of the pack
+    int32_t nslot;   // slots (incl. padding)
+    int32_t rd0;     // first round
+    int32_t nrd;     // rounds
+    int32_t cell0;   // first entry in the pack-cell arrays
+    int32_t ncell;
+    int32_t nl0;     // first nonlinear CV entry (CVs with hh, synapses or clamps)
+    int32_t nnl;
+    int32_t hh0;     // first hh instance
+    int32_t nhh;
+    int32_t syn0;    // first synapse (pack-local synapse q is global q - syn0 + syn0)
+    int32_t nsyn;
+    int32_t pr0;     // probes
+    int32_t npr;
+    int32_t pad;
+    int64_t xe0, xe1; // external events [xe0, xe1), sorted by (step, syn, input order)
+};
+
+struct RoundDesc {
+    int32_t slot0;  // pack-local slot of (k = 0, t = 0)
+    int32_t w;      // branches in the round
+    int32_t len;    // longest branch
+    int32_t task0;  // first task (one per branch)
+};
+
+struct TaskDesc {
+    int32_t len;    // CVs of the branch (1 for a soma)
+    int32_t par;    // pack-local slot of the parent CV of the proximal CV, -1 at a soma
+    int32_t ch0;    // children: ch_slot[ch0 .. ch0+nch), pack-local slots of the
+    int32_t nch;    //   proximal CVs of the child branches, in branch order
+};
+
+struct NlDesc {     // one CV carrying nonlinear or point terms
+    int32_t slot;   // pack-local slot
+    int32_t hh;     // pack-local hh instance, -1 if none
+    int32_t syn0;   // pack-local synapses [syn0, syn0 + nsyn)
+    int32_t nsyn;
+    int32_t ic0;    // global clamp entries [ic0, ic0 + nic)
+    int32_t nic;
+};
+
+// Device counters and flags of a sim.
+struct Counters {
+    uint32_t sp_count;      // spikes in the buffer
+    uint32_t sp_exch;       // spikes [0, sp_exch) already exchanged
+    uint32_t flags;         // kFlag*
+    uint32_t pad;
+};
+constexpr uint32_t kFlagSpikeOverflow = 1u;
+constexpr uint32_t kFlagEventOverflow = 2u;
+
+}  // namespace arbmi

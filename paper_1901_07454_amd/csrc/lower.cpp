@@ -1,0 +1,576 @@
+// lower.cpp -- validation, discretisation and packing of a model (host).
+//
+// Discretisation follows Sec. II of the Arbor paper (vertex-centred finite
+// volumes with first-order axial flux, eq. 2a) with these choices for what
+// the paper leaves open: a branch of length L split into n CVs has nodes at
+// k L/n (k = 1..n) from its proximal end; node k's CV is [x_k - h/2, x_k +
+// h/2] clipped to the branch, so a branch end without children is a sealed
+// half-CV and the parent node owns the first half-segment; the soma is one
+// isopotential node of the given area; a mechanism acts on the part of a CV's
+// membrane that carries it.
+//
+// The implicit-Euler matrix (Sec. II) is c_i/dt on the diagonal plus the
+// weighted Laplacian of the CV tree.  The membrane current is explicit in
+// the scheme, so for a fixed dt the matrix never changes: its leaves-to-root
+// elimination (extended Thomas / Hines) is done here once, and the kernels
+// only replay the right-hand-side part of the elimination and the
+// substitution every step, using
+//   F_i = u_i / d'_i  (u_i = -sigma_i, d'_i the eliminated diagonal)
+//   rhs'_p -= F_c rhs'_c     (elimination, children c of p)
+//   x_i = rhs'_i / d'_i - F_i x_parent(i)  (substitution).
+#include "lower.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <numeric>
+#include <sstream>
+
+namespace arbmi {
+
+int64_t pack_lds_bytes(int64_t nslot, int64_t nsyn, int64_t nhh, int coef_mode) {
+    const int64_t per_slot = (coef_mode == 1) ? 6 : 2;  // V, R (+ alpha, beta, F, invd)
+    return 8 * (per_slot * nslot + nsyn + 3 * nhh);
+}
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+
+struct CellCV {
+    int ncv = 0;
+    std::vector<int> parent;        // local parent, -1 at the soma
+    std::vector<double> cap, sig;   // pF, nS to parent
+    std::vector<int> first;         // first local CV of each branch
+    std::vector<int> depth;         // per branch (soma = 0, root branch = 1)
+    std::vector<int> pnode;         // per branch: local CV the branch hangs from
+};
+
+template <class... A>
+std::string fmt(const char* f, A... a) {
+    char buf[512];
+    std::snprintf(buf, sizeof buf, f, a...);
+    return buf;
+}
+
+// local CV index of (branch, cv) in a cell, or -1 if out of range
+int64_t locate(const arb_cell& c, const arb_branch* br, const std::vector<int>& first, int32_t b,
+               int32_t k) {
+    if (b == -1) return k == 0 ? 0 : -1;
+    if (b < -1 || b >= c.n_branch) return -1;
+    if (k < 0 || k >= br[c.branch_begin + b].n_cv) return -1;
+    return first[b] + k;
+}
+
+// One candidate pack: which cells, and the slot layout that results.
+struct PackPlan {
+    std::vector<int32_t> cells;
+    int64_t nslot = 0;
+    int64_t nsyn = 0, nhh = 0;
+};
+
+}  // namespace
+
+int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, int64_t n_br,
+                const arb_synapse* syn, int64_t n_syn, const arb_connection* conn, int64_t n_conn,
+                const arb_event* ev, int64_t n_ev, const arb_iclamp* ic, int32_t n_ic,
+                const arb_params& p, const LowerOptions& opt, Lowered& L, std::string& err) {
+    // ---------------------------------------------------------------- checks
+    if (n_cells < 1) { err = "n_cells must be >= 1"; return ARB_EINVAL; }
+    if (!cells || (n_br > 0 && !br)) { err = "null cell or branch array"; return ARB_EINVAL; }
+    if (n_br < 0 || n_syn < 0 || n_conn < 0 || n_ev < 0 || n_ic < 0) { err = "negative count"; return ARB_EINVAL; }
+    if ((n_syn && !syn) || (n_conn && !conn) || (n_ev && !ev) || (n_ic && !ic)) {
+        err = "null array with a positive count"; return ARB_EINVAL;
+    }
+    if (!(p.dt_ms > 0) || !std::isfinite(p.dt_ms)) { err = "dt must be positive"; return ARB_EINVAL; }
+    if (!std::isfinite(p.threshold_mV) || !std::isfinite(p.v_init_mV)) { err = "threshold/v_init not finite"; return ARB_EINVAL; }
+    if (p.epoch_steps < 0) { err = "epoch_steps must be >= 0"; return ARB_EINVAL; }
+    L.dt = p.dt_ms;
+    L.threshold = p.threshold_mV;
+    L.v_init = p.v_init_mV;
+    L.n_cells = n_cells;
+    const double dt = p.dt_ms;
+
+    std::vector<CellCV> geo(n_cells);
+    L.cell_cv0.assign(n_cells + 1, 0);
+    L.cell_reg0.assign(n_cells + 1, 0);
+    int64_t br_seen = 0;
+    for (int32_t c = 0; c < n_cells; ++c) {
+        const arb_cell& C = cells[c];
+        if (C.n_branch < 0 || C.branch_begin < 0 || C.branch_begin + C.n_branch > n_br) {
+            err = fmt("cell %d: branch range out of bounds", c); return ARB_EINVAL;
+        }
+        if (!(C.soma_area_um2 > 0) || !(C.cm_uF_cm2 > 0) || !(C.Ra_ohm_cm > 0) ||
+            !std::isfinite(C.soma_area_um2) || !std::isfinite(C.cm_uF_cm2) || !std::isfinite(C.Ra_ohm_cm)) {
+            err = fmt("cell %d: soma area, cm and Ra must be positive", c); return ARB_EINVAL;
+        }
+        const double sg[5] = {C.soma_gbar_na, C.soma_gbar_k, C.soma_gl_hh, C.soma_g_pas, C.soma_e_pas};
+        for (double x : sg) if (!std::isfinite(x)) { err = fmt("cell %d: soma parameter not finite", c); return ARB_EINVAL; }
+        if (C.soma_mech & ~(ARB_MECH_HH | ARB_MECH_PAS)) { err = fmt("cell %d: unknown soma mechanism bits", c); return ARB_EINVAL; }
+        int64_t ncv = 1;
+        for (int32_t b = 0; b < C.n_branch; ++b) {
+            const arb_branch& B = br[C.branch_begin + b];
+            if (B.parent < -1 || B.parent >= b) { err = fmt("cell %d branch %d: parent %d must be -1 or a lower index", c, b, B.parent); return ARB_EINVAL; }
+            if (B.n_cv < 1) { err = fmt("cell %d branch %d: n_cv < 1", c, b); return ARB_EINVAL; }
+            if (!(B.length_um > 0) || !(B.diam_um > 0) || !std::isfinite(B.length_um) || !std::isfinite(B.diam_um)) {
+                err = fmt("cell %d branch %d: length and diameter must be positive", c, b); return ARB_EINVAL;
+            }
+            const double bg[5] = {B.gbar_na, B.gbar_k, B.gl_hh, B.g_pas, B.e_pas};
+            for (double x : bg) if (!std::isfinite(x)) { err = fmt("cell %d branch %d: parameter not finite", c, b); return ARB_EINVAL; }
+            if (B.mech & ~(ARB_MECH_HH | ARB_MECH_PAS)) { err = fmt("cell %d branch %d: unknown mechanism bits", c, b); return ARB_EINVAL; }
+            ncv += B.n_cv;
+        }
+        if (ncv > (1 << 24)) { err = fmt("cell %d: too many CVs", c); return ARB_EINVAL; }
+        br_seen += C.n_branch;
+        L.cell_cv0[c + 1] = L.cell_cv0[c] + ncv;
+        L.cell_reg0[c + 1] = L.cell_reg0[c] + 1 + C.n_branch;
+    }
+    (void)br_seen;
+    L.n_cv = L.cell_cv0[n_cells];
+    const int64_t n_reg = L.cell_reg0[n_cells];
+
+    // ------------------------------------------------- discretisation (eq. 2a)
+    L.regions.resize(n_reg);
+    L.piece_off.assign(L.n_cv + 1, 0);
+    std::vector<std::vector<std::pair<int32_t, double>>> pieces(L.n_cv);
+    for (int32_t c = 0; c < n_cells; ++c) {
+        const arb_cell& C = cells[c];
+        CellCV& G = geo[c];
+        const int64_t cv0 = L.cell_cv0[c], r0 = L.cell_reg0[c];
+        G.ncv = int(L.cell_cv0[c + 1] - cv0);
+        G.parent.assign(G.ncv, -1);
+        G.cap.assign(G.ncv, 0.0);
+        G.sig.assign(G.ncv, 0.0);
+        G.first.assign(C.n_branch, 0);
+        G.depth.assign(C.n_branch, 0);
+        G.pnode.assign(C.n_branch, 0);
+        L.regions[r0] = Region{C.soma_mech, C.soma_gbar_na, C.soma_gbar_k, C.soma_gl_hh, C.soma_g_pas, C.soma_e_pas};
+        pieces[cv0].push_back({int32_t(r0), C.soma_area_um2});
+        int next = 1;
+        for (int32_t b = 0; b < C.n_branch; ++b) { G.first[b] = next; next += br[C.branch_begin + b].n_cv; }
+        for (int32_t b = 0; b < C.n_branch; ++b) {
+            const arb_branch& B = br[C.branch_begin + b];
+            const int32_t r = int32_t(r0 + 1 + b);
+            L.regions[r] = Region{B.mech, B.gbar_na, B.gbar_k, B.gl_hh, B.g_pas, B.e_pas};
+            const double h = B.length_um / B.n_cv;
+            const int pn = (B.parent < 0) ? 0 : G.first[B.parent] + br[C.branch_begin + B.parent].n_cv - 1;
+            G.pnode[b] = pn;
+            G.depth[b] = (B.parent < 0) ? 1 : G.depth[B.parent] + 1;
+            // the parent node's CV reaches h/2 into this branch
+            pieces[cv0 + pn].push_back({r, kPi * B.diam_um * 0.5 * h});
+            // axial conductance between consecutive nodes, cylinder of length h:
+            // pi d^2 / (4 Ra h) S  ==  2.5e4 pi d^2 / (Ra h) nS  (d, h in um)
+            const double sigma = 2.5e4 * kPi * B.diam_um * B.diam_um / (C.Ra_ohm_cm * h);
+            for (int k = 0; k < B.n_cv; ++k) {
+                const int i = G.first[b] + k;
+                G.parent[i] = (k == 0) ? pn : i - 1;
+                G.sig[i] = sigma;
+                const double len = (k + 1 < B.n_cv) ? h : 0.5 * h;  // sealed half at the far end
+                pieces[cv0 + i].push_back({r, kPi * B.diam_um * len});
+            }
+        }
+    }
+    for (int64_t i = 0; i < L.n_cv; ++i) L.piece_off[i + 1] = L.piece_off[i] + int64_t(pieces[i].size());
+    L.piece_reg.resize(L.piece_off[L.n_cv]);
+    L.piece_area.resize(L.piece_off[L.n_cv]);
+    for (int64_t i = 0; i < L.n_cv; ++i)
+        for (size_t k = 0; k < pieces[i].size(); ++k) {
+            L.piece_reg[L.piece_off[i] + k] = pieces[i][k].first;
+            L.piece_area[L.piece_off[i] + k] = pieces[i][k].second;
+        }
+    pieces.clear();
+    pieces.shrink_to_fit();
+
+    std::vector<double> cap_user(L.n_cv, 0.0);
+    std::vector<char> has_hh(L.n_cv, 0);
+    for (int32_t c = 0; c < n_cells; ++c)
+        for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i) {
+            double a = 0.0;
+            for (int64_t k = L.piece_off[i]; k < L.piece_off[i + 1]; ++k) {
+                a += L.piece_area[k];
+                if (L.regions[L.piece_reg[k]].mech & ARB_MECH_HH) has_hh[i] = 1;
+            }
+            cap_user[i] = 0.01 * cells[c].cm_uF_cm2 * a;  // uF/cm^2 x um^2 -> pF
+            geo[c].cap[i - L.cell_cv0[c]] = cap_user[i];
+        }
+
+    // ------------------------------------------------ synapses, clamps, events
+    std::vector<int64_t> syn_cv(n_syn);
+    for (int64_t q = 0; q < n_syn; ++q) {
+        const arb_synapse& S = syn[q];
+        if (S.cell < 0 || S.cell >= n_cells) { err = fmt("synapse %lld: cell out of range", (long long)q); return ARB_EINVAL; }
+        int64_t i = locate(cells[S.cell], br, geo[S.cell].first, S.branch, S.cv);
+        if (i < 0) { err = fmt("synapse %lld: branch/cv out of range", (long long)q); return ARB_EINVAL; }
+        if (!(S.tau_ms > 0) || !std::isfinite(S.tau_ms) || !std::isfinite(S.e_rev_mV)) {
+            err = fmt("synapse %lld: tau must be positive", (long long)q); return ARB_EINVAL;
+        }
+        syn_cv[q] = L.cell_cv0[S.cell] + i;
+    }
+    std::vector<int64_t> ic_cv(n_ic);
+    for (int32_t q = 0; q < n_ic; ++q) {
+        const arb_iclamp& I = ic[q];
+        if (I.cell < 0 || I.cell >= n_cells) { err = fmt("clamp %d: cell out of range", q); return ARB_EINVAL; }
+        int64_t i = locate(cells[I.cell], br, geo[I.cell].first, I.branch, I.cv);
+        if (i < 0) { err = fmt("clamp %d: branch/cv out of range", q); return ARB_EINVAL; }
+        if (!std::isfinite(I.amp_nA)) { err = fmt("clamp %d: amplitude not finite", q); return ARB_EINVAL; }
+        ic_cv[q] = L.cell_cv0[I.cell] + i;
+    }
+    for (int64_t q = 0; q < n_ev; ++q) {
+        if (int64_t(ev[q].syn) >= n_syn) { err = fmt("event %lld: synapse out of range", (long long)q); return ARB_EINVAL; }
+        if (ev[q].step < 0 || ev[q].step >= (int64_t(1) << 31)) { err = fmt("event %lld: step out of range", (long long)q); return ARB_EINVAL; }
+        if (!std::isfinite(ev[q].w_uS)) { err = fmt("event %lld: weight not finite", (long long)q); return ARB_EINVAL; }
+    }
+    L.min_delay = 0;
+    L.max_delay = 0;
+    for (int64_t q = 0; q < n_conn; ++q) {
+        const arb_connection& K = conn[q];
+        if (K.src >= uint32_t(n_cells) || K.dst >= uint32_t(n_cells)) { err = fmt("connection %lld: cell out of range", (long long)q); return ARB_EINVAL; }
+        if (int64_t(K.syn) >= n_syn || syn[K.syn].cell != int32_t(K.dst)) {
+            err = fmt("connection %lld: synapse not on the destination cell", (long long)q); return ARB_EINVAL;
+        }
+        if (K.delay_steps < 1) { err = fmt("connection %lld: delay_steps must be >= 1", (long long)q); return ARB_EINVAL; }
+        if (!std::isfinite(K.w_uS)) { err = fmt("connection %lld: weight not finite", (long long)q); return ARB_EINVAL; }
+        L.min_delay = q == 0 ? K.delay_steps : std::min(L.min_delay, K.delay_steps);
+        L.max_delay = std::max(L.max_delay, K.delay_steps);
+    }
+    if (n_conn && p.epoch_steps > L.min_delay) {
+        err = fmt("epoch_steps %d exceeds the minimum delay %d", p.epoch_steps, L.min_delay); return ARB_EINVAL;
+    }
+
+    // per-CV markers for the nonlinear list
+    std::vector<int32_t> nsyn_cv(L.n_cv, 0), nic_cv(L.n_cv, 0);
+    for (int64_t q = 0; q < n_syn; ++q) nsyn_cv[syn_cv[q]]++;
+    for (int32_t q = 0; q < n_ic; ++q) nic_cv[ic_cv[q]]++;
+    std::vector<int32_t> nhh_cell(n_cells, 0), nsyn_cell(n_cells, 0);
+    for (int32_t c = 0; c < n_cells; ++c)
+        for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i) {
+            nhh_cell[c] += has_hh[i];
+            nsyn_cell[c] += nsyn_cv[i];
+        }
+
+    // -------------------------------------------------------------- packing
+    const int T = opt.block_threads;
+    L.block_threads = T;
+    // slot count of a set of cells under the round layout
+    auto plan_slots = [&](const std::vector<int32_t>& cs) -> int64_t {
+        int maxd = 0;
+        for (int32_t c : cs) for (int d : geo[c].depth) maxd = std::max(maxd, d);
+        int64_t ns = 0;
+        for (int d = maxd; d >= 0; --d) {
+            std::vector<int> lens;
+            for (int32_t c : cs) {
+                if (d == 0) { lens.push_back(1); continue; }
+                for (int32_t b = 0; b < cells[c].n_branch; ++b)
+                    if (geo[c].depth[b] == d) lens.push_back(br[cells[c].branch_begin + b].n_cv);
+            }
+            for (size_t s = 0; s < lens.size(); s += T) {
+                size_t e = std::min(lens.size(), s + T);
+                int mx = *std::max_element(lens.begin() + s, lens.begin() + e);
+                ns += int64_t(mx) * int64_t(e - s);
+            }
+        }
+        return ns;
+    };
+    std::vector<int32_t> order(n_cells);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return geo[a].ncv > geo[b].ncv; });
+    const int64_t max_cells = std::max<int64_t>(1, std::min<int64_t>(T, opt.max_cells_per_pack));
+    std::vector<PackPlan> plans;
+    int coef_mode = opt.coef_mode;
+    {
+        PackPlan cur;
+        for (int32_t c : order) {
+            PackPlan trial = cur;
+            trial.cells.push_back(c);
+            trial.nsyn += nsyn_cell[c];
+            trial.nhh += nhh_cell[c];
+            bool fits = int64_t(trial.cells.size()) <= max_cells;
+            if (fits && !cur.cells.empty()) {
+                trial.nslot = plan_slots(trial.cells);
+                fits = pack_lds_bytes(trial.nslot, trial.nsyn, trial.nhh, coef_mode) <= opt.lds_budget;
+            }
+            if (!fits) {
+                plans.push_back(cur);
+                cur = PackPlan();
+                cur.cells.push_back(c);
+                cur.nsyn = nsyn_cell[c];
+                cur.nhh = nhh_cell[c];
+                cur.nslot = plan_slots(cur.cells);
+            } else {
+                if (cur.cells.empty()) trial.nslot = plan_slots(trial.cells);
+                cur = trial;
+            }
+        }
+        if (!cur.cells.empty()) plans.push_back(cur);
+    }
+    for (const PackPlan& pp : plans)
+        if (pack_lds_bytes(pp.nslot, pp.nsyn, pp.nhh, coef_mode) > opt.lds_hard_max) {
+            err = fmt("a cell needs %lld bytes of LDS, more than the %lld available",
+                      (long long)pack_lds_bytes(pp.nslot, pp.nsyn, pp.nhh, coef_mode), (long long)opt.lds_hard_max);
+            return ARB_EINVAL;
+        }
+    L.coef_mode = coef_mode;
+
+    // ------------------------------------------------- slot layout per pack
+    const int64_t n_packs = int64_t(plans.size());
+    L.packs.resize(n_packs);
+    L.perm.assign(L.n_cv, -1);
+    std::vector<int64_t> pack_of_cell(n_cells), slot_of_user(L.n_cv, -1);
+    int64_t slot_base = 0;
+    for (int64_t pk = 0; pk < n_packs; ++pk) {
+        const PackPlan& pp = plans[pk];
+        PackDesc& D = L.packs[pk];
+        D = PackDesc{};
+        D.slot0 = slot_base;
+        D.rd0 = int32_t(L.rounds.size());
+        D.cell0 = int32_t(L.pc_gid.size());
+        D.ncell = int32_t(pp.cells.size());
+        int maxd = 0;
+        for (int32_t c : pp.cells) {
+            pack_of_cell[c] = pk;
+            for (int d : geo[c].depth) maxd = std::max(maxd, d);
+        }
+        // rounds, deepest first; a task is (cell, branch) with branch -1 = soma
+        struct Item { int32_t c, b; int len; };
+        std::vector<std::vector<Item>> rounds_items;
+        int64_t ns = 0;
+        std::vector<RoundDesc> rds;
+        for (int d = maxd; d >= 0; --d) {
+            std::vector<Item> items;
+            for (int32_t c : pp.cells) {
+                if (d == 0) { items.push_back({c, -1, 1}); continue; }
+                for (int32_t b = 0; b < cells[c].n_branch; ++b)
+                    if (geo[c].depth[b] == d) items.push_back({c, b, br[cells[c].branch_begin + b].n_cv});
+            }
+            for (size_t s = 0; s < items.size(); s += T) {
+                size_t e = std::min(items.size(), s + size_t(T));
+                std::vector<Item> ri(items.begin() + s, items.begin() + e);
+                int mx = 0;
+                for (auto& it : ri) mx = std::max(mx, it.len);
+                RoundDesc R{int32_t(ns), int32_t(ri.size()), mx, 0};
+                // slots of every CV of the round
+                for (size_t t = 0; t < ri.size(); ++t) {
+                    const Item& it = ri[t];
+                    const int64_t cv0 = L.cell_cv0[it.c];
+                    if (it.b < 0) {
+                        slot_of_user[cv0] = slot_base + ns + int64_t(t);
+                    } else {
+                        for (int k = 0; k < it.len; ++k)
+                            slot_of_user[cv0 + geo[it.c].first[it.b] + k] = slot_base + ns + int64_t(k) * int64_t(ri.size()) + int64_t(t);
+                    }
+                }
+                ns += int64_t(mx) * int64_t(ri.size());
+                rds.push_back(R);
+                rounds_items.push_back(std::move(ri));
+            }
+        }
+        D.nslot = int32_t(ns);
+        D.nrd = int32_t(rds.size());
+        // tasks (need every slot assigned first, for parents and children)
+        for (size_t r = 0; r < rds.size(); ++r) {
+            rds[r].task0 = int32_t(L.tasks.size());
+            for (const Item& it : rounds_items[r]) {
+                const int64_t cv0 = L.cell_cv0[it.c];
+                TaskDesc T_{};
+                T_.len = it.len;
+                T_.par = (it.b < 0) ? -1 : int32_t(slot_of_user[cv0 + geo[it.c].pnode[it.b]] - slot_base);
+                T_.ch0 = int32_t(L.ch_slot.size());
+                T_.nch = 0;
+                for (int32_t b2 = 0; b2 < cells[it.c].n_branch; ++b2)
+                    if (br[cells[it.c].branch_begin + b2].parent == it.b) {
+                        L.ch_slot.push_back(int32_t(slot_of_user[cv0 + geo[it.c].first[b2]] - slot_base));
+                        T_.nch++;
+                    }
+                L.tasks.push_back(T_);
+            }
+            L.rounds.push_back(rds[r]);
+        }
+        for (int32_t c : pp.cells) {
+            L.pc_gid.push_back(c);
+            L.pc_soma.push_back(int32_t(slot_of_user[L.cell_cv0[c]] - slot_base));
+        }
+        slot_base += ns;
+    }
+    L.n_slots = slot_base;
+    L.perm = slot_of_user;
+    L.slot_cell.assign(L.n_slots, -1);
+    for (int32_t c = 0; c < n_cells; ++c)
+        for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i) L.slot_cell[L.perm[i]] = c;
+
+    // --------------------------------------- coefficients and factorisation
+    L.cap.assign(L.n_slots, 0.0);
+    L.alpha.assign(L.n_slots, 0.0);
+    L.beta.assign(L.n_slots, 0.0);
+    L.F.assign(L.n_slots, 0.0);
+    L.invd.assign(L.n_slots, 0.0);
+    L.d_elim.assign(L.n_slots, 0.0);
+    for (int32_t c = 0; c < n_cells; ++c) {
+        const CellCV& G = geo[c];
+        const int64_t cv0 = L.cell_cv0[c];
+        std::vector<double> d(G.ncv);
+        for (int i = 0; i < G.ncv; ++i) d[i] = G.cap[i] / dt;
+        for (int i = 1; i < G.ncv; ++i) { d[i] += G.sig[i]; d[G.parent[i]] += G.sig[i]; }
+        std::vector<double> Fl(G.ncv, 0.0);
+        for (int i = G.ncv - 1; i >= 1; --i) {
+            const double u = -G.sig[i];
+            Fl[i] = u / d[i];
+            d[G.parent[i]] -= Fl[i] * u;
+        }
+        for (int i = 0; i < G.ncv; ++i) {
+            const int64_t s = L.perm[cv0 + i];
+            L.cap[s] = G.cap[i];
+            L.F[s] = Fl[i];
+            L.d_elim[s] = d[i];
+            L.invd[s] = 1.0 / d[i];
+        }
+    }
+
+    // ------------------------------------------- nonlinear CVs per pack
+    std::vector<std::vector<int64_t>> syn_at(L.n_cv), ic_at(L.n_cv);
+    for (int64_t q = 0; q < n_syn; ++q) syn_at[syn_cv[q]].push_back(q);
+    for (int32_t q = 0; q < n_ic; ++q) ic_at[ic_cv[q]].push_back(q);
+    L.syn_pack_index.assign(n_syn, -1);
+    for (int64_t pk = 0; pk < n_packs; ++pk) {
+        PackDesc& D = L.packs[pk];
+        D.nl0 = int32_t(L.nl.size());
+        D.hh0 = int32_t(L.hh_cv.size());
+        D.syn0 = int32_t(L.syn_global.size());
+        std::vector<std::pair<int64_t, int64_t>> here;  // (slot, user cv)
+        for (int32_t k = 0; k < D.ncell; ++k) {
+            const int32_t c = L.pc_gid[D.cell0 + k];
+            for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i)
+                if (has_hh[i] || nsyn_cv[i] || nic_cv[i]) here.push_back({L.perm[i], i});
+        }
+        std::sort(here.begin(), here.end());
+        for (auto& sc : here) {
+            const int64_t i = sc.second;
+            NlDesc N{};
+            N.slot = int32_t(sc.first - D.slot0);
+            N.hh = -1;
+            if (has_hh[i]) { N.hh = int32_t(L.hh_cv.size()) - D.hh0; L.hh_cv.push_back(i); }
+            N.syn0 = int32_t(L.syn_global.size()) - D.syn0;
+            N.nsyn = int32_t(syn_at[i].size());
+            for (int64_t q : syn_at[i]) {
+                L.syn_pack_index[q] = int64_t(L.syn_global.size());
+                L.syn_global.push_back(q);
+                L.syn_e.push_back(syn[q].e_rev_mV);
+                L.syn_decay.push_back(std::exp(-dt / syn[q].tau_ms));
+            }
+            N.ic0 = int32_t(L.ic_on.size());
+            N.nic = int32_t(ic_at[i].size());
+            for (int64_t q : ic_at[i]) {
+                L.ic_on.push_back(ic[q].step_on);
+                L.ic_off.push_back(ic[q].step_off);
+                L.ic_amp.push_back(1000.0 * ic[q].amp_nA);  // nA -> pA
+            }
+            L.nl.push_back(N);
+        }
+        D.nnl = int32_t(L.nl.size()) - D.nl0;
+        D.nhh = int32_t(L.hh_cv.size()) - D.hh0;
+        D.nsyn = int32_t(L.syn_global.size()) - D.syn0;
+    }
+    L.n_hh_total = int64_t(L.hh_cv.size());
+    L.hh_gna.assign(L.hh_cv.size(), 0.0);
+    L.hh_gk.assign(L.hh_cv.size(), 0.0);
+    L.glin_extra.assign(L.n_cv, 0.0);
+    recompute_coefficients(L);
+
+    // external events, grouped per pack, ordered (step, pack synapse, input order)
+    {
+        std::vector<int64_t> idx(n_ev);
+        std::iota(idx.begin(), idx.end(), 0);
+        auto key_pack = [&](int64_t q) { return pack_of_cell[syn[ev[q].syn].cell]; };
+        std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+            const int64_t pa = key_pack(a), pb = key_pack(b);
+            if (pa != pb) return pa < pb;
+            if (ev[a].step != ev[b].step) return ev[a].step < ev[b].step;
+            const int64_t sa = L.syn_pack_index[ev[a].syn], sb = L.syn_pack_index[ev[b].syn];
+            if (sa != sb) return sa < sb;
+            return a < b;
+        });
+        L.xe_step.resize(n_ev);
+        L.xe_syn.resize(n_ev);
+        L.xe_w.resize(n_ev);
+        for (auto& D : L.packs) { D.xe0 = 0; D.xe1 = 0; }
+        int64_t at = 0;
+        for (int64_t pk = 0; pk < n_packs; ++pk) {
+            L.packs[pk].xe0 = at;
+            while (at < n_ev && key_pack(idx[at]) == pk) {
+                const int64_t q = idx[at];
+                L.xe_step[at] = ev[q].step;
+                L.xe_syn[at] = int32_t(L.syn_pack_index[ev[q].syn] - L.packs[pk].syn0);
+                L.xe_w[at] = 1000.0 * ev[q].w_uS;  // uS -> nS
+                ++at;
+            }
+            L.packs[pk].xe1 = at;
+        }
+    }
+
+    // connections: rank by (dst pack, pack synapse, src, index); CSR by source
+    {
+        std::vector<int64_t> idx(n_conn);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+            const arb_connection &A = conn[a], &B = conn[b];
+            const int64_t pa = pack_of_cell[A.dst], pb = pack_of_cell[B.dst];
+            if (pa != pb) return pa < pb;
+            const int64_t sa = L.syn_pack_index[A.syn], sb = L.syn_pack_index[B.syn];
+            if (sa != sb) return sa < sb;
+            if (A.src != B.src) return A.src < B.src;
+            return a < b;
+        });
+        if (n_conn >= (int64_t(1) << 32)) { err = "too many connections"; return ARB_EINVAL; }
+        L.cr_pack.resize(n_conn);
+        L.cr_syn.resize(n_conn);
+        L.cr_delay.resize(n_conn);
+        L.cr_w.resize(n_conn);
+        std::vector<int64_t> in_per_pack(n_packs, 0);
+        L.out_off.assign(n_cells + 1, 0);
+        for (int64_t r = 0; r < n_conn; ++r) {
+            const arb_connection& K = conn[idx[r]];
+            const int64_t pk = pack_of_cell[K.dst];
+            L.cr_pack[r] = int32_t(pk);
+            L.cr_syn[r] = int32_t(L.syn_pack_index[K.syn] - L.packs[pk].syn0);
+            L.cr_delay[r] = K.delay_steps;
+            L.cr_w[r] = 1000.0 * K.w_uS;
+            in_per_pack[pk]++;
+            L.out_off[K.src + 1]++;
+        }
+        L.max_in_per_pack = n_packs ? *std::max_element(in_per_pack.begin(), in_per_pack.end()) : 0;
+        for (int32_t c = 0; c < n_cells; ++c) L.out_off[c + 1] += L.out_off[c];
+        L.out_rank.resize(n_conn);
+        std::vector<int64_t> fill(n_cells, 0);
+        for (int64_t r = 0; r < n_conn; ++r) {
+            const uint32_t src = conn[idx[r]].src;
+            L.out_rank[L.out_off[src] + fill[src]++] = uint32_t(r);
+        }
+    }
+    return ARB_OK;
+}
+
+// alpha_i = c_i/dt - G_lin,i and beta_i = sum G e over the linear terms
+// (pas and the hh leak), so that the right-hand side of the implicit-Euler
+// system is  rhs_i = alpha_i V_i + beta_i - (nonlinear and point currents).
+void recompute_coefficients(Lowered& L) {
+    const double dt = L.dt;
+    std::vector<double> gna(L.n_cv, 0.0), gk(L.n_cv, 0.0);
+    for (int64_t i = 0; i < L.n_cv; ++i) {
+        double G = 0.0, GE = 0.0, gl = 0.0;
+        for (int64_t k = L.piece_off[i]; k < L.piece_off[i + 1]; ++k) {
+            const Region& R = L.regions[L.piece_reg[k]];
+            const double a10 = 10.0 * L.piece_area[k];  // S/cm^2 x um^2 -> nS
+            if (R.mech & ARB_MECH_PAS) { G += a10 * R.gpas; GE += a10 * R.gpas * R.epas; }
+            if (R.mech & ARB_MECH_HH) { gna[i] += a10 * R.gna; gk[i] += a10 * R.gk; gl += a10 * R.gl; }
+        }
+        const int64_t s = L.perm[i];
+        L.alpha[s] = L.cap[s] / dt - G - gl;
+        L.beta[s] = GE + gl * kEL;
+        L.glin_extra[i] = gl;
+    }
+    for (size_t q = 0; q < L.hh_cv.size(); ++q) {
+        L.hh_gna[q] = gna[L.hh_cv[q]];
+        L.hh_gk[q] = gk[L.hh_cv[q]];
+    }
+}
+
+}  // namespace arbmi

@@ -1,0 +1,95 @@
+// lower.hpp -- host-side lowering of a model into the packed device layout.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/arbmi.h"
+#include "layout.hpp"
+
+namespace arbmi {
+
+struct Region {
+    uint32_t mech;
+    double gna, gk, gl, gpas, epas;  // S/cm^2, mV
+};
+
+// Everything the device needs, in packed order, plus what the host keeps to
+// recompute coefficients when parameters change.
+struct Lowered {
+    // sizes
+    int32_t n_cells = 0;
+    int64_t n_cv = 0, n_slots = 0;
+    int32_t block_threads = 64;
+    int32_t coef_mode = 1;
+    double dt = 0.025, threshold = -10.0, v_init = -65.0;
+
+    std::vector<PackDesc> packs;
+    std::vector<RoundDesc> rounds;
+    std::vector<TaskDesc> tasks;
+    std::vector<int32_t> ch_slot;
+    std::vector<NlDesc> nl;
+    std::vector<int32_t> pc_gid, pc_soma;  // per pack cell: gid, pack-local soma slot
+
+    // per global slot
+    std::vector<double> cap;                  // pF (0 in padding)
+    std::vector<double> alpha, beta, F, invd; // step coefficients
+    std::vector<double> d_elim;               // eliminated diagonal (kept for checks)
+    std::vector<int64_t> perm;                // user CV -> global slot
+    std::vector<int32_t> slot_cell;           // global slot -> gid (-1 padding)
+
+    // membrane pieces of each user CV (for parameter updates and gradients)
+    std::vector<int64_t> piece_off;           // [n_cv + 1]
+    std::vector<int32_t> piece_reg;           // global region
+    std::vector<double> piece_area;           // um^2
+    std::vector<Region> regions;              // [n_cells + n_branches], soma first per cell
+    std::vector<int64_t> cell_reg0;           // [n_cells + 1]
+    std::vector<int64_t> cell_cv0;            // [n_cells + 1] user CV offsets
+    std::vector<double> glin_extra;           // per user CV: hh leak part of the linear conductance
+
+    // hh instances, pack order
+    std::vector<int64_t> hh_cv;               // user CV
+    std::vector<double> hh_gna, hh_gk;        // nS
+    // synapses, pack order
+    std::vector<int64_t> syn_global;          // pack-order index -> global synapse
+    std::vector<int64_t> syn_pack_index;      // global synapse -> pack-order index
+    std::vector<double> syn_e, syn_decay;
+    // clamps, NL order
+    std::vector<int64_t> ic_on, ic_off;
+    std::vector<double> ic_amp;               // pA
+    // external events, pack order
+    std::vector<int64_t> xe_step;
+    std::vector<int32_t> xe_syn;              // pack-local synapse
+    std::vector<double> xe_w;                 // nS
+    // connections: ranks sorted by (dst pack, dst pack-local synapse, src, index)
+    std::vector<int64_t> out_off;             // [n_cells + 1] CSR by source gid
+    std::vector<uint32_t> out_rank;
+    std::vector<int32_t> cr_pack, cr_syn, cr_delay;
+    std::vector<double> cr_w;                 // nS
+    int32_t min_delay = 0, max_delay = 0;
+    int64_t max_in_per_pack = 0;              // incoming connections of the busiest pack
+    int64_t n_hh_total = 0;
+};
+
+struct LowerOptions {
+    int32_t block_threads = 64;
+    int32_t coef_mode = 1;            // 1 LDS, 2 streamed
+    int64_t lds_budget = 160 * 1024;  // target bytes per workgroup when packing several cells
+    int64_t lds_hard_max = 160 * 1024; // a single cell may use up to this
+    int64_t max_cells_per_pack = int64_t(1) << 30;
+};
+
+// Validates and lowers.  Returns ARB_OK or ARB_EINVAL (message in err).
+int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, int64_t n_br,
+                const arb_synapse* syn, int64_t n_syn, const arb_connection* conn, int64_t n_conn,
+                const arb_event* ev, int64_t n_ev, const arb_iclamp* ic, int32_t n_ic,
+                const arb_params& p, const LowerOptions& opt, Lowered& out, std::string& err);
+
+// Recompute alpha, beta, hh_gna, hh_gk from lw.regions (after a parameter change).
+void recompute_coefficients(Lowered& lw);
+
+// LDS bytes a pack needs in the given coefficient mode.
+int64_t pack_lds_bytes(int64_t nslot, int64_t nsyn, int64_t nhh, int coef_mode);
+
+}  // namespace arbmi

@@ -1,0 +1,103 @@
+// sim.hpp -- the simulation object behind the opaque arb_sim handle.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/arbmi.h"
+#include "kernels.hpp"
+#include "lower.hpp"
+
+struct arb_sim_ {};
+
+namespace arbmi {
+
+struct RecordArgs {
+    double *V, *m, *h, *n, *g;
+};
+
+// Launch shape and packing chosen before lowering.
+struct Plan {
+    int block_threads = 64;
+    int coef_mode = 1;
+    int64_t lds_budget = 160 * 1024;
+    int64_t lds_hard_max = 160 * 1024;
+    int64_t max_cells_per_pack = 64;
+};
+Plan choose_plan(const arb_cell* cells, int32_t n_cells, const arb_branch* br, int64_t n_br, const arb_params& p,
+                 int64_t lds_max, int n_cu);
+
+struct GradState;
+
+struct Sim : arb_sim_ {
+    arb_params p{};
+    hipStream_t st = nullptr;
+    int device = 0, n_cu = 256;
+    int64_t lds_max = 0;
+    Lowered L;
+    int32_t K = 1;          // epoch length in steps
+    LaunchCfg cfg{};
+    int exch_grid = 1;
+    int32_t n_buckets = 1, bk_cap = 0;
+    uint32_t sp_cap = 0, sp_user = 0;
+    int64_t step = 0;
+    double m0 = 0, h0 = 0, n0 = 0;
+    std::vector<int64_t> xcur0;
+
+    std::vector<void*> allocs;
+    int64_t device_bytes = 0;
+    std::vector<hipEvent_t> timer_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_pending;
+
+    PackDesc* d_pk = nullptr;
+    RoundDesc* d_rd = nullptr;
+    TaskDesc* d_tk = nullptr;
+    int32_t* d_ch = nullptr;
+    NlDesc* d_nl = nullptr;
+    int32_t *d_pc_gid = nullptr, *d_pc_soma = nullptr;
+    double *d_V = nullptr, *d_alpha = nullptr, *d_beta = nullptr, *d_F = nullptr, *d_invd = nullptr;
+    double *d_hh_m = nullptr, *d_hh_h = nullptr, *d_hh_n = nullptr, *d_hh_gna = nullptr, *d_hh_gk = nullptr;
+    double *d_syn_g = nullptr, *d_syn_e = nullptr, *d_syn_decay = nullptr;
+    int64_t *d_ic_on = nullptr, *d_ic_off = nullptr;
+    double* d_ic_amp = nullptr;
+    int64_t* d_xe_step = nullptr;
+    int32_t* d_xe_syn = nullptr;
+    double* d_xe_w = nullptr;
+    int64_t* d_pk_xcur = nullptr;
+    uint64_t* d_bk_ev = nullptr;
+    uint32_t* d_bk_cnt = nullptr;
+    int32_t* d_pk_ncur = nullptr;
+    int32_t *d_cr_syn = nullptr, *d_cr_pack = nullptr, *d_cr_delay = nullptr;
+    double* d_cr_w = nullptr;
+    int64_t* d_out_off = nullptr;
+    uint32_t* d_out_rank = nullptr;
+    uint32_t* d_sp_gid = nullptr;
+    int64_t* d_sp_step = nullptr;
+    double* d_sp_t = nullptr;
+    Counters* d_ctr = nullptr;
+    int64_t* d_perm = nullptr;
+    double* d_tmp = nullptr;
+    int64_t tmp_n = 0;
+    // probes
+    int32_t *d_pr_slot = nullptr, *d_pr_id = nullptr;
+    double* d_trace = nullptr;
+    int64_t n_probe = 0, trace_cap = 0, trace_step0 = 0;
+    // gradients
+    GradState* grad = nullptr;
+    bool grad_valid = false;
+
+    void* raw_alloc(size_t bytes);
+    void release_all();
+    int upload(void* dst, const void* src, size_t bytes);
+    int fill_zero(void* dst, size_t bytes);
+    StepArgs step_args() const;
+    int advance(int64_t n, const RecordArgs* rec);
+    int check_flags(bool& spikes_lost, bool& events_lost);
+};
+
+int set_error(int code, const std::string& msg);
+int set_hip_error(hipError_t e, const char* where);
+
+}  // namespace arbmi

@@ -1,0 +1,166 @@
+"""The C ABI library loads, exports every declared symbol, its structs match
+the binding's layouts, and host-side validation rejects bad models (no GPU
+needed: validation runs before any device call)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1901_07454_amd import arbmi
+from workloads import gen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "arbmi.h")
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def test_library_exports_every_declared_symbol():
+    lib = arbmi.load()
+    declared = set(re.findall(r"\b(arb_[a-z_]+)\s*\(", open(HDR).read()))
+    assert declared >= {"arb_build_cells", "arb_step", "arb_get_voltages", "arb_get_spikes"}
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(arbmi.EXPORTS) == declared
+
+
+def test_struct_layouts_match_header(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "arbmi.h"\n'
+                    '#define S(t) printf(#t " %zu\\n", sizeof(t));\n'
+                    '#define O(t,f) printf(#t "." #f " %zu\\n", offsetof(t,f));\n'
+                    "int main(void){S(arb_branch)S(arb_cell)S(arb_synapse)S(arb_connection)S(arb_event)"
+                    "S(arb_iclamp)S(arb_spike)S(arb_params)S(arb_info)"
+                    "O(arb_branch,gbar_na)O(arb_cell,soma_area_um2)O(arb_params,hip_stream)"
+                    "O(arb_params,spike_capacity)O(arb_params,coef_mode)O(arb_info,bytes_per_step)return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                              check=True).stdout.split("\n") if line)
+    got = {k: int(v) for k, v in got.items()}
+    assert got["arb_branch"] == arbmi.BRANCH.itemsize
+    assert got["arb_cell"] == arbmi.CELL.itemsize
+    assert got["arb_synapse"] == arbmi.SYNAPSE.itemsize
+    assert got["arb_connection"] == arbmi.CONNECTION.itemsize
+    assert got["arb_event"] == arbmi.EVENT.itemsize
+    assert got["arb_iclamp"] == arbmi.ICLAMP.itemsize
+    assert got["arb_spike"] == arbmi.SPIKE.itemsize
+    assert got["arb_params"] == ctypes.sizeof(arbmi.arb_params)
+    assert got["arb_info"] == ctypes.sizeof(arbmi.arb_info)
+    assert got["arb_branch.gbar_na"] == arbmi.BRANCH.fields["gbar_na"][1]
+    assert got["arb_cell.soma_area_um2"] == arbmi.CELL.fields["soma_area_um2"][1]
+    assert got["arb_params.hip_stream"] == arbmi.arb_params.hip_stream.offset
+    assert got["arb_params.spike_capacity"] == arbmi.arb_params.spike_capacity.offset
+    assert got["arb_params.coef_mode"] == arbmi.arb_params.coef_mode.offset
+    assert got["arb_info.bytes_per_step"] == arbmi.arb_info.bytes_per_step.offset
+
+
+def _params(**kw):
+    p = arbmi.arb_params()
+    p.dt_ms, p.threshold_mV, p.v_init_mV = 0.025, -10.0, -65.0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _build(m, **kw):
+    return arbmi.arb_build_cells(*arbmi.model_structs(m), _params(**kw))
+
+
+def _expect_einval(m, text, **kw):
+    with pytest.raises(arbmi.ArbError) as e:
+        _build(m, **kw)
+    assert e.value.code == arbmi.ARB_EINVAL, str(e.value)
+    assert text in str(e.value)
+
+
+def _ring():
+    return gen.config2(n_cells=3, n_steps=10)
+
+
+def test_rejects_bad_parent():
+    m = _ring()
+    m["br_parent"] = m["br_parent"].copy()
+    m["br_parent"][5] = 9
+    _expect_einval(m, "parent")
+
+
+def test_rejects_zero_cvs_and_bad_geometry():
+    m = _ring()
+    m["br_n_cv"] = m["br_n_cv"].copy()
+    m["br_n_cv"][3] = 0
+    _expect_einval(m, "n_cv")
+    m = _ring()
+    m["br_diam"] = m["br_diam"].copy()
+    m["br_diam"][0] = 0.0
+    _expect_einval(m, "diameter")
+    m = _ring()
+    m["soma_area"] = m["soma_area"].copy()
+    m["soma_area"][1] = -1.0
+    _expect_einval(m, "soma area")
+    m = _ring()
+    m["br_gpas"] = m["br_gpas"].copy()
+    m["br_gpas"][2] = np.nan
+    _expect_einval(m, "not finite")
+
+
+def test_rejects_bad_synapses_and_connections():
+    m = _ring()
+    m["syn_cv"] = m["syn_cv"].copy()
+    m["syn_cv"][4] = 99
+    _expect_einval(m, "synapse 4")
+    m = _ring()
+    m["con_delay"] = m["con_delay"].copy()
+    m["con_delay"][0] = 0
+    _expect_einval(m, "delay_steps")
+    m = _ring()
+    m["con_syn"] = m["con_syn"].copy()
+    m["con_syn"][0] = 10  # a synapse of cell 1, but connection 0 ends on cell 0
+    _expect_einval(m, "destination")
+    m = _ring()
+    m["ev_syn"] = m["ev_syn"].copy()
+    m["ev_syn"][0] = 10_000
+    _expect_einval(m, "event 0")
+    m = _ring()
+    m["ic_cell"], m["ic_branch"], m["ic_cv"] = np.array([0], np.int32), np.array([-1], np.int32), np.array([1], np.int32)
+    m["ic_on"], m["ic_off"], m["ic_amp"] = np.array([0]), np.array([5]), np.array([0.1])
+    _expect_einval(m, "clamp 0")
+
+
+def test_rejects_epoch_longer_than_min_delay():
+    _expect_einval(_ring(), "minimum delay", epoch_steps=201)
+
+
+def test_rejects_bad_launch_parameters():
+    _expect_einval(_ring(), "block_threads", block_threads=96)
+    _expect_einval(_ring(), "coef_mode", coef_mode=3)
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")
+def test_valid_model_without_device_reports_hip_error():
+    with pytest.raises(arbmi.ArbError) as e:
+        _build(_ring())
+    assert e.value.code == arbmi.ARB_EHIP
+
+
+def test_null_sim_handles_are_rejected():
+    lib = arbmi.load()
+    assert lib.arb_step(None, 1) == arbmi.ARB_EINVAL
+    assert lib.arb_free(None) == arbmi.ARB_OK
+    n = ctypes.c_int64()
+    assert lib.arb_get_spikes(None, None, 0, ctypes.byref(n)) == arbmi.ARB_EINVAL
+
+
+def test_rejects_lds_resident_coefficients_for_a_huge_cell():
+    big = [i for i in range(40) if 1 + gen.cell_c3(i, 10.0).n_cv.sum() > 4000][:1]
+    m = gen.config3(cells=big, n_steps=10)
+    _expect_einval(m, "LDS", coef_mode=1)

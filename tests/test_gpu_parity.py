@@ -1,0 +1,181 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on
+the same seeded inputs.  Bar: max |dV| <= 1e-8 mV over every recorded step
+and identical spike (gid, step) lists."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import models
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-8
+
+
+def _sim(m, **kw):
+    from paper_1901_07454_amd import arbmi
+    return arbmi.Simulation(m, **kw)
+
+
+def gpu_run(m, n, probes, **kw):
+    sim = _sim(m, **kw)
+    sim.set_probes(probes, n)
+    sim.step(n)
+    tr = sim.trace(n)
+    V = sim.voltages_host()
+    sp = sim.spikes()
+    info = sim.info
+    sim.close()
+    return tr, V, sorted(zip(sp["step"].tolist(), sp["gid"].tolist())), info
+
+
+def oracle_run(m, n, probes, K=None):
+    s = oracle.Sim(m, epoch_steps=K)
+    tr = s.run(n, probes=probes)
+    g, st, _ = s.spikes()
+    return tr, s.state()["V"], sorted(zip(st.tolist(), g.tolist()))
+
+
+def check(m, n, probes=None, **kw):
+    ncv = int(gen.n_cvs(m).sum())
+    if probes is None:
+        probes = oracle.cell_cv_begin(m)[:-1]
+    probes = np.asarray(probes, np.int64)
+    tr, V, sp, info = gpu_run(m, n, probes, **kw)
+    rtr, rV, rsp = oracle_run(m, n, probes)
+    assert tr.shape == rtr.shape
+    err = max(np.max(np.abs(tr - rtr)), np.max(np.abs(V - rV)))
+    print(f"cells={len(m['cell_n_branch'])} cvs={ncv} steps={n} cfg={kw} info={info} "
+          f"max|dV|={err:.3e} spikes={len(sp)}", flush=True)
+    assert err <= TOL
+    assert sp == rsp
+    return err, sp
+
+
+def test_config1_full_run_every_cv():
+    m = gen.config1()
+    check(m, 4000, probes=np.arange(129))
+
+
+@pytest.mark.parametrize("kick_all", [True, False])
+def test_ring_small(kick_all):
+    m = gen.config2(n_cells=12, kick_all=kick_all)
+    _, sp = check(m, 4000)
+    assert len(sp) >= 12
+
+
+@pytest.mark.parametrize("coef_mode", [1, 2])
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_config3_small_uneven(coef_mode, block):
+    # LDS-resident coefficients need cells below ~2.7k CVs; streamed mode takes any
+    ids = [i for i in range(60) if coef_mode == 2 or 1 + gen.cell_c3(i, 37.5).n_cv.sum() < 2500][:20]
+    m = gen.config3(cells=ids, n_steps=1500)
+    check(m, 1500, block_threads=block, coef_mode=coef_mode)
+
+
+def test_config4_cells_with_clamp():
+    m = gen.config4(n_cells=4, n_steps=2000)
+    _, sp = check(m, 2000)
+    assert len(sp) > 0
+
+
+def test_config5_small_network():
+    m = gen.config5(n_cells=40, n_in=12, n_steps=1600)
+    m["con_w"] = np.full_like(m["con_w"], 0.04)
+    m["ev_w"] = np.full_like(m["ev_w"], 0.2)
+    _, sp = check(m, 1600)
+    assert len(sp) > 5
+
+
+def test_edge_morphologies():
+    cells = [
+        models.bare_cell([], [], [], []),                                   # soma only
+        models.bare_cell([-1], [1], [50.0], [1.0]),                         # one single-CV branch
+        models.bare_cell([-1, 0], [100, 3], [900.0, 40.0], [2.5, 0.7]),     # long branch, ragged child
+        models.bare_cell([-1] * 70, [2] * 70, np.linspace(50, 200, 70), [1.5] * 70),  # 70 roots: 2 rounds of 64
+        models.bare_cell(gen.full_binary_parents(3), np.arange(1, 16), np.linspace(20, 300, 15),
+                         np.linspace(0.5, 4, 15), soma_mech=gen.MECH_HH | gen.MECH_PAS, dend_mech=gen.MECH_HH),
+    ]
+    for k, d in enumerate(cells):
+        d.clamps.append((-1, 0, 40, 900, 0.3 + 0.1 * k))
+    m = gen.assemble(cells, n_steps=1200)
+    check(m, 1200, probes=np.arange(int(gen.n_cvs(m).sum())))
+
+
+def test_epoch_length_invariance_bitwise():
+    m = gen.config2(n_cells=8, kick_all=False)
+    probes = oracle.cell_cv_begin(m)[:-1]
+    ref = gpu_run(m, 1400, probes, epoch_steps=200)
+    for K in (1, 37, 100):
+        got = gpu_run(m, 1400, probes, epoch_steps=K)
+        assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1]) and ref[2] == got[2]
+
+
+def test_determinism_bitwise():
+    m = gen.config5(n_cells=24, n_in=8, n_steps=1000)
+    m["ev_w"] = np.full_like(m["ev_w"], 0.3)
+    probes = np.arange(int(gen.n_cvs(m).sum()))
+    a = gpu_run(m, 1000, probes)
+    b = gpu_run(m, 1000, probes)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_checkpoint_roundtrip_bitwise():
+    m = gen.config2(n_cells=6, kick_all=False)
+    s1 = _sim(m)
+    s1.step(700)
+    blob = s1.get_state()
+    s1.step(700)
+    v1, sp1 = s1.voltages_host(), s1.spikes()
+    s2 = _sim(m)
+    s2.set_state(blob)
+    s2.step(700)
+    v2 = s2.voltages_host()
+    assert np.array_equal(v1, v2)
+    s1.close()
+    s2.close()
+    assert len(sp1) > 0
+
+
+def test_arbitrary_step_splits_match_one_call():
+    m = gen.config2(n_cells=6, kick_all=False)
+    a = _sim(m)
+    a.step(1000)
+    b = _sim(m)
+    for k in (1, 199, 1, 350, 449):
+        b.step(k)
+    assert np.array_equal(a.voltages_host(), b.voltages_host())
+    sa, sb = a.spikes(), b.spikes()
+    assert np.array_equal(sa, sb)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("target", [0, 1, 4097, 8191])
+def test_config2_full_size_light_cone(target, _full_ring):
+    """Full 8192-cell ring, 4000 steps, in the launch configuration the
+    benchmark uses; each sampled cell is checked against an oracle run of the
+    cells whose spikes can reach it within the run."""
+    trace, V, spikes, cv0 = _full_ring
+    chain = gen.ring_light_cone(8192, target, 4000)
+    sub = gen.config2(n_cells=8192, cells=chain)
+    s = oracle.Sim(sub)
+    c0 = oracle.cell_cv_begin(sub)
+    rtr = s.run(4000, probes=[c0[-2]])[0]
+    g, st, _ = s.spikes()
+    err = max(np.max(np.abs(trace[target] - rtr)),
+              np.max(np.abs(V[cv0[target]:cv0[target + 1]] - s.state()["V"][c0[-2]:c0[-1]])))
+    print(f"target {target}: max|dV| = {err:.3e}", flush=True)
+    assert err <= TOL
+    mine = sorted(stp for (stp, gid) in spikes if gid == target)
+    ref = sorted(int(x) for x, gg in zip(st, g) if gg == len(chain) - 1)
+    assert mine == ref
+
+
+@pytest.fixture(scope="module")
+def _full_ring():
+    m = gen.config2()
+    cv0 = oracle.cell_cv_begin(m)
+    tr, V, sp, info = gpu_run(m, 4000, cv0[:-1])
+    print("full ring info", info, flush=True)
+    return tr, V, sp, cv0
