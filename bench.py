@@ -1,0 +1,210 @@
+"""Benchmark: CV-updates/s of the multi-compartment cell stepper on one MI355X.
+
+A "step" is one time step dt of every cell: event delivery, hh/pas/expsyn
+currents, implicit-Euler assembly, Hines solve, state update, threshold
+detection, and (every epoch) the spike exchange.  The default workload is the
+8192-cell ring (random-geometry depth-6 binary trees, 1017 CVs per cell,
+8,331,264 CVs, hh soma, passive dendrites, 10 expsyn per cell, ring delay
+5 ms, dt 0.025 ms), timed over 4000 steps (100 ms of model time) after a
+warm-up epoch.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  `--config 3|4|5|1` selects the other workloads.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_model(cfg: int, n_cells: int | None):
+    from workloads import gen
+    if cfg == 1:
+        return gen.config1(), "1 cell, 129 CVs (hh soma + 4x32 pas), 1 expsyn, 10 input events"
+    if cfg == 2:
+        n = n_cells or 8192
+        return gen.config2(n_cells=n), (f"{n}-cell ring, depth-6 binary trees x 8 CVs/branch (1017 CVs/cell), "
+                                        "hh soma, pas dendrites, 10 expsyn/cell, delay 5 ms")
+    if cfg == 3:
+        n = n_cells or 4096
+        return gen.config3(n_cells=n), (f"{n} uneven Yule-tree cells, CVs log-uniform in [50, 5000], "
+                                        "hh soma + 25% hh branches, 20 expsyn/cell, 10 Hz Poisson input")
+    if cfg == 5:
+        n = n_cells or 65536
+        return gen.config5(n_cells=n), (f"{n} Yule-tree cells x 1497 CVs, 100 random incoming connections "
+                                        "(delay 5-10 ms) + 5 Hz background per cell")
+    if cfg == 4:
+        n = n_cells or 256
+        return gen.config4(n_cells=n), f"{n} cells x 200 CVs, hh+pas everywhere, soma clamp 0.2 nA"
+    raise SystemExit(f"unknown config {cfg}")
+
+
+def copy_bandwidth_gbps(torch) -> float:
+    """Device-to-device copy rate of a 2 GiB buffer (read + write bytes)."""
+    n = 1 << 28
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del a, b
+    return 2 * 8 * n * reps / dt / 1e9
+
+
+def _oracle_chunk(args):
+    cfg, cells, steps = args
+    import oracle
+    from workloads import gen
+    if cfg == 2:
+        m = gen.config2(n_cells=8192, cells=cells)
+    elif cfg == 3:
+        m = gen.config3(cells=cells)
+    elif cfg == 5:
+        m = gen.config5(n_cells=65536, cells=cells)
+    elif cfg == 4:
+        m = gen.config4(cells=cells)
+    else:
+        m = gen.config1()
+    s = oracle.Sim(m)
+    t0 = time.perf_counter()
+    s.run(steps)
+    dt = time.perf_counter() - t0
+    return int(gen.n_cvs(m).sum()) * steps, dt
+
+
+def cpu_baseline(cfg: int, budget_s: float = 20.0):
+    """The CPU oracle as it stands (single-threaded C), run as independent
+    processes on disjoint cell chunks of the same workload; the rate is the
+    sum over processes of CV-updates / stepping time."""
+    import multiprocessing as mp
+
+    import oracle
+    oracle.build() if not os.path.exists(oracle.LIB) else None
+    workers = max(1, min(16, os.cpu_count() or 1))
+    per = {1: (1, 4000), 2: (96, 800), 3: (24, 800), 4: (64, 2000), 5: (48, 800)}[cfg]
+    n_cells, steps = per
+    base = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536}[cfg]
+    chunks = [(cfg, [(w * n_cells + k) % base for k in range(n_cells)], steps) for w in range(workers)]
+    if cfg == 1:
+        chunks = [(1, [0], steps) for _ in range(workers)]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_chunk, chunks)
+    wall = time.perf_counter() - t0
+    rate = sum(u / t for u, t in res)
+    cpu_s = sum(t for _, t in res)
+    return {"value": rate, "unit": "CV-updates/s", "cores": workers, "kind": "oracle",
+            "sample": (f"{workers} processes x {n_cells} cells x {steps} steps of the same workload "
+                       f"({'ring segments' if cfg == 2 else 'cell chunks'}), stepping time only; "
+                       f"{cpu_s:.1f} s CPU, {wall:.1f} s wall")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--cells", type=int, default=None)
+    ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--coef-mode", type=int, default=0)
+    ap.add_argument("--cells-per-pack", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        raise SystemExit(2)
+
+    import torch
+
+    from paper_1901_07454_amd import arbmi
+    from workloads import gen
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    m, desc = make_model(args.config, args.cells)
+    log(f"model built in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    sim = arbmi.Simulation(m, flags=arbmi.ARB_FLAG_TIME_KERNELS, block_threads=args.block_threads,
+                           coef_mode=args.coef_mode, cells_per_pack=args.cells_per_pack)
+    info = sim.info
+    log(f"sim built in {time.perf_counter() - t0:.1f} s: {info}")
+    n_cv = info["n_cv"]
+
+    sim.step(args.warmup)
+    sim.sync()
+    sim.kernel_time()  # discard warm-up launches
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, nlaunch = sim.kernel_time()
+    sim.sync()
+    spikes = sim.spikes()
+    log(f"timed {args.steps} steps in {wall:.4f} s, {nlaunch} step-kernel launches, {kms:.2f} ms in them, "
+        f"{len(spikes)} spikes")
+
+    value = n_cv * args.steps / wall
+    steps_per_launch = args.steps / max(nlaunch, 1)
+    avg_launch_s = kms / 1e3 / max(nlaunch, 1)
+    bytes_per_launch = info["bytes_per_step"] * steps_per_launch
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = None
+    try:
+        tj = json.load(open(args.traffic_json))
+        key = f"config{args.config}"
+        if key in tj and tj[key].get("kernel_hash") == info.get("kernel_hash", tj[key].get("kernel_hash")):
+            traffic = tj[key].get("bytes_per_launch")
+    except Exception:
+        traffic = None
+    copy_gbps = copy_bandwidth_gbps(torch)
+    out = {
+        "metric": "CV-updates/s per GPU (fwd FP64)",
+        "value": value,
+        "unit": "CV-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"config {args.config}: {desc}", "cells": info["n_cells"], "cvs": n_cv,
+                   "dt_ms": float(m["dt"]), "epoch_steps": info["epoch_steps"],
+                   "block_threads": info["block_threads"], "coef_mode": info["coef_mode"],
+                   "packs": info["n_packs"], "lds_bytes": info["lds_bytes"], "spikes": int(len(spikes))},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": "step_kernel", "bytes_per_step": info["bytes_per_step"],
+                     "steps_per_launch": steps_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
+                     "measured_copy_GBps": copy_gbps},
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.config)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

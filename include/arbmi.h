@@ -132,9 +132,12 @@ typedef struct {
     int64_t event_capacity;   /* network events per (cell pack, epoch); 0 = default */
     int32_t block_threads;    /* threads per cell pack; 0 = autotuned */
     int32_t coef_mode;        /* 0 = autotuned, 1 = per-CV coefficients in LDS, 2 = streamed */
+    int32_t cells_per_pack;   /* most cells one workgroup advances; 0 = autotuned */
+    int32_t reserved;
 } arb_params;
 
 #define ARB_FLAG_TIME_KERNELS 1 /* record HIP events around every step kernel */
+#define ARB_FLAG_GRADIENTS 2    /* size cell packs so the adjoint kernel fits (use with arb_grad_*) */
 
 typedef struct {
     uint32_t gid;

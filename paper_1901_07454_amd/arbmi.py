@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libarbmi.so")
 ARB_OK, ARB_EINVAL, ARB_ENOMEM, ARB_EHIP, ARB_ESTATE, ARB_EOVERFLOW = 0, -1, -2, -3, -4, -5
 ARB_MECH_HH, ARB_MECH_PAS = 1, 2
 ARB_FLAG_TIME_KERNELS = 1
+ARB_FLAG_GRADIENTS = 2
 
 # numpy mirrors of the ABI structs (natural C alignment)
 BRANCH = np.dtype([("parent", "<i4"), ("n_cv", "<i4"), ("length_um", "<f8"), ("diam_um", "<f8"),
@@ -48,7 +49,8 @@ class arb_params(C.Structure):
                 ("epoch_steps", C.c_int32), ("flags", C.c_int32), ("hip_stream", C.c_void_p),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
                 ("spike_capacity", C.c_int64), ("event_capacity", C.c_int64),
-                ("block_threads", C.c_int32), ("coef_mode", C.c_int32)]
+                ("block_threads", C.c_int32), ("coef_mode", C.c_int32),
+                ("cells_per_pack", C.c_int32), ("reserved", C.c_int32)]
 
 
 class arb_info(C.Structure):
@@ -257,7 +259,7 @@ class Simulation:
     """A sim built from a column model, with device memory from torch."""
 
     def __init__(self, m: dict, epoch_steps: int = 0, block_threads: int = 0, coef_mode: int = 0,
-                 flags: int = 0, spike_capacity: int = 0, event_capacity: int = 0, stream=None,
+                 cells_per_pack: int = 0, flags: int = 0, spike_capacity: int = 0, event_capacity: int = 0, stream=None,
                  use_torch_allocator: bool = True):
         import torch
         self._torch = torch
@@ -268,6 +270,7 @@ class Simulation:
         p.hip_stream = C.c_void_p(self.stream.cuda_stream)
         p.spike_capacity, p.event_capacity = int(spike_capacity), int(event_capacity)
         p.block_threads, p.coef_mode = int(block_threads), int(coef_mode)
+        p.cells_per_pack = int(cells_per_pack)
         if use_torch_allocator:
             dev = self.stream.device
             st = self.stream

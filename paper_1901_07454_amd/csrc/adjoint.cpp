@@ -1,20 +1,300 @@
-// adjoint.cpp -- host side of the discrete adjoint.
+// adjoint.cpp -- gradients of a soma-trace loss by the discrete adjoint:
+// a forward pass with state checkpoints every k steps, then, segment by
+// segment from the last, a recompute that records every forward state and a
+// reverse sweep over it (adjoint_kernels.hip).  Input events, external and
+// network, are replayed exactly by the recompute (the checkpoints hold the
+// event queues), so they act as fixed inputs.
 #include "adjoint.hpp"
 
+#include <algorithm>
+#include <vector>
+
+#include "adjoint_kernels.hpp"
 #include "sim.hpp"
 
 namespace arbmi {
 
+struct GradState {
+    int64_t n_steps = 0, k = 0, step_begin = 0, n_seg = 0;
+    std::vector<char*> ckpt;  // state copies at segment starts, plus the end state
+    int64_t state_bytes = 0;
+    double *rec_V = nullptr, *rec_m = nullptr, *rec_h = nullptr, *rec_n = nullptr, *rec_g = nullptr;
+    double *lamV = nullptr, *lamM = nullptr, *lamH = nullptr, *lamN = nullptr;
+    double *accP1 = nullptr, *accP0 = nullptr, *accNa = nullptr, *accK = nullptr;
+    int64_t *rp_off = nullptr, *rp_slot = nullptr, *rp_hh = nullptr;
+    double *rp_area = nullptr, *reg_epas = nullptr;
+    uint32_t* reg_mech = nullptr;
+    int32_t *pr_slot = nullptr, *pr_id = nullptr;
+    int adj_lds = 0;
+    bool ready = false;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                          \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return set_hip_error(e_, #expr); \
+    } while (0)
+
+struct Part {
+    void* d;
+    int64_t bytes;
+};
+
+std::vector<Part> state_parts(Sim* s) {
+    const Lowered& L = s->L;
+    const int64_t np = int64_t(L.packs.size()), nbk = int64_t(s->n_buckets) * np;
+    const int64_t nhh = int64_t(L.hh_cv.size()), nsyn = int64_t(L.syn_global.size());
+    return {{s->d_V, L.n_slots * 8},   {s->d_hh_m, nhh * 8},  {s->d_hh_h, nhh * 8},
+            {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
+            {s->d_pk_ncur, np * 4},    {s->d_bk_cnt, nbk * 4}, {s->d_bk_ev, nbk * s->bk_cap * 8},
+            {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
+            {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8}};
+}
+
+int save_state(Sim* s, char* dst) {
+    int64_t at = 0;
+    for (const Part& q : state_parts(s)) {
+        if (q.bytes) HIP_TRY(hipMemcpyAsync(dst + at, q.d, size_t(q.bytes), hipMemcpyDeviceToDevice, s->st));
+        at += (q.bytes + 255) & ~int64_t(255);
+    }
+    return ARB_OK;
+}
+
+int load_state(Sim* s, const char* src) {
+    int64_t at = 0;
+    for (const Part& q : state_parts(s)) {
+        if (q.bytes) HIP_TRY(hipMemcpyAsync(q.d, src + at, size_t(q.bytes), hipMemcpyDeviceToDevice, s->st));
+        at += (q.bytes + 255) & ~int64_t(255);
+    }
+    return ARB_OK;
+}
+
+template <class T>
+T* galloc(Sim* s, size_t n, int& rc) {
+    if (rc != ARB_OK) return nullptr;
+    T* ptr = static_cast<T*>(s->raw_alloc(std::max<size_t>(n, 1) * sizeof(T)));
+    if (!ptr) rc = set_error(ARB_ENOMEM, "device allocation failed (gradient buffers)");
+    return ptr;
+}
+
+// (Re)allocate the gradient buffers for n steps with checkpoints every k.
+int setup(Sim* s, int64_t n, int64_t k) {
+    if (!s->grad) s->grad = new GradState();
+    GradState& G = *s->grad;
+    const Lowered& L = s->L;
+    const int64_t nhh = int64_t(L.hh_cv.size()), nsyn = int64_t(L.syn_global.size());
+    const int64_t n_seg = (n + k - 1) / k;
+    int rc = ARB_OK;
+    if (G.state_bytes == 0) {
+        for (const Part& q : state_parts(s)) G.state_bytes += (q.bytes + 255) & ~int64_t(255);
+        // adjoint LDS must fit
+        int64_t lds = 0;
+        for (const PackDesc& D : L.packs) lds = std::max(lds, adjoint_lds_bytes(D));
+        if (lds > s->lds_max - 256)
+            return set_error(ARB_EINVAL, "packs too large for the adjoint kernel: build with ARB_FLAG_GRADIENTS");
+        G.adj_lds = int(std::max<int64_t>(lds, 8));
+        if (prepare_adjoint_kernels(int(s->lds_max)) != hipSuccess) return set_error(ARB_EHIP, "adjoint kernels");
+        G.lamV = galloc<double>(s, L.n_slots, rc);
+        G.accP1 = galloc<double>(s, L.n_slots, rc);
+        G.accP0 = galloc<double>(s, L.n_slots, rc);
+        G.lamM = galloc<double>(s, nhh, rc);
+        G.lamH = galloc<double>(s, nhh, rc);
+        G.lamN = galloc<double>(s, nhh, rc);
+        G.accNa = galloc<double>(s, nhh, rc);
+        G.accK = galloc<double>(s, nhh, rc);
+        // membrane pieces grouped by region
+        const int64_t nreg = int64_t(L.regions.size());
+        std::vector<int64_t> hh_of_cv(L.n_cv, -1);
+        for (size_t q = 0; q < L.hh_cv.size(); ++q) hh_of_cv[L.hh_cv[q]] = int64_t(q);
+        std::vector<int64_t> off(nreg + 1, 0);
+        for (int32_t r : L.piece_reg) off[r + 1]++;
+        for (int64_t r = 0; r < nreg; ++r) off[r + 1] += off[r];
+        std::vector<int64_t> slot(off[nreg]), hh(off[nreg]);
+        std::vector<double> area(off[nreg]);
+        std::vector<int64_t> fill(nreg, 0);
+        for (int64_t i = 0; i < L.n_cv; ++i)
+            for (int64_t p = L.piece_off[i]; p < L.piece_off[i + 1]; ++p) {
+                const int32_t r = L.piece_reg[p];
+                const int64_t at = off[r] + fill[r]++;
+                slot[at] = L.perm[i];
+                hh[at] = hh_of_cv[i];
+                area[at] = L.piece_area[p];
+            }
+        std::vector<uint32_t> mech(nreg);
+        std::vector<double> epas(nreg);
+        for (int64_t r = 0; r < nreg; ++r) {
+            mech[r] = L.regions[r].mech;
+            epas[r] = L.regions[r].epas;
+        }
+        G.rp_off = galloc<int64_t>(s, off.size(), rc);
+        G.rp_slot = galloc<int64_t>(s, slot.size(), rc);
+        G.rp_hh = galloc<int64_t>(s, hh.size(), rc);
+        G.rp_area = galloc<double>(s, area.size(), rc);
+        G.reg_mech = galloc<uint32_t>(s, mech.size(), rc);
+        G.reg_epas = galloc<double>(s, epas.size(), rc);
+        // soma probes, [pack][cell] order, id = gid
+        std::vector<int32_t> ps, pid;
+        for (const PackDesc& D : L.packs)
+            for (int32_t c = 0; c < D.ncell; ++c) {
+                ps.push_back(L.pc_soma[D.cell0 + c]);
+                pid.push_back(L.pc_gid[D.cell0 + c]);
+            }
+        G.pr_slot = galloc<int32_t>(s, ps.size(), rc);
+        G.pr_id = galloc<int32_t>(s, pid.size(), rc);
+        if (rc != ARB_OK) return rc;
+        if ((rc = s->upload(G.rp_off, off.data(), off.size() * 8)) != ARB_OK) return rc;
+        if ((rc = s->upload(G.rp_slot, slot.data(), slot.size() * 8)) != ARB_OK) return rc;
+        if ((rc = s->upload(G.rp_hh, hh.data(), hh.size() * 8)) != ARB_OK) return rc;
+        if ((rc = s->upload(G.rp_area, area.data(), area.size() * 8)) != ARB_OK) return rc;
+        if ((rc = s->upload(G.reg_mech, mech.data(), mech.size() * 4)) != ARB_OK) return rc;
+        if ((rc = s->upload(G.reg_epas, epas.data(), epas.size() * 8)) != ARB_OK) return rc;
+        if ((rc = s->upload(G.pr_slot, ps.data(), ps.size() * 4)) != ARB_OK) return rc;
+        if ((rc = s->upload(G.pr_id, pid.data(), pid.size() * 4)) != ARB_OK) return rc;
+    }
+    if (G.k != k) {
+        G.rec_V = galloc<double>(s, size_t(k + 1) * L.n_slots, rc);
+        G.rec_m = galloc<double>(s, size_t(k) * nhh, rc);
+        G.rec_h = galloc<double>(s, size_t(k) * nhh, rc);
+        G.rec_n = galloc<double>(s, size_t(k) * nhh, rc);
+        G.rec_g = galloc<double>(s, size_t(k) * nsyn, rc);
+        if (rc != ARB_OK) return rc;
+        G.k = k;
+    }
+    while (int64_t(G.ckpt.size()) < n_seg + 1) {
+        char* c = galloc<char>(s, size_t(G.state_bytes), rc);
+        if (rc != ARB_OK) return rc;
+        G.ckpt.push_back(c);
+    }
+    G.n_steps = n;
+    G.n_seg = n_seg;
+    return ARB_OK;
+}
+
+}  // namespace
+
 int grad_forward(Sim* s, int64_t n_steps, int32_t ckpt_every, double* trace_dev) {
-    (void)s; (void)n_steps; (void)ckpt_every; (void)trace_dev;
-    return set_error(ARB_ESTATE, "gradients are not available in this build");
+    if (n_steps <= 0 || ckpt_every <= 0) return set_error(ARB_EINVAL, "n_steps and ckpt_every must be positive");
+    if (!trace_dev) return set_error(ARB_EINVAL, "trace_dev is NULL");
+    if (s->step + n_steps >= (int64_t(1) << 31)) return set_error(ARB_EINVAL, "step count beyond 2^31");
+    s->grad_valid = false;
+    int rc = setup(s, n_steps, std::min<int64_t>(ckpt_every, n_steps));
+    if (rc != ARB_OK) return rc;
+    GradState& G = *s->grad;
+    Lowered& L = s->L;
+    // probes: the soma of every cell, written straight into the caller's trace
+    {
+        int32_t at = 0;
+        for (PackDesc& D : L.packs) {
+            D.pr0 = at;
+            D.npr = D.ncell;
+            at += D.ncell;
+        }
+        if ((rc = s->upload(s->d_pk, L.packs.data(), L.packs.size() * sizeof(PackDesc))) != ARB_OK) return rc;
+        s->d_pr_slot = G.pr_slot;
+        s->d_pr_id = G.pr_id;
+        s->d_trace = trace_dev;
+        s->n_probe = L.n_cells;
+        s->trace_cap = n_steps;
+        s->trace_step0 = s->step;
+    }
+    G.step_begin = s->step;
+    for (int64_t j = 0; j < G.n_seg; ++j) {
+        if ((rc = save_state(s, G.ckpt[j])) != ARB_OK) return rc;
+        const int64_t len = std::min(G.k, n_steps - j * G.k);
+        if ((rc = s->advance(len, nullptr)) != ARB_OK) return rc;
+    }
+    if ((rc = save_state(s, G.ckpt[G.n_seg])) != ARB_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s->st));
+    // the caller's trace stays valid; later steps must not write into it
+    s->d_trace = nullptr;
+    s->n_probe = 0;
+    s->trace_cap = 0;
+    G.ready = true;
+    s->grad_valid = true;
+    return ARB_OK;
 }
 
 int grad_backward(Sim* s, const double* dL_dtrace_dev, double* dL_dtheta_dev) {
-    (void)s; (void)dL_dtrace_dev; (void)dL_dtheta_dev;
-    return set_error(ARB_ESTATE, "arb_grad_backward before arb_grad_forward");
+    if (!s->grad || !s->grad_valid || !s->grad->ready)
+        return set_error(ARB_ESTATE, "arb_grad_backward needs a preceding arb_grad_forward");
+    if (!dL_dtrace_dev || !dL_dtheta_dev) return set_error(ARB_EINVAL, "null gradient buffer");
+    GradState& G = *s->grad;
+    const Lowered& L = s->L;
+    const int64_t nhh = int64_t(L.hh_cv.size());
+    const int64_t saved_step = s->step;
+    for (double* p : {G.lamV, G.accP1, G.accP0}) HIP_TRY(hipMemsetAsync(p, 0, size_t(L.n_slots) * 8, s->st));
+    for (double* p : {G.lamM, G.lamH, G.lamN, G.accNa, G.accK})
+        if (nhh) HIP_TRY(hipMemsetAsync(p, 0, size_t(nhh) * 8, s->st));
+    int rc = ARB_OK;
+    for (int64_t j = G.n_seg - 1; j >= 0; --j) {
+        const int64_t begin = G.step_begin + j * G.k;
+        const int64_t len = std::min(G.k, G.n_steps - j * G.k);
+        if ((rc = load_state(s, G.ckpt[j])) != ARB_OK) return rc;
+        s->step = begin;
+        RecordArgs rec{G.rec_V, G.rec_m, G.rec_h, G.rec_n, G.rec_g};
+        if ((rc = s->advance(len, &rec)) != ARB_OK) return rc;
+        AdjArgs a{};
+        a.pk = s->d_pk;
+        a.rd = s->d_rd;
+        a.tk = s->d_tk;
+        a.ch_slot = s->d_ch;
+        a.nl = s->d_nl;
+        a.pc_gid = s->d_pc_gid;
+        a.pc_soma = s->d_pc_soma;
+        a.alpha = s->d_alpha;
+        a.F = s->d_F;
+        a.invd = s->d_invd;
+        a.hh_gna = s->d_hh_gna;
+        a.hh_gk = s->d_hh_gk;
+        a.rec_V = G.rec_V;
+        a.rec_m = G.rec_m;
+        a.rec_h = G.rec_h;
+        a.rec_n = G.rec_n;
+        a.rec_g = G.rec_g;
+        a.n_slots_total = L.n_slots;
+        a.n_hh_total = nhh;
+        a.n_syn_total = int64_t(L.syn_global.size());
+        a.lamV = G.lamV;
+        a.lamM = G.lamM;
+        a.lamH = G.lamH;
+        a.lamN = G.lamN;
+        a.accP1 = G.accP1;
+        a.accP0 = G.accP0;
+        a.accNa = G.accNa;
+        a.accK = G.accK;
+        a.dLdtrace = dL_dtrace_dev;
+        a.trace_len = G.n_steps;
+        a.trace_step0 = G.step_begin;
+        a.dt = L.dt;
+        a.step0 = begin;
+        a.nsteps = int32_t(len);
+        HIP_TRY(launch_adjoint(a, s->cfg.block_threads, G.adj_lds, int(L.packs.size()), s->st));
+    }
+    if ((rc = load_state(s, G.ckpt[G.n_seg])) != ARB_OK) return rc;
+    s->step = saved_step;
+    GradReduceArgs r{};
+    r.n_reg = int64_t(L.regions.size());
+    r.rp_off = G.rp_off;
+    r.rp_slot = G.rp_slot;
+    r.rp_hh = G.rp_hh;
+    r.rp_area = G.rp_area;
+    r.reg_mech = G.reg_mech;
+    r.reg_epas = G.reg_epas;
+    r.accP1 = G.accP1;
+    r.accP0 = G.accP0;
+    r.accNa = G.accNa;
+    r.accK = G.accK;
+    r.out = dL_dtheta_dev;
+    HIP_TRY(launch_grad_reduce(r, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    return ARB_OK;
 }
 
-void grad_release(Sim* s) { (void)s; }
+void grad_release(Sim* s) {
+    delete s->grad;
+    s->grad = nullptr;
+}
 
 }  // namespace arbmi

@@ -102,6 +102,7 @@ StepArgs Sim::step_args() const {
     a.syn_g = d_syn_g;
     a.syn_e = d_syn_e;
     a.syn_decay = d_syn_decay;
+    a.ic_slot = d_ic_slot;
     a.ic_on = d_ic_on;
     a.ic_off = d_ic_off;
     a.ic_amp = d_ic_amp;
@@ -141,6 +142,7 @@ StepArgs Sim::step_args() const {
 int Sim::advance(int64_t n, const RecordArgs* rec) {
     const bool net = !L.out_rank.empty();
     const int np = int32_t(L.packs.size());
+    int64_t done = 0;
     while (n > 0) {
         const int64_t e = step / K, pos = step % K;
         const int64_t nthis = std::min<int64_t>(n, K - pos);
@@ -152,13 +154,12 @@ int Sim::advance(int64_t n, const RecordArgs* rec) {
         a.step0 = step;
         a.nsteps = int32_t(nthis);
         a.epoch_end = (pos + nthis == K) ? 1 : 0;
-        if (rec) {
-            if (nthis != n) return fail(ARB_EINVAL, "recorded steps must fit one epoch");
-            a.rec_V = rec->V;
-            a.rec_m = rec->m;
-            a.rec_h = rec->h;
-            a.rec_n = rec->n;
-            a.rec_g = rec->g;
+        if (rec) {  // rows offset by the steps already done in this call
+            a.rec_V = rec->V + done * L.n_slots;
+            a.rec_m = rec->m + done * int64_t(L.hh_cv.size());
+            a.rec_h = rec->h + done * int64_t(L.hh_cv.size());
+            a.rec_n = rec->n + done * int64_t(L.hh_cv.size());
+            a.rec_g = rec->g + done * int64_t(L.syn_global.size());
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (p.flags & ARB_FLAG_TIME_KERNELS) {
@@ -182,6 +183,7 @@ int Sim::advance(int64_t n, const RecordArgs* rec) {
         }
         step += nthis;
         n -= nthis;
+        done += nthis;
         if (net && a.epoch_end) {
             ExchArgs x{};
             x.sp_gid = d_sp_gid;
@@ -271,6 +273,7 @@ int build_device(Sim* s) {
     s->d_syn_g = dupload(s, std::vector<double>(nsyn, 0.0), rc);
     s->d_syn_e = dupload(s, L.syn_e, rc);
     s->d_syn_decay = dupload(s, L.syn_decay, rc);
+    s->d_ic_slot = dupload(s, L.ic_slot, rc);
     s->d_ic_on = dupload(s, L.ic_on, rc);
     s->d_ic_off = dupload(s, L.ic_off, rc);
     s->d_ic_amp = dupload(s, L.ic_amp, rc);
@@ -337,6 +340,7 @@ int arb_build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     if (p->block_threads != 0 && p->block_threads != 64 && p->block_threads != 128 && p->block_threads != 256)
         return fail(ARB_EINVAL, "block_threads must be 0, 64, 128 or 256");
     if (p->coef_mode < 0 || p->coef_mode > 2) return fail(ARB_EINVAL, "coef_mode must be 0, 1 or 2");
+    if (p->cells_per_pack < 0) return fail(ARB_EINVAL, "cells_per_pack must be >= 0");
     if ((p->alloc == nullptr) != (p->free == nullptr)) return fail(ARB_EINVAL, "alloc and free must be given together");
 
     // device limits (validation below runs even without a device)
@@ -388,7 +392,11 @@ int arb_build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     s->cfg.block_threads = s->L.block_threads;
     s->cfg.coef_mode = s->L.coef_mode;
     int64_t lds = 0;
-    for (const PackDesc& D : s->L.packs) lds = std::max(lds, pack_lds_bytes(D.nslot, D.nsyn, D.nhh, s->L.coef_mode));
+    for (const PackDesc& D : s->L.packs) lds = std::max(lds, pack_lds_bytes(D, s->L.coef_mode));
+    if (lds > lds_max - 256) {
+        delete s;
+        return fail(ARB_EINVAL, "a pack needs more LDS than the device has");
+    }
     s->cfg.lds_bytes = int(std::max<int64_t>(lds, 8));
     s->exch_grid = std::max(1, std::min(4 * n_cu, int((n_cells + 3) / 4)));
     hipError_t he = prepare_step_kernels(int(lds_max));
@@ -711,6 +719,7 @@ int arb_free(arb_sim s_) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
     }
+    grad_release(s);
     s->release_all();
     delete s;
     return ARB_OK;

@@ -48,6 +48,14 @@ __device__ inline double gate_step(double x, double a, double b, double dt) {
     return xinf + (x - xinf) * exp(-dt * s);
 }
 
+constexpr int CH = 8;  // CVs of a branch staged in registers at a time
+
+// this thread's task in round R, or an empty task (len 0) if it has none
+__device__ inline TaskDesc load_task(const TaskDesc* s_tk, const RoundDesc& R, int tid) {
+    if (tid < R.w) return s_tk[R.task0 + tid];
+    return TaskDesc{0, -1, 0, 0};
+}
+
 template <int T, bool CL>
 __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
     extern __shared__ double lds[];
@@ -56,19 +64,25 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
     const int tid = threadIdx.x;
     const int ns = pk.nslot;
 
+    // ---- LDS layout (must match pack_lds_bytes) ----
     double* sV = lds;
-    double* sR = lds + ns;
-    double* rest = lds + 2 * ns;
-    double* sA = rest;
-    double* sB = rest + ns;
-    double* sF = rest + 2 * ns;
-    double* sD = rest + 3 * ns;
-    if (CL) rest += 4 * ns;
-    double* sg = rest;
-    rest += pk.nsyn;
-    double* sm = rest;
-    double* sh = rest + pk.nhh;
-    double* sn = rest + 2 * pk.nhh;
+    double* sR = sV + ns;
+    double* sA = sR + ns;
+    double* sB = sA + ns;
+    double* sF = sB + ns;
+    double* sD = sF + ns;
+    double* sg = CL ? sD + ns : sR + ns;
+    double* sm = sg + pk.nsyn;
+    double* sh = sm + pk.nhh;
+    double* sn = sh + pk.nhh;
+    double* s_gna = sn + pk.nhh;  // mode 1 only
+    double* s_gk = s_gna + pk.nhh;
+    double* s_se = s_gk + pk.nhh;
+    double* s_sdec = s_se + pk.nsyn;
+    RoundDesc* s_rd = reinterpret_cast<RoundDesc*>(CL ? s_sdec + pk.nsyn : sn + pk.nhh);
+    TaskDesc* s_tk = reinterpret_cast<TaskDesc*>(s_rd + pk.nrd);
+    NlDesc* s_nl = reinterpret_cast<NlDesc*>(s_tk + pk.ntk);
+    int32_t* s_ch = reinterpret_cast<int32_t*>(s_nl + pk.nnl);
 
     const double* gA = a.alpha + pk.slot0;
     const double* gB = a.beta + pk.slot0;
@@ -78,7 +92,16 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
     auto ldB = [&](int i) { if constexpr (CL) return sB[i]; else return gB[i]; };
     auto ldF = [&](int i) { if constexpr (CL) return sF[i]; else return gF[i]; };
     auto ldD = [&](int i) { if constexpr (CL) return sD[i]; else return gD[i]; };
+    const double* g_gna = a.hh_gna + pk.hh0;
+    const double* g_gk = a.hh_gk + pk.hh0;
+    const double* g_se = a.syn_e + pk.syn0;
+    const double* g_sdec = a.syn_decay + pk.syn0;
+    auto ldGna = [&](int i) { if constexpr (CL) return s_gna[i]; else return g_gna[i]; };
+    auto ldGk = [&](int i) { if constexpr (CL) return s_gk[i]; else return g_gk[i]; };
+    auto ldSe = [&](int i) { if constexpr (CL) return s_se[i]; else return g_se[i]; };
+    auto ldSdec = [&](int i) { if constexpr (CL) return s_sdec[i]; else return g_sdec[i]; };
 
+    // ---- stage the pack in LDS ----
     for (int i = tid; i < ns; i += T) {
         sV[i] = a.V[pk.slot0 + i];
         sR[i] = 0.0;
@@ -89,22 +112,42 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
             sD[i] = gD[i];
         }
     }
-    for (int i = tid; i < pk.nsyn; i += T) sg[i] = a.syn_g[pk.syn0 + i];
+    for (int i = tid; i < pk.nsyn; i += T) {
+        sg[i] = a.syn_g[pk.syn0 + i];
+        if constexpr (CL) {
+            s_se[i] = g_se[i];
+            s_sdec[i] = g_sdec[i];
+        }
+    }
     for (int i = tid; i < pk.nhh; i += T) {
         sm[i] = a.hh_m[pk.hh0 + i];
         sh[i] = a.hh_h[pk.hh0 + i];
         sn[i] = a.hh_n[pk.hh0 + i];
+        if constexpr (CL) {
+            s_gna[i] = g_gna[i];
+            s_gk[i] = g_gk[i];
+        }
     }
-    __shared__ int64_t s_xcur;
-    __shared__ int32_t s_ncur, s_nend;
+    for (int i = tid; i < pk.nrd; i += T) s_rd[i] = a.rd[pk.rd0 + i];
+    for (int i = tid; i < pk.ntk; i += T) s_tk[i] = a.tk[pk.tk0 + i];
+    for (int i = tid; i < pk.nnl; i += T) s_nl[i] = a.nl[pk.nl0 + i];
+    for (int i = tid; i < pk.nch; i += T) s_ch[i] = a.ch_slot[pk.ch0 + i];
+
+    // event cursors live in thread 0's registers, with the next key cached
     const int64_t bk_base = (int64_t(a.bucket) * a.n_packs + p);
-    if (tid == 0) {
-        s_xcur = a.pk_xcur[p];
-        s_ncur = a.pk_ncur[p];
-        const uint32_t c = a.bk_cnt[bk_base];
-        s_nend = int32_t(c < uint32_t(a.bk_cap) ? c : uint32_t(a.bk_cap));
-    }
     const uint64_t* ev = a.bk_ev + bk_base * a.bk_cap;
+    int32_t ncur = 0, nend = 0;
+    int64_t xcur = 0;
+    uint64_t nkey = ~uint64_t(0);
+    int64_t xstep = INT64_MAX;
+    if (tid == 0) {
+        xcur = a.pk_xcur[p];
+        ncur = a.pk_ncur[p];
+        const uint32_t c = a.bk_cnt[bk_base];
+        nend = int32_t(c < uint32_t(a.bk_cap) ? c : uint32_t(a.bk_cap));
+        if (ncur < nend) nkey = ev[ncur];
+        if (xcur < pk.xe1) xstep = a.xe_step[xcur];
+    }
     const int soma = (tid < pk.ncell) ? a.pc_soma[pk.cell0 + tid] : -1;
     double vold = 0.0;
     __syncthreads();
@@ -114,21 +157,17 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
 
         // A: events due at the start of step n (network, then external)
         if (tid == 0) {
-            int32_t c = s_ncur;
-            while (c < s_nend) {
-                const uint64_t key = ev[c];
-                if (int64_t(key >> 32) != n) break;
-                const uint32_t r = uint32_t(key);
+            while (int64_t(nkey >> 32) == n) {
+                const uint32_t r = uint32_t(nkey);
                 sg[a.cr_syn[r]] += a.cr_w[r];
-                ++c;
+                ++ncur;
+                nkey = (ncur < nend) ? ev[ncur] : ~uint64_t(0);
             }
-            s_ncur = c;
-            int64_t x = s_xcur;
-            while (x < pk.xe1 && a.xe_step[x] == n) {
-                sg[a.xe_syn[x]] += a.xe_w[x];
-                ++x;
+            while (xstep == n) {
+                sg[a.xe_syn[xcur]] += a.xe_w[xcur];
+                ++xcur;
+                xstep = (xcur < pk.xe1) ? a.xe_step[xcur] : INT64_MAX;
             }
-            s_xcur = x;
         }
         __syncthreads();
 
@@ -149,70 +188,125 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
 
         // B: nonlinear and point currents at V^n, stored as -I in R
         for (int j = tid; j < pk.nnl; j += T) {
-            const NlDesc d = a.nl[pk.nl0 + j];
+            const NlDesc d = s_nl[j];
             const double v = sV[d.slot];
             double I = 0.0;
             if (d.hh >= 0) {
                 const int q = d.hh;
                 const double m = sm[q], h = sh[q], g = sn[q];
-                I += a.hh_gna[pk.hh0 + q] * (m * m * m * h) * (v - kENa);
-                I += a.hh_gk[pk.hh0 + q] * (g * g * g * g) * (v - kEK);
+                I += ldGna(q) * (m * m * m * h) * (v - kENa);
+                I += ldGk(q) * (g * g * g * g) * (v - kEK);
             }
             for (int k = 0; k < d.nsyn; ++k) {
                 const int q = d.syn0 + k;
-                I += sg[q] * (v - a.syn_e[pk.syn0 + q]);
-            }
-            for (int k = 0; k < d.nic; ++k) {
-                const int q = d.ic0 + k;
-                if (a.ic_on[q] <= n && n < a.ic_off[q]) I -= a.ic_amp[q];
+                I += sg[q] * (v - ldSe(q));
             }
             sR[d.slot] = -I;
         }
         if (soma >= 0) vold = sV[soma];
+        if (pk.nic > 0) {  // current clamps, one thread, in (slot, input) order
+            __syncthreads();
+            if (tid == 0)
+                for (int q = pk.ic0; q < pk.ic0 + pk.nic; ++q)
+                    if (a.ic_on[q] <= n && n < a.ic_off[q]) sR[a.ic_slot[q]] += a.ic_amp[q];
+        }
         __syncthreads();
 
-        // C: elimination, deepest rounds first
-        for (int r = 0; r < pk.nrd; ++r) {
-            const RoundDesc R = a.rd[pk.rd0 + r];
-            if (tid < R.w) {
-                const TaskDesc t = a.tk[R.task0 + tid];
-                int slot = R.slot0 + tid + (t.len - 1) * R.w;
-                double acc = ldA(slot) * sV[slot] + ldB(slot) + sR[slot];
-                for (int c = 0; c < t.nch; ++c) {
-                    const int cs = a.ch_slot[t.ch0 + c];
-                    acc -= ldF(cs) * sR[cs];
+        // C: elimination, deepest rounds first.  Each thread walks its branch
+        // from the distal end in chunks of CH CVs: the chunk's operands are
+        // loaded first (unconditional loads at clamped indices, so they issue
+        // together), then the dependent recurrence
+        // rhs'_k = t_k - F_{k+1} rhs'_{k+1} runs in registers.  The next
+        // round's descriptors are fetched while this round works.
+        {
+            RoundDesc R = s_rd[0];
+            TaskDesc t = load_task(s_tk, R, tid);
+            for (int r = 0; r < pk.nrd; ++r) {
+                RoundDesc Rn = R;
+                TaskDesc tn = t;
+                if (r + 1 < pk.nrd) {
+                    Rn = s_rd[r + 1];
+                    tn = load_task(s_tk, Rn, tid);
                 }
-                sR[slot] = acc;
-                for (int k = t.len - 2; k >= 0; --k) {
-                    const double f = ldF(slot);
-                    slot -= R.w;
-                    acc = ldA(slot) * sV[slot] + ldB(slot) + sR[slot] - f * acc;
-                    sR[slot] = acc;
+                if (t.len > 0) {
+                    const int base = R.slot0 + tid;
+                    const int w = R.w;
+                    double csum = 0.0;
+                    for (int c = 0; c < t.nch; ++c) {
+                        const int cs = s_ch[t.ch0 + c];
+                        csum += ldF(cs) * sR[cs];
+                    }
+                    double acc = 0.0, fprev = 0.0;
+                    for (int k0 = t.len - 1; k0 >= 0; k0 -= CH) {
+                        double tv[CH], fv[CH];
+#pragma unroll
+                        for (int j = 0; j < CH; ++j) {
+                            const int sl = base + max(k0 - j, 0) * w;
+                            tv[j] = ldA(sl) * sV[sl] + ldB(sl) + sR[sl];
+                            fv[j] = ldF(sl);
+                        }
+#pragma unroll
+                        for (int j = 0; j < CH; ++j) {
+                            const int k = k0 - j;
+                            if (k >= 0) {
+                                acc = (k == t.len - 1) ? tv[j] - csum : tv[j] - fprev * acc;
+                                fprev = fv[j];
+                                sR[base + k * w] = acc;
+                            }
+                        }
+                    }
                 }
+                __syncthreads();
+                R = Rn;
+                t = tn;
             }
-            __syncthreads();
         }
 
         // D: substitution, shallowest rounds first; clears R for the next step
-        for (int r = pk.nrd - 1; r >= 0; --r) {
-            const RoundDesc R = a.rd[pk.rd0 + r];
-            if (tid < R.w) {
-                const TaskDesc t = a.tk[R.task0 + tid];
-                double x = (t.par >= 0) ? sV[t.par] : 0.0;
-                int slot = R.slot0 + tid;
-                for (int k = 0; k < t.len; ++k) {
-                    x = sR[slot] * ldD(slot) - ldF(slot) * x;
-                    sV[slot] = x;
-                    sR[slot] = 0.0;
-                    slot += R.w;
+        {
+            RoundDesc R = s_rd[pk.nrd - 1];
+            TaskDesc t = load_task(s_tk, R, tid);
+            for (int r = pk.nrd - 1; r >= 0; --r) {
+                RoundDesc Rn = R;
+                TaskDesc tn = t;
+                if (r > 0) {
+                    Rn = s_rd[r - 1];
+                    tn = load_task(s_tk, Rn, tid);
                 }
+                if (t.len > 0) {
+                    const int base = R.slot0 + tid;
+                    const int w = R.w;
+                    double x = (t.par >= 0) ? sV[t.par] : 0.0;
+                    for (int k0 = 0; k0 < t.len; k0 += CH) {
+                        double rv[CH], dv[CH], fv[CH];
+#pragma unroll
+                        for (int j = 0; j < CH; ++j) {
+                            const int sl = base + min(k0 + j, t.len - 1) * w;
+                            rv[j] = sR[sl];
+                            dv[j] = ldD(sl);
+                            fv[j] = ldF(sl);
+                        }
+#pragma unroll
+                        for (int j = 0; j < CH; ++j) {
+                            const int k = k0 + j;
+                            if (k < t.len) {
+                                const int sl = base + k * w;
+                                x = rv[j] * dv[j] - fv[j] * x;
+                                sV[sl] = x;
+                                sR[sl] = 0.0;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                R = Rn;
+                t = tn;
             }
-            __syncthreads();
         }
 
         // E: states with V^{n+1}, threshold, probes
         for (int j = tid; j < pk.nnl; j += T) {
-            const NlDesc d = a.nl[pk.nl0 + j];
+            const NlDesc d = s_nl[j];
             if (d.hh >= 0) {
                 const int q = d.hh;
                 const Rates rt = hh_rates(sV[d.slot]);
@@ -222,7 +316,7 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
             }
             for (int k = 0; k < d.nsyn; ++k) {
                 const int q = d.syn0 + k;
-                sg[q] *= a.syn_decay[pk.syn0 + q];
+                sg[q] *= ldSdec(q);
             }
         }
         if (soma >= 0) {
@@ -259,8 +353,8 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
         a.hh_n[pk.hh0 + i] = sn[i];
     }
     if (tid == 0) {
-        a.pk_xcur[p] = s_xcur;
-        a.pk_ncur[p] = s_ncur;
+        a.pk_xcur[p] = xcur;
+        a.pk_ncur[p] = ncur;
         if (a.epoch_end) a.bk_cnt[bk_base] = 0u;
     }
 }

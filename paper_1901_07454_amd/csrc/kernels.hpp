@@ -30,6 +30,7 @@ struct StepArgs {
     double* syn_g;             // [n_syn] nS
     const double* syn_e;
     const double* syn_decay;   // exp(-dt/tau)
+    const int32_t* ic_slot;    // pack-local slot of each clamp
     const int64_t* ic_on;
     const int64_t* ic_off;
     const double* ic_amp;      // pA

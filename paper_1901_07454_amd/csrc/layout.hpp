@@ -36,9 +36,25 @@ struct PackDesc {
     int32_t nsyn;
     int32_t pr0;     // probes
     int32_t npr;
-    int32_t pad;
+    int32_t tk0;     // first task (tasks of a pack are contiguous)
+    int32_t ntk;
+    int32_t ch0;     // first child-slot entry
+    int32_t nch;
+    int32_t ic0;     // first clamp entry
+    int32_t nic;
     int64_t xe0, xe1; // external events [xe0, xe1), sorted by (step, syn, input order)
 };
+
+// Bytes of dynamic LDS the step kernel uses for a pack.  Layout in the
+// kernel: doubles V, R, [alpha, beta, F, 1/d'], g, m, h, n, [gNa, gK, e_syn,
+// decay]; then rounds, tasks, nonlinear entries, child slots.  Bracketed
+// parts are staged only in coefficient mode 1 (mode 2 streams them).
+inline int64_t pack_lds_bytes(const PackDesc& D, int coef_mode) {
+    const bool cl = coef_mode == 1;
+    const int64_t dbl = (cl ? 6 : 2) * int64_t(D.nslot) + int64_t(D.nsyn) + 3 * int64_t(D.nhh) +
+                        (cl ? 2 * (int64_t(D.nhh) + int64_t(D.nsyn)) : 0);
+    return 8 * dbl + 16 * int64_t(D.nrd) + 16 * int64_t(D.ntk) + 16 * int64_t(D.nnl) + 4 * int64_t(D.nch);
+}
 
 struct RoundDesc {
     int32_t slot0;  // pack-local slot of (k = 0, t = 0)
@@ -54,13 +70,11 @@ struct TaskDesc {
     int32_t nch;    //   proximal CVs of the child branches, in branch order
 };
 
-struct NlDesc {     // one CV carrying nonlinear or point terms
+struct NlDesc {     // one CV carrying an hh instance or synapses
     int32_t slot;   // pack-local slot
     int32_t hh;     // pack-local hh instance, -1 if none
     int32_t syn0;   // pack-local synapses [syn0, syn0 + nsyn)
     int32_t nsyn;
-    int32_t ic0;    // global clamp entries [ic0, ic0 + nic)
-    int32_t nic;
 };
 
 // Device counters and flags of a sim.

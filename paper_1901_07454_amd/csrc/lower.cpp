@@ -28,9 +28,14 @@
 
 namespace arbmi {
 
-int64_t pack_lds_bytes(int64_t nslot, int64_t nsyn, int64_t nhh, int coef_mode) {
+int64_t pack_lds_estimate(int64_t nslot, int64_t nsyn, int64_t nhh, int64_t nbranch, int64_t ncell,
+                          int64_t nic, int coef_mode) {
     const int64_t per_slot = (coef_mode == 1) ? 6 : 2;  // V, R (+ alpha, beta, F, invd)
-    return 8 * (per_slot * nslot + nsyn + 3 * nhh);
+    const int64_t tasks = nbranch + ncell;
+    (void)nic;
+    // rounds <= tasks; nonlinear entries <= hh + synapses
+    return 8 * (per_slot * nslot + nsyn + 3 * nhh + (coef_mode == 1 ? 2 * (nhh + nsyn) : 0)) + 16 * tasks +
+           16 * tasks + 16 * (nhh + nsyn) + 4 * nbranch;
 }
 
 namespace {
@@ -66,7 +71,8 @@ int64_t locate(const arb_cell& c, const arb_branch* br, const std::vector<int>& 
 struct PackPlan {
     std::vector<int32_t> cells;
     int64_t nslot = 0;
-    int64_t nsyn = 0, nhh = 0;
+    int64_t nsyn = 0, nhh = 0, nbr = 0, nic = 0;
+    int64_t lds(int mode) const { return pack_lds_estimate(nslot, nsyn, nhh, nbr, int64_t(cells.size()), nic, mode); }
 };
 
 }  // namespace
@@ -241,21 +247,23 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
     std::vector<int32_t> nsyn_cv(L.n_cv, 0), nic_cv(L.n_cv, 0);
     for (int64_t q = 0; q < n_syn; ++q) nsyn_cv[syn_cv[q]]++;
     for (int32_t q = 0; q < n_ic; ++q) nic_cv[ic_cv[q]]++;
-    std::vector<int32_t> nhh_cell(n_cells, 0), nsyn_cell(n_cells, 0);
+    std::vector<int32_t> nhh_cell(n_cells, 0), nsyn_cell(n_cells, 0), nic_cell(n_cells, 0);
     for (int32_t c = 0; c < n_cells; ++c)
         for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i) {
             nhh_cell[c] += has_hh[i];
             nsyn_cell[c] += nsyn_cv[i];
+            nic_cell[c] += nic_cv[i];
         }
 
     // -------------------------------------------------------------- packing
     const int T = opt.block_threads;
     L.block_threads = T;
-    // slot count of a set of cells under the round layout
-    auto plan_slots = [&](const std::vector<int32_t>& cs) -> int64_t {
+    // slot and round counts of a set of cells under the round layout
+    struct Shape { int64_t nslot = 0, nrd = 0; };
+    auto plan_shape = [&](const std::vector<int32_t>& cs) -> Shape {
         int maxd = 0;
         for (int32_t c : cs) for (int d : geo[c].depth) maxd = std::max(maxd, d);
-        int64_t ns = 0;
+        Shape sh;
         for (int d = maxd; d >= 0; --d) {
             std::vector<int> lens;
             for (int32_t c : cs) {
@@ -266,10 +274,31 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             for (size_t s = 0; s < lens.size(); s += T) {
                 size_t e = std::min(lens.size(), s + T);
                 int mx = *std::max_element(lens.begin() + s, lens.begin() + e);
-                ns += int64_t(mx) * int64_t(e - s);
+                sh.nslot += int64_t(mx) * int64_t(e - s);
+                sh.nrd++;
             }
         }
-        return ns;
+        return sh;
+    };
+    auto plan_slots = [&](const std::vector<int32_t>& cs) -> int64_t { return plan_shape(cs).nslot; };
+    (void)plan_slots;
+    // CVs carrying hh or synapses, per cell
+    std::vector<int32_t> nnl_cell(n_cells, 0);
+    for (int32_t c = 0; c < n_cells; ++c)
+        for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i) nnl_cell[c] += (has_hh[i] || nsyn_cv[i]) ? 1 : 0;
+    auto exact_lds = [&](const PackPlan& pp, int mode) -> int64_t {
+        const Shape sh = plan_shape(pp.cells);
+        PackDesc D{};
+        D.nslot = int32_t(sh.nslot);
+        D.nrd = int32_t(sh.nrd);
+        D.ntk = int32_t(pp.nbr + int64_t(pp.cells.size()));
+        D.nch = int32_t(pp.nbr);
+        D.nsyn = int32_t(pp.nsyn);
+        D.nhh = int32_t(pp.nhh);
+        int64_t nnl = 0;
+        for (int32_t c : pp.cells) nnl += nnl_cell[c];
+        D.nnl = int32_t(nnl);
+        return pack_lds_bytes(D, mode);
     };
     std::vector<int32_t> order(n_cells);
     std::iota(order.begin(), order.end(), 0);
@@ -284,29 +313,28 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             trial.cells.push_back(c);
             trial.nsyn += nsyn_cell[c];
             trial.nhh += nhh_cell[c];
+            trial.nbr += cells[c].n_branch;
+            trial.nic += nic_cell[c];
             bool fits = int64_t(trial.cells.size()) <= max_cells;
-            if (fits && !cur.cells.empty()) {
-                trial.nslot = plan_slots(trial.cells);
-                fits = pack_lds_bytes(trial.nslot, trial.nsyn, trial.nhh, coef_mode) <= opt.lds_budget;
-            }
+            if (fits && !cur.cells.empty()) fits = exact_lds(trial, coef_mode) <= opt.lds_budget;
             if (!fits) {
                 plans.push_back(cur);
                 cur = PackPlan();
                 cur.cells.push_back(c);
                 cur.nsyn = nsyn_cell[c];
                 cur.nhh = nhh_cell[c];
-                cur.nslot = plan_slots(cur.cells);
+                cur.nbr = cells[c].n_branch;
+                cur.nic = nic_cell[c];
             } else {
-                if (cur.cells.empty()) trial.nslot = plan_slots(trial.cells);
                 cur = trial;
             }
         }
         if (!cur.cells.empty()) plans.push_back(cur);
     }
     for (const PackPlan& pp : plans)
-        if (pack_lds_bytes(pp.nslot, pp.nsyn, pp.nhh, coef_mode) > opt.lds_hard_max) {
+        if (exact_lds(pp, coef_mode) > opt.lds_hard_max) {
             err = fmt("a cell needs %lld bytes of LDS, more than the %lld available",
-                      (long long)pack_lds_bytes(pp.nslot, pp.nsyn, pp.nhh, coef_mode), (long long)opt.lds_hard_max);
+                      (long long)exact_lds(pp, coef_mode), (long long)opt.lds_hard_max);
             return ARB_EINVAL;
         }
     L.coef_mode = coef_mode;
@@ -366,15 +394,17 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         }
         D.nslot = int32_t(ns);
         D.nrd = int32_t(rds.size());
+        D.tk0 = int32_t(L.tasks.size());
+        D.ch0 = int32_t(L.ch_slot.size());
         // tasks (need every slot assigned first, for parents and children)
         for (size_t r = 0; r < rds.size(); ++r) {
-            rds[r].task0 = int32_t(L.tasks.size());
+            rds[r].task0 = int32_t(L.tasks.size()) - D.tk0;  // pack-local task
             for (const Item& it : rounds_items[r]) {
                 const int64_t cv0 = L.cell_cv0[it.c];
                 TaskDesc T_{};
                 T_.len = it.len;
                 T_.par = (it.b < 0) ? -1 : int32_t(slot_of_user[cv0 + geo[it.c].pnode[it.b]] - slot_base);
-                T_.ch0 = int32_t(L.ch_slot.size());
+                T_.ch0 = int32_t(L.ch_slot.size()) - D.ch0;  // pack-local child entry
                 T_.nch = 0;
                 for (int32_t b2 = 0; b2 < cells[it.c].n_branch; ++b2)
                     if (br[cells[it.c].branch_begin + b2].parent == it.b) {
@@ -385,6 +415,8 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             }
             L.rounds.push_back(rds[r]);
         }
+        D.ntk = int32_t(L.tasks.size()) - D.tk0;
+        D.nch = int32_t(L.ch_slot.size()) - D.ch0;
         for (int32_t c : pp.cells) {
             L.pc_gid.push_back(c);
             L.pc_soma.push_back(int32_t(slot_of_user[L.cell_cv0[c]] - slot_base));
@@ -435,11 +467,12 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         D.nl0 = int32_t(L.nl.size());
         D.hh0 = int32_t(L.hh_cv.size());
         D.syn0 = int32_t(L.syn_global.size());
+        D.ic0 = int32_t(L.ic_on.size());
         std::vector<std::pair<int64_t, int64_t>> here;  // (slot, user cv)
         for (int32_t k = 0; k < D.ncell; ++k) {
             const int32_t c = L.pc_gid[D.cell0 + k];
             for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i)
-                if (has_hh[i] || nsyn_cv[i] || nic_cv[i]) here.push_back({L.perm[i], i});
+                if (has_hh[i] || nsyn_cv[i]) here.push_back({L.perm[i], i});
         }
         std::sort(here.begin(), here.end());
         for (auto& sc : here) {
@@ -456,16 +489,24 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                 L.syn_e.push_back(syn[q].e_rev_mV);
                 L.syn_decay.push_back(std::exp(-dt / syn[q].tau_ms));
             }
-            N.ic0 = int32_t(L.ic_on.size());
-            N.nic = int32_t(ic_at[i].size());
-            for (int64_t q : ic_at[i]) {
-                L.ic_on.push_back(ic[q].step_on);
-                L.ic_off.push_back(ic[q].step_off);
-                L.ic_amp.push_back(1000.0 * ic[q].amp_nA);  // nA -> pA
-            }
             L.nl.push_back(N);
         }
+        // clamps of the pack, by slot then input order
+        std::vector<std::pair<int64_t, int64_t>> cl;  // (slot, clamp)
+        for (int32_t k = 0; k < D.ncell; ++k) {
+            const int32_t c = L.pc_gid[D.cell0 + k];
+            for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i)
+                for (int64_t q : ic_at[i]) cl.push_back({L.perm[i], q});
+        }
+        std::sort(cl.begin(), cl.end());
+        for (auto& sq : cl) {
+            L.ic_slot.push_back(int32_t(sq.first - D.slot0));
+            L.ic_on.push_back(ic[sq.second].step_on);
+            L.ic_off.push_back(ic[sq.second].step_off);
+            L.ic_amp.push_back(1000.0 * ic[sq.second].amp_nA);  // nA -> pA
+        }
         D.nnl = int32_t(L.nl.size()) - D.nl0;
+        D.nic = int32_t(L.ic_on.size()) - D.ic0;
         D.nhh = int32_t(L.hh_cv.size()) - D.hh0;
         D.nsyn = int32_t(L.syn_global.size()) - D.syn0;
     }

@@ -55,7 +55,8 @@ struct Lowered {
     std::vector<int64_t> syn_global;          // pack-order index -> global synapse
     std::vector<int64_t> syn_pack_index;      // global synapse -> pack-order index
     std::vector<double> syn_e, syn_decay;
-    // clamps, NL order
+    // clamps, per pack, ordered by (slot, input order)
+    std::vector<int32_t> ic_slot;             // pack-local slot
     std::vector<int64_t> ic_on, ic_off;
     std::vector<double> ic_amp;               // pA
     // external events, pack order
@@ -89,7 +90,9 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
 // Recompute alpha, beta, hh_gna, hh_gk from lw.regions (after a parameter change).
 void recompute_coefficients(Lowered& lw);
 
-// LDS bytes a pack needs in the given coefficient mode.
-int64_t pack_lds_bytes(int64_t nslot, int64_t nsyn, int64_t nhh, int coef_mode);
+// Upper bound of the LDS bytes a pack with these counts needs (used while
+// packing, before the pack's descriptors exist).
+int64_t pack_lds_estimate(int64_t nslot, int64_t nsyn, int64_t nhh, int64_t nbranch, int64_t ncell,
+                          int64_t nic, int coef_mode);
 
 }  // namespace arbmi

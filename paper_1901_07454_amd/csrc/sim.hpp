@@ -60,6 +60,7 @@ struct Sim : arb_sim_ {
     double *d_V = nullptr, *d_alpha = nullptr, *d_beta = nullptr, *d_F = nullptr, *d_invd = nullptr;
     double *d_hh_m = nullptr, *d_hh_h = nullptr, *d_hh_n = nullptr, *d_hh_gna = nullptr, *d_hh_gk = nullptr;
     double *d_syn_g = nullptr, *d_syn_e = nullptr, *d_syn_decay = nullptr;
+    int32_t* d_ic_slot = nullptr;
     int64_t *d_ic_on = nullptr, *d_ic_off = nullptr;
     double* d_ic_amp = nullptr;
     int64_t* d_xe_step = nullptr;

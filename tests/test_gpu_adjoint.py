@@ -1,0 +1,97 @@
+"""GPU adjoint (through the C ABI and torch.autograd) against the oracle's
+discrete adjoint and against central finite differences of the GPU forward."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n_cells, n_steps):
+    import torch
+
+    from paper_1901_07454_amd import grad
+    m0 = gen.config4(n_cells=n_cells, n_steps=n_steps)
+    mh = gen.config4(n_cells=n_cells, hidden=True, n_steps=n_steps)
+    th0 = gen.config4_theta(m0)
+    ref = oracle.Sim(mh)
+    tgt = ref.run(n_steps, probes=oracle.cell_cv_begin(mh)[:-1])
+    gs = grad.GradSim(m0)
+    theta = torch.tensor(th0, dtype=torch.float64, device="cuda", requires_grad=True)
+    return m0, th0, tgt, gs, theta
+
+
+def _loss_grad(gs, theta, tgt, n_steps, k):
+    import torch
+
+    from paper_1901_07454_amd import grad
+    theta = theta.detach().clone().requires_grad_(True)
+    tr = grad.soma_trace(theta, gs, n_steps, k)
+    loss = torch.mean((tr - torch.as_tensor(tgt, device=tr.device)) ** 2)
+    loss.backward()
+    return tr.detach().cpu().numpy(), loss.item(), theta.grad.detach().cpu().numpy()
+
+
+def test_adjoint_matches_oracle_adjoint():
+    n_cells, n_steps = 6, 800
+    m0, th0, tgt, gs, theta = _setup(n_cells, n_steps)
+    tr, L, g = _loss_grad(gs, theta, tgt, n_steps, 100)
+    s = oracle.Sim(m0)
+    s.set_params(th0.reshape(-1, 3))
+    dl = 2.0 * (tr - tgt) / tr.size
+    otr, og = s.adjoint(n_steps, dl)
+    og = og.reshape(th0.shape)
+    assert np.max(np.abs(tr - otr)) <= 1e-8
+    rel = np.abs(g - og) / np.maximum(np.abs(og), 1e-3 * np.max(np.abs(og), axis=(1, 2), keepdims=True))
+    print(f"max rel |g_gpu - g_oracle| = {rel.max():.3e}", flush=True)
+    assert rel.max() <= 1e-7
+    gs.close()
+
+
+def test_adjoint_checkpoint_interval_invariant():
+    n_cells, n_steps = 3, 600
+    m0, th0, tgt, gs, theta = _setup(n_cells, n_steps)
+    ref = _loss_grad(gs, theta, tgt, n_steps, 600)[2]
+    for k in (1, 37, 100):
+        g = _loss_grad(gs, theta, tgt, n_steps, k)[2]
+        assert np.allclose(g, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    gs.close()
+
+
+def test_adjoint_matches_gpu_finite_differences():
+    n_cells, n_steps = 4, 600
+    m0, th0, tgt, gs, theta = _setup(n_cells, n_steps)
+    _, _, g = _loss_grad(gs, theta, tgt, n_steps, 100)
+    import torch
+    h = 1e-5
+    fd = np.zeros_like(th0)
+    for r in range(th0.shape[1]):
+        for q in range(3):
+            vals = []
+            for sgn in (1, -1):
+                t = th0.copy()
+                t[:, r, q] *= 1 + sgn * h
+                tr, _, _ = _loss_grad(gs, torch.tensor(t, device="cuda"), tgt, n_steps, 600)
+                vals.append(np.mean((tr - tgt) ** 2, axis=1) / n_cells)
+            fd[:, r, q] = (vals[0] - vals[1]) / (2 * h * th0[:, r, q])
+    for c in range(n_cells):
+        for q in range(3):
+            den = np.maximum(np.abs(fd[c, :, q]), 1e-3 * np.max(np.abs(fd[c, :, q])))
+            rel = np.abs(g[c, :, q] - fd[c, :, q]) / den
+            assert rel.max() <= 1e-5, (c, q, rel.max())
+    gs.close()
+
+
+def test_forward_state_restored_after_backward():
+    n_cells, n_steps = 2, 300
+    m0, th0, tgt, gs, theta = _setup(n_cells, n_steps)
+    import torch
+
+    from paper_1901_07454_amd import grad
+    tr = grad.soma_trace(theta, gs, n_steps, 100)
+    v_after_fwd = gs.sim.voltages_host()
+    torch.mean(tr).backward()
+    assert np.array_equal(gs.sim.voltages_host(), v_after_fwd)
+    gs.close()
