@@ -116,6 +116,47 @@ def cpu_baseline(cfg: int, budget_s: float = 20.0):
                        f"{cpu_s:.1f} s CPU, {wall:.1f} s wall")}
 
 
+def grad_ratio(torch, reps: int = 3):
+    """Config 4: time of forward+adjoint gradient over time of the plain
+    forward, same sim, same GPU (2000 steps, checkpoints every 100)."""
+    from paper_1901_07454_amd import grad
+    from workloads import gen
+    n_steps, k = 2000, 100
+    m0 = gen.config4(n_steps=n_steps)
+    gs = grad.GradSim(m0)
+    theta = torch.tensor(gen.config4_theta(m0), dtype=torch.float64, device="cuda", requires_grad=True)
+    target = torch.zeros(gs.n_cells, n_steps, dtype=torch.float64, device="cuda")
+
+    def fwd():
+        gs.sim.set_state(gs.state0)
+        gs.sim.step(n_steps)
+        gs.sim.sync()
+
+    def fwd_adj():
+        th = theta.detach().clone().requires_grad_(True)
+        tr = grad.soma_trace(th, gs, n_steps, k)
+        loss = torch.mean((tr - target) ** 2)
+        loss.backward()
+        torch.cuda.synchronize()
+        return th.grad
+
+    fwd()
+    fwd_adj()
+    t_f, t_fa = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fwd()
+        t_f.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        fwd_adj()
+        t_fa.append(time.perf_counter() - t0)
+    gs.close()
+    f, fa = min(t_f), min(t_fa)
+    return {"workload": "config 4: 256 cells x 200 CVs, hh+pas, 2000 steps, checkpoint every 100",
+            "fwd_ms": f * 1e3, "fwd_adj_ms": fa * 1e3, "ratio": fa / f, "target_ratio": 4.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +168,7 @@ def main():
     ap.add_argument("--coef-mode", type=int, default=0)
     ap.add_argument("--cells-per-pack", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -201,6 +243,8 @@ def main():
                      "measured_copy_GBps": copy_gbps},
     }
     sim.close()
+    if not args.no_grad:
+        out["grad"] = grad_ratio(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.config)
     print(json.dumps(out))

@@ -131,13 +131,18 @@ typedef struct {
     int64_t spike_capacity;   /* spikes kept between arb_get_spikes calls; 0 = default */
     int64_t event_capacity;   /* network events per (cell pack, epoch); 0 = default */
     int32_t block_threads;    /* threads per cell pack; 0 = autotuned */
-    int32_t coef_mode;        /* 0 = autotuned, 1 = per-CV coefficients in LDS, 2 = streamed */
+    int32_t coef_mode;        /* 0 = autotuned, 1 = per-CV coefficients in LDS, 2 = streamed,
+                                 3 = held in registers (branches of <= 16 CVs) */
     int32_t cells_per_pack;   /* most cells one workgroup advances; 0 = autotuned */
     int32_t reserved;
 } arb_params;
 
 #define ARB_FLAG_TIME_KERNELS 1 /* record HIP events around every step kernel */
 #define ARB_FLAG_GRADIENTS 2    /* size cell packs so the adjoint kernel fits (use with arb_grad_*) */
+#define ARB_FLAG_GRAPH 4        /* replay whole epochs from a captured HIP graph */
+#define ARB_FLAG_AUTOTUNE 8     /* time candidate launch shapes on a sample of the cells at build;
+                                   cached by model shape and device in the file named by the
+                                   environment variable ARB_AUTOTUNE_CACHE, if set */
 
 typedef struct {
     uint32_t gid;
@@ -155,7 +160,7 @@ typedef struct {
     int64_t step;             /* steps completed */
     int32_t epoch_steps;
     int32_t block_threads;
-    int32_t coef_mode;        /* 1 = LDS, 2 = streamed */
+    int32_t coef_mode;        /* 1 = LDS, 2 = streamed, 3 = registers */
     int32_t lds_bytes;        /* dynamic LDS per workgroup */
     int64_t device_bytes;     /* device memory held by the sim */
     int64_t bytes_per_step;   /* algorithmic HBM bytes one step must move (SoA model) */

@@ -22,6 +22,8 @@ ARB_OK, ARB_EINVAL, ARB_ENOMEM, ARB_EHIP, ARB_ESTATE, ARB_EOVERFLOW = 0, -1, -2,
 ARB_MECH_HH, ARB_MECH_PAS = 1, 2
 ARB_FLAG_TIME_KERNELS = 1
 ARB_FLAG_GRADIENTS = 2
+ARB_FLAG_GRAPH = 4
+ARB_FLAG_AUTOTUNE = 8
 
 # numpy mirrors of the ABI structs (natural C alignment)
 BRANCH = np.dtype([("parent", "<i4"), ("n_cv", "<i4"), ("length_um", "<f8"), ("diam_um", "<f8"),

@@ -198,6 +198,7 @@ int grad_forward(Sim* s, int64_t n_steps, int32_t ckpt_every, double* trace_dev)
         s->n_probe = L.n_cells;
         s->trace_cap = n_steps;
         s->trace_step0 = s->step;
+        s->graph_dirty = true;
     }
     G.step_begin = s->step;
     for (int64_t j = 0; j < G.n_seg; ++j) {
@@ -211,6 +212,7 @@ int grad_forward(Sim* s, int64_t n_steps, int32_t ckpt_every, double* trace_dev)
     s->d_trace = nullptr;
     s->n_probe = 0;
     s->trace_cap = 0;
+    s->graph_dirty = true;
     G.ready = true;
     s->grad_valid = true;
     return ARB_OK;

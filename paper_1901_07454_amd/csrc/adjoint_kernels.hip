@@ -18,19 +18,13 @@
 #include <hip/hip_runtime.h>
 
 #include "adjoint_kernels.hpp"
+#include "kernel_common.hpp"
 
 namespace arbmi {
 
 namespace {
 
-__device__ inline double exprelr(double x) { return (1.0 + x == 1.0) ? 1.0 : x / expm1(x); }
-
-// d/dx of x / (exp(x) - 1); a short series near the removable singularity
-__device__ inline double exprelr_dx(double x) {
-    if (fabs(x) < 1e-4) return -0.5 + x * (1.0 / 6.0) - x * x * x * (1.0 / 180.0);
-    const double em = expm1(x);
-    return (em - x * (em + 1.0)) / (em * em);
-}
+using namespace dev;
 
 struct GateD {
     double E;      // dPhi/dx = exp(-dt (a + b))
@@ -47,11 +41,6 @@ __device__ inline GateD gate_sens(double x0, double a, double b, double da, doub
     g.E = E;
     g.dPhi = dxinf * (1.0 - E) + (x0 - xinf) * E * (-dt * (da + db));
     return g;
-}
-
-__device__ inline TaskDesc load_task(const TaskDesc* s_tk, const RoundDesc& R, int tid) {
-    if (tid < R.w) return s_tk[R.task0 + tid];
-    return TaskDesc{0, -1, 0, 0};
 }
 
 constexpr int CH = 8;
@@ -158,7 +147,7 @@ __global__ void __launch_bounds__(T) adjoint_kernel(AdjArgs a) {
                     tn = load_task(s_tk, Rn, tid);
                 }
                 if (t.len > 0) {
-                    const int base = R.slot0 + tid;
+                    const int base = R.slot0 + (tid - R.t0);
                     const int w = R.w;
                     double csum = 0.0;
                     for (int c = 0; c < t.nch; ++c) {
@@ -201,7 +190,7 @@ __global__ void __launch_bounds__(T) adjoint_kernel(AdjArgs a) {
                     tn = load_task(s_tk, Rn, tid);
                 }
                 if (t.len > 0) {
-                    const int base = R.slot0 + tid;
+                    const int base = R.slot0 + (tid - R.t0);
                     const int w = R.w;
                     double x = (t.par >= 0) ? sW[t.par] : 0.0;
                     for (int k0 = 0; k0 < t.len; k0 += CH) {

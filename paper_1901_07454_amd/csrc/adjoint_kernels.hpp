@@ -44,7 +44,7 @@ struct AdjArgs {
 // sum w per slot; lambda_m/h/n and two gradient sums per hh instance; then
 // rounds, tasks, nonlinear entries, child slots.
 inline int64_t adjoint_lds_bytes(const PackDesc& D) {
-    return 8 * (4 * int64_t(D.nslot) + 5 * int64_t(D.nhh)) + 16 * int64_t(D.nrd) + 16 * int64_t(D.ntk) +
+    return 8 * (4 * int64_t(D.nslot) + 5 * int64_t(D.nhh)) + 24 * int64_t(D.nrd) + 16 * int64_t(D.ntk) +
            16 * int64_t(D.nnl) + 4 * int64_t(D.nch);
 }
 

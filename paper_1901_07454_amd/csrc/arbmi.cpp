@@ -135,16 +135,112 @@ StepArgs Sim::step_args() const {
     return a;
 }
 
+// One epoch's kernels after the step arguments are set: the step kernel,
+// then (network) the exchange of the epoch's spikes; in graph mode also the
+// bucket sort before it and the device epoch counter's advance after it.
+int Sim::launch_epoch_sequence(const StepArgs& a, bool net, bool graph_mode) {
+    const int np = int32_t(L.packs.size());
+    if (graph_mode && net)
+        HIP_TRY(launch_sort_buckets(d_bk_ev, d_bk_cnt, d_pk_ncur, bk_cap, 0, np, d_ctr, st, d_epoch, n_buckets));
+    HIP_TRY(launch_step(a, cfg, np, st));
+    if (net && a.epoch_end) {
+        ExchArgs x{};
+        x.sp_gid = d_sp_gid;
+        x.sp_step = d_sp_step;
+        x.out_off = d_out_off;
+        x.out_rank = d_out_rank;
+        x.cr_pack = d_cr_pack;
+        x.cr_delay = d_cr_delay;
+        x.bk_ev = d_bk_ev;
+        x.bk_cnt = d_bk_cnt;
+        x.bk_cap = bk_cap;
+        x.n_buckets = n_buckets;
+        x.n_packs = np;
+        x.epoch_steps = K;
+        x.sp_cap = sp_cap;
+        x.ctr = d_ctr;
+        HIP_TRY(launch_exchange(x, exch_grid, st));
+    }
+    if (graph_mode) HIP_TRY(launch_advance_epoch(d_epoch, st));
+    return ARB_OK;
+}
+
+// Capture one full epoch, with its step and bucket read from d_epoch.
+int Sim::capture_epoch_graph() {
+    if (graph) {
+        (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+    }
+    const bool net = !L.out_rank.empty();
+    StepArgs a = step_args();
+    a.epoch_ptr = d_epoch;
+    a.n_buckets = n_buckets;
+    a.nsteps = K;
+    a.epoch_end = 1;
+    hipGraph_t g = nullptr;
+    if (!st_capture) HIP_TRY(hipStreamCreateWithFlags(&st_capture, hipStreamNonBlocking));
+    hipStream_t keep = st;
+    st = st_capture;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int rc = launch_epoch_sequence(a, net, true);
+    hipGraph_t captured = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &captured);
+    st = keep;
+    if (rc != ARB_OK) return rc;
+    HIP_TRY(e);
+    g = captured;
+    hipError_t ie = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(ie);
+    graph_dirty = false;
+    return ARB_OK;
+}
+
 // Enqueue steps [step, step + n): epochs of K steps aligned at multiples of
 // K; network events are sorted at each epoch start and spikes exchanged at
 // each epoch end.  `rec` (optional) records the pre-step state of every step
-// for the adjoint; then the steps must lie in one launch.
+// for the adjoint.  With ARB_FLAG_GRAPH, whole epochs replay a captured graph.
 int Sim::advance(int64_t n, const RecordArgs* rec) {
     const bool net = !L.out_rank.empty();
     const int np = int32_t(L.packs.size());
     int64_t done = 0;
     while (n > 0) {
         const int64_t e = step / K, pos = step % K;
+        if ((p.flags & ARB_FLAG_GRAPH) && !rec && pos == 0 && n >= K) {
+            const int64_t ne = n / K;
+            if (graph_dirty || !graph) {
+                const int rc = capture_epoch_graph();
+                if (rc != ARB_OK) return rc;
+            }
+            HIP_TRY(hipMemcpyAsync(d_epoch, &e, sizeof e, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));  // e lives on this stack frame
+            for (int64_t q = 0; q < ne; ++q) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (p.flags & ARB_FLAG_TIME_KERNELS) {
+                    if (timer_free.size() < 2) {
+                        hipEvent_t x;
+                        HIP_TRY(hipEventCreate(&x));
+                        timer_free.push_back(x);
+                        HIP_TRY(hipEventCreate(&x));
+                        timer_free.push_back(x);
+                    }
+                    e0 = timer_free.back();
+                    timer_free.pop_back();
+                    e1 = timer_free.back();
+                    timer_free.pop_back();
+                    HIP_TRY(hipEventRecord(e0, st));
+                }
+                HIP_TRY(hipGraphLaunch(graph, st));
+                if (e0) {
+                    HIP_TRY(hipEventRecord(e1, st));
+                    timer_pending.push_back({e0, e1});
+                }
+            }
+            step += ne * K;
+            n -= ne * K;
+            done += ne * K;
+            continue;
+        }
         const int64_t nthis = std::min<int64_t>(n, K - pos);
         const int32_t bucket = int32_t(e % n_buckets);
         if (net && pos == 0)
@@ -154,6 +250,7 @@ int Sim::advance(int64_t n, const RecordArgs* rec) {
         a.step0 = step;
         a.nsteps = int32_t(nthis);
         a.epoch_end = (pos + nthis == K) ? 1 : 0;
+        a.n_buckets = n_buckets;
         if (rec) {  // rows offset by the steps already done in this call
             a.rec_V = rec->V + done * L.n_slots;
             a.rec_m = rec->m + done * int64_t(L.hh_cv.size());
@@ -319,6 +416,7 @@ int build_device(Sim* s) {
     s->d_sp_gid = dalloc<uint32_t>(s, s->sp_cap, rc);
     s->d_sp_step = dalloc<int64_t>(s, s->sp_cap, rc);
     s->d_sp_t = dalloc<double>(s, s->sp_cap, rc);
+    s->d_epoch = dalloc<int64_t>(s, 1, rc);
     s->d_ctr = dalloc<Counters>(s, 1, rc);
     if (rc == ARB_OK) rc = s->fill_zero(s->d_ctr, sizeof(Counters));
     if (rc != ARB_OK) return rc;
@@ -326,6 +424,104 @@ int build_device(Sim* s) {
 }
 
 }  // namespace
+
+namespace arbmi {
+
+int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, Sim** out, std::string& err) {
+    const arb_params* p = &pp;
+    *out = nullptr;
+    Sim* s = new Sim();
+    s->p = *p;
+    s->st = static_cast<hipStream_t>(p->hip_stream);
+    s->device = d.dev;
+    s->n_cu = d.n_cu;
+    s->lds_max = d.lds_max;
+    const Plan plan = choose_plan(m.cells, m.n_cells, m.br, m.n_br, *p, d.lds_max, d.n_cu);
+    LowerOptions opt;
+    opt.block_threads = plan.block_threads;
+    opt.coef_mode = plan.coef_mode;
+    opt.lds_budget = plan.lds_budget;
+    opt.lds_hard_max = plan.lds_hard_max;
+    opt.max_cells_per_pack = plan.max_cells_per_pack;
+    opt.reg_slots = plan.coef_mode == 3 ? plan.reg_slots : 0;
+    opt.reg_len = plan.reg_len;
+    int rc = lower_model(m.cells, m.n_cells, m.br, m.n_br, m.syn, m.n_syn, m.conn, m.n_conn, m.ev, m.n_ev, m.ic,
+                         m.n_ic, *p, opt, s->L, err);
+    const bool auto_mode = p->coef_mode == 0 || (p->flags & ARB_FLAG_AUTOTUNE);
+    if (rc == ARB_EINVAL && auto_mode && opt.coef_mode != 2 &&
+        (err.find("LDS") != std::string::npos || err.find("register") != std::string::npos)) {
+        // a cell too large for LDS- or register-resident coefficients: stream them
+        opt.coef_mode = 2;
+        opt.reg_slots = 0;
+        opt.block_threads = p->block_threads ? p->block_threads : 256;
+        opt.max_cells_per_pack = std::max<int64_t>(1, plan.fallback_cells_per_pack);
+        opt.lds_budget = plan.fallback_lds_budget;
+        opt.lds_hard_max = d.lds_max - 256;
+        s->L = Lowered();
+        rc = lower_model(m.cells, m.n_cells, m.br, m.n_br, m.syn, m.n_syn, m.conn, m.n_conn, m.ev, m.n_ev, m.ic,
+                         m.n_ic, *p, opt, s->L, err);
+    }
+    if (rc != ARB_OK) {
+        delete s;
+        return rc;
+    }
+    if (!d.have_dev) {
+        delete s;
+        err = "no HIP device available";
+        return ARB_EHIP;
+    }
+    const bool net = !s->L.out_rank.empty();
+    s->K = p->epoch_steps > 0 ? p->epoch_steps : (net ? s->L.min_delay : 1000);
+    s->cfg.block_threads = s->L.block_threads;
+    s->cfg.coef_mode = s->L.coef_mode;
+    s->cfg.reg_slots = s->L.reg_slots;
+    s->cfg.reg_len = s->L.reg_len;
+    int64_t lds = 0;
+    for (const PackDesc& D : s->L.packs) lds = std::max(lds, pack_lds_bytes(D, s->L.coef_mode));
+    if (lds > d.lds_max - 256) {
+        delete s;
+        err = "a pack needs more LDS than the device has";
+        return ARB_EINVAL;
+    }
+    s->cfg.lds_bytes = int(std::max<int64_t>(lds, 8));
+    s->exch_grid = std::max(1, std::min(4 * d.n_cu, int((m.n_cells + 3) / 4)));
+    hipError_t he = prepare_step_kernels(int(d.lds_max));
+    if (he != hipSuccess) {
+        delete s;
+        err = std::string("prepare_step_kernels: ") + hipGetErrorString(he);
+        return ARB_EHIP;
+    }
+    rc = build_device(s);
+    if (rc == ARB_OK) {
+        hipError_t e = hipStreamSynchronize(s->st);
+        if (e != hipSuccess) rc = hip_fail(e, "upload");
+    }
+    if (rc != ARB_OK) {
+        err = g_err;
+        s->release_all();
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return ARB_OK;
+}
+
+void destroy_sim(Sim* s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->st);
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    if (s->st_capture) (void)hipStreamDestroy(s->st_capture);
+    for (hipEvent_t e : s->timer_free) (void)hipEventDestroy(e);
+    for (auto& pr : s->timer_pending) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    grad_release(s);
+    s->release_all();
+    delete s;
+}
+
+}  // namespace arbmi
 
 extern "C" {
 
@@ -339,81 +535,30 @@ int arb_build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     if (!p) return fail(ARB_EINVAL, "params is NULL");
     if (p->block_threads != 0 && p->block_threads != 64 && p->block_threads != 128 && p->block_threads != 256)
         return fail(ARB_EINVAL, "block_threads must be 0, 64, 128 or 256");
-    if (p->coef_mode < 0 || p->coef_mode > 2) return fail(ARB_EINVAL, "coef_mode must be 0, 1 or 2");
+    if (p->coef_mode < 0 || p->coef_mode > 3) return fail(ARB_EINVAL, "coef_mode must be 0, 1, 2 or 3");
     if (p->cells_per_pack < 0) return fail(ARB_EINVAL, "cells_per_pack must be >= 0");
     if ((p->alloc == nullptr) != (p->free == nullptr)) return fail(ARB_EINVAL, "alloc and free must be given together");
 
-    // device limits (validation below runs even without a device)
+    // device limits (validation runs even without a device)
+    DeviceLimits d;
     int ndev = 0;
-    const bool have_dev = hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0;
-    int dev = 0;
-    int64_t lds_max = 160 * 1024;
-    int n_cu = 256;
-    if (have_dev) {
-        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    d.have_dev = hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0;
+    if (d.have_dev) {
+        if (hipGetDevice(&d.dev) != hipSuccess) d.dev = 0;
         int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0) lds_max = v;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) n_cu = v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, d.dev) == hipSuccess && v > 0)
+            d.lds_max = v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d.dev) == hipSuccess && v > 0) d.n_cu = v;
     }
-
-    Sim* s = new Sim();
-    s->p = *p;
-    s->st = static_cast<hipStream_t>(p->hip_stream);
-    s->device = dev;
-    s->n_cu = n_cu;
-    s->lds_max = lds_max;
-    const Plan plan = choose_plan(cells, n_cells, branches, n_branches, *p, lds_max, n_cu);
-    LowerOptions opt;
-    opt.block_threads = plan.block_threads;
-    opt.coef_mode = plan.coef_mode;
-    opt.lds_budget = plan.lds_budget;
-    opt.lds_hard_max = plan.lds_hard_max;
-    opt.max_cells_per_pack = plan.max_cells_per_pack;
+    const ModelView m{cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim};
+    arb_params q = *p;
+    if ((p->flags & ARB_FLAG_AUTOTUNE) && d.have_dev && p->block_threads == 0 && p->coef_mode == 0 &&
+        p->cells_per_pack == 0)
+        q = autotune(m, *p, d);
+    Sim* s = nullptr;
     std::string err;
-    int rc = lower_model(cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim, *p,
-                         opt, s->L, err);
-    if (rc == ARB_EINVAL && p->coef_mode == 0 && opt.coef_mode == 1 && err.find("LDS") != std::string::npos) {
-        // a cell too large for LDS-resident coefficients: stream them instead
-        opt.coef_mode = 2;
-        s->L = Lowered();
-        rc = lower_model(cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim, *p,
-                         opt, s->L, err);
-    }
-    if (rc != ARB_OK) {
-        delete s;
-        return fail(rc, err);
-    }
-    if (!have_dev) {
-        delete s;
-        return fail(ARB_EHIP, "no HIP device available");
-    }
-    const bool net = !s->L.out_rank.empty();
-    s->K = p->epoch_steps > 0 ? p->epoch_steps : (net ? s->L.min_delay : 1000);
-    s->cfg.block_threads = s->L.block_threads;
-    s->cfg.coef_mode = s->L.coef_mode;
-    int64_t lds = 0;
-    for (const PackDesc& D : s->L.packs) lds = std::max(lds, pack_lds_bytes(D, s->L.coef_mode));
-    if (lds > lds_max - 256) {
-        delete s;
-        return fail(ARB_EINVAL, "a pack needs more LDS than the device has");
-    }
-    s->cfg.lds_bytes = int(std::max<int64_t>(lds, 8));
-    s->exch_grid = std::max(1, std::min(4 * n_cu, int((n_cells + 3) / 4)));
-    hipError_t he = prepare_step_kernels(int(lds_max));
-    if (he != hipSuccess) {
-        delete s;
-        return hip_fail(he, "prepare_step_kernels");
-    }
-    rc = build_device(s);
-    if (rc == ARB_OK) {
-        hipError_t e = hipStreamSynchronize(s->st);
-        if (e != hipSuccess) rc = hip_fail(e, "upload");
-    }
-    if (rc != ARB_OK) {
-        s->release_all();
-        delete s;
-        return rc;
-    }
+    const int rc = build_sim(m, q, d, &s, err);
+    if (rc != ARB_OK) return fail(rc, err);
     *out = s;
     return ARB_OK;
 }
@@ -533,6 +678,7 @@ int arb_set_probes(arb_sim s_, const int64_t* cv, int32_t n, int64_t max_steps) 
     s->n_probe = n;
     s->trace_cap = (n > 0) ? max_steps : 0;
     s->trace_step0 = s->step;
+    s->graph_dirty = true;
     HIP_TRY(hipStreamSynchronize(s->st));
     return ARB_OK;
 }
@@ -553,6 +699,7 @@ int arb_get_trace(arb_sim s_, double* dst, int64_t cap, int dst_on_device, int64
     HIP_TRY(hipStreamSynchronize(s->st));
     *n_steps_out = rec;
     s->trace_step0 = s->step;
+    s->graph_dirty = true;
     return ARB_OK;
 }
 
@@ -649,6 +796,7 @@ int arb_set_state(arb_sim s_, const void* blob, int64_t n) {
     s->step = h.step;
     s->sp_user = uint32_t(h.sp_user);
     s->trace_step0 = s->step;
+    s->graph_dirty = true;
     s->grad_valid = false;
     return ARB_OK;
 }
@@ -711,17 +859,7 @@ int arb_sync(arb_sim s_) {
 }
 
 int arb_free(arb_sim s_) {
-    Sim* s = static_cast<Sim*>(s_);
-    if (!s) return ARB_OK;
-    (void)hipStreamSynchronize(s->st);
-    for (hipEvent_t e : s->timer_free) (void)hipEventDestroy(e);
-    for (auto& pr : s->timer_pending) {
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
-    }
-    grad_release(s);
-    s->release_all();
-    delete s;
+    destroy_sim(static_cast<Sim*>(s_));
     return ARB_OK;
 }
 

@@ -17,44 +17,16 @@
 // factorisation (F, 1/d') is computed once on the host.
 #include <hip/hip_runtime.h>
 
+#include "kernel_common.hpp"
 #include "kernels.hpp"
 
 namespace arbmi {
 
 namespace {
 
-// x / (exp(x) - 1) with its removable singularity at 0
-__device__ inline double exprelr(double x) { return (1.0 + x == 1.0) ? 1.0 : x / expm1(x); }
-
-// textbook Hodgkin-Huxley rates (1/ms) at 6.3 C, V in mV
-struct Rates {
-    double am, bm, ah, bh, an, bn;
-};
-__device__ inline Rates hh_rates(double v) {
-    Rates r;
-    r.am = exprelr(-(v + 40.0) * 0.1);
-    r.bm = 4.0 * exp(-(v + 65.0) * (1.0 / 18.0));
-    r.ah = 0.07 * exp(-(v + 65.0) * 0.05);
-    r.bh = 1.0 / (exp(-(v + 35.0) * 0.1) + 1.0);
-    r.an = 0.1 * exprelr(-(v + 55.0) * 0.1);
-    r.bn = 0.125 * exp(-(v + 65.0) * (1.0 / 80.0));
-    return r;
-}
-
-// exact update of a gate obeying x' = a(1-x) - b x at fixed V over dt
-__device__ inline double gate_step(double x, double a, double b, double dt) {
-    const double s = a + b;
-    const double xinf = a / s;
-    return xinf + (x - xinf) * exp(-dt * s);
-}
+using namespace dev;
 
 constexpr int CH = 8;  // CVs of a branch staged in registers at a time
-
-// this thread's task in round R, or an empty task (len 0) if it has none
-__device__ inline TaskDesc load_task(const TaskDesc* s_tk, const RoundDesc& R, int tid) {
-    if (tid < R.w) return s_tk[R.task0 + tid];
-    return TaskDesc{0, -1, 0, 0};
-}
 
 template <int T, bool CL>
 __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
@@ -134,7 +106,14 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
     for (int i = tid; i < pk.nch; i += T) s_ch[i] = a.ch_slot[pk.ch0 + i];
 
     // event cursors live in thread 0's registers, with the next key cached
-    const int64_t bk_base = (int64_t(a.bucket) * a.n_packs + p);
+    int64_t step0 = a.step0;
+    int32_t bucket = a.bucket;
+    if (a.epoch_ptr) {
+        const int64_t e = *a.epoch_ptr;
+        step0 = e * a.nsteps;
+        bucket = int32_t(e % a.n_buckets);
+    }
+    const int64_t bk_base = (int64_t(bucket) * a.n_packs + p);
     const uint64_t* ev = a.bk_ev + bk_base * a.bk_cap;
     int32_t ncur = 0, nend = 0;
     int64_t xcur = 0;
@@ -153,7 +132,7 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
     __syncthreads();
 
     for (int s = 0; s < a.nsteps; ++s) {
-        const int64_t n = a.step0 + s;
+        const int64_t n = step0 + s;
 
         // A: events due at the start of step n (network, then external)
         if (tid == 0) {
@@ -229,7 +208,7 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
                     tn = load_task(s_tk, Rn, tid);
                 }
                 if (t.len > 0) {
-                    const int base = R.slot0 + tid;
+                    const int base = R.slot0 + (tid - R.t0);
                     const int w = R.w;
                     double csum = 0.0;
                     for (int c = 0; c < t.nch; ++c) {
@@ -274,7 +253,7 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
                     tn = load_task(s_tk, Rn, tid);
                 }
                 if (t.len > 0) {
-                    const int base = R.slot0 + tid;
+                    const int base = R.slot0 + (tid - R.t0);
                     const int w = R.w;
                     double x = (t.par >= 0) ? sV[t.par] : 0.0;
                     for (int k0 = 0; k0 < t.len; k0 += CH) {
@@ -361,10 +340,12 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
 
 __global__ void __launch_bounds__(256) sort_buckets_kernel(uint64_t* bk_ev, uint32_t* bk_cnt, int32_t* pk_ncur,
                                                            int32_t cap, int32_t bucket, int32_t n_packs,
-                                                           Counters* ctr) {
+                                                           Counters* ctr, const int64_t* epoch_ptr,
+                                                           int32_t n_buckets) {
     extern __shared__ uint64_t keys[];
     const int p = blockIdx.x;
     const int tid = threadIdx.x;
+    if (epoch_ptr) bucket = int32_t(*epoch_ptr % n_buckets);
     const int64_t base_i = int64_t(bucket) * n_packs + p;
     uint32_t n = bk_cnt[base_i];
     if (tid == 0) pk_ncur[p] = 0;
@@ -423,6 +404,8 @@ __global__ void __launch_bounds__(256) exchange_kernel(ExchArgs a) {
     }
 }
 
+__global__ void advance_epoch_kernel(int64_t* epoch) { *epoch += 1; }
+
 __global__ void commit_exchange_kernel(Counters* ctr, uint32_t sp_cap) {
     const uint32_t e = ctr->sp_count;
     ctr->sp_exch = e > sp_cap ? sp_cap : e;
@@ -468,10 +451,11 @@ hipError_t prepare_step_kernels(int max_lds) {
                          reinterpret_cast<const void*>(&step_kernel<256, false>),
                          reinterpret_cast<const void*>(&sort_buckets_kernel)};
     for (const void* f : fns) allow_lds(f, max_lds);
-    return hipSuccess;
+    return prepare_reg_kernels(max_lds);
 }
 
 hipError_t launch_step(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st) {
+    if (cfg.coef_mode == 3) return launch_reg_step(a, cfg, n_packs, st);
     const bool cl = cfg.coef_mode == 1;
     switch (cfg.block_threads) {
         case 64: return cl ? launch_one<64, true>(a, cfg.lds_bytes, n_packs, st) : launch_one<64, false>(a, cfg.lds_bytes, n_packs, st);
@@ -482,11 +466,17 @@ hipError_t launch_step(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hip
 }
 
 hipError_t launch_sort_buckets(uint64_t* bk_ev, uint32_t* bk_cnt, int32_t* pk_ncur, int32_t bk_cap,
-                               int32_t bucket, int32_t n_packs, Counters* ctr, hipStream_t st) {
+                               int32_t bucket, int32_t n_packs, Counters* ctr, hipStream_t st,
+                               const int64_t* epoch_ptr, int32_t n_buckets) {
     int m = 1;
     while (m < bk_cap) m <<= 1;
     hipLaunchKernelGGL(sort_buckets_kernel, dim3(n_packs), dim3(256), size_t(m) * 8, st, bk_ev, bk_cnt, pk_ncur,
-                       bk_cap, bucket, n_packs, ctr);
+                       bk_cap, bucket, n_packs, ctr, epoch_ptr, n_buckets);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_epoch(int64_t* epoch, hipStream_t st) {
+    hipLaunchKernelGGL(advance_epoch_kernel, dim3(1), dim3(1), 0, st, epoch);
     return hipGetLastError();
 }
 

@@ -77,22 +77,34 @@ struct StepArgs {
     int64_t step0;             // first step of this launch
     int32_t nsteps;            // steps in this launch
     int32_t epoch_end;         // 1 if the launch completes an epoch (reset the bucket)
+    // graph replay: when set, the launch is the full epoch *epoch_ptr
+    // (step0 = epoch * nsteps, bucket = epoch % n_buckets)
+    const int64_t* epoch_ptr;
+    int32_t n_buckets;
+    int32_t pad2;
 };
 
 // Per-launch configuration chosen by the host.
 struct LaunchCfg {
     int block_threads;  // 64, 128, 256
-    int coef_mode;      // 1 LDS, 2 streamed
+    int coef_mode;      // 1 LDS, 2 streamed, 3 register-resident
     int lds_bytes;      // dynamic LDS per workgroup
+    int reg_slots;      // mode 3: branches per thread
+    int reg_len;        // mode 3: CVs per branch held in registers (8 or 16)
 };
 
 hipError_t launch_step(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st);
 hipError_t prepare_step_kernels(int max_lds_bytes);
+hipError_t launch_reg_step(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st);
+hipError_t prepare_reg_kernels(int max_lds_bytes);
 
 // Sort each pack's run of network events of `bucket` (keys ascending) and
 // reset the packs' cursors.  Flags an overflow if a run exceeded bk_cap.
 hipError_t launch_sort_buckets(uint64_t* bk_ev, uint32_t* bk_cnt, int32_t* pk_ncur, int32_t bk_cap,
-                               int32_t bucket, int32_t n_packs, Counters* ctr, hipStream_t st);
+                               int32_t bucket, int32_t n_packs, Counters* ctr, hipStream_t st,
+                               const int64_t* epoch_ptr = nullptr, int32_t n_buckets = 1);
+// ++*epoch (end of a replayed epoch)
+hipError_t launch_advance_epoch(int64_t* epoch, hipStream_t st);
 
 // Turn the spikes [ctr.sp_exch, ctr.sp_count) into network events.
 struct ExchArgs {

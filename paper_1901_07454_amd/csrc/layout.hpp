@@ -49,18 +49,21 @@ struct PackDesc {
 // kernel: doubles V, R, [alpha, beta, F, 1/d'], g, m, h, n, [gNa, gK, e_syn,
 // decay]; then rounds, tasks, nonlinear entries, child slots.  Bracketed
 // parts are staged only in coefficient mode 1 (mode 2 streams them).
+// Mode 3 (register-resident coefficients) uses the mode-2 layout.
 inline int64_t pack_lds_bytes(const PackDesc& D, int coef_mode) {
     const bool cl = coef_mode == 1;
     const int64_t dbl = (cl ? 6 : 2) * int64_t(D.nslot) + int64_t(D.nsyn) + 3 * int64_t(D.nhh) +
                         (cl ? 2 * (int64_t(D.nhh) + int64_t(D.nsyn)) : 0);
-    return 8 * dbl + 16 * int64_t(D.nrd) + 16 * int64_t(D.ntk) + 16 * int64_t(D.nnl) + 4 * int64_t(D.nch);
+    return 8 * dbl + 24 * int64_t(D.nrd) + 16 * int64_t(D.ntk) + 16 * int64_t(D.nnl) + 4 * int64_t(D.nch);
 }
 
 struct RoundDesc {
-    int32_t slot0;  // pack-local slot of (k = 0, t = 0)
+    int32_t slot0;  // pack-local slot of (k = 0, first thread)
     int32_t w;      // branches in the round
     int32_t len;    // longest branch
     int32_t task0;  // first task (one per branch)
+    int32_t t0;     // threads t0 .. t0 + w - 1 take the round's branches in order
+    int32_t j;      // register slot the round's threads use (register-resident kernel)
 };
 
 struct TaskDesc {

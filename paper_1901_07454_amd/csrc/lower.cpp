@@ -258,26 +258,62 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
     // -------------------------------------------------------------- packing
     const int T = opt.block_threads;
     L.block_threads = T;
-    // slot and round counts of a set of cells under the round layout
-    struct Shape { int64_t nslot = 0, nrd = 0; };
-    auto plan_shape = [&](const std::vector<int32_t>& cs) -> Shape {
+    // Rounds of a set of cells: the branches of one depth level (deepest
+    // first; the soma is level 0) split into rounds of at most T.  In the
+    // register-resident layout (S > 0) every thread has S register slots and
+    // each round takes one slot index j on a contiguous run of threads that
+    // have not used slot j yet; it fails when the slots run out or a branch
+    // is longer than the registers hold.
+    struct Item { int32_t c, b; int len; };
+    struct RoundPlan { std::vector<Item> items; int t0 = 0, j = 0, len = 0; };
+    const int S = opt.reg_slots;
+    auto build_rounds = [&](const std::vector<int32_t>& cs, std::vector<RoundPlan>& out) -> bool {
+        out.clear();
         int maxd = 0;
         for (int32_t c : cs) for (int d : geo[c].depth) maxd = std::max(maxd, d);
-        Shape sh;
+        std::vector<int> next_free(std::max(S, 1), 0);
         for (int d = maxd; d >= 0; --d) {
-            std::vector<int> lens;
+            std::vector<Item> items;
             for (int32_t c : cs) {
-                if (d == 0) { lens.push_back(1); continue; }
+                if (d == 0) { items.push_back({c, -1, 1}); continue; }
                 for (int32_t b = 0; b < cells[c].n_branch; ++b)
-                    if (geo[c].depth[b] == d) lens.push_back(br[cells[c].branch_begin + b].n_cv);
+                    if (geo[c].depth[b] == d) items.push_back({c, b, br[cells[c].branch_begin + b].n_cv});
             }
-            for (size_t s = 0; s < lens.size(); s += T) {
-                size_t e = std::min(lens.size(), s + T);
-                int mx = *std::max_element(lens.begin() + s, lens.begin() + e);
-                sh.nslot += int64_t(mx) * int64_t(e - s);
-                sh.nrd++;
+            size_t s0 = 0;
+            while (s0 < items.size()) {
+                int jb = 0;
+                size_t room = size_t(T);
+                if (S > 0) {
+                    jb = -1;
+                    int best = 0;
+                    for (int j = 0; j < S; ++j)
+                        if (T - next_free[j] > best) { best = T - next_free[j]; jb = j; }
+                    if (jb < 0) return false;
+                    room = size_t(best);
+                }
+                const size_t m = std::min(items.size() - s0, room);
+                RoundPlan rp;
+                rp.items.assign(items.begin() + s0, items.begin() + s0 + m);
+                rp.t0 = (S > 0) ? next_free[jb] : 0;
+                rp.j = jb;
+                for (const Item& it : rp.items) rp.len = std::max(rp.len, it.len);
+                if (S > 0) {
+                    if (rp.len > opt.reg_len) return false;
+                    next_free[jb] += int(m);
+                }
+                out.push_back(std::move(rp));
+                s0 += m;
             }
         }
+        return true;
+    };
+    struct Shape { int64_t nslot = 0, nrd = 0; bool ok = true; };
+    auto plan_shape = [&](const std::vector<int32_t>& cs) -> Shape {
+        std::vector<RoundPlan> rps;
+        Shape sh;
+        sh.ok = build_rounds(cs, rps);
+        for (const RoundPlan& rp : rps) sh.nslot += int64_t(rp.len) * int64_t(rp.items.size());
+        sh.nrd = int64_t(rps.size());
         return sh;
     };
     auto plan_slots = [&](const std::vector<int32_t>& cs) -> int64_t { return plan_shape(cs).nslot; };
@@ -288,6 +324,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i) nnl_cell[c] += (has_hh[i] || nsyn_cv[i]) ? 1 : 0;
     auto exact_lds = [&](const PackPlan& pp, int mode) -> int64_t {
         const Shape sh = plan_shape(pp.cells);
+        if (!sh.ok) return int64_t(1) << 40;  // does not fit the register slots
         PackDesc D{};
         D.nslot = int32_t(sh.nslot);
         D.nrd = int32_t(sh.nrd);
@@ -332,12 +369,19 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         if (!cur.cells.empty()) plans.push_back(cur);
     }
     for (const PackPlan& pp : plans)
+        if (S > 0 && !plan_shape(pp.cells).ok) {
+            err = "a cell does not fit the register-resident layout";
+            return ARB_EINVAL;
+        }
+    for (const PackPlan& pp : plans)
         if (exact_lds(pp, coef_mode) > opt.lds_hard_max) {
             err = fmt("a cell needs %lld bytes of LDS, more than the %lld available",
                       (long long)exact_lds(pp, coef_mode), (long long)opt.lds_hard_max);
             return ARB_EINVAL;
         }
     L.coef_mode = coef_mode;
+    L.reg_slots = opt.reg_slots;
+    L.reg_len = opt.reg_slots > 0 ? opt.reg_len : 0;
 
     // ------------------------------------------------- slot layout per pack
     const int64_t n_packs = int64_t(plans.size());
@@ -359,38 +403,26 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             for (int d : geo[c].depth) maxd = std::max(maxd, d);
         }
         // rounds, deepest first; a task is (cell, branch) with branch -1 = soma
-        struct Item { int32_t c, b; int len; };
-        std::vector<std::vector<Item>> rounds_items;
+        std::vector<RoundPlan> rps;
+        if (!build_rounds(pp.cells, rps)) { err = "a cell does not fit the register-resident layout"; return ARB_EINVAL; }
         int64_t ns = 0;
         std::vector<RoundDesc> rds;
-        for (int d = maxd; d >= 0; --d) {
-            std::vector<Item> items;
-            for (int32_t c : pp.cells) {
-                if (d == 0) { items.push_back({c, -1, 1}); continue; }
-                for (int32_t b = 0; b < cells[c].n_branch; ++b)
-                    if (geo[c].depth[b] == d) items.push_back({c, b, br[cells[c].branch_begin + b].n_cv});
-            }
-            for (size_t s = 0; s < items.size(); s += T) {
-                size_t e = std::min(items.size(), s + size_t(T));
-                std::vector<Item> ri(items.begin() + s, items.begin() + e);
-                int mx = 0;
-                for (auto& it : ri) mx = std::max(mx, it.len);
-                RoundDesc R{int32_t(ns), int32_t(ri.size()), mx, 0};
-                // slots of every CV of the round
-                for (size_t t = 0; t < ri.size(); ++t) {
-                    const Item& it = ri[t];
-                    const int64_t cv0 = L.cell_cv0[it.c];
-                    if (it.b < 0) {
-                        slot_of_user[cv0] = slot_base + ns + int64_t(t);
-                    } else {
-                        for (int k = 0; k < it.len; ++k)
-                            slot_of_user[cv0 + geo[it.c].first[it.b] + k] = slot_base + ns + int64_t(k) * int64_t(ri.size()) + int64_t(t);
-                    }
+        for (const RoundPlan& rp : rps) {
+            const std::vector<Item>& ri = rp.items;
+            RoundDesc R{int32_t(ns), int32_t(ri.size()), rp.len, 0, rp.t0, rp.j};
+            // slots of every CV of the round
+            for (size_t t = 0; t < ri.size(); ++t) {
+                const Item& it = ri[t];
+                const int64_t cv0 = L.cell_cv0[it.c];
+                if (it.b < 0) {
+                    slot_of_user[cv0] = slot_base + ns + int64_t(t);
+                } else {
+                    for (int k = 0; k < it.len; ++k)
+                        slot_of_user[cv0 + geo[it.c].first[it.b] + k] = slot_base + ns + int64_t(k) * int64_t(ri.size()) + int64_t(t);
                 }
-                ns += int64_t(mx) * int64_t(ri.size());
-                rds.push_back(R);
-                rounds_items.push_back(std::move(ri));
             }
+            ns += int64_t(rp.len) * int64_t(ri.size());
+            rds.push_back(R);
         }
         D.nslot = int32_t(ns);
         D.nrd = int32_t(rds.size());
@@ -399,7 +431,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         // tasks (need every slot assigned first, for parents and children)
         for (size_t r = 0; r < rds.size(); ++r) {
             rds[r].task0 = int32_t(L.tasks.size()) - D.tk0;  // pack-local task
-            for (const Item& it : rounds_items[r]) {
+            for (const Item& it : rps[r].items) {
                 const int64_t cv0 = L.cell_cv0[it.c];
                 TaskDesc T_{};
                 T_.len = it.len;

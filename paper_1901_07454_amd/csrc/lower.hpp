@@ -23,6 +23,7 @@ struct Lowered {
     int64_t n_cv = 0, n_slots = 0;
     int32_t block_threads = 64;
     int32_t coef_mode = 1;
+    int32_t reg_slots = 0, reg_len = 0;
     double dt = 0.025, threshold = -10.0, v_init = -65.0;
 
     std::vector<PackDesc> packs;
@@ -79,6 +80,8 @@ struct LowerOptions {
     int64_t lds_budget = 160 * 1024;  // target bytes per workgroup when packing several cells
     int64_t lds_hard_max = 160 * 1024; // a single cell may use up to this
     int64_t max_cells_per_pack = int64_t(1) << 30;
+    int32_t reg_slots = 0;            // register-resident layout: branches per thread (0 = LDS layout)
+    int32_t reg_len = 8;              // and the longest branch it takes
 };
 
 // Validates and lowers.  Returns ARB_OK or ARB_EINVAL (message in err).

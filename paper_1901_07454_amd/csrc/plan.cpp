@@ -11,8 +11,8 @@ Plan choose_plan(const arb_cell* cells, int32_t n_cells, const arb_branch* br, i
     (void)n_cu;
     Plan pl;
     lds_max -= 256;  // static LDS of the kernels
-    // largest cell (CVs) and widest branch level over all cells
-    int64_t max_cv = 1, max_width = 1;
+    // largest cell (CVs), widest branch level, longest branch, most branches
+    int64_t max_cv = 1, max_width = 1, max_len = 1, max_tasks = 1;
     std::vector<int> depth, count;
     for (int32_t c = 0; c < n_cells && cells; ++c) {
         const arb_cell& C = cells[c];
@@ -23,23 +23,48 @@ Plan choose_plan(const arb_cell* cells, int32_t n_cells, const arb_branch* br, i
         for (int32_t b = 0; b < C.n_branch; ++b) {
             const arb_branch& B = br[C.branch_begin + b];
             n += std::max(0, B.n_cv);
+            max_len = std::max<int64_t>(max_len, B.n_cv);
             depth[b] = (B.parent < 0 || B.parent >= b) ? 1 : depth[B.parent] + 1;
             if (depth[b] <= C.n_branch) count[depth[b]]++;
         }
         for (int v : count) max_width = std::max<int64_t>(max_width, v);
         max_cv = std::max(max_cv, n);
+        max_tasks = std::max<int64_t>(max_tasks, int64_t(C.n_branch) + 1);
     }
-    // Streamed coefficients (mode 2) keep 16 B of LDS per CV and allow several
-    // workgroups per CU; measured faster than LDS-resident coefficients on
-    // the 1017-CV ring cells.  256 threads, with enough cells per pack that
-    // the widest branch level fills the workgroup.
-    pl.block_threads = p.block_threads ? p.block_threads : 256;
+    const bool grads = (p.flags & ARB_FLAG_GRADIENTS) != 0;
+
+    // Streamed coefficients (mode 2): 16 B of LDS per CV, 256 threads, enough
+    // cells per pack that the widest branch level fills the workgroup.  Also
+    // the fallback of the other modes.
+    const int T2 = p.block_threads ? p.block_threads : 256;
+    pl.fallback_cells_per_pack = std::max<int64_t>(1, std::min<int64_t>(T2, T2 / max_width));
+    pl.fallback_lds_budget = lds_max / 2;
+
+    // Register-resident coefficients (mode 3) when every branch fits the
+    // registers: L = 8 CVs with up to 3 branches per thread, or L = 16 with 1.
+    const bool reg_ok = max_len <= 16 && !grads && (p.coef_mode == 0 || p.coef_mode == 3);
+    if (reg_ok) {
+        pl.coef_mode = 3;
+        pl.block_threads = p.block_threads ? p.block_threads : 256;
+        pl.reg_len = max_len <= 8 ? 8 : 16;
+        if (pl.reg_len == 8)
+            pl.reg_slots = (max_tasks <= 2 * pl.block_threads) ? 2 : 3;
+        else
+            pl.reg_slots = 1;
+        pl.lds_budget = lds_max / 2;
+        pl.lds_hard_max = lds_max;
+        pl.max_cells_per_pack = p.cells_per_pack > 0 ? std::min(p.cells_per_pack, pl.block_threads) : pl.block_threads;
+        if (p.cells_per_pack > 0) pl.lds_budget = lds_max;
+        return pl;
+    }
+
+    pl.block_threads = T2;
     const int64_t need_lds1 = (max_cv + max_cv / 4) * 6 * 8 + max_cv * 3 * 8;
-    pl.coef_mode = p.coef_mode ? p.coef_mode : 2;
+    pl.coef_mode = (p.coef_mode == 1 || p.coef_mode == 2) ? p.coef_mode : 2;
     if (pl.coef_mode == 1 && need_lds1 > lds_max && p.coef_mode == 0) pl.coef_mode = 2;
     pl.lds_budget = lds_max / 2;
     pl.lds_hard_max = lds_max;
-    if (p.flags & ARB_FLAG_GRADIENTS) {
+    if (grads) {
         // the adjoint kernel keeps 32 B per CV (forward, streamed: 16 B)
         pl.coef_mode = 2;
         pl.lds_budget = lds_max / 3;
@@ -49,7 +74,7 @@ Plan choose_plan(const arb_cell* cells, int32_t n_cells, const arb_branch* br, i
         pl.max_cells_per_pack = std::min(p.cells_per_pack, pl.block_threads);
         pl.lds_budget = lds_max;  // an explicit pack size wins over the LDS target
     } else {
-        pl.max_cells_per_pack = std::max<int64_t>(1, std::min<int64_t>(pl.block_threads, pl.block_threads / max_width));
+        pl.max_cells_per_pack = pl.fallback_cells_per_pack;
     }
     return pl;
 }

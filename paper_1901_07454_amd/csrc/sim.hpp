@@ -25,6 +25,9 @@ struct Plan {
     int64_t lds_budget = 160 * 1024;
     int64_t lds_hard_max = 160 * 1024;
     int64_t max_cells_per_pack = 64;
+    int reg_slots = 0, reg_len = 8;
+    int64_t fallback_cells_per_pack = 1;  // streamed mode, if the chosen layout fails
+    int64_t fallback_lds_budget = 0;
 };
 Plan choose_plan(const arb_cell* cells, int32_t n_cells, const arb_branch* br, int64_t n_br, const arb_params& p,
                  int64_t lds_max, int n_cu);
@@ -85,6 +88,12 @@ struct Sim : arb_sim_ {
     int32_t *d_pr_slot = nullptr, *d_pr_id = nullptr;
     double* d_trace = nullptr;
     int64_t n_probe = 0, trace_cap = 0, trace_step0 = 0;
+    // graph replay of whole epochs (ARB_FLAG_GRAPH)
+    int64_t* d_epoch = nullptr;
+    hipGraphExec_t graph = nullptr;
+    hipStream_t st_capture = nullptr;  // capture happens here; replays go on st
+    bool graph_dirty = true;
+    int capture_epoch_graph();
     // gradients
     GradState* grad = nullptr;
     bool grad_valid = false;
@@ -95,8 +104,38 @@ struct Sim : arb_sim_ {
     int fill_zero(void* dst, size_t bytes);
     StepArgs step_args() const;
     int advance(int64_t n, const RecordArgs* rec);
+    int launch_epoch_sequence(const StepArgs& a, bool net, bool graph_mode);
     int check_flags(bool& spikes_lost, bool& events_lost);
 };
+
+struct ModelView {
+    const arb_cell* cells;
+    int32_t n_cells;
+    const arb_branch* br;
+    int64_t n_br;
+    const arb_synapse* syn;
+    int64_t n_syn;
+    const arb_connection* conn;
+    int64_t n_conn;
+    const arb_event* ev;
+    int64_t n_ev;
+    const arb_iclamp* ic;
+    int32_t n_ic;
+};
+
+struct DeviceLimits {
+    bool have_dev = false;
+    int dev = 0;
+    int64_t lds_max = 160 * 1024;
+    int n_cu = 256;
+};
+
+// Lower and upload a model with the launch parameters in p (0 = planned).
+int build_sim(const ModelView& m, const arb_params& p, const DeviceLimits& d, Sim** out, std::string& err);
+void destroy_sim(Sim* s);
+// Time candidate launch shapes on a sample of the model's cells; returns p
+// with block_threads, coef_mode and cells_per_pack set to the fastest.
+arb_params autotune(const ModelView& m, const arb_params& p, const DeviceLimits& d);
 
 int set_error(int code, const std::string& msg);
 int set_hip_error(hipError_t e, const char* where);

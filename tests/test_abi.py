@@ -142,7 +142,7 @@ def test_rejects_epoch_longer_than_min_delay():
 
 def test_rejects_bad_launch_parameters():
     _expect_einval(_ring(), "block_threads", block_threads=96)
-    _expect_einval(_ring(), "coef_mode", coef_mode=3)
+    _expect_einval(_ring(), "coef_mode", coef_mode=4)
 
 
 @pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")

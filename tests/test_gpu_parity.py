@@ -73,6 +73,15 @@ def test_config3_small_uneven(coef_mode, block):
     check(m, 1500, block_threads=block, coef_mode=coef_mode)
 
 
+def test_autotuned_and_register_layouts_match_oracle():
+    from paper_1901_07454_amd import arbmi
+    m = gen.config3(n_cells=24, n_steps=1200)
+    check(m, 1200, flags=arbmi.ARB_FLAG_AUTOTUNE)
+    m = gen.config2(n_cells=10, kick_all=False, n_steps=1200)
+    for T in (64, 128, 256):
+        check(m, 1200, coef_mode=3, block_threads=T)
+
+
 def test_config4_cells_with_clamp():
     m = gen.config4(n_cells=4, n_steps=2000)
     _, sp = check(m, 2000)
@@ -109,6 +118,27 @@ def test_epoch_length_invariance_bitwise():
     for K in (1, 37, 100):
         got = gpu_run(m, 1400, probes, epoch_steps=K)
         assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1]) and ref[2] == got[2]
+
+
+def test_graph_replay_matches_direct_launches_bitwise():
+    from paper_1901_07454_amd import arbmi
+    m = gen.config2(n_cells=6, kick_all=False)
+    probes = np.arange(int(gen.n_cvs(m).sum()))
+    ref = gpu_run(m, 1400, probes)
+    got = gpu_run(m, 1400, probes, flags=arbmi.ARB_FLAG_GRAPH)
+    assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1]) and ref[2] == got[2]
+    # a run split into partial epochs around graph replays, with a trace read in between
+    sim = _sim(m, flags=arbmi.ARB_FLAG_GRAPH)
+    sim.set_probes(probes, 1400)
+    sim.step(130)
+    a = sim.trace(1400)
+    sim.step(870)
+    sim.step(400)
+    b = sim.trace(1400)
+    tr = np.concatenate([a, b], axis=1)
+    assert np.array_equal(tr, ref[0])
+    assert np.array_equal(sim.voltages_host(), ref[1])
+    sim.close()
 
 
 def test_determinism_bitwise():
