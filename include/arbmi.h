@@ -227,6 +227,19 @@ int arb_set_state(arb_sim s, const void *blob, int64_t n);
 /* Sizes and the chosen launch configuration. */
 int arb_get_info(arb_sim s, arb_info *info);
 
+/* Plan without a device: validate and lower the model exactly as
+ * arb_build_cells would with these parameters (launch parameters 0 are
+ * planned as if on an MI355X: 256 CUs, 160 KiB LDS), check the packed
+ * layout's invariants (every CV in one slot; children eliminated before their
+ * parents; each thread's register slot used by one branch), and report sizes
+ * in info (step = 0, device_bytes = 0).  No device memory is touched.
+ * ARB_EINVAL on a bad model or a violated invariant (message names it). */
+int arb_plan_layout(const arb_cell *cells, int32_t n_cells, const arb_branch *branches,
+                    int64_t n_branches, const arb_synapse *syn, int64_t n_syn,
+                    const arb_connection *conn, int64_t n_conn, const arb_event *ev,
+                    int64_t n_ev, const arb_iclamp *stim, int32_t n_stim,
+                    const arb_params *p, arb_info *info);
+
 /* Step-kernel timing (ARB_FLAG_TIME_KERNELS): total ms and number of
  * launches since the last call; synchronises the stream. */
 int arb_get_kernel_time(arb_sim s, double *ms_total, int64_t *n_launches);

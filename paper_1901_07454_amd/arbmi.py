@@ -69,7 +69,7 @@ class arb_info(C.Structure):
 EXPORTS = ["arb_build_cells", "arb_step", "arb_get_voltages", "arb_get_spikes", "arb_set_probes",
            "arb_get_trace", "arb_set_params", "arb_grad_forward", "arb_grad_backward",
            "arb_get_state", "arb_set_state", "arb_get_info", "arb_get_kernel_time", "arb_sync",
-           "arb_free", "arb_last_error"]
+           "arb_free", "arb_last_error", "arb_plan_layout"]
 
 _lib = None
 
@@ -105,6 +105,8 @@ def load():
             "arb_sync": [P],
             "arb_free": [P],
             "arb_last_error": [],
+            "arb_plan_layout": [P, I32, P, I64, P, I64, P, I64, P, I64, P, I32, C.POINTER(arb_params),
+                                C.POINTER(arb_info)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -145,6 +147,17 @@ def arb_build_cells(cells, branches, syn, conn, ev, stim, params: arb_params):
     _check(L.arb_build_cells(_ptr(c), len(c), _ptr(b), len(b), _ptr(s), len(s), _ptr(k), len(k), _ptr(e), len(e),
                              _ptr(i), len(i), C.byref(params), C.byref(out)))
     return out
+
+
+def arb_plan_layout(cells, branches, syn, conn, ev, stim, params: arb_params) -> dict:
+    L = load()
+    info = arb_info()
+    arrs = [np.ascontiguousarray(x, dtype=d) for x, d in
+            ((cells, CELL), (branches, BRANCH), (syn, SYNAPSE), (conn, CONNECTION), (ev, EVENT), (stim, ICLAMP))]
+    c, b, s, k, e, i = arrs
+    _check(L.arb_plan_layout(_ptr(c), len(c), _ptr(b), len(b), _ptr(s), len(s), _ptr(k), len(k), _ptr(e), len(e),
+                             _ptr(i), len(i), C.byref(params), C.byref(info)))
+    return info.as_dict()
 
 
 def arb_step(sim, n_steps: int):

@@ -563,6 +563,65 @@ int arb_build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     return ARB_OK;
 }
 
+int arb_plan_layout(const arb_cell* cells, int32_t n_cells, const arb_branch* branches, int64_t n_branches,
+                    const arb_synapse* syn, int64_t n_syn, const arb_connection* conn, int64_t n_conn,
+                    const arb_event* ev, int64_t n_ev, const arb_iclamp* stim, int32_t n_stim,
+                    const arb_params* p, arb_info* info) {
+    g_err.clear();
+    if (!p || !info) return fail(ARB_EINVAL, "null argument");
+    if (p->block_threads != 0 && p->block_threads != 64 && p->block_threads != 128 && p->block_threads != 256)
+        return fail(ARB_EINVAL, "block_threads must be 0, 64, 128 or 256");
+    if (p->coef_mode < 0 || p->coef_mode > 3) return fail(ARB_EINVAL, "coef_mode must be 0, 1, 2 or 3");
+    if (p->cells_per_pack < 0) return fail(ARB_EINVAL, "cells_per_pack must be >= 0");
+    DeviceLimits d;  // MI355X: 256 CUs, 160 KiB LDS
+    const Plan plan = choose_plan(cells, n_cells, branches, n_branches, *p, d.lds_max, d.n_cu);
+    LowerOptions opt;
+    opt.block_threads = plan.block_threads;
+    opt.coef_mode = plan.coef_mode;
+    opt.lds_budget = plan.lds_budget;
+    opt.lds_hard_max = plan.lds_hard_max;
+    opt.max_cells_per_pack = plan.max_cells_per_pack;
+    opt.reg_slots = plan.coef_mode == 3 ? plan.reg_slots : 0;
+    opt.reg_len = plan.reg_len;
+    Lowered L;
+    std::string err;
+    int rc = lower_model(cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim, *p,
+                         opt, L, err);
+    const bool auto_mode = p->coef_mode == 0 || (p->flags & ARB_FLAG_AUTOTUNE);
+    if (rc == ARB_EINVAL && auto_mode && opt.coef_mode != 2 &&
+        (err.find("LDS") != std::string::npos || err.find("register") != std::string::npos)) {
+        opt.coef_mode = 2;
+        opt.reg_slots = 0;
+        opt.block_threads = p->block_threads ? p->block_threads : 256;
+        opt.max_cells_per_pack = std::max<int64_t>(1, plan.fallback_cells_per_pack);
+        opt.lds_budget = plan.fallback_lds_budget;
+        opt.lds_hard_max = d.lds_max - 256;
+        L = Lowered();
+        rc = lower_model(cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim, *p,
+                         opt, L, err);
+    }
+    if (rc != ARB_OK) return fail(rc, err);
+    const std::string bad = verify_layout(L);
+    if (!bad.empty()) return fail(ARB_EINVAL, "layout invariant violated: " + bad);
+    arb_info I{};
+    I.n_cells = L.n_cells;
+    I.n_packs = int32_t(L.packs.size());
+    I.n_cv = L.n_cv;
+    I.n_slots = L.n_slots;
+    I.n_hh = int64_t(L.hh_cv.size());
+    I.n_syn = int64_t(L.syn_global.size());
+    I.n_conn = int64_t(L.out_rank.size());
+    I.epoch_steps = p->epoch_steps > 0 ? p->epoch_steps : (L.out_rank.empty() ? 1000 : L.min_delay);
+    I.block_threads = L.block_threads;
+    I.coef_mode = L.coef_mode;
+    int64_t lds = 0;
+    for (const PackDesc& D : L.packs) lds = std::max(lds, pack_lds_bytes(D, L.coef_mode));
+    I.lds_bytes = int32_t(lds);
+    I.bytes_per_step = 44 * L.n_cv + 56 * I.n_hh + 20 * I.n_syn;
+    *info = I;
+    return ARB_OK;
+}
+
 int arb_step(arb_sim s_, int64_t n_steps) {
     Sim* s = static_cast<Sim*>(s_);
     if (!s) return fail(ARB_EINVAL, "sim is NULL");

@@ -621,6 +621,50 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
     return ARB_OK;
 }
 
+std::string verify_layout(const Lowered& L) {
+    // every user CV in exactly one slot, slots inside their pack
+    std::vector<int32_t> hit(L.n_slots, 0);
+    for (int64_t i = 0; i < L.n_cv; ++i) {
+        const int64_t s = L.perm[i];
+        if (s < 0 || s >= L.n_slots) return fmt("CV %lld has no slot", (long long)i);
+        if (hit[s]++) return fmt("slot %lld holds two CVs", (long long)s);
+    }
+    for (size_t pk = 0; pk < L.packs.size(); ++pk) {
+        const PackDesc& D = L.packs[pk];
+        if (D.ncell > L.block_threads) return fmt("pack %zu has more cells than threads", pk);
+        // round order: a task's children finished in earlier rounds (elimination
+        // runs rounds in order); its parent's slot lies in a later round
+        std::vector<int32_t> round_of_slot(D.nslot, -1);
+        for (int32_t r = 0; r < D.nrd; ++r) {
+            const RoundDesc& R = L.rounds[D.rd0 + r];
+            if (R.w < 1 || R.t0 < 0 || R.t0 + R.w > L.block_threads) return fmt("pack %zu round %d: bad threads", pk, r);
+            if (int64_t(R.slot0) + int64_t(R.len) * R.w > D.nslot) return fmt("pack %zu round %d: slots overflow", pk, r);
+            for (int64_t q = R.slot0; q < int64_t(R.slot0) + int64_t(R.len) * R.w; ++q) round_of_slot[q] = r;
+        }
+        std::vector<std::vector<char>> used(std::max(L.reg_slots, 1), std::vector<char>(L.block_threads, 0));
+        for (int32_t r = 0; r < D.nrd; ++r) {
+            const RoundDesc& R = L.rounds[D.rd0 + r];
+            if (L.reg_slots > 0) {
+                if (R.j < 0 || R.j >= L.reg_slots) return fmt("pack %zu round %d: register slot out of range", pk, r);
+                if (R.len > L.reg_len) return fmt("pack %zu round %d: branch longer than the registers", pk, r);
+                for (int t = R.t0; t < R.t0 + R.w; ++t)
+                    if (used[R.j][t]++) return fmt("pack %zu: thread %d register slot %d used twice", pk, t, R.j);
+            }
+            for (int i = 0; i < R.w; ++i) {
+                const TaskDesc& T = L.tasks[D.tk0 + R.task0 + i];
+                if (T.len < 1 || T.len > R.len) return fmt("pack %zu round %d: bad task length", pk, r);
+                if (T.par >= 0 && !(round_of_slot[T.par] > r)) return fmt("pack %zu round %d: parent not later", pk, r);
+                for (int c = 0; c < T.nch; ++c) {
+                    const int32_t cs = L.ch_slot[D.ch0 + T.ch0 + c];
+                    if (cs < 0 || cs >= D.nslot || !(round_of_slot[cs] < r))
+                        return fmt("pack %zu round %d: child not earlier", pk, r);
+                }
+            }
+        }
+    }
+    return "";
+}
+
 // alpha_i = c_i/dt - G_lin,i and beta_i = sum G e over the linear terms
 // (pas and the hh leak), so that the right-hand side of the implicit-Euler
 // system is  rhs_i = alpha_i V_i + beta_i - (nonlinear and point currents).

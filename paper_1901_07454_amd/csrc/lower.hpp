@@ -90,6 +90,9 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                 const arb_event* ev, int64_t n_ev, const arb_iclamp* ic, int32_t n_ic,
                 const arb_params& p, const LowerOptions& opt, Lowered& out, std::string& err);
 
+// Check the packed layout's invariants; empty string if all hold.
+std::string verify_layout(const Lowered& lw);
+
 // Recompute alpha, beta, hh_gna, hh_gk from lw.regions (after a parameter change).
 void recompute_coefficients(Lowered& lw);
 

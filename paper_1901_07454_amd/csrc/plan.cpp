@@ -42,7 +42,8 @@ Plan choose_plan(const arb_cell* cells, int32_t n_cells, const arb_branch* br, i
 
     // Register-resident coefficients (mode 3) when every branch fits the
     // registers: L = 8 CVs with up to 3 branches per thread, or L = 16 with 1.
-    const bool reg_ok = max_len <= 16 && !grads && (p.coef_mode == 0 || p.coef_mode == 3);
+    // an explicit request is honoured or refused by the lowering, never changed
+    const bool reg_ok = p.coef_mode == 3 || (p.coef_mode == 0 && max_len <= 16 && !grads);
     if (reg_ok) {
         pl.coef_mode = 3;
         pl.block_threads = p.block_threads ? p.block_threads : 256;

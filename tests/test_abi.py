@@ -164,3 +164,47 @@ def test_rejects_lds_resident_coefficients_for_a_huge_cell():
     big = [i for i in range(40) if 1 + gen.cell_c3(i, 10.0).n_cv.sum() > 4000][:1]
     m = gen.config3(cells=big, n_steps=10)
     _expect_einval(m, "LDS", coef_mode=1)
+
+
+def _plan(m, **kw):
+    return arbmi.arb_plan_layout(*arbmi.model_structs(m), _params(**kw))
+
+
+@pytest.mark.parametrize("mode,T", [(0, 0), (1, 64), (2, 128), (2, 256), (3, 64), (3, 128), (3, 256)])
+def test_plan_layout_invariants_ring(mode, T):
+    m = gen.config2(n_cells=40, n_steps=10)
+    info = _plan(m, coef_mode=mode, block_threads=T)
+    assert info["n_cv"] == 40 * 1017
+    assert info["n_slots"] >= info["n_cv"]
+    assert info["lds_bytes"] <= 160 * 1024 - 256
+    if mode in (0, 3):
+        assert info["coef_mode"] == 3
+        # full binary trees pack exactly: no padding slots
+        assert info["n_slots"] == info["n_cv"]
+
+
+@pytest.mark.parametrize("mode,T", [(0, 0), (2, 64), (2, 256), (3, 128), (3, 256)])
+def test_plan_layout_invariants_uneven_and_networks(mode, T):
+    for m in (gen.config3(n_cells=30, n_steps=10), gen.config5(n_cells=20, n_in=6, n_steps=10),
+              gen.config4(n_cells=9, n_steps=10), gen.config1()):
+        try:
+            info = _plan(m, coef_mode=mode, block_threads=T)
+        except arbmi.ArbError as e:
+            # an explicit register layout may not hold every cell
+            assert mode == 3 and e.code == arbmi.ARB_EINVAL and "register" in str(e)
+            continue
+        assert info["n_cv"] == int(gen.n_cvs(m).sum())
+        assert info["lds_bytes"] <= 160 * 1024 - 256
+
+
+def test_plan_falls_back_from_registers_for_long_branches():
+    m = gen.config1()  # 32-CV branches do not fit 16 registers
+    assert _plan(m)["coef_mode"] == 2
+    with pytest.raises(arbmi.ArbError):
+        _plan(m, coef_mode=3)
+
+
+def test_plan_register_layout_for_full_ring_packs_four_cells():
+    m = gen.config2(n_cells=64, n_steps=10)
+    info = _plan(m, coef_mode=3, block_threads=256)
+    assert info["n_packs"] == 16  # 4 cells of 128 branch tasks fill 256 threads x 2 slots

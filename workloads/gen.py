@@ -241,10 +241,10 @@ def cell_c5(i: int, n_cells: int, n_in: int = 100, t_ms: float = 200.0,
     src = rng.choice(n_cells - 1, size=n_in, replace=False)
     src = np.where(src >= i, src + 1, src)
     delays = np.rint(rng.uniform(5.0, 10.0, n_in) / DT).astype(np.int64)
-    for j in range(n_in):
-        b, k = _random_cv(rng, d)
-        d.syn.append((b, k, 2.0, 0.0))
-        d.in_conn.append((int(src[j]), j, int(delays[j]), 0.01))
+    bs = rng.integers(nb, size=n_in)
+    ks = rng.integers(d.n_cv[bs])
+    d.syn = list(zip(bs.tolist(), ks.tolist(), [2.0] * n_in, [0.0] * n_in))
+    d.in_conn = list(zip(src.tolist(), range(n_in), delays.tolist(), [0.01] * n_in))
     d.syn.append((-1, 0, 2.0, 0.0))
     for st in _poisson_steps(rng, 5.0, t_ms):
         d.ext.append((n_in, int(st), w_bg))
