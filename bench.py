@@ -116,6 +116,30 @@ def cpu_baseline(cfg: int, budget_s: float = 20.0):
                        f"{cpu_s:.1f} s CPU, {wall:.1f} s wall")}
 
 
+def kernel_name(info: dict) -> str:
+    if info["coef_mode"] == 3:
+        return f"reg_step_kernel<{info['block_threads']}, {info['reg_slots']}, {info['reg_len']}>"
+    return f"step_kernel<{info['block_threads']}, {'true' if info['coef_mode'] == 1 else 'false'}>"
+
+
+def measured_traffic(path: str, cfg: int, kernel: str, steps_per_launch: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on this kernel variant, at this launch length, with the
+    kernel sources unchanged since; else None."""
+    import hashlib
+    try:
+        rec = json.load(open(path))[f"config{cfg}"]
+        h = hashlib.sha256()
+        for p in rec["kernel_sources"]:
+            h.update(open(os.path.join(ROOT, p), "rb").read())
+        if (h.hexdigest() == rec["kernel_sha256"] and rec["kernel"] == kernel
+                and abs(rec["steps_per_launch"] - steps_per_launch) < 1e-9):
+            return rec["bytes_per_launch"]
+    except Exception:
+        pass
+    return None
+
+
 def grad_ratio(torch, reps: int = 3):
     """Config 4: time of forward+adjoint gradient over time of the plain
     forward, same sim, same GPU (2000 steps, checkpoints every 100)."""
@@ -169,7 +193,7 @@ def main():
     ap.add_argument("--cells-per-pack", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -185,7 +209,10 @@ def main():
     m, desc = make_model(args.config, args.cells)
     log(f"model built in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    sim = arbmi.Simulation(m, flags=arbmi.ARB_FLAG_TIME_KERNELS, block_threads=args.block_threads,
+    flags = arbmi.ARB_FLAG_TIME_KERNELS
+    if not (args.block_threads or args.coef_mode or args.cells_per_pack):
+        flags |= arbmi.ARB_FLAG_AUTOTUNE
+    sim = arbmi.Simulation(m, flags=flags, block_threads=args.block_threads,
                            coef_mode=args.coef_mode, cells_per_pack=args.cells_per_pack)
     info = sim.info
     log(f"sim built in {time.perf_counter() - t0:.1f} s: {info}")
@@ -210,14 +237,8 @@ def main():
     avg_launch_s = kms / 1e3 / max(nlaunch, 1)
     bytes_per_launch = info["bytes_per_step"] * steps_per_launch
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = None
-    try:
-        tj = json.load(open(args.traffic_json))
-        key = f"config{args.config}"
-        if key in tj and tj[key].get("kernel_hash") == info.get("kernel_hash", tj[key].get("kernel_hash")):
-            traffic = tj[key].get("bytes_per_launch")
-    except Exception:
-        traffic = None
+    kernel = kernel_name(info)
+    traffic = measured_traffic(args.traffic_json, args.config, kernel, steps_per_launch)
     copy_gbps = copy_bandwidth_gbps(torch)
     out = {
         "metric": "CV-updates/s per GPU (fwd FP64)",
@@ -238,7 +259,7 @@ def main():
                    "packs": info["n_packs"], "lds_bytes": info["lds_bytes"], "spikes": int(len(spikes))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "step_kernel", "bytes_per_step": info["bytes_per_step"],
+                     "kernel": kernel, "bytes_per_step": info["bytes_per_step"],
                      "steps_per_launch": steps_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
                      "measured_copy_GBps": copy_gbps},
     }

@@ -164,6 +164,8 @@ typedef struct {
     int32_t lds_bytes;        /* dynamic LDS per workgroup */
     int64_t device_bytes;     /* device memory held by the sim */
     int64_t bytes_per_step;   /* algorithmic HBM bytes one step must move (SoA model) */
+    int32_t reg_slots;        /* coef_mode 3: branches per thread held in registers */
+    int32_t reg_len;          /* coef_mode 3: CVs per branch held in registers */
 } arb_info;
 
 /* Build a simulation from a fully enumerated model (Sec. III-A: cells,

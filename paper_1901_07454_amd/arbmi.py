@@ -60,7 +60,8 @@ class arb_info(C.Structure):
                 ("n_slots", C.c_int64), ("n_hh", C.c_int64), ("n_syn", C.c_int64),
                 ("n_conn", C.c_int64), ("step", C.c_int64), ("epoch_steps", C.c_int32),
                 ("block_threads", C.c_int32), ("coef_mode", C.c_int32), ("lds_bytes", C.c_int32),
-                ("device_bytes", C.c_int64), ("bytes_per_step", C.c_int64)]
+                ("device_bytes", C.c_int64), ("bytes_per_step", C.c_int64),
+                ("reg_slots", C.c_int32), ("reg_len", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

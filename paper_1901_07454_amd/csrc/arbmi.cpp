@@ -618,6 +618,8 @@ int arb_plan_layout(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     for (const PackDesc& D : L.packs) lds = std::max(lds, pack_lds_bytes(D, L.coef_mode));
     I.lds_bytes = int32_t(lds);
     I.bytes_per_step = 44 * L.n_cv + 56 * I.n_hh + 20 * I.n_syn;
+    I.reg_slots = L.coef_mode == 3 ? L.reg_slots : 0;
+    I.reg_len = L.coef_mode == 3 ? L.reg_len : 0;
     *info = I;
     return ARB_OK;
 }
@@ -883,6 +885,8 @@ int arb_get_info(arb_sim s_, arb_info* info) {
     // gates read+write plus a weight (56 B); per synapse g read+write plus
     // its CV index (20 B)
     I.bytes_per_step = 44 * L.n_cv + 56 * I.n_hh + 20 * I.n_syn;
+    I.reg_slots = s->cfg.coef_mode == 3 ? s->cfg.reg_slots : 0;
+    I.reg_len = s->cfg.coef_mode == 3 ? s->cfg.reg_len : 0;
     *info = I;
     return ARB_OK;
 }
