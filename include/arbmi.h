@@ -132,7 +132,8 @@ typedef struct {
     int64_t event_capacity;   /* network events per (cell pack, epoch); 0 = default */
     int32_t block_threads;    /* threads per cell pack; 0 = autotuned */
     int32_t coef_mode;        /* 0 = autotuned, 1 = per-CV coefficients in LDS, 2 = streamed,
-                                 3 = held in registers (branches of <= 16 CVs) */
+                                 3 = held in registers (branches of <= 16 CVs; not with
+                                 ARB_FLAG_GRADIENTS, which needs the states mode 1 or 2 records) */
     int32_t cells_per_pack;   /* most cells one workgroup advances; 0 = autotuned */
     int32_t reserved;
 } arb_params;

@@ -135,6 +135,33 @@ StepArgs Sim::step_args() const {
     return a;
 }
 
+// The step kernel over every pack: one launch per class, the first on the
+// sim's stream, the others on auxiliary streams forked from and joined back
+// into it.
+int Sim::launch_classes(const StepArgs& a0) {
+    if (classes.size() <= 1) {
+        StepArgs a = a0;
+        a.pack0 = 0;
+        HIP_TRY(launch_step(a, cfg, int32_t(L.packs.size()), st));
+        return ARB_OK;
+    }
+    HIP_TRY(hipEventRecord(fork_ev[0], st));
+    for (size_t c = 1; c < classes.size(); ++c) HIP_TRY(hipStreamWaitEvent(aux[c - 1], fork_ev[0], 0));
+    for (size_t c = 0; c < classes.size(); ++c) {
+        StepArgs a = a0;
+        a.pack0 = classes[c].pack0;
+        LaunchCfg lc = cfg;
+        lc.lds_bytes = classes[c].lds;
+        hipStream_t s_c = (c == 0) ? st : aux[c - 1];
+        HIP_TRY(launch_step(a, lc, classes[c].npack, s_c));
+    }
+    for (size_t c = 1; c < classes.size(); ++c) {
+        HIP_TRY(hipEventRecord(join_ev[c - 1], aux[c - 1]));
+        HIP_TRY(hipStreamWaitEvent(st, join_ev[c - 1], 0));
+    }
+    return ARB_OK;
+}
+
 // One epoch's kernels after the step arguments are set: the step kernel,
 // then (network) the exchange of the epoch's spikes; in graph mode also the
 // bucket sort before it and the device epoch counter's advance after it.
@@ -142,7 +169,10 @@ int Sim::launch_epoch_sequence(const StepArgs& a, bool net, bool graph_mode) {
     const int np = int32_t(L.packs.size());
     if (graph_mode && net)
         HIP_TRY(launch_sort_buckets(d_bk_ev, d_bk_cnt, d_pk_ncur, bk_cap, 0, np, d_ctr, st, d_epoch, n_buckets));
-    HIP_TRY(launch_step(a, cfg, np, st));
+    {
+        const int rc = launch_classes(a);
+        if (rc != ARB_OK) return rc;
+    }
     if (net && a.epoch_end) {
         ExchArgs x{};
         x.sp_gid = d_sp_gid;
@@ -252,6 +282,8 @@ int Sim::advance(int64_t n, const RecordArgs* rec) {
         a.epoch_end = (pos + nthis == K) ? 1 : 0;
         a.n_buckets = n_buckets;
         if (rec) {  // rows offset by the steps already done in this call
+            if (cfg.coef_mode == 3)
+                return set_error(ARB_EINVAL, "recording needs the streamed or LDS-resident step kernel");
             a.rec_V = rec->V + done * L.n_slots;
             a.rec_m = rec->m + done * int64_t(L.hh_cv.size());
             a.rec_h = rec->h + done * int64_t(L.hh_cv.size());
@@ -273,7 +305,10 @@ int Sim::advance(int64_t n, const RecordArgs* rec) {
             timer_free.pop_back();
             HIP_TRY(hipEventRecord(e0, st));
         }
-        HIP_TRY(launch_step(a, cfg, np, st));
+        {
+            const int rc = launch_classes(a);
+            if (rc != ARB_OK) return rc;
+        }
         if (e0) {
             HIP_TRY(hipEventRecord(e1, st));
             timer_pending.push_back({e0, e1});
@@ -485,6 +520,64 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
     }
     s->cfg.lds_bytes = int(std::max<int64_t>(lds, 8));
     s->exch_grid = std::max(1, std::min(4 * d.n_cu, int((m.n_cells + 3) / 4)));
+    // classes by workgroups per CU the LDS allows: 1, 2, 3, 4 or more.  Packs
+    // come out of the packer largest first, so each class is a contiguous
+    // range; a class's LDS is its largest pack's.
+    {
+        const int64_t lim = d.lds_max - 256;
+        auto cat = [&](int64_t b) { return b > lim / 2 ? 1 : b > lim / 3 ? 2 : b > lim / 4 ? 3 : 4; };
+        const int32_t np = int32_t(s->L.packs.size());
+        int32_t start = 0;
+        int cur = np ? cat(pack_lds_bytes(s->L.packs[0], s->L.coef_mode)) : 4;
+        int64_t mx = 0;
+        for (int32_t k = 0; k <= np; ++k) {
+            const int64_t b = (k < np) ? pack_lds_bytes(s->L.packs[k], s->L.coef_mode) : 0;
+            const int c = (k < np) ? std::max(cur, cat(b)) : 99;
+            if (c != cur) {
+                s->classes.push_back({start, k - start, int(std::max<int64_t>(mx, 8))});
+                start = k;
+                mx = 0;
+                cur = c;
+            }
+            mx = std::max(mx, b);
+        }
+        // a class of a few packs is not worth a stream of its own: merge it
+        // into the previous (larger-LDS) class
+        std::vector<Sim::Class> merged;
+        for (const Sim::Class& c : s->classes) {
+            if (!merged.empty() && c.npack < 2 * d.n_cu) {
+                merged.back().npack += c.npack;
+                continue;
+            }
+            merged.push_back(c);
+        }
+        s->classes = merged;
+        if (s->classes.size() > 1) {
+            for (size_t c = 1; c < s->classes.size(); ++c) {
+                hipStream_t x;
+                hipEvent_t e;
+                if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) {
+                    delete s;
+                    err = "stream creation failed";
+                    return ARB_EHIP;
+                }
+                s->aux.push_back(x);
+                if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                    delete s;
+                    err = "event creation failed";
+                    return ARB_EHIP;
+                }
+                s->join_ev.push_back(e);
+            }
+            hipEvent_t e;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                delete s;
+                err = "event creation failed";
+                return ARB_EHIP;
+            }
+            s->fork_ev.push_back(e);
+        }
+    }
     hipError_t he = prepare_step_kernels(int(d.lds_max));
     if (he != hipSuccess) {
         delete s;
@@ -511,6 +604,9 @@ void destroy_sim(Sim* s) {
     (void)hipStreamSynchronize(s->st);
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     if (s->st_capture) (void)hipStreamDestroy(s->st_capture);
+    for (hipStream_t x : s->aux) (void)hipStreamDestroy(x);
+    for (hipEvent_t e : s->fork_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->join_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->timer_free) (void)hipEventDestroy(e);
     for (auto& pr : s->timer_pending) {
         (void)hipEventDestroy(pr.first);
@@ -536,6 +632,8 @@ int arb_build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     if (p->block_threads != 0 && p->block_threads != 64 && p->block_threads != 128 && p->block_threads != 256)
         return fail(ARB_EINVAL, "block_threads must be 0, 64, 128 or 256");
     if (p->coef_mode < 0 || p->coef_mode > 3) return fail(ARB_EINVAL, "coef_mode must be 0, 1, 2 or 3");
+    if (p->coef_mode == 3 && (p->flags & ARB_FLAG_GRADIENTS))
+        return fail(ARB_EINVAL, "coef_mode 3 does not record states: gradients need coef_mode 0, 1 or 2");
     if (p->cells_per_pack < 0) return fail(ARB_EINVAL, "cells_per_pack must be >= 0");
     if ((p->alloc == nullptr) != (p->free == nullptr)) return fail(ARB_EINVAL, "alloc and free must be given together");
 
@@ -572,6 +670,8 @@ int arb_plan_layout(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     if (p->block_threads != 0 && p->block_threads != 64 && p->block_threads != 128 && p->block_threads != 256)
         return fail(ARB_EINVAL, "block_threads must be 0, 64, 128 or 256");
     if (p->coef_mode < 0 || p->coef_mode > 3) return fail(ARB_EINVAL, "coef_mode must be 0, 1, 2 or 3");
+    if (p->coef_mode == 3 && (p->flags & ARB_FLAG_GRADIENTS))
+        return fail(ARB_EINVAL, "coef_mode 3 does not record states: gradients need coef_mode 0, 1 or 2");
     if (p->cells_per_pack < 0) return fail(ARB_EINVAL, "cells_per_pack must be >= 0");
     DeviceLimits d;  // MI355X: 256 CUs, 160 KiB LDS
     const Plan plan = choose_plan(cells, n_cells, branches, n_branches, *p, d.lds_max, d.n_cu);

@@ -53,7 +53,7 @@ uint64_t shape_key(const ModelView& m, const DeviceLimits& d) {
     for (uint64_t x : cv_hist) mix(x);
     mix(uint64_t(d.n_cu));
     mix(uint64_t(d.lds_max));
-    mix(3);  // version of the candidate set
+    mix(4);  // version of the candidate set
     return h;
 }
 
@@ -207,9 +207,9 @@ arb_params autotune(const ModelView& m, const arb_params& p, const DeviceLimits&
         }
         const int fill256 = int(std::max<int64_t>(1, 256 / max_width));
         const std::vector<Candidate> cands = {
-            {3, 256, 0}, {3, 128, 0}, {3, 64, 0},
+            {3, 256, 0}, {3, 128, 0}, {3, 64, 0}, {3, 64, 1}, {3, 128, 1},
             {2, 256, fill256}, {2, 256, std::max(1, fill256 / 2)}, {2, 128, std::max(1, fill256 / 2)},
-            {1, 64, 1}, {1, 256, 0}};
+            {2, 64, 1}, {1, 64, 1}, {1, 256, 0}};
         double best_rate = 0.0;
         for (const Candidate& c : cands) {
             const double r = time_candidate(smp, p, d, c);

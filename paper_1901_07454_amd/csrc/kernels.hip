@@ -31,7 +31,7 @@ constexpr int CH = 8;  // CVs of a branch staged in registers at a time
 template <int T, bool CL>
 __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
     extern __shared__ double lds[];
-    const int p = blockIdx.x;
+    const int p = blockIdx.x + a.pack0;
     const PackDesc pk = a.pk[p];
     const int tid = threadIdx.x;
     const int ns = pk.nslot;

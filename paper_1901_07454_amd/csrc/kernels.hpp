@@ -81,7 +81,7 @@ struct StepArgs {
     // (step0 = epoch * nsteps, bucket = epoch % n_buckets)
     const int64_t* epoch_ptr;
     int32_t n_buckets;
-    int32_t pad2;
+    int32_t pack0;             // first pack of this launch (block b runs pack pack0 + b)
 };
 
 // Per-launch configuration chosen by the host.

@@ -46,11 +46,18 @@ struct PackDesc {
 };
 
 // Bytes of dynamic LDS the step kernel uses for a pack.  Layout in the
-// kernel: doubles V, R, [alpha, beta, F, 1/d'], g, m, h, n, [gNa, gK, e_syn,
-// decay]; then rounds, tasks, nonlinear entries, child slots.  Bracketed
-// parts are staged only in coefficient mode 1 (mode 2 streams them).
-// Mode 3 (register-resident coefficients) uses the mode-2 layout.
+// streamed and LDS-resident kernels: doubles V, R, [alpha, beta, F, 1/d'], g,
+// m, h, n, [gNa, gK, e_syn, decay]; then rounds, tasks, nonlinear entries,
+// child slots.  Bracketed parts are staged only in coefficient mode 1 (mode 2
+// streams them).  The register-resident kernel (mode 3) keeps its branches'
+// descriptors in registers and stages: (V, R) pairs for every slot plus a
+// zero pair and a discard pair, g, m, h, n, gNa, gK, e_syn, decay, beta of
+// each nonlinear CV, the nonlinear entries and the child slots.
 inline int64_t pack_lds_bytes(const PackDesc& D, int coef_mode) {
+    if (coef_mode == 3) {
+        const int64_t dbl = 2 * (int64_t(D.nslot) + 2) + 3 * int64_t(D.nsyn) + 5 * int64_t(D.nhh) + int64_t(D.nnl);
+        return 8 * dbl + 16 * int64_t(D.nnl) + 4 * int64_t(D.nch);
+    }
     const bool cl = coef_mode == 1;
     const int64_t dbl = (cl ? 6 : 2) * int64_t(D.nslot) + int64_t(D.nsyn) + 3 * int64_t(D.nhh) +
                         (cl ? 2 * (int64_t(D.nhh) + int64_t(D.nsyn)) : 0);
@@ -73,7 +80,7 @@ struct TaskDesc {
     int32_t nch;    //   proximal CVs of the child branches, in branch order
 };
 
-struct NlDesc {     // one CV carrying an hh instance or synapses
+struct NlDesc {     // one CV carrying an hh instance, synapses or current clamps
     int32_t slot;   // pack-local slot
     int32_t hh;     // pack-local hh instance, -1 if none
     int32_t syn0;   // pack-local synapses [syn0, syn0 + nsyn)

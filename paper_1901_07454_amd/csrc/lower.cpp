@@ -28,16 +28,6 @@
 
 namespace arbmi {
 
-int64_t pack_lds_estimate(int64_t nslot, int64_t nsyn, int64_t nhh, int64_t nbranch, int64_t ncell,
-                          int64_t nic, int coef_mode) {
-    const int64_t per_slot = (coef_mode == 1) ? 6 : 2;  // V, R (+ alpha, beta, F, invd)
-    const int64_t tasks = nbranch + ncell;
-    (void)nic;
-    // rounds <= tasks; nonlinear entries <= hh + synapses
-    return 8 * (per_slot * nslot + nsyn + 3 * nhh + (coef_mode == 1 ? 2 * (nhh + nsyn) : 0)) + 16 * tasks +
-           16 * tasks + 16 * (nhh + nsyn) + 4 * nbranch;
-}
-
 namespace {
 
 const double kPi = 3.14159265358979323846;
@@ -72,7 +62,6 @@ struct PackPlan {
     std::vector<int32_t> cells;
     int64_t nslot = 0;
     int64_t nsyn = 0, nhh = 0, nbr = 0, nic = 0;
-    int64_t lds(int mode) const { return pack_lds_estimate(nslot, nsyn, nhh, nbr, int64_t(cells.size()), nic, mode); }
 };
 
 }  // namespace
@@ -284,12 +273,20 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                 int jb = 0;
                 size_t room = size_t(T);
                 if (S > 0) {
+                    // the first slot that takes the rest of the level whole,
+                    // else the one with the most free threads: few slots in
+                    // use let the kernel keep fewer registers
                     jb = -1;
-                    int best = 0;
-                    for (int j = 0; j < S; ++j)
-                        if (T - next_free[j] > best) { best = T - next_free[j]; jb = j; }
+                    const size_t rest = items.size() - s0;
+                    for (int j = 0; j < S && jb < 0; ++j)
+                        if (size_t(T - next_free[j]) >= rest) jb = j;
+                    if (jb < 0) {
+                        int best = 0;
+                        for (int j = 0; j < S; ++j)
+                            if (T - next_free[j] > best) { best = T - next_free[j]; jb = j; }
+                    }
                     if (jb < 0) return false;
-                    room = size_t(best);
+                    room = size_t(T - next_free[jb]);
                 }
                 const size_t m = std::min(items.size() - s0, room);
                 RoundPlan rp;
@@ -321,7 +318,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
     // CVs carrying hh or synapses, per cell
     std::vector<int32_t> nnl_cell(n_cells, 0);
     for (int32_t c = 0; c < n_cells; ++c)
-        for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i) nnl_cell[c] += (has_hh[i] || nsyn_cv[i]) ? 1 : 0;
+        for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i) nnl_cell[c] += (has_hh[i] || nsyn_cv[i] || nic_cv[i]) ? 1 : 0;
     auto exact_lds = [&](const PackPlan& pp, int mode) -> int64_t {
         const Shape sh = plan_shape(pp.cells);
         if (!sh.ok) return int64_t(1) << 40;  // does not fit the register slots
@@ -504,7 +501,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         for (int32_t k = 0; k < D.ncell; ++k) {
             const int32_t c = L.pc_gid[D.cell0 + k];
             for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i)
-                if (has_hh[i] || nsyn_cv[i]) here.push_back({L.perm[i], i});
+                if (has_hh[i] || nsyn_cv[i] || nic_cv[i]) here.push_back({L.perm[i], i});
         }
         std::sort(here.begin(), here.end());
         for (auto& sc : here) {
@@ -547,6 +544,12 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
     L.hh_gk.assign(L.hh_cv.size(), 0.0);
     L.glin_extra.assign(L.n_cv, 0.0);
     recompute_coefficients(L);
+    // the register-resident kernel needs only as many slots as the rounds use
+    if (L.reg_slots > 0) {
+        int used = 1;
+        for (const RoundDesc& R : L.rounds) used = std::max(used, R.j + 1);
+        L.reg_slots = used;
+    }
 
     // external events, grouped per pack, ordered (step, pack synapse, input order)
     {

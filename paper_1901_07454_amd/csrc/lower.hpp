@@ -96,9 +96,4 @@ std::string verify_layout(const Lowered& lw);
 // Recompute alpha, beta, hh_gna, hh_gk from lw.regions (after a parameter change).
 void recompute_coefficients(Lowered& lw);
 
-// Upper bound of the LDS bytes a pack with these counts needs (used while
-// packing, before the pack's descriptors exist).
-int64_t pack_lds_estimate(int64_t nslot, int64_t nsyn, int64_t nhh, int64_t nbranch, int64_t ncell,
-                          int64_t nic, int coef_mode);
-
 }  // namespace arbmi

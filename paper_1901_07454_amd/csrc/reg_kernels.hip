@@ -1,16 +1,25 @@
 // reg_kernels.hip -- register-resident variant of the fused step kernel.
 //
-// Same scheme and phases as step_kernel (kernels.hip), but each thread keeps
-// the step-invariant coefficients of its branches (alpha, beta, F, 1/d') and
-// the eliminated right-hand side in VGPRs for the whole epoch.  A thread owns
-// up to S branches of at most L CVs; every round of the level sweep uses one
-// register slot j on all of its threads (the host assigns them), so the
-// per-slot register arrays are indexed with compile-time constants.  Per CV
-// and step the LDS traffic is one load of V, one of the point/nonlinear
-// current, and one store of the new V; branches exchange only their end
-// values: a child leaves F * rhs' of its proximal CV in R at that CV's slot
-// for the parent's elimination, and the parent's new V is read from LDS by
-// the children's substitution.
+// Same scheme and phases as step_kernel (kernels.hip): events, point
+// currents, elimination by rounds (deepest first), substitution, states and
+// threshold.  Here each thread holds, for the whole launch, everything about
+// its branches that does not change between steps: the step coefficients
+// (alpha, F = u/d', 1/d'), the LDS offsets of the branch's CVs, of its
+// parent's CV and of its children's proximal CVs.  A thread owns up to S
+// branches of at most L CVs; the host gives every round one register slot j
+// on all of its threads, so the per-slot arrays are indexed with
+// compile-time constants.  The rounds themselves need no descriptor loads.
+// The kernel does not record states for the adjoint (the host refuses that).
+//
+// LDS keeps V and R (the right-hand side) as interleaved pairs, so one
+// 128-bit load brings both operands of a CV; between a branch's elimination
+// and its substitution its V entries hold rhs'/d'.  R starts every step as beta
+// (the step-invariant part of the right-hand side); the point-current pass
+// writes beta - I at the CVs with currents, a branch's elimination leaves
+// F * rhs' of its proximal CV in that CV's R for the parent and its
+// substitution puts beta back.  A branch shorter than L is padded: the pad
+// CVs read a pair of zeros and carry the children's sum through unchanged
+// (F = -1, and +1 at the first pad), their results go to a discard pair.
 #include <hip/hip_runtime.h>
 
 #include "kernel_common.hpp"
@@ -22,108 +31,154 @@ namespace {
 
 using namespace dev;
 
-template <int S, int L>
-struct Regs {
-    double A[S][L], B[S][L], F[S][L], D[S][L], R[S][L];
+__device__ __forceinline__ double2 ld_pair(const char* vr, int off) {
+    return *reinterpret_cast<const double2*>(vr + off);
+}
+__device__ __forceinline__ double ld_V(const char* vr, int off) { return *reinterpret_cast<const double*>(vr + off); }
+__device__ __forceinline__ double ld_R(const char* vr, int off) {
+    return *reinterpret_cast<const double*>(vr + off + 8);
+}
+__device__ __forceinline__ void st_V(char* vr, int off, double x) { *reinterpret_cast<double*>(vr + off) = x; }
+__device__ __forceinline__ void st_R(char* vr, int off, double x) { *reinterpret_cast<double*>(vr + off + 8) = x; }
+
+// The registers of one branch slot.  Offsets are bytes into the pair array.
+template <int L>
+struct Slot {
+    double A[L], F[L], D[L];        // alpha, F (pads: +1 then -1), 1/d' (pads: 0)
+    double B0;                      // beta of the proximal CV
+    int ea[L];                      // pairs of the CVs (pads: the zero pair)
+    int r;                          // round of the branch, -1 if the slot is empty
+    int len;
+    int par;                        // pair of the parent's CV (zero pair at a soma)
+    int c0, c1;                     // pairs of the first two children (zero pair if fewer)
+    int cx0, ncx;                   // further children: s_ch[cx0 .. cx0 + ncx)
 };
 
-// Elimination of one branch held in register slot J, distal to proximal.
-template <int J, int S, int L>
-__device__ inline void elim(Regs<S, L>& g, const double* sV, double* sR, int base, int w, int len, double csum) {
-    double v[L], rn[L];
+// Elimination of one branch, distal to proximal:
+// rhs'_k = alpha_k V_k + R_k - F_{k+1} rhs'_{k+1}, the distal CV taking the
+// children's contributions instead of the last term.  V_k is not read again
+// before the substitution writes its new value, so rhs'_k / d'_k waits there.
+template <int L>
+__device__ __forceinline__ void elim(const Slot<L>& g, char* vr, const int32_t* s_ch, int discard) {
+    double2 p[L];
 #pragma unroll
-    for (int k = 0; k < L; ++k) {
-        const int sl = base + min(k, len - 1) * w;
-        v[k] = sV[sl];
-        rn[k] = sR[sl];
-    }
-    double acc = 0.0;
+    for (int k = 0; k < L; ++k) p[k] = ld_pair(vr, g.ea[k]);
+    double csum = ld_R(vr, g.c0) + ld_R(vr, g.c1);
+    for (int q = 0; q < g.ncx; ++q) csum += ld_R(vr, 16 * s_ch[g.cx0 + q]);
+    double acc = (g.len == L) ? csum : -csum;
 #pragma unroll
     for (int k = L - 1; k >= 0; --k) {
-        if (k < len) {
-            const double t = g.A[J][k] * v[k] + g.B[J][k] + rn[k];
-            const double fnext = (k + 1 < L) ? g.F[J][(k + 1 < L) ? k + 1 : k] : 0.0;
-            acc = (k == len - 1) ? t - csum : t - fnext * acc;
-            g.R[J][k] = acc;
-        }
+        const double t = g.A[k] * p[k].x + p[k].y;
+        const double r = (k == L - 1) ? t - acc : t - g.F[(k + 1 < L) ? k + 1 : k] * acc;
+        st_V(vr, (k == 0 || k < g.len) ? g.ea[k] : discard, r * g.D[k]);
+        acc = r;
     }
-    sR[base] = g.F[J][0] * g.R[J][0];  // contribution to the parent's elimination
+    st_R(vr, g.ea[0], g.F[0] * acc);  // contribution to the parent's elimination
 }
 
-// Substitution of one branch held in register slot J, proximal to distal.
-template <int J, int S, int L>
-__device__ inline void subst(Regs<S, L>& g, double* sV, double* sR, int base, int w, int len, double x) {
+// Substitution of one branch, proximal to distal: V_k = rhs'_k/d'_k - F_k V_{k-1}
+// (V_{-1} the parent's CV); then beta back into R.
+template <int L>
+__device__ __forceinline__ void subst(const Slot<L>& g, char* vr, int discard) {
+    double y[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) y[k] = ld_V(vr, g.ea[k]);
+    double x = ld_V(vr, g.par);
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-        if (k < len) {
-            x = g.R[J][k] * g.D[J][k] - g.F[J][k] * x;
-            sV[base + k * w] = x;
-        }
+        x = y[k] - g.F[k] * x;
+        st_V(vr, (k == 0 || k < g.len) ? g.ea[k] : discard, x);
     }
-    sR[base] = 0.0;  // clear the contribution left for the parent
+    st_R(vr, g.ea[0], g.B0);
 }
 
-template <int J, int S, int L>
-__device__ inline void load_slot(Regs<S, L>& g, const StepArgs& a, const PackDesc& pk, const RoundDesc* s_rd,
-                                 const TaskDesc* s_tk, int r, int tid) {
-    if (r < 0) {
-#pragma unroll
-        for (int k = 0; k < L; ++k) g.A[J][k] = g.B[J][k] = g.F[J][k] = g.D[J][k] = g.R[J][k] = 0.0;
-        return;
-    }
-    const RoundDesc R = s_rd[r];
-    const int i = round_index(R, tid);
-    const TaskDesc t = s_tk[R.task0 + i];
-    const int64_t base = pk.slot0 + R.slot0 + i;
+// Fill slot g with the branch this thread takes in round r of the pack (an
+// empty slot if r < 0).  Branch-free: an empty slot reads valid entries of
+// the pack and keeps neutral values.
+template <int L>
+__device__ __forceinline__ void load_slot(Slot<L>& g, const StepArgs& a, const PackDesc& pk, int r, int tid,
+                                          int zero) {
+    const bool has = r >= 0;
+    const RoundDesc R = a.rd[pk.rd0 + (has ? r : 0)];
+    const int i = has ? round_index(R, tid) : 0;
+    const TaskDesc t = a.tk[pk.tk0 + (has ? R.task0 + i : 0)];
+    const int len = has ? t.len : 1;
+    const int base = has ? R.slot0 + i : 0;
+    const int w = has ? R.w : 0;
+    g.r = has ? r : -1;
+    g.len = len;
+    g.par = (has && t.par >= 0) ? 16 * t.par : zero;
+    g.c0 = zero;
+    g.c1 = zero;
+    if (has && t.nch > 0) g.c0 = 16 * a.ch_slot[pk.ch0 + t.ch0];
+    if (has && t.nch > 1) g.c1 = 16 * a.ch_slot[pk.ch0 + t.ch0 + 1];
+    g.cx0 = t.ch0 + 2;
+    g.ncx = has ? max(0, t.nch - 2) : 0;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-        const int64_t sl = base + int64_t(min(k, t.len - 1)) * R.w;
-        g.A[J][k] = a.alpha[sl];
-        g.B[J][k] = a.beta[sl];
-        g.F[J][k] = a.F[sl];
-        g.D[J][k] = a.invd[sl];
-        g.R[J][k] = 0.0;
+        const bool real = has && k < len;
+        const int loc = base + min(k, len - 1) * w;
+        const int64_t sl = pk.slot0 + loc;
+        const double al = a.alpha[sl], f = a.F[sl], dv = a.invd[sl];
+        g.ea[k] = real ? 16 * loc : zero;
+        g.A[k] = real ? al : 0.0;
+        g.D[k] = real ? dv : 0.0;
+        g.F[k] = real ? f : (k == len ? 1.0 : -1.0);
     }
+    const double b0 = a.beta[pk.slot0 + base];
+    g.B0 = has ? b0 : 0.0;
 }
 
+// Waves per SIMD the registers allow without spilling: three for one slot
+// of 8 CVs, two for two such slots, one otherwise.
 template <int T, int S, int L>
-__global__ void __launch_bounds__(T) reg_step_kernel(StepArgs a) {
-    extern __shared__ double lds[];
-    const int p = blockIdx.x;
+__global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S == 2 && L == 8 ? 2 : 1)) reg_step_kernel(StepArgs a) {
+    extern __shared__ __align__(16) char lds_raw[];
+    const int p = blockIdx.x + a.pack0;
     const PackDesc pk = a.pk[p];
     const int tid = threadIdx.x;
     const int ns = pk.nslot;
 
-    // ---- LDS layout (coefficient mode 2 layout of pack_lds_bytes) ----
-    double* sV = lds;
-    double* sR = sV + ns;
-    double* sg = sR + ns;
-    double* sm = sg + pk.nsyn;
+    // ---- LDS layout (the mode-3 layout of pack_lds_bytes) ----
+    char* vr = lds_raw;                                        // (V, R) pairs [ns + 2]
+    const int zero = 16 * ns, discard = 16 * (ns + 1);
+    double* sg = reinterpret_cast<double*>(vr + 16 * (ns + 2));
+    double* s_se = sg + pk.nsyn;
+    double* s_sdec = s_se + pk.nsyn;
+    double* sm = s_sdec + pk.nsyn;
     double* sh = sm + pk.nhh;
     double* sn = sh + pk.nhh;
-    RoundDesc* s_rd = reinterpret_cast<RoundDesc*>(sn + pk.nhh);
-    TaskDesc* s_tk = reinterpret_cast<TaskDesc*>(s_rd + pk.nrd);
-    NlDesc* s_nl = reinterpret_cast<NlDesc*>(s_tk + pk.ntk);
+    double* s_gna = sn + pk.nhh;
+    double* s_gk = s_gna + pk.nhh;
+    double* s_nlb = s_gk + pk.nhh;                             // beta of each nonlinear CV
+    NlDesc* s_nl = reinterpret_cast<NlDesc*>(s_nlb + pk.nnl);
     int32_t* s_ch = reinterpret_cast<int32_t*>(s_nl + pk.nnl);
 
-    const double* g_gna = a.hh_gna + pk.hh0;
-    const double* g_gk = a.hh_gk + pk.hh0;
-    const double* g_se = a.syn_e + pk.syn0;
-    const double* g_sdec = a.syn_decay + pk.syn0;
-
     for (int i = tid; i < ns; i += T) {
-        sV[i] = a.V[pk.slot0 + i];
-        sR[i] = 0.0;
+        st_V(vr, 16 * i, a.V[pk.slot0 + i]);
+        st_R(vr, 16 * i, a.beta[pk.slot0 + i]);
     }
-    for (int i = tid; i < pk.nsyn; i += T) sg[i] = a.syn_g[pk.syn0 + i];
+    if (tid < 2) {
+        st_V(vr, zero + 16 * tid, 0.0);
+        st_R(vr, zero + 16 * tid, 0.0);
+    }
+    for (int i = tid; i < pk.nsyn; i += T) {
+        sg[i] = a.syn_g[pk.syn0 + i];
+        s_se[i] = a.syn_e[pk.syn0 + i];
+        s_sdec[i] = a.syn_decay[pk.syn0 + i];
+    }
     for (int i = tid; i < pk.nhh; i += T) {
         sm[i] = a.hh_m[pk.hh0 + i];
         sh[i] = a.hh_h[pk.hh0 + i];
         sn[i] = a.hh_n[pk.hh0 + i];
+        s_gna[i] = a.hh_gna[pk.hh0 + i];
+        s_gk[i] = a.hh_gk[pk.hh0 + i];
     }
-    for (int i = tid; i < pk.nrd; i += T) s_rd[i] = a.rd[pk.rd0 + i];
-    for (int i = tid; i < pk.ntk; i += T) s_tk[i] = a.tk[pk.tk0 + i];
-    for (int i = tid; i < pk.nnl; i += T) s_nl[i] = a.nl[pk.nl0 + i];
+    for (int i = tid; i < pk.nnl; i += T) {
+        const NlDesc d = a.nl[pk.nl0 + i];
+        s_nl[i] = d;
+        s_nlb[i] = a.beta[pk.slot0 + d.slot];
+    }
     for (int i = tid; i < pk.nch; i += T) s_ch[i] = a.ch_slot[pk.ch0 + i];
 
     int64_t step0 = a.step0;
@@ -147,26 +202,26 @@ __global__ void __launch_bounds__(T) reg_step_kernel(StepArgs a) {
         if (ncur < nend) nkey = ev[ncur];
         if (xcur < pk.xe1) xstep = a.xe_step[xcur];
     }
-    const int soma = (tid < pk.ncell) ? a.pc_soma[pk.cell0 + tid] : -1;
+    const int soma = (tid < pk.ncell) ? 16 * a.pc_soma[pk.cell0 + tid] : -1;
     double vold = 0.0;
-    __syncthreads();
 
-    // this thread's round in each register slot, then its coefficients
+    // this thread's round in each register slot, then its branches
     int myr[S];
 #pragma unroll
     for (int j = 0; j < S; ++j) myr[j] = -1;
     for (int r = 0; r < pk.nrd; ++r) {
-        const RoundDesc R = s_rd[r];
+        const RoundDesc R = a.rd[pk.rd0 + r];
         if (round_index(R, tid) >= 0) {
 #pragma unroll
             for (int j = 0; j < S; ++j)
                 if (R.j == j) myr[j] = r;
         }
     }
-    Regs<S, L> g;
-    load_slot<0, S, L>(g, a, pk, s_rd, s_tk, myr[0], tid);
-    if constexpr (S > 1) load_slot<1, S, L>(g, a, pk, s_rd, s_tk, myr[1], tid);
-    if constexpr (S > 2) load_slot<2, S, L>(g, a, pk, s_rd, s_tk, myr[2], tid);
+    Slot<L> g0, g1, g2;
+    load_slot<L>(g0, a, pk, myr[0], tid, zero);
+    if constexpr (S > 1) load_slot<L>(g1, a, pk, myr[1], tid, zero);
+    if constexpr (S > 2) load_slot<L>(g2, a, pk, myr[2], tid, zero);
+    __syncthreads();
 
     for (int s = 0; s < a.nsteps; ++s) {
         const int64_t n = step0 + s;
@@ -187,76 +242,55 @@ __global__ void __launch_bounds__(T) reg_step_kernel(StepArgs a) {
         }
         __syncthreads();
 
-        if (a.rec_V) {  // state entering the step, for the adjoint
-            double* rv = a.rec_V + int64_t(s) * a.n_slots_total + pk.slot0;
-            for (int i = tid; i < ns; i += T) rv[i] = sV[i];
-            double* rm = a.rec_m + int64_t(s) * a.n_hh_total + pk.hh0;
-            double* rh = a.rec_h + int64_t(s) * a.n_hh_total + pk.hh0;
-            double* rn = a.rec_n + int64_t(s) * a.n_hh_total + pk.hh0;
-            for (int i = tid; i < pk.nhh; i += T) {
-                rm[i] = sm[i];
-                rh[i] = sh[i];
-                rn[i] = sn[i];
-            }
-            double* rg = a.rec_g + int64_t(s) * a.n_syn_total + pk.syn0;
-            for (int i = tid; i < pk.nsyn; i += T) rg[i] = sg[i];
-        }
-
-        // B: nonlinear and point currents at V^n, stored as -I in R
+        // B: R = beta - I at the CVs with nonlinear and point currents (V^n)
         for (int j = tid; j < pk.nnl; j += T) {
             const NlDesc d = s_nl[j];
-            const double v = sV[d.slot];
+            const double v = ld_V(vr, 16 * d.slot);
             double I = 0.0;
             if (d.hh >= 0) {
                 const int q = d.hh;
                 const double m = sm[q], h = sh[q], x = sn[q];
-                I += g_gna[q] * (m * m * m * h) * (v - kENa);
-                I += g_gk[q] * (x * x * x * x) * (v - kEK);
+                I += s_gna[q] * (m * m * m * h) * (v - kENa);
+                I += s_gk[q] * (x * x * x * x) * (v - kEK);
             }
             for (int k = 0; k < d.nsyn; ++k) {
                 const int q = d.syn0 + k;
-                I += sg[q] * (v - g_se[q]);
+                I += sg[q] * (v - s_se[q]);
             }
-            sR[d.slot] = -I;
+            st_R(vr, 16 * d.slot, s_nlb[j] - I);
         }
-        if (soma >= 0) vold = sV[soma];
+        if (soma >= 0) vold = ld_V(vr, soma);
         if (pk.nic > 0) {
             __syncthreads();
             if (tid == 0)
                 for (int q = pk.ic0; q < pk.ic0 + pk.nic; ++q)
-                    if (a.ic_on[q] <= n && n < a.ic_off[q]) sR[a.ic_slot[q]] += a.ic_amp[q];
+                    if (a.ic_on[q] <= n && n < a.ic_off[q]) {
+                        const int o = 16 * a.ic_slot[q];
+                        st_R(vr, o, ld_R(vr, o) + a.ic_amp[q]);
+                    }
         }
         __syncthreads();
 
         // C: elimination, deepest rounds first
         for (int r = 0; r < pk.nrd; ++r) {
-            const RoundDesc R = s_rd[r];
-            const int i = round_index(R, tid);
-            if (i >= 0) {
-                const TaskDesc t = s_tk[R.task0 + i];
-                double csum = 0.0;
-                for (int c = 0; c < t.nch; ++c) csum += sR[s_ch[t.ch0 + c]];
-                const int base = R.slot0 + i;
-                const int j = __builtin_amdgcn_readfirstlane(R.j);
-                if (j == 0) elim<0, S, L>(g, sV, sR, base, R.w, t.len, csum);
-                if constexpr (S > 1) if (j == 1) elim<(S > 1 ? 1 : 0), S, L>(g, sV, sR, base, R.w, t.len, csum);
-                if constexpr (S > 2) if (j == 2) elim<(S > 2 ? 2 : 0), S, L>(g, sV, sR, base, R.w, t.len, csum);
+            if (g0.r == r) elim<L>(g0, vr, s_ch, discard);
+            if constexpr (S > 1) {
+                if (g1.r == r) elim<L>(g1, vr, s_ch, discard);
+            }
+            if constexpr (S > 2) {
+                if (g2.r == r) elim<L>(g2, vr, s_ch, discard);
             }
             __syncthreads();
         }
 
         // D: substitution, shallowest rounds first
         for (int r = pk.nrd - 1; r >= 0; --r) {
-            const RoundDesc R = s_rd[r];
-            const int i = round_index(R, tid);
-            if (i >= 0) {
-                const TaskDesc t = s_tk[R.task0 + i];
-                const double x = (t.par >= 0) ? sV[t.par] : 0.0;
-                const int base = R.slot0 + i;
-                const int j = __builtin_amdgcn_readfirstlane(R.j);
-                if (j == 0) subst<0, S, L>(g, sV, sR, base, R.w, t.len, x);
-                if constexpr (S > 1) if (j == 1) subst<(S > 1 ? 1 : 0), S, L>(g, sV, sR, base, R.w, t.len, x);
-                if constexpr (S > 2) if (j == 2) subst<(S > 2 ? 2 : 0), S, L>(g, sV, sR, base, R.w, t.len, x);
+            if (g0.r == r) subst<L>(g0, vr, discard);
+            if constexpr (S > 1) {
+                if (g1.r == r) subst<L>(g1, vr, discard);
+            }
+            if constexpr (S > 2) {
+                if (g2.r == r) subst<L>(g2, vr, discard);
             }
             __syncthreads();
         }
@@ -266,18 +300,18 @@ __global__ void __launch_bounds__(T) reg_step_kernel(StepArgs a) {
             const NlDesc d = s_nl[j];
             if (d.hh >= 0) {
                 const int q = d.hh;
-                const Rates rt = hh_rates(sV[d.slot]);
+                const Rates rt = hh_rates(ld_V(vr, 16 * d.slot));
                 sm[q] = gate_step(sm[q], rt.am, rt.bm, a.dt);
                 sh[q] = gate_step(sh[q], rt.ah, rt.bh, a.dt);
                 sn[q] = gate_step(sn[q], rt.an, rt.bn, a.dt);
             }
             for (int k = 0; k < d.nsyn; ++k) {
                 const int q = d.syn0 + k;
-                sg[q] *= g_sdec[q];
+                sg[q] *= s_sdec[q];
             }
         }
         if (soma >= 0) {
-            const double vnew = sV[soma];
+            const double vnew = ld_V(vr, soma);
             if (vold < a.threshold && vnew >= a.threshold) {
                 const uint32_t pos = atomicAdd(&a.ctr->sp_count, 1u);
                 if (pos < a.sp_cap) {
@@ -293,16 +327,12 @@ __global__ void __launch_bounds__(T) reg_step_kernel(StepArgs a) {
             const int64_t col = n - a.trace_step0;
             if (col >= 0 && col < a.trace_cap)
                 for (int j = tid; j < pk.npr; j += T)
-                    a.trace[int64_t(a.pr_id[pk.pr0 + j]) * a.trace_cap + col] = sV[a.pr_slot[pk.pr0 + j]];
+                    a.trace[int64_t(a.pr_id[pk.pr0 + j]) * a.trace_cap + col] = ld_V(vr, 16 * a.pr_slot[pk.pr0 + j]);
         }
         __syncthreads();
     }
 
-    if (a.rec_V) {
-        double* rv = a.rec_V + int64_t(a.nsteps) * a.n_slots_total + pk.slot0;
-        for (int i = tid; i < ns; i += T) rv[i] = sV[i];
-    }
-    for (int i = tid; i < ns; i += T) a.V[pk.slot0 + i] = sV[i];
+    for (int i = tid; i < ns; i += T) a.V[pk.slot0 + i] = ld_V(vr, 16 * i);
     for (int i = tid; i < pk.nsyn; i += T) a.syn_g[pk.syn0 + i] = sg[i];
     for (int i = tid; i < pk.nhh; i += T) {
         a.hh_m[pk.hh0 + i] = sm[i];

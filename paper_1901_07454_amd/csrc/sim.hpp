@@ -42,6 +42,14 @@ struct Sim : arb_sim_ {
     Lowered L;
     int32_t K = 1;          // epoch length in steps
     LaunchCfg cfg{};
+    // launch classes: contiguous pack ranges run as separate concurrent
+    // kernels, each with the LDS its largest pack needs
+    struct Class {
+        int32_t pack0, npack, lds;
+    };
+    std::vector<Class> classes;
+    std::vector<hipStream_t> aux;       // one per class after the first
+    std::vector<hipEvent_t> fork_ev, join_ev;
     int exch_grid = 1;
     int32_t n_buckets = 1, bk_cap = 0;
     uint32_t sp_cap = 0, sp_user = 0;
@@ -105,6 +113,7 @@ struct Sim : arb_sim_ {
     StepArgs step_args() const;
     int advance(int64_t n, const RecordArgs* rec);
     int launch_epoch_sequence(const StepArgs& a, bool net, bool graph_mode);
+    int launch_classes(const StepArgs& a);
     int check_flags(bool& spikes_lost, bool& events_lost);
 };
 

@@ -144,6 +144,7 @@ def test_rejects_epoch_longer_than_min_delay():
 def test_rejects_bad_launch_parameters():
     _expect_einval(_ring(), "block_threads", block_threads=96)
     _expect_einval(_ring(), "coef_mode", coef_mode=4)
+    _expect_einval(_ring(), "gradients", coef_mode=3, flags=arbmi.ARB_FLAG_GRADIENTS)
 
 
 @pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")

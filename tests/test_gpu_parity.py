@@ -111,6 +111,24 @@ def test_edge_morphologies():
     check(m, 1200, probes=np.arange(int(gen.n_cvs(m).sum())))
 
 
+@pytest.mark.parametrize("coef_mode", [1, 2, 3])
+def test_clamps_on_passive_dendrites(coef_mode):
+    """Clamps on dendritic CVs without channels or synapses (inside a branch,
+    at a branch's proximal and distal ends), switching on and off, on short
+    branches that every kernel takes, padded branches included."""
+    cells = []
+    for k in range(3):
+        d = models.bare_cell(gen.full_binary_parents(3), [8, 5, 8, 3, 8, 1, 7] + [8] * 8,
+                             np.linspace(40, 160, 15), np.linspace(0.8, 2.4, 15))
+        d.clamps.append((2, 3, 10 + k, 500, 0.4))     # inside a branch
+        d.clamps.append((4, 0, 100, 700, -0.2))       # proximal CV
+        d.clamps.append((6, 6, 0, 300 + 50 * k, 0.3))  # distal CV
+        d.clamps.append((-1, 0, 200, 260, 0.5))       # soma
+        cells.append(d)
+    m = gen.assemble(cells, n_steps=900)
+    check(m, 900, probes=np.arange(int(gen.n_cvs(m).sum())), coef_mode=coef_mode, block_threads=64)
+
+
 def test_epoch_length_invariance_bitwise():
     m = gen.config2(n_cells=8, kick_all=False)
     probes = oracle.cell_cv_begin(m)[:-1]
