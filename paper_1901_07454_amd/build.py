@@ -12,6 +12,10 @@ SOURCES = ["kernels.hip", "reg_kernels.hip", "adjoint_kernels.hip", "arbmi.cpp",
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# The register-resident kernel holds its branches' coefficients in VGPRs for
+# a whole launch; hoisting the FP64 exp/expm1 polynomial constants out of the
+# step loop (machine LICM) would pin another ~40 VGPRs and cost occupancy.
+EXTRA = {"reg_kernels.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
 def build(verbose: bool = False) -> str:
@@ -22,7 +26,7 @@ def build(verbose: bool = False) -> str:
         if not os.path.exists(path):
             continue
         obj = os.path.join(HERE, "_build", src.replace(".", "_") + ".o")
-        cmd = ["hipcc", *FLAGS, "-c", path, "-o", obj]
+        cmd = ["hipcc", *FLAGS, *EXTRA.get(src, []), "-c", path, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             sys.stderr.write(r.stderr)

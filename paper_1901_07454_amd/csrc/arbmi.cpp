@@ -86,6 +86,8 @@ StepArgs Sim::step_args() const {
     a.rd = d_rd;
     a.tk = d_tk;
     a.ch_slot = d_ch;
+    a.ch_task = d_ch_task;
+    a.tk_ptask = d_tk_ptask;
     a.nl = d_nl;
     a.pc_gid = d_pc_gid;
     a.pc_soma = d_pc_soma;
@@ -374,6 +376,8 @@ int build_device(Sim* s) {
     s->d_rd = dupload(s, L.rounds, rc);
     s->d_tk = dupload(s, L.tasks, rc);
     s->d_ch = dupload(s, L.ch_slot, rc);
+    s->d_ch_task = dupload(s, L.ch_task, rc);
+    s->d_tk_ptask = dupload(s, L.tk_ptask, rc);
     s->d_nl = dupload(s, L.nl, rc);
     s->d_pc_gid = dupload(s, L.pc_gid, rc);
     s->d_pc_soma = dupload(s, L.pc_soma, rc);

@@ -53,7 +53,7 @@ uint64_t shape_key(const ModelView& m, const DeviceLimits& d) {
     for (uint64_t x : cv_hist) mix(x);
     mix(uint64_t(d.n_cu));
     mix(uint64_t(d.lds_max));
-    mix(4);  // version of the candidate set
+    mix(5);  // version of the candidate set and kernels
     return h;
 }
 
@@ -168,7 +168,7 @@ double time_candidate(const Sample& smp, const arb_params& base, const DeviceLim
         destroy_sim(s);
         return 0.0;
     }
-    const int warm = 10, timed = 60;
+    const int warm = 10, timed = 100;
     double rate = 0.0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
@@ -193,8 +193,9 @@ arb_params autotune(const ModelView& m, const arb_params& p, const DeviceLimits&
     const uint64_t key = shape_key(m, d);
     Candidate best{0, 0, 0};
     if (!cache_lookup(key, best)) {
-        // enough cells for several waves of workgroups on every CU
-        const Sample smp = make_sample(m, std::max(64, d.n_cu * 8));
+        // enough cells for several waves of workgroups on every CU, so that
+        // the last, partial wave weighs about as much as in the full model
+        const Sample smp = make_sample(m, std::max(64, d.n_cu * 32));
         int64_t max_width = 1;
         for (const arb_cell& C : smp.cells) {
             std::vector<int> depth(C.n_branch, 0), count(C.n_branch + 2, 0);

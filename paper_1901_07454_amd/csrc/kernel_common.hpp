@@ -32,6 +32,21 @@ __device__ inline Rates hh_rates(double v) {
     return r;
 }
 
+// The rates of hh_rates one at a time, with the same expressions (so the
+// same values), for spreading them over threads: the four built on exp
+// (w = 0..3: bm, ah, bh, bn) and the two built on exprelr (w = 0, 1: am, an).
+__device__ inline double hh_rate_exp(int w, double v) {
+    const double d = (w == 2) ? 35.0 : 65.0;
+    const double k = (w == 0) ? (1.0 / 18.0) : (w == 1) ? 0.05 : (w == 2) ? 0.1 : (1.0 / 80.0);
+    const double e = exp(-(v + d) * k);
+    if (w == 2) return 1.0 / (e + 1.0);
+    return ((w == 0) ? 4.0 : (w == 1) ? 0.07 : 0.125) * e;
+}
+__device__ inline double hh_rate_exprelr(int w, double v) {
+    const double r = exprelr(-(v + (w ? 55.0 : 40.0)) * 0.1);
+    return w ? 0.1 * r : r;
+}
+
 // exact update of a gate obeying x' = a(1-x) - b x at fixed V over dt
 __device__ inline double gate_step(double x, double a, double b, double dt) {
     const double s = a + b;

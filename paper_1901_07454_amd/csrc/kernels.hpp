@@ -14,6 +14,8 @@ struct StepArgs {
     const RoundDesc* rd;
     const TaskDesc* tk;
     const int32_t* ch_slot;
+    const int32_t* ch_task;    // per child entry: the child's pack-local task
+    const int32_t* tk_ptask;   // per task: the parent's pack-local task, -1 at a soma
     const NlDesc* nl;
     const int32_t* pc_gid;
     const int32_t* pc_soma;

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <map>
 #include <numeric>
 #include <sstream>
 
@@ -309,7 +310,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         std::vector<RoundPlan> rps;
         Shape sh;
         sh.ok = build_rounds(cs, rps);
-        for (const RoundPlan& rp : rps) sh.nslot += int64_t(rp.len) * int64_t(rp.items.size());
+        for (const RoundPlan& rp : rps) sh.nslot += int64_t(S > 0 ? opt.reg_len : rp.len) * int64_t(rp.items.size());
         sh.nrd = int64_t(rps.size());
         return sh;
     };
@@ -418,14 +419,21 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                         slot_of_user[cv0 + geo[it.c].first[it.b] + k] = slot_base + ns + int64_t(k) * int64_t(ri.size()) + int64_t(t);
                 }
             }
-            ns += int64_t(rp.len) * int64_t(ri.size());
+            // the register-resident kernel gives every branch reg_len rows: a
+            // shorter branch's spare rows take its pad CVs
+            ns += int64_t(S > 0 ? opt.reg_len : rp.len) * int64_t(ri.size());
             rds.push_back(R);
         }
         D.nslot = int32_t(ns);
         D.nrd = int32_t(rds.size());
         D.tk0 = int32_t(L.tasks.size());
         D.ch0 = int32_t(L.ch_slot.size());
-        // tasks (need every slot assigned first, for parents and children)
+        // tasks (need every slot assigned first, for parents and children).
+        // Rounds run deepest first, so a task's children already have their
+        // pack-local task index when the task is made; parents get theirs in
+        // a second pass.
+        std::map<std::pair<int32_t, int32_t>, int32_t> task_of;  // (cell, branch) -> pack-local task
+        std::vector<std::pair<int32_t, int32_t>> item_of;        // pack-local task -> (cell, branch)
         for (size_t r = 0; r < rds.size(); ++r) {
             rds[r].task0 = int32_t(L.tasks.size()) - D.tk0;  // pack-local task
             for (const Item& it : rps[r].items) {
@@ -438,11 +446,19 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                 for (int32_t b2 = 0; b2 < cells[it.c].n_branch; ++b2)
                     if (br[cells[it.c].branch_begin + b2].parent == it.b) {
                         L.ch_slot.push_back(int32_t(slot_of_user[cv0 + geo[it.c].first[b2]] - slot_base));
+                        L.ch_task.push_back(task_of.at({it.c, b2}));
                         T_.nch++;
                     }
+                task_of[{it.c, it.b}] = int32_t(L.tasks.size()) - D.tk0;
+                item_of.push_back({it.c, it.b});
                 L.tasks.push_back(T_);
             }
             L.rounds.push_back(rds[r]);
+        }
+        for (const auto& cb : item_of) {
+            const int32_t b = cb.second;
+            const int32_t pb = (b < 0) ? -2 : br[cells[cb.first].branch_begin + b].parent;
+            L.tk_ptask.push_back(pb == -2 ? -1 : task_of.at({cb.first, pb}));
         }
         D.ntk = int32_t(L.tasks.size()) - D.tk0;
         D.nch = int32_t(L.ch_slot.size()) - D.ch0;
@@ -644,6 +660,17 @@ std::string verify_layout(const Lowered& L) {
             if (int64_t(R.slot0) + int64_t(R.len) * R.w > D.nslot) return fmt("pack %zu round %d: slots overflow", pk, r);
             for (int64_t q = R.slot0; q < int64_t(R.slot0) + int64_t(R.len) * R.w; ++q) round_of_slot[q] = r;
         }
+        // first and last slot of every task of the pack
+        std::vector<int32_t> task_slot0(D.ntk, -1), task_last(D.ntk, -1);
+        for (int32_t r = 0; r < D.nrd; ++r) {
+            const RoundDesc& R = L.rounds[D.rd0 + r];
+            for (int i = 0; i < R.w; ++i) {
+                const int32_t t = R.task0 + i;
+                if (t < 0 || t >= D.ntk) return fmt("pack %zu round %d: task out of range", pk, r);
+                task_slot0[t] = R.slot0 + i;
+                task_last[t] = R.slot0 + (L.tasks[D.tk0 + t].len - 1) * R.w + i;
+            }
+        }
         std::vector<std::vector<char>> used(std::max(L.reg_slots, 1), std::vector<char>(L.block_threads, 0));
         for (int32_t r = 0; r < D.nrd; ++r) {
             const RoundDesc& R = L.rounds[D.rd0 + r];
@@ -661,7 +688,16 @@ std::string verify_layout(const Lowered& L) {
                     const int32_t cs = L.ch_slot[D.ch0 + T.ch0 + c];
                     if (cs < 0 || cs >= D.nslot || !(round_of_slot[cs] < r))
                         return fmt("pack %zu round %d: child not earlier", pk, r);
+                    // the child's task starts at that slot and names this task as its parent
+                    const int32_t ct = L.ch_task[D.ch0 + T.ch0 + c];
+                    if (ct < 0 || ct >= D.ntk || task_slot0[ct] != cs || L.tk_ptask[D.tk0 + ct] != R.task0 + i)
+                        return fmt("pack %zu round %d: child task does not match its slot", pk, r);
                 }
+                // the parent task's distal CV is the one this branch hangs from
+                const int32_t pt = L.tk_ptask[D.tk0 + R.task0 + i];
+                if ((pt < 0) != (T.par < 0)) return fmt("pack %zu round %d: parent task and slot disagree", pk, r);
+                if (pt >= 0 && (pt >= D.ntk || task_last[pt] != T.par))
+                    return fmt("pack %zu round %d: parent task does not end at the parent slot", pk, r);
             }
         }
     }

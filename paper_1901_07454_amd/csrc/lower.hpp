@@ -30,6 +30,8 @@ struct Lowered {
     std::vector<RoundDesc> rounds;
     std::vector<TaskDesc> tasks;
     std::vector<int32_t> ch_slot;
+    std::vector<int32_t> ch_task;     // per child entry: the child's pack-local task
+    std::vector<int32_t> tk_ptask;    // per task: the parent's pack-local task, -1 at a soma
     std::vector<NlDesc> nl;
     std::vector<int32_t> pc_gid, pc_soma;  // per pack cell: gid, pack-local soma slot
 

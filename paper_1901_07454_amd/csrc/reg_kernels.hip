@@ -1,25 +1,38 @@
 // reg_kernels.hip -- register-resident variant of the fused step kernel.
 //
-// Same scheme and phases as step_kernel (kernels.hip): events, point
-// currents, elimination by rounds (deepest first), substitution, states and
-// threshold.  Here each thread holds, for the whole launch, everything about
-// its branches that does not change between steps: the step coefficients
-// (alpha, F = u/d', 1/d'), the LDS offsets of the branch's CVs, of its
-// parent's CV and of its children's proximal CVs.  A thread owns up to S
-// branches of at most L CVs; the host gives every round one register slot j
-// on all of its threads, so the per-slot arrays are indexed with
-// compile-time constants.  The rounds themselves need no descriptor loads.
-// The kernel does not record states for the adjoint (the host refuses that).
+// Same phases as step_kernel (kernels.hip): events, point currents, the
+// Hines solve, states and threshold.  Each thread holds, for the whole
+// launch, everything about its branches that does not change between
+// steps: the step coefficients (alpha, F = u/d', 1/d') and where the
+// branch's CVs, its parent and its children live.  A thread owns up to S
+// branches of at most L CVs; the host gives every round one register slot
+// j on all of its threads, so the per-slot arrays are indexed with
+// compile-time constants.
+//
+// The solve of a branch is split so that only one multiply-add per branch
+// waits on the tree.  With the children's sum s and the parent's new V xp
+// as unknowns, the branch's recurrences are linear in them:
+//   rhs'_k = P_k - Q_k s,  F_0 rhs'_0 = F_0 P_0 - (F_0 Q_0) s,
+//   V_last = Y_last + Z xp,
+// where P and Y come from the branch's own CVs (all branches at once) and
+// F_0 Q_0 = F_0 prod_{k>=1}(-F_k), Z = prod_k(-F_k) are step-invariant.  So a
+// step runs: all branches' local elimination; rounds deepest first passing
+// the contributions up (one multiply-add per branch); all branches' full
+// elimination with their s and the local substitution; rounds shallowest
+// first passing the distal V down; all branches' substitution with xp.
+// The elimination and substitution themselves are the Hines recurrences of
+// the serial solve; only the values passed between branches are formed
+// through the split.
 //
 // LDS keeps V and R (the right-hand side) as interleaved pairs, so one
-// 128-bit load brings both operands of a CV; between a branch's elimination
-// and its substitution its V entries hold rhs'/d'.  R starts every step as beta
-// (the step-invariant part of the right-hand side); the point-current pass
-// writes beta - I at the CVs with currents, a branch's elimination leaves
-// F * rhs' of its proximal CV in that CV's R for the parent and its
-// substitution puts beta back.  A branch shorter than L is padded: the pad
-// CVs read a pair of zeros and carry the children's sum through unchanged
-// (F = -1, and +1 at the first pad), their results go to a discard pair.
+// 128-bit load brings both operands of a CV; R holds beta (the
+// step-invariant part of the right-hand side) minus the point currents.
+// Between the phases of the solve, a branch keeps its intermediate values
+// in its own V entries.  Every branch has L rows in the layout; a shorter
+// branch's spare rows hold pad CVs (alpha = beta = 1/d' = 0) that carry the
+// recurrences through unchanged (F = +1 at the first pad, -1 after it).
+// An empty register slot works on a spare pair past the pack's slots.
+// The kernel does not record states for the adjoint (the host refuses that).
 #include <hip/hip_runtime.h>
 
 #include "kernel_common.hpp"
@@ -41,98 +54,160 @@ __device__ __forceinline__ double ld_R(const char* vr, int off) {
 __device__ __forceinline__ void st_V(char* vr, int off, double x) { *reinterpret_cast<double*>(vr + off) = x; }
 __device__ __forceinline__ void st_R(char* vr, int off, double x) { *reinterpret_cast<double*>(vr + off + 8) = x; }
 
-// The registers of one branch slot.  Offsets are bytes into the pair array.
+// The registers of one branch slot.
 template <int L>
 struct Slot {
-    double A[L], F[L], D[L];        // alpha, F (pads: +1 then -1), 1/d' (pads: 0)
-    double B0;                      // beta of the proximal CV
-    int ea[L];                      // pairs of the CVs (pads: the zero pair)
-    int r;                          // round of the branch, -1 if the slot is empty
-    int len;
-    int par;                        // pair of the parent's CV (zero pair at a soma)
-    int c0, c1;                     // pairs of the first two children (zero pair if fewer)
-    int cx0, ncx;                   // further children: s_ch[cx0 .. cx0 + ncx)
+    double A[L], F[L], D[L];  // alpha, F (pads: +1 then -1), 1/d' (pads: 0)
+    double FQ;                // F_0 Q_0
+    double Z;                 // prod_k (-F_k)
+    double fp, cs, yl, xp;    // per step: F_0 P_0, children's sum, V_last with xp = 0, parent's V
+    int base, w, len;         // CV k of the branch is pair base + k w
+    int r;                    // round of the branch, -1 if the slot is empty
+    int task, ptask;          // own task, parent's task (none: a zero entry)
+    int c0, c1;               // first two children's tasks (a zero entry if fewer)
+    int cx0, ncx;             // further children: s_ch[cx0 .. cx0 + ncx)
 };
 
-// Elimination of one branch, distal to proximal:
-// rhs'_k = alpha_k V_k + R_k - F_{k+1} rhs'_{k+1}, the distal CV taking the
-// children's contributions instead of the last term.  V_k is not read again
-// before the substitution writes its new value, so rhs'_k / d'_k waits there.
+// byte offset of CV k's pair
 template <int L>
-__device__ __forceinline__ void elim(const Slot<L>& g, char* vr, const int32_t* s_ch, int discard) {
-    double2 p[L];
-#pragma unroll
-    for (int k = 0; k < L; ++k) p[k] = ld_pair(vr, g.ea[k]);
-    double csum = ld_R(vr, g.c0) + ld_R(vr, g.c1);
-    for (int q = 0; q < g.ncx; ++q) csum += ld_R(vr, 16 * s_ch[g.cx0 + q]);
-    double acc = (g.len == L) ? csum : -csum;
-#pragma unroll
-    for (int k = L - 1; k >= 0; --k) {
-        const double t = g.A[k] * p[k].x + p[k].y;
-        const double r = (k == L - 1) ? t - acc : t - g.F[(k + 1 < L) ? k + 1 : k] * acc;
-        st_V(vr, (k == 0 || k < g.len) ? g.ea[k] : discard, r * g.D[k]);
-        acc = r;
-    }
-    st_R(vr, g.ea[0], g.F[0] * acc);  // contribution to the parent's elimination
+__device__ __forceinline__ int cv_off(const Slot<L>& g, int k) {
+    return 16 * (g.base + k * g.w);
 }
 
-// Substitution of one branch, proximal to distal: V_k = rhs'_k/d'_k - F_k V_{k-1}
-// (V_{-1} the parent's CV); then beta back into R.
+// Local elimination (children's sum taken as 0): t_k = alpha_k V_k + R_k,
+// P_k = t_k - F_{k+1} P_{k+1}.  t waits in the V entries; F_0 P_0 is the
+// branch's contribution if it has no children.
 template <int L>
-__device__ __forceinline__ void subst(const Slot<L>& g, char* vr, int discard) {
-    double y[L];
+__device__ __forceinline__ void local_elim(Slot<L>& g, char* vr, double* sC) {
+    double t[L];
 #pragma unroll
-    for (int k = 0; k < L; ++k) y[k] = ld_V(vr, g.ea[k]);
-    double x = ld_V(vr, g.par);
+    for (int k = 0; k < L; ++k) {
+        const double2 p = ld_pair(vr, cv_off(g, k));
+        t[k] = g.A[k] * p.x + p.y;
+    }
+#pragma unroll
+    for (int k = 0; k < L; ++k) st_V(vr, cv_off(g, k), t[k]);
+    double acc = 0.0;
+#pragma unroll
+    for (int k = L - 1; k >= 0; --k) acc = (k == L - 1) ? t[k] : t[k] - g.F[(k + 1 < L) ? k + 1 : k] * acc;
+    g.fp = g.F[0] * acc;
+    sC[g.task] = g.fp;
+}
+
+// Full elimination with the children's sum, rhs'/d' into the V entries, and
+// the distal V for a grounded parent.
+template <int L>
+__device__ __forceinline__ void full_elim(Slot<L>& g, char* vr) {
+    double t[L], y[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) t[k] = ld_V(vr, cv_off(g, k));
+    double acc = (g.len == L) ? g.cs : -g.cs;
+#pragma unroll
+    for (int k = L - 1; k >= 0; --k) {
+        const double r = (k == L - 1) ? t[k] - acc : t[k] - g.F[(k + 1 < L) ? k + 1 : k] * acc;
+        y[k] = r * g.D[k];
+        acc = r;
+    }
+    double x = 0.0;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
         x = y[k] - g.F[k] * x;
-        st_V(vr, (k == 0 || k < g.len) ? g.ea[k] : discard, x);
+        st_V(vr, cv_off(g, k), y[k]);
     }
-    st_R(vr, g.ea[0], g.B0);
+    g.yl = (g.len == L) ? x : -x;
+}
+
+// Substitution with the parent's V: V_k = rhs'_k/d'_k - F_k V_{k-1}.
+template <int L>
+__device__ __forceinline__ void subst(const Slot<L>& g, char* vr) {
+    double y[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) y[k] = ld_V(vr, cv_off(g, k));
+    double x = g.xp;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        x = y[k] - g.F[k] * x;
+        st_V(vr, cv_off(g, k), x);
+    }
 }
 
 // Fill slot g with the branch this thread takes in round r of the pack (an
-// empty slot if r < 0).  Branch-free: an empty slot reads valid entries of
-// the pack and keeps neutral values.
+// empty slot, len 0, if r < 0).  Branch-free: an empty slot reads valid
+// entries of the pack and keeps neutral values.
 template <int L>
-__device__ __forceinline__ void load_slot(Slot<L>& g, const StepArgs& a, const PackDesc& pk, int r, int tid,
-                                          int zero) {
+__device__ __forceinline__ void load_slot(Slot<L>& g, const StepArgs& a, const PackDesc& pk, int r, int tid) {
     const bool has = r >= 0;
+    const int none = pk.ntk, dump = pk.ntk + 1;
     const RoundDesc R = a.rd[pk.rd0 + (has ? r : 0)];
     const int i = has ? round_index(R, tid) : 0;
-    const TaskDesc t = a.tk[pk.tk0 + (has ? R.task0 + i : 0)];
-    const int len = has ? t.len : 1;
-    const int base = has ? R.slot0 + i : 0;
-    const int w = has ? R.w : 0;
+    const int task = has ? R.task0 + i : 0;
+    const TaskDesc t = a.tk[pk.tk0 + task];
+    const int len = has ? t.len : 0;
     g.r = has ? r : -1;
     g.len = len;
-    g.par = (has && t.par >= 0) ? 16 * t.par : zero;
-    g.c0 = zero;
-    g.c1 = zero;
-    if (has && t.nch > 0) g.c0 = 16 * a.ch_slot[pk.ch0 + t.ch0];
-    if (has && t.nch > 1) g.c1 = 16 * a.ch_slot[pk.ch0 + t.ch0 + 1];
+    g.base = has ? R.slot0 + i : pk.nslot;
+    g.w = has ? R.w : 0;
+    g.task = has ? task : dump;
+    const int pt = a.tk_ptask[pk.tk0 + task];
+    g.ptask = (has && pt >= 0) ? pt : none;
+    g.c0 = none;
+    g.c1 = none;
+    if (has && t.nch > 0) g.c0 = a.ch_task[pk.ch0 + t.ch0];
+    if (has && t.nch > 1) g.c1 = a.ch_task[pk.ch0 + t.ch0 + 1];
     g.cx0 = t.ch0 + 2;
     g.ncx = has ? max(0, t.nch - 2) : 0;
+    double q = 1.0, z = 1.0;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-        const bool real = has && k < len;
-        const int loc = base + min(k, len - 1) * w;
-        const int64_t sl = pk.slot0 + loc;
+        const bool real = k < len;
+        const int64_t sl = pk.slot0 + (has ? g.base + int64_t(min(k, len - 1)) * g.w : 0);
         const double al = a.alpha[sl], f = a.F[sl], dv = a.invd[sl];
-        g.ea[k] = real ? 16 * loc : zero;
         g.A[k] = real ? al : 0.0;
         g.D[k] = real ? dv : 0.0;
         g.F[k] = real ? f : (k == len ? 1.0 : -1.0);
+        if (real) z *= -g.F[k];
+        if (real && k >= 1) q *= -g.F[k];
     }
-    const double b0 = a.beta[pk.slot0 + base];
-    g.B0 = has ? b0 : 0.0;
+    g.FQ = g.F[0] * q;
+    g.Z = z;
+    g.fp = 0.0;
+    g.cs = 0.0;
+    g.yl = 0.0;
+    g.xp = 0.0;
 }
 
-// Waves per SIMD the registers allow without spilling: three for one slot
-// of 8 CVs, two for two such slots, one otherwise.
+// Up round: the children's sum and this branch's contribution to its parent.
+template <int L>
+__device__ __forceinline__ void pass_up(Slot<L>& g, double* sC, const int32_t* s_ch) {
+    double cs = sC[g.c0] + sC[g.c1];
+    for (int q = 0; q < g.ncx; ++q) cs += sC[s_ch[g.cx0 + q]];
+    g.cs = cs;
+    sC[g.task] = g.fp - g.FQ * cs;
+}
+
+// Down round: the parent's V and this branch's distal V.
+template <int L>
+__device__ __forceinline__ void pass_down(Slot<L>& g, double* sX) {
+    g.xp = sX[g.ptask];
+    sX[g.task] = g.yl + g.Z * g.xp;
+}
+
+// End of a round of the tree passes.  A one-wave workgroup needs no
+// barrier and no wait: a wave's LDS operations take effect in issue order,
+// so the next round's loads see this round's stores.
+template <int T>
+__device__ __forceinline__ void round_sync() {
+    if constexpr (T == 64)
+        __builtin_amdgcn_wave_barrier();
+    else
+        __syncthreads();
+}
+
+// Waves per SIMD the registers allow without spilling (built without
+// machine loop-invariant code motion): three for one slot of 8 CVs, two for
+// 16 CVs in all, one otherwise.
 template <int T, int S, int L>
-__global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S == 2 && L == 8 ? 2 : 1)) reg_step_kernel(StepArgs a) {
+__global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) reg_step_kernel(StepArgs a) {
     extern __shared__ __align__(16) char lds_raw[];
     const int p = blockIdx.x + a.pack0;
     const PackDesc pk = a.pk[p];
@@ -140,9 +215,8 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S == 2 && L == 8 ? 2 : 
     const int ns = pk.nslot;
 
     // ---- LDS layout (the mode-3 layout of pack_lds_bytes) ----
-    char* vr = lds_raw;                                        // (V, R) pairs [ns + 2]
-    const int zero = 16 * ns, discard = 16 * (ns + 1);
-    double* sg = reinterpret_cast<double*>(vr + 16 * (ns + 2));
+    char* vr = lds_raw;                                        // (V, R) pairs [ns + 1]
+    double* sg = reinterpret_cast<double*>(vr + 16 * (ns + 1));
     double* s_se = sg + pk.nsyn;
     double* s_sdec = s_se + pk.nsyn;
     double* sm = s_sdec + pk.nsyn;
@@ -151,17 +225,22 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S == 2 && L == 8 ? 2 : 
     double* s_gna = sn + pk.nhh;
     double* s_gk = s_gna + pk.nhh;
     double* s_nlb = s_gk + pk.nhh;                             // beta of each nonlinear CV
-    NlDesc* s_nl = reinterpret_cast<NlDesc*>(s_nlb + pk.nnl);
-    int32_t* s_ch = reinterpret_cast<int32_t*>(s_nl + pk.nnl);
+    double* sC = s_nlb + pk.nnl;                               // per task [ntk + 2]: contribution, then distal V
+    double* sX = sC;
+    double* s_rate = sC + (pk.ntk + 2);                        // per hh instance: am, bm, ah, bh, an, bn
+    NlDesc* s_nl = reinterpret_cast<NlDesc*>(s_rate + (pk.nhh <= kSpreadHH ? 6 * pk.nhh : 0));
+    int32_t* s_ch = reinterpret_cast<int32_t*>(s_nl + pk.nnl);  // children's tasks
+    int32_t* s_hhs = s_ch + pk.nch;                            // per hh instance: its CV's pair
 
     for (int i = tid; i < ns; i += T) {
         st_V(vr, 16 * i, a.V[pk.slot0 + i]);
         st_R(vr, 16 * i, a.beta[pk.slot0 + i]);
     }
-    if (tid < 2) {
-        st_V(vr, zero + 16 * tid, 0.0);
-        st_R(vr, zero + 16 * tid, 0.0);
+    if (tid == 0) {
+        st_V(vr, 16 * ns, 0.0);
+        st_R(vr, 16 * ns, 0.0);
     }
+    if (tid < 2) sC[pk.ntk + tid] = 0.0;
     for (int i = tid; i < pk.nsyn; i += T) {
         sg[i] = a.syn_g[pk.syn0 + i];
         s_se[i] = a.syn_e[pk.syn0 + i];
@@ -178,8 +257,9 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S == 2 && L == 8 ? 2 : 
         const NlDesc d = a.nl[pk.nl0 + i];
         s_nl[i] = d;
         s_nlb[i] = a.beta[pk.slot0 + d.slot];
+        if (d.hh >= 0) s_hhs[d.hh] = 16 * d.slot;
     }
-    for (int i = tid; i < pk.nch; i += T) s_ch[i] = a.ch_slot[pk.ch0 + i];
+    for (int i = tid; i < pk.nch; i += T) s_ch[i] = a.ch_task[pk.ch0 + i];
 
     int64_t step0 = a.step0;
     int32_t bucket = a.bucket;
@@ -218,9 +298,9 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S == 2 && L == 8 ? 2 : 
         }
     }
     Slot<L> g0, g1, g2;
-    load_slot<L>(g0, a, pk, myr[0], tid, zero);
-    if constexpr (S > 1) load_slot<L>(g1, a, pk, myr[1], tid, zero);
-    if constexpr (S > 2) load_slot<L>(g2, a, pk, myr[2], tid, zero);
+    load_slot<L>(g0, a, pk, myr[0], tid);
+    if constexpr (S > 1) load_slot<L>(g1, a, pk, myr[1], tid);
+    if constexpr (S > 2) load_slot<L>(g2, a, pk, myr[2], tid);
     __syncthreads();
 
     for (int s = 0; s < a.nsteps; ++s) {
@@ -240,7 +320,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S == 2 && L == 8 ? 2 : 
                 xstep = (xcur < pk.xe1) ? a.xe_step[xcur] : INT64_MAX;
             }
         }
-        __syncthreads();
+        round_sync<T>();
 
         // B: R = beta - I at the CVs with nonlinear and point currents (V^n)
         for (int j = tid; j < pk.nnl; j += T) {
@@ -261,7 +341,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S == 2 && L == 8 ? 2 : 
         }
         if (soma >= 0) vold = ld_V(vr, soma);
         if (pk.nic > 0) {
-            __syncthreads();
+            round_sync<T>();
             if (tid == 0)
                 for (int q = pk.ic0; q < pk.ic0 + pk.nic; ++q)
                     if (a.ic_on[q] <= n && n < a.ic_off[q]) {
@@ -269,45 +349,67 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S == 2 && L == 8 ? 2 : 
                         st_R(vr, o, ld_R(vr, o) + a.ic_amp[q]);
                     }
         }
-        __syncthreads();
+        round_sync<T>();
 
-        // C: elimination, deepest rounds first
-        for (int r = 0; r < pk.nrd; ++r) {
-            if (g0.r == r) elim<L>(g0, vr, s_ch, discard);
+        // C: the solve
+        local_elim<L>(g0, vr, sC);
+        if constexpr (S > 1) local_elim<L>(g1, vr, sC);
+        if constexpr (S > 2) local_elim<L>(g2, vr, sC);
+        round_sync<T>();
+        for (int r = 0; r < pk.nrd; ++r) {  // contributions up, deepest rounds first
+            if (g0.r == r && g0.c0 != pk.ntk) pass_up<L>(g0, sC, s_ch);
             if constexpr (S > 1) {
-                if (g1.r == r) elim<L>(g1, vr, s_ch, discard);
+                if (g1.r == r && g1.c0 != pk.ntk) pass_up<L>(g1, sC, s_ch);
             }
             if constexpr (S > 2) {
-                if (g2.r == r) elim<L>(g2, vr, s_ch, discard);
+                if (g2.r == r && g2.c0 != pk.ntk) pass_up<L>(g2, sC, s_ch);
             }
-            __syncthreads();
+            round_sync<T>();
         }
-
-        // D: substitution, shallowest rounds first
-        for (int r = pk.nrd - 1; r >= 0; --r) {
-            if (g0.r == r) subst<L>(g0, vr, discard);
+        full_elim<L>(g0, vr);
+        if constexpr (S > 1) full_elim<L>(g1, vr);
+        if constexpr (S > 2) full_elim<L>(g2, vr);
+        for (int r = pk.nrd - 1; r >= 0; --r) {  // distal V down, shallowest rounds first
+            if (g0.r == r) pass_down<L>(g0, sX);
             if constexpr (S > 1) {
-                if (g1.r == r) subst<L>(g1, vr, discard);
+                if (g1.r == r) pass_down<L>(g1, sX);
             }
             if constexpr (S > 2) {
-                if (g2.r == r) subst<L>(g2, vr, discard);
+                if (g2.r == r) pass_down<L>(g2, sX);
             }
-            __syncthreads();
+            round_sync<T>();
         }
+        subst<L>(g0, vr);
+        if constexpr (S > 1) subst<L>(g1, vr);
+        if constexpr (S > 2) subst<L>(g2, vr);
+        round_sync<T>();
 
-        // E: states with V^{n+1}, threshold, probes
-        for (int j = tid; j < pk.nnl; j += T) {
-            const NlDesc d = s_nl[j];
-            if (d.hh >= 0) {
-                const int q = d.hh;
-                const Rates rt = hh_rates(ld_V(vr, 16 * d.slot));
+        // E: states with V^{n+1}; synapse decay; threshold.  A pack with few
+        // hh instances spreads each instance's six rates over six threads
+        // (exp-based and exprelr-based in separate passes) and its three
+        // gates over three; otherwise a thread takes a whole instance.
+        for (int j = tid; j < pk.nsyn; j += T) sg[j] *= s_sdec[j];
+        if (pk.nhh <= kSpreadHH) {
+            for (int j = tid; j < 4 * pk.nhh; j += T) {
+                const int q = j >> 2, w = j & 3;
+                s_rate[6 * q + ((w == 3) ? 5 : w + 1)] = hh_rate_exp(w, ld_V(vr, s_hhs[q]));  // bm, ah, bh, bn
+            }
+            for (int j = tid; j < 2 * pk.nhh; j += T) {
+                const int q = j >> 1, w = j & 1;
+                s_rate[6 * q + 4 * w] = hh_rate_exprelr(w, ld_V(vr, s_hhs[q]));  // am, an
+            }
+            round_sync<T>();
+            for (int j = tid; j < 3 * pk.nhh; j += T) {
+                const int q = j / 3, w = j - 3 * q;
+                double* x = (w == 0) ? sm : (w == 1) ? sh : sn;
+                x[q] = gate_step(x[q], s_rate[6 * q + 2 * w], s_rate[6 * q + 2 * w + 1], a.dt);
+            }
+        } else {
+            for (int q = tid; q < pk.nhh; q += T) {
+                const Rates rt = hh_rates(ld_V(vr, s_hhs[q]));
                 sm[q] = gate_step(sm[q], rt.am, rt.bm, a.dt);
                 sh[q] = gate_step(sh[q], rt.ah, rt.bh, a.dt);
                 sn[q] = gate_step(sn[q], rt.an, rt.bn, a.dt);
-            }
-            for (int k = 0; k < d.nsyn; ++k) {
-                const int q = d.syn0 + k;
-                sg[q] *= s_sdec[q];
             }
         }
         if (soma >= 0) {
@@ -329,7 +431,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S == 2 && L == 8 ? 2 : 
                 for (int j = tid; j < pk.npr; j += T)
                     a.trace[int64_t(a.pr_id[pk.pr0 + j]) * a.trace_cap + col] = ld_V(vr, 16 * a.pr_slot[pk.pr0 + j]);
         }
-        __syncthreads();
+        round_sync<T>();
     }
 
     for (int i = tid; i < ns; i += T) a.V[pk.slot0 + i] = ld_V(vr, 16 * i);

@@ -66,6 +66,8 @@ struct Sim : arb_sim_ {
     RoundDesc* d_rd = nullptr;
     TaskDesc* d_tk = nullptr;
     int32_t* d_ch = nullptr;
+    int32_t* d_ch_task = nullptr;
+    int32_t* d_tk_ptask = nullptr;
     NlDesc* d_nl = nullptr;
     int32_t *d_pc_gid = nullptr, *d_pc_soma = nullptr;
     double *d_V = nullptr, *d_alpha = nullptr, *d_beta = nullptr, *d_F = nullptr, *d_invd = nullptr;
