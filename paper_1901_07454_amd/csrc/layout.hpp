@@ -50,8 +50,9 @@ struct PackDesc {
 // m, h, n, [gNa, gK, e_syn, decay]; then rounds, tasks, nonlinear entries,
 // child slots.  Bracketed parts are staged only in coefficient mode 1 (mode 2
 // streams them).  The register-resident kernel (mode 3) keeps its branches'
-// descriptors in registers and stages: (V, R) pairs for every slot plus a
-// spare pair, g, e_syn, decay, m, h, n, gNa, gK, beta of each nonlinear CV,
+// descriptors in registers and stages: V and R for every slot plus a spare
+// slot, in blocks of 64 slots (64 V, 64 R), g, e_syn, decay, m, h, n, gNa,
+// gK, beta of each nonlinear CV,
 // one per-task scalar (a branch's contribution to its parent in the upward
 // pass, its distal V in the downward one) with two spare entries, the six
 // rates of each hh instance (packs of at most kSpreadHH instances), the
@@ -63,7 +64,7 @@ constexpr int kSpreadHH = 10;
 inline int64_t pack_lds_bytes(const PackDesc& D, int coef_mode) {
     if (coef_mode == 3) {
         const int64_t rates = (D.nhh <= kSpreadHH) ? 6 * int64_t(D.nhh) : 0;
-        const int64_t dbl = 2 * (int64_t(D.nslot) + 1) + 3 * int64_t(D.nsyn) + 5 * int64_t(D.nhh) + rates +
+        const int64_t dbl = 128 * ((int64_t(D.nslot) + 64) / 64) + 3 * int64_t(D.nsyn) + 5 * int64_t(D.nhh) + rates +
                             int64_t(D.nnl) + (int64_t(D.ntk) + 2);
         return 8 * dbl + 16 * int64_t(D.nnl) + 4 * int64_t(D.nch) + 4 * int64_t(D.nhh);
     }

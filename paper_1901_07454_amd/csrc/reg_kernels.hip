@@ -24,14 +24,15 @@
 // the serial solve; only the values passed between branches are formed
 // through the split.
 //
-// LDS keeps V and R (the right-hand side) as interleaved pairs, so one
-// 128-bit load brings both operands of a CV; R holds beta (the
-// step-invariant part of the right-hand side) minus the point currents.
+// LDS keeps V and R (the right-hand side) per slot, in blocks of 64 slots
+// (64 V then 64 R): V-only accesses of consecutive slots are 8 bytes apart
+// and R is a fixed offset from V.  R holds beta (the step-invariant part of
+// the right-hand side) minus the point currents.
 // Between the phases of the solve, a branch keeps its intermediate values
 // in its own V entries.  Every branch has L rows in the layout; a shorter
 // branch's spare rows hold pad CVs (alpha = beta = 1/d' = 0) that carry the
 // recurrences through unchanged (F = +1 at the first pad, -1 after it).
-// An empty register slot works on a spare pair past the pack's slots.
+// An empty register slot works on a spare slot past the pack's slots.
 // The kernel does not record states for the adjoint (the host refuses that).
 #include <hip/hip_runtime.h>
 
@@ -44,16 +45,6 @@ namespace {
 
 using namespace dev;
 
-__device__ __forceinline__ double2 ld_pair(const char* vr, int off) {
-    return *reinterpret_cast<const double2*>(vr + off);
-}
-__device__ __forceinline__ double ld_V(const char* vr, int off) { return *reinterpret_cast<const double*>(vr + off); }
-__device__ __forceinline__ double ld_R(const char* vr, int off) {
-    return *reinterpret_cast<const double*>(vr + off + 8);
-}
-__device__ __forceinline__ void st_V(char* vr, int off, double x) { *reinterpret_cast<double*>(vr + off) = x; }
-__device__ __forceinline__ void st_R(char* vr, int off, double x) { *reinterpret_cast<double*>(vr + off + 8) = x; }
-
 // The registers of one branch slot.
 template <int L>
 struct Slot {
@@ -61,32 +52,35 @@ struct Slot {
     double FQ;                // F_0 Q_0
     double Z;                 // prod_k (-F_k)
     double fp, cs, yl, xp;    // per step: F_0 P_0, children's sum, V_last with xp = 0, parent's V
-    int base, w, len;         // CV k of the branch is pair base + k w
+    int base, w, len;         // CV k of the branch is slot base + k w
     int r;                    // round of the branch, -1 if the slot is empty
     int task, ptask;          // own task, parent's task (none: a zero entry)
     int c0, c1;               // first two children's tasks (a zero entry if fewer)
     int cx0, ncx;             // further children: s_ch[cx0 .. cx0 + ncx)
 };
 
-// byte offset of CV k's pair
+// V and R sit in blocks of 64 slots: 64 V, then the same slots' 64 R.  So
+// consecutive slots are 8 bytes apart (no bank conflicts for V alone) and R
+// is a fixed 512 bytes past V.
+__device__ __forceinline__ int vix(int slot) { return slot + (slot & ~63); }
+constexpr int kRoff = 64;
+
+// V index of the branch's CV k
 template <int L>
-__device__ __forceinline__ int cv_off(const Slot<L>& g, int k) {
-    return 16 * (g.base + k * g.w);
+__device__ __forceinline__ int cv_slot(const Slot<L>& g, int k) {
+    return vix(g.base + k * g.w);
 }
 
 // Local elimination (children's sum taken as 0): t_k = alpha_k V_k + R_k,
 // P_k = t_k - F_{k+1} P_{k+1}.  t waits in the V entries; F_0 P_0 is the
 // branch's contribution if it has no children.
 template <int L>
-__device__ __forceinline__ void local_elim(Slot<L>& g, char* vr, double* sC) {
+__device__ __forceinline__ void local_elim(Slot<L>& g, double* sV, double* sC) {
     double t[L];
 #pragma unroll
-    for (int k = 0; k < L; ++k) {
-        const double2 p = ld_pair(vr, cv_off(g, k));
-        t[k] = g.A[k] * p.x + p.y;
-    }
+    for (int k = 0; k < L; ++k) t[k] = g.A[k] * sV[cv_slot(g, k)] + sV[cv_slot(g, k) + kRoff];
 #pragma unroll
-    for (int k = 0; k < L; ++k) st_V(vr, cv_off(g, k), t[k]);
+    for (int k = 0; k < L; ++k) sV[cv_slot(g, k)] = t[k];
     double acc = 0.0;
 #pragma unroll
     for (int k = L - 1; k >= 0; --k) acc = (k == L - 1) ? t[k] : t[k] - g.F[(k + 1 < L) ? k + 1 : k] * acc;
@@ -97,10 +91,10 @@ __device__ __forceinline__ void local_elim(Slot<L>& g, char* vr, double* sC) {
 // Full elimination with the children's sum, rhs'/d' into the V entries, and
 // the distal V for a grounded parent.
 template <int L>
-__device__ __forceinline__ void full_elim(Slot<L>& g, char* vr) {
+__device__ __forceinline__ void full_elim(Slot<L>& g, double* sV) {
     double t[L], y[L];
 #pragma unroll
-    for (int k = 0; k < L; ++k) t[k] = ld_V(vr, cv_off(g, k));
+    for (int k = 0; k < L; ++k) t[k] = sV[cv_slot(g, k)];
     double acc = (g.len == L) ? g.cs : -g.cs;
 #pragma unroll
     for (int k = L - 1; k >= 0; --k) {
@@ -112,22 +106,22 @@ __device__ __forceinline__ void full_elim(Slot<L>& g, char* vr) {
 #pragma unroll
     for (int k = 0; k < L; ++k) {
         x = y[k] - g.F[k] * x;
-        st_V(vr, cv_off(g, k), y[k]);
+        sV[cv_slot(g, k)] = y[k];
     }
     g.yl = (g.len == L) ? x : -x;
 }
 
 // Substitution with the parent's V: V_k = rhs'_k/d'_k - F_k V_{k-1}.
 template <int L>
-__device__ __forceinline__ void subst(const Slot<L>& g, char* vr) {
+__device__ __forceinline__ void subst(const Slot<L>& g, double* sV) {
     double y[L];
 #pragma unroll
-    for (int k = 0; k < L; ++k) y[k] = ld_V(vr, cv_off(g, k));
+    for (int k = 0; k < L; ++k) y[k] = sV[cv_slot(g, k)];
     double x = g.xp;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
         x = y[k] - g.F[k] * x;
-        st_V(vr, cv_off(g, k), x);
+        sV[cv_slot(g, k)] = x;
     }
 }
 
@@ -215,8 +209,8 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     const int ns = pk.nslot;
 
     // ---- LDS layout (the mode-3 layout of pack_lds_bytes) ----
-    char* vr = lds_raw;                                        // (V, R) pairs [ns + 1]
-    double* sg = reinterpret_cast<double*>(vr + 16 * (ns + 1));
+    double* sV = reinterpret_cast<double*>(lds_raw);           // V and R blocks for ns + 1 slots
+    double* sg = sV + 128 * ((ns + 64) / 64);
     double* s_se = sg + pk.nsyn;
     double* s_sdec = s_se + pk.nsyn;
     double* sm = s_sdec + pk.nsyn;
@@ -233,12 +227,12 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     int32_t* s_hhs = s_ch + pk.nch;                            // per hh instance: its CV's pair
 
     for (int i = tid; i < ns; i += T) {
-        st_V(vr, 16 * i, a.V[pk.slot0 + i]);
-        st_R(vr, 16 * i, a.beta[pk.slot0 + i]);
+        sV[vix(i)] = a.V[pk.slot0 + i];
+        sV[vix(i) + kRoff] = a.beta[pk.slot0 + i];
     }
     if (tid == 0) {
-        st_V(vr, 16 * ns, 0.0);
-        st_R(vr, 16 * ns, 0.0);
+        sV[vix(ns)] = 0.0;
+        sV[vix(ns) + kRoff] = 0.0;
     }
     if (tid < 2) sC[pk.ntk + tid] = 0.0;
     for (int i = tid; i < pk.nsyn; i += T) {
@@ -257,7 +251,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         const NlDesc d = a.nl[pk.nl0 + i];
         s_nl[i] = d;
         s_nlb[i] = a.beta[pk.slot0 + d.slot];
-        if (d.hh >= 0) s_hhs[d.hh] = 16 * d.slot;
+        if (d.hh >= 0) s_hhs[d.hh] = vix(d.slot);
     }
     for (int i = tid; i < pk.nch; i += T) s_ch[i] = a.ch_task[pk.ch0 + i];
 
@@ -282,7 +276,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         if (ncur < nend) nkey = ev[ncur];
         if (xcur < pk.xe1) xstep = a.xe_step[xcur];
     }
-    const int soma = (tid < pk.ncell) ? 16 * a.pc_soma[pk.cell0 + tid] : -1;
+    const int soma = (tid < pk.ncell) ? vix(a.pc_soma[pk.cell0 + tid]) : -1;
     double vold = 0.0;
 
     // this thread's round in each register slot, then its branches
@@ -325,7 +319,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         // B: R = beta - I at the CVs with nonlinear and point currents (V^n)
         for (int j = tid; j < pk.nnl; j += T) {
             const NlDesc d = s_nl[j];
-            const double v = ld_V(vr, 16 * d.slot);
+            const double v = sV[vix(d.slot)];
             double I = 0.0;
             if (d.hh >= 0) {
                 const int q = d.hh;
@@ -337,24 +331,23 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
                 const int q = d.syn0 + k;
                 I += sg[q] * (v - s_se[q]);
             }
-            st_R(vr, 16 * d.slot, s_nlb[j] - I);
+            sV[vix(d.slot) + kRoff] = s_nlb[j] - I;
         }
-        if (soma >= 0) vold = ld_V(vr, soma);
+        if (soma >= 0) vold = sV[soma];
         if (pk.nic > 0) {
             round_sync<T>();
             if (tid == 0)
                 for (int q = pk.ic0; q < pk.ic0 + pk.nic; ++q)
                     if (a.ic_on[q] <= n && n < a.ic_off[q]) {
-                        const int o = 16 * a.ic_slot[q];
-                        st_R(vr, o, ld_R(vr, o) + a.ic_amp[q]);
+                        sV[vix(a.ic_slot[q]) + kRoff] += a.ic_amp[q];
                     }
         }
         round_sync<T>();
 
         // C: the solve
-        local_elim<L>(g0, vr, sC);
-        if constexpr (S > 1) local_elim<L>(g1, vr, sC);
-        if constexpr (S > 2) local_elim<L>(g2, vr, sC);
+        local_elim<L>(g0, sV, sC);
+        if constexpr (S > 1) local_elim<L>(g1, sV, sC);
+        if constexpr (S > 2) local_elim<L>(g2, sV, sC);
         round_sync<T>();
         for (int r = 0; r < pk.nrd; ++r) {  // contributions up, deepest rounds first
             if (g0.r == r && g0.c0 != pk.ntk) pass_up<L>(g0, sC, s_ch);
@@ -366,9 +359,9 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
             }
             round_sync<T>();
         }
-        full_elim<L>(g0, vr);
-        if constexpr (S > 1) full_elim<L>(g1, vr);
-        if constexpr (S > 2) full_elim<L>(g2, vr);
+        full_elim<L>(g0, sV);
+        if constexpr (S > 1) full_elim<L>(g1, sV);
+        if constexpr (S > 2) full_elim<L>(g2, sV);
         for (int r = pk.nrd - 1; r >= 0; --r) {  // distal V down, shallowest rounds first
             if (g0.r == r) pass_down<L>(g0, sX);
             if constexpr (S > 1) {
@@ -379,9 +372,9 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
             }
             round_sync<T>();
         }
-        subst<L>(g0, vr);
-        if constexpr (S > 1) subst<L>(g1, vr);
-        if constexpr (S > 2) subst<L>(g2, vr);
+        subst<L>(g0, sV);
+        if constexpr (S > 1) subst<L>(g1, sV);
+        if constexpr (S > 2) subst<L>(g2, sV);
         round_sync<T>();
 
         // E: states with V^{n+1}; synapse decay; threshold.  A pack with few
@@ -392,11 +385,11 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         if (pk.nhh <= kSpreadHH) {
             for (int j = tid; j < 4 * pk.nhh; j += T) {
                 const int q = j >> 2, w = j & 3;
-                s_rate[6 * q + ((w == 3) ? 5 : w + 1)] = hh_rate_exp(w, ld_V(vr, s_hhs[q]));  // bm, ah, bh, bn
+                s_rate[6 * q + ((w == 3) ? 5 : w + 1)] = hh_rate_exp(w, sV[s_hhs[q]]);  // bm, ah, bh, bn
             }
             for (int j = tid; j < 2 * pk.nhh; j += T) {
                 const int q = j >> 1, w = j & 1;
-                s_rate[6 * q + 4 * w] = hh_rate_exprelr(w, ld_V(vr, s_hhs[q]));  // am, an
+                s_rate[6 * q + 4 * w] = hh_rate_exprelr(w, sV[s_hhs[q]]);  // am, an
             }
             round_sync<T>();
             for (int j = tid; j < 3 * pk.nhh; j += T) {
@@ -406,14 +399,14 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
             }
         } else {
             for (int q = tid; q < pk.nhh; q += T) {
-                const Rates rt = hh_rates(ld_V(vr, s_hhs[q]));
+                const Rates rt = hh_rates(sV[s_hhs[q]]);
                 sm[q] = gate_step(sm[q], rt.am, rt.bm, a.dt);
                 sh[q] = gate_step(sh[q], rt.ah, rt.bh, a.dt);
                 sn[q] = gate_step(sn[q], rt.an, rt.bn, a.dt);
             }
         }
         if (soma >= 0) {
-            const double vnew = ld_V(vr, soma);
+            const double vnew = sV[soma];
             if (vold < a.threshold && vnew >= a.threshold) {
                 const uint32_t pos = atomicAdd(&a.ctr->sp_count, 1u);
                 if (pos < a.sp_cap) {
@@ -429,12 +422,12 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
             const int64_t col = n - a.trace_step0;
             if (col >= 0 && col < a.trace_cap)
                 for (int j = tid; j < pk.npr; j += T)
-                    a.trace[int64_t(a.pr_id[pk.pr0 + j]) * a.trace_cap + col] = ld_V(vr, 16 * a.pr_slot[pk.pr0 + j]);
+                    a.trace[int64_t(a.pr_id[pk.pr0 + j]) * a.trace_cap + col] = sV[vix(a.pr_slot[pk.pr0 + j])];
         }
         round_sync<T>();
     }
 
-    for (int i = tid; i < ns; i += T) a.V[pk.slot0 + i] = ld_V(vr, 16 * i);
+    for (int i = tid; i < ns; i += T) a.V[pk.slot0 + i] = sV[vix(i)];
     for (int i = tid; i < pk.nsyn; i += T) a.syn_g[pk.syn0 + i] = sg[i];
     for (int i = tid; i < pk.nhh; i += T) {
         a.hh_m[pk.hh0 + i] = sm[i];
