@@ -22,6 +22,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64
+
+# Algorithmic FP64 operations per step (a transcendental or a division counts
+# as one): a CV's assembly (alpha V + R), elimination and substitution with
+# the step-invariant factorisation take 7; an hh instance's current (14), six
+# rates (26) and three gate updates (21) take 61; an expsyn's current and
+# decay take 4.
+FLOPS_PER_CV, FLOPS_PER_HH, FLOPS_PER_SYN = 7, 61, 4
 
 
 def log(*a):
@@ -237,6 +245,8 @@ def main():
     avg_launch_s = kms / 1e3 / max(nlaunch, 1)
     bytes_per_launch = info["bytes_per_step"] * steps_per_launch
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    flops_per_step = FLOPS_PER_CV * n_cv + FLOPS_PER_HH * info["n_hh"] + FLOPS_PER_SYN * info["n_syn"]
+    tflops = flops_per_step * steps_per_launch / avg_launch_s / 1e12
     kernel = kernel_name(info)
     traffic = measured_traffic(args.traffic_json, args.config, kernel, steps_per_launch)
     copy_gbps = copy_bandwidth_gbps(torch)
@@ -261,7 +271,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": kernel, "bytes_per_step": info["bytes_per_step"],
                      "steps_per_launch": steps_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
-                     "measured_copy_GBps": copy_gbps},
+                     "measured_copy_GBps": copy_gbps, "frac_of_measured_copy": achieved / copy_gbps,
+                     "note": ("achieved = per-step algorithmic bytes x steps per launch / launch time; one "
+                              "launch runs a whole epoch with voltages, states and coefficients held in "
+                              "LDS and registers, so it moves far fewer bytes than the per-step model "
+                              "(see traffic) and the model's rate can be exceeded"),
+                     "alu": {"achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": tflops / FP64_PEAK_TFLOPS, "flops_per_step": flops_per_step}},
     }
     sim.close()
     if not args.no_grad:
