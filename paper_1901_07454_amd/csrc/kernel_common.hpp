@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "fastexp.hpp"
 #include "layout.hpp"
 
 namespace arbmi {
@@ -32,19 +33,34 @@ __device__ inline Rates hh_rates(double v) {
     return r;
 }
 
-// The rates of hh_rates one at a time, with the same expressions (so the
-// same values), for spreading them over threads: the four built on exp
-// (w = 0..3: bm, ah, bh, bn) and the two built on exprelr (w = 0, 1: am, an).
-__device__ inline double hh_rate_exp(int w, double v) {
-    const double d = (w == 2) ? 35.0 : 65.0;
-    const double k = (w == 0) ? (1.0 / 18.0) : (w == 1) ? 0.05 : (w == 2) ? 0.1 : (1.0 / 80.0);
-    const double e = exp(-(v + d) * k);
-    if (w == 2) return 1.0 / (e + 1.0);
-    return ((w == 0) ? 4.0 : (w == 1) ? 0.07 : 0.125) * e;
+// The two rates of one gate of hh_rates (w = 0, 1, 2: m, h, n), with the
+// same expressions, for giving each gate its own thread; e^x and e^x - 1 come
+// from exp_pair (a shorter dependency chain than the library's, within 2 ulp
+// of it).  Both candidate forms of alpha (exprelr-based for m and n,
+// exp-based for h) come from the one exp_pair of its argument and one is
+// kept, so every thread runs the same straight-line code; the per-gate
+// constants go through an empty asm so that the compiler does not specialise
+// the code for each constant.
+__device__ inline double opaque(double x) {
+    asm volatile("" : "+v"(x));
+    return x;
 }
-__device__ inline double hh_rate_exprelr(int w, double v) {
-    const double r = exprelr(-(v + (w ? 55.0 : 40.0)) * 0.1);
-    return w ? 0.1 * r : r;
+__device__ inline void hh_gate_rates(int w, double v, double& alpha, double& beta) {
+    const double xa = -(v + opaque((w == 0) ? 40.0 : (w == 1) ? 65.0 : 55.0)) * opaque((w == 1) ? 0.05 : 0.1);
+    const ExpPair pa = exp_pair(xa);
+    const double er = (1.0 + xa == 1.0) ? 1.0 : xa / pa.em1;  // exprelr(xa)
+    alpha = (w == 1) ? 0.07 * pa.e : (w == 2) ? 0.1 * er : er;
+    const double xb = -(v + opaque((w == 1) ? 35.0 : 65.0)) *
+                      opaque((w == 0) ? (1.0 / 18.0) : (w == 1) ? 0.1 : (1.0 / 80.0));
+    const double eb = exp_pair(xb).e;
+    beta = (w == 1) ? 1.0 / (eb + 1.0) : ((w == 0) ? 4.0 : 0.125) * eb;
+}
+
+// gate_step with e^x from exp_pair
+__device__ inline double gate_step_pair(double x, double a, double b, double dt) {
+    const double s = a + b;
+    const double xinf = a / s;
+    return xinf + (x - xinf) * exp_pair(-dt * s).e;
 }
 
 // exact update of a gate obeying x' = a(1-x) - b x at fixed V over dt

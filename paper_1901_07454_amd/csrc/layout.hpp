@@ -54,17 +54,15 @@ struct PackDesc {
 // slot, in blocks of 64 slots (64 V, 64 R), g, e_syn, decay, m, h, n, gNa,
 // gK, beta of each nonlinear CV,
 // one per-task scalar (a branch's contribution to its parent in the upward
-// pass, its distal V in the downward one) with two spare entries, the six
-// rates of each hh instance (packs of at most kSpreadHH instances), the
+// pass, its distal V in the downward one) with two spare entries, the
 // nonlinear entries, the children's tasks and the slot of each hh instance.
-// Packs with at most this many hh instances spread each instance's rates
-// over threads in the register-resident kernel (and keep the rates in LDS).
-constexpr int kSpreadHH = 10;
+// Packs with at most this many hh instances give each gate its own thread
+// in the register-resident kernel.
+constexpr int kSpreadHH = 20;
 
 inline int64_t pack_lds_bytes(const PackDesc& D, int coef_mode) {
     if (coef_mode == 3) {
-        const int64_t rates = (D.nhh <= kSpreadHH) ? 6 * int64_t(D.nhh) : 0;
-        const int64_t dbl = 128 * ((int64_t(D.nslot) + 64) / 64) + 3 * int64_t(D.nsyn) + 5 * int64_t(D.nhh) + rates +
+        const int64_t dbl = 128 * ((int64_t(D.nslot) + 64) / 64) + 3 * int64_t(D.nsyn) + 5 * int64_t(D.nhh) +
                             int64_t(D.nnl) + (int64_t(D.ntk) + 2);
         return 8 * dbl + 16 * int64_t(D.nnl) + 4 * int64_t(D.nch) + 4 * int64_t(D.nhh);
     }

@@ -71,57 +71,68 @@ __device__ __forceinline__ int cv_slot(const Slot<L>& g, int k) {
     return vix(g.base + k * g.w);
 }
 
+// The three all-branch parts of the solve, each split into loads, arithmetic
+// and stores so that the kernel can issue every slot's loads before any
+// slot's stores (LDS stores may alias later loads, so the compiler keeps
+// them in source order) and overlap the slots' recurrences.
+
 // Local elimination (children's sum taken as 0): t_k = alpha_k V_k + R_k,
 // P_k = t_k - F_{k+1} P_{k+1}.  t waits in the V entries; F_0 P_0 is the
 // branch's contribution if it has no children.
 template <int L>
-__device__ __forceinline__ void local_elim(Slot<L>& g, double* sV, double* sC) {
-    double t[L];
+__device__ __forceinline__ void local_load(const Slot<L>& g, const double* sV, double* t) {
 #pragma unroll
     for (int k = 0; k < L; ++k) t[k] = g.A[k] * sV[cv_slot(g, k)] + sV[cv_slot(g, k) + kRoff];
-#pragma unroll
-    for (int k = 0; k < L; ++k) sV[cv_slot(g, k)] = t[k];
+}
+template <int L>
+__device__ __forceinline__ void local_chain(Slot<L>& g, const double* t) {
     double acc = 0.0;
 #pragma unroll
     for (int k = L - 1; k >= 0; --k) acc = (k == L - 1) ? t[k] : t[k] - g.F[(k + 1 < L) ? k + 1 : k] * acc;
     g.fp = g.F[0] * acc;
+}
+template <int L>
+__device__ __forceinline__ void local_store(const Slot<L>& g, double* sV, double* sC, const double* t) {
+#pragma unroll
+    for (int k = 0; k < L; ++k) sV[cv_slot(g, k)] = t[k];
     sC[g.task] = g.fp;
 }
 
-// Full elimination with the children's sum, rhs'/d' into the V entries, and
-// the distal V for a grounded parent.
+// Full elimination with the children's sum (t becomes rhs'/d', which goes to
+// the V entries), and the distal V for a grounded parent.
 template <int L>
-__device__ __forceinline__ void full_elim(Slot<L>& g, double* sV) {
-    double t[L], y[L];
+__device__ __forceinline__ void load_v(const Slot<L>& g, const double* sV, double* t) {
 #pragma unroll
     for (int k = 0; k < L; ++k) t[k] = sV[cv_slot(g, k)];
+}
+template <int L>
+__device__ __forceinline__ void full_chain(Slot<L>& g, double* t) {
     double acc = (g.len == L) ? g.cs : -g.cs;
 #pragma unroll
     for (int k = L - 1; k >= 0; --k) {
         const double r = (k == L - 1) ? t[k] - acc : t[k] - g.F[(k + 1 < L) ? k + 1 : k] * acc;
-        y[k] = r * g.D[k];
+        t[k] = r * g.D[k];
         acc = r;
     }
     double x = 0.0;
 #pragma unroll
-    for (int k = 0; k < L; ++k) {
-        x = y[k] - g.F[k] * x;
-        sV[cv_slot(g, k)] = y[k];
-    }
+    for (int k = 0; k < L; ++k) x = t[k] - g.F[k] * x;
     g.yl = (g.len == L) ? x : -x;
+}
+template <int L>
+__device__ __forceinline__ void store_v(const Slot<L>& g, double* sV, const double* t) {
+#pragma unroll
+    for (int k = 0; k < L; ++k) sV[cv_slot(g, k)] = t[k];
 }
 
 // Substitution with the parent's V: V_k = rhs'_k/d'_k - F_k V_{k-1}.
 template <int L>
-__device__ __forceinline__ void subst(const Slot<L>& g, double* sV) {
-    double y[L];
-#pragma unroll
-    for (int k = 0; k < L; ++k) y[k] = sV[cv_slot(g, k)];
+__device__ __forceinline__ void subst_chain(const Slot<L>& g, double* y) {
     double x = g.xp;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
         x = y[k] - g.F[k] * x;
-        sV[cv_slot(g, k)] = x;
+        y[k] = x;
     }
 }
 
@@ -221,8 +232,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     double* s_nlb = s_gk + pk.nhh;                             // beta of each nonlinear CV
     double* sC = s_nlb + pk.nnl;                               // per task [ntk + 2]: contribution, then distal V
     double* sX = sC;
-    double* s_rate = sC + (pk.ntk + 2);                        // per hh instance: am, bm, ah, bh, an, bn
-    NlDesc* s_nl = reinterpret_cast<NlDesc*>(s_rate + (pk.nhh <= kSpreadHH ? 6 * pk.nhh : 0));
+    NlDesc* s_nl = reinterpret_cast<NlDesc*>(sC + (pk.ntk + 2));
     int32_t* s_ch = reinterpret_cast<int32_t*>(s_nl + pk.nnl);  // children's tasks
     int32_t* s_hhs = s_ch + pk.nch;                            // per hh instance: its CV's pair
 
@@ -345,9 +355,18 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         round_sync<T>();
 
         // C: the solve
-        local_elim<L>(g0, sV, sC);
-        if constexpr (S > 1) local_elim<L>(g1, sV, sC);
-        if constexpr (S > 2) local_elim<L>(g2, sV, sC);
+        {
+            double b0[L], b1[L], b2[L];
+            local_load<L>(g0, sV, b0);
+            if constexpr (S > 1) local_load<L>(g1, sV, b1);
+            if constexpr (S > 2) local_load<L>(g2, sV, b2);
+            local_chain<L>(g0, b0);
+            if constexpr (S > 1) local_chain<L>(g1, b1);
+            if constexpr (S > 2) local_chain<L>(g2, b2);
+            local_store<L>(g0, sV, sC, b0);
+            if constexpr (S > 1) local_store<L>(g1, sV, sC, b1);
+            if constexpr (S > 2) local_store<L>(g2, sV, sC, b2);
+        }
         round_sync<T>();
         for (int r = 0; r < pk.nrd; ++r) {  // contributions up, deepest rounds first
             if (g0.r == r && g0.c0 != pk.ntk) pass_up<L>(g0, sC, s_ch);
@@ -359,9 +378,18 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
             }
             round_sync<T>();
         }
-        full_elim<L>(g0, sV);
-        if constexpr (S > 1) full_elim<L>(g1, sV);
-        if constexpr (S > 2) full_elim<L>(g2, sV);
+        {
+            double b0[L], b1[L], b2[L];
+            load_v<L>(g0, sV, b0);
+            if constexpr (S > 1) load_v<L>(g1, sV, b1);
+            if constexpr (S > 2) load_v<L>(g2, sV, b2);
+            full_chain<L>(g0, b0);
+            if constexpr (S > 1) full_chain<L>(g1, b1);
+            if constexpr (S > 2) full_chain<L>(g2, b2);
+            store_v<L>(g0, sV, b0);
+            if constexpr (S > 1) store_v<L>(g1, sV, b1);
+            if constexpr (S > 2) store_v<L>(g2, sV, b2);
+        }
         for (int r = pk.nrd - 1; r >= 0; --r) {  // distal V down, shallowest rounds first
             if (g0.r == r) pass_down<L>(g0, sX);
             if constexpr (S > 1) {
@@ -372,30 +400,32 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
             }
             round_sync<T>();
         }
-        subst<L>(g0, sV);
-        if constexpr (S > 1) subst<L>(g1, sV);
-        if constexpr (S > 2) subst<L>(g2, sV);
+        {
+            double b0[L], b1[L], b2[L];
+            load_v<L>(g0, sV, b0);
+            if constexpr (S > 1) load_v<L>(g1, sV, b1);
+            if constexpr (S > 2) load_v<L>(g2, sV, b2);
+            subst_chain<L>(g0, b0);
+            if constexpr (S > 1) subst_chain<L>(g1, b1);
+            if constexpr (S > 2) subst_chain<L>(g2, b2);
+            store_v<L>(g0, sV, b0);
+            if constexpr (S > 1) store_v<L>(g1, sV, b1);
+            if constexpr (S > 2) store_v<L>(g2, sV, b2);
+        }
         round_sync<T>();
 
         // E: states with V^{n+1}; synapse decay; threshold.  A pack with few
-        // hh instances spreads each instance's six rates over six threads
-        // (exp-based and exprelr-based in separate passes) and its three
-        // gates over three; otherwise a thread takes a whole instance.
+        // hh instances gives each gate of an instance its own thread (which
+        // computes that gate's two rates and the update); otherwise a thread
+        // takes a whole instance.
         for (int j = tid; j < pk.nsyn; j += T) sg[j] *= s_sdec[j];
         if (pk.nhh <= kSpreadHH) {
-            for (int j = tid; j < 4 * pk.nhh; j += T) {
-                const int q = j >> 2, w = j & 3;
-                s_rate[6 * q + ((w == 3) ? 5 : w + 1)] = hh_rate_exp(w, sV[s_hhs[q]]);  // bm, ah, bh, bn
-            }
-            for (int j = tid; j < 2 * pk.nhh; j += T) {
-                const int q = j >> 1, w = j & 1;
-                s_rate[6 * q + 4 * w] = hh_rate_exprelr(w, sV[s_hhs[q]]);  // am, an
-            }
-            round_sync<T>();
             for (int j = tid; j < 3 * pk.nhh; j += T) {
                 const int q = j / 3, w = j - 3 * q;
+                double al, be;
+                hh_gate_rates(w, sV[s_hhs[q]], al, be);
                 double* x = (w == 0) ? sm : (w == 1) ? sh : sn;
-                x[q] = gate_step(x[q], s_rate[6 * q + 2 * w], s_rate[6 * q + 2 * w + 1], a.dt);
+                x[q] = gate_step_pair(x[q], al, be, a.dt);
             }
         } else {
             for (int q = tid; q < pk.nhh; q += T) {
