@@ -88,6 +88,8 @@ StepArgs Sim::step_args() const {
     a.ch_slot = d_ch;
     a.ch_task = d_ch_task;
     a.tk_ptask = d_tk_ptask;
+    a.tk_lev = d_tk_lev;
+    a.tk_Z = d_tk_Z;
     a.nl = d_nl;
     a.pc_gid = d_pc_gid;
     a.pc_soma = d_pc_soma;
@@ -378,6 +380,8 @@ int build_device(Sim* s) {
     s->d_ch = dupload(s, L.ch_slot, rc);
     s->d_ch_task = dupload(s, L.ch_task, rc);
     s->d_tk_ptask = dupload(s, L.tk_ptask, rc);
+    s->d_tk_lev = dupload(s, L.tk_lev, rc);
+    s->d_tk_Z = dupload(s, L.tk_Z, rc);
     s->d_nl = dupload(s, L.nl, rc);
     s->d_pc_gid = dupload(s, L.pc_gid, rc);
     s->d_pc_soma = dupload(s, L.pc_soma, rc);

@@ -16,6 +16,8 @@ struct StepArgs {
     const int32_t* ch_slot;
     const int32_t* ch_task;    // per child entry: the child's pack-local task
     const int32_t* tk_ptask;   // per task: the parent's pack-local task, -1 at a soma
+    const int32_t* tk_lev;     // per task: depth level (the soma is 0)
+    const double* tk_Z;        // per task: prod over its CVs of (-F)
     const NlDesc* nl;
     const int32_t* pc_gid;
     const int32_t* pc_soma;

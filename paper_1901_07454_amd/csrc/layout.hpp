@@ -12,6 +12,7 @@
 // Rounds are stored deepest first: the elimination sweep runs them in order
 // and the substitution sweep in reverse.
 #pragma once
+#include <algorithm>
 #include <stdint.h>
 
 namespace arbmi {
@@ -42,6 +43,8 @@ struct PackDesc {
     int32_t nch;
     int32_t ic0;     // first clamp entry
     int32_t nic;
+    int32_t spare;   // register-resident layout: a slot no CV uses (a pad row, or nslot)
+    int32_t nlev;    // depth levels of the pack's cells (the soma is level 0)
     int64_t xe0, xe1; // external events [xe0, xe1), sorted by (step, syn, input order)
 };
 
@@ -50,20 +53,29 @@ struct PackDesc {
 // m, h, n, [gNa, gK, e_syn, decay]; then rounds, tasks, nonlinear entries,
 // child slots.  Bracketed parts are staged only in coefficient mode 1 (mode 2
 // streams them).  The register-resident kernel (mode 3) keeps its branches'
-// descriptors in registers and stages: V and R for every slot plus a spare
-// slot, in blocks of 64 slots (64 V, 64 R), g, e_syn, decay, m, h, n, gNa,
-// gK, beta of each nonlinear CV,
-// one per-task scalar (a branch's contribution to its parent in the upward
-// pass, its distal V in the downward one) with two spare entries, the
-// nonlinear entries, the children's tasks and the slot of each hh instance.
+// descriptors in registers and stages: V and R for every slot (and the
+// spare slot, when it lies past them), in blocks of 64 slots (64 V, 64 R),
+// g, e_syn, decay, m, h, n, gNa, gK, beta of each nonlinear CV, two per-task
+// scalars with two spare entries each (a branch's contribution to its parent
+// in the upward pass, then its distal V; and its distal V for a grounded
+// parent), the nonlinear entries, the children's tasks and the slot of each
+// hh instance.
+
 // Packs with at most this many hh instances give each gate its own thread
 // in the register-resident kernel.
 constexpr int kSpreadHH = 20;
 
+// Doubles of the register-resident kernel's V and R blocks (64 V then 64 R per
+// 64 slots) for a pack: every slot and the spare slot.  The kernel and the
+// LDS accounting below both use this.
+constexpr int vr_block_doubles(int nslot, int spare) {
+    return 128 * (((nslot > spare + 1 ? nslot : spare + 1) + 63) / 64);
+}
+
 inline int64_t pack_lds_bytes(const PackDesc& D, int coef_mode) {
     if (coef_mode == 3) {
-        const int64_t dbl = 128 * ((int64_t(D.nslot) + 64) / 64) + 3 * int64_t(D.nsyn) + 5 * int64_t(D.nhh) +
-                            int64_t(D.nnl) + (int64_t(D.ntk) + 2);
+        const int64_t dbl = vr_block_doubles(D.nslot, D.spare) + 3 * int64_t(D.nsyn) + 5 * int64_t(D.nhh) +
+                            int64_t(D.nnl) + 2 * (int64_t(D.ntk) + 2);
         return 8 * dbl + 16 * int64_t(D.nnl) + 4 * int64_t(D.nch) + 4 * int64_t(D.nhh);
     }
     const bool cl = coef_mode == 1;

@@ -305,17 +305,18 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         }
         return true;
     };
-    struct Shape { int64_t nslot = 0, nrd = 0; bool ok = true; };
+    struct Shape { int64_t nslot = 0, nrd = 0; bool ok = true, has_pad = false; };
     auto plan_shape = [&](const std::vector<int32_t>& cs) -> Shape {
         std::vector<RoundPlan> rps;
         Shape sh;
         sh.ok = build_rounds(cs, rps);
-        for (const RoundPlan& rp : rps) sh.nslot += int64_t(S > 0 ? opt.reg_len : rp.len) * int64_t(rp.items.size());
+        for (const RoundPlan& rp : rps) {
+            sh.nslot += int64_t(S > 0 ? opt.reg_len : rp.len) * int64_t(rp.items.size());
+            for (const Item& it : rp.items) sh.has_pad = sh.has_pad || (S > 0 && it.len < opt.reg_len);
+        }
         sh.nrd = int64_t(rps.size());
         return sh;
     };
-    auto plan_slots = [&](const std::vector<int32_t>& cs) -> int64_t { return plan_shape(cs).nslot; };
-    (void)plan_slots;
     // CVs carrying hh or synapses, per cell
     std::vector<int32_t> nnl_cell(n_cells, 0);
     for (int32_t c = 0; c < n_cells; ++c)
@@ -325,6 +326,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         if (!sh.ok) return int64_t(1) << 40;  // does not fit the register slots
         PackDesc D{};
         D.nslot = int32_t(sh.nslot);
+        D.spare = sh.has_pad ? 0 : D.nslot;
         D.nrd = int32_t(sh.nrd);
         D.ntk = int32_t(pp.nbr + int64_t(pp.cells.size()));
         D.nch = int32_t(pp.nbr);
@@ -426,6 +428,19 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         }
         D.nslot = int32_t(ns);
         D.nrd = int32_t(rds.size());
+        D.nlev = maxd + 1;
+        // the register-resident kernel's empty slots write to a slot no CV
+        // uses: the first pad row if there is one, else one past the end
+        D.spare = D.nslot;
+        if (S > 0) {
+            int64_t at = 0;
+            for (const RoundPlan& rp : rps) {
+                const int64_t w = int64_t(rp.items.size());
+                for (int64_t t = 0; t < w && D.spare == D.nslot; ++t)
+                    if (rp.items[t].len < opt.reg_len) D.spare = int32_t(at + int64_t(rp.items[t].len) * w + t);
+                at += int64_t(opt.reg_len) * w;
+            }
+        }
         D.tk0 = int32_t(L.tasks.size());
         D.ch0 = int32_t(L.ch_slot.size());
         // tasks (need every slot assigned first, for parents and children).
@@ -459,6 +474,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             const int32_t b = cb.second;
             const int32_t pb = (b < 0) ? -2 : br[cells[cb.first].branch_begin + b].parent;
             L.tk_ptask.push_back(pb == -2 ? -1 : task_of.at({cb.first, pb}));
+            L.tk_lev.push_back(b < 0 ? 0 : geo[cb.first].depth[b]);
         }
         D.ntk = int32_t(L.tasks.size()) - D.tk0;
         D.nch = int32_t(L.ch_slot.size()) - D.ch0;
@@ -501,6 +517,18 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             L.invd[s] = 1.0 / d[i];
         }
     }
+    // per task: Z = prod_k (-F_k) over its CVs, proximal to distal
+    L.tk_Z.assign(L.tasks.size(), 1.0);
+    for (const PackDesc& D : L.packs)
+        for (int32_t r = 0; r < D.nrd; ++r) {
+            const RoundDesc& R = L.rounds[D.rd0 + r];
+            for (int32_t i = 0; i < R.w; ++i) {
+                const int64_t t = int64_t(D.tk0) + R.task0 + i;
+                double z = 1.0;
+                for (int32_t k = 0; k < L.tasks[t].len; ++k) z *= -L.F[D.slot0 + R.slot0 + int64_t(k) * R.w + i];
+                L.tk_Z[t] = z;
+            }
+        }
 
     // ------------------------------------------- nonlinear CVs per pack
     std::vector<std::vector<int64_t>> syn_at(L.n_cv), ic_at(L.n_cv);
@@ -660,6 +688,15 @@ std::string verify_layout(const Lowered& L) {
             if (int64_t(R.slot0) + int64_t(R.len) * R.w > D.nslot) return fmt("pack %zu round %d: slots overflow", pk, r);
             for (int64_t q = R.slot0; q < int64_t(R.slot0) + int64_t(R.len) * R.w; ++q) round_of_slot[q] = r;
         }
+        if (L.reg_slots > 0) {
+            if (D.spare < 0 || D.spare > D.nslot) return fmt("pack %zu: spare slot out of range", pk);
+            if (D.spare < D.nslot && round_of_slot[D.spare] >= 0) {
+                // inside a round: it must be a pad row of that round's branch
+                const RoundDesc& R = L.rounds[D.rd0 + round_of_slot[D.spare]];
+                const int32_t i = (D.spare - R.slot0) % R.w, k = (D.spare - R.slot0) / R.w;
+                if (k < L.tasks[D.tk0 + R.task0 + i].len) return fmt("pack %zu: spare slot holds a CV", pk);
+            }
+        }
         // first and last slot of every task of the pack
         std::vector<int32_t> task_slot0(D.ntk, -1), task_last(D.ntk, -1);
         for (int32_t r = 0; r < D.nrd; ++r) {
@@ -693,8 +730,12 @@ std::string verify_layout(const Lowered& L) {
                     if (ct < 0 || ct >= D.ntk || task_slot0[ct] != cs || L.tk_ptask[D.tk0 + ct] != R.task0 + i)
                         return fmt("pack %zu round %d: child task does not match its slot", pk, r);
                 }
-                // the parent task's distal CV is the one this branch hangs from
+                // the parent task's distal CV is the one this branch hangs from,
+                // one level up
                 const int32_t pt = L.tk_ptask[D.tk0 + R.task0 + i];
+                const int32_t lv = L.tk_lev[D.tk0 + R.task0 + i];
+                if (lv < 0 || lv >= D.nlev || (pt >= 0 && L.tk_lev[D.tk0 + pt] != lv - 1) || (pt < 0 && lv != 0))
+                    return fmt("pack %zu round %d: bad task level", pk, r);
                 if ((pt < 0) != (T.par < 0)) return fmt("pack %zu round %d: parent task and slot disagree", pk, r);
                 if (pt >= 0 && (pt >= D.ntk || task_last[pt] != T.par))
                     return fmt("pack %zu round %d: parent task does not end at the parent slot", pk, r);

@@ -32,6 +32,8 @@ struct Lowered {
     std::vector<int32_t> ch_slot;
     std::vector<int32_t> ch_task;     // per child entry: the child's pack-local task
     std::vector<int32_t> tk_ptask;    // per task: the parent's pack-local task, -1 at a soma
+    std::vector<int32_t> tk_lev;      // per task: depth level (the soma is 0)
+    std::vector<double> tk_Z;         // per task: prod over its CVs of (-F), the distal V's weight on the parent's
     std::vector<NlDesc> nl;
     std::vector<int32_t> pc_gid, pc_soma;  // per pack cell: gid, pack-local soma slot
 

@@ -19,7 +19,9 @@
 // step runs: all branches' local elimination; rounds deepest first passing
 // the contributions up (one multiply-add per branch); all branches' full
 // elimination with their s and the local substitution; rounds shallowest
-// first passing the distal V down; all branches' substitution with xp.
+// first passing the distal V down, two tree levels a round (a branch forms
+// its parent's V from its grandparent's: x_p = Y_p + Z_p x_gp); all
+// branches' substitution with xp.
 // The elimination and substitution themselves are the Hines recurrences of
 // the serial solve; only the values passed between branches are formed
 // through the split.
@@ -32,7 +34,8 @@
 // in its own V entries.  Every branch has L rows in the layout; a shorter
 // branch's spare rows hold pad CVs (alpha = beta = 1/d' = 0) that carry the
 // recurrences through unchanged (F = +1 at the first pad, -1 after it).
-// An empty register slot works on a spare slot past the pack's slots.
+// An empty register slot works on a slot no CV uses (a pad row, or one past
+// the pack's slots).
 // The kernel does not record states for the adjoint (the host refuses that).
 #include <hip/hip_runtime.h>
 
@@ -50,11 +53,12 @@ template <int L>
 struct Slot {
     double A[L], F[L], D[L];  // alpha, F (pads: +1 then -1), 1/d' (pads: 0)
     double FQ;                // F_0 Q_0
-    double Z;                 // prod_k (-F_k)
+    double Z, Zp;             // prod_k (-F_k) of this branch and of its parent
     double fp, cs, yl, xp;    // per step: F_0 P_0, children's sum, V_last with xp = 0, parent's V
     int base, w, len;         // CV k of the branch is slot base + k w
     int r;                    // round of the branch, -1 if the slot is empty
-    int task, ptask;          // own task, parent's task (none: a zero entry)
+    int lev;                  // depth level (the soma is 0)
+    int task, ptask, gptask;  // own, parent's and grandparent's task (none: a zero entry)
     int c0, c1;               // first two children's tasks (a zero entry if fewer)
     int cx0, ncx;             // further children: s_ch[cx0 .. cx0 + ncx)
 };
@@ -150,11 +154,15 @@ __device__ __forceinline__ void load_slot(Slot<L>& g, const StepArgs& a, const P
     const int len = has ? t.len : 0;
     g.r = has ? r : -1;
     g.len = len;
-    g.base = has ? R.slot0 + i : pk.nslot;
+    g.base = has ? R.slot0 + i : pk.spare;
     g.w = has ? R.w : 0;
     g.task = has ? task : dump;
     const int pt = a.tk_ptask[pk.tk0 + task];
     g.ptask = (has && pt >= 0) ? pt : none;
+    const int gpt = (g.ptask != none) ? a.tk_ptask[pk.tk0 + g.ptask] : -1;
+    g.gptask = (gpt >= 0) ? gpt : none;
+    g.lev = has ? a.tk_lev[pk.tk0 + task] : -1;
+    g.Zp = (g.ptask != none) ? a.tk_Z[pk.tk0 + g.ptask] : 0.0;
     g.c0 = none;
     g.c1 = none;
     if (has && t.nch > 0) g.c0 = a.ch_task[pk.ch0 + t.ch0];
@@ -174,7 +182,7 @@ __device__ __forceinline__ void load_slot(Slot<L>& g, const StepArgs& a, const P
         if (real && k >= 1) q *= -g.F[k];
     }
     g.FQ = g.F[0] * q;
-    g.Z = z;
+    g.Z = has ? a.tk_Z[pk.tk0 + task] : z;
     g.fp = 0.0;
     g.cs = 0.0;
     g.yl = 0.0;
@@ -190,10 +198,12 @@ __device__ __forceinline__ void pass_up(Slot<L>& g, double* sC, const int32_t* s
     sC[g.task] = g.fp - g.FQ * cs;
 }
 
-// Down round: the parent's V and this branch's distal V.
+// Down round, two levels at a time: the parent's V from the grandparent's
+// (x_p = Y_p + Z_p x_gp, so a branch and its parent can take the same round),
+// then this branch's distal V.
 template <int L>
-__device__ __forceinline__ void pass_down(Slot<L>& g, double* sX) {
-    g.xp = sX[g.ptask];
+__device__ __forceinline__ void pass_down(Slot<L>& g, const double* sY, double* sX) {
+    g.xp = sY[g.ptask] + g.Zp * sX[g.gptask];
     sX[g.task] = g.yl + g.Z * g.xp;
 }
 
@@ -220,8 +230,8 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     const int ns = pk.nslot;
 
     // ---- LDS layout (the mode-3 layout of pack_lds_bytes) ----
-    double* sV = reinterpret_cast<double*>(lds_raw);           // V and R blocks for ns + 1 slots
-    double* sg = sV + 128 * ((ns + 64) / 64);
+    double* sV = reinterpret_cast<double*>(lds_raw);           // V and R blocks (pack_lds_bytes)
+    double* sg = sV + vr_block_doubles(ns, pk.spare);
     double* s_se = sg + pk.nsyn;
     double* s_sdec = s_se + pk.nsyn;
     double* sm = s_sdec + pk.nsyn;
@@ -232,7 +242,8 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     double* s_nlb = s_gk + pk.nhh;                             // beta of each nonlinear CV
     double* sC = s_nlb + pk.nnl;                               // per task [ntk + 2]: contribution, then distal V
     double* sX = sC;
-    NlDesc* s_nl = reinterpret_cast<NlDesc*>(sC + (pk.ntk + 2));
+    double* sY = sC + (pk.ntk + 2);                            // per task [ntk + 2]: distal V for a grounded parent
+    NlDesc* s_nl = reinterpret_cast<NlDesc*>(sY + (pk.ntk + 2));
     int32_t* s_ch = reinterpret_cast<int32_t*>(s_nl + pk.nnl);  // children's tasks
     int32_t* s_hhs = s_ch + pk.nch;                            // per hh instance: its CV's pair
 
@@ -240,11 +251,14 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         sV[vix(i)] = a.V[pk.slot0 + i];
         sV[vix(i) + kRoff] = a.beta[pk.slot0 + i];
     }
-    if (tid == 0) {
+    if (tid == 0 && pk.spare == ns) {
         sV[vix(ns)] = 0.0;
         sV[vix(ns) + kRoff] = 0.0;
     }
-    if (tid < 2) sC[pk.ntk + tid] = 0.0;
+    if (tid < 2) {
+        sC[pk.ntk + tid] = 0.0;
+        sY[pk.ntk + tid] = 0.0;
+    }
     for (int i = tid; i < pk.nsyn; i += T) {
         sg[i] = a.syn_g[pk.syn0 + i];
         s_se[i] = a.syn_e[pk.syn0 + i];
@@ -389,14 +403,18 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
             store_v<L>(g0, sV, b0);
             if constexpr (S > 1) store_v<L>(g1, sV, b1);
             if constexpr (S > 2) store_v<L>(g2, sV, b2);
+            sY[g0.task] = g0.yl;
+            if constexpr (S > 1) sY[g1.task] = g1.yl;
+            if constexpr (S > 2) sY[g2.task] = g2.yl;
         }
-        for (int r = pk.nrd - 1; r >= 0; --r) {  // distal V down, shallowest rounds first
-            if (g0.r == r) pass_down<L>(g0, sX);
+        round_sync<T>();
+        for (int sr = 0; 2 * sr < pk.nlev; ++sr) {  // distal V down, two levels a round, shallowest first
+            if ((g0.lev >> 1) == sr) pass_down<L>(g0, sY, sX);
             if constexpr (S > 1) {
-                if (g1.r == r) pass_down<L>(g1, sX);
+                if ((g1.lev >> 1) == sr) pass_down<L>(g1, sY, sX);
             }
             if constexpr (S > 2) {
-                if (g2.r == r) pass_down<L>(g2, sX);
+                if ((g2.lev >> 1) == sr) pass_down<L>(g2, sY, sX);
             }
             round_sync<T>();
         }

@@ -68,6 +68,8 @@ struct Sim : arb_sim_ {
     int32_t* d_ch = nullptr;
     int32_t* d_ch_task = nullptr;
     int32_t* d_tk_ptask = nullptr;
+    int32_t* d_tk_lev = nullptr;
+    double* d_tk_Z = nullptr;
     NlDesc* d_nl = nullptr;
     int32_t *d_pc_gid = nullptr, *d_pc_soma = nullptr;
     double *d_V = nullptr, *d_alpha = nullptr, *d_beta = nullptr, *d_F = nullptr, *d_invd = nullptr;
