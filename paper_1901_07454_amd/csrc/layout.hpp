@@ -45,6 +45,8 @@ struct PackDesc {
     int32_t nic;
     int32_t spare;   // register-resident layout: a slot no CV uses (a pad row, or nslot)
     int32_t nlev;    // depth levels of the pack's cells (the soma is level 0)
+    int32_t binary;  // 1 if no task of the pack has more than two children
+    int32_t unused;
     int64_t xe0, xe1; // external events [xe0, xe1), sorted by (step, syn, input order)
 };
 
@@ -55,11 +57,12 @@ struct PackDesc {
 // streams them).  The register-resident kernel (mode 3) keeps its branches'
 // descriptors in registers and stages: V and R for every slot (and the
 // spare slot, when it lies past them), in blocks of 64 slots (64 V, 64 R),
-// g, e_syn, decay, m, h, n, gNa, gK, beta of each nonlinear CV, two per-task
-// scalars with two spare entries each (a branch's contribution to its parent
-// in the upward pass, then its distal V; and its distal V for a grounded
-// parent), the nonlinear entries, the children's tasks and the slot of each
-// hh instance.
+// g, e_syn, decay, m, h, n, gNa, gK, beta of each nonlinear CV, per-task
+// scalars with two spare entries each (a branch's contribution to its parent,
+// then its distal V; its contribution with no children, then its distal V
+// for a grounded parent; in packs of at most binary branch points, F_0 Q_0),
+// the nonlinear entries, the children's tasks (other packs) and the slot of
+// each hh instance.
 
 // Packs with at most this many hh instances give each gate its own thread
 // in the register-resident kernel.
@@ -75,8 +78,8 @@ constexpr int vr_block_doubles(int nslot, int spare) {
 inline int64_t pack_lds_bytes(const PackDesc& D, int coef_mode) {
     if (coef_mode == 3) {
         const int64_t dbl = vr_block_doubles(D.nslot, D.spare) + 3 * int64_t(D.nsyn) + 5 * int64_t(D.nhh) +
-                            int64_t(D.nnl) + 2 * (int64_t(D.ntk) + 2);
-        return 8 * dbl + 16 * int64_t(D.nnl) + 4 * int64_t(D.nch) + 4 * int64_t(D.nhh);
+                            int64_t(D.nnl) + (D.binary ? 3 : 2) * (int64_t(D.ntk) + 2);
+        return 8 * dbl + 16 * int64_t(D.nnl) + (D.binary ? 0 : 4 * int64_t(D.nch)) + 4 * int64_t(D.nhh);
     }
     const bool cl = coef_mode == 1;
     const int64_t dbl = (cl ? 6 : 2) * int64_t(D.nslot) + int64_t(D.nsyn) + 3 * int64_t(D.nhh) +

@@ -305,6 +305,13 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         }
         return true;
     };
+    // most children of any task (soma or branch) of each cell
+    std::vector<int32_t> max_children(n_cells, 0);
+    for (int32_t c = 0; c < n_cells; ++c) {
+        std::vector<int32_t> nch(cells[c].n_branch + 1, 0);  // [0] = soma, [b + 1] = branch b
+        for (int32_t b = 0; b < cells[c].n_branch; ++b) nch[br[cells[c].branch_begin + b].parent + 1]++;
+        for (int32_t v : nch) max_children[c] = std::max(max_children[c], v);
+    }
     struct Shape { int64_t nslot = 0, nrd = 0; bool ok = true, has_pad = false; };
     auto plan_shape = [&](const std::vector<int32_t>& cs) -> Shape {
         std::vector<RoundPlan> rps;
@@ -327,6 +334,8 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         PackDesc D{};
         D.nslot = int32_t(sh.nslot);
         D.spare = sh.has_pad ? 0 : D.nslot;
+        D.binary = 1;
+        for (int32_t c : pp.cells) D.binary = D.binary && max_children[c] <= 2;
         D.nrd = int32_t(sh.nrd);
         D.ntk = int32_t(pp.nbr + int64_t(pp.cells.size()));
         D.nch = int32_t(pp.nbr);
@@ -429,6 +438,8 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         D.nslot = int32_t(ns);
         D.nrd = int32_t(rds.size());
         D.nlev = maxd + 1;
+        D.binary = 1;
+        for (int32_t c : pp.cells) D.binary = D.binary && max_children[c] <= 2;
         // the register-resident kernel's empty slots write to a slot no CV
         // uses: the first pad row if there is one, else one past the end
         D.spare = D.nslot;
@@ -689,6 +700,9 @@ std::string verify_layout(const Lowered& L) {
             for (int64_t q = R.slot0; q < int64_t(R.slot0) + int64_t(R.len) * R.w; ++q) round_of_slot[q] = r;
         }
         if (L.reg_slots > 0) {
+            if (D.ntk + 2 > 65535) return fmt("pack %zu: too many tasks for the register layout", pk);
+            for (int32_t t = 0; t < D.ntk && D.binary; ++t)
+                if (L.tasks[D.tk0 + t].nch > 2) return fmt("pack %zu: binary flag with a wider branch point", pk);
             if (D.spare < 0 || D.spare > D.nslot) return fmt("pack %zu: spare slot out of range", pk);
             if (D.spare < D.nslot && round_of_slot[D.spare] >= 0) {
                 // inside a round: it must be a pad row of that round's branch

@@ -60,7 +60,9 @@ struct Slot {
     int lev;                  // depth level (the soma is 0)
     int task, ptask, gptask;  // own, parent's and grandparent's task (none: a zero entry)
     int c0, c1;               // first two children's tasks (a zero entry if fewer)
-    int cx0, ncx;             // further children: s_ch[cx0 .. cx0 + ncx)
+    int x0, x1;               // binary packs: grandchildren's tasks, two 16-bit fields each
+                              // (children of c0, of c1); other packs: further children
+                              // s_ch[x0 .. x0 + x1)
 };
 
 // V and R sit in blocks of 64 slots: 64 V, then the same slots' 64 R.  So
@@ -96,10 +98,11 @@ __device__ __forceinline__ void local_chain(Slot<L>& g, const double* t) {
     g.fp = g.F[0] * acc;
 }
 template <int L>
-__device__ __forceinline__ void local_store(const Slot<L>& g, double* sV, double* sC, const double* t) {
+__device__ __forceinline__ void local_store(const Slot<L>& g, double* sV, double* sC, double* sF, const double* t) {
 #pragma unroll
     for (int k = 0; k < L; ++k) sV[cv_slot(g, k)] = t[k];
     sC[g.task] = g.fp;
+    sF[g.task] = g.fp;
 }
 
 // Full elimination with the children's sum (t becomes rhs'/d', which goes to
@@ -161,14 +164,29 @@ __device__ __forceinline__ void load_slot(Slot<L>& g, const StepArgs& a, const P
     g.ptask = (has && pt >= 0) ? pt : none;
     const int gpt = (g.ptask != none) ? a.tk_ptask[pk.tk0 + g.ptask] : -1;
     g.gptask = (gpt >= 0) ? gpt : none;
-    g.lev = has ? a.tk_lev[pk.tk0 + task] : -1;
+    g.lev = has ? a.tk_lev[pk.tk0 + task] : -1000;  // empty: no round matches
     g.Zp = (g.ptask != none) ? a.tk_Z[pk.tk0 + g.ptask] : 0.0;
     g.c0 = none;
     g.c1 = none;
     if (has && t.nch > 0) g.c0 = a.ch_task[pk.ch0 + t.ch0];
     if (has && t.nch > 1) g.c1 = a.ch_task[pk.ch0 + t.ch0 + 1];
-    g.cx0 = t.ch0 + 2;
-    g.ncx = has ? max(0, t.nch - 2) : 0;
+    if (pk.binary) {
+        int gc[4] = {none, none, none, none};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = h ? g.c1 : g.c0;
+            if (c != none) {
+                const TaskDesc tc = a.tk[pk.tk0 + c];
+                if (tc.nch > 0) gc[2 * h] = a.ch_task[pk.ch0 + tc.ch0];
+                if (tc.nch > 1) gc[2 * h + 1] = a.ch_task[pk.ch0 + tc.ch0 + 1];
+            }
+        }
+        g.x0 = gc[0] | (gc[1] << 16);
+        g.x1 = gc[2] | (gc[3] << 16);
+    } else {
+        g.x0 = t.ch0 + 2;
+        g.x1 = has ? max(0, t.nch - 2) : 0;
+    }
     double q = 1.0, z = 1.0;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
@@ -189,13 +207,28 @@ __device__ __forceinline__ void load_slot(Slot<L>& g, const StepArgs& a, const P
     g.xp = 0.0;
 }
 
-// Up round: the children's sum and this branch's contribution to its parent.
+// Up round, one level at a time: the children's sum and this branch's
+// contribution to its parent.
 template <int L>
 __device__ __forceinline__ void pass_up(Slot<L>& g, double* sC, const int32_t* s_ch) {
     double cs = sC[g.c0] + sC[g.c1];
-    for (int q = 0; q < g.ncx; ++q) cs += sC[s_ch[g.cx0 + q]];
+    for (int q = 0; q < g.x1; ++q) cs += sC[s_ch[g.x0 + q]];
     g.cs = cs;
     sC[g.task] = g.fp - g.FQ * cs;
+}
+
+// Up round, two levels at a time (packs of at most binary branch points):
+// each child's contribution formed from its local value and its own
+// children's final contributions, C_c = F_0 P_0(c) - F_0 Q_0(c) sum C_g, so a
+// branch and its children share a round.
+template <int L>
+__device__ __forceinline__ void pass_up2(Slot<L>& g, const double* sF, const double* sQ, double* sC) {
+    const int g00 = g.x0 & 0xffff, g01 = int(unsigned(g.x0) >> 16);
+    const int g10 = g.x1 & 0xffff, g11 = int(unsigned(g.x1) >> 16);
+    const double s0 = sF[g.c0] - sQ[g.c0] * (sC[g00] + sC[g01]);
+    const double s1 = sF[g.c1] - sQ[g.c1] * (sC[g10] + sC[g11]);
+    g.cs = s0 + s1;
+    sC[g.task] = g.fp - g.FQ * g.cs;
 }
 
 // Down round, two levels at a time: the parent's V from the grandparent's
@@ -240,12 +273,17 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     double* s_gna = sn + pk.nhh;
     double* s_gk = s_gna + pk.nhh;
     double* s_nlb = s_gk + pk.nhh;                             // beta of each nonlinear CV
-    double* sC = s_nlb + pk.nnl;                               // per task [ntk + 2]: contribution, then distal V
+    // per task, two spare entries (zero, discard) each: contribution, then
+    // distal V; contribution with no children, then distal V for a grounded
+    // parent; F_0 Q_0 (binary packs)
+    double* sC = s_nlb + pk.nnl;
     double* sX = sC;
-    double* sY = sC + (pk.ntk + 2);                            // per task [ntk + 2]: distal V for a grounded parent
-    NlDesc* s_nl = reinterpret_cast<NlDesc*>(sY + (pk.ntk + 2));
-    int32_t* s_ch = reinterpret_cast<int32_t*>(s_nl + pk.nnl);  // children's tasks
-    int32_t* s_hhs = s_ch + pk.nch;                            // per hh instance: its CV's pair
+    double* sF = sC + (pk.ntk + 2);
+    double* sY = sF;
+    double* sQ = sF + (pk.ntk + 2);
+    NlDesc* s_nl = reinterpret_cast<NlDesc*>(sQ + (pk.binary ? pk.ntk + 2 : 0));
+    int32_t* s_ch = reinterpret_cast<int32_t*>(s_nl + pk.nnl);  // children's tasks (other packs)
+    int32_t* s_hhs = s_ch + (pk.binary ? 0 : pk.nch);          // per hh instance: its CV's slot
 
     for (int i = tid; i < ns; i += T) {
         sV[vix(i)] = a.V[pk.slot0 + i];
@@ -257,7 +295,8 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     }
     if (tid < 2) {
         sC[pk.ntk + tid] = 0.0;
-        sY[pk.ntk + tid] = 0.0;
+        sF[pk.ntk + tid] = 0.0;
+        if (pk.binary) sQ[pk.ntk + tid] = 0.0;
     }
     for (int i = tid; i < pk.nsyn; i += T) {
         sg[i] = a.syn_g[pk.syn0 + i];
@@ -277,7 +316,8 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         s_nlb[i] = a.beta[pk.slot0 + d.slot];
         if (d.hh >= 0) s_hhs[d.hh] = vix(d.slot);
     }
-    for (int i = tid; i < pk.nch; i += T) s_ch[i] = a.ch_task[pk.ch0 + i];
+    if (!pk.binary)
+        for (int i = tid; i < pk.nch; i += T) s_ch[i] = a.ch_task[pk.ch0 + i];
 
     int64_t step0 = a.step0;
     int32_t bucket = a.bucket;
@@ -319,6 +359,15 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     load_slot<L>(g0, a, pk, myr[0], tid);
     if constexpr (S > 1) load_slot<L>(g1, a, pk, myr[1], tid);
     if constexpr (S > 2) load_slot<L>(g2, a, pk, myr[2], tid);
+    if (pk.binary) {
+        if (g0.r >= 0) sQ[g0.task] = g0.FQ;
+        if constexpr (S > 1) {
+            if (g1.r >= 0) sQ[g1.task] = g1.FQ;
+        }
+        if constexpr (S > 2) {
+            if (g2.r >= 0) sQ[g2.task] = g2.FQ;
+        }
+    }
     __syncthreads();
 
     for (int s = 0; s < a.nsteps; ++s) {
@@ -377,20 +426,33 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
             local_chain<L>(g0, b0);
             if constexpr (S > 1) local_chain<L>(g1, b1);
             if constexpr (S > 2) local_chain<L>(g2, b2);
-            local_store<L>(g0, sV, sC, b0);
-            if constexpr (S > 1) local_store<L>(g1, sV, sC, b1);
-            if constexpr (S > 2) local_store<L>(g2, sV, sC, b2);
+            local_store<L>(g0, sV, sC, sF, b0);
+            if constexpr (S > 1) local_store<L>(g1, sV, sC, sF, b1);
+            if constexpr (S > 2) local_store<L>(g2, sV, sC, sF, b2);
         }
         round_sync<T>();
-        for (int r = 0; r < pk.nrd; ++r) {  // contributions up, deepest rounds first
-            if (g0.r == r && g0.c0 != pk.ntk) pass_up<L>(g0, sC, s_ch);
-            if constexpr (S > 1) {
-                if (g1.r == r && g1.c0 != pk.ntk) pass_up<L>(g1, sC, s_ch);
+        if (pk.binary) {  // contributions up, two levels a round, deepest first
+            for (int sr = 0; 2 * sr < pk.nlev; ++sr) {
+                if (((pk.nlev - 1 - g0.lev) >> 1) == sr && g0.c0 != pk.ntk) pass_up2<L>(g0, sF, sQ, sC);
+                if constexpr (S > 1) {
+                    if (((pk.nlev - 1 - g1.lev) >> 1) == sr && g1.c0 != pk.ntk) pass_up2<L>(g1, sF, sQ, sC);
+                }
+                if constexpr (S > 2) {
+                    if (((pk.nlev - 1 - g2.lev) >> 1) == sr && g2.c0 != pk.ntk) pass_up2<L>(g2, sF, sQ, sC);
+                }
+                round_sync<T>();
             }
-            if constexpr (S > 2) {
-                if (g2.r == r && g2.c0 != pk.ntk) pass_up<L>(g2, sC, s_ch);
+        } else {
+            for (int r = 0; r < pk.nrd; ++r) {  // contributions up, deepest rounds first
+                if (g0.r == r && g0.c0 != pk.ntk) pass_up<L>(g0, sC, s_ch);
+                if constexpr (S > 1) {
+                    if (g1.r == r && g1.c0 != pk.ntk) pass_up<L>(g1, sC, s_ch);
+                }
+                if constexpr (S > 2) {
+                    if (g2.r == r && g2.c0 != pk.ntk) pass_up<L>(g2, sC, s_ch);
+                }
+                round_sync<T>();
             }
-            round_sync<T>();
         }
         {
             double b0[L], b1[L], b2[L];

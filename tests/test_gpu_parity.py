@@ -129,6 +129,29 @@ def test_clamps_on_passive_dendrites(coef_mode):
     check(m, 900, probes=np.arange(int(gen.n_cvs(m).sum())), coef_mode=coef_mode, block_threads=64)
 
 
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_register_layout_with_wide_branch_points(block):
+    """Short branches (register-resident kernel) on trees whose soma has 5
+    children and whose branches have 3 or 4 children, so sums over children
+    beyond the first two and odd tree depths are exercised; several cells
+    per pack."""
+    from paper_1901_07454_amd import arbmi
+    cells = []
+    for k in range(6):
+        parents = [-1] * 5 + [0, 0, 0, 1, 1, 1, 1, 5, 5, 5, 8] + [15] * 3
+        n = len(parents)
+        d = models.bare_cell(parents, [(3 + 2 * i + k) % 8 + 1 for i in range(n)],
+                             np.linspace(30, 150, n), np.linspace(0.7, 2.2, n))
+        d.clamps.append((-1, 0, 20 + 10 * k, 700, 0.5))
+        d.clamps.append((7, 0, 100, 400, 0.2))
+        d.syn.append((12, 0, 2.0, 0.0))
+        d.ext.append((0, 150 + 20 * k, 0.05))
+        cells.append(d)
+    m = gen.assemble(cells, n_steps=900)
+    _, sp = check(m, 900, probes=np.arange(int(gen.n_cvs(m).sum())), coef_mode=3, block_threads=block)
+    assert len(sp) > 0
+
+
 def test_epoch_length_invariance_bitwise():
     m = gen.config2(n_cells=8, kick_all=False)
     probes = oracle.cell_cv_begin(m)[:-1]
