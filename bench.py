@@ -8,7 +8,8 @@ detection, and (every epoch) the spike exchange.  The default workload is the
 5 ms, dt 0.025 ms), timed over 4000 steps (100 ms of model time) after a
 warm-up epoch.  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line.  `--config 3|4|5|1` selects the other workloads.
+Prints one JSON line.  `--config 3|4|5|1` selects the other workloads and
+`--config 6` the synapse-dominated ring (10,000 expsyn per cell).
 """
 from __future__ import annotations
 
@@ -55,6 +56,10 @@ def make_model(cfg: int, n_cells: int | None):
     if cfg == 4:
         n = n_cells or 256
         return gen.config4(n_cells=n), f"{n} cells x 200 CVs, hh+pas everywhere, soma clamp 0.2 nA"
+    if cfg == 6:
+        n = n_cells or 8192
+        return gen.config6(n_cells=n), (f"{n}-cell synapse-dominated ring, random trees of 90-170 CVs (mean 130), "
+                                        "hh soma, pas dendrites, 10,000 expsyn/cell (one on the ring), delay 5 ms")
     raise SystemExit(f"unknown config {cfg}")
 
 
@@ -87,6 +92,8 @@ def _oracle_chunk(args):
         m = gen.config5(n_cells=65536, cells=cells)
     elif cfg == 4:
         m = gen.config4(cells=cells)
+    elif cfg == 6:
+        m = gen.config6(n_cells=8192, cells=cells)
     else:
         m = gen.config1()
     s = oracle.Sim(m)
@@ -105,9 +112,9 @@ def cpu_baseline(cfg: int, budget_s: float = 20.0):
     import oracle
     oracle.build() if not os.path.exists(oracle.LIB) else None
     workers = max(1, min(16, os.cpu_count() or 1))
-    per = {1: (1, 4000), 2: (96, 800), 3: (24, 800), 4: (64, 2000), 5: (48, 800)}[cfg]
+    per = {1: (1, 4000), 2: (96, 800), 3: (24, 800), 4: (64, 2000), 5: (48, 800), 6: (16, 400)}[cfg]
     n_cells, steps = per
-    base = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536}[cfg]
+    base = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536, 6: 8192}[cfg]
     chunks = [(cfg, [(w * n_cells + k) % base for k in range(n_cells)], steps) for w in range(workers)]
     if cfg == 1:
         chunks = [(1, [0], steps) for _ in range(workers)]
@@ -120,7 +127,7 @@ def cpu_baseline(cfg: int, budget_s: float = 20.0):
     cpu_s = sum(t for _, t in res)
     return {"value": rate, "unit": "CV-updates/s", "cores": workers, "kind": "oracle",
             "sample": (f"{workers} processes x {n_cells} cells x {steps} steps of the same workload "
-                       f"({'ring segments' if cfg == 2 else 'cell chunks'}), stepping time only; "
+                       f"({'ring segments' if cfg in (2, 6) else 'cell chunks'}), stepping time only; "
                        f"{cpu_s:.1f} s CPU, {wall:.1f} s wall")}
 
 
@@ -279,6 +286,8 @@ def main():
                      "alu": {"achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": tflops / FP64_PEAK_TFLOPS, "flops_per_step": flops_per_step}},
     }
+    if info["n_syn"] > 0:
+        out["synapse_updates_per_s"] = info["n_syn"] * args.steps / wall
     sim.close()
     if not args.no_grad:
         out["grad"] = grad_ratio(torch)

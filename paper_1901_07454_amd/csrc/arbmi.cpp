@@ -717,7 +717,7 @@ int arb_plan_layout(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     I.n_cv = L.n_cv;
     I.n_slots = L.n_slots;
     I.n_hh = int64_t(L.hh_cv.size());
-    I.n_syn = int64_t(L.syn_global.size());
+    I.n_syn = int64_t(L.syn_pack_index.size());  // the model's synapses (pack order may pad)
     I.n_conn = int64_t(L.out_rank.size());
     I.epoch_steps = p->epoch_steps > 0 ? p->epoch_steps : (L.out_rank.empty() ? 1000 : L.min_delay);
     I.block_threads = L.block_threads;
@@ -980,7 +980,7 @@ int arb_get_info(arb_sim s_, arb_info* info) {
     I.n_cv = L.n_cv;
     I.n_slots = L.n_slots;
     I.n_hh = int64_t(L.hh_cv.size());
-    I.n_syn = int64_t(L.syn_global.size());
+    I.n_syn = int64_t(L.syn_pack_index.size());  // the model's synapses (pack order may pad)
     I.n_conn = int64_t(L.out_rank.size());
     I.step = s->step;
     I.epoch_steps = s->K;

@@ -194,8 +194,12 @@ arb_params autotune(const ModelView& m, const arb_params& p, const DeviceLimits&
     Candidate best{0, 0, 0};
     if (!cache_lookup(key, best)) {
         // enough cells for several waves of workgroups on every CU, so that
-        // the last, partial wave weighs about as much as in the full model
-        const Sample smp = make_sample(m, std::max(64, d.n_cu * 32));
+        // the last, partial wave weighs about as much as in the full model;
+        // at most about 8M synapses, which bounds the trial builds' time
+        const int64_t syn_per_cell = m.n_cells > 0 ? std::max<int64_t>(1, m.n_syn / m.n_cells) : 1;
+        const int32_t n_sample =
+            int32_t(std::max<int64_t>(64, std::min<int64_t>(int64_t(d.n_cu) * 32, 8000000 / syn_per_cell)));
+        const Sample smp = make_sample(m, n_sample);
         int64_t max_width = 1;
         for (const arb_cell& C : smp.cells) {
             std::vector<int> depth(C.n_branch, 0), count(C.n_branch + 2, 0);

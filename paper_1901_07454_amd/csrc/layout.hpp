@@ -46,8 +46,11 @@ struct PackDesc {
     int32_t spare;   // register-resident layout: a slot no CV uses (a pad row, or nslot)
     int32_t nlev;    // depth levels of the pack's cells (the soma is level 0)
     int32_t binary;  // 1 if no task of the pack has more than two children
+    int32_t syn_global;  // register-resident layout: synapse state stays in HBM
+    int32_t syn_uniform; // all synapses of the pack share e_syn and decay (below)
     int32_t unused;
     int64_t xe0, xe1; // external events [xe0, xe1), sorted by (step, syn, input order)
+    double syn_e, syn_decay;  // the shared values when syn_uniform
 };
 
 // Bytes of dynamic LDS the step kernel uses for a pack.  Layout in the
@@ -68,6 +71,10 @@ struct PackDesc {
 // in the register-resident kernel.
 constexpr int kSpreadHH = 20;
 
+// A register-resident pack whose synapses would take more LDS than this
+// keeps their state in HBM and streams it every step.
+constexpr int64_t kSynLdsMax = 16384;
+
 // Doubles of the register-resident kernel's V and R blocks (64 V then 64 R per
 // 64 slots) for a pack: every slot and the spare slot.  The kernel and the
 // LDS accounting below both use this.
@@ -77,7 +84,8 @@ constexpr int vr_block_doubles(int nslot, int spare) {
 
 inline int64_t pack_lds_bytes(const PackDesc& D, int coef_mode) {
     if (coef_mode == 3) {
-        const int64_t dbl = vr_block_doubles(D.nslot, D.spare) + 3 * int64_t(D.nsyn) + 5 * int64_t(D.nhh) +
+        const int64_t dbl = vr_block_doubles(D.nslot, D.spare) + (D.syn_global ? 0 : 3 * int64_t(D.nsyn)) +
+                            5 * int64_t(D.nhh) +
                             int64_t(D.nnl) + (D.binary ? 3 : 2) * (int64_t(D.ntk) + 2);
         return 8 * dbl + 16 * int64_t(D.nnl) + (D.binary ? 0 : 4 * int64_t(D.nch)) + 4 * int64_t(D.nhh);
     }
@@ -106,8 +114,8 @@ struct TaskDesc {
 struct NlDesc {     // one CV carrying an hh instance, synapses or current clamps
     int32_t slot;   // pack-local slot
     int32_t hh;     // pack-local hh instance, -1 if none
-    int32_t syn0;   // pack-local synapses [syn0, syn0 + nsyn)
-    int32_t nsyn;
+    int32_t syn0;   // pack-local synapses syn0 + k s, k < nsyn, with s = 1, or in a pack
+    int32_t nsyn;   //   keeping synapses in HBM s = the entries of its group of T
 };
 
 // Device counters and flags of a sim.

@@ -336,6 +336,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         D.spare = sh.has_pad ? 0 : D.nslot;
         D.binary = 1;
         for (int32_t c : pp.cells) D.binary = D.binary && max_children[c] <= 2;
+        D.syn_global = (S > 0 && 24 * pp.nsyn > kSynLdsMax) ? 1 : 0;
         D.nrd = int32_t(sh.nrd);
         D.ntk = int32_t(pp.nbr + int64_t(pp.cells.size()));
         D.nch = int32_t(pp.nbr);
@@ -440,6 +441,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         D.nlev = maxd + 1;
         D.binary = 1;
         for (int32_t c : pp.cells) D.binary = D.binary && max_children[c] <= 2;
+        D.syn_global = (S > 0 && 24 * pp.nsyn > kSynLdsMax) ? 1 : 0;
         // the register-resident kernel's empty slots write to a slot no CV
         // uses: the first pad row if there is one, else one past the end
         D.spare = D.nslot;
@@ -559,21 +561,68 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                 if (has_hh[i] || nsyn_cv[i] || nic_cv[i]) here.push_back({L.perm[i], i});
         }
         std::sort(here.begin(), here.end());
+        if (D.syn_global)  // CVs with similar synapse counts share a group: little padding
+            std::stable_sort(here.begin(), here.end(), [&](const std::pair<int64_t, int64_t>& a,
+                                                           const std::pair<int64_t, int64_t>& b) {
+                return syn_at[a.second].size() > syn_at[b.second].size();
+            });
+        const size_t nl_first = L.nl.size();
         for (auto& sc : here) {
             const int64_t i = sc.second;
             NlDesc N{};
             N.slot = int32_t(sc.first - D.slot0);
             N.hh = -1;
             if (has_hh[i]) { N.hh = int32_t(L.hh_cv.size()) - D.hh0; L.hh_cv.push_back(i); }
-            N.syn0 = int32_t(L.syn_global.size()) - D.syn0;
             N.nsyn = int32_t(syn_at[i].size());
-            for (int64_t q : syn_at[i]) {
-                L.syn_pack_index[q] = int64_t(L.syn_global.size());
-                L.syn_global.push_back(q);
-                L.syn_e.push_back(syn[q].e_rev_mV);
-                L.syn_decay.push_back(std::exp(-dt / syn[q].tau_ms));
-            }
             L.nl.push_back(N);
+        }
+        // Synapses in pack order.  In LDS they are contiguous per CV.  A pack
+        // that keeps them in HBM interleaves them over the threads that take
+        // the CVs (thread t takes nonlinear entries t, t + T, ...): synapse k
+        // of entry u T + t sits at group base + k w + t, w the group's
+        // entries, so a wave's loads of one k are consecutive; shorter CVs
+        // are padded with zero entries.
+        auto put = [&](int64_t pos, int64_t q) {
+            L.syn_pack_index[q] = pos;
+            L.syn_global[pos] = q;
+            L.syn_e[pos] = syn[q].e_rev_mV;
+            L.syn_decay[pos] = std::exp(-dt / syn[q].tau_ms);
+        };
+        const int64_t nhere = int64_t(here.size());
+        const int64_t group = D.syn_global ? int64_t(T) : 1;
+        for (int64_t u0 = 0; u0 < nhere; u0 += group) {
+            const int64_t w = std::min(group, nhere - u0);
+            int64_t mx = 0;
+            for (int64_t t = 0; t < w; ++t) mx = std::max<int64_t>(mx, L.nl[nl_first + u0 + t].nsyn);
+            const int64_t base = int64_t(L.syn_global.size());
+            const int64_t len = D.syn_global ? mx * w : L.nl[nl_first + u0].nsyn;
+            L.syn_global.resize(base + len, -1);
+            L.syn_e.resize(base + len, 0.0);
+            L.syn_decay.resize(base + len, 0.0);
+            for (int64_t t = 0; t < w; ++t) {
+                NlDesc& N = L.nl[nl_first + u0 + t];
+                N.syn0 = int32_t(base + t - D.syn0);
+                const std::vector<int64_t>& qs = syn_at[here[u0 + t].second];
+                for (size_t k = 0; k < qs.size(); ++k) put(base + int64_t(k) * w + t, qs[k]);
+            }
+        }
+        // one e_syn and decay for the whole pack, if its synapses share them
+        D.syn_uniform = 0;
+        D.syn_e = 0.0;
+        D.syn_decay = 0.0;
+        {
+            bool first = true, same = true;
+            for (int64_t pos = D.syn0; pos < int64_t(L.syn_global.size()) && same; ++pos) {
+                if (L.syn_global[pos] < 0) continue;
+                if (first) {
+                    D.syn_e = L.syn_e[pos];
+                    D.syn_decay = L.syn_decay[pos];
+                    first = false;
+                } else {
+                    same = L.syn_e[pos] == D.syn_e && L.syn_decay[pos] == D.syn_decay;
+                }
+            }
+            D.syn_uniform = (!first && same) ? 1 : 0;
         }
         // clamps of the pack, by slot then input order
         std::vector<std::pair<int64_t, int64_t>> cl;  // (slot, clamp)
@@ -680,6 +729,12 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
 }
 
 std::string verify_layout(const Lowered& L) {
+    // every synapse at exactly one pack-order position, and back
+    for (size_t q = 0; q < L.syn_pack_index.size(); ++q) {
+        const int64_t pos = L.syn_pack_index[q];
+        if (pos < 0 || pos >= int64_t(L.syn_global.size()) || L.syn_global[pos] != int64_t(q))
+            return fmt("synapse %zu has no pack-order position", q);
+    }
     // every user CV in exactly one slot, slots inside their pack
     std::vector<int32_t> hit(L.n_slots, 0);
     for (int64_t i = 0; i < L.n_cv; ++i) {

@@ -264,10 +264,16 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
 
     // ---- LDS layout (the mode-3 layout of pack_lds_bytes) ----
     double* sV = reinterpret_cast<double*>(lds_raw);           // V and R blocks (pack_lds_bytes)
+    // synapse state in LDS, or in HBM (pack_lds_bytes) for synapse-heavy packs
+    const int nsyn_lds = pk.syn_global ? 0 : pk.nsyn;
     double* sg = sV + vr_block_doubles(ns, pk.spare);
-    double* s_se = sg + pk.nsyn;
-    double* s_sdec = s_se + pk.nsyn;
-    double* sm = s_sdec + pk.nsyn;
+    double* s_se = sg + nsyn_lds;
+    double* s_sdec = s_se + nsyn_lds;
+    double* sm = s_sdec + nsyn_lds;
+    double* g_g = a.syn_g + pk.syn0;                           // HBM synapse state of the pack
+    const double* g_se = a.syn_e + pk.syn0;
+    const double* g_sdec = a.syn_decay + pk.syn0;
+    double* sgv = pk.syn_global ? g_g : sg;                    // where events add to g
     double* sh = sm + pk.nhh;
     double* sn = sh + pk.nhh;
     double* s_gna = sn + pk.nhh;
@@ -298,10 +304,10 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         sF[pk.ntk + tid] = 0.0;
         if (pk.binary) sQ[pk.ntk + tid] = 0.0;
     }
-    for (int i = tid; i < pk.nsyn; i += T) {
-        sg[i] = a.syn_g[pk.syn0 + i];
-        s_se[i] = a.syn_e[pk.syn0 + i];
-        s_sdec[i] = a.syn_decay[pk.syn0 + i];
+    for (int i = tid; i < nsyn_lds; i += T) {
+        sg[i] = g_g[i];
+        s_se[i] = g_se[i];
+        s_sdec[i] = g_sdec[i];
     }
     for (int i = tid; i < pk.nhh; i += T) {
         sm[i] = a.hh_m[pk.hh0 + i];
@@ -377,15 +383,16 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         if (tid == 0) {
             while (int64_t(nkey >> 32) == n) {
                 const uint32_t r = uint32_t(nkey);
-                sg[a.cr_syn[r]] += a.cr_w[r];
+                sgv[a.cr_syn[r]] += a.cr_w[r];
                 ++ncur;
                 nkey = (ncur < nend) ? ev[ncur] : ~uint64_t(0);
             }
             while (xstep == n) {
-                sg[a.xe_syn[xcur]] += a.xe_w[xcur];
+                sgv[a.xe_syn[xcur]] += a.xe_w[xcur];
                 ++xcur;
                 xstep = (xcur < pk.xe1) ? a.xe_step[xcur] : INT64_MAX;
             }
+            if (pk.syn_global) __threadfence_block();  // the adds reach the other threads' loads
         }
         round_sync<T>();
 
@@ -400,9 +407,48 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
                 I += s_gna[q] * (m * m * m * h) * (v - kENa);
                 I += s_gk[q] * (x * x * x * x) * (v - kEK);
             }
-            for (int k = 0; k < d.nsyn; ++k) {
-                const int q = d.syn0 + k;
-                I += sg[q] * (v - s_se[q]);
+            if (!pk.syn_global) {
+                for (int k = 0; k < d.nsyn; ++k) {
+                    const int q = d.syn0 + k;
+                    I += sg[q] * (v - s_se[q]);
+                }
+            } else {
+                // HBM synapses, interleaved over the threads of this group
+                // of entries (stride w), four at a time so their loads
+                // overlap; the decay of phase E is applied here (g is not
+                // read again before the next step's events)
+                const int w = min(T, pk.nnl - (j / T) * T);
+                if (pk.syn_uniform) {  // shared e_syn and decay: only g moves
+                    const double e = pk.syn_e, dec = pk.syn_decay;
+                    for (int k0 = 0; k0 < d.nsyn; k0 += 4) {
+                        double gg[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) gg[i] = g_g[d.syn0 + min(k0 + i, d.nsyn - 1) * w];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (k0 + i < d.nsyn) {
+                                I += gg[i] * (v - e);
+                                g_g[d.syn0 + (k0 + i) * w] = gg[i] * dec;
+                            }
+                    }
+                } else {
+                    for (int k0 = 0; k0 < d.nsyn; k0 += 4) {
+                        double gg[4], ee[4], dd[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int q = d.syn0 + min(k0 + i, d.nsyn - 1) * w;
+                            gg[i] = g_g[q];
+                            ee[i] = g_se[q];
+                            dd[i] = g_sdec[q];
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (k0 + i < d.nsyn) {
+                                I += gg[i] * (v - ee[i]);
+                                g_g[d.syn0 + (k0 + i) * w] = gg[i] * dd[i];
+                            }
+                    }
+                }
             }
             sV[vix(d.slot) + kRoff] = s_nlb[j] - I;
         }
@@ -498,7 +544,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         // hh instances gives each gate of an instance its own thread (which
         // computes that gate's two rates and the update); otherwise a thread
         // takes a whole instance.
-        for (int j = tid; j < pk.nsyn; j += T) sg[j] *= s_sdec[j];
+        for (int j = tid; j < nsyn_lds; j += T) sg[j] *= s_sdec[j];
         if (pk.nhh <= kSpreadHH) {
             for (int j = tid; j < 3 * pk.nhh; j += T) {
                 const int q = j / 3, w = j - 3 * q;
@@ -534,11 +580,12 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
                 for (int j = tid; j < pk.npr; j += T)
                     a.trace[int64_t(a.pr_id[pk.pr0 + j]) * a.trace_cap + col] = sV[vix(a.pr_slot[pk.pr0 + j])];
         }
+        if (pk.syn_global) __threadfence_block();  // phase B's g stores before the next step's events
         round_sync<T>();
     }
 
     for (int i = tid; i < ns; i += T) a.V[pk.slot0 + i] = sV[vix(i)];
-    for (int i = tid; i < pk.nsyn; i += T) a.syn_g[pk.syn0 + i] = sg[i];
+    for (int i = tid; i < nsyn_lds; i += T) g_g[i] = sg[i];
     for (int i = tid; i < pk.nhh; i += T) {
         a.hh_m[pk.hh0 + i] = sm[i];
         a.hh_h[pk.hh0 + i] = sh[i];

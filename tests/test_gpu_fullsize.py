@@ -103,3 +103,29 @@ def test_config4_full_size_adjoint_sampled_cells():
         print(f"cell {c}: max rel grad err {rel.max():.3e}", flush=True)
         assert rel.max() <= 1e-7
     gs.close()
+
+
+def test_config6_full_size_light_cone():
+    """The synapse-dominated ring at full size (8192 cells x ~130 CVs x 10,000
+    expsyn, 82M synapses), 400 steps, autotuned shape: a sampled cell's inputs
+    within 400 steps come from its own kick and its ring predecessor."""
+    from paper_1901_07454_amd import arbmi
+    n = 400
+    m = gen.config6(n_steps=n)
+    cv0 = oracle.cell_cv_begin(m)
+    samples = [0, 4097, 8191]
+    tr, V, sp, info = _gpu(m, n, cv0[samples], flags=arbmi.ARB_FLAG_AUTOTUNE)
+    print("config 6 info", info, "spikes", len(sp), flush=True)
+    del m
+    for k, c in enumerate(samples):
+        chain = gen.ring_light_cone(8192, c, n)
+        sub = gen.config6(n_cells=8192, cells=chain, n_steps=n)
+        s = oracle.Sim(sub)
+        c0 = oracle.cell_cv_begin(sub)
+        rtr = s.run(n, probes=[c0[-2]])[0]
+        err = max(np.max(np.abs(tr[k] - rtr)), np.max(np.abs(V[cv0[c]:cv0[c + 1]] - s.state()["V"][c0[-2]:c0[-1]])))
+        g, st, _ = s.spikes()
+        mine = sorted(int(x) for x in sp["step"][sp["gid"] == c])
+        print(f"cell {c}: max|dV| = {err:.3e}", flush=True)
+        assert err <= TOL
+        assert mine == sorted(int(x) for x, gg in zip(st, g) if gg == len(chain) - 1)

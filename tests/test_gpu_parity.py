@@ -152,6 +152,37 @@ def test_register_layout_with_wide_branch_points(block):
     assert len(sp) > 0
 
 
+@pytest.mark.parametrize("n_syn", [10000, 400])
+def test_synapse_dominated_ring_small(n_syn):
+    """Trees of ~130 CVs with n_syn expsyn each, one of them on the ring:
+    10,000 per cell keep the synapse state in HBM, 400 keep it in LDS."""
+    m = gen.config6(n_cells=5, n_syn=n_syn, n_steps=700)
+    m["ev_w"] = np.full_like(m["ev_w"], 0.1)
+    _, sp = check(m, 700)
+    assert len(sp) >= 5
+
+
+def test_synapse_dominated_mixed_parameters():
+    """HBM-resident synapses whose reversal potentials and time constants
+    differ, with external events on thousands of them, so every synapse the
+    kernel streams carries conductance."""
+    rng = np.random.default_rng(61)
+    m = gen.config6(n_cells=4, n_syn=6000, n_steps=600)
+    ns = len(m["syn_e"])
+    m["syn_tau"] = rng.uniform(1.0, 6.0, ns)
+    m["syn_e"] = np.where(rng.random(ns) < 0.8, 0.0, -75.0)
+    k = 8000
+    syn = rng.integers(ns, size=k).astype(np.uint32)
+    step = rng.integers(0, 500, size=k).astype(np.int64)
+    w = rng.uniform(0.0, 2e-4, k)
+    syn = np.concatenate([m["ev_syn"], syn])
+    step = np.concatenate([m["ev_step"], step])
+    w = np.concatenate([np.full(len(m["ev_w"]), 0.1), w])
+    o = np.lexsort((syn, step))
+    m["ev_syn"], m["ev_step"], m["ev_w"] = syn[o], step[o], w[o]
+    check(m, 600)
+
+
 def test_epoch_length_invariance_bitwise():
     m = gen.config2(n_cells=8, kick_all=False)
     probes = oracle.cell_cv_begin(m)[:-1]

@@ -106,11 +106,12 @@ def spread(total: int, parts: int, rng: np.random.Generator) -> np.ndarray:
 
 class CellDesc:
     __slots__ = ("parents", "n_cv", "length", "diam", "mech", "gna", "gk", "gl",
-                 "gpas", "epas", "soma_mech", "soma_g", "syn", "in_conn",
+                 "gpas", "epas", "soma_mech", "soma_g", "syn", "syn_arr", "in_conn",
                  "ext", "clamps")
 
     def __init__(self):
         self.syn = []       # (branch, cv, tau, e)
+        self.syn_arr = None  # or the same four columns as arrays (many synapses)
         self.in_conn = []   # (src gid, local syn, delay_steps, w)
         self.ext = []       # (local syn, step, w)
         self.clamps = []    # (branch, cv, on, off, amp)
@@ -251,6 +252,28 @@ def cell_c5(i: int, n_cells: int, n_in: int = 100, t_ms: float = 200.0,
     return d
 
 
+def cell_c6(i: int, n_cells: int, n_syn: int = 10000, kick_all: bool = True) -> CellDesc:
+    """The synapse-dominated ring: random trees of 90-170 CVs (mean 130),
+    hh soma, pas dendrites, n_syn expsyn at random CVs of which only synapse 0
+    (on the soma) receives the ring connection from cell i - 1."""
+    rng = cell_rng(6, i)
+    d = CellDesc()
+    n = int(rng.integers(90, 171))
+    d.parents = yule_parents(rng, -(-(n - 1) // 8))
+    nb = len(d.parents)
+    _geometry(d, rng, spread(n - 1, nb, rng))
+    _dend_pas(d)
+    _soma_hh(d)
+    bs = rng.integers(nb, size=n_syn - 1)
+    ks = rng.integers(d.n_cv[bs])
+    d.syn_arr = (np.concatenate([[-1], bs]), np.concatenate([[0], ks]),
+                 np.full(n_syn, 2.0), np.zeros(n_syn))
+    d.in_conn.append(((i - 1) % n_cells, 0, 200, 0.05))
+    if kick_all or i == 0:
+        d.ext.append((0, 0, 0.05))
+    return d
+
+
 # ----------------------------------------------------------------------------
 # assembly of a model from cell descriptions
 
@@ -279,14 +302,21 @@ def assemble(cells: list[CellDesc], gids=None, n_steps: int = 0,
         br_mech=cat("mech", np.uint32), br_gna=cat("gna", np.float64), br_gk=cat("gk", np.float64),
         br_gl=cat("gl", np.float64), br_gpas=cat("gpas", np.float64), br_epas=cat("epas", np.float64),
     )
+    cols = []
+    for c in cells:
+        if c.syn_arr is not None:
+            cols.append(tuple(np.asarray(x) for x in c.syn_arr))
+        else:
+            cols.append(tuple(np.array([s[j] for s in c.syn]) for j in range(4)))
+    nsyn = np.array([len(x[0]) for x in cols], np.int64)
     sb = np.zeros(C + 1, np.int64)
-    sb[1:] = np.cumsum([len(c.syn) for c in cells])
-    syn = [(ci, s) for ci, c in enumerate(cells) for s in c.syn]
-    m["syn_cell"] = np.array([ci for ci, _ in syn], np.int32)
-    m["syn_branch"] = np.array([s[0] for _, s in syn], np.int32)
-    m["syn_cv"] = np.array([s[1] for _, s in syn], np.int32)
-    m["syn_tau"] = np.array([s[2] for _, s in syn], np.float64)
-    m["syn_e"] = np.array([s[3] for _, s in syn], np.float64)
+    sb[1:] = np.cumsum(nsyn)
+    colcat = lambda j, dt_: np.concatenate([x[j].astype(dt_) for x in cols]) if C else np.zeros(0, dt_)
+    m["syn_cell"] = np.repeat(np.arange(C, dtype=np.int32), nsyn)
+    m["syn_branch"] = colcat(0, np.int32)
+    m["syn_cv"] = colcat(1, np.int32)
+    m["syn_tau"] = colcat(2, np.float64)
+    m["syn_e"] = colcat(3, np.float64)
     con = [(remap[src], ci, int(sb[ci]) + ls, dl, w)
            for ci, c in enumerate(cells) for (src, ls, dl, w) in c.in_conn if int(src) in remap]
     m["con_src"] = np.array([x[0] for x in con], np.uint32)
@@ -358,6 +388,12 @@ def config5(n_cells: int = 65536, cells=None, n_in: int = 100, n_steps: int = 80
     ids = range(n_cells) if cells is None else cells
     t_ms = n_steps * DT
     return assemble([cell_c5(i, n_cells, n_in, t_ms) for i in ids], gids=list(ids), n_steps=n_steps)
+
+
+def config6(n_cells: int = 8192, cells=None, kick_all: bool = True, n_steps: int = 4000,
+            n_syn: int = 10000) -> dict:
+    ids = range(n_cells) if cells is None else cells
+    return assemble([cell_c6(i, n_cells, n_syn, kick_all) for i in ids], gids=list(ids), n_steps=n_steps)
 
 
 def ring_light_cone(n_cells: int, target: int, n_steps: int, delay: int = 200) -> list[int]:
