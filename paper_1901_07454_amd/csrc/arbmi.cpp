@@ -519,8 +519,12 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
     s->cfg.coef_mode = s->L.coef_mode;
     s->cfg.reg_slots = s->L.reg_slots;
     s->cfg.reg_len = s->L.reg_len;
+    s->cfg.syn_hbm = 0;
     int64_t lds = 0;
-    for (const PackDesc& D : s->L.packs) lds = std::max(lds, pack_lds_bytes(D, s->L.coef_mode));
+    for (const PackDesc& D : s->L.packs) {
+        lds = std::max(lds, pack_lds_bytes(D, s->L.coef_mode));
+        if (s->L.coef_mode == 3 && D.syn_global) s->cfg.syn_hbm = 1;
+    }
     if (lds > d.lds_max - 256) {
         delete s;
         err = "a pack needs more LDS than the device has";

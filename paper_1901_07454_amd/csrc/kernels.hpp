@@ -95,6 +95,7 @@ struct LaunchCfg {
     int lds_bytes;      // dynamic LDS per workgroup
     int reg_slots;      // mode 3: branches per thread
     int reg_len;        // mode 3: CVs per branch held in registers (8 or 16)
+    int syn_hbm;        // mode 3: some pack keeps its synapse state in HBM
 };
 
 hipError_t launch_step(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st);

@@ -253,8 +253,9 @@ __device__ __forceinline__ void round_sync() {
 
 // Waves per SIMD the registers allow without spilling (built without
 // machine loop-invariant code motion): three for one slot of 8 CVs, two for
-// 16 CVs in all, one otherwise.
-template <int T, int S, int L>
+// 16 CVs in all, one otherwise.  G: some pack of the launch keeps its
+// synapse state in HBM (without it, that path is compiled out).
+template <int T, int S, int L, bool G>
 __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) reg_step_kernel(StepArgs a) {
     extern __shared__ __align__(16) char lds_raw[];
     const int p = blockIdx.x + a.pack0;
@@ -265,7 +266,8 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     // ---- LDS layout (the mode-3 layout of pack_lds_bytes) ----
     double* sV = reinterpret_cast<double*>(lds_raw);           // V and R blocks (pack_lds_bytes)
     // synapse state in LDS, or in HBM (pack_lds_bytes) for synapse-heavy packs
-    const int nsyn_lds = pk.syn_global ? 0 : pk.nsyn;
+    const bool syn_hbm = G && pk.syn_global;
+    const int nsyn_lds = syn_hbm ? 0 : pk.nsyn;
     double* sg = sV + vr_block_doubles(ns, pk.spare);
     double* s_se = sg + nsyn_lds;
     double* s_sdec = s_se + nsyn_lds;
@@ -273,7 +275,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     double* g_g = a.syn_g + pk.syn0;                           // HBM synapse state of the pack
     const double* g_se = a.syn_e + pk.syn0;
     const double* g_sdec = a.syn_decay + pk.syn0;
-    double* sgv = pk.syn_global ? g_g : sg;                    // where events add to g
+    double* sgv = syn_hbm ? g_g : sg;                    // where events add to g
     double* sh = sm + pk.nhh;
     double* sn = sh + pk.nhh;
     double* s_gna = sn + pk.nhh;
@@ -392,7 +394,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
                 ++xcur;
                 xstep = (xcur < pk.xe1) ? a.xe_step[xcur] : INT64_MAX;
             }
-            if (pk.syn_global) __threadfence_block();  // the adds reach the other threads' loads
+            if (syn_hbm) __threadfence_block();  // the adds reach the other threads' loads
         }
         round_sync<T>();
 
@@ -407,7 +409,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
                 I += s_gna[q] * (m * m * m * h) * (v - kENa);
                 I += s_gk[q] * (x * x * x * x) * (v - kEK);
             }
-            if (!pk.syn_global) {
+            if (!syn_hbm) {
                 for (int k = 0; k < d.nsyn; ++k) {
                     const int q = d.syn0 + k;
                     I += sg[q] * (v - s_se[q]);
@@ -580,7 +582,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
                 for (int j = tid; j < pk.npr; j += T)
                     a.trace[int64_t(a.pr_id[pk.pr0 + j]) * a.trace_cap + col] = sV[vix(a.pr_slot[pk.pr0 + j])];
         }
-        if (pk.syn_global) __threadfence_block();  // phase B's g stores before the next step's events
+        if (syn_hbm) __threadfence_block();  // phase B's g stores before the next step's events
         round_sync<T>();
     }
 
@@ -599,14 +601,17 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
 }
 
 template <int T, int S, int L>
-hipError_t launch_reg(const StepArgs& a, int lds, int n_packs, hipStream_t st) {
-    hipLaunchKernelGGL((reg_step_kernel<T, S, L>), dim3(n_packs), dim3(T), lds, st, a);
+hipError_t launch_reg(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st) {
+    if (cfg.syn_hbm)
+        hipLaunchKernelGGL((reg_step_kernel<T, S, L, true>), dim3(n_packs), dim3(T), cfg.lds_bytes, st, a);
+    else
+        hipLaunchKernelGGL((reg_step_kernel<T, S, L, false>), dim3(n_packs), dim3(T), cfg.lds_bytes, st, a);
     return hipGetLastError();
 }
 
-template <int T, int S, int L>
-void allow_lds(int lds_max) {
-    const void* f = reinterpret_cast<const void*>(&reg_step_kernel<T, S, L>);
+template <int T, int S, int L, bool G>
+void allow_lds_one(int lds_max) {
+    const void* f = reinterpret_cast<const void*>(&reg_step_kernel<T, S, L, G>);
     hipFuncAttributes at{};
     if (hipFuncGetAttributes(&at, f) != hipSuccess) return;
     const int allowed = lds_max - int(at.sharedSizeBytes);
@@ -614,17 +619,23 @@ void allow_lds(int lds_max) {
     (void)hipGetLastError();
 }
 
+template <int T, int S, int L>
+void allow_lds(int lds_max) {
+    allow_lds_one<T, S, L, false>(lds_max);
+    allow_lds_one<T, S, L, true>(lds_max);
+}
+
 template <int T>
 hipError_t launch_reg_T(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st) {
     if (cfg.reg_len == 8) {
         switch (cfg.reg_slots) {
-            case 1: return launch_reg<T, 1, 8>(a, cfg.lds_bytes, n_packs, st);
-            case 2: return launch_reg<T, 2, 8>(a, cfg.lds_bytes, n_packs, st);
-            case 3: return launch_reg<T, 3, 8>(a, cfg.lds_bytes, n_packs, st);
+            case 1: return launch_reg<T, 1, 8>(a, cfg, n_packs, st);
+            case 2: return launch_reg<T, 2, 8>(a, cfg, n_packs, st);
+            case 3: return launch_reg<T, 3, 8>(a, cfg, n_packs, st);
             default: break;
         }
     } else if (cfg.reg_len == 16 && cfg.reg_slots == 1) {
-        return launch_reg<T, 1, 16>(a, cfg.lds_bytes, n_packs, st);
+        return launch_reg<T, 1, 16>(a, cfg, n_packs, st);
     }
     return hipErrorInvalidValue;
 }
