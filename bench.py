@@ -133,7 +133,8 @@ def cpu_baseline(cfg: int, budget_s: float = 20.0):
 
 def kernel_name(info: dict) -> str:
     if info["coef_mode"] == 3:
-        return f"reg_step_kernel<{info['block_threads']}, {info['reg_slots']}, {info['reg_len']}>"
+        return (f"reg_step_kernel<{info['block_threads']}, {info['reg_slots']}, {info['reg_len']}, "
+                f"{'true' if info['syn_hbm'] else 'false'}>")
     return f"step_kernel<{info['block_threads']}, {'true' if info['coef_mode'] == 1 else 'false'}>"
 
 
@@ -276,6 +277,7 @@ def main():
                    "packs": info["n_packs"], "lds_bytes": info["lds_bytes"], "spikes": int(len(spikes))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "traffic_GBps": None if traffic is None else traffic / avg_launch_s / 1e9,
                      "kernel": kernel, "bytes_per_step": info["bytes_per_step"],
                      "steps_per_launch": steps_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
                      "measured_copy_GBps": copy_gbps, "frac_of_measured_copy": achieved / copy_gbps,

@@ -732,6 +732,9 @@ int arb_plan_layout(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     I.bytes_per_step = 44 * L.n_cv + 56 * I.n_hh + 20 * I.n_syn;
     I.reg_slots = L.coef_mode == 3 ? L.reg_slots : 0;
     I.reg_len = L.coef_mode == 3 ? L.reg_len : 0;
+    I.syn_hbm = 0;
+    for (const PackDesc& D : L.packs)
+        if (L.coef_mode == 3 && D.syn_global) I.syn_hbm = 1;
     *info = I;
     return ARB_OK;
 }
@@ -999,6 +1002,7 @@ int arb_get_info(arb_sim s_, arb_info* info) {
     I.bytes_per_step = 44 * L.n_cv + 56 * I.n_hh + 20 * I.n_syn;
     I.reg_slots = s->cfg.coef_mode == 3 ? s->cfg.reg_slots : 0;
     I.reg_len = s->cfg.coef_mode == 3 ? s->cfg.reg_len : 0;
+    I.syn_hbm = s->cfg.syn_hbm;
     *info = I;
     return ARB_OK;
 }

@@ -41,7 +41,7 @@ def test_struct_layouts_match_header(tmp_path):
                     "int main(void){S(arb_branch)S(arb_cell)S(arb_synapse)S(arb_connection)S(arb_event)"
                     "S(arb_iclamp)S(arb_spike)S(arb_params)S(arb_info)"
                     "O(arb_branch,gbar_na)O(arb_cell,soma_area_um2)O(arb_params,hip_stream)"
-                    "O(arb_params,spike_capacity)O(arb_params,coef_mode)O(arb_info,bytes_per_step)O(arb_info,reg_len)return 0;}\n")
+                    "O(arb_params,spike_capacity)O(arb_params,coef_mode)O(arb_info,bytes_per_step)O(arb_info,reg_len)O(arb_info,syn_hbm)return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
@@ -63,6 +63,7 @@ def test_struct_layouts_match_header(tmp_path):
     assert got["arb_params.coef_mode"] == arbmi.arb_params.coef_mode.offset
     assert got["arb_info.bytes_per_step"] == arbmi.arb_info.bytes_per_step.offset
     assert got["arb_info.reg_len"] == arbmi.arb_info.reg_len.offset
+    assert got["arb_info.syn_hbm"] == arbmi.arb_info.syn_hbm.offset
 
 
 def _params(**kw):
