@@ -8,8 +8,9 @@ detection, and (every epoch) the spike exchange.  The default workload is the
 5 ms, dt 0.025 ms), timed over 4000 steps (100 ms of model time) after a
 warm-up epoch.  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line.  `--config 3|4|5|1` selects the other workloads and
-`--config 6` the synapse-dominated ring (10,000 expsyn per cell).
+Prints one JSON line.  `--config 3|4|5|1` selects the other workloads,
+`--config 6` the synapse-dominated ring (10,000 expsyn per cell) and
+`--config 7` the 10k-connectivity model.
 """
 from __future__ import annotations
 
@@ -60,6 +61,11 @@ def make_model(cfg: int, n_cells: int | None):
         n = n_cells or 8192
         return gen.config6(n_cells=n), (f"{n}-cell synapse-dominated ring, random trees of 90-170 CVs (mean 130), "
                                         "hh soma, pas dendrites, 10,000 expsyn/cell (one on the ring), delay 5 ms")
+    if cfg == 7:
+        n = n_cells or 8192
+        return gen.config7(n_cells=n), (f"{n}-cell 10k-connectivity model: the cells of config 6, every synapse "
+                                        "wired from a random other cell (delay 20 ms), all cells driven to fire "
+                                        "together at 50 Hz")
     raise SystemExit(f"unknown config {cfg}")
 
 
@@ -94,6 +100,8 @@ def _oracle_chunk(args):
         m = gen.config4(cells=cells)
     elif cfg == 6:
         m = gen.config6(n_cells=8192, cells=cells)
+    elif cfg == 7:
+        m = gen.config7(n_cells=8192, cells=cells)
     else:
         m = gen.config1()
     s = oracle.Sim(m)
@@ -112,9 +120,10 @@ def cpu_baseline(cfg: int, budget_s: float = 20.0):
     import oracle
     oracle.build() if not os.path.exists(oracle.LIB) else None
     workers = max(1, min(16, os.cpu_count() or 1))
-    per = {1: (1, 4000), 2: (96, 800), 3: (24, 800), 4: (64, 2000), 5: (48, 800), 6: (16, 400)}[cfg]
+    per = {1: (1, 4000), 2: (96, 800), 3: (24, 800), 4: (64, 2000), 5: (48, 800), 6: (16, 1200),
+           7: (16, 1200)}[cfg]
     n_cells, steps = per
-    base = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536, 6: 8192}[cfg]
+    base = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536, 6: 8192, 7: 8192}[cfg]
     chunks = [(cfg, [(w * n_cells + k) % base for k in range(n_cells)], steps) for w in range(workers)]
     if cfg == 1:
         chunks = [(1, [0], steps) for _ in range(workers)]
@@ -127,7 +136,8 @@ def cpu_baseline(cfg: int, budget_s: float = 20.0):
     cpu_s = sum(t for _, t in res)
     return {"value": rate, "unit": "CV-updates/s", "cores": workers, "kind": "oracle",
             "sample": (f"{workers} processes x {n_cells} cells x {steps} steps of the same workload "
-                       f"({'ring segments' if cfg in (2, 6) else 'cell chunks'}), stepping time only; "
+                       f"({'ring segments' if cfg in (2, 6) else 'cell chunks'}"
+                       f"{', connections inside a chunk only' if cfg in (5, 7) else ''}), stepping time only; "
                        f"{cpu_s:.1f} s CPU, {wall:.1f} s wall")}
 
 

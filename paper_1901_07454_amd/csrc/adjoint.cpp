@@ -50,7 +50,10 @@ std::vector<Part> state_parts(Sim* s) {
             {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
             {s->d_pk_ncur, np * 4},    {s->d_bk_cnt, nbk * 4}, {s->d_bk_ev, nbk * s->bk_cap * 8},
             {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
-            {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8}};
+            {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8},
+            {s->d_hist_cnt, int64_t(s->n_hist) * 4},
+            {s->d_hist_gid, int64_t(s->n_hist) * s->hist_cap * 4},
+            {s->d_hist_step, int64_t(s->n_hist) * s->hist_cap * 8}};
 }
 
 int save_state(Sim* s, char* dst) {

@@ -166,34 +166,51 @@ int Sim::launch_classes(const StepArgs& a0) {
     return ARB_OK;
 }
 
-// One epoch's kernels after the step arguments are set: the step kernel,
-// then (network) the exchange of the epoch's spikes; in graph mode also the
-// bucket sort before it and the device epoch counter's advance after it.
+// The epoch's network events: index the spike history by source, then every
+// pack pulls its events of the epoch into its bucket.
+int Sim::launch_pull(int64_t epoch, const int64_t* epoch_ptr) {
+    HIP_TRY(launch_index_spikes(d_hist_gid, d_hist_step, d_hist_cnt, hist_cap, n_hist, d_sx_cnt, d_sx_off, d_sx_step,
+                                L.n_cells, st));
+    PullArgs x{};
+    x.in_off = d_in_off;
+    x.cr_src = d_cr_src;
+    x.cr_delay = d_cr_delay;
+    x.sx_off = d_sx_off;
+    x.sx_step = d_sx_step;
+    x.bk_ev = d_bk_ev;
+    x.bk_cnt = d_bk_cnt;
+    x.pk_ncur = d_pk_ncur;
+    x.ctr = d_ctr;
+    x.epoch_ptr = epoch_ptr;
+    x.epoch = epoch;
+    x.bk_cap = bk_cap;
+    x.epoch_steps = K;
+    HIP_TRY(launch_pull_events(x, int32_t(L.packs.size()), st));
+    return ARB_OK;
+}
+
+// The finished epoch's spikes into its history slot.
+int Sim::launch_collect(int64_t epoch, const int64_t* epoch_ptr) {
+    HIP_TRY(launch_collect_spikes(d_ctr, d_sp_gid, d_sp_step, sp_cap, d_hist_gid, d_hist_step, d_hist_cnt, hist_cap,
+                                  n_hist, epoch, epoch_ptr, st));
+    return ARB_OK;
+}
+
+// One epoch's kernels after the step arguments are set: (network) the
+// epoch's events, the step kernel, (network) the spikes into the history;
+// in graph mode the device epoch counter's advance after them.
 int Sim::launch_epoch_sequence(const StepArgs& a, bool net, bool graph_mode) {
-    const int np = int32_t(L.packs.size());
-    if (graph_mode && net)
-        HIP_TRY(launch_sort_buckets(d_bk_ev, d_bk_cnt, d_pk_ncur, bk_cap, 0, np, d_ctr, st, d_epoch, n_buckets));
+    if (graph_mode && net) {
+        const int rc = launch_pull(0, d_epoch);
+        if (rc != ARB_OK) return rc;
+    }
     {
         const int rc = launch_classes(a);
         if (rc != ARB_OK) return rc;
     }
     if (net && a.epoch_end) {
-        ExchArgs x{};
-        x.sp_gid = d_sp_gid;
-        x.sp_step = d_sp_step;
-        x.out_off = d_out_off;
-        x.out_rank = d_out_rank;
-        x.cr_pack = d_cr_pack;
-        x.cr_delay = d_cr_delay;
-        x.bk_ev = d_bk_ev;
-        x.bk_cnt = d_bk_cnt;
-        x.bk_cap = bk_cap;
-        x.n_buckets = n_buckets;
-        x.n_packs = np;
-        x.epoch_steps = K;
-        x.sp_cap = sp_cap;
-        x.ctr = d_ctr;
-        HIP_TRY(launch_exchange(x, exch_grid, st));
+        const int rc = launch_collect(a.step0 / K, graph_mode ? d_epoch : nullptr);
+        if (rc != ARB_OK) return rc;
     }
     if (graph_mode) HIP_TRY(launch_advance_epoch(d_epoch, st));
     return ARB_OK;
@@ -236,7 +253,6 @@ int Sim::capture_epoch_graph() {
 // for the adjoint.  With ARB_FLAG_GRAPH, whole epochs replay a captured graph.
 int Sim::advance(int64_t n, const RecordArgs* rec) {
     const bool net = !L.out_rank.empty();
-    const int np = int32_t(L.packs.size());
     int64_t done = 0;
     while (n > 0) {
         const int64_t e = step / K, pos = step % K;
@@ -277,8 +293,10 @@ int Sim::advance(int64_t n, const RecordArgs* rec) {
         }
         const int64_t nthis = std::min<int64_t>(n, K - pos);
         const int32_t bucket = int32_t(e % n_buckets);
-        if (net && pos == 0)
-            HIP_TRY(launch_sort_buckets(d_bk_ev, d_bk_cnt, d_pk_ncur, bk_cap, bucket, np, d_ctr, st));
+        if (net && pos == 0) {
+            const int rc = launch_pull(e, nullptr);
+            if (rc != ARB_OK) return rc;
+        }
         StepArgs a = step_args();
         a.bucket = bucket;
         a.step0 = step;
@@ -321,22 +339,8 @@ int Sim::advance(int64_t n, const RecordArgs* rec) {
         n -= nthis;
         done += nthis;
         if (net && a.epoch_end) {
-            ExchArgs x{};
-            x.sp_gid = d_sp_gid;
-            x.sp_step = d_sp_step;
-            x.out_off = d_out_off;
-            x.out_rank = d_out_rank;
-            x.cr_pack = d_cr_pack;
-            x.cr_delay = d_cr_delay;
-            x.bk_ev = d_bk_ev;
-            x.bk_cnt = d_bk_cnt;
-            x.bk_cap = bk_cap;
-            x.n_buckets = n_buckets;
-            x.n_packs = np;
-            x.epoch_steps = K;
-            x.sp_cap = sp_cap;
-            x.ctr = d_ctr;
-            HIP_TRY(launch_exchange(x, exch_grid, st));
+            const int rc = launch_collect(e, nullptr);
+            if (rc != ARB_OK) return rc;
         }
     }
     return ARB_OK;
@@ -426,31 +430,11 @@ int build_device(Sim* s) {
     s->d_pk_xcur = dupload(s, xcur, rc);
     s->d_pk_ncur = dupload(s, std::vector<int32_t>(np, 0), rc);
     s->d_cr_syn = dupload(s, L.cr_syn, rc);
-    s->d_cr_pack = dupload(s, L.cr_pack, rc);
     s->d_cr_delay = dupload(s, L.cr_delay, rc);
+    s->d_cr_src = dupload(s, L.cr_src, rc);
     s->d_cr_w = dupload(s, L.cr_w, rc);
-    s->d_out_off = dupload(s, L.out_off, rc);
-    s->d_out_rank = dupload(s, L.out_rank, rc);
+    s->d_in_off = dupload(s, L.in_off, rc);
     s->d_perm = dupload(s, L.perm, rc);
-    // network event buckets
-    const bool net = !L.out_rank.empty();
-    if (net) {
-        s->n_buckets = int32_t(2 + (L.max_delay + s->K - 1) / s->K);
-        int64_t cap = s->p.event_capacity;
-        if (cap <= 0) cap = std::max<int64_t>(64, 4 * L.max_in_per_pack);
-        // the per-pack sort stages a run in LDS, rounded up to a power of two
-        int64_t lim = 1;
-        while (lim * 2 * 8 <= std::min<int64_t>(s->lds_max - 256, 128 * 1024)) lim *= 2;
-        cap = std::min<int64_t>(cap, lim);
-        s->bk_cap = int32_t(cap);
-    } else {
-        s->n_buckets = 1;
-        s->bk_cap = 0;
-    }
-    const size_t nbk = size_t(s->n_buckets) * size_t(np);
-    s->d_bk_cnt = dalloc<uint32_t>(s, nbk, rc);
-    if (rc == ARB_OK) rc = s->fill_zero(s->d_bk_cnt, nbk * sizeof(uint32_t));
-    s->d_bk_ev = dalloc<uint64_t>(s, std::max<size_t>(1, nbk * size_t(s->bk_cap)), rc);
     // spikes
     int64_t spc = s->p.spike_capacity;
     if (spc <= 0) spc = std::max<int64_t>(1 << 16, int64_t(L.n_cells) * 64);
@@ -459,6 +443,34 @@ int build_device(Sim* s) {
     s->d_sp_gid = dalloc<uint32_t>(s, s->sp_cap, rc);
     s->d_sp_step = dalloc<int64_t>(s, s->sp_cap, rc);
     s->d_sp_t = dalloc<double>(s, s->sp_cap, rc);
+    // network: one event bucket per pack for the running epoch, and the spike
+    // history of the epochs whose spikes can still arrive (a spike of epoch
+    // e - n_hist + 1 .. e - 1 can deliver into epoch e, none of epoch e)
+    const bool net = !L.out_rank.empty();
+    s->n_buckets = 1;
+    if (net) {
+        int64_t cap = s->p.event_capacity;
+        if (cap <= 0) cap = std::max<int64_t>(64, 4 * L.max_in_per_pack);
+        s->bk_cap = int32_t(std::min<int64_t>(cap, INT32_MAX));
+        s->n_hist = int32_t(1 + (L.max_delay + s->K - 1) / s->K);
+        s->hist_cap = s->sp_cap;
+    } else {
+        s->bk_cap = 0;
+        s->n_hist = 1;
+        s->hist_cap = 0;
+    }
+    const size_t nbk = size_t(np);
+    s->d_bk_cnt = dalloc<uint32_t>(s, nbk, rc);
+    if (rc == ARB_OK) rc = s->fill_zero(s->d_bk_cnt, nbk * sizeof(uint32_t));
+    s->d_bk_ev = dalloc<uint64_t>(s, std::max<size_t>(1, nbk * size_t(s->bk_cap)), rc);
+    const size_t nh = std::max<size_t>(1, size_t(s->n_hist) * s->hist_cap);
+    s->d_hist_gid = dalloc<uint32_t>(s, nh, rc);
+    s->d_hist_step = dalloc<int64_t>(s, nh, rc);
+    s->d_hist_cnt = dalloc<uint32_t>(s, size_t(s->n_hist), rc);
+    if (rc == ARB_OK) rc = s->fill_zero(s->d_hist_cnt, size_t(s->n_hist) * sizeof(uint32_t));
+    s->d_sx_cnt = dalloc<int32_t>(s, size_t(L.n_cells) + 1, rc);
+    s->d_sx_off = dalloc<int64_t>(s, size_t(L.n_cells) + 1, rc);
+    s->d_sx_step = dalloc<int64_t>(s, nh, rc);
     s->d_epoch = dalloc<int64_t>(s, 1, rc);
     s->d_ctr = dalloc<Counters>(s, 1, rc);
     if (rc == ARB_OK) rc = s->fill_zero(s->d_ctr, sizeof(Counters));
@@ -514,7 +526,12 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
         return ARB_EHIP;
     }
     const bool net = !s->L.out_rank.empty();
-    s->K = p->epoch_steps > 0 ? p->epoch_steps : (net ? s->L.min_delay : 1000);
+    s->K = p->epoch_steps > 0 ? p->epoch_steps : (net ? std::min(s->L.min_delay, kMaxEpochSteps) : 1000);
+    if (net && s->K > kMaxEpochSteps) {
+        delete s;
+        err = "epoch_steps exceeds 16384 in a network";
+        return ARB_EINVAL;
+    }
     s->cfg.block_threads = s->L.block_threads;
     s->cfg.coef_mode = s->L.coef_mode;
     s->cfg.reg_slots = s->L.reg_slots;
@@ -531,7 +548,6 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
         return ARB_EINVAL;
     }
     s->cfg.lds_bytes = int(std::max<int64_t>(lds, 8));
-    s->exch_grid = std::max(1, std::min(4 * d.n_cu, int((m.n_cells + 3) / 4)));
     // classes by workgroups per CU the LDS allows: 1, 2, 3, 4 or more.  Packs
     // come out of the packer largest first, so each class is a contiguous
     // range; a class's LDS is its largest pack's.
@@ -723,7 +739,8 @@ int arb_plan_layout(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     I.n_hh = int64_t(L.hh_cv.size());
     I.n_syn = int64_t(L.syn_pack_index.size());  // the model's synapses (pack order may pad)
     I.n_conn = int64_t(L.out_rank.size());
-    I.epoch_steps = p->epoch_steps > 0 ? p->epoch_steps : (L.out_rank.empty() ? 1000 : L.min_delay);
+    I.epoch_steps = p->epoch_steps > 0 ? p->epoch_steps
+                                       : (L.out_rank.empty() ? 1000 : std::min(L.min_delay, kMaxEpochSteps));
     I.block_threads = L.block_threads;
     I.coef_mode = L.coef_mode;
     int64_t lds = 0;
@@ -904,12 +921,12 @@ int arb_set_params(arb_sim s_, const double* theta, int64_t n) {
 }
 
 // blob: header, then V, hh m/h/n, syn g, ext cursors, net cursors, bucket
-// counts and keys, counters, spike buffer
+// counts and keys, counters, spike buffer, spike history
 struct StateHeader {
     uint64_t magic;
     int64_t step, n_slots, n_hh, n_syn, n_packs, n_bk, bk_cap, sp_cap, sp_user;
 };
-static const uint64_t kMagic = 0x41524232535441ull;
+static const uint64_t kMagic = 0x41524233535441ull;
 
 int arb_get_state(arb_sim s_, void* blob, int64_t cap, int64_t* n_out) {
     Sim* s = static_cast<Sim*>(s_);
@@ -922,7 +939,10 @@ int arb_get_state(arb_sim s_, void* blob, int64_t cap, int64_t* n_out) {
                           {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
                           {s->d_pk_ncur, np * 4},    {s->d_bk_cnt, nbk * 4}, {s->d_bk_ev, nbk * s->bk_cap * 8},
                           {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
-                          {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8}};
+                          {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8},
+                          {s->d_hist_cnt, int64_t(s->n_hist) * 4},
+                          {s->d_hist_gid, int64_t(s->n_hist) * s->hist_cap * 4},
+                          {s->d_hist_step, int64_t(s->n_hist) * s->hist_cap * 8}};
     int64_t total = sizeof(StateHeader);
     for (const Part& q : parts) total += q.bytes;
     *n_out = total;
@@ -957,7 +977,10 @@ int arb_set_state(arb_sim s_, const void* blob, int64_t n) {
                           {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
                           {s->d_pk_ncur, np * 4},    {s->d_bk_cnt, nbk * 4}, {s->d_bk_ev, nbk * s->bk_cap * 8},
                           {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
-                          {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8}};
+                          {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8},
+                          {s->d_hist_cnt, int64_t(s->n_hist) * 4},
+                          {s->d_hist_gid, int64_t(s->n_hist) * s->hist_cap * 4},
+                          {s->d_hist_step, int64_t(s->n_hist) * s->hist_cap * 8}};
     int64_t total = sizeof(StateHeader);
     for (const Part& q : parts) total += q.bytes;
     if (n < total) return fail(ARB_EINVAL, "state blob truncated");

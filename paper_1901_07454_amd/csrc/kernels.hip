@@ -17,6 +17,9 @@
 // factorisation (F, 1/d') is computed once on the host.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
+
 #include "kernel_common.hpp"
 #include "kernels.hpp"
 
@@ -338,69 +341,168 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
     }
 }
 
-__global__ void __launch_bounds__(256) sort_buckets_kernel(uint64_t* bk_ev, uint32_t* bk_cnt, int32_t* pk_ncur,
-                                                           int32_t cap, int32_t bucket, int32_t n_packs,
-                                                           Counters* ctr, const int64_t* epoch_ptr,
-                                                           int32_t n_buckets) {
-    extern __shared__ uint64_t keys[];
-    const int p = blockIdx.x;
-    const int tid = threadIdx.x;
-    if (epoch_ptr) bucket = int32_t(*epoch_ptr % n_buckets);
-    const int64_t base_i = int64_t(bucket) * n_packs + p;
-    uint32_t n = bk_cnt[base_i];
-    if (tid == 0) pk_ncur[p] = 0;
-    if (n > uint32_t(cap)) {
-        if (tid == 0) atomicOr(&ctr->flags, kFlagEventOverflow);
-        n = uint32_t(cap);
+// ---------------------------------------------------------------------------
+// Spike exchange between epochs.  An event reaches its synapse no earlier
+// than the minimum delay after the spike (Sec. II), and an epoch is no
+// longer than that, so the events of epoch e come only from spikes of
+// earlier epochs.  At each epoch end the epoch's spikes are copied into a
+// ring of per-epoch history slots covering the longest delay; at each epoch
+// start the history is indexed by source gid and every pack pulls its
+// incoming connections (ranks in order) against the index, writing its
+// bucket of the epoch already in (step, rank) order.
+
+__global__ void __launch_bounds__(256) collect_spikes_kernel(Counters* ctr, const uint32_t* sp_gid,
+                                                             const int64_t* sp_step, uint32_t sp_cap,
+                                                             uint32_t* h_gid, int64_t* h_step, uint32_t* h_cnt,
+                                                             uint32_t h_cap, int32_t n_hist, int64_t epoch,
+                                                             const int64_t* epoch_ptr) {
+    const int64_t e = epoch_ptr ? *epoch_ptr : epoch;
+    const int64_t slot = e % n_hist;
+    const uint32_t b = ctr->sp_exch;
+    const uint32_t end = ctr->sp_count < sp_cap ? ctr->sp_count : sp_cap;
+    const uint32_t n = end > b ? end - b : 0u;
+    const uint32_t m = n < h_cap ? n : h_cap;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        h_gid[slot * h_cap + i] = sp_gid[b + i];
+        h_step[slot * h_cap + i] = sp_step[b + i];
     }
-    if (n <= 1) return;
-    uint32_t m = 1;
-    while (m < n) m <<= 1;
-    uint64_t* base = bk_ev + base_i * cap;
-    for (uint32_t i = tid; i < m; i += blockDim.x) keys[i] = (i < n) ? base[i] : ~uint64_t(0);
-    __syncthreads();
-    for (uint32_t k = 2; k <= m; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = tid; i < m; i += blockDim.x) {
-                const uint32_t ixj = i ^ j;
-                if (ixj > i) {
-                    const bool up = (i & k) == 0;
-                    const uint64_t x = keys[i], y = keys[ixj];
-                    if ((x > y) == up) {
-                        keys[i] = y;
-                        keys[ixj] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        h_cnt[slot] = m;
+        if (n > h_cap) atomicOr(&ctr->flags, kFlagEventOverflow);
     }
-    for (uint32_t i = tid; i < n; i += blockDim.x) base[i] = keys[i];
 }
 
-__global__ void __launch_bounds__(256) exchange_kernel(ExchArgs a) {
-    const uint32_t sp_cap = a.sp_cap;
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
-    const uint32_t b = a.ctr->sp_exch;
-    uint32_t e = a.ctr->sp_count;
-    if (e > sp_cap) e = sp_cap;
-    for (int64_t i = int64_t(b) + wave; i < int64_t(e); i += nwaves) {
-        const uint32_t gid = a.sp_gid[i];
-        const int64_t st = a.sp_step[i];
-        for (int64_t c = a.out_off[gid] + lane; c < a.out_off[gid + 1]; c += 64) {
-            const uint32_t r = a.out_rank[c];
-            const int32_t pkk = a.cr_pack[r];
-            const int64_t sd = st + a.cr_delay[r];
-            const int32_t bk = int32_t((sd / a.epoch_steps) % a.n_buckets);
-            const int64_t slot = int64_t(bk) * a.n_packs + pkk;
-            const uint32_t pos = atomicAdd(&a.bk_cnt[slot], 1u);
-            if (pos < uint32_t(a.bk_cap))
-                a.bk_ev[slot * a.bk_cap + pos] = (uint64_t(sd) << 32) | uint64_t(r);
-            else
-                atomicOr(&a.ctr->flags, kFlagEventOverflow);
+__global__ void __launch_bounds__(256) sx_clear_kernel(int32_t* cnt, int32_t n) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) cnt[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) sx_count_kernel(const uint32_t* h_gid, const uint32_t* h_cnt, uint32_t h_cap,
+                                                       int32_t n_hist, int32_t* cnt) {
+    const int64_t total = int64_t(n_hist) * h_cap;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x)
+        if (uint32_t(i % h_cap) < h_cnt[i / h_cap]) atomicAdd(&cnt[h_gid[i]], 1);
+}
+
+// Exclusive scan of cnt[0, n) into off[0, n] by one workgroup (each thread
+// sums a contiguous segment, the segment sums are scanned in LDS); cnt is
+// cleared for use as fill counters.
+__global__ void __launch_bounds__(1024) sx_scan_kernel(int32_t* cnt, int64_t* off, int32_t n) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int32_t seg = (n + 1023) / 1024;
+    const int32_t i0 = t * seg < n ? t * seg : n, i1 = i0 + seg < n ? i0 + seg : n;
+    int64_t sum = 0;
+    for (int32_t i = i0; i < i1; ++i) sum += cnt[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t x = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    int64_t run = part[t] - sum;
+    for (int32_t i = i0; i < i1; ++i) {
+        off[i] = run;
+        run += cnt[i];
+        cnt[i] = 0;
+    }
+    if (t == 1023) off[n] = part[1023];
+}
+
+__global__ void __launch_bounds__(256) sx_scatter_kernel(const uint32_t* h_gid, const int64_t* h_step,
+                                                         const uint32_t* h_cnt, uint32_t h_cap, int32_t n_hist,
+                                                         const int64_t* off, int32_t* cnt, int64_t* sx_step) {
+    const int64_t total = int64_t(n_hist) * h_cap;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x)
+        if (uint32_t(i % h_cap) < h_cnt[i / h_cap]) {
+            const uint32_t g = h_gid[i];
+            sx_step[off[g] + atomicAdd(&cnt[g], 1)] = h_step[i];
         }
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+// One wave per pack.  Pass 1 counts the epoch's events per step (LDS
+// counters over the K steps), a scan turns the counts into each step's
+// first position, and pass 2 walks the connections again in rank order, 64
+// at a time: the chunk's events are placed step by step, increasing, a
+// lane's event at its step's cursor plus the number of lower lanes with an
+// event at that step, so every step's events are in rank order.
+__global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
+    extern __shared__ uint32_t bins[];
+    const int p = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t e = a.epoch_ptr ? *a.epoch_ptr : a.epoch;
+    const int K = a.epoch_steps;
+    const int64_t lo = e * K;
+    const int64_t r0 = a.in_off[p], r1 = a.in_off[p + 1];
+    for (int b = lane; b < K; b += 64) bins[b] = 0u;
+    __syncthreads();
+    for (int64_t r = r0 + lane; r < r1; r += 64) {
+        const uint32_t src = a.cr_src[r];
+        const int64_t d = a.cr_delay[r];
+        const int64_t k1 = a.sx_off[src + 1];
+        for (int64_t k = a.sx_off[src]; k < k1; ++k) {
+            const int64_t b = a.sx_step[k] + d - lo;
+            if (b >= 0 && b < K) atomicAdd(&bins[b], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t run = 0;
+    for (int b0 = 0; b0 < K; b0 += 64) {
+        const int b = b0 + lane;
+        const uint32_t c = b < K ? bins[b] : 0u;
+        uint32_t x = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (b < K) bins[b] = run + x - c;
+        run += __shfl(x, 63);
+    }
+    const uint32_t total = run;
+    __syncthreads();
+    const uint32_t cap = uint32_t(a.bk_cap);
+    uint64_t* out = a.bk_ev + int64_t(p) * a.bk_cap;
+    const uint64_t below = (uint64_t(1) << lane) - 1u;
+    for (int64_t c0 = r0; c0 < r1; c0 += 64) {
+        const int64_t r = c0 + lane;
+        int64_t d = 0, k0 = 0, k1 = 0;
+        if (r < r1) {
+            const uint32_t src = a.cr_src[r];
+            d = a.cr_delay[r];
+            k0 = a.sx_off[src];
+            k1 = a.sx_off[src + 1];
+        }
+        int last = -1;
+        for (;;) {
+            int mine = INT_MAX;  // this lane's first event step after `last`
+            for (int64_t k = k0; k < k1; ++k) {
+                const int64_t b = a.sx_step[k] + d - lo;
+                if (b > last && b < K && b < mine) mine = int(b);
+            }
+            const int B = wave_min(mine);
+            if (B == INT_MAX) break;
+            const uint64_t mask = __ballot(mine == B);
+            const uint32_t base = bins[B];
+            if (mine == B) {
+                const uint32_t pos = base + uint32_t(__popcll(mask & below));
+                if (pos < cap) out[pos] = (uint64_t(lo + B) << 32) | uint64_t(uint32_t(r));
+            }
+            __syncthreads();
+            if (lane == 0) bins[B] = base + uint32_t(__popcll(mask));
+            __syncthreads();
+            last = B;
+        }
+    }
+    if (lane == 0) {
+        a.bk_cnt[p] = total < cap ? total : cap;
+        a.pk_ncur[p] = 0;
+        if (total > cap) atomicOr(&a.ctr->flags, kFlagEventOverflow);
     }
 }
 
@@ -449,7 +551,7 @@ hipError_t prepare_step_kernels(int max_lds) {
                          reinterpret_cast<const void*>(&step_kernel<128, false>),
                          reinterpret_cast<const void*>(&step_kernel<256, true>),
                          reinterpret_cast<const void*>(&step_kernel<256, false>),
-                         reinterpret_cast<const void*>(&sort_buckets_kernel)};
+                         reinterpret_cast<const void*>(&pull_events_kernel)};
     for (const void* f : fns) allow_lds(f, max_lds);
     return prepare_reg_kernels(max_lds);
 }
@@ -465,26 +567,38 @@ hipError_t launch_step(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hip
     }
 }
 
-hipError_t launch_sort_buckets(uint64_t* bk_ev, uint32_t* bk_cnt, int32_t* pk_ncur, int32_t bk_cap,
-                               int32_t bucket, int32_t n_packs, Counters* ctr, hipStream_t st,
-                               const int64_t* epoch_ptr, int32_t n_buckets) {
-    int m = 1;
-    while (m < bk_cap) m <<= 1;
-    hipLaunchKernelGGL(sort_buckets_kernel, dim3(n_packs), dim3(256), size_t(m) * 8, st, bk_ev, bk_cnt, pk_ncur,
-                       bk_cap, bucket, n_packs, ctr, epoch_ptr, n_buckets);
-    return hipGetLastError();
-}
-
 hipError_t launch_advance_epoch(int64_t* epoch, hipStream_t st) {
     hipLaunchKernelGGL(advance_epoch_kernel, dim3(1), dim3(1), 0, st, epoch);
     return hipGetLastError();
 }
 
-hipError_t launch_exchange(const ExchArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(exchange_kernel, dim3(grid), dim3(256), 0, st, a);
+hipError_t launch_collect_spikes(Counters* ctr, const uint32_t* sp_gid, const int64_t* sp_step, uint32_t sp_cap,
+                                 uint32_t* h_gid, int64_t* h_step, uint32_t* h_cnt, uint32_t h_cap, int32_t n_hist,
+                                 int64_t epoch, const int64_t* epoch_ptr, hipStream_t st) {
+    hipLaunchKernelGGL(collect_spikes_kernel, dim3(256), dim3(256), 0, st, ctr, sp_gid, sp_step, sp_cap, h_gid, h_step,
+                       h_cnt, h_cap, n_hist, epoch, epoch_ptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(commit_exchange_kernel, dim3(1), dim3(1), 0, st, a.ctr, a.sp_cap);
+    hipLaunchKernelGGL(commit_exchange_kernel, dim3(1), dim3(1), 0, st, ctr, sp_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_index_spikes(const uint32_t* h_gid, const int64_t* h_step, const uint32_t* h_cnt, uint32_t h_cap,
+                               int32_t n_hist, int32_t* sx_cnt, int64_t* sx_off, int64_t* sx_step, int32_t n_cells,
+                               hipStream_t st) {
+    const int64_t total = int64_t(n_hist) * h_cap;
+    const unsigned gc = unsigned(std::min<int64_t>(1024, (n_cells + 255) / 256 + 1));
+    const unsigned gh = unsigned(std::min<int64_t>(2048, (total + 255) / 256 + 1));
+    hipLaunchKernelGGL(sx_clear_kernel, dim3(gc), dim3(256), 0, st, sx_cnt, n_cells);
+    hipLaunchKernelGGL(sx_count_kernel, dim3(gh), dim3(256), 0, st, h_gid, h_cnt, h_cap, n_hist, sx_cnt);
+    hipLaunchKernelGGL(sx_scan_kernel, dim3(1), dim3(1024), 0, st, sx_cnt, sx_off, n_cells);
+    hipLaunchKernelGGL(sx_scatter_kernel, dim3(gh), dim3(256), 0, st, h_gid, h_step, h_cnt, h_cap, n_hist, sx_off,
+                       sx_cnt, sx_step);
+    return hipGetLastError();
+}
+
+hipError_t launch_pull_events(const PullArgs& a, int32_t n_packs, hipStream_t st) {
+    hipLaunchKernelGGL(pull_events_kernel, dim3(n_packs), dim3(64), size_t(a.epoch_steps) * 4, st, a);
     return hipGetLastError();
 }
 

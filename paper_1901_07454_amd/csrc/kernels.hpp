@@ -103,33 +103,39 @@ hipError_t prepare_step_kernels(int max_lds_bytes);
 hipError_t launch_reg_step(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st);
 hipError_t prepare_reg_kernels(int max_lds_bytes);
 
-// Sort each pack's run of network events of `bucket` (keys ascending) and
-// reset the packs' cursors.  Flags an overflow if a run exceeded bk_cap.
-hipError_t launch_sort_buckets(uint64_t* bk_ev, uint32_t* bk_cnt, int32_t* pk_ncur, int32_t bk_cap,
-                               int32_t bucket, int32_t n_packs, Counters* ctr, hipStream_t st,
-                               const int64_t* epoch_ptr = nullptr, int32_t n_buckets = 1);
 // ++*epoch (end of a replayed epoch)
 hipError_t launch_advance_epoch(int64_t* epoch, hipStream_t st);
 
-// Turn the spikes [ctr.sp_exch, ctr.sp_count) into network events.
-struct ExchArgs {
-    const uint32_t* sp_gid;
-    const int64_t* sp_step;
-    const int64_t* out_off;
-    const uint32_t* out_rank;
-    const int32_t* cr_pack;
-    const int32_t* cr_delay;
-    uint64_t* bk_ev;
-    uint32_t* bk_cnt;
-    int32_t bk_cap;
-    int32_t n_buckets;
-    int32_t n_packs;
-    int32_t epoch_steps;
-    uint32_t sp_cap;
-    uint32_t pad;
+// Spike exchange between epochs (Sec. II min-delay epochs, Sec. IV-A).
+// Epoch end: copy the spikes [ctr.sp_exch, ctr.sp_count) into history slot
+// epoch % n_hist (h_cap entries each; overflow is flagged) and mark them
+// exchanged.  `epoch_ptr`, when set, holds the epoch instead of `epoch`.
+hipError_t launch_collect_spikes(Counters* ctr, const uint32_t* sp_gid, const int64_t* sp_step, uint32_t sp_cap,
+                                 uint32_t* h_gid, int64_t* h_step, uint32_t* h_cnt, uint32_t h_cap, int32_t n_hist,
+                                 int64_t epoch, const int64_t* epoch_ptr, hipStream_t st);
+// Epoch start: index the history's spikes by source gid: sx_off[n_cells + 1]
+// (exclusive offsets) and sx_step (their steps); sx_cnt[n_cells] is scratch.
+hipError_t launch_index_spikes(const uint32_t* h_gid, const int64_t* h_step, const uint32_t* h_cnt, uint32_t h_cap,
+                               int32_t n_hist, int32_t* sx_cnt, int64_t* sx_off, int64_t* sx_step, int32_t n_cells,
+                               hipStream_t st);
+// Epoch start, after the index: each pack's network events of the epoch,
+// keys (step << 32 | rank) sorted, into its bucket; resets its cursor.
+struct PullArgs {
+    const int64_t* in_off;     // [n_packs + 1] first connection rank of each pack
+    const uint32_t* cr_src;    // per rank: source gid
+    const int32_t* cr_delay;   // per rank: delay in steps
+    const int64_t* sx_off;
+    const int64_t* sx_step;
+    uint64_t* bk_ev;           // [n_packs][bk_cap]
+    uint32_t* bk_cnt;          // [n_packs]
+    int32_t* pk_ncur;          // [n_packs]
     Counters* ctr;
+    const int64_t* epoch_ptr;  // or null: `epoch`
+    int64_t epoch;
+    int32_t bk_cap;
+    int32_t epoch_steps;       // K: LDS holds one counter per step
 };
-hipError_t launch_exchange(const ExchArgs& a, int grid, hipStream_t st);
+hipError_t launch_pull_events(const PullArgs& a, int32_t n_packs, hipStream_t st);
 
 // dst[i] = V[perm[i]] for i < n
 hipError_t launch_gather(const double* V, const int64_t* perm, double* dst, int64_t n, hipStream_t st);

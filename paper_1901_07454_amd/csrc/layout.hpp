@@ -75,6 +75,14 @@ constexpr int kSpreadHH = 20;
 // keeps their state in HBM and streams it every step.
 constexpr int64_t kSynLdsMax = 16384;
 
+// Incoming connections a pack of several cells may have: one workgroup
+// pulls and delivers all of its pack's network events.
+constexpr int64_t kPackInMax = 4096;
+
+// Longest epoch of a network (steps): events are placed per step with one
+// LDS counter per step of the epoch.
+constexpr int32_t kMaxEpochSteps = 16384;
+
 // Doubles of the register-resident kernel's V and R blocks (64 V then 64 R per
 // 64 slots) for a pack: every slot and the spare slot.  The kernel and the
 // LDS accounting below both use this.

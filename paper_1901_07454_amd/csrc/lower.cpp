@@ -62,7 +62,7 @@ int64_t locate(const arb_cell& c, const arb_branch* br, const std::vector<int>& 
 struct PackPlan {
     std::vector<int32_t> cells;
     int64_t nslot = 0;
-    int64_t nsyn = 0, nhh = 0, nbr = 0, nic = 0;
+    int64_t nsyn = 0, nhh = 0, nbr = 0, nic = 0, nin = 0;
 };
 
 }  // namespace
@@ -244,6 +244,8 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             nsyn_cell[c] += nsyn_cv[i];
             nic_cell[c] += nic_cv[i];
         }
+    std::vector<int64_t> nin_cell(n_cells, 0);  // incoming connections
+    for (int64_t q = 0; q < n_conn; ++q) nin_cell[conn[q].dst]++;
 
     // -------------------------------------------------------------- packing
     const int T = opt.block_threads;
@@ -362,7 +364,9 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             trial.nhh += nhh_cell[c];
             trial.nbr += cells[c].n_branch;
             trial.nic += nic_cell[c];
-            bool fits = int64_t(trial.cells.size()) <= max_cells;
+            trial.nin += nin_cell[c];
+            // a cell alone always makes a pack
+            bool fits = cur.cells.empty() || (int64_t(trial.cells.size()) <= max_cells && trial.nin <= kPackInMax);
             if (fits && !cur.cells.empty()) fits = exact_lds(trial, coef_mode) <= opt.lds_budget;
             if (!fits) {
                 plans.push_back(cur);
@@ -372,6 +376,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                 cur.nhh = nhh_cell[c];
                 cur.nbr = cells[c].n_branch;
                 cur.nic = nic_cell[c];
+                cur.nin = nin_cell[c];
             } else {
                 cur = trial;
             }
@@ -686,23 +691,30 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         }
     }
 
-    // connections: rank by (dst pack, pack synapse, src, index); CSR by source
+    // connections: rank by (dst pack, pack synapse, src, index); CSR by source.
+    // A pack's synapse positions are contiguous and packs follow each other,
+    // so ordering by position orders by pack: a counting sort by position
+    // (stable, so by index within a position), then by source where several
+    // connections share a synapse.
     {
+        const size_t npos = L.syn_global.size();
+        std::vector<int64_t> at(npos + 1, 0);
+        for (int64_t q = 0; q < n_conn; ++q) at[size_t(L.syn_pack_index[conn[q].syn]) + 1]++;
+        for (size_t k = 0; k < npos; ++k) at[k + 1] += at[k];
         std::vector<int64_t> idx(n_conn);
-        std::iota(idx.begin(), idx.end(), 0);
-        std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
-            const arb_connection &A = conn[a], &B = conn[b];
-            const int64_t pa = pack_of_cell[A.dst], pb = pack_of_cell[B.dst];
-            if (pa != pb) return pa < pb;
-            const int64_t sa = L.syn_pack_index[A.syn], sb = L.syn_pack_index[B.syn];
-            if (sa != sb) return sa < sb;
-            if (A.src != B.src) return A.src < B.src;
-            return a < b;
-        });
+        {
+            std::vector<int64_t> fill(at.begin(), at.end() - 1);
+            for (int64_t q = 0; q < n_conn; ++q) idx[size_t(fill[size_t(L.syn_pack_index[conn[q].syn])]++)] = q;
+        }
+        for (size_t k = 0; k < npos; ++k)
+            if (at[k + 1] - at[k] > 1)
+                std::stable_sort(idx.begin() + at[k], idx.begin() + at[k + 1],
+                                 [&](int64_t a, int64_t b) { return conn[a].src < conn[b].src; });
         if (n_conn >= (int64_t(1) << 32)) { err = "too many connections"; return ARB_EINVAL; }
         L.cr_pack.resize(n_conn);
         L.cr_syn.resize(n_conn);
         L.cr_delay.resize(n_conn);
+        L.cr_src.resize(n_conn);
         L.cr_w.resize(n_conn);
         std::vector<int64_t> in_per_pack(n_packs, 0);
         L.out_off.assign(n_cells + 1, 0);
@@ -712,11 +724,14 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             L.cr_pack[r] = int32_t(pk);
             L.cr_syn[r] = int32_t(L.syn_pack_index[K.syn] - L.packs[pk].syn0);
             L.cr_delay[r] = K.delay_steps;
+            L.cr_src[r] = K.src;
             L.cr_w[r] = 1000.0 * K.w_uS;
             in_per_pack[pk]++;
             L.out_off[K.src + 1]++;
         }
         L.max_in_per_pack = n_packs ? *std::max_element(in_per_pack.begin(), in_per_pack.end()) : 0;
+        L.in_off.assign(n_packs + 1, 0);
+        for (int64_t pk = 0; pk < n_packs; ++pk) L.in_off[pk + 1] = L.in_off[pk] + in_per_pack[pk];
         for (int32_t c = 0; c < n_cells; ++c) L.out_off[c + 1] += L.out_off[c];
         L.out_rank.resize(n_conn);
         std::vector<int64_t> fill(n_cells, 0);
@@ -735,6 +750,16 @@ std::string verify_layout(const Lowered& L) {
         if (pos < 0 || pos >= int64_t(L.syn_global.size()) || L.syn_global[pos] != int64_t(q))
             return fmt("synapse %zu has no pack-order position", q);
     }
+    // connection ranks grouped by destination pack, in pack order
+    if (!L.cr_pack.empty()) {
+        if (L.in_off.size() != L.packs.size() + 1 || L.in_off.back() != int64_t(L.cr_pack.size()))
+            return "connection rank ranges do not cover the ranks";
+        for (size_t r = 0; r < L.cr_pack.size(); ++r) {
+            const int32_t pk = L.cr_pack[r];
+            if (int64_t(r) < L.in_off[size_t(pk)] || int64_t(r) >= L.in_off[size_t(pk) + 1])
+                return fmt("connection rank %zu outside its pack's range", r);
+        }
+    }
     // every user CV in exactly one slot, slots inside their pack
     std::vector<int32_t> hit(L.n_slots, 0);
     for (int64_t i = 0; i < L.n_cv; ++i) {
@@ -744,7 +769,7 @@ std::string verify_layout(const Lowered& L) {
     }
     for (size_t pk = 0; pk < L.packs.size(); ++pk) {
         const PackDesc& D = L.packs[pk];
-        if (D.ncell > L.block_threads) return fmt("pack %zu has more cells than threads", pk);
+        if (D.ncell < 1 || D.ncell > L.block_threads) return fmt("pack %zu has no cell or more cells than threads", pk);
         // round order: a task's children finished in earlier rounds (elimination
         // runs rounds in order); its parent's slot lies in a later round
         std::vector<int32_t> round_of_slot(D.nslot, -1);

@@ -244,6 +244,14 @@ __device__ __forceinline__ void pass_down(Slot<L>& g, const double* sY, double* 
 // barrier and no wait: a wave's LDS operations take effect in issue order,
 // so the next round's loads see this round's stores.
 template <int T>
+__device__ __forceinline__ int block_count(bool pred) {
+    if constexpr (T == 64)
+        return __popcll(__ballot(pred));
+    else
+        return __syncthreads_count(pred);
+}
+
+template <int T>
 __device__ __forceinline__ void round_sync() {
     if constexpr (T == 64)
         __builtin_amdgcn_wave_barrier();
@@ -336,18 +344,13 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     }
     const int64_t bk_base = (int64_t(bucket) * a.n_packs + p);
     const uint64_t* ev = a.bk_ev + bk_base * a.bk_cap;
-    int32_t ncur = 0, nend = 0;
-    int64_t xcur = 0;
-    uint64_t nkey = ~uint64_t(0);
-    int64_t xstep = INT64_MAX;
-    if (tid == 0) {
-        xcur = a.pk_xcur[p];
-        ncur = a.pk_ncur[p];
-        const uint32_t c = a.bk_cnt[bk_base];
-        nend = int32_t(c < uint32_t(a.bk_cap) ? c : uint32_t(a.bk_cap));
-        if (ncur < nend) nkey = ev[ncur];
-        if (xcur < pk.xe1) xstep = a.xe_step[xcur];
-    }
+    // event cursors, the same in every thread
+    int64_t xcur = a.pk_xcur[p];
+    int32_t ncur = a.pk_ncur[p];
+    const uint32_t bk_c = a.bk_cnt[bk_base];
+    const int32_t nend = int32_t(bk_c < uint32_t(a.bk_cap) ? bk_c : uint32_t(a.bk_cap));
+    uint64_t nkey = (ncur < nend) ? ev[ncur] : ~uint64_t(0);
+    int64_t xstep = (xcur < pk.xe1) ? a.xe_step[xcur] : INT64_MAX;
     const int soma = (tid < pk.ncell) ? vix(a.pc_soma[pk.cell0 + tid]) : -1;
     double vold = 0.0;
 
@@ -381,19 +384,56 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     for (int s = 0; s < a.nsteps; ++s) {
         const int64_t n = step0 + s;
 
-        // A: events due at the start of step n (network, then external)
-        if (tid == 0) {
-            while (int64_t(nkey >> 32) == n) {
-                const uint32_t r = uint32_t(nkey);
-                sgv[a.cr_syn[r]] += a.cr_w[r];
-                ++ncur;
-                nkey = (ncur < nend) ? ev[ncur] : ~uint64_t(0);
+        // A: events due at the start of step n, network ones (sorted by step,
+        // then synapse) before external ones (sorted likewise).  The threads
+        // take T due events at a time; the one holding the first event of a
+        // run of same-synapse events adds the whole run in sorted order, so
+        // every synapse's sum is the serial one.
+        if (int64_t(nkey >> 32) == n) {
+            const int32_t first = ncur;
+            for (;;) {
+                const int32_t i = ncur + tid;
+                const uint64_t key = (i < nend) ? ev[i] : ~uint64_t(0);
+                const bool due = int64_t(key >> 32) == n;
+                if (due) {
+                    const int q = a.cr_syn[uint32_t(key)];
+                    if (i == first || a.cr_syn[uint32_t(ev[i - 1])] != q) {
+                        double gq = sgv[q] + a.cr_w[uint32_t(key)];
+                        for (int32_t j = i + 1; j < nend; ++j) {
+                            const uint64_t kj = ev[j];
+                            if (int64_t(kj >> 32) != n || a.cr_syn[uint32_t(kj)] != q) break;
+                            gq += a.cr_w[uint32_t(kj)];
+                        }
+                        sgv[q] = gq;
+                    }
+                }
+                const int cnt = block_count<T>(due);
+                ncur += cnt;
+                if (cnt < T) break;
             }
-            while (xstep == n) {
-                sgv[a.xe_syn[xcur]] += a.xe_w[xcur];
-                ++xcur;
-                xstep = (xcur < pk.xe1) ? a.xe_step[xcur] : INT64_MAX;
+            nkey = (ncur < nend) ? ev[ncur] : ~uint64_t(0);
+            if (syn_hbm) __threadfence_block();
+            round_sync<T>();
+        }
+        if (xstep == n) {
+            const int64_t first = xcur;
+            for (;;) {
+                const int64_t i = xcur + tid;
+                const bool due = i < pk.xe1 && a.xe_step[i] == n;
+                if (due) {
+                    const int q = a.xe_syn[i];
+                    if (i == first || a.xe_syn[i - 1] != q) {
+                        double gq = sgv[q] + a.xe_w[i];
+                        for (int64_t j = i + 1; j < pk.xe1 && a.xe_step[j] == n && a.xe_syn[j] == q; ++j)
+                            gq += a.xe_w[j];
+                        sgv[q] = gq;
+                    }
+                }
+                const int cnt = block_count<T>(due);
+                xcur += cnt;
+                if (cnt < T) break;
             }
+            xstep = (xcur < pk.xe1) ? a.xe_step[xcur] : INT64_MAX;
             if (syn_hbm) __threadfence_block();  // the adds reach the other threads' loads
         }
         round_sync<T>();

@@ -50,8 +50,9 @@ struct Sim : arb_sim_ {
     std::vector<Class> classes;
     std::vector<hipStream_t> aux;       // one per class after the first
     std::vector<hipEvent_t> fork_ev, join_ev;
-    int exch_grid = 1;
     int32_t n_buckets = 1, bk_cap = 0;
+    int32_t n_hist = 1;     // epochs of spike history the longest delay needs
+    uint32_t hist_cap = 0;  // spikes per history epoch
     uint32_t sp_cap = 0, sp_user = 0;
     int64_t step = 0;
     double m0 = 0, h0 = 0, n0 = 0;
@@ -85,10 +86,16 @@ struct Sim : arb_sim_ {
     uint64_t* d_bk_ev = nullptr;
     uint32_t* d_bk_cnt = nullptr;
     int32_t* d_pk_ncur = nullptr;
-    int32_t *d_cr_syn = nullptr, *d_cr_pack = nullptr, *d_cr_delay = nullptr;
+    int32_t *d_cr_syn = nullptr, *d_cr_delay = nullptr;
+    uint32_t* d_cr_src = nullptr;
     double* d_cr_w = nullptr;
-    int64_t* d_out_off = nullptr;
-    uint32_t* d_out_rank = nullptr;
+    int64_t* d_in_off = nullptr;
+    // spike history ring and its per-source index
+    uint32_t* d_hist_gid = nullptr;
+    int64_t* d_hist_step = nullptr;
+    uint32_t* d_hist_cnt = nullptr;
+    int32_t* d_sx_cnt = nullptr;
+    int64_t *d_sx_off = nullptr, *d_sx_step = nullptr;
     uint32_t* d_sp_gid = nullptr;
     int64_t* d_sp_step = nullptr;
     double* d_sp_t = nullptr;
@@ -117,6 +124,8 @@ struct Sim : arb_sim_ {
     StepArgs step_args() const;
     int advance(int64_t n, const RecordArgs* rec);
     int launch_epoch_sequence(const StepArgs& a, bool net, bool graph_mode);
+    int launch_pull(int64_t epoch, const int64_t* epoch_ptr);     // the epoch's network events
+    int launch_collect(int64_t epoch, const int64_t* epoch_ptr);  // the epoch's spikes into the history
     int launch_classes(const StepArgs& a);
     int check_flags(bool& spikes_lost, bool& events_lost);
 };

@@ -129,3 +129,46 @@ def test_config6_full_size_light_cone():
         print(f"cell {c}: max|dV| = {err:.3e}", flush=True)
         assert err <= TOL
         assert mine == sorted(int(x) for x, gg in zip(st, g) if gg == len(chain) - 1)
+
+
+def _c7_reduced_source(s: int) -> gen.CellDesc:
+    """Source cell s of the 10k-connectivity model without its network input
+    and without the synapses that only network input reaches: before the
+    first volley arrives (step 800) its voltages, hence its first spike, are
+    those of the full cell (idle synapses add exactly zero current)."""
+    d = gen.cell_c7(s, 8192, n_steps=900)
+    d.syn_arr = tuple(np.asarray(x)[:1] for x in d.syn_arr)
+    d.in_conn_arr = None
+    return d
+
+
+def test_config7_full_size_first_volley():
+    """The 10k-connectivity model at full size (8192 cells x ~130 CVs,
+    82M synapses and connections, delay 800 steps, 50 Hz drive), 900 steps,
+    autotuned shape: a sampled cell receives the first volley (its ~5,900
+    distinct sources' spikes after the drive at step 0) at steps 811-825,
+    while it fires after the second drive; the oracle runs it with every
+    source reduced as above."""
+    from paper_1901_07454_amd import arbmi
+    n = 900
+    m = gen.config7(n_steps=n)
+    cv0 = oracle.cell_cv_begin(m)
+    samples = [0, 5003, 8191]
+    tr, V, sp, info = _gpu(m, n, cv0[samples], flags=arbmi.ARB_FLAG_AUTOTUNE)
+    print("config 7 info", info, "spikes", len(sp), flush=True)
+    del m
+    assert len(sp) == 2 * 8192  # every cell fires once per drive
+    for k, c in enumerate(samples):
+        tgt = gen.cell_c7(c, 8192, n_steps=n)
+        srcs = sorted(set(int(x) for x in tgt.in_conn_arr[0]))
+        sub = gen.assemble([tgt] + [_c7_reduced_source(x) for x in srcs], gids=[c] + srcs, n_steps=n)
+        assert len(sub["con_src"]) == 10000
+        s = oracle.Sim(sub)
+        c0 = oracle.cell_cv_begin(sub)
+        rtr = s.run(n, probes=[0])[0]
+        err = max(np.max(np.abs(tr[k] - rtr)), np.max(np.abs(V[cv0[c]:cv0[c + 1]] - s.state()["V"][:c0[1]])))
+        g, st, _ = s.spikes()
+        mine = sorted(int(x) for x in sp["step"][sp["gid"] == c])
+        print(f"cell {c}: {len(srcs)} sources, max|dV| = {err:.3e}, spikes {mine}", flush=True)
+        assert err <= TOL
+        assert mine == sorted(int(x) for x in st[g == 0])

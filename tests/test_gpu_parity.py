@@ -183,6 +183,52 @@ def test_synapse_dominated_mixed_parameters():
     check(m, 600)
 
 
+def _event_run_model(n_cells=12, n_syn=6, dup=3, delay=120):
+    """Every cell wired to every synapse of every other cell `dup` times
+    (same delay, different weights), external events on the same synapses
+    every 7 steps, among them the step the volley arrives (the cells fire
+    together at step 17): a pack sees hundreds of due events in one step, in
+    runs of same-synapse events that cross groups of 64, with external
+    events on the same synapses after them."""
+    rng = np.random.default_rng(77)
+    cells = []
+    for k in range(n_cells):
+        d = models.bare_cell(gen.full_binary_parents(2), [8, 5, 7, 8, 3, 6, 8], np.linspace(60, 180, 7),
+                             np.linspace(0.8, 2.0, 7))
+        for j in range(n_syn):
+            d.syn.append((j % 7 - 1 if j else -1, 0, 1.5 + 0.25 * j, 0.0 if j % 3 else -20.0))
+        for src in range(n_cells):
+            if src == k:
+                continue
+            for j in range(n_syn):
+                for u in range(dup):
+                    d.in_conn.append((src, j, delay, float(rng.uniform(1e-4, 6e-4))))
+        d.ext.append((0, 0, 0.05))
+        for st in range(delay + 3, 700, 7):  # includes the volley's step, delay + 17
+            for j in range(n_syn):
+                for u in range(2):
+                    d.ext.append((j, st, float(rng.uniform(0.0, 3e-4))))
+        cells.append(d)
+    return gen.assemble(cells, n_steps=700)
+
+
+@pytest.mark.parametrize("coef_mode,block", [(3, 64), (3, 128), (3, 256), (1, 64), (2, 128)])
+def test_event_runs_across_thread_groups(coef_mode, block):
+    m = _event_run_model()
+    _, sp = check(m, 700, probes=np.arange(int(gen.n_cvs(m).sum())), coef_mode=coef_mode, block_threads=block)
+    assert len(sp) >= 12
+
+
+@pytest.mark.parametrize("block", [0, 64, 256])
+def test_ten_thousand_way_network_small(block):
+    """The 10k-connectivity model's cells and wiring (every synapse from a
+    random other cell, delay 20 ms, 50 Hz drive) at 16 cells, three volleys."""
+    m = gen.config7(n_cells=16, n_steps=1700)
+    kw = dict(coef_mode=3, block_threads=block) if block else {}
+    _, sp = check(m, 1700, **kw)
+    assert len(sp) == 48
+
+
 def test_epoch_length_invariance_bitwise():
     m = gen.config2(n_cells=8, kick_all=False)
     probes = oracle.cell_cv_begin(m)[:-1]

@@ -107,12 +107,13 @@ def spread(total: int, parts: int, rng: np.random.Generator) -> np.ndarray:
 class CellDesc:
     __slots__ = ("parents", "n_cv", "length", "diam", "mech", "gna", "gk", "gl",
                  "gpas", "epas", "soma_mech", "soma_g", "syn", "syn_arr", "in_conn",
-                 "ext", "clamps")
+                 "in_conn_arr", "ext", "clamps")
 
     def __init__(self):
         self.syn = []       # (branch, cv, tau, e)
         self.syn_arr = None  # or the same four columns as arrays (many synapses)
         self.in_conn = []   # (src gid, local syn, delay_steps, w)
+        self.in_conn_arr = None  # or the same four columns as arrays (many connections)
         self.ext = []       # (local syn, step, w)
         self.clamps = []    # (branch, cv, on, off, amp)
 
@@ -274,6 +275,27 @@ def cell_c6(i: int, n_cells: int, n_syn: int = 10000, kick_all: bool = True) -> 
     return d
 
 
+def cell_c7(i: int, n_cells: int, n_syn: int = 10000, min_delay_ms: float = 20.0,
+            w_net: float = 2e-6, rate_hz: float = 50.0, n_steps: int = 4000) -> CellDesc:
+    """The 10k-connectivity model: the cells of the synapse-dominated ring
+    (same morphologies and synapse placement), every synapse wired from a
+    uniformly drawn other cell with the minimum delay and a small excitatory
+    weight, and a periodic drive on synapse 0 that makes all cells fire
+    together at `rate_hz`."""
+    d = cell_c6(i, n_cells, n_syn, kick_all=False)
+    d.in_conn = []
+    d.ext = []
+    rng = cell_rng(7, i)
+    src = rng.integers(n_cells - 1, size=n_syn) if n_cells > 1 else np.zeros(0, np.int64)
+    src = np.where(src >= i, src + 1, src)
+    k = len(src)
+    d.in_conn_arr = (src, np.arange(k), np.full(k, int(round(min_delay_ms / DT))), np.full(k, w_net))
+    period = int(round(1000.0 / rate_hz / DT))
+    for st in range(0, max(int(n_steps), 1), period):
+        d.ext.append((0, st, 0.05))
+    return d
+
+
 # ----------------------------------------------------------------------------
 # assembly of a model from cell descriptions
 
@@ -319,11 +341,24 @@ def assemble(cells: list[CellDesc], gids=None, n_steps: int = 0,
     m["syn_e"] = colcat(3, np.float64)
     con = [(remap[src], ci, int(sb[ci]) + ls, dl, w)
            for ci, c in enumerate(cells) for (src, ls, dl, w) in c.in_conn if int(src) in remap]
-    m["con_src"] = np.array([x[0] for x in con], np.uint32)
-    m["con_dst"] = np.array([x[1] for x in con], np.uint32)
-    m["con_syn"] = np.array([x[2] for x in con], np.uint32)
-    m["con_delay"] = np.array([x[3] for x in con], np.int32)
-    m["con_w"] = np.array([x[4] for x in con], np.float64)
+    ccols = [np.array([x[j] for x in con], t) for j, t in
+             enumerate((np.uint32, np.uint32, np.uint32, np.int32, np.float64))]
+    if any(c.in_conn_arr is not None for c in cells):
+        # vectorised connection columns (many connections per cell)
+        lut = np.full(int(max(gids)) + 1 if len(gids) else 1, -1, np.int64)
+        lut[np.asarray(gids, np.int64)] = np.arange(len(gids))
+        parts = [ccols]
+        for ci, c in enumerate(cells):
+            if c.in_conn_arr is None:
+                continue
+            src, ls, dl, w = (np.asarray(x) for x in c.in_conn_arr)
+            src = src.astype(np.int64)
+            ok = src < len(lut)
+            ok[ok] = lut[src[ok]] >= 0
+            parts.append([lut[src[ok]].astype(np.uint32), np.full(int(ok.sum()), ci, np.uint32),
+                          (sb[ci] + ls[ok]).astype(np.uint32), dl[ok].astype(np.int32), w[ok].astype(np.float64)])
+        ccols = [np.concatenate([p_[j] for p_ in parts]) for j in range(5)]
+    m["con_src"], m["con_dst"], m["con_syn"], m["con_delay"], m["con_w"] = ccols
     ev = [(int(sb[ci]) + ls, st, w) for ci, c in enumerate(cells) for (ls, st, w) in c.ext]
     m["ev_syn"] = np.array([x[0] for x in ev], np.uint32)
     m["ev_step"] = np.array([x[1] for x in ev], np.int64)
@@ -394,6 +429,13 @@ def config6(n_cells: int = 8192, cells=None, kick_all: bool = True, n_steps: int
             n_syn: int = 10000) -> dict:
     ids = range(n_cells) if cells is None else cells
     return assemble([cell_c6(i, n_cells, n_syn, kick_all) for i in ids], gids=list(ids), n_steps=n_steps)
+
+
+def config7(n_cells: int = 8192, cells=None, n_steps: int = 4000, n_syn: int = 10000,
+            min_delay_ms: float = 20.0, w_net: float = 2e-6) -> dict:
+    ids = range(n_cells) if cells is None else cells
+    return assemble([cell_c7(i, n_cells, n_syn, min_delay_ms, w_net, n_steps=n_steps) for i in ids],
+                    gids=list(ids), n_steps=n_steps)
 
 
 def ring_light_cone(n_cells: int, target: int, n_steps: int, delay: int = 200) -> list[int]:
