@@ -114,13 +114,11 @@ StepArgs Sim::step_args() const {
     a.xe_syn = d_xe_syn;
     a.xe_w = d_xe_w;
     a.pk_xcur = d_pk_xcur;
-    a.bk_ev = d_bk_ev;
-    a.bk_cnt = d_bk_cnt;
-    a.pk_ncur = d_pk_ncur;
+    a.bk_off = d_bk_off;
+    a.bk_q = d_bk_q;
+    a.bk_w = d_bk_w;
     a.bk_cap = bk_cap;
-    a.n_packs = int32_t(L.packs.size());
-    a.cr_syn = d_cr_syn;
-    a.cr_w = d_cr_w;
+    a.epoch_steps = K;
     a.sp_gid = d_sp_gid;
     a.sp_step = d_sp_step;
     a.sp_t = d_sp_t;
@@ -175,11 +173,13 @@ int Sim::launch_pull(int64_t epoch, const int64_t* epoch_ptr) {
     x.in_off = d_in_off;
     x.cr_src = d_cr_src;
     x.cr_delay = d_cr_delay;
+    x.cr_syn = d_cr_syn;
+    x.cr_w = d_cr_w;
     x.sx_off = d_sx_off;
     x.sx_step = d_sx_step;
-    x.bk_ev = d_bk_ev;
-    x.bk_cnt = d_bk_cnt;
-    x.pk_ncur = d_pk_ncur;
+    x.bk_off = d_bk_off;
+    x.bk_q = d_bk_q;
+    x.bk_w = d_bk_w;
     x.ctr = d_ctr;
     x.epoch_ptr = epoch_ptr;
     x.epoch = epoch;
@@ -216,7 +216,7 @@ int Sim::launch_epoch_sequence(const StepArgs& a, bool net, bool graph_mode) {
     return ARB_OK;
 }
 
-// Capture one full epoch, with its step and bucket read from d_epoch.
+// Capture one full epoch, with its step read from d_epoch.
 int Sim::capture_epoch_graph() {
     if (graph) {
         (void)hipGraphExecDestroy(graph);
@@ -225,7 +225,6 @@ int Sim::capture_epoch_graph() {
     const bool net = !L.out_rank.empty();
     StepArgs a = step_args();
     a.epoch_ptr = d_epoch;
-    a.n_buckets = n_buckets;
     a.nsteps = K;
     a.epoch_end = 1;
     hipGraph_t g = nullptr;
@@ -292,18 +291,15 @@ int Sim::advance(int64_t n, const RecordArgs* rec) {
             continue;
         }
         const int64_t nthis = std::min<int64_t>(n, K - pos);
-        const int32_t bucket = int32_t(e % n_buckets);
         if (net && pos == 0) {
             const int rc = launch_pull(e, nullptr);
             if (rc != ARB_OK) return rc;
         }
         StepArgs a = step_args();
-        a.bucket = bucket;
         a.step0 = step;
         a.nsteps = int32_t(nthis);
         a.epoch_end = (pos + nthis == K) ? 1 : 0;
-        a.n_buckets = n_buckets;
-        if (rec) {  // rows offset by the steps already done in this call
+            if (rec) {  // rows offset by the steps already done in this call
             if (cfg.coef_mode == 3)
                 return set_error(ARB_EINVAL, "recording needs the streamed or LDS-resident step kernel");
             a.rec_V = rec->V + done * L.n_slots;
@@ -428,7 +424,6 @@ int build_device(Sim* s) {
     for (int k = 0; k < np; ++k) xcur[k] = L.packs[k].xe0;
     s->xcur0 = xcur;
     s->d_pk_xcur = dupload(s, xcur, rc);
-    s->d_pk_ncur = dupload(s, std::vector<int32_t>(np, 0), rc);
     s->d_cr_syn = dupload(s, L.cr_syn, rc);
     s->d_cr_delay = dupload(s, L.cr_delay, rc);
     s->d_cr_src = dupload(s, L.cr_src, rc);
@@ -447,7 +442,6 @@ int build_device(Sim* s) {
     // history of the epochs whose spikes can still arrive (a spike of epoch
     // e - n_hist + 1 .. e - 1 can deliver into epoch e, none of epoch e)
     const bool net = !L.out_rank.empty();
-    s->n_buckets = 1;
     if (net) {
         int64_t cap = s->p.event_capacity;
         if (cap <= 0) cap = std::max<int64_t>(64, 4 * L.max_in_per_pack);
@@ -459,10 +453,13 @@ int build_device(Sim* s) {
         s->n_hist = 1;
         s->hist_cap = 0;
     }
-    const size_t nbk = size_t(np);
-    s->d_bk_cnt = dalloc<uint32_t>(s, nbk, rc);
-    if (rc == ARB_OK) rc = s->fill_zero(s->d_bk_cnt, nbk * sizeof(uint32_t));
-    s->d_bk_ev = dalloc<uint64_t>(s, std::max<size_t>(1, nbk * size_t(s->bk_cap)), rc);
+    if (net) {
+        const size_t noff = size_t(np) * (size_t(s->K) + 1);
+        s->d_bk_off = dalloc<uint32_t>(s, noff, rc);
+        if (rc == ARB_OK) rc = s->fill_zero(s->d_bk_off, noff * sizeof(uint32_t));
+        s->d_bk_q = dalloc<int32_t>(s, size_t(np) * size_t(s->bk_cap), rc);
+        s->d_bk_w = dalloc<double>(s, size_t(np) * size_t(s->bk_cap), rc);
+    }
     const size_t nh = std::max<size_t>(1, size_t(s->n_hist) * s->hist_cap);
     s->d_hist_gid = dalloc<uint32_t>(s, nh, rc);
     s->d_hist_step = dalloc<int64_t>(s, nh, rc);
@@ -920,8 +917,8 @@ int arb_set_params(arb_sim s_, const double* theta, int64_t n) {
     return ARB_OK;
 }
 
-// blob: header, then V, hh m/h/n, syn g, ext cursors, net cursors, bucket
-// counts and keys, counters, spike buffer, spike history
+// blob: header, then V, hh m/h/n, syn g, ext cursors, the running epoch's
+// network events, counters, spike buffer, spike history
 struct StateHeader {
     uint64_t magic;
     int64_t step, n_slots, n_hh, n_syn, n_packs, n_bk, bk_cap, sp_cap, sp_user;
@@ -932,12 +929,13 @@ int arb_get_state(arb_sim s_, void* blob, int64_t cap, int64_t* n_out) {
     Sim* s = static_cast<Sim*>(s_);
     if (!s || !n_out) return fail(ARB_EINVAL, "null argument");
     const Lowered& L = s->L;
-    const int64_t np = int64_t(L.packs.size()), nbk = int64_t(s->n_buckets) * np;
+    const int64_t np = int64_t(L.packs.size()), nbk = np;
     const int64_t nhh = int64_t(L.hh_cv.size()), nsyn = int64_t(L.syn_global.size());
     struct Part { const void* d; int64_t bytes; };
     const Part parts[] = {{s->d_V, L.n_slots * 8},   {s->d_hh_m, nhh * 8},  {s->d_hh_h, nhh * 8},
                           {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
-                          {s->d_pk_ncur, np * 4},    {s->d_bk_cnt, nbk * 4}, {s->d_bk_ev, nbk * s->bk_cap * 8},
+                          {s->d_bk_off, s->d_bk_off ? np * (s->K + 1) * 4 : 0},
+                          {s->d_bk_q, np * s->bk_cap * 4}, {s->d_bk_w, np * s->bk_cap * 8},
                           {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
                           {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8},
                           {s->d_hist_cnt, int64_t(s->n_hist) * 4},
@@ -967,7 +965,7 @@ int arb_set_state(arb_sim s_, const void* blob, int64_t n) {
     if (n < int64_t(sizeof(StateHeader))) return fail(ARB_EINVAL, "state blob too small");
     StateHeader h;
     std::memcpy(&h, blob, sizeof h);
-    const int64_t np = int64_t(L.packs.size()), nbk = int64_t(s->n_buckets) * np;
+    const int64_t np = int64_t(L.packs.size()), nbk = np;
     const int64_t nhh = int64_t(L.hh_cv.size()), nsyn = int64_t(L.syn_global.size());
     if (h.magic != kMagic || h.n_slots != L.n_slots || h.n_hh != nhh || h.n_syn != nsyn || h.n_packs != np ||
         h.n_bk != nbk || h.bk_cap != s->bk_cap || h.sp_cap != int64_t(s->sp_cap))
@@ -975,7 +973,8 @@ int arb_set_state(arb_sim s_, const void* blob, int64_t n) {
     struct Part { void* d; int64_t bytes; };
     const Part parts[] = {{s->d_V, L.n_slots * 8},   {s->d_hh_m, nhh * 8},  {s->d_hh_h, nhh * 8},
                           {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
-                          {s->d_pk_ncur, np * 4},    {s->d_bk_cnt, nbk * 4}, {s->d_bk_ev, nbk * s->bk_cap * 8},
+                          {s->d_bk_off, s->d_bk_off ? np * (s->K + 1) * 4 : 0},
+                          {s->d_bk_q, np * s->bk_cap * 4}, {s->d_bk_w, np * s->bk_cap * 8},
                           {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
                           {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8},
                           {s->d_hist_cnt, int64_t(s->n_hist) * 4},

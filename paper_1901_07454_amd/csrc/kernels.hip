@@ -108,26 +108,17 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
     for (int i = tid; i < pk.nnl; i += T) s_nl[i] = a.nl[pk.nl0 + i];
     for (int i = tid; i < pk.nch; i += T) s_ch[i] = a.ch_slot[pk.ch0 + i];
 
-    // event cursors live in thread 0's registers, with the next key cached
+    // external-event cursor in thread 0's registers, with the next step cached
     int64_t step0 = a.step0;
-    int32_t bucket = a.bucket;
-    if (a.epoch_ptr) {
-        const int64_t e = *a.epoch_ptr;
-        step0 = e * a.nsteps;
-        bucket = int32_t(e % a.n_buckets);
-    }
-    const int64_t bk_base = (int64_t(bucket) * a.n_packs + p);
-    const uint64_t* ev = a.bk_ev + bk_base * a.bk_cap;
-    int32_t ncur = 0, nend = 0;
+    if (a.epoch_ptr) step0 = *a.epoch_ptr * a.nsteps;
+    const int64_t estart = step0 - step0 % a.epoch_steps;  // the epoch's first step
+    const uint32_t* eoff = a.bk_off ? a.bk_off + int64_t(p) * (a.epoch_steps + 1) : nullptr;
+    const int32_t* eq = a.bk_q + int64_t(p) * a.bk_cap;
+    const double* ew = a.bk_w + int64_t(p) * a.bk_cap;
     int64_t xcur = 0;
-    uint64_t nkey = ~uint64_t(0);
     int64_t xstep = INT64_MAX;
     if (tid == 0) {
         xcur = a.pk_xcur[p];
-        ncur = a.pk_ncur[p];
-        const uint32_t c = a.bk_cnt[bk_base];
-        nend = int32_t(c < uint32_t(a.bk_cap) ? c : uint32_t(a.bk_cap));
-        if (ncur < nend) nkey = ev[ncur];
         if (xcur < pk.xe1) xstep = a.xe_step[xcur];
     }
     const int soma = (tid < pk.ncell) ? a.pc_soma[pk.cell0 + tid] : -1;
@@ -139,11 +130,9 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
 
         // A: events due at the start of step n (network, then external)
         if (tid == 0) {
-            while (int64_t(nkey >> 32) == n) {
-                const uint32_t r = uint32_t(nkey);
-                sg[a.cr_syn[r]] += a.cr_w[r];
-                ++ncur;
-                nkey = (ncur < nend) ? ev[ncur] : ~uint64_t(0);
+            if (eoff) {
+                const uint32_t i1 = eoff[n - estart + 1];
+                for (uint32_t i = eoff[n - estart]; i < i1; ++i) sg[eq[i]] += ew[i];
             }
             while (xstep == n) {
                 sg[a.xe_syn[xcur]] += a.xe_w[xcur];
@@ -334,11 +323,7 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
         a.hh_h[pk.hh0 + i] = sh[i];
         a.hh_n[pk.hh0 + i] = sn[i];
     }
-    if (tid == 0) {
-        a.pk_xcur[p] = xcur;
-        a.pk_ncur[p] = ncur;
-        if (a.epoch_end) a.bk_cnt[bk_base] = 0u;
-    }
+    if (tid == 0) a.pk_xcur[p] = xcur;
 }
 
 // ---------------------------------------------------------------------------
@@ -428,12 +413,15 @@ __device__ __forceinline__ int wave_min(int v) {
 
 // One wave per pack.  Pass 1 counts the epoch's events per step (LDS
 // counters over the K steps), a scan turns the counts into each step's
-// first position, and pass 2 walks the connections again in rank order, 64
-// at a time: the chunk's events are placed step by step, increasing, a
-// lane's event at its step's cursor plus the number of lower lanes with an
-// event at that step, so every step's events are in rank order.
+// first position (stored as the bucket's step offsets), and pass 2 walks
+// the connections again in rank order, 64 at a time: the chunk's events are
+// placed step by step, increasing, a lane's event at its step's cursor plus
+// the number of lower lanes with an event at that step, so every step's
+// events are in rank order.  An event is stored as (pack-local synapse,
+// weight).
 __global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
     extern __shared__ uint32_t bins[];
+    constexpr int U = 4;  // connections per lane in flight, spikes per source kept in registers
     const int p = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t e = a.epoch_ptr ? *a.epoch_ptr : a.epoch;
@@ -442,14 +430,28 @@ __global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
     const int64_t r0 = a.in_off[p], r1 = a.in_off[p + 1];
     for (int b = lane; b < K; b += 64) bins[b] = 0u;
     __syncthreads();
-    for (int64_t r = r0 + lane; r < r1; r += 64) {
-        const uint32_t src = a.cr_src[r];
-        const int64_t d = a.cr_delay[r];
-        const int64_t k1 = a.sx_off[src + 1];
-        for (int64_t k = a.sx_off[src]; k < k1; ++k) {
-            const int64_t b = a.sx_step[k] + d - lo;
-            if (b >= 0 && b < K) atomicAdd(&bins[b], 1u);
+    // pass 1: U connections per lane at a time, their loads issued together
+    for (int64_t c = r0; c < r1; c += 64 * U) {
+        uint32_t src[U];
+        int64_t d[U], k0[U], k1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t r = c + u * 64 + lane;
+            src[u] = r < r1 ? a.cr_src[r] : 0u;
+            d[u] = r < r1 ? a.cr_delay[r] : 0;
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = c + u * 64 + lane < r1;
+            k0[u] = ok ? a.sx_off[src[u]] : 0;
+            k1[u] = ok ? a.sx_off[src[u] + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            for (int64_t k = k0[u]; k < k1[u]; ++k) {
+                const int64_t b = a.sx_step[k] + d[u] - lo;
+                if (b >= 0 && b < K) atomicAdd(&bins[b], 1u);
+            }
     }
     __syncthreads();
     uint32_t run = 0;
@@ -467,31 +469,60 @@ __global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
     const uint32_t total = run;
     __syncthreads();
     const uint32_t cap = uint32_t(a.bk_cap);
-    uint64_t* out = a.bk_ev + int64_t(p) * a.bk_cap;
+    uint32_t* off = a.bk_off + int64_t(p) * (K + 1);
+    for (int b = lane; b < K; b += 64) off[b] = bins[b] < cap ? bins[b] : cap;
+    if (lane == 0) off[K] = total < cap ? total : cap;
+    int32_t* oq = a.bk_q + int64_t(p) * a.bk_cap;
+    double* ow = a.bk_w + int64_t(p) * a.bk_cap;
     const uint64_t below = (uint64_t(1) << lane) - 1u;
+    // pass 2: 64 connections at a time, this lane's event steps (the source's
+    // spikes in the window, up to U of them in registers, more re-read)
     for (int64_t c0 = r0; c0 < r1; c0 += 64) {
         const int64_t r = c0 + lane;
         int64_t d = 0, k0 = 0, k1 = 0;
+        int32_t q = 0;
+        double w = 0.0;
+        int bs[U];
         if (r < r1) {
             const uint32_t src = a.cr_src[r];
             d = a.cr_delay[r];
             k0 = a.sx_off[src];
             k1 = a.sx_off[src + 1];
+            if (k1 > k0) {
+                q = a.cr_syn[r];
+                w = a.cr_w[r];
+            }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            bs[u] = INT_MAX;
+            if (k0 + u < k1) {
+                const int64_t b = a.sx_step[k0 + u] + d - lo;
+                if (b >= 0 && b < K) bs[u] = int(b);
+            }
+        }
+        const bool more = k1 - k0 > U;
         int last = -1;
         for (;;) {
             int mine = INT_MAX;  // this lane's first event step after `last`
-            for (int64_t k = k0; k < k1; ++k) {
-                const int64_t b = a.sx_step[k] + d - lo;
-                if (b > last && b < K && b < mine) mine = int(b);
-            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (bs[u] > last && bs[u] < mine) mine = bs[u];
+            if (more)
+                for (int64_t k = k0 + U; k < k1; ++k) {
+                    const int64_t b = a.sx_step[k] + d - lo;
+                    if (b > last && b < K && b < mine) mine = int(b);
+                }
             const int B = wave_min(mine);
             if (B == INT_MAX) break;
             const uint64_t mask = __ballot(mine == B);
             const uint32_t base = bins[B];
             if (mine == B) {
                 const uint32_t pos = base + uint32_t(__popcll(mask & below));
-                if (pos < cap) out[pos] = (uint64_t(lo + B) << 32) | uint64_t(uint32_t(r));
+                if (pos < cap) {
+                    oq[pos] = q;
+                    ow[pos] = w;
+                }
             }
             __syncthreads();
             if (lane == 0) bins[B] = base + uint32_t(__popcll(mask));
@@ -499,11 +530,7 @@ __global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
             last = B;
         }
     }
-    if (lane == 0) {
-        a.bk_cnt[p] = total < cap ? total : cap;
-        a.pk_ncur[p] = 0;
-        if (total > cap) atomicOr(&a.ctr->flags, kFlagEventOverflow);
-    }
+    if (lane == 0 && total > cap) atomicOr(&a.ctr->flags, kFlagEventOverflow);
 }
 
 __global__ void advance_epoch_kernel(int64_t* epoch) { *epoch += 1; }

@@ -42,17 +42,14 @@ struct StepArgs {
     const int32_t* xe_syn;
     const double* xe_w;        // nS
     int64_t* pk_xcur;          // [n_packs] cursor into the external events
-    // network events of the current epoch: per pack a sorted run of keys
-    // (delivery step << 32 | connection rank)
-    const uint64_t* bk_ev;     // [NB][n_packs][bk_cap]
-    uint32_t* bk_cnt;          // [NB][n_packs] (the step kernel clears its run at the epoch end)
-    int32_t* pk_ncur;          // [n_packs] cursor into the current bucket
+    // network events of the current epoch (null without a network): per
+    // pack the events in (step, connection rank) order, and where each step
+    // of the epoch starts among them
+    const uint32_t* bk_off;    // [n_packs][epoch_steps + 1]
+    const int32_t* bk_q;       // [n_packs][bk_cap] pack-local synapse
+    const double* bk_w;        // [n_packs][bk_cap] weight nS
     int32_t bk_cap;
-    int32_t bucket;            // bucket of the current epoch
-    int32_t n_packs;
-    int32_t pad0;
-    const int32_t* cr_syn;     // per connection rank: pack-local synapse
-    const double* cr_w;        //   weight nS
+    int32_t epoch_steps;       // K: epochs start at multiples of K
     // spikes
     uint32_t* sp_gid;
     int64_t* sp_step;
@@ -80,11 +77,11 @@ struct StepArgs {
     double threshold;
     int64_t step0;             // first step of this launch
     int32_t nsteps;            // steps in this launch
-    int32_t epoch_end;         // 1 if the launch completes an epoch (reset the bucket)
+    int32_t epoch_end;         // 1 if the launch completes an epoch
     // graph replay: when set, the launch is the full epoch *epoch_ptr
-    // (step0 = epoch * nsteps, bucket = epoch % n_buckets)
+    // (step0 = epoch * nsteps)
     const int64_t* epoch_ptr;
-    int32_t n_buckets;
+    int32_t pad0;
     int32_t pack0;             // first pack of this launch (block b runs pack pack0 + b)
 };
 
@@ -118,17 +115,19 @@ hipError_t launch_collect_spikes(Counters* ctr, const uint32_t* sp_gid, const in
 hipError_t launch_index_spikes(const uint32_t* h_gid, const int64_t* h_step, const uint32_t* h_cnt, uint32_t h_cap,
                                int32_t n_hist, int32_t* sx_cnt, int64_t* sx_off, int64_t* sx_step, int32_t n_cells,
                                hipStream_t st);
-// Epoch start, after the index: each pack's network events of the epoch,
-// keys (step << 32 | rank) sorted, into its bucket; resets its cursor.
+// Epoch start, after the index: each pack's network events of the epoch in
+// (step, rank) order, with each step's start, into its bucket.
 struct PullArgs {
     const int64_t* in_off;     // [n_packs + 1] first connection rank of each pack
     const uint32_t* cr_src;    // per rank: source gid
     const int32_t* cr_delay;   // per rank: delay in steps
+    const int32_t* cr_syn;     // per rank: pack-local synapse
+    const double* cr_w;        // per rank: weight nS
     const int64_t* sx_off;
     const int64_t* sx_step;
-    uint64_t* bk_ev;           // [n_packs][bk_cap]
-    uint32_t* bk_cnt;          // [n_packs]
-    int32_t* pk_ncur;          // [n_packs]
+    uint32_t* bk_off;          // [n_packs][epoch_steps + 1]
+    int32_t* bk_q;             // [n_packs][bk_cap]
+    double* bk_w;              // [n_packs][bk_cap]
     Counters* ctr;
     const int64_t* epoch_ptr;  // or null: `epoch`
     int64_t epoch;

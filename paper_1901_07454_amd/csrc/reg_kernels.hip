@@ -336,20 +336,14 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         for (int i = tid; i < pk.nch; i += T) s_ch[i] = a.ch_task[pk.ch0 + i];
 
     int64_t step0 = a.step0;
-    int32_t bucket = a.bucket;
-    if (a.epoch_ptr) {
-        const int64_t e = *a.epoch_ptr;
-        step0 = e * a.nsteps;
-        bucket = int32_t(e % a.n_buckets);
-    }
-    const int64_t bk_base = (int64_t(bucket) * a.n_packs + p);
-    const uint64_t* ev = a.bk_ev + bk_base * a.bk_cap;
-    // event cursors, the same in every thread
+    if (a.epoch_ptr) step0 = *a.epoch_ptr * a.nsteps;
+    // network events: where each step of the epoch starts in the pack's
+    // bucket; external-event cursor, the same in every thread
+    const int64_t estart = step0 - step0 % a.epoch_steps;
+    const uint32_t* eoff = a.bk_off ? a.bk_off + int64_t(p) * (a.epoch_steps + 1) : nullptr;
+    const int32_t* eq = a.bk_q + int64_t(p) * a.bk_cap;
+    const double* ew = a.bk_w + int64_t(p) * a.bk_cap;
     int64_t xcur = a.pk_xcur[p];
-    int32_t ncur = a.pk_ncur[p];
-    const uint32_t bk_c = a.bk_cnt[bk_base];
-    const int32_t nend = int32_t(bk_c < uint32_t(a.bk_cap) ? bk_c : uint32_t(a.bk_cap));
-    uint64_t nkey = (ncur < nend) ? ev[ncur] : ~uint64_t(0);
     int64_t xstep = (xcur < pk.xe1) ? a.xe_step[xcur] : INT64_MAX;
     const int soma = (tid < pk.ncell) ? vix(a.pc_soma[pk.cell0 + tid]) : -1;
     double vold = 0.0;
@@ -384,36 +378,46 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     for (int s = 0; s < a.nsteps; ++s) {
         const int64_t n = step0 + s;
 
-        // A: events due at the start of step n, network ones (sorted by step,
-        // then synapse) before external ones (sorted likewise).  The threads
-        // take T due events at a time; the one holding the first event of a
-        // run of same-synapse events adds the whole run in sorted order, so
-        // every synapse's sum is the serial one.
-        if (int64_t(nkey >> 32) == n) {
-            const int32_t first = ncur;
-            for (;;) {
-                const int32_t i = ncur + tid;
-                const uint64_t key = (i < nend) ? ev[i] : ~uint64_t(0);
-                const bool due = int64_t(key >> 32) == n;
-                if (due) {
-                    const int q = a.cr_syn[uint32_t(key)];
-                    if (i == first || a.cr_syn[uint32_t(ev[i - 1])] != q) {
-                        double gq = sgv[q] + a.cr_w[uint32_t(key)];
-                        for (int32_t j = i + 1; j < nend; ++j) {
-                            const uint64_t kj = ev[j];
-                            if (int64_t(kj >> 32) != n || a.cr_syn[uint32_t(kj)] != q) break;
-                            gq += a.cr_w[uint32_t(kj)];
+        // A: events due at the start of step n, network ones (in connection
+        // rank order, so a synapse's events are adjacent) before external ones
+        // (sorted by step, then synapse).  The thread holding the first event
+        // of a run of same-synapse events adds the whole run in order, so
+        // every synapse's sum is the serial one.  A thread takes up to four
+        // network events at once: their synapses and weights are loaded
+        // together, then their conductances (distinct synapses), then the
+        // sums are stored.
+        if (eoff) {
+            const uint32_t i0 = eoff[n - estart], i1 = eoff[n - estart + 1];
+            if (i1 > i0) {
+                for (uint32_t c = i0; c < i1; c += 4 * T) {
+                    int q[4];
+                    double w[4], gq[4];
+                    bool head[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const uint32_t i = c + uint32_t(u * T + tid);
+                        head[u] = false;
+                        q[u] = 0;
+                        w[u] = 0.0;
+                        if (i < i1) {
+                            q[u] = eq[i];
+                            w[u] = ew[i];
+                            head[u] = i == i0 || eq[i - 1] != q[u];
                         }
-                        sgv[q] = gq;
                     }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) gq[u] = head[u] ? sgv[q[u]] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (head[u]) {
+                            double x = gq[u] + w[u];
+                            for (uint32_t j = c + uint32_t(u * T + tid) + 1; j < i1 && eq[j] == q[u]; ++j) x += ew[j];
+                            sgv[q[u]] = x;
+                        }
                 }
-                const int cnt = block_count<T>(due);
-                ncur += cnt;
-                if (cnt < T) break;
+                if (syn_hbm) __threadfence_block();
+                round_sync<T>();
             }
-            nkey = (ncur < nend) ? ev[ncur] : ~uint64_t(0);
-            if (syn_hbm) __threadfence_block();
-            round_sync<T>();
         }
         if (xstep == n) {
             const int64_t first = xcur;
@@ -633,11 +637,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         a.hh_h[pk.hh0 + i] = sh[i];
         a.hh_n[pk.hh0 + i] = sn[i];
     }
-    if (tid == 0) {
-        a.pk_xcur[p] = xcur;
-        a.pk_ncur[p] = ncur;
-        if (a.epoch_end) a.bk_cnt[bk_base] = 0u;
-    }
+    if (tid == 0) a.pk_xcur[p] = xcur;
 }
 
 template <int T, int S, int L>

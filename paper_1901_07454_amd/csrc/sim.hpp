@@ -50,7 +50,7 @@ struct Sim : arb_sim_ {
     std::vector<Class> classes;
     std::vector<hipStream_t> aux;       // one per class after the first
     std::vector<hipEvent_t> fork_ev, join_ev;
-    int32_t n_buckets = 1, bk_cap = 0;
+    int32_t bk_cap = 0;
     int32_t n_hist = 1;     // epochs of spike history the longest delay needs
     uint32_t hist_cap = 0;  // spikes per history epoch
     uint32_t sp_cap = 0, sp_user = 0;
@@ -83,9 +83,9 @@ struct Sim : arb_sim_ {
     int32_t* d_xe_syn = nullptr;
     double* d_xe_w = nullptr;
     int64_t* d_pk_xcur = nullptr;
-    uint64_t* d_bk_ev = nullptr;
-    uint32_t* d_bk_cnt = nullptr;
-    int32_t* d_pk_ncur = nullptr;
+    uint32_t* d_bk_off = nullptr;  // network events of the running epoch (StepArgs)
+    int32_t* d_bk_q = nullptr;
+    double* d_bk_w = nullptr;
     int32_t *d_cr_syn = nullptr, *d_cr_delay = nullptr;
     uint32_t* d_cr_src = nullptr;
     double* d_cr_w = nullptr;

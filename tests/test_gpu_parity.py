@@ -219,6 +219,33 @@ def test_event_runs_across_thread_groups(coef_mode, block):
     assert len(sp) >= 12
 
 
+def _fast_source_model(n_cells=6, n_steps=4000):
+    """Soma-only cells firing tonically under a clamp, all-to-all with delays
+    of 20, 40 and 60 ms: a source fires several times within the spike
+    history an epoch's events come from (epochs of 20 ms, history 80 ms)."""
+    rng = np.random.default_rng(5)
+    cells = []
+    for k in range(n_cells):
+        d = models.bare_cell([], [], [], [])
+        d.clamps.append((-1, 0, 0, n_steps, 0.06 + 0.01 * k))
+        for j in range(3):
+            d.syn.append((-1, 0, 2.0, 0.0 if j < 2 else -70.0))
+        for src in range(n_cells):
+            if src != k:
+                for j, dl in enumerate((800, 1600, 2400)):
+                    d.in_conn.append((src, j, dl, float(rng.uniform(1e-4, 1e-3))))
+        cells.append(d)
+    return gen.assemble(cells, n_steps=n_steps)
+
+
+@pytest.mark.parametrize("coef_mode", [3, 1])
+def test_sources_firing_often_within_the_delay(coef_mode):
+    m = _fast_source_model()
+    _, sp = check(m, 4000, probes=np.arange(len(m["cell_n_branch"])), coef_mode=coef_mode, block_threads=64)
+    per_cell = np.bincount([g for _, g in sp])
+    assert per_cell.min() >= 8  # more than four spikes of a source within 80 ms
+
+
 @pytest.mark.parametrize("block", [0, 64, 256])
 def test_ten_thousand_way_network_small(block):
     """The 10k-connectivity model's cells and wiring (every synapse from a
