@@ -49,6 +49,7 @@ std::vector<Part> state_parts(Sim* s) {
     return {{s->d_V, L.n_slots * 8},   {s->d_hh_m, nhh * 8},  {s->d_hh_h, nhh * 8},
             {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
             {s->d_bk_off, s->d_bk_off ? np * (s->K + 1) * 4 : 0},
+            {s->d_bk_nxt, s->d_bk_nxt ? np * (s->K + 1) * 4 : 0},
             {s->d_bk_q, np * s->bk_cap * 4}, {s->d_bk_w, np * s->bk_cap * 8},
             {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
             {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8},

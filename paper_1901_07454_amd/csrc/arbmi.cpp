@@ -115,6 +115,7 @@ StepArgs Sim::step_args() const {
     a.xe_w = d_xe_w;
     a.pk_xcur = d_pk_xcur;
     a.bk_off = d_bk_off;
+    a.bk_nxt = d_bk_nxt;
     a.bk_q = d_bk_q;
     a.bk_w = d_bk_w;
     a.bk_cap = bk_cap;
@@ -178,6 +179,7 @@ int Sim::launch_pull(int64_t epoch, const int64_t* epoch_ptr) {
     x.sx_off = d_sx_off;
     x.sx_step = d_sx_step;
     x.bk_off = d_bk_off;
+    x.bk_nxt = d_bk_nxt;
     x.bk_q = d_bk_q;
     x.bk_w = d_bk_w;
     x.ctr = d_ctr;
@@ -457,6 +459,8 @@ int build_device(Sim* s) {
         const size_t noff = size_t(np) * (size_t(s->K) + 1);
         s->d_bk_off = dalloc<uint32_t>(s, noff, rc);
         if (rc == ARB_OK) rc = s->fill_zero(s->d_bk_off, noff * sizeof(uint32_t));
+        s->d_bk_nxt = dalloc<uint32_t>(s, noff, rc);
+        if (rc == ARB_OK) rc = s->fill_zero(s->d_bk_nxt, noff * sizeof(uint32_t));
         s->d_bk_q = dalloc<int32_t>(s, size_t(np) * size_t(s->bk_cap), rc);
         s->d_bk_w = dalloc<double>(s, size_t(np) * size_t(s->bk_cap), rc);
     }
@@ -466,6 +470,7 @@ int build_device(Sim* s) {
     s->d_hist_cnt = dalloc<uint32_t>(s, size_t(s->n_hist), rc);
     if (rc == ARB_OK) rc = s->fill_zero(s->d_hist_cnt, size_t(s->n_hist) * sizeof(uint32_t));
     s->d_sx_cnt = dalloc<int32_t>(s, size_t(L.n_cells) + 1, rc);
+    if (rc == ARB_OK) rc = s->fill_zero(s->d_sx_cnt, (size_t(L.n_cells) + 1) * sizeof(int32_t));
     s->d_sx_off = dalloc<int64_t>(s, size_t(L.n_cells) + 1, rc);
     s->d_sx_step = dalloc<int64_t>(s, nh, rc);
     s->d_epoch = dalloc<int64_t>(s, 1, rc);
@@ -935,6 +940,7 @@ int arb_get_state(arb_sim s_, void* blob, int64_t cap, int64_t* n_out) {
     const Part parts[] = {{s->d_V, L.n_slots * 8},   {s->d_hh_m, nhh * 8},  {s->d_hh_h, nhh * 8},
                           {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
                           {s->d_bk_off, s->d_bk_off ? np * (s->K + 1) * 4 : 0},
+                          {s->d_bk_nxt, s->d_bk_nxt ? np * (s->K + 1) * 4 : 0},
                           {s->d_bk_q, np * s->bk_cap * 4}, {s->d_bk_w, np * s->bk_cap * 8},
                           {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
                           {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8},
@@ -974,6 +980,7 @@ int arb_set_state(arb_sim s_, const void* blob, int64_t n) {
     const Part parts[] = {{s->d_V, L.n_slots * 8},   {s->d_hh_m, nhh * 8},  {s->d_hh_h, nhh * 8},
                           {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
                           {s->d_bk_off, s->d_bk_off ? np * (s->K + 1) * 4 : 0},
+                          {s->d_bk_nxt, s->d_bk_nxt ? np * (s->K + 1) * 4 : 0},
                           {s->d_bk_q, np * s->bk_cap * 4}, {s->d_bk_w, np * s->bk_cap * 8},
                           {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
                           {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8},

@@ -117,9 +117,11 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
     const double* ew = a.bk_w + int64_t(p) * a.bk_cap;
     int64_t xcur = 0;
     int64_t xstep = INT64_MAX;
+    int32_t eb = INT32_MAX;  // the next step of the epoch with network events
     if (tid == 0) {
         xcur = a.pk_xcur[p];
         if (xcur < pk.xe1) xstep = a.xe_step[xcur];
+        if (eoff) eb = int32_t(a.bk_nxt[int64_t(p) * (a.epoch_steps + 1) + (step0 - estart)]);
     }
     const int soma = (tid < pk.ncell) ? a.pc_soma[pk.cell0 + tid] : -1;
     double vold = 0.0;
@@ -130,9 +132,11 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
 
         // A: events due at the start of step n (network, then external)
         if (tid == 0) {
-            if (eoff) {
-                const uint32_t i1 = eoff[n - estart + 1];
-                for (uint32_t i = eoff[n - estart]; i < i1; ++i) sg[eq[i]] += ew[i];
+            const int32_t b = int32_t(n - estart);
+            if (b == eb) {
+                const uint32_t i0 = eoff[b], i1 = eoff[b + 1];
+                eb = int32_t(a.bk_nxt[int64_t(p) * (a.epoch_steps + 1) + b + 1]);
+                for (uint32_t i = i0; i < i1; ++i) sg[eq[i]] += ew[i];
             }
             while (xstep == n) {
                 sg[a.xe_syn[xcur]] += a.xe_w[xcur];
@@ -336,44 +340,48 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
 // incoming connections (ranks in order) against the index, writing its
 // bucket of the epoch already in (step, rank) order.
 
-__global__ void __launch_bounds__(256) collect_spikes_kernel(Counters* ctr, const uint32_t* sp_gid,
-                                                             const int64_t* sp_step, uint32_t sp_cap,
-                                                             uint32_t* h_gid, int64_t* h_step, uint32_t* h_cnt,
-                                                             uint32_t h_cap, int32_t n_hist, int64_t epoch,
-                                                             const int64_t* epoch_ptr) {
+// One workgroup: the copy is small (an epoch's spikes) and the exchanged
+// mark moves after every thread has read it.
+__global__ void __launch_bounds__(1024) collect_spikes_kernel(Counters* ctr, const uint32_t* sp_gid,
+                                                              const int64_t* sp_step, uint32_t sp_cap,
+                                                              uint32_t* h_gid, int64_t* h_step, uint32_t* h_cnt,
+                                                              uint32_t h_cap, int32_t n_hist, int64_t epoch,
+                                                              const int64_t* epoch_ptr) {
     const int64_t e = epoch_ptr ? *epoch_ptr : epoch;
     const int64_t slot = e % n_hist;
     const uint32_t b = ctr->sp_exch;
     const uint32_t end = ctr->sp_count < sp_cap ? ctr->sp_count : sp_cap;
     const uint32_t n = end > b ? end - b : 0u;
     const uint32_t m = n < h_cap ? n : h_cap;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
         h_gid[slot * h_cap + i] = sp_gid[b + i];
         h_step[slot * h_cap + i] = sp_step[b + i];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
         h_cnt[slot] = m;
         if (n > h_cap) atomicOr(&ctr->flags, kFlagEventOverflow);
+        ctr->sp_exch = end;
     }
 }
 
-__global__ void __launch_bounds__(256) sx_clear_kernel(int32_t* cnt, int32_t n) {
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) cnt[i] = 0;
-}
-
-__global__ void __launch_bounds__(256) sx_count_kernel(const uint32_t* h_gid, const uint32_t* h_cnt, uint32_t h_cap,
-                                                       int32_t n_hist, int32_t* cnt) {
-    const int64_t total = int64_t(n_hist) * h_cap;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x)
-        if (uint32_t(i % h_cap) < h_cnt[i / h_cap]) atomicAdd(&cnt[h_gid[i]], 1);
-}
-
-// Exclusive scan of cnt[0, n) into off[0, n] by one workgroup (each thread
-// sums a contiguous segment, the segment sums are scanned in LDS); cnt is
-// cleared for use as fill counters.
-__global__ void __launch_bounds__(1024) sx_scan_kernel(int32_t* cnt, int64_t* off, int32_t n) {
+// Index the history's spikes by source gid, in one workgroup: count per gid
+// (cnt starts at zero), exclusive scan into off[0, n_cells] (each thread
+// sums a contiguous segment, the segment sums are scanned in LDS), then
+// scatter the steps while counting back down, which leaves cnt at zero for
+// the next epoch.
+__global__ void __launch_bounds__(1024) index_spikes_kernel(const uint32_t* h_gid, const int64_t* h_step,
+                                                            const uint32_t* h_cnt, uint32_t h_cap, int32_t n_hist,
+                                                            int32_t* cnt, int64_t* off, int64_t* sx_step,
+                                                            int32_t n) {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
+    for (int32_t h = 0; h < n_hist; ++h) {
+        const uint32_t c = h_cnt[h];
+        for (uint32_t i = t; i < c; i += 1024) atomicAdd(&cnt[h_gid[int64_t(h) * h_cap + i]], 1);
+    }
+    __threadfence_block();
+    __syncthreads();
     const int32_t seg = (n + 1023) / 1024;
     const int32_t i0 = t * seg < n ? t * seg : n, i1 = i0 + seg < n ? i0 + seg : n;
     int64_t sum = 0;
@@ -390,20 +398,17 @@ __global__ void __launch_bounds__(1024) sx_scan_kernel(int32_t* cnt, int64_t* of
     for (int32_t i = i0; i < i1; ++i) {
         off[i] = run;
         run += cnt[i];
-        cnt[i] = 0;
     }
     if (t == 1023) off[n] = part[1023];
-}
-
-__global__ void __launch_bounds__(256) sx_scatter_kernel(const uint32_t* h_gid, const int64_t* h_step,
-                                                         const uint32_t* h_cnt, uint32_t h_cap, int32_t n_hist,
-                                                         const int64_t* off, int32_t* cnt, int64_t* sx_step) {
-    const int64_t total = int64_t(n_hist) * h_cap;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x)
-        if (uint32_t(i % h_cap) < h_cnt[i / h_cap]) {
-            const uint32_t g = h_gid[i];
-            sx_step[off[g] + atomicAdd(&cnt[g], 1)] = h_step[i];
+    __threadfence_block();
+    __syncthreads();
+    for (int32_t h = 0; h < n_hist; ++h) {
+        const uint32_t c = h_cnt[h];
+        for (uint32_t i = t; i < c; i += 1024) {
+            const uint32_t g = h_gid[int64_t(h) * h_cap + i];
+            sx_step[off[g] + atomicSub(&cnt[g], 1) - 1] = h_step[int64_t(h) * h_cap + i];
         }
+    }
 }
 
 __device__ __forceinline__ int wave_min(int v) {
@@ -472,6 +477,29 @@ __global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
     uint32_t* off = a.bk_off + int64_t(p) * (K + 1);
     for (int b = lane; b < K; b += 64) off[b] = bins[b] < cap ? bins[b] : cap;
     if (lane == 0) off[K] = total < cap ? total : cap;
+    // for each step, the first step at or after it with events (K if none):
+    // a suffix minimum over 64 steps at a time, from the last
+    {
+        uint32_t* nxt = a.bk_nxt + int64_t(p) * (K + 1);
+        int later = K;
+        for (int b0 = ((K - 1) / 64) * 64; b0 >= 0; b0 -= 64) {
+            const int b = b0 + lane;
+            int x = K;
+            if (b < K) {
+                const uint32_t s0 = bins[b] < cap ? bins[b] : cap;
+                const uint32_t e1 = b + 1 < K ? bins[b + 1] : total;
+                if ((e1 < cap ? e1 : cap) > s0) x = b;
+            }
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_down(x, o);
+                if (lane + o < 64) x = min(x, y);
+            }
+            x = min(x, later);
+            if (b < K) nxt[b] = uint32_t(x);
+            later = __shfl(x, 0);
+        }
+        if (lane == 0) nxt[K] = uint32_t(K);
+    }
     int32_t* oq = a.bk_q + int64_t(p) * a.bk_cap;
     double* ow = a.bk_w + int64_t(p) * a.bk_cap;
     const uint64_t below = (uint64_t(1) << lane) - 1u;
@@ -535,11 +563,6 @@ __global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
 
 __global__ void advance_epoch_kernel(int64_t* epoch) { *epoch += 1; }
 
-__global__ void commit_exchange_kernel(Counters* ctr, uint32_t sp_cap) {
-    const uint32_t e = ctr->sp_count;
-    ctr->sp_exch = e > sp_cap ? sp_cap : e;
-}
-
 __global__ void gather_kernel(const double* V, const int64_t* perm, double* dst, int64_t n) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = V[perm[i]];
@@ -602,25 +625,16 @@ hipError_t launch_advance_epoch(int64_t* epoch, hipStream_t st) {
 hipError_t launch_collect_spikes(Counters* ctr, const uint32_t* sp_gid, const int64_t* sp_step, uint32_t sp_cap,
                                  uint32_t* h_gid, int64_t* h_step, uint32_t* h_cnt, uint32_t h_cap, int32_t n_hist,
                                  int64_t epoch, const int64_t* epoch_ptr, hipStream_t st) {
-    hipLaunchKernelGGL(collect_spikes_kernel, dim3(256), dim3(256), 0, st, ctr, sp_gid, sp_step, sp_cap, h_gid, h_step,
+    hipLaunchKernelGGL(collect_spikes_kernel, dim3(1), dim3(1024), 0, st, ctr, sp_gid, sp_step, sp_cap, h_gid, h_step,
                        h_cnt, h_cap, n_hist, epoch, epoch_ptr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(commit_exchange_kernel, dim3(1), dim3(1), 0, st, ctr, sp_cap);
     return hipGetLastError();
 }
 
 hipError_t launch_index_spikes(const uint32_t* h_gid, const int64_t* h_step, const uint32_t* h_cnt, uint32_t h_cap,
                                int32_t n_hist, int32_t* sx_cnt, int64_t* sx_off, int64_t* sx_step, int32_t n_cells,
                                hipStream_t st) {
-    const int64_t total = int64_t(n_hist) * h_cap;
-    const unsigned gc = unsigned(std::min<int64_t>(1024, (n_cells + 255) / 256 + 1));
-    const unsigned gh = unsigned(std::min<int64_t>(2048, (total + 255) / 256 + 1));
-    hipLaunchKernelGGL(sx_clear_kernel, dim3(gc), dim3(256), 0, st, sx_cnt, n_cells);
-    hipLaunchKernelGGL(sx_count_kernel, dim3(gh), dim3(256), 0, st, h_gid, h_cnt, h_cap, n_hist, sx_cnt);
-    hipLaunchKernelGGL(sx_scan_kernel, dim3(1), dim3(1024), 0, st, sx_cnt, sx_off, n_cells);
-    hipLaunchKernelGGL(sx_scatter_kernel, dim3(gh), dim3(256), 0, st, h_gid, h_step, h_cnt, h_cap, n_hist, sx_off,
-                       sx_cnt, sx_step);
+    hipLaunchKernelGGL(index_spikes_kernel, dim3(1), dim3(1024), 0, st, h_gid, h_step, h_cnt, h_cap, n_hist, sx_cnt,
+                       sx_off, sx_step, n_cells);
     return hipGetLastError();
 }
 

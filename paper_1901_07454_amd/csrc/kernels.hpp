@@ -46,6 +46,7 @@ struct StepArgs {
     // pack the events in (step, connection rank) order, and where each step
     // of the epoch starts among them
     const uint32_t* bk_off;    // [n_packs][epoch_steps + 1]
+    const uint32_t* bk_nxt;    // [n_packs][epoch_steps + 1] first step >= b with events (epoch_steps if none)
     const int32_t* bk_q;       // [n_packs][bk_cap] pack-local synapse
     const double* bk_w;        // [n_packs][bk_cap] weight nS
     int32_t bk_cap;
@@ -111,7 +112,8 @@ hipError_t launch_collect_spikes(Counters* ctr, const uint32_t* sp_gid, const in
                                  uint32_t* h_gid, int64_t* h_step, uint32_t* h_cnt, uint32_t h_cap, int32_t n_hist,
                                  int64_t epoch, const int64_t* epoch_ptr, hipStream_t st);
 // Epoch start: index the history's spikes by source gid: sx_off[n_cells + 1]
-// (exclusive offsets) and sx_step (their steps); sx_cnt[n_cells] is scratch.
+// (exclusive offsets) and sx_step (their steps); sx_cnt[n_cells] is scratch
+// that must be zero on entry and is zero again on return.
 hipError_t launch_index_spikes(const uint32_t* h_gid, const int64_t* h_step, const uint32_t* h_cnt, uint32_t h_cap,
                                int32_t n_hist, int32_t* sx_cnt, int64_t* sx_off, int64_t* sx_step, int32_t n_cells,
                                hipStream_t st);
@@ -126,6 +128,7 @@ struct PullArgs {
     const int64_t* sx_off;
     const int64_t* sx_step;
     uint32_t* bk_off;          // [n_packs][epoch_steps + 1]
+    uint32_t* bk_nxt;          // [n_packs][epoch_steps + 1]
     int32_t* bk_q;             // [n_packs][bk_cap]
     double* bk_w;              // [n_packs][bk_cap]
     Counters* ctr;

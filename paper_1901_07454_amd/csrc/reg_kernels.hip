@@ -343,6 +343,10 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     const uint32_t* eoff = a.bk_off ? a.bk_off + int64_t(p) * (a.epoch_steps + 1) : nullptr;
     const int32_t* eq = a.bk_q + int64_t(p) * a.bk_cap;
     const double* ew = a.bk_w + int64_t(p) * a.bk_cap;
+    // the next step of the epoch with network events: steps without any
+    // load nothing
+    const uint32_t* enxt = eoff ? a.bk_nxt + int64_t(p) * (a.epoch_steps + 1) : nullptr;
+    int32_t eb = eoff ? int32_t(enxt[step0 - estart]) : INT32_MAX;
     int64_t xcur = a.pk_xcur[p];
     int64_t xstep = (xcur < pk.xe1) ? a.xe_step[xcur] : INT64_MAX;
     const int soma = (tid < pk.ncell) ? vix(a.pc_soma[pk.cell0 + tid]) : -1;
@@ -386,38 +390,37 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         // network events at once: their synapses and weights are loaded
         // together, then their conductances (distinct synapses), then the
         // sums are stored.
-        if (eoff) {
-            const uint32_t i0 = eoff[n - estart], i1 = eoff[n - estart + 1];
-            if (i1 > i0) {
-                for (uint32_t c = i0; c < i1; c += 4 * T) {
-                    int q[4];
-                    double w[4], gq[4];
-                    bool head[4];
+        if (int32_t(n - estart) == eb) {
+            const uint32_t i0 = eoff[eb], i1 = eoff[eb + 1];
+            eb = int32_t(enxt[eb + 1]);
+            for (uint32_t c = i0; c < i1; c += 4 * T) {
+                int q[4];
+                double w[4], gq[4];
+                bool head[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const uint32_t i = c + uint32_t(u * T + tid);
-                        head[u] = false;
-                        q[u] = 0;
-                        w[u] = 0.0;
-                        if (i < i1) {
-                            q[u] = eq[i];
-                            w[u] = ew[i];
-                            head[u] = i == i0 || eq[i - 1] != q[u];
-                        }
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t i = c + uint32_t(u * T + tid);
+                    head[u] = false;
+                    q[u] = 0;
+                    w[u] = 0.0;
+                    if (i < i1) {
+                        q[u] = eq[i];
+                        w[u] = ew[i];
+                        head[u] = i == i0 || eq[i - 1] != q[u];
                     }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) gq[u] = head[u] ? sgv[q[u]] : 0.0;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (head[u]) {
-                            double x = gq[u] + w[u];
-                            for (uint32_t j = c + uint32_t(u * T + tid) + 1; j < i1 && eq[j] == q[u]; ++j) x += ew[j];
-                            sgv[q[u]] = x;
-                        }
                 }
-                if (syn_hbm) __threadfence_block();
-                round_sync<T>();
+#pragma unroll
+                for (int u = 0; u < 4; ++u) gq[u] = head[u] ? sgv[q[u]] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (head[u]) {
+                        double x = gq[u] + w[u];
+                        for (uint32_t j = c + uint32_t(u * T + tid) + 1; j < i1 && eq[j] == q[u]; ++j) x += ew[j];
+                        sgv[q[u]] = x;
+                    }
             }
+            if (syn_hbm) __threadfence_block();
+            round_sync<T>();
         }
         if (xstep == n) {
             const int64_t first = xcur;

@@ -84,6 +84,7 @@ struct Sim : arb_sim_ {
     double* d_xe_w = nullptr;
     int64_t* d_pk_xcur = nullptr;
     uint32_t* d_bk_off = nullptr;  // network events of the running epoch (StepArgs)
+    uint32_t* d_bk_nxt = nullptr;
     int32_t* d_bk_q = nullptr;
     double* d_bk_w = nullptr;
     int32_t *d_cr_syn = nullptr, *d_cr_delay = nullptr;
