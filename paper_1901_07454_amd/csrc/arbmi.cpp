@@ -178,6 +178,7 @@ int Sim::launch_pull(int64_t epoch, const int64_t* epoch_ptr) {
     x.cr_w = d_cr_w;
     x.sx_off = d_sx_off;
     x.sx_step = d_sx_step;
+    x.n_cells = L.n_cells;
     x.bk_off = d_bk_off;
     x.bk_nxt = d_bk_nxt;
     x.bk_q = d_bk_q;

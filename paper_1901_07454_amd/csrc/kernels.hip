@@ -376,6 +376,12 @@ __global__ void __launch_bounds__(1024) index_spikes_kernel(const uint32_t* h_gi
                                                             int32_t n) {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
+    int64_t any = 0;
+    for (int32_t h = 0; h < n_hist; ++h) any += h_cnt[h];
+    if (any == 0) {  // no spikes: only the total, which the pull checks first
+        if (t == 0) off[n] = 0;
+        return;
+    }
     for (int32_t h = 0; h < n_hist; ++h) {
         const uint32_t c = h_cnt[h];
         for (uint32_t i = t; i < c; i += 1024) atomicAdd(&cnt[h_gid[int64_t(h) * h_cap + i]], 1);
@@ -433,6 +439,11 @@ __global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
     const int K = a.epoch_steps;
     const int64_t lo = e * K;
     const int64_t r0 = a.in_off[p], r1 = a.in_off[p + 1];
+    if (a.sx_off[a.n_cells] == 0) {  // no spikes in the history: no events this epoch
+        uint32_t* nxt = a.bk_nxt + int64_t(p) * (K + 1);
+        for (int b = lane; b <= K; b += 64) nxt[b] = uint32_t(K);
+        return;
+    }
     for (int b = lane; b < K; b += 64) bins[b] = 0u;
     __syncthreads();
     // pass 1: U connections per lane at a time, their loads issued together

@@ -125,8 +125,10 @@ struct PullArgs {
     const int32_t* cr_delay;   // per rank: delay in steps
     const int32_t* cr_syn;     // per rank: pack-local synapse
     const double* cr_w;        // per rank: weight nS
-    const int64_t* sx_off;
+    const int64_t* sx_off;     // [n_cells + 1]
     const int64_t* sx_step;
+    int32_t n_cells;
+    int32_t pad;
     uint32_t* bk_off;          // [n_packs][epoch_steps + 1]
     uint32_t* bk_nxt;          // [n_packs][epoch_steps + 1]
     int32_t* bk_q;             // [n_packs][bk_cap]
