@@ -95,3 +95,38 @@ def test_forward_state_restored_after_backward():
     torch.mean(tr).backward()
     assert np.array_equal(gs.sim.voltages_host(), v_after_fwd)
     gs.close()
+
+
+def _ring_of_c4_cells(n_steps):
+    cells = [gen.cell_c4(i, False) for i in range(4)]
+    for i, d in enumerate(cells):
+        d.syn.append((-1, 0, 2.0, 0.0))
+        d.in_conn.append(((i - 1) % 4, len(d.syn) - 1, 120, 0.02))
+    return gen.assemble(cells, n_steps=n_steps)
+
+
+def test_adjoint_through_network_events():
+    """The config-4 cells on a ring (delay 120 steps, epochs of 120): the
+    events the recompute replays come from the spike exchange, and
+    checkpoints every 37 steps restore the state in the middle of epochs."""
+    import torch
+
+    from paper_1901_07454_amd import grad
+    n = 600
+    m0 = _ring_of_c4_cells(n)
+    th0 = gen.config4_theta(m0)
+    tgt = 0.9 * oracle.Sim(m0).run(n, probes=oracle.cell_cv_begin(m0)[:-1])
+    gs = grad.GradSim(m0)
+    theta = torch.tensor(th0, dtype=torch.float64, device="cuda", requires_grad=True)
+    tr, L, g = _loss_grad(gs, theta, tgt, n, 100)
+    s = oracle.Sim(m0)
+    s.set_params(th0.reshape(-1, 3))
+    otr, og = s.adjoint(n, 2.0 * (tr - tgt) / tr.size)
+    og = og.reshape(th0.shape)
+    assert np.max(np.abs(tr - otr)) <= 1e-8
+    rel = np.abs(g - og) / np.maximum(np.abs(og), 1e-3 * np.max(np.abs(og), axis=(1, 2), keepdims=True))
+    print(f"max rel |g_gpu - g_oracle| = {rel.max():.3e}", flush=True)
+    assert rel.max() <= 1e-7
+    g37 = _loss_grad(gs, theta, tgt, n, 37)[2]
+    assert np.allclose(g37, g, rtol=1e-12, atol=1e-14 * np.abs(g).max())
+    gs.close()

@@ -256,6 +256,14 @@ def test_ten_thousand_way_network_small(block):
     assert len(sp) == 48
 
 
+def test_ten_thousand_way_network_short_delay():
+    """The 10 ms variant: epochs of 400 steps, each volley arriving 400 steps
+    after the spikes, mid-way between drives."""
+    m = gen.config7(n_cells=16, n_steps=1700, min_delay_ms=10.0)
+    _, sp = check(m, 1700)
+    assert len(sp) == 48
+
+
 def test_epoch_length_invariance_bitwise():
     m = gen.config2(n_cells=8, kick_all=False)
     probes = oracle.cell_cv_begin(m)[:-1]
