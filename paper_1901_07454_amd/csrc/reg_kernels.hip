@@ -457,9 +457,13 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
                 I += s_gk[q] * (x * x * x * x) * (v - kEK);
             }
             if (!syn_hbm) {
+                // the decay of phase E is applied here too: g is not read
+                // again before the next step's events
                 for (int k = 0; k < d.nsyn; ++k) {
                     const int q = d.syn0 + k;
-                    I += sg[q] * (v - s_se[q]);
+                    const double gq = sg[q];
+                    I += gq * (v - s_se[q]);
+                    sg[q] = gq * s_sdec[q];
                 }
             } else {
                 // HBM synapses, interleaved over the threads of this group
@@ -589,11 +593,10 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         }
         round_sync<T>();
 
-        // E: states with V^{n+1}; synapse decay; threshold.  A pack with few
-        // hh instances gives each gate of an instance its own thread (which
-        // computes that gate's two rates and the update); otherwise a thread
-        // takes a whole instance.
-        for (int j = tid; j < nsyn_lds; j += T) sg[j] *= s_sdec[j];
+        // E: states with V^{n+1} (synapses decayed in phase B); threshold.  A
+        // pack with few hh instances gives each gate of an instance its own
+        // thread (which computes that gate's two rates and the update);
+        // otherwise a thread takes a whole instance.
         if (pk.nhh <= kSpreadHH) {
             for (int j = tid; j < 3 * pk.nhh; j += T) {
                 const int q = j / 3, w = j - 3 * q;
