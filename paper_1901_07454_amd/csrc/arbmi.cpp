@@ -823,8 +823,9 @@ int arb_get_spikes(arb_sim s_, arb_spike* dst, int64_t cap, int64_t* n_out) {
     }
     *n_out = n;
     s->sp_user = have;
-    // everything returned and exchanged: start the buffer over
-    if (c.sp_exch == have && have == c.sp_count && (c.flags & kFlagSpikeOverflow) == 0) {
+    // everything returned and (in a network) exchanged: start the buffer over
+    const bool exchanged = s->L.out_rank.empty() || c.sp_exch == have;
+    if (exchanged && have == c.sp_count && (c.flags & kFlagSpikeOverflow) == 0) {
         Counters z = c;
         z.sp_count = 0;
         z.sp_exch = 0;

@@ -553,17 +553,16 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
                 round_sync<T>();
             }
         }
+        // rhs'/d' of the thread's rows stay in registers across the downward
+        // pass (no other thread reads them)
+        double y0[L], y1[L], y2[L];
         {
-            double b0[L], b1[L], b2[L];
-            load_v<L>(g0, sV, b0);
-            if constexpr (S > 1) load_v<L>(g1, sV, b1);
-            if constexpr (S > 2) load_v<L>(g2, sV, b2);
-            full_chain<L>(g0, b0);
-            if constexpr (S > 1) full_chain<L>(g1, b1);
-            if constexpr (S > 2) full_chain<L>(g2, b2);
-            store_v<L>(g0, sV, b0);
-            if constexpr (S > 1) store_v<L>(g1, sV, b1);
-            if constexpr (S > 2) store_v<L>(g2, sV, b2);
+            load_v<L>(g0, sV, y0);
+            if constexpr (S > 1) load_v<L>(g1, sV, y1);
+            if constexpr (S > 2) load_v<L>(g2, sV, y2);
+            full_chain<L>(g0, y0);
+            if constexpr (S > 1) full_chain<L>(g1, y1);
+            if constexpr (S > 2) full_chain<L>(g2, y2);
             sY[g0.task] = g0.yl;
             if constexpr (S > 1) sY[g1.task] = g1.yl;
             if constexpr (S > 2) sY[g2.task] = g2.yl;
@@ -580,16 +579,12 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
             round_sync<T>();
         }
         {
-            double b0[L], b1[L], b2[L];
-            load_v<L>(g0, sV, b0);
-            if constexpr (S > 1) load_v<L>(g1, sV, b1);
-            if constexpr (S > 2) load_v<L>(g2, sV, b2);
-            subst_chain<L>(g0, b0);
-            if constexpr (S > 1) subst_chain<L>(g1, b1);
-            if constexpr (S > 2) subst_chain<L>(g2, b2);
-            store_v<L>(g0, sV, b0);
-            if constexpr (S > 1) store_v<L>(g1, sV, b1);
-            if constexpr (S > 2) store_v<L>(g2, sV, b2);
+            subst_chain<L>(g0, y0);
+            if constexpr (S > 1) subst_chain<L>(g1, y1);
+            if constexpr (S > 2) subst_chain<L>(g2, y2);
+            store_v<L>(g0, sV, y0);
+            if constexpr (S > 1) store_v<L>(g1, sV, y1);
+            if constexpr (S > 2) store_v<L>(g2, sV, y2);
         }
         round_sync<T>();
 

@@ -264,6 +264,25 @@ def test_ten_thousand_way_network_short_delay():
     assert len(sp) == 48
 
 
+def test_spike_buffer_drained_without_network():
+    """A model without connections: reading the spikes empties the buffer,
+    so a run that fires several times what the buffer holds loses none."""
+    cells = [models.bare_cell([], [], [], []) for _ in range(4)]
+    for k, d in enumerate(cells):
+        d.clamps.append((-1, 0, 0, 8000, 0.08 + 0.01 * k))
+    m = gen.assemble(cells, n_steps=8000)
+    sim = _sim(m, spike_capacity=16)
+    got = []
+    for _ in range(40):
+        sim.step(200)
+        sp = sim.spikes()
+        got += list(zip(sp["step"].tolist(), sp["gid"].tolist()))
+    sim.close()
+    _, _, ref = oracle_run(m, 8000, [0])
+    assert len(ref) > 48
+    assert sorted(got) == ref
+
+
 def test_epoch_length_invariance_bitwise():
     m = gen.config2(n_cells=8, kick_all=False)
     probes = oracle.cell_cv_begin(m)[:-1]
