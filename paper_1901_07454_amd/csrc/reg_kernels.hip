@@ -83,8 +83,8 @@ __device__ __forceinline__ int cv_slot(const Slot<L>& g, int k) {
 // them in source order) and overlap the slots' recurrences.
 
 // Local elimination (children's sum taken as 0): t_k = alpha_k V_k + R_k,
-// P_k = t_k - F_{k+1} P_{k+1}.  t waits in the V entries; F_0 P_0 is the
-// branch's contribution if it has no children.
+// P_k = t_k - F_{k+1} P_{k+1}.  t stays in the thread's registers; F_0 P_0
+// is the branch's contribution if it has no children.
 template <int L>
 __device__ __forceinline__ void local_load(const Slot<L>& g, const double* sV, double* t) {
 #pragma unroll
@@ -98,20 +98,13 @@ __device__ __forceinline__ void local_chain(Slot<L>& g, const double* t) {
     g.fp = g.F[0] * acc;
 }
 template <int L>
-__device__ __forceinline__ void local_store(const Slot<L>& g, double* sV, double* sC, double* sF, const double* t) {
-#pragma unroll
-    for (int k = 0; k < L; ++k) sV[cv_slot(g, k)] = t[k];
+__device__ __forceinline__ void local_store(const Slot<L>& g, double* sC, double* sF) {
     sC[g.task] = g.fp;
     sF[g.task] = g.fp;
 }
 
-// Full elimination with the children's sum (t becomes rhs'/d', which goes to
-// the V entries), and the distal V for a grounded parent.
-template <int L>
-__device__ __forceinline__ void load_v(const Slot<L>& g, const double* sV, double* t) {
-#pragma unroll
-    for (int k = 0; k < L; ++k) t[k] = sV[cv_slot(g, k)];
-}
+// Full elimination with the children's sum (t becomes rhs'/d', kept in
+// registers for the substitution), and the distal V for a grounded parent.
 template <int L>
 __device__ __forceinline__ void full_chain(Slot<L>& g, double* t) {
     double acc = (g.len == L) ? g.cs : -g.cs;
@@ -516,19 +509,19 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
         }
         round_sync<T>();
 
-        // C: the solve
-        {
-            double b0[L], b1[L], b2[L];
-            local_load<L>(g0, sV, b0);
-            if constexpr (S > 1) local_load<L>(g1, sV, b1);
-            if constexpr (S > 2) local_load<L>(g2, sV, b2);
-            local_chain<L>(g0, b0);
-            if constexpr (S > 1) local_chain<L>(g1, b1);
-            if constexpr (S > 2) local_chain<L>(g2, b2);
-            local_store<L>(g0, sV, sC, sF, b0);
-            if constexpr (S > 1) local_store<L>(g1, sV, sC, sF, b1);
-            if constexpr (S > 2) local_store<L>(g2, sV, sC, sF, b2);
-        }
+        // C: the solve.  Each row's t, then rhs'/d', stays in the owning
+        // thread's registers from the local elimination to the substitution
+        // (no other thread reads them); the V entries keep V^n until then.
+        double y0[L], y1[L], y2[L];
+        local_load<L>(g0, sV, y0);
+        if constexpr (S > 1) local_load<L>(g1, sV, y1);
+        if constexpr (S > 2) local_load<L>(g2, sV, y2);
+        local_chain<L>(g0, y0);
+        if constexpr (S > 1) local_chain<L>(g1, y1);
+        if constexpr (S > 2) local_chain<L>(g2, y2);
+        local_store<L>(g0, sC, sF);
+        if constexpr (S > 1) local_store<L>(g1, sC, sF);
+        if constexpr (S > 2) local_store<L>(g2, sC, sF);
         round_sync<T>();
         if (pk.binary) {  // contributions up, two levels a round, deepest first
             for (int sr = 0; 2 * sr < pk.nlev; ++sr) {
@@ -553,13 +546,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
                 round_sync<T>();
             }
         }
-        // rhs'/d' of the thread's rows stay in registers across the downward
-        // pass (no other thread reads them)
-        double y0[L], y1[L], y2[L];
         {
-            load_v<L>(g0, sV, y0);
-            if constexpr (S > 1) load_v<L>(g1, sV, y1);
-            if constexpr (S > 2) load_v<L>(g2, sV, y2);
             full_chain<L>(g0, y0);
             if constexpr (S > 1) full_chain<L>(g1, y1);
             if constexpr (S > 2) full_chain<L>(g2, y2);
