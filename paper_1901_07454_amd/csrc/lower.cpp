@@ -40,6 +40,11 @@ struct CellCV {
     std::vector<int> first;         // first local CV of each branch
     std::vector<int> depth;         // per branch (soma = 0, root branch = 1)
     std::vector<int> pnode;         // per branch: local CV the branch hangs from
+    // solver segments: the branches, each cut into a chain of segments of at
+    // most the register layout's rows (one segment per branch otherwise);
+    // the CVs and their tree are the same, the solve's tasks are segments
+    std::vector<int> sfirst, slen, sparent, sdepth, spnode;  // sparent -1: the soma
+    int nseg() const { return int(sfirst.size()); }
 };
 
 template <class... A>
@@ -165,6 +170,29 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                 pieces[cv0 + i].push_back({r, kPi * B.diam_um * len});
             }
         }
+        // solver segments, in branch order (a parent's before its children's):
+        // a branch of n CVs becomes ceil(n / seg_max) segments of nearly equal
+        // length, each hanging from the previous one's last CV
+        const int seg_max = (opt.reg_slots > 0 && opt.reg_len > 0) ? opt.reg_len : INT32_MAX;
+        std::vector<int> last_seg(C.n_branch, -1);
+        for (int32_t b = 0; b < C.n_branch; ++b) {
+            const arb_branch& B = br[C.branch_begin + b];
+            const int parts = (B.n_cv <= seg_max) ? 1 : (B.n_cv + seg_max - 1) / seg_max;
+            const int base = B.n_cv / parts, rem = B.n_cv % parts;
+            int prev = (B.parent < 0) ? -1 : last_seg[B.parent];
+            int off = 0;
+            for (int k = 0; k < parts; ++k) {
+                const int len = base + (k < rem ? 1 : 0);
+                G.sfirst.push_back(G.first[b] + off);
+                G.slen.push_back(len);
+                G.sparent.push_back(prev);
+                G.sdepth.push_back(prev < 0 ? 1 : G.sdepth[prev] + 1);
+                G.spnode.push_back(k == 0 ? G.pnode[b] : G.first[b] + off - 1);
+                prev = G.nseg() - 1;
+                off += len;
+            }
+            last_seg[b] = prev;
+        }
     }
     for (int64_t i = 0; i < L.n_cv; ++i) L.piece_off[i + 1] = L.piece_off[i] + int64_t(pieces[i].size());
     L.piece_reg.resize(L.piece_off[L.n_cv]);
@@ -262,14 +290,14 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
     auto build_rounds = [&](const std::vector<int32_t>& cs, std::vector<RoundPlan>& out) -> bool {
         out.clear();
         int maxd = 0;
-        for (int32_t c : cs) for (int d : geo[c].depth) maxd = std::max(maxd, d);
+        for (int32_t c : cs) for (int d : geo[c].sdepth) maxd = std::max(maxd, d);
         std::vector<int> next_free(std::max(S, 1), 0);
         for (int d = maxd; d >= 0; --d) {
             std::vector<Item> items;
             for (int32_t c : cs) {
                 if (d == 0) { items.push_back({c, -1, 1}); continue; }
-                for (int32_t b = 0; b < cells[c].n_branch; ++b)
-                    if (geo[c].depth[b] == d) items.push_back({c, b, br[cells[c].branch_begin + b].n_cv});
+                for (int32_t b = 0; b < geo[c].nseg(); ++b)
+                    if (geo[c].sdepth[b] == d) items.push_back({c, b, geo[c].slen[b]});
             }
             size_t s0 = 0;
             while (s0 < items.size()) {
@@ -307,11 +335,11 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         }
         return true;
     };
-    // most children of any task (soma or branch) of each cell
+    // most children of any task (soma or segment) of each cell
     std::vector<int32_t> max_children(n_cells, 0);
     for (int32_t c = 0; c < n_cells; ++c) {
-        std::vector<int32_t> nch(cells[c].n_branch + 1, 0);  // [0] = soma, [b + 1] = branch b
-        for (int32_t b = 0; b < cells[c].n_branch; ++b) nch[br[cells[c].branch_begin + b].parent + 1]++;
+        std::vector<int32_t> nch(geo[c].nseg() + 1, 0);  // [0] = soma, [b + 1] = segment b
+        for (int32_t b = 0; b < geo[c].nseg(); ++b) nch[geo[c].sparent[b] + 1]++;
         for (int32_t v : nch) max_children[c] = std::max(max_children[c], v);
     }
     struct Shape { int64_t nslot = 0, nrd = 0; bool ok = true, has_pad = false; };
@@ -362,7 +390,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             trial.cells.push_back(c);
             trial.nsyn += nsyn_cell[c];
             trial.nhh += nhh_cell[c];
-            trial.nbr += cells[c].n_branch;
+            trial.nbr += geo[c].nseg();
             trial.nic += nic_cell[c];
             trial.nin += nin_cell[c];
             // a cell alone always makes a pack
@@ -374,7 +402,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                 cur.cells.push_back(c);
                 cur.nsyn = nsyn_cell[c];
                 cur.nhh = nhh_cell[c];
-                cur.nbr = cells[c].n_branch;
+                cur.nbr = geo[c].nseg();
                 cur.nic = nic_cell[c];
                 cur.nin = nin_cell[c];
             } else {
@@ -415,7 +443,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         int maxd = 0;
         for (int32_t c : pp.cells) {
             pack_of_cell[c] = pk;
-            for (int d : geo[c].depth) maxd = std::max(maxd, d);
+            for (int d : geo[c].sdepth) maxd = std::max(maxd, d);
         }
         // rounds, deepest first; a task is (cell, branch) with branch -1 = soma
         std::vector<RoundPlan> rps;
@@ -433,7 +461,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                     slot_of_user[cv0] = slot_base + ns + int64_t(t);
                 } else {
                     for (int k = 0; k < it.len; ++k)
-                        slot_of_user[cv0 + geo[it.c].first[it.b] + k] = slot_base + ns + int64_t(k) * int64_t(ri.size()) + int64_t(t);
+                        slot_of_user[cv0 + geo[it.c].sfirst[it.b] + k] = slot_base + ns + int64_t(k) * int64_t(ri.size()) + int64_t(t);
                 }
             }
             // the register-resident kernel gives every branch reg_len rows: a
@@ -473,12 +501,12 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                 const int64_t cv0 = L.cell_cv0[it.c];
                 TaskDesc T_{};
                 T_.len = it.len;
-                T_.par = (it.b < 0) ? -1 : int32_t(slot_of_user[cv0 + geo[it.c].pnode[it.b]] - slot_base);
+                T_.par = (it.b < 0) ? -1 : int32_t(slot_of_user[cv0 + geo[it.c].spnode[it.b]] - slot_base);
                 T_.ch0 = int32_t(L.ch_slot.size()) - D.ch0;  // pack-local child entry
                 T_.nch = 0;
-                for (int32_t b2 = 0; b2 < cells[it.c].n_branch; ++b2)
-                    if (br[cells[it.c].branch_begin + b2].parent == it.b) {
-                        L.ch_slot.push_back(int32_t(slot_of_user[cv0 + geo[it.c].first[b2]] - slot_base));
+                for (int32_t b2 = 0; b2 < geo[it.c].nseg(); ++b2)
+                    if (geo[it.c].sparent[b2] == it.b) {
+                        L.ch_slot.push_back(int32_t(slot_of_user[cv0 + geo[it.c].sfirst[b2]] - slot_base));
                         L.ch_task.push_back(task_of.at({it.c, b2}));
                         T_.nch++;
                     }
@@ -490,9 +518,9 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         }
         for (const auto& cb : item_of) {
             const int32_t b = cb.second;
-            const int32_t pb = (b < 0) ? -2 : br[cells[cb.first].branch_begin + b].parent;
+            const int32_t pb = (b < 0) ? -2 : geo[cb.first].sparent[b];
             L.tk_ptask.push_back(pb == -2 ? -1 : task_of.at({cb.first, pb}));
-            L.tk_lev.push_back(b < 0 ? 0 : geo[cb.first].depth[b]);
+            L.tk_lev.push_back(b < 0 ? 0 : geo[cb.first].sdepth[b]);
         }
         D.ntk = int32_t(L.tasks.size()) - D.tk0;
         D.nch = int32_t(L.ch_slot.size()) - D.ch0;

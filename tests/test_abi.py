@@ -203,11 +203,12 @@ def test_plan_layout_invariants_uneven_and_networks(mode, T):
         assert info["lds_bytes"] <= 160 * 1024 - 256
 
 
-def test_plan_falls_back_from_registers_for_long_branches():
+def test_plan_cuts_long_branches_into_register_segments():
     m = gen.config1()  # 32-CV branches do not fit 16 registers
-    assert _plan(m)["coef_mode"] == 2
-    with pytest.raises(arbmi.ArbError):
-        _plan(m, coef_mode=3)
+    assert _plan(m)["coef_mode"] == 2  # the default keeps the streamed layout for them
+    info = _plan(m, coef_mode=3)  # on request: chains of four 8-CV segments
+    assert info["coef_mode"] == 3 and info["reg_len"] == 8
+    assert info["n_slots"] == 8 * (1 + 4 * 4)  # soma + 16 segments, 8 rows each
 
 
 def test_plan_register_layout_for_full_ring_packs_four_cells():

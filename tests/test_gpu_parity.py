@@ -57,6 +57,16 @@ def test_config1_full_run_every_cv():
     check(m, 4000, probes=np.arange(129))
 
 
+@pytest.mark.parametrize("block", [64, 256])
+def test_config1_register_layout_with_segmented_branches(block):
+    """The register-resident kernel on 32-CV branches, each cut into a chain
+    of four 8-CV segments."""
+    m = gen.config1()
+    _, _, _, info = gpu_run(m, 10, np.arange(2), coef_mode=3, block_threads=block)
+    assert info["coef_mode"] == 3 and info["reg_len"] == 8
+    check(m, 4000, probes=np.arange(129), coef_mode=3, block_threads=block)
+
+
 @pytest.mark.parametrize("kick_all", [True, False])
 def test_ring_small(kick_all):
     m = gen.config2(n_cells=12, kick_all=kick_all)
@@ -109,6 +119,8 @@ def test_edge_morphologies():
         d.clamps.append((-1, 0, 40, 900, 0.3 + 0.1 * k))
     m = gen.assemble(cells, n_steps=1200)
     check(m, 1200, probes=np.arange(int(gen.n_cvs(m).sum())))
+    # the register-resident layout, the 100-CV branch cut into 8-CV segments
+    check(m, 1200, probes=np.arange(int(gen.n_cvs(m).sum())), coef_mode=3, block_threads=128)
 
 
 @pytest.mark.parametrize("coef_mode", [1, 2, 3])
