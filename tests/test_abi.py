@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from paper_1901_07454_amd import arbmi
+from tests import models
 from workloads import gen
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -215,3 +216,25 @@ def test_plan_register_layout_for_full_ring_packs_four_cells():
     m = gen.config2(n_cells=64, n_steps=10)
     info = _plan(m, coef_mode=3, block_threads=256)
     assert info["n_packs"] == 16  # 4 cells of 128 branch tasks fill 256 threads x 2 slots
+
+
+def test_plan_network_epochs_at_most_16384_steps():
+    """A network's epoch is its minimum delay, at most 16,384 steps (the event
+    pull keeps one LDS counter per step of the epoch)."""
+    cells = [models.bare_cell([], [], [], []) for _ in range(2)]
+    for k, d in enumerate(cells):
+        d.syn.append((-1, 0, 2.0, 0.0))
+        d.in_conn.append((1 - k, 0, 20000, 0.01))
+    m = gen.assemble(cells, n_steps=10)
+    assert _plan(m)["epoch_steps"] == 16384
+    cells[0].in_conn[0] = (1, 0, 300, 0.01)
+    assert _plan(gen.assemble(cells, n_steps=10))["epoch_steps"] == 300
+
+
+def test_plan_cells_with_many_inputs_get_a_pack_each():
+    """Packs of several cells hold at most 4096 incoming connections; a cell
+    with more takes a pack of its own."""
+    m = gen.config7(n_cells=8, n_syn=5000, n_steps=10)
+    assert _plan(m, coef_mode=3, block_threads=128)["n_packs"] == 8
+    m = gen.config7(n_cells=8, n_syn=500, n_steps=10)
+    assert _plan(m, coef_mode=3, block_threads=128)["n_packs"] < 8
