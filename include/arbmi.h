@@ -122,18 +122,22 @@ typedef struct {
     double dt_ms;             /* > 0 */
     double threshold_mV;      /* soma spike threshold (upward crossing) */
     double v_init_mV;         /* initial V; gates start at steady state, g = 0 */
-    int32_t epoch_steps;      /* 0 = the minimum connection delay; must not exceed it */
+    int32_t epoch_steps;      /* 0 = the minimum connection delay (at most 16384 in a
+                                 network); must not exceed either */
     int32_t flags;            /* ARB_FLAG_* */
     void *hip_stream;         /* hipStream_t, NULL = null stream */
     void *(*alloc)(size_t bytes, void *ctx); /* device allocator, NULL = hipMalloc */
     void (*free)(void *ptr, void *ctx);
     void *alloc_ctx;
     int64_t spike_capacity;   /* spikes kept between arb_get_spikes calls; 0 = default */
-    int64_t event_capacity;   /* network events per (cell pack, epoch); 0 = default */
+    int64_t event_capacity;   /* network events per (cell pack, epoch); 0 = 4 x the busiest
+                                 pack's incoming connections */
     int32_t block_threads;    /* threads per cell pack; 0 = autotuned */
     int32_t coef_mode;        /* 0 = autotuned, 1 = per-CV coefficients in LDS, 2 = streamed,
-                                 3 = held in registers (branches of <= 16 CVs; not with
-                                 ARB_FLAG_GRADIENTS, which needs the states mode 1 or 2 records) */
+                                 3 = held in registers (by default for branches of <= 16 CVs;
+                                 on request longer branches are cut into chains of 8-CV
+                                 segments; not with ARB_FLAG_GRADIENTS, which needs the
+                                 states mode 1 or 2 records) */
     int32_t cells_per_pack;   /* most cells one workgroup advances; 0 = autotuned */
     int32_t reserved;
 } arb_params;
