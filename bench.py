@@ -120,7 +120,7 @@ def cpu_baseline(cfg: int, budget_s: float = 20.0):
     import oracle
     oracle.build() if not os.path.exists(oracle.LIB) else None
     workers = max(1, min(16, os.cpu_count() or 1))
-    per = {1: (1, 4000), 2: (96, 1000), 3: (24, 800), 4: (64, 2000), 5: (48, 800), 6: (16, 1600),
+    per = {1: (1, 4000), 2: (96, 1000), 3: (24, 800), 4: (64, 2000), 5: (48, 1200), 6: (16, 1600),
            7: (16, 1600)}[cfg]
     n_cells, steps = per
     base = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536, 6: 8192, 7: 8192}[cfg]
