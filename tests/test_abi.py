@@ -238,3 +238,13 @@ def test_plan_cells_with_many_inputs_get_a_pack_each():
     assert _plan(m, coef_mode=3, block_threads=128)["n_packs"] == 8
     m = gen.config7(n_cells=8, n_syn=500, n_steps=10)
     assert _plan(m, coef_mode=3, block_threads=128)["n_packs"] < 8
+
+
+def test_plan_segments_are_balanced_chains():
+    """A 100-CV branch in the register layout: ceil(100 / 8) = 13 segments of
+    7 or 8 CVs (nearly equal), each given 8 register rows, plus the soma."""
+    m = gen.assemble([models.bare_cell([-1], [100], [900.0], [2.0])], n_steps=10)
+    info = _plan(m, coef_mode=3, block_threads=64)
+    assert info["coef_mode"] == 3 and info["reg_len"] == 8
+    assert info["n_cv"] == 101 and info["n_slots"] == 8 * (1 + 13)
+    assert _plan(m)["coef_mode"] == 2  # not chosen by default for such branches
