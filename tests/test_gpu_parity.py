@@ -174,10 +174,12 @@ def test_synapse_dominated_ring_small(n_syn):
     assert len(sp) >= 5
 
 
-def test_synapse_dominated_mixed_parameters():
+@pytest.mark.parametrize("block", [0, 64, 256])
+def test_synapse_dominated_mixed_parameters(block):
     """HBM-resident synapses whose reversal potentials and time constants
     differ, with external events on thousands of them, so every synapse the
-    kernel streams carries conductance."""
+    kernel streams carries conductance; groups of 64, 128 (the default) and
+    256 threads interleave them."""
     rng = np.random.default_rng(61)
     m = gen.config6(n_cells=4, n_syn=6000, n_steps=600)
     ns = len(m["syn_e"])
@@ -192,7 +194,32 @@ def test_synapse_dominated_mixed_parameters():
     w = np.concatenate([np.full(len(m["ev_w"]), 0.1), w])
     o = np.lexsort((syn, step))
     m["ev_syn"], m["ev_step"], m["ev_w"] = syn[o], step[o], w[o]
-    check(m, 600)
+    kw = dict(coef_mode=3, block_threads=block) if block else {}
+    check(m, 600, **kw)
+
+
+def test_network_exchange_under_graph_replay_and_state_restore():
+    """The 10k-connectivity model (16 cells): whole epochs replayed from a
+    captured graph (the exchange reads the epoch from device memory) match
+    direct launches bitwise, and a state saved in the middle of an epoch
+    with events pending resumes identically."""
+    from paper_1901_07454_amd import arbmi
+    m = gen.config7(n_cells=16, n_steps=2400)
+    probes = oracle.cell_cv_begin(m)[:-1]
+    ref = gpu_run(m, 2400, probes)
+    got = gpu_run(m, 2400, probes, flags=arbmi.ARB_FLAG_GRAPH)
+    assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1]) and ref[2] == got[2]
+    a = _sim(m)
+    a.step(815)  # the first volley arrives over steps 811-825
+    blob = a.get_state()
+    a.step(1585)
+    b = _sim(m)
+    b.set_state(blob)
+    b.step(1585)
+    assert np.array_equal(a.voltages_host(), b.voltages_host())
+    assert np.array_equal(a.voltages_host(), ref[1])
+    a.close()
+    b.close()
 
 
 def _event_run_model(n_cells=12, n_syn=6, dup=3, delay=120):
