@@ -563,9 +563,12 @@ __global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
                     ow[pos] = w;
                 }
             }
-            __syncthreads();
+            // one wave: its LDS operations take effect in issue order, so a
+            // wave barrier orders the cursor's read and update without
+            // waiting for the event stores
+            __builtin_amdgcn_wave_barrier();
             if (lane == 0) bins[B] = base + uint32_t(__popcll(mask));
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
             last = B;
         }
     }
