@@ -541,6 +541,47 @@ __global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
             }
         }
         const bool more = k1 - k0 > U;
+        // fast path, when no lane has more than one event in the epoch (a
+        // volley): sort the chunk's (step, lane) keys across the wave
+        // (bitonic network over the lanes); an event's place among its
+        // step's events is its distance from the start of its step's run,
+        // which keeps lane order, as the general path below does
+        int nev = more ? 2 : 0, one = K;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (bs[u] != INT_MAX) {
+                ++nev;
+                one = bs[u];
+            }
+        if (__all(nev <= 1)) {
+            uint32_t key = (uint32_t(one) << 6) | uint32_t(lane);
+            for (int k = 2; k <= 64; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    const uint32_t other = __shfl_xor(key, j);
+                    const bool low = (lane & j) == 0, up = (lane & k) == 0;
+                    key = (low == up) ? min(key, other) : max(key, other);
+                }
+            const int b = int(key >> 6), from = int(key & 63u);
+            const int32_t qq = __shfl(q, from);
+            const double ww = __shfl(w, from);
+            const int prev = __shfl_up(b, 1), next = __shfl_down(b, 1);  // every lane shuffles
+            const bool start = lane == 0 || prev != b;
+            const bool end = lane == 63 || next != b;
+            const uint64_t starts = __ballot(start) & ((uint64_t(2) << lane) - 1u);
+            const uint32_t rank = uint32_t(lane - (63 - __clzll(starts)));
+            const uint32_t base = (b < K) ? bins[b] : 0u;
+            if (b < K) {
+                const uint32_t pos = base + rank;
+                if (pos < cap) {
+                    oq[pos] = qq;
+                    ow[pos] = ww;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (b < K && end) bins[b] = base + rank + 1u;
+            __builtin_amdgcn_wave_barrier();
+            continue;
+        }
         int last = -1;
         for (;;) {
             int mine = INT_MAX;  // this lane's first event step after `last`
