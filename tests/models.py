@@ -70,3 +70,37 @@ def chain(n_cells, delays, w=0.05, n_steps=2000, cfg_cells=None):
         d.ext = [(0, 0, 0.05)] if k == 0 else []
         cells.append(d)
     return gen.assemble(cells, n_steps=n_steps)
+
+
+def mixed_pull_chunks(n_steps=4000, seed=11):
+    """Targets whose incoming connections, in rank order (synapse, then
+    source), make chunks of 64 of three kinds within one epoch of 800 steps
+    (all delays 800): gids 0-95 and 98-105 are sources kicked every 850 steps
+    (even gids from step 100, odd from step 400), so each has at most one
+    spike per epoch; gids 96 and 97 fire every ~366 steps under a clamp, two
+    or three spikes per epoch.  Each of the two targets (106, 107) hears every
+    kicked source once and each clamped source 16 times, on synapse 0 (plus a
+    few kicked sources on synapse 1): its first 64 connections carry at most
+    one event each, the next 64 mix kicked and clamped sources, and the last
+    ones are a ragged chunk of kicked sources, whose events share their steps
+    with the first chunk's."""
+    rng = np.random.default_rng(seed)
+    kicked = list(range(96)) + list(range(98, 106))
+    cells = []
+    for g in range(106):
+        d = bare_cell([], [], [], [])
+        if g in (96, 97):
+            d.clamps.append((-1, 0, 0, n_steps, 0.2))
+        else:
+            d.syn.append((-1, 0, 2.0, 0.0))
+            d.ext = [(0, s, 0.05) for s in range(100 if g % 2 == 0 else 400, n_steps, 850)]
+        cells.append(d)
+    for _ in range(2):
+        d = bare_cell([], [], [], [])
+        d.syn.append((-1, 0, 2.0, 0.0))
+        d.syn.append((-1, 0, 5.0, -70.0))
+        d.in_conn = [(s, 0, 800, float(rng.uniform(1e-4, 5e-4))) for s in kicked]
+        d.in_conn += [(s, 0, 800, float(rng.uniform(1e-4, 5e-4))) for s in (96, 97) for _ in range(16)]
+        d.in_conn += [(s, 1, 800, float(rng.uniform(1e-4, 5e-4))) for s in kicked[:5]]
+        cells.append(d)
+    return gen.assemble(cells, n_steps=n_steps)

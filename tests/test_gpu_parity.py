@@ -285,6 +285,19 @@ def test_sources_firing_often_within_the_delay(coef_mode):
     assert per_cell.min() >= 8  # more than four spikes of a source within 80 ms
 
 
+@pytest.mark.parametrize("coef_mode,block", [(0, 0), (3, 64), (3, 256), (1, 64)])
+def test_pull_mixes_sorted_and_stepwise_chunks(coef_mode, block):
+    """One pack's incoming connections in chunks of 64 where every lane has at
+    most one event in the epoch (placed by the in-wave sort), chunks with
+    lanes of two or three events (placed step by step) and a ragged chunk,
+    their events sharing delivery steps: both placements advance the same
+    per-step cursors."""
+    m = models.mixed_pull_chunks()
+    kw = dict(coef_mode=coef_mode, block_threads=block) if block else {}
+    _, sp = check(m, 4000, **kw)
+    assert sum(1 for _, g in sp if g >= 106) >= 8
+
+
 @pytest.mark.parametrize("block", [0, 64, 256])
 def test_ten_thousand_way_network_small(block):
     """The 10k-connectivity model's cells and wiring (every synapse from a

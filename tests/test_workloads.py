@@ -33,3 +33,38 @@ def test_subsets_regenerate_identically():
     assert np.array_equal(sub["br_length"], np.concatenate(
         [full["br_length"][full["cell_branch_begin"][c]:full["cell_branch_begin"][c] + full["cell_n_branch"][c]]
          for c in (3, 7)]))
+
+
+def test_local_synapse_indices_are_checked():
+    """A connection or external event names a synapse of its own cell."""
+    import pytest
+    from tests import models
+    for field, entry in (("in_conn", (0, 1, 10, 1e-3)), ("ext", (1, 5, 0.05))):
+        src, dst = models.bare_cell([], [], [], []), models.bare_cell([], [], [], [])
+        dst.syn.append((-1, 0, 2.0, 0.0))
+        getattr(dst, field).append(entry)  # synapse 1 of a cell with one synapse
+        with pytest.raises(ValueError, match="cell 1"):
+            gen.assemble([src, dst], n_steps=10)
+
+
+def test_mixed_pull_chunks_event_counts():
+    """The model behind the event pull's mixed-chunk parity test does what it
+    claims, in the oracle: in every epoch window each kicked source fires
+    exactly once and each clamped source at least twice, the two kicked
+    groups at different steps, and the targets fire."""
+    import oracle
+    from tests import models
+    m = models.mixed_pull_chunks()
+    s = oracle.Sim(m)
+    s.run(4000)
+    g, st, _ = s.spikes()
+    kicked = [k for k in range(106) if k not in (96, 97)]
+    for e in range(4):  # spikes of [800 e, 800 e + 800) arrive in epoch e + 1
+        inw = (st >= 800 * e) & (st < 800 * e + 800)
+        per = np.bincount(g[inw], minlength=108)
+        assert np.all(per[kicked] == 1) and per[96] >= 2 and per[97] >= 2
+        assert len(np.unique(st[inw & np.isin(g, kicked)])) == 2
+    assert np.sum(g == 106) >= 4 and np.sum(g == 107) >= 4
+    # rank order on the targets: 96 kicked, 32 clamped, 8 kicked on synapse 0
+    src = m["con_src"][(m["con_dst"] == 106) & (m["con_syn"] == m["con_syn"][m["con_dst"] == 106].min())]
+    assert np.array_equal(np.sort(src)[:96], np.arange(96)) and np.all(np.sort(src)[96:128] >= 96)

@@ -359,6 +359,15 @@ def assemble(cells: list[CellDesc], gids=None, n_steps: int = 0,
                           (sb[ci] + ls[ok]).astype(np.uint32), dl[ok].astype(np.int32), w[ok].astype(np.float64)])
         ccols = [np.concatenate([p_[j] for p_ in parts]) for j in range(5)]
     m["con_src"], m["con_dst"], m["con_syn"], m["con_delay"], m["con_w"] = ccols
+    # a connection's or event's synapse is local to its cell: one index past
+    # the cell's synapses would silently name another cell's synapse
+    bad = [ci for ci, c in enumerate(cells)
+           if any(not 0 <= int(x[1]) < nsyn[ci] for x in c.in_conn)
+           or any(not 0 <= int(x[0]) < nsyn[ci] for x in c.ext)
+           or (c.in_conn_arr is not None and len(c.in_conn_arr[1])
+               and not (0 <= np.min(c.in_conn_arr[1]) and np.max(c.in_conn_arr[1]) < nsyn[ci]))]
+    if bad:
+        raise ValueError(f"cell {bad[0]}: connection or event synapse out of the cell's range")
     ev = [(int(sb[ci]) + ls, st, w) for ci, c in enumerate(cells) for (ls, st, w) in c.ext]
     m["ev_syn"] = np.array([x[0] for x in ev], np.uint32)
     m["ev_step"] = np.array([x[1] for x in ev], np.int64)
