@@ -190,8 +190,12 @@ int arb_build_cells(const arb_cell *cells, int32_t n_cells, const arb_branch *br
 /* Advance every cell by n_steps steps of dt (Sec. II operator splitting:
  * events due at the step start, currents at V(t), implicit Euler + Hines for
  * V(t+dt), states with the new V, threshold test; spike exchange at each
- * epoch end, Sec. IV-A).  Asynchronous.  On failure the sim is left at the
- * last completed epoch.  ARB_EOVERFLOW if a spike or event buffer filled. */
+ * epoch end, Sec. IV-A).  Asynchronous: errors returned here are those of the
+ * host (arguments, launches); on such a failure the sim is left at the last
+ * completed epoch.  A spike or event buffer that fills during the steps is
+ * flagged on the device (the writes past it are dropped, never made out of
+ * bounds), and arb_sync and arb_get_spikes report the flag as ARB_EOVERFLOW;
+ * it stays set for the life of the sim. */
 int arb_step(arb_sim s, int64_t n_steps);
 
 /* Copy all n_cv voltages in user CV order into dst (n >= n_cv doubles),
@@ -199,8 +203,9 @@ int arb_step(arb_sim s, int64_t n_steps);
 int arb_get_voltages(arb_sim s, double *dst, int64_t n, int dst_on_device);
 
 /* Drain the spikes recorded since the last call into host dst, sorted by
- * (step, gid).  *n_out = number written; ARB_EOVERFLOW if cap was too small
- * (nothing is drained then) or spikes were lost to a full device buffer. */
+ * (step, gid).  *n_out = number written.  ARB_EOVERFLOW if cap was too small
+ * (nothing is drained then, *n_out = 0), or if a spike or event buffer has
+ * overflowed (the kept spikes are still written and counted in *n_out). */
 int arb_get_spikes(arb_sim s, arb_spike *dst, int64_t cap, int64_t *n_out);
 
 /* Record V of the given user CVs after every step from now on, for up to
@@ -254,7 +259,8 @@ int arb_plan_layout(const arb_cell *cells, int32_t n_cells, const arb_branch *br
  * launches since the last call; synchronises the stream. */
 int arb_get_kernel_time(arb_sim s, double *ms_total, int64_t *n_launches);
 
-/* Wait for all enqueued work of the sim. */
+/* Wait for all enqueued work of the sim.  ARB_EOVERFLOW if a spike or event
+ * buffer has overflowed (arb_step). */
 int arb_sync(arb_sim s);
 
 /* Release everything the sim holds.  NULL is accepted. */

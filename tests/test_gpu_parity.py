@@ -298,6 +298,27 @@ def test_pull_mixes_sorted_and_stepwise_chunks(coef_mode, block):
     assert sum(1 for _, g in sp if g >= 106) >= 8
 
 
+@pytest.mark.parametrize("coef_mode", [3, 1])
+def test_buffer_overflow_is_flagged_and_reported(coef_mode):
+    """Capacities set far below what the run needs (on the host): ~140 events
+    per target and epoch into buckets of 16, ~106 spikes of one epoch into a
+    buffer of 8.  The kernels drop what does not fit and flag it; arb_sync
+    and arb_get_spikes return ARB_EOVERFLOW naming the buffer, and keep
+    doing so.  A sim built afterwards with default capacities still matches
+    the oracle."""
+    from paper_1901_07454_amd import arbmi
+    m = models.mixed_pull_chunks(n_steps=2400)
+    for kw, what in ((dict(event_capacity=16), "event"), (dict(spike_capacity=8), "spike")):
+        sim = _sim(m, coef_mode=coef_mode, block_threads=64, **kw)
+        sim.step(1200)
+        for call in (sim.sync, sim.spikes, sim.sync):
+            with pytest.raises(arbmi.ArbError) as e:
+                call()
+            assert e.value.code == arbmi.ARB_EOVERFLOW and what in str(e.value)
+        sim.close()
+    check(m, 2400, coef_mode=coef_mode, block_threads=64)
+
+
 @pytest.mark.parametrize("block", [0, 64, 256])
 def test_ten_thousand_way_network_small(block):
     """The 10k-connectivity model's cells and wiring (every synapse from a
