@@ -104,3 +104,23 @@ def mixed_pull_chunks(n_steps=4000, seed=11):
         d.in_conn += [(s, 1, 800, float(rng.uniform(1e-4, 5e-4))) for s in kicked[:5]]
         cells.append(d)
     return gen.assemble(cells, n_steps=n_steps)
+
+
+def longest_epochs(n_steps=33000):
+    """Soma-only cells whose shortest delay (20,000 steps) exceeds the
+    longest network epoch (16,384 steps), with events due at the last step
+    of epoch 1 (step 32767) and the first step of epoch 2 (32768): cell 0,
+    kicked at step 0, fires at step 7 and reaches cell 1 (delay 20,000) and
+    cell 2 (delay 32,760); cell 3, kicked at step 12,761, fires at 12,768 and
+    reaches cell 4 (delay 20,000).  Each event makes its target fire."""
+    cells = []
+    for _ in range(5):
+        d = bare_cell([], [], [], [])
+        d.syn.append((-1, 0, 2.0, 0.0))
+        cells.append(d)
+    cells[0].ext = [(0, 0, 0.05)]
+    cells[3].ext = [(0, 12761, 0.05)]
+    cells[1].in_conn = [(0, 0, 20000, 0.05)]
+    cells[2].in_conn = [(0, 0, 32760, 0.05)]
+    cells[4].in_conn = [(3, 0, 20000, 0.05)]
+    return gen.assemble(cells, n_steps=n_steps)

@@ -319,6 +319,19 @@ def test_buffer_overflow_is_flagged_and_reported(coef_mode):
     check(m, 2400, coef_mode=coef_mode, block_threads=64)
 
 
+@pytest.mark.parametrize("coef_mode", [3, 1])
+def test_longest_network_epochs(coef_mode):
+    """Epochs at their cap of 16,384 steps (one LDS counter per step in the
+    event pull), events due at an epoch's last and next epoch's first step,
+    a spike history of three epochs."""
+    m = models.longest_epochs()
+    _, sp = check(m, 33000, coef_mode=coef_mode, block_threads=64)
+    assert sp == [(7, 0), (12768, 3), (20014, 1), (32774, 2), (32775, 4)]
+    sim = _sim(m, coef_mode=coef_mode, block_threads=64)
+    assert sim.info["epoch_steps"] == 16384
+    sim.close()
+
+
 @pytest.mark.parametrize("block", [0, 64, 256])
 def test_ten_thousand_way_network_small(block):
     """The 10k-connectivity model's cells and wiring (every synapse from a

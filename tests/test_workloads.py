@@ -68,3 +68,16 @@ def test_mixed_pull_chunks_event_counts():
     # rank order on the targets: 96 kicked, 32 clamped, 8 kicked on synapse 0
     src = m["con_src"][(m["con_dst"] == 106) & (m["con_syn"] == m["con_syn"][m["con_dst"] == 106].min())]
     assert np.array_equal(np.sort(src)[:96], np.arange(96)) and np.all(np.sort(src)[96:128] >= 96)
+
+
+def test_longest_epochs_model_in_the_oracle():
+    """The spikes the longest-epoch parity test expects, from the oracle at
+    its own epoch length and at the 16,384-step epochs of the library."""
+    import oracle
+    from tests import models
+    m = models.longest_epochs()
+    for K in (None, 16384):
+        s = oracle.Sim(m, epoch_steps=K)
+        s.run(33000)
+        g, st, _ = s.spikes()
+        assert sorted(zip(st.tolist(), g.tolist())) == [(7, 0), (12768, 3), (20014, 1), (32774, 2), (32775, 4)]
