@@ -515,28 +515,60 @@ __global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
     double* ow = a.bk_w + int64_t(p) * a.bk_cap;
     const uint64_t below = (uint64_t(1) << lane) - 1u;
     // pass 2: 64 connections at a time, this lane's event steps (the source's
-    // spikes in the window, up to U of them in registers, more re-read)
-    for (int64_t c0 = r0; c0 < r1; c0 += 64) {
-        const int64_t r = c0 + lane;
-        int64_t d = 0, k0 = 0, k1 = 0;
-        int32_t q = 0;
-        double w = 0.0;
-        int bs[U];
+    // spikes in the window, up to U of them in registers, more re-read).
+    // The loads run ahead of the placement: a chunk's source and delay two
+    // chunks early, its source's spike range one chunk early, so a chunk
+    // waits for one round of loads (its spike steps, and its synapse and
+    // weight if the source fired). Loads complete in issue order, so each
+    // chunk issues its own loads before those it issues for later chunks.
+    int64_t d_c = 0, k0_c = 0, k1_c = 0;  // the chunk about to run
+    uint32_t src_n = 0u;                  // the chunk after it
+    int64_t d_n = 0;
+    {
+        const int64_t r = r0 + lane;
         if (r < r1) {
             const uint32_t src = a.cr_src[r];
-            d = a.cr_delay[r];
-            k0 = a.sx_off[src];
-            k1 = a.sx_off[src + 1];
-            if (k1 > k0) {
-                q = a.cr_syn[r];
-                w = a.cr_w[r];
-            }
+            d_c = a.cr_delay[r];
+            k0_c = a.sx_off[src];
+            k1_c = a.sx_off[src + 1];
         }
+        if (r + 64 < r1) {
+            src_n = a.cr_src[r + 64];
+            d_n = a.cr_delay[r + 64];
+        }
+    }
+    for (int64_t c0 = r0; c0 < r1; c0 += 64) {
+        const int64_t r = c0 + lane;
+        const int64_t d = d_c, k0 = k0_c, k1 = k1_c;  // k0 = k1 = 0 past r1
+        int32_t q = 0;
+        double w = 0.0;
+        if (k1 > k0) {
+            q = a.cr_syn[r];
+            w = a.cr_w[r];
+        }
+        int64_t st[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) st[u] = k0 + u < k1 ? a.sx_step[k0 + u] : 0;
+        // the next chunk's spike ranges, the chunk after's sources and delays
+        k0_c = 0;
+        k1_c = 0;
+        d_c = d_n;
+        if (r + 64 < r1) {
+            k0_c = a.sx_off[src_n];
+            k1_c = a.sx_off[src_n + 1];
+        }
+        src_n = 0u;
+        d_n = 0;
+        if (r + 128 < r1) {
+            src_n = a.cr_src[r + 128];
+            d_n = a.cr_delay[r + 128];
+        }
+        int bs[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             bs[u] = INT_MAX;
             if (k0 + u < k1) {
-                const int64_t b = a.sx_step[k0 + u] + d - lo;
+                const int64_t b = st[u] + d - lo;
                 if (b >= 0 && b < K) bs[u] = int(b);
             }
         }
