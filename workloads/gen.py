@@ -29,9 +29,10 @@ Every cell draws from its own generator, SeedSequence(entropy, spawn_key=(i,)),
 so any subset of cells can be regenerated alone and identically (used to build
 the light-cone sub-models the full-size parity checks run on the CPU).
 
-Units and constants follow the textbook Hodgkin-Huxley squid-axon values and
-the passive/synapse readings recorded for this build: hh gNa 0.12, gK 0.036,
-gL 0.0003 S/cm^2; pas 0.001 S/cm^2 at -65 mV; expsyn reversal 0 mV.
+Units and constants follow the textbook Hodgkin-Huxley squid-axon values,
+with passive and synapse values chosen where the paper gives none: hh gNa
+0.12, gK 0.036, gL 0.0003 S/cm^2; pas 0.001 S/cm^2 at -65 mV; expsyn
+reversal 0 mV.
 """
 from __future__ import annotations
 
