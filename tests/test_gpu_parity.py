@@ -430,7 +430,8 @@ def test_arbitrary_step_splits_match_one_call():
     a = _sim(m)
     a.step(1000)
     b = _sim(m)
-    for k in (1, 199, 1, 350, 449):
+    assert len(b.spikes()) == 0  # nothing recorded before the first step
+    for k in (0, 1, 199, 0, 1, 350, 449):  # zero-step calls do nothing
         b.step(k)
     assert np.array_equal(a.voltages_host(), b.voltages_host())
     sa, sb = a.spikes(), b.spikes()
