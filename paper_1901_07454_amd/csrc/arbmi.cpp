@@ -588,13 +588,13 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
                 hipStream_t x;
                 hipEvent_t e;
                 if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) {
-                    delete s;
+                    destroy_sim(s);  // the streams and events made so far
                     err = "stream creation failed";
                     return ARB_EHIP;
                 }
                 s->aux.push_back(x);
                 if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-                    delete s;
+                    destroy_sim(s);  // the streams and events made so far
                     err = "event creation failed";
                     return ARB_EHIP;
                 }
@@ -602,7 +602,7 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
             }
             hipEvent_t e;
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-                delete s;
+                destroy_sim(s);  // the streams and events made so far
                 err = "event creation failed";
                 return ARB_EHIP;
             }
@@ -611,7 +611,7 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
     }
     hipError_t he = prepare_step_kernels(int(d.lds_max));
     if (he != hipSuccess) {
-        delete s;
+        destroy_sim(s);
         err = std::string("prepare_step_kernels: ") + hipGetErrorString(he);
         return ARB_EHIP;
     }
@@ -622,8 +622,7 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
     }
     if (rc != ARB_OK) {
         err = g_err;
-        s->release_all();
-        delete s;
+        destroy_sim(s);  // buffers, streams and events
         return rc;
     }
     *out = s;
