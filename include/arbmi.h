@@ -234,8 +234,11 @@ int arb_grad_forward(arb_sim s, int64_t n_steps, int32_t ckpt_every, double *tra
 int arb_grad_backward(arb_sim s, const double *dL_dtrace_dev, double *dL_dtheta_dev);
 
 /* Checkpoint: serialise / restore the dynamic state (step, V, gates,
- * synaptic conductances, pending events, event cursors).  With blob NULL,
- * arb_get_state writes only the size into *n_out. */
+ * synaptic conductances, pending events, event cursors, spike buffer and
+ * history).  With blob NULL, arb_get_state writes only the size into *n_out.
+ * arb_set_state takes a blob of the same model (ARB_EINVAL otherwise, or if
+ * any cursor, offset, synapse index or gid in it is out of range; the sim is
+ * then unchanged). */
 int arb_get_state(arb_sim s, void *blob, int64_t cap, int64_t *n_out);
 int arb_set_state(arb_sim s, const void *blob, int64_t n);
 

@@ -992,6 +992,53 @@ int arb_set_state(arb_sim s_, const void* blob, int64_t n) {
     for (const Part& q : parts) total += q.bytes;
     if (n < total) return fail(ARB_EINVAL, "state blob truncated");
     const char* in = static_cast<const char*>(blob);
+    {
+        // every value a kernel indexes with must lie in range before it
+        // reaches the device (the blob is the caller's memory)
+        const char* at_part[sizeof parts / sizeof parts[0]];
+        int64_t off = sizeof h;
+        for (size_t k = 0; k < sizeof parts / sizeof parts[0]; ++k) {
+            at_part[k] = in + off;
+            off += parts[k].bytes;
+        }
+        auto rd32 = [](const char* b, int64_t i) { uint32_t v; std::memcpy(&v, b + 4 * i, 4); return v; };
+        auto rd64 = [](const char* b, int64_t i) { int64_t v; std::memcpy(&v, b + 8 * i, 8); return v; };
+        Counters c;
+        std::memcpy(&c, at_part[10], sizeof c);
+        const uint32_t have = std::min(c.sp_count, s->sp_cap);
+        if (h.step < 0 || h.step >= (int64_t(1) << 31) || h.sp_user < 0 || h.sp_user > int64_t(have) ||
+            c.sp_exch > have)
+            return fail(ARB_EINVAL, "state blob: step or spike counters out of range");
+        for (int64_t p = 0; p < np; ++p) {
+            const int64_t x = rd64(at_part[5], p);
+            if (x < L.packs[p].xe0 || x > L.packs[p].xe1) return fail(ARB_EINVAL, "state blob: event cursor out of range");
+        }
+        for (uint32_t i = 0; i < have; ++i)
+            if (rd32(at_part[11], i) >= uint32_t(L.n_cells)) return fail(ARB_EINVAL, "state blob: spike gid out of range");
+        if (s->d_bk_off) {
+            const int64_t K = s->K;
+            for (int64_t p = 0; p < np; ++p) {
+                uint32_t prev = 0;
+                for (int64_t b = 0; b <= K; ++b) {
+                    const uint32_t o = rd32(at_part[6], p * (K + 1) + b), x = rd32(at_part[7], p * (K + 1) + b);
+                    if (o < prev || o > uint32_t(s->bk_cap) || x > uint32_t(K))
+                        return fail(ARB_EINVAL, "state blob: event bucket offsets out of range");
+                    prev = o;
+                }
+                for (uint32_t i = 0; i < prev; ++i) {
+                    const uint32_t q = rd32(at_part[8], p * int64_t(s->bk_cap) + i);
+                    if (q >= uint32_t(L.packs[p].nsyn)) return fail(ARB_EINVAL, "state blob: event synapse out of range");
+                }
+            }
+            for (int64_t k = 0; k < s->n_hist; ++k) {
+                const uint32_t m = rd32(at_part[14], k);
+                if (m > s->hist_cap) return fail(ARB_EINVAL, "state blob: spike history count out of range");
+                for (uint32_t i = 0; i < m; ++i)
+                    if (rd32(at_part[15], k * int64_t(s->hist_cap) + i) >= uint32_t(L.n_cells))
+                        return fail(ARB_EINVAL, "state blob: spike history gid out of range");
+            }
+        }
+    }
     int64_t at = sizeof h;
     HIP_TRY(hipStreamSynchronize(s->st));
     for (const Part& q : parts) {

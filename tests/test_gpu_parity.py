@@ -332,6 +332,67 @@ def test_longest_network_epochs(coef_mode):
     sim.close()
 
 
+def _state_offsets(blob, K):
+    """Byte offsets of the parts of a state blob: an 80-byte header (magic,
+    step, n_slots, n_hh, n_syn, n_packs, n_bk, bk_cap, sp_cap, sp_user), then
+    V, the three gates, g, event cursors, bucket offsets and next steps,
+    bucket synapses and weights, counters, spikes (gid, step, t) and the
+    spike history (counts, gids, steps)."""
+    h = np.frombuffer(bytes(blob[:80]), np.int64)
+    n_slots, n_hh, n_syn, n_packs, _, bk_cap, sp_cap = (int(x) for x in h[2:9])
+    sizes = [("V", 8 * n_slots), ("m", 8 * n_hh), ("h", 8 * n_hh), ("n", 8 * n_hh), ("g", 8 * n_syn),
+             ("xcur", 8 * n_packs), ("bk_off", 4 * n_packs * (K + 1)), ("bk_nxt", 4 * n_packs * (K + 1)),
+             ("bk_q", 4 * n_packs * bk_cap), ("bk_w", 8 * n_packs * bk_cap), ("ctr", 16),
+             ("sp_gid", 4 * sp_cap), ("sp_step", 8 * sp_cap), ("sp_t", 8 * sp_cap)]
+    off, at = {}, 80
+    for name, n in sizes:
+        off[name] = at
+        at += n
+    n_hist = (len(blob) - at) // (4 + 12 * sp_cap)
+    assert at + n_hist * (4 + 12 * sp_cap) == len(blob)
+    off["hist_cnt"] = at
+    off["hist_gid"] = at + 4 * n_hist
+    return off, bk_cap, sp_cap
+
+
+def test_state_restore_rejects_out_of_range_indices():
+    """A state blob whose indexing values lie outside the model is refused
+    on the host before any of it reaches the device: the step, an event
+    cursor, a buffered spike's gid, a bucket offset, a bucket event's
+    synapse, a history count.  The unmodified blob still restores."""
+    from paper_1901_07454_amd import arbmi
+    m = models.mixed_pull_chunks(n_steps=2400)
+    sim = _sim(m, coef_mode=3, block_threads=64)
+    sim.step(1000)  # mid epoch 1: the buckets hold events, the history spikes
+    blob = np.array(sim.get_state(), copy=True)
+    off, bk_cap, sp_cap = _state_offsets(blob, sim.info["epoch_steps"])
+    n_cells = len(m["cell_n_branch"])
+
+    def put(b, at, value, dt):
+        b[at:at + np.dtype(dt).itemsize] = np.frombuffer(np.array([value], dt).tobytes(), np.uint8)
+
+    cases = [(8, -1, np.int64, "step"),
+             (off["xcur"], -1, np.int64, "event cursor"),
+             (off["sp_gid"], n_cells, np.uint32, "spike gid"),
+             (off["bk_off"], bk_cap + 1, np.uint32, "bucket offsets"),
+             (off["hist_cnt"], sp_cap + 1, np.uint32, "history count")]
+    # a bucket event's synapse: the first pack whose bucket holds events
+    K = sim.info["epoch_steps"]
+    ends = [int(np.frombuffer(bytes(blob[off["bk_off"] + 4 * (p * (K + 1) + K):][:4]), np.uint32)[0])
+            for p in range(sim.info["n_packs"])]
+    p = next(i for i, e in enumerate(ends) if e > 0)
+    cases.append((off["bk_q"] + 4 * p * bk_cap, 1 << 30, np.uint32, "event synapse"))
+    for at, value, dt, what in cases:
+        bad = blob.copy()
+        put(bad, at, value, dt)
+        with pytest.raises(arbmi.ArbError) as e:
+            sim.set_state(bad)
+        assert e.value.code == arbmi.ARB_EINVAL and what in str(e.value), (what, str(e.value))
+    sim.set_state(blob)
+    assert np.array_equal(np.asarray(sim.get_state()), blob)
+    sim.close()
+
+
 @pytest.mark.parametrize("block", [0, 64, 256])
 def test_ten_thousand_way_network_small(block):
     """The 10k-connectivity model's cells and wiring (every synapse from a
