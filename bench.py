@@ -111,34 +111,73 @@ def _oracle_chunk(args):
     return int(gen.n_cvs(m).sum()) * steps, dt
 
 
-def cpu_baseline(cfg: int, budget_s: float = 20.0):
-    """The CPU oracle as it stands (single-threaded C), run as independent
-    processes on disjoint cell chunks of the same workload; the rate is the
-    sum over processes of CV-updates / stepping time."""
+def host_cpu():
+    """Host cores this process may use, the machine's count and the CPU model."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return usable, os.cpu_count() or 1, model
+
+
+# Host cores one GPU's share of the box provides: the CPU oracle's process
+# pool never exceeds it.
+HOST_CORES_PER_GPU = 16
+
+# The oracle's workload per configuration: (cells, steps) of the parallel leg
+# (the whole model where its rate allows a run of about 10-30 s) and of the
+# single-thread leg.
+CPU_LEGS = {1: ((1, 4000), (1, 4000)), 2: ((8192, 4000), (64, 4000)), 3: ((4096, 8000), (16, 8000)),
+            4: ((256, 2000), (64, 2000)), 5: ((65536, 800), (16, 800)), 6: ((8192, 800), (16, 800)),
+            7: ((8192, 800), (16, 800))}
+CPU_BASE_CELLS = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536, 6: 8192, 7: 8192}
+
+
+def cpu_baseline(cfg: int):
+    """The CPU oracle as it stands (single-threaded C, built -O2 without
+    fast-math), timed twice on the same workload as the GPU: on every usable
+    host core (up to one GPU's share), as independent processes over disjoint
+    contiguous chunks of the cells, and on one core.  Only the stepping loop
+    is timed; the rate is CV-updates / stepping time (summed over processes
+    for the parallel leg)."""
     import multiprocessing as mp
 
     import oracle
     oracle.build() if not os.path.exists(oracle.LIB) else None
-    workers = max(1, min(16, os.cpu_count() or 1))
-    per = {1: (1, 4000), 2: (96, 1000), 3: (24, 800), 4: (64, 2000), 5: (48, 1200), 6: (16, 1600),
-           7: (16, 1600)}[cfg]
-    n_cells, steps = per
-    base = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536, 6: 8192, 7: 8192}[cfg]
-    chunks = [(cfg, [(w * n_cells + k) % base for k in range(n_cells)], steps) for w in range(workers)]
+    usable, nproc, model = host_cpu()
+    workers = max(1, min(HOST_CORES_PER_GPU, usable))
+    (n_cells, steps), (n1, steps1) = CPU_LEGS[cfg]
+    base = CPU_BASE_CELLS[cfg]
     if cfg == 1:
         chunks = [(1, [0], steps) for _ in range(workers)]
+    else:
+        per = (n_cells + workers - 1) // workers
+        chunks = [(cfg, list(range(w * per, min(n_cells, (w + 1) * per))), steps) for w in range(workers)
+                  if w * per < n_cells]
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
-    with ctx.Pool(workers) as pool:
+    with ctx.Pool(len(chunks)) as pool:
         res = pool.map(_oracle_chunk, chunks)
     wall = time.perf_counter() - t0
     rate = sum(u / t for u, t in res)
     cpu_s = sum(t for _, t in res)
-    return {"value": rate, "unit": "CV-updates/s", "cores": workers, "kind": "oracle",
-            "sample": (f"{workers} processes x {n_cells} cells x {steps} steps of the same workload "
-                       f"({'ring segments' if cfg in (2, 6) else 'cell chunks'}"
-                       f"{', connections inside a chunk only' if cfg in (5, 7) else ''}), stepping time only; "
-                       f"{cpu_s:.1f} s CPU, {wall:.1f} s wall")}
+    u1, t1 = _oracle_chunk((cfg, list(range(min(n1, base))), steps1))
+    whole = "the whole model" if n_cells >= base else f"cells 0-{n_cells - 1} of {base}"
+    return {"value": rate, "unit": "CV-updates/s", "cores": len(chunks), "kind": "oracle",
+            "single_thread": {"value": u1 / t1, "unit": "CV-updates/s", "cells": min(n1, base), "steps": steps1},
+            "nproc": nproc, "usable_cores": usable, "cpu_model": model,
+            "sample": (f"{whole} x {steps} steps, split into {len(chunks)} contiguous cell chunks run as "
+                       f"independent processes (connections between chunks dropped), stepping time only; "
+                       f"{cpu_s:.1f} s CPU, {wall:.1f} s wall; pool capped at {HOST_CORES_PER_GPU} cores, "
+                       f"one GPU's share of the host")}
 
 
 def kernel_name(info: dict) -> str:
@@ -149,38 +188,43 @@ def kernel_name(info: dict) -> str:
 
 
 def measured_traffic(path: str, cfg: int, kernel: str, steps_per_launch: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on this kernel variant, at this launch length, with the
-    kernel sources unchanged since; else None."""
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary, if it was taken on this kernel variant with the kernel
+    sources unchanged since; else None.  The summary holds a fixed part per
+    launch (loading and storing the packs' state) and a part per step, fitted
+    from launches of two lengths, so any launch length gets a figure."""
     import hashlib
     try:
         rec = json.load(open(path))[f"config{cfg}"]
         h = hashlib.sha256()
         for p in rec["kernel_sources"]:
             h.update(open(os.path.join(ROOT, p), "rb").read())
-        if (h.hexdigest() == rec["kernel_sha256"] and rec["kernel"] == kernel
-                and abs(rec["steps_per_launch"] - steps_per_launch) < 1e-9):
-            return rec["bytes_per_launch"]
+        if h.hexdigest() != rec["kernel_sha256"] or rec["kernel"] != kernel:
+            return None
+        return rec["fixed_bytes_per_launch"] + rec["bytes_per_step"] * steps_per_launch
     except Exception:
-        pass
-    return None
+        return None
 
 
 def grad_ratio(torch, reps: int = 3):
-    """Config 4: time of forward+adjoint gradient over time of the plain
-    forward, same sim, same GPU (2000 steps, checkpoints every 100)."""
-    from paper_1901_07454_amd import grad
+    """Config 4: wall time of the forward+adjoint gradient (2000 steps,
+    checkpoints every 100, through the autograd wrapper) over the wall time
+    of the plain forward of the same model on the same GPU, built as the
+    plain benchmark builds it (autotuned launch shape, no gradient flag)."""
+    from paper_1901_07454_amd import arbmi, grad
     from workloads import gen
     n_steps, k = 2000, 100
     m0 = gen.config4(n_steps=n_steps)
-    gs = grad.GradSim(m0)
+    plain = arbmi.Simulation(m0, flags=arbmi.ARB_FLAG_AUTOTUNE)
+    plain_state0 = plain.get_state()
+    gs = grad.GradSim(m0, flags=arbmi.ARB_FLAG_AUTOTUNE)
     theta = torch.tensor(gen.config4_theta(m0), dtype=torch.float64, device="cuda", requires_grad=True)
     target = torch.zeros(gs.n_cells, n_steps, dtype=torch.float64, device="cuda")
 
     def fwd():
-        gs.sim.set_state(gs.state0)
-        gs.sim.step(n_steps)
-        gs.sim.sync()
+        plain.set_state(plain_state0)
+        plain.step(n_steps)
+        plain.sync()
 
     def fwd_adj():
         th = theta.detach().clone().requires_grad_(True)
@@ -201,10 +245,14 @@ def grad_ratio(torch, reps: int = 3):
         t0 = time.perf_counter()
         fwd_adj()
         t_fa.append(time.perf_counter() - t0)
+    kp, kg = kernel_name(plain.info), kernel_name(gs.sim.info)
     gs.close()
+    plain.close()
     f, fa = min(t_f), min(t_fa)
     return {"workload": "config 4: 256 cells x 200 CVs, hh+pas, 2000 steps, checkpoint every 100",
-            "fwd_ms": f * 1e3, "fwd_adj_ms": fa * 1e3, "ratio": fa / f, "target_ratio": 4.0}
+            "fwd_ms": f * 1e3, "fwd_adj_ms": fa * 1e3, "ratio": fa / f, "target_ratio": 4.0,
+            "fwd_kernel": kp, "grad_sim_kernel": kg,
+            "note": "fwd: the plain benchmark's sim (autotuned, no gradient flag); fwd_adj: the gradient sim"}
 
 
 def main():
@@ -217,6 +265,7 @@ def main():
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--coef-mode", type=int, default=0)
     ap.add_argument("--cells-per-pack", type=int, default=0)
+    ap.add_argument("--epoch-steps", type=int, default=0, help="0 = the minimum delay (or 1000 without a network)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.txt"))
@@ -238,68 +287,95 @@ def main():
     flags = arbmi.ARB_FLAG_TIME_KERNELS
     if not (args.block_threads or args.coef_mode or args.cells_per_pack):
         flags |= arbmi.ARB_FLAG_AUTOTUNE
-    sim = arbmi.Simulation(m, flags=flags, block_threads=args.block_threads,
+    sim = arbmi.Simulation(m, flags=flags, block_threads=args.block_threads, epoch_steps=args.epoch_steps,
                            coef_mode=args.coef_mode, cells_per_pack=args.cells_per_pack)
     info = sim.info
     log(f"sim built in {time.perf_counter() - t0:.1f} s: {info}")
     n_cv = info["n_cv"]
 
-    sim.step(args.warmup)
+    # whole epochs only, so that every timed step pays its share of the
+    # spike exchange (index, pull and collect run once per epoch), after at
+    # least one warm-up epoch
+    K = info["epoch_steps"]
+    warmup = max(1, -(-args.warmup // K)) * K
+    steps = max(1, -(-args.steps // K)) * K
+    sim.step(warmup)
     sim.sync()
     sim.kernel_time()  # discard warm-up launches
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(args.steps)
+    sim.step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kms, nlaunch = sim.kernel_time()
     sim.sync()
     spikes = sim.spikes()
-    log(f"timed {args.steps} steps in {wall:.4f} s, {nlaunch} step-kernel launches, {kms:.2f} ms in them, "
+    log(f"timed {steps} steps in {wall:.4f} s, {nlaunch} step-kernel launches, {kms:.2f} ms in them, "
         f"{len(spikes)} spikes")
 
-    value = n_cv * args.steps / wall
-    steps_per_launch = args.steps / max(nlaunch, 1)
+    value = n_cv * steps / wall
+    steps_per_launch = steps / max(nlaunch, 1)
     avg_launch_s = kms / 1e3 / max(nlaunch, 1)
-    bytes_per_launch = info["bytes_per_step"] * steps_per_launch
-    achieved = bytes_per_launch / avg_launch_s / 1e9
     flops_per_step = FLOPS_PER_CV * n_cv + FLOPS_PER_HH * info["n_hh"] + FLOPS_PER_SYN * info["n_syn"]
     tflops = flops_per_step * steps_per_launch / avg_launch_s / 1e12
+    model_gbps = info["bytes_per_step"] * steps_per_launch / avg_launch_s / 1e9
     kernel = kernel_name(info)
     traffic = measured_traffic(args.traffic_json, args.config, kernel, steps_per_launch)
+    traffic_gbps = None if traffic is None else traffic / avg_launch_s / 1e9
     copy_gbps = copy_bandwidth_gbps(torch)
+    # The bound: the resource the kernel comes closest to.  The fused kernel
+    # keeps voltages, states and coefficients on chip for a whole epoch, so on
+    # the CV-dominated workloads its measured HBM traffic is a small fraction
+    # of the peak and FP64 issue is the nearer roofline (the kernel itself is
+    # bound by the latency of the solve's dependency chains); synapse-heavy
+    # workloads stream their synapse state and sit on HBM.
+    alu_frac = tflops / FP64_PEAK_TFLOPS
+    hbm_frac = None if traffic_gbps is None else traffic_gbps / HBM_PEAK_GBPS
+    if hbm_frac is not None and hbm_frac > alu_frac:
+        roof = {"bound": "hbm", "achieved": traffic_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": hbm_frac, "traffic": traffic,
+                "basis": "measured FETCH_SIZE + WRITE_SIZE bytes per launch / average launch time"}
+    else:
+        roof = {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": alu_frac, "traffic": traffic,
+                "basis": ("algorithmic FP64 operations per launch (7 per CV, 61 per hh instance, 4 per "
+                          "synapse, per step) / average launch time; peak = MI355X vector FP64")}
+    roof.update({
+        "kernel": kernel, "steps_per_launch": steps_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
+        "launches": nlaunch, "kernel_ms_total": kms,
+        "traffic_GBps": traffic_gbps, "traffic_frac_of_hbm_peak": hbm_frac,
+        "fp64": {"achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": alu_frac,
+                 "flops_per_step": flops_per_step},
+        "byte_model": {"bytes_per_step": info["bytes_per_step"], "GBps": model_gbps,
+                       "ratio_to_hbm_peak": model_gbps / HBM_PEAK_GBPS,
+                       "note": ("per-step SoA byte model (44 B/CV, 56 B/hh, 20 B/synapse) over the launch time; "
+                                "not a roofline fraction: one launch keeps the state on chip for a whole "
+                                "epoch, so it moves far fewer bytes than the model counts")},
+        "measured_copy_GBps": copy_gbps,
+    })
     out = {
         "metric": "CV-updates/s per GPU (fwd FP64)",
         "value": value,
         "unit": "CV-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "ms_per_step": wall * 1e3 / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"config {args.config}: {desc}", "cells": info["n_cells"], "cvs": n_cv,
-                   "dt_ms": float(m["dt"]), "epoch_steps": info["epoch_steps"],
+                   "dt_ms": float(m["dt"]), "epoch_steps": K,
                    "block_threads": info["block_threads"], "coef_mode": info["coef_mode"],
                    "packs": info["n_packs"], "lds_bytes": info["lds_bytes"], "spikes": int(len(spikes))},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "traffic_GBps": None if traffic is None else traffic / avg_launch_s / 1e9,
-                     "kernel": kernel, "bytes_per_step": info["bytes_per_step"],
-                     "steps_per_launch": steps_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
-                     "measured_copy_GBps": copy_gbps, "frac_of_measured_copy": achieved / copy_gbps,
-                     "note": ("achieved = per-step algorithmic bytes x steps per launch / launch time; one "
-                              "launch runs a whole epoch with voltages, states and coefficients held in "
-                              "LDS and registers, so it moves far fewer bytes than the per-step model "
-                              "(see traffic) and the model's rate can be exceeded"),
-                     "alu": {"achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                             "frac": tflops / FP64_PEAK_TFLOPS, "flops_per_step": flops_per_step}},
+        "roofline": roof,
     }
     if info["n_syn"] > 0:
-        out["synapse_updates_per_s"] = info["n_syn"] * args.steps / wall
+        out["synapse_updates_per_s"] = info["n_syn"] * steps / wall
     sim.close()
     if not args.no_grad:
         out["grad"] = grad_ratio(torch)

@@ -198,34 +198,48 @@ int arb_build_cells(const arb_cell *cells, int32_t n_cells, const arb_branch *br
  * it stays set for the life of the sim. */
 int arb_step(arb_sim s, int64_t n_steps);
 
-/* Copy all n_cv voltages in user CV order into dst (n >= n_cv doubles),
- * a device pointer if dst_on_device, else host. */
+/* Copy all n_cv voltages V_i (the discretised voltages of eq. 2a, one per
+ * control volume) in user CV order into dst (n >= n_cv doubles), a device
+ * pointer if dst_on_device, else host.  The paper validates its models by
+ * comparing the voltage traces of individual cells (Sec. V-A, "Models").
+ * A host dst is staged through a device buffer the sim allocates on the
+ * first such call and keeps until arb_free. */
 int arb_get_voltages(arb_sim s, double *dst, int64_t n, int dst_on_device);
 
 /* Drain the spikes recorded since the last call into host dst, sorted by
- * (step, gid).  *n_out = number written.  ARB_EOVERFLOW if cap was too small
+ * (step, gid).  A spike is an upward crossing of the fixed threshold by the
+ * soma voltage (Sec. II); spike trains are the second output the paper
+ * validates its models by (Sec. V-A, "Models").  *n_out = number written.  ARB_EOVERFLOW if cap was too small
  * (nothing is drained then, *n_out = 0), or if a spike or event buffer has
  * overflowed (the kept spikes are still written and counted in *n_out). */
 int arb_get_spikes(arb_sim s, arb_spike *dst, int64_t cap, int64_t *n_out);
 
 /* Record V of the given user CVs after every step from now on, for up to
- * max_steps steps (replaces earlier probes). */
+ * max_steps steps (the voltage traces of Sec. V-A, "Models").  Replaces
+ * earlier probes; the previous probe table and trace buffer are released. */
 int arb_set_probes(arb_sim s, const int64_t *cv, int32_t n, int64_t max_steps);
 
-/* Copy the recorded trace, layout [probe][step], into dst (n_probe * cap
- * doubles, device or host) and restart recording.  *n_steps_out = steps
+/* Copy the recorded voltage trace (Sec. V-A, "Models"), layout
+ * [probe][step], into dst (n_probe * cap doubles, device or host) and
+ * restart recording.  *n_steps_out = steps
  * recorded. */
 int arb_get_trace(arb_sim s, double *dst, int64_t cap, int dst_on_device, int64_t *n_steps_out);
 
 /* Replace per-region channel densities theta[cell][region][3] =
  * (gbar_na, gbar_k, g_pas), region 0 = soma, 1 + b = branch b (host array of
- * n = 3 * (n_cells + n_branches) doubles).  Takes effect at the next step. */
+ * n = 3 * (n_cells + n_branches) doubles).  These are the areal conductances
+ * g_k of the channel terms S_i g_k (V_i - e_k) in eq. 2a.  Takes effect at
+ * the next step. */
 int arb_set_params(arb_sim s, const double *theta, int64_t n);
 
-/* Gradient support (discrete adjoint of the step).  Forward: run n_steps
+/* Gradient support (discrete adjoint of the step).  An addition beyond the
+ * paper, which computes no gradients: the adjoint differentiates exactly the
+ * operator-split implicit-Euler step of Sec. II.  Forward: run n_steps
  * recording the soma voltage of every cell after each step into trace_dev
  * (device, [cell][step]), storing a state checkpoint every ckpt_every
- * steps; input events are recorded and treated as fixed in the backward. */
+ * steps; input events are recorded and treated as fixed in the backward.
+ * Probes set with arb_set_probes are suspended for these steps and resume
+ * afterwards, their recording restarted at the step the forward ends at. */
 int arb_grad_forward(arb_sim s, int64_t n_steps, int32_t ckpt_every, double *trace_dev);
 
 /* Backward: given dL/dtrace (device, [cell][step]), write dL/dtheta (device,
@@ -233,7 +247,8 @@ int arb_grad_forward(arb_sim s, int64_t n_steps, int32_t ckpt_every, double *tra
  * arb_grad_forward.  Leaves the sim's state at the end of the forward. */
 int arb_grad_backward(arb_sim s, const double *dL_dtrace_dev, double *dL_dtheta_dev);
 
-/* Checkpoint: serialise / restore the dynamic state (step, V, gates,
+/* Checkpoint: serialise / restore the dynamic state (an addition beyond the
+ * paper, which describes no checkpointing: step, V, gates,
  * synaptic conductances, pending events, event cursors, spike buffer and
  * history).  With blob NULL, arb_get_state writes only the size into *n_out.
  * arb_set_state takes a blob of the same model (ARB_EINVAL otherwise, or if

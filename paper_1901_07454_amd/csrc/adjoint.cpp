@@ -188,6 +188,28 @@ int grad_forward(Sim* s, int64_t n_steps, int32_t ckpt_every, double* trace_dev)
     if (rc != ARB_OK) return rc;
     GradState& G = *s->grad;
     Lowered& L = s->L;
+    // the caller's probes (arb_set_probes) are suspended during the forward
+    // and resume afterwards, recording from the step the forward ends at
+    std::vector<std::pair<int32_t, int32_t>> user_pr(L.packs.size());
+    for (size_t k = 0; k < L.packs.size(); ++k) user_pr[k] = {L.packs[k].pr0, L.packs[k].npr};
+    int32_t* const user_slot = s->d_pr_slot;
+    int32_t* const user_id = s->d_pr_id;
+    double* const user_trace = s->d_trace;
+    const int64_t user_np = s->n_probe, user_cap = s->trace_cap;
+    auto restore_probes = [&]() -> int {
+        for (size_t k = 0; k < L.packs.size(); ++k) {
+            L.packs[k].pr0 = user_pr[k].first;
+            L.packs[k].npr = user_pr[k].second;
+        }
+        s->d_pr_slot = user_slot;
+        s->d_pr_id = user_id;
+        s->d_trace = user_trace;
+        s->n_probe = user_np;
+        s->trace_cap = user_cap;
+        s->trace_step0 = s->step;
+        s->graph_dirty = true;
+        return s->upload(s->d_pk, L.packs.data(), L.packs.size() * sizeof(PackDesc));
+    };
     // probes: the soma of every cell, written straight into the caller's trace
     {
         int32_t at = 0;
@@ -196,7 +218,10 @@ int grad_forward(Sim* s, int64_t n_steps, int32_t ckpt_every, double* trace_dev)
             D.npr = D.ncell;
             at += D.ncell;
         }
-        if ((rc = s->upload(s->d_pk, L.packs.data(), L.packs.size() * sizeof(PackDesc))) != ARB_OK) return rc;
+        if ((rc = s->upload(s->d_pk, L.packs.data(), L.packs.size() * sizeof(PackDesc))) != ARB_OK) {
+            (void)restore_probes();
+            return rc;
+        }
         s->d_pr_slot = G.pr_slot;
         s->d_pr_id = G.pr_id;
         s->d_trace = trace_dev;
@@ -206,18 +231,21 @@ int grad_forward(Sim* s, int64_t n_steps, int32_t ckpt_every, double* trace_dev)
         s->graph_dirty = true;
     }
     G.step_begin = s->step;
-    for (int64_t j = 0; j < G.n_seg; ++j) {
-        if ((rc = save_state(s, G.ckpt[j])) != ARB_OK) return rc;
+    for (int64_t j = 0; j < G.n_seg && rc == ARB_OK; ++j) {
+        if ((rc = save_state(s, G.ckpt[j])) != ARB_OK) break;
         const int64_t len = std::min(G.k, n_steps - j * G.k);
-        if ((rc = s->advance(len, nullptr)) != ARB_OK) return rc;
+        rc = s->advance(len, nullptr);
     }
-    if ((rc = save_state(s, G.ckpt[G.n_seg])) != ARB_OK) return rc;
+    if (rc == ARB_OK) rc = save_state(s, G.ckpt[G.n_seg]);
+    if (rc == ARB_OK) {
+        const hipError_t e = hipStreamSynchronize(s->st);
+        if (e != hipSuccess) rc = set_hip_error(e, "hipStreamSynchronize");
+    }
+    // the gradient trace (the caller's buffer) is not written again
+    const int rc2 = restore_probes();
+    if (rc != ARB_OK) return rc;
+    if (rc2 != ARB_OK) return rc2;
     HIP_TRY(hipStreamSynchronize(s->st));
-    // the caller's trace stays valid; later steps must not write into it
-    s->d_trace = nullptr;
-    s->n_probe = 0;
-    s->trace_cap = 0;
-    s->graph_dirty = true;
     G.ready = true;
     s->grad_valid = true;
     return ARB_OK;

@@ -52,9 +52,25 @@ void* Sim::raw_alloc(size_t bytes) {
     }
     if (ptr) {
         allocs.push_back(ptr);
+        alloc_bytes.push_back(int64_t(bytes));
         device_bytes += int64_t(bytes);
     }
     return ptr;
+}
+
+void Sim::release(void* ptr) {
+    if (!ptr) return;
+    for (size_t k = 0; k < allocs.size(); ++k)
+        if (allocs[k] == ptr) {
+            if (p.free)
+                p.free(ptr, p.alloc_ctx);
+            else
+                (void)hipFree(ptr);
+            device_bytes -= alloc_bytes[k];
+            allocs.erase(allocs.begin() + int64_t(k));
+            alloc_bytes.erase(alloc_bytes.begin() + int64_t(k));
+            return;
+        }
 }
 
 void Sim::release_all() {
@@ -65,6 +81,7 @@ void Sim::release_all() {
             (void)hipFree(q);
     }
     allocs.clear();
+    alloc_bytes.clear();
     device_bytes = 0;
 }
 
@@ -865,12 +882,32 @@ int arb_set_probes(arb_sim s_, const int64_t* cv, int32_t n, int64_t max_steps) 
         }
     }
     HIP_TRY(hipStreamSynchronize(s->st));
+    // the previous probe table and trace are no longer read by any kernel
+    s->release(s->own_pr_slot);
+    s->release(s->own_pr_id);
+    s->release(s->own_trace);
+    s->own_pr_slot = s->own_pr_id = nullptr;
+    s->own_trace = nullptr;
+    s->d_pr_slot = s->d_pr_id = nullptr;
+    s->d_trace = nullptr;
+    s->n_probe = 0;
+    s->trace_cap = 0;
     int rc = ARB_OK;
-    s->d_pr_slot = dupload(s, ps, rc);
-    s->d_pr_id = dupload(s, pid, rc);
+    s->d_pr_slot = s->own_pr_slot = dupload(s, ps, rc);
+    s->d_pr_id = s->own_pr_id = dupload(s, pid, rc);
     if (rc == ARB_OK) rc = s->upload(s->d_pk, L.packs.data(), L.packs.size() * sizeof(PackDesc));
-    s->d_trace = (n > 0 && max_steps > 0) ? dalloc<double>(s, size_t(n) * size_t(max_steps), rc) : nullptr;
-    if (rc != ARB_OK) return rc;
+    s->d_trace = s->own_trace =
+        (n > 0 && max_steps > 0) ? dalloc<double>(s, size_t(n) * size_t(max_steps), rc) : nullptr;
+    if (rc != ARB_OK) {
+        // no probes rather than a half-made table
+        for (PackDesc& D : L.packs) D.npr = 0;
+        (void)s->upload(s->d_pk, L.packs.data(), L.packs.size() * sizeof(PackDesc));
+        s->d_trace = nullptr;
+        s->n_probe = 0;
+        s->trace_cap = 0;
+        s->graph_dirty = true;
+        return rc;
+    }
     s->n_probe = n;
     s->trace_cap = (n > 0) ? max_steps : 0;
     s->trace_step0 = s->step;

@@ -59,6 +59,7 @@ struct Sim : arb_sim_ {
     std::vector<int64_t> xcur0;
 
     std::vector<void*> allocs;
+    std::vector<int64_t> alloc_bytes;
     int64_t device_bytes = 0;
     std::vector<hipEvent_t> timer_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_pending;
@@ -107,6 +108,9 @@ struct Sim : arb_sim_ {
     // probes
     int32_t *d_pr_slot = nullptr, *d_pr_id = nullptr;
     double* d_trace = nullptr;
+    // the buffers arb_set_probes allocated (released when probes are replaced)
+    int32_t *own_pr_slot = nullptr, *own_pr_id = nullptr;
+    double* own_trace = nullptr;
     int64_t n_probe = 0, trace_cap = 0, trace_step0 = 0;
     // graph replay of whole epochs (ARB_FLAG_GRAPH)
     int64_t* d_epoch = nullptr;
@@ -119,6 +123,7 @@ struct Sim : arb_sim_ {
     bool grad_valid = false;
 
     void* raw_alloc(size_t bytes);
+    void release(void* ptr);  // frees one allocation of raw_alloc (no-op for others)
     void release_all();
     int upload(void* dst, const void* src, size_t bytes);
     int fill_zero(void* dst, size_t bytes);
