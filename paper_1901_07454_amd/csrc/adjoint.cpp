@@ -18,7 +18,11 @@ struct GradState {
     int64_t n_steps = 0, k = 0, step_begin = 0, n_seg = 0;
     std::vector<char*> ckpt;  // state copies at segment starts, plus the end state
     int64_t state_bytes = 0;
-    double *rec_V = nullptr, *rec_m = nullptr, *rec_h = nullptr, *rec_n = nullptr, *rec_g = nullptr;
+    // two sets of segment records: the recompute of segment j - 1 fills one
+    // (on the auxiliary stream) while the adjoint of segment j reads the other
+    double *rec_V[2] = {}, *rec_m[2] = {}, *rec_h[2] = {}, *rec_n[2] = {}, *rec_g[2] = {};
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_rec[2] = {}, ev_adj[2] = {}, ev_join = nullptr;
     double *lamV = nullptr, *lamM = nullptr, *lamH = nullptr, *lamN = nullptr;
     double *accP1 = nullptr, *accP0 = nullptr, *accNa = nullptr, *accK = nullptr;
     int64_t *rp_off = nullptr, *rp_slot = nullptr, *rp_hh = nullptr;
@@ -26,6 +30,7 @@ struct GradState {
     uint32_t* reg_mech = nullptr;
     int32_t *pr_slot = nullptr, *pr_id = nullptr;
     int adj_lds = 0;
+    bool reg = false;  // register-resident adjoint (the sim's layout is the register one)
     bool ready = false;
 };
 
@@ -58,23 +63,29 @@ std::vector<Part> state_parts(Sim* s) {
             {s->d_hist_step, int64_t(s->n_hist) * s->hist_cap * 8}};
 }
 
-int save_state(Sim* s, char* dst) {
+// The dynamic state into (save) or out of (load) a checkpoint, in one
+// launch on stream st.
+int copy_state(Sim* s, char* ckpt, bool save, hipStream_t st) {
+    CopyList c{};
     int64_t at = 0;
     for (const Part& q : state_parts(s)) {
-        if (q.bytes) HIP_TRY(hipMemcpyAsync(dst + at, q.d, size_t(q.bytes), hipMemcpyDeviceToDevice, s->st));
+        if (q.bytes) {
+            if (c.n == kCopyParts) return set_error(ARB_EINVAL, "internal: too many state parts");
+            uint32_t* dev = static_cast<uint32_t*>(q.d);
+            uint32_t* cp = reinterpret_cast<uint32_t*>(ckpt + at);
+            c.src[c.n] = save ? dev : cp;
+            c.dst[c.n] = save ? cp : dev;
+            c.words[c.n] = q.bytes / 4;
+            ++c.n;
+        }
         at += (q.bytes + 255) & ~int64_t(255);
     }
+    HIP_TRY(launch_copy_parts(c, st));
     return ARB_OK;
 }
 
-int load_state(Sim* s, const char* src) {
-    int64_t at = 0;
-    for (const Part& q : state_parts(s)) {
-        if (q.bytes) HIP_TRY(hipMemcpyAsync(q.d, src + at, size_t(q.bytes), hipMemcpyDeviceToDevice, s->st));
-        at += (q.bytes + 255) & ~int64_t(255);
-    }
-    return ARB_OK;
-}
+int save_state(Sim* s, char* dst) { return copy_state(s, dst, true, s->st); }
+int load_state(Sim* s, const char* src, hipStream_t st) { return copy_state(s, const_cast<char*>(src), false, st); }
 
 template <class T>
 T* galloc(Sim* s, size_t n, int& rc) {
@@ -95,12 +106,17 @@ int setup(Sim* s, int64_t n, int64_t k) {
     if (G.state_bytes == 0) {
         for (const Part& q : state_parts(s)) G.state_bytes += (q.bytes + 255) & ~int64_t(255);
         // adjoint LDS must fit
+        G.reg = s->cfg.coef_mode == 3;
+        if (G.reg && !s->cfg.rec)
+            return set_error(ARB_ESTATE, "gradients of a register-layout sim need ARB_FLAG_GRADIENTS at build");
         int64_t lds = 0;
-        for (const PackDesc& D : L.packs) lds = std::max(lds, adjoint_lds_bytes(D));
+        for (const PackDesc& D : L.packs) lds = std::max(lds, G.reg ? reg_adjoint_lds_bytes(D) : adjoint_lds_bytes(D));
         if (lds > s->lds_max - 256)
             return set_error(ARB_EINVAL, "packs too large for the adjoint kernel: build with ARB_FLAG_GRADIENTS");
         G.adj_lds = int(std::max<int64_t>(lds, 8));
-        if (prepare_adjoint_kernels(int(s->lds_max)) != hipSuccess) return set_error(ARB_EHIP, "adjoint kernels");
+        const hipError_t pe =
+            G.reg ? prepare_reg_adjoint_kernels(int(s->lds_max)) : prepare_adjoint_kernels(int(s->lds_max));
+        if (pe != hipSuccess) return set_error(ARB_EHIP, "adjoint kernels");
         G.lamV = galloc<double>(s, L.n_slots, rc);
         G.accP1 = galloc<double>(s, L.n_slots, rc);
         G.accP0 = galloc<double>(s, L.n_slots, rc);
@@ -158,13 +174,27 @@ int setup(Sim* s, int64_t n, int64_t k) {
         if ((rc = s->upload(G.pr_slot, ps.data(), ps.size() * 4)) != ARB_OK) return rc;
         if ((rc = s->upload(G.pr_id, pid.data(), pid.size() * 4)) != ARB_OK) return rc;
     }
+    if (!G.aux) {
+        HIP_TRY(hipStreamCreateWithFlags(&G.aux, hipStreamNonBlocking));
+        for (int b = 0; b < 2; ++b) {
+            HIP_TRY(hipEventCreateWithFlags(&G.ev_rec[b], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&G.ev_adj[b], hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventCreateWithFlags(&G.ev_join, hipEventDisableTiming));
+    }
     if (G.k != k) {
-        G.rec_V = galloc<double>(s, size_t(k + 1) * L.n_slots, rc);
-        G.rec_m = galloc<double>(s, size_t(k) * nhh, rc);
-        G.rec_h = galloc<double>(s, size_t(k) * nhh, rc);
-        G.rec_n = galloc<double>(s, size_t(k) * nhh, rc);
-        G.rec_g = galloc<double>(s, size_t(k) * nsyn, rc);
-        if (rc != ARB_OK) return rc;
+        for (int b = 0; b < 2; ++b) {
+            for (double* q : {G.rec_V[b], G.rec_m[b], G.rec_h[b], G.rec_n[b], G.rec_g[b]}) s->release(q);
+            G.rec_V[b] = galloc<double>(s, size_t(k + 1) * L.n_slots, rc);
+            G.rec_m[b] = galloc<double>(s, size_t(k) * nhh, rc);
+            G.rec_h[b] = galloc<double>(s, size_t(k) * nhh, rc);
+            G.rec_n[b] = galloc<double>(s, size_t(k) * nhh, rc);
+            G.rec_g[b] = galloc<double>(s, size_t(k) * nsyn, rc);
+        }
+        if (rc != ARB_OK) {
+            G.k = 0;
+            return rc;
+        }
         G.k = k;
     }
     while (int64_t(G.ckpt.size()) < n_seg + 1) {
@@ -259,17 +289,44 @@ int grad_backward(Sim* s, const double* dL_dtrace_dev, double* dL_dtheta_dev) {
     const Lowered& L = s->L;
     const int64_t nhh = int64_t(L.hh_cv.size());
     const int64_t saved_step = s->step;
-    for (double* p : {G.lamV, G.accP1, G.accP0}) HIP_TRY(hipMemsetAsync(p, 0, size_t(L.n_slots) * 8, s->st));
+    hipStream_t const main = s->st;
+    for (double* p : {G.lamV, G.accP1, G.accP0}) HIP_TRY(hipMemsetAsync(p, 0, size_t(L.n_slots) * 8, main));
     for (double* p : {G.lamM, G.lamH, G.lamN, G.accNa, G.accK})
-        if (nhh) HIP_TRY(hipMemsetAsync(p, 0, size_t(nhh) * 8, s->st));
-    int rc = ARB_OK;
-    for (int64_t j = G.n_seg - 1; j >= 0; --j) {
+        if (nhh) HIP_TRY(hipMemsetAsync(p, 0, size_t(nhh) * 8, main));
+    // Segments from the last: the recompute of segment j (auxiliary stream)
+    // restores its checkpoint and records every step into record set j % 2;
+    // the adjoint of segment j (the sim's stream) waits for it and runs
+    // backwards over it, while the recompute of segment j - 1 fills the
+    // other set once the adjoint of segment j + 1 has finished reading it.
+    // The adjoint reads only the records and the step-invariant
+    // coefficients, so the recompute may change the sim's state meanwhile.
+    HIP_TRY(hipEventRecord(G.ev_join, main));
+    HIP_TRY(hipStreamWaitEvent(G.aux, G.ev_join, 0));
+    auto recompute = [&](int64_t j) -> int {
+        const int b = int(j & 1);
+        s->st = G.aux;
+        int rc = load_state(s, G.ckpt[j], G.aux);
+        if (rc == ARB_OK) {
+            s->step = G.step_begin + j * G.k;
+            RecordArgs rec{G.rec_V[b], G.rec_m[b], G.rec_h[b], G.rec_n[b], G.rec_g[b]};
+            rc = s->advance(std::min(G.k, G.n_steps - j * G.k), &rec);
+        }
+        s->st = main;
+        if (rc != ARB_OK) return rc;
+        HIP_TRY(hipEventRecord(G.ev_rec[b], G.aux));
+        return ARB_OK;
+    };
+    auto join_aux = [&]() -> int {  // the sim's stream waits for the auxiliary one
+        HIP_TRY(hipEventRecord(G.ev_join, G.aux));
+        HIP_TRY(hipStreamWaitEvent(main, G.ev_join, 0));
+        return ARB_OK;
+    };
+    int rc = recompute(G.n_seg - 1);
+    for (int64_t j = G.n_seg - 1; j >= 0 && rc == ARB_OK; --j) {
+        const int b = int(j & 1);
         const int64_t begin = G.step_begin + j * G.k;
         const int64_t len = std::min(G.k, G.n_steps - j * G.k);
-        if ((rc = load_state(s, G.ckpt[j])) != ARB_OK) return rc;
-        s->step = begin;
-        RecordArgs rec{G.rec_V, G.rec_m, G.rec_h, G.rec_n, G.rec_g};
-        if ((rc = s->advance(len, &rec)) != ARB_OK) return rc;
+        HIP_TRY(hipStreamWaitEvent(main, G.ev_rec[b], 0));
         AdjArgs a{};
         a.pk = s->d_pk;
         a.rd = s->d_rd;
@@ -283,11 +340,11 @@ int grad_backward(Sim* s, const double* dL_dtrace_dev, double* dL_dtheta_dev) {
         a.invd = s->d_invd;
         a.hh_gna = s->d_hh_gna;
         a.hh_gk = s->d_hh_gk;
-        a.rec_V = G.rec_V;
-        a.rec_m = G.rec_m;
-        a.rec_h = G.rec_h;
-        a.rec_n = G.rec_n;
-        a.rec_g = G.rec_g;
+        a.rec_V = G.rec_V[b];
+        a.rec_m = G.rec_m[b];
+        a.rec_h = G.rec_h[b];
+        a.rec_n = G.rec_n[b];
+        a.rec_g = G.rec_g[b];
         a.n_slots_total = L.n_slots;
         a.n_hh_total = nhh;
         a.n_syn_total = int64_t(L.syn_global.size());
@@ -305,9 +362,21 @@ int grad_backward(Sim* s, const double* dL_dtrace_dev, double* dL_dtheta_dev) {
         a.dt = L.dt;
         a.step0 = begin;
         a.nsteps = int32_t(len);
-        HIP_TRY(launch_adjoint(a, s->cfg.block_threads, G.adj_lds, int(L.packs.size()), s->st));
+        if (G.reg)
+            HIP_TRY(launch_reg_adjoint(s->step_args(), a, s->cfg, G.adj_lds, int(L.packs.size()), main));
+        else
+            HIP_TRY(launch_adjoint(a, s->cfg.block_threads, G.adj_lds, int(L.packs.size()), main));
+        HIP_TRY(hipEventRecord(G.ev_adj[b], main));
+        if (j > 0) {
+            // set (j - 1) % 2 was last read by the adjoint of segment j + 1
+            if (j + 1 < G.n_seg) HIP_TRY(hipStreamWaitEvent(G.aux, G.ev_adj[(j - 1) & 1], 0));
+            rc = recompute(j - 1);
+        }
     }
-    if ((rc = load_state(s, G.ckpt[G.n_seg])) != ARB_OK) return rc;
+    const int rcj = join_aux();
+    if (rc != ARB_OK) return rc;
+    if (rcj != ARB_OK) return rcj;
+    if ((rc = load_state(s, G.ckpt[G.n_seg], main)) != ARB_OK) return rc;
     s->step = saved_step;
     GradReduceArgs r{};
     r.n_reg = int64_t(L.regions.size());
@@ -322,12 +391,22 @@ int grad_backward(Sim* s, const double* dL_dtrace_dev, double* dL_dtheta_dev) {
     r.accNa = G.accNa;
     r.accK = G.accK;
     r.out = dL_dtheta_dev;
-    HIP_TRY(launch_grad_reduce(r, s->st));
-    HIP_TRY(hipStreamSynchronize(s->st));
+    HIP_TRY(launch_grad_reduce(r, main));
+    HIP_TRY(hipStreamSynchronize(main));
     return ARB_OK;
 }
 
 void grad_release(Sim* s) {
+    if (s->grad) {
+        GradState& G = *s->grad;
+        if (G.aux) (void)hipStreamSynchronize(G.aux);
+        for (int b = 0; b < 2; ++b) {
+            if (G.ev_rec[b]) (void)hipEventDestroy(G.ev_rec[b]);
+            if (G.ev_adj[b]) (void)hipEventDestroy(G.ev_adj[b]);
+        }
+        if (G.ev_join) (void)hipEventDestroy(G.ev_join);
+        if (G.aux) (void)hipStreamDestroy(G.aux);
+    }
     delete s->grad;
     s->grad = nullptr;
 }

@@ -17,6 +17,8 @@
 // forward states of the segment were recorded by a recompute pass.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "adjoint_kernels.hpp"
 #include "kernel_common.hpp"
 
@@ -287,6 +289,15 @@ __global__ void grad_reduce_kernel(GradReduceArgs a) {
     a.out[3 * r + 2] = gpas;
 }
 
+__global__ void copy_parts_kernel(CopyList c) {
+    const int q = blockIdx.y;
+    const int64_t n = c.words[q];
+    const uint32_t* src = c.src[q];
+    uint32_t* dst = c.dst[q];
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        dst[i] = src[i];
+}
+
 template <int T>
 hipError_t launch_adj(const AdjArgs& a, int lds, int n_packs, hipStream_t st) {
     hipLaunchKernelGGL((adjoint_kernel<T>), dim3(n_packs), dim3(T), lds, st, a);
@@ -316,6 +327,16 @@ hipError_t launch_adjoint(const AdjArgs& a, int block_threads, int lds_bytes, in
         case 256: return launch_adj<256>(a, lds_bytes, n_packs, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_copy_parts(const CopyList& c, hipStream_t st) {
+    if (c.n <= 0) return hipSuccess;
+    if (c.n > kCopyParts) return hipErrorInvalidValue;
+    int64_t most = 0;
+    for (int q = 0; q < c.n; ++q) most = c.words[q] > most ? c.words[q] : most;
+    const unsigned nb = unsigned(std::min<int64_t>(1024, std::max<int64_t>(1, (most + 255) / 256)));
+    hipLaunchKernelGGL(copy_parts_kernel, dim3(nb, unsigned(c.n)), dim3(256), 0, st, c);
+    return hipGetLastError();
 }
 
 hipError_t launch_grad_reduce(const GradReduceArgs& a, hipStream_t st) {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kernels.hpp"
 #include "layout.hpp"
 
 namespace arbmi {
@@ -60,8 +61,27 @@ struct GradReduceArgs {
     double* out;             // [n_reg][3]
 };
 
+// Up to kCopyParts device-to-device copies of whole 32-bit words in one
+// launch (the dynamic state into and out of a checkpoint).
+constexpr int kCopyParts = 24;
+struct CopyList {
+    int32_t n;
+    int32_t pad;
+    const uint32_t* src[kCopyParts];
+    uint32_t* dst[kCopyParts];
+    int64_t words[kCopyParts];
+};
+hipError_t launch_copy_parts(const CopyList& c, hipStream_t st);
+
 hipError_t prepare_adjoint_kernels(int lds_max);
 hipError_t launch_adjoint(const AdjArgs& a, int block_threads, int lds_bytes, int n_packs, hipStream_t st);
 hipError_t launch_grad_reduce(const GradReduceArgs& a, hipStream_t st);
+
+// The register-resident adjoint (reg_adjoint_kernels.hip): one workgroup per
+// pack of the sim's register layout (a: the sim's step arguments, for the
+// layout and coefficients; cfg: its launch shape), LDS reg_adjoint_lds_bytes.
+hipError_t prepare_reg_adjoint_kernels(int lds_max);
+hipError_t launch_reg_adjoint(const StepArgs& a, const AdjArgs& b, const LaunchCfg& cfg, int lds_bytes, int n_packs,
+                              hipStream_t st);
 
 }  // namespace arbmi

@@ -319,9 +319,9 @@ int Sim::advance(int64_t n, const RecordArgs* rec) {
         a.step0 = step;
         a.nsteps = int32_t(nthis);
         a.epoch_end = (pos + nthis == K) ? 1 : 0;
-            if (rec) {  // rows offset by the steps already done in this call
-            if (cfg.coef_mode == 3)
-                return set_error(ARB_EINVAL, "recording needs the streamed or LDS-resident step kernel");
+        if (rec) {  // rows offset by the steps already done in this call
+            if (cfg.coef_mode == 3 && !cfg.rec)
+                return set_error(ARB_ESTATE, "recording needs a sim built with ARB_FLAG_GRADIENTS");
             a.rec_V = rec->V + done * L.n_slots;
             a.rec_m = rec->m + done * int64_t(L.hh_cv.size());
             a.rec_h = rec->h + done * int64_t(L.hh_cv.size());
@@ -520,6 +520,7 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
     opt.max_cells_per_pack = plan.max_cells_per_pack;
     opt.reg_slots = plan.coef_mode == 3 ? plan.reg_slots : 0;
     opt.reg_len = plan.reg_len;
+    opt.grads = (p->flags & ARB_FLAG_GRADIENTS) != 0;
     int rc = lower_model(m.cells, m.n_cells, m.br, m.n_br, m.syn, m.n_syn, m.conn, m.n_conn, m.ev, m.n_ev, m.ic,
                          m.n_ic, *p, opt, s->L, err);
     const bool auto_mode = p->coef_mode == 0 || (p->flags & ARB_FLAG_AUTOTUNE);
@@ -531,7 +532,7 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
         opt.block_threads = p->block_threads ? p->block_threads : 256;
         opt.max_cells_per_pack = std::max<int64_t>(1, plan.fallback_cells_per_pack);
         opt.lds_budget = plan.fallback_lds_budget;
-        opt.lds_hard_max = d.lds_max - 256;
+        opt.lds_hard_max = plan.fallback_lds_hard_max;
         s->L = Lowered();
         rc = lower_model(m.cells, m.n_cells, m.br, m.n_br, m.syn, m.n_syn, m.conn, m.n_conn, m.ev, m.n_ev, m.ic,
                          m.n_ic, *p, opt, s->L, err);
@@ -557,10 +558,16 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
     s->cfg.reg_slots = s->L.reg_slots;
     s->cfg.reg_len = s->L.reg_len;
     s->cfg.syn_hbm = 0;
+    s->cfg.rec = (s->L.coef_mode == 3 && (p->flags & ARB_FLAG_GRADIENTS)) ? 1 : 0;
     int64_t lds = 0;
     for (const PackDesc& D : s->L.packs) {
         lds = std::max(lds, pack_lds_bytes(D, s->L.coef_mode));
         if (s->L.coef_mode == 3 && D.syn_global) s->cfg.syn_hbm = 1;
+    }
+    if (s->cfg.rec && s->cfg.syn_hbm) {  // the lowering keeps gradient sims' synapses in LDS
+        delete s;
+        err = "internal: a gradient sim keeps synapse state in HBM";
+        return ARB_EINVAL;
     }
     if (lds > d.lds_max - 256) {
         delete s;
@@ -679,8 +686,6 @@ int arb_build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     if (p->block_threads != 0 && p->block_threads != 64 && p->block_threads != 128 && p->block_threads != 256)
         return fail(ARB_EINVAL, "block_threads must be 0, 64, 128 or 256");
     if (p->coef_mode < 0 || p->coef_mode > 3) return fail(ARB_EINVAL, "coef_mode must be 0, 1, 2 or 3");
-    if (p->coef_mode == 3 && (p->flags & ARB_FLAG_GRADIENTS))
-        return fail(ARB_EINVAL, "coef_mode 3 does not record states: gradients need coef_mode 0, 1 or 2");
     if (p->cells_per_pack < 0) return fail(ARB_EINVAL, "cells_per_pack must be >= 0");
     if ((p->alloc == nullptr) != (p->free == nullptr)) return fail(ARB_EINVAL, "alloc and free must be given together");
 
@@ -717,8 +722,6 @@ int arb_plan_layout(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     if (p->block_threads != 0 && p->block_threads != 64 && p->block_threads != 128 && p->block_threads != 256)
         return fail(ARB_EINVAL, "block_threads must be 0, 64, 128 or 256");
     if (p->coef_mode < 0 || p->coef_mode > 3) return fail(ARB_EINVAL, "coef_mode must be 0, 1, 2 or 3");
-    if (p->coef_mode == 3 && (p->flags & ARB_FLAG_GRADIENTS))
-        return fail(ARB_EINVAL, "coef_mode 3 does not record states: gradients need coef_mode 0, 1 or 2");
     if (p->cells_per_pack < 0) return fail(ARB_EINVAL, "cells_per_pack must be >= 0");
     DeviceLimits d;  // MI355X: 256 CUs, 160 KiB LDS
     const Plan plan = choose_plan(cells, n_cells, branches, n_branches, *p, d.lds_max, d.n_cu);
@@ -730,6 +733,7 @@ int arb_plan_layout(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     opt.max_cells_per_pack = plan.max_cells_per_pack;
     opt.reg_slots = plan.coef_mode == 3 ? plan.reg_slots : 0;
     opt.reg_len = plan.reg_len;
+    opt.grads = (p->flags & ARB_FLAG_GRADIENTS) != 0;
     Lowered L;
     std::string err;
     int rc = lower_model(cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim, *p,
@@ -742,7 +746,7 @@ int arb_plan_layout(const arb_cell* cells, int32_t n_cells, const arb_branch* br
         opt.block_threads = p->block_threads ? p->block_threads : 256;
         opt.max_cells_per_pack = std::max<int64_t>(1, plan.fallback_cells_per_pack);
         opt.lds_budget = plan.fallback_lds_budget;
-        opt.lds_hard_max = d.lds_max - 256;
+        opt.lds_hard_max = plan.fallback_lds_hard_max;
         L = Lowered();
         rc = lower_model(cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim, *p,
                          opt, L, err);

@@ -28,8 +28,10 @@ struct Candidate {
     int coef_mode, threads, cells_per_pack;
 };
 
-// FNV-1a over the quantities that decide the best launch shape
-uint64_t shape_key(const ModelView& m, const DeviceLimits& d) {
+// FNV-1a over the quantities that decide the best launch shape (a sim built
+// for gradients runs the recording variants and packs for the adjoint's LDS,
+// so it has keys of its own)
+uint64_t shape_key(const ModelView& m, const DeviceLimits& d, const arb_params& p) {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](uint64_t x) {
         for (int i = 0; i < 8; ++i) {
@@ -53,7 +55,8 @@ uint64_t shape_key(const ModelView& m, const DeviceLimits& d) {
     for (uint64_t x : cv_hist) mix(x);
     mix(uint64_t(d.n_cu));
     mix(uint64_t(d.lds_max));
-    mix(5);  // version of the candidate set and kernels
+    mix(uint64_t((p.flags & ARB_FLAG_GRADIENTS) ? 1 : 0));
+    mix(6);  // version of the candidate set and kernels
     return h;
 }
 
@@ -190,7 +193,7 @@ double time_candidate(const Sample& smp, const arb_params& base, const DeviceLim
 
 arb_params autotune(const ModelView& m, const arb_params& p, const DeviceLimits& d) {
     arb_params out = p;
-    const uint64_t key = shape_key(m, d);
+    const uint64_t key = shape_key(m, d, p);
     Candidate best{0, 0, 0};
     if (!cache_lookup(key, best)) {
         // enough cells for several waves of workgroups on every CU, so that

@@ -94,6 +94,7 @@ struct LaunchCfg {
     int reg_slots;      // mode 3: branches per thread
     int reg_len;        // mode 3: CVs per branch held in registers (8 or 16)
     int syn_hbm;        // mode 3: some pack keeps its synapse state in HBM
+    int rec;            // mode 3: the sim is built for gradients (kernels that can record states)
 };
 
 hipError_t launch_step(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st);

@@ -103,6 +103,20 @@ inline int64_t pack_lds_bytes(const PackDesc& D, int coef_mode) {
     return 8 * dbl + 24 * int64_t(D.nrd) + 16 * int64_t(D.ntk) + 16 * int64_t(D.nnl) + 4 * int64_t(D.nch);
 }
 
+// Bytes of dynamic LDS the register-resident adjoint kernel uses for a pack
+// (reg_adjoint_kernels.hip): the V and R blocks (w and lambda_V), two
+// gradient sums per slot, three rows of voltage records, two rows of gate
+// and synapse records, seven doubles per hh instance (three adjoint gates,
+// two gradient sums, the two conductances), the per-task scalars of the
+// solve, the nonlinear entries, the children's tasks (other packs) and each
+// hh instance's slot.
+inline int64_t reg_adjoint_lds_bytes(const PackDesc& D) {
+    const int64_t nsp = std::max<int64_t>(D.nslot, int64_t(D.spare) + 1);
+    const int64_t dbl = vr_block_doubles(D.nslot, D.spare) + 5 * nsp + 13 * int64_t(D.nhh) +
+                        2 * int64_t(D.nsyn) + (D.binary ? 3 : 2) * (int64_t(D.ntk) + 2);
+    return 8 * dbl + 16 * int64_t(D.nnl) + (D.binary ? 0 : 4 * int64_t(D.nch)) + 4 * int64_t(D.nhh);
+}
+
 struct RoundDesc {
     int32_t slot0;  // pack-local slot of (k = 0, first thread)
     int32_t w;      // branches in the round

@@ -375,6 +375,11 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         int64_t nnl = 0;
         for (int32_t c : pp.cells) nnl += nnl_cell[c];
         D.nnl = int32_t(nnl);
+        if (opt.grads && mode == 3) {
+            // the adjoint reads the synapses' recorded conductances from LDS
+            if (D.syn_global) return int64_t(1) << 40;
+            return std::max(pack_lds_bytes(D, mode), reg_adjoint_lds_bytes(D));
+        }
         return pack_lds_bytes(D, mode);
     };
     std::vector<int32_t> order(n_cells);

@@ -88,6 +88,8 @@ struct LowerOptions {
     int64_t max_cells_per_pack = int64_t(1) << 30;
     int32_t reg_slots = 0;            // register-resident layout: branches per thread (0 = LDS layout)
     int32_t reg_len = 8;              // and the longest branch it takes
+    bool grads = false;               // packs must also fit the adjoint kernel (register layout:
+                                      // its LDS, and synapse state in LDS)
 };
 
 // Validates and lowers.  Returns ARB_OK or ARB_EINVAL (message in err).

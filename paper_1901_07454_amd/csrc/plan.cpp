@@ -41,13 +41,19 @@ Plan choose_plan(const arb_cell* cells, int32_t n_cells, const arb_branch* br, i
     const int T2 = p.block_threads ? p.block_threads : 256;
     pl.fallback_cells_per_pack = std::max<int64_t>(1, std::min<int64_t>(T2, T2 / max_width));
     pl.fallback_lds_budget = lds_max / 2;
+    pl.fallback_lds_hard_max = lds_max;
+    if (grads) {  // the streamed adjoint kernel keeps 32 B per CV (forward: 16 B)
+        pl.fallback_lds_budget = lds_max / 3;
+        pl.fallback_lds_hard_max = lds_max / 2 - 1024;
+    }
 
     // Register-resident coefficients (mode 3) by default when every branch
     // fits the registers: L = 8 CVs with up to 3 branches per thread, or
     // L = 16 with 1.  On request (and for the autotuner) longer branches are
     // cut into chains of 8-CV segments.  An explicit request is honoured or
-    // refused by the lowering, never changed.
-    const bool reg_ok = p.coef_mode == 3 || (p.coef_mode == 0 && max_len <= 16 && !grads);
+    // refused by the lowering, never changed.  With gradients the packs must
+    // also fit the register-resident adjoint kernel (the lowering checks).
+    const bool reg_ok = p.coef_mode == 3 || (p.coef_mode == 0 && max_len <= 16);
     if (reg_ok) {
         pl.coef_mode = 3;
         pl.block_threads = p.block_threads ? p.block_threads : 256;

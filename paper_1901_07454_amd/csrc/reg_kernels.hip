@@ -9,22 +9,13 @@
 // j on all of its threads, so the per-slot arrays are indexed with
 // compile-time constants.
 //
-// The solve of a branch is split so that only one multiply-add per branch
-// waits on the tree.  With the children's sum s and the parent's new V xp
-// as unknowns, the branch's recurrences are linear in them:
-//   rhs'_k = P_k - Q_k s,  F_0 rhs'_0 = F_0 P_0 - (F_0 Q_0) s,
-//   V_last = Y_last + Z xp,
-// where P and Y come from the branch's own CVs (all branches at once) and
-// F_0 Q_0 = F_0 prod_{k>=1}(-F_k), Z = prod_k(-F_k) are step-invariant.  So a
-// step runs: all branches' local elimination; rounds deepest first passing
-// the contributions up (one multiply-add per branch); all branches' full
-// elimination with their s and the local substitution; rounds shallowest
-// first passing the distal V down, two tree levels a round (a branch forms
-// its parent's V from its grandparent's: x_p = Y_p + Z_p x_gp); all
-// branches' substitution with xp.
-// The elimination and substitution themselves are the Hines recurrences of
-// the serial solve; only the values passed between branches are formed
-// through the split.
+// The solve is the split Hines solve of reg_solve.hpp: all branches'
+// local elimination; rounds deepest first passing the contributions up (one
+// multiply-add per branch); all branches' full elimination with their
+// children's sum and the local substitution; rounds shallowest first passing
+// the distal V down, two tree levels a round (a branch forms its parent's V
+// from its grandparent's: x_p = Y_p + Z_p x_gp); all branches' substitution
+// with the parent's V.
 //
 // LDS keeps V and R (the right-hand side) per slot, in blocks of 64 slots
 // (64 V then 64 R): V-only accesses of consecutive slots are 8 bytes apart
@@ -36,228 +27,34 @@
 // recurrences through unchanged (F = +1 at the first pad, -1 after it).
 // An empty register slot works on a slot no CV uses (a pad row, or one past
 // the pack's slots).
-// The kernel does not record states for the adjoint (the host refuses that).
+// With recording on (REC, for the adjoint's recompute) every step also
+// writes the state the adjoint needs to HBM: V after the step, the gates
+// before their update and the synapse conductances after the step's events.
 #include <hip/hip_runtime.h>
 
 #include "kernel_common.hpp"
 #include "kernels.hpp"
+#include "reg_solve.hpp"
 
 namespace arbmi {
 
 namespace {
 
 using namespace dev;
-
-// The registers of one branch slot.
-template <int L>
-struct Slot {
-    double A[L], F[L], D[L];  // alpha, F (pads: +1 then -1), 1/d' (pads: 0)
-    double FQ;                // F_0 Q_0
-    double Z, Zp;             // prod_k (-F_k) of this branch and of its parent
-    double fp, cs, yl, xp;    // per step: F_0 P_0, children's sum, V_last with xp = 0, parent's V
-    int base, w, len;         // CV k of the branch is slot base + k w
-    int r;                    // round of the branch, -1 if the slot is empty
-    int lev;                  // depth level (the soma is 0)
-    int task, ptask, gptask;  // own, parent's and grandparent's task (none: a zero entry)
-    int c0, c1;               // first two children's tasks (a zero entry if fewer)
-    int x0, x1;               // binary packs: grandchildren's tasks, two 16-bit fields each
-                              // (children of c0, of c1); other packs: further children
-                              // s_ch[x0 .. x0 + x1)
-};
-
-// V and R sit in blocks of 64 slots: 64 V, then the same slots' 64 R.  So
-// consecutive slots are 8 bytes apart (no bank conflicts for V alone) and R
-// is a fixed 512 bytes past V.
-__device__ __forceinline__ int vix(int slot) { return slot + (slot & ~63); }
-constexpr int kRoff = 64;
-
-// V index of the branch's CV k
-template <int L>
-__device__ __forceinline__ int cv_slot(const Slot<L>& g, int k) {
-    return vix(g.base + k * g.w);
-}
-
-// The three all-branch parts of the solve, each split into loads, arithmetic
-// and stores so that the kernel can issue every slot's loads before any
-// slot's stores (LDS stores may alias later loads, so the compiler keeps
-// them in source order) and overlap the slots' recurrences.
-
-// Local elimination (children's sum taken as 0): t_k = alpha_k V_k + R_k,
-// P_k = t_k - F_{k+1} P_{k+1}.  t stays in the thread's registers; F_0 P_0
-// is the branch's contribution if it has no children.
-template <int L>
-__device__ __forceinline__ void local_load(const Slot<L>& g, const double* sV, double* t) {
-#pragma unroll
-    for (int k = 0; k < L; ++k) t[k] = g.A[k] * sV[cv_slot(g, k)] + sV[cv_slot(g, k) + kRoff];
-}
-template <int L>
-__device__ __forceinline__ void local_chain(Slot<L>& g, const double* t) {
-    double acc = 0.0;
-#pragma unroll
-    for (int k = L - 1; k >= 0; --k) acc = (k == L - 1) ? t[k] : t[k] - g.F[(k + 1 < L) ? k + 1 : k] * acc;
-    g.fp = g.F[0] * acc;
-}
-template <int L>
-__device__ __forceinline__ void local_store(const Slot<L>& g, double* sC, double* sF) {
-    sC[g.task] = g.fp;
-    sF[g.task] = g.fp;
-}
-
-// Full elimination with the children's sum (t becomes rhs'/d', kept in
-// registers for the substitution), and the distal V for a grounded parent.
-template <int L>
-__device__ __forceinline__ void full_chain(Slot<L>& g, double* t) {
-    double acc = (g.len == L) ? g.cs : -g.cs;
-#pragma unroll
-    for (int k = L - 1; k >= 0; --k) {
-        const double r = (k == L - 1) ? t[k] - acc : t[k] - g.F[(k + 1 < L) ? k + 1 : k] * acc;
-        t[k] = r * g.D[k];
-        acc = r;
-    }
-    double x = 0.0;
-#pragma unroll
-    for (int k = 0; k < L; ++k) x = t[k] - g.F[k] * x;
-    g.yl = (g.len == L) ? x : -x;
-}
-template <int L>
-__device__ __forceinline__ void store_v(const Slot<L>& g, double* sV, const double* t) {
-#pragma unroll
-    for (int k = 0; k < L; ++k) sV[cv_slot(g, k)] = t[k];
-}
-
-// Substitution with the parent's V: V_k = rhs'_k/d'_k - F_k V_{k-1}.
-template <int L>
-__device__ __forceinline__ void subst_chain(const Slot<L>& g, double* y) {
-    double x = g.xp;
-#pragma unroll
-    for (int k = 0; k < L; ++k) {
-        x = y[k] - g.F[k] * x;
-        y[k] = x;
-    }
-}
-
-// Fill slot g with the branch this thread takes in round r of the pack (an
-// empty slot, len 0, if r < 0).  Branch-free: an empty slot reads valid
-// entries of the pack and keeps neutral values.
-template <int L>
-__device__ __forceinline__ void load_slot(Slot<L>& g, const StepArgs& a, const PackDesc& pk, int r, int tid) {
-    const bool has = r >= 0;
-    const int none = pk.ntk, dump = pk.ntk + 1;
-    const RoundDesc R = a.rd[pk.rd0 + (has ? r : 0)];
-    const int i = has ? round_index(R, tid) : 0;
-    const int task = has ? R.task0 + i : 0;
-    const TaskDesc t = a.tk[pk.tk0 + task];
-    const int len = has ? t.len : 0;
-    g.r = has ? r : -1;
-    g.len = len;
-    g.base = has ? R.slot0 + i : pk.spare;
-    g.w = has ? R.w : 0;
-    g.task = has ? task : dump;
-    const int pt = a.tk_ptask[pk.tk0 + task];
-    g.ptask = (has && pt >= 0) ? pt : none;
-    const int gpt = (g.ptask != none) ? a.tk_ptask[pk.tk0 + g.ptask] : -1;
-    g.gptask = (gpt >= 0) ? gpt : none;
-    g.lev = has ? a.tk_lev[pk.tk0 + task] : -1000;  // empty: no round matches
-    g.Zp = (g.ptask != none) ? a.tk_Z[pk.tk0 + g.ptask] : 0.0;
-    g.c0 = none;
-    g.c1 = none;
-    if (has && t.nch > 0) g.c0 = a.ch_task[pk.ch0 + t.ch0];
-    if (has && t.nch > 1) g.c1 = a.ch_task[pk.ch0 + t.ch0 + 1];
-    if (pk.binary) {
-        int gc[4] = {none, none, none, none};
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int c = h ? g.c1 : g.c0;
-            if (c != none) {
-                const TaskDesc tc = a.tk[pk.tk0 + c];
-                if (tc.nch > 0) gc[2 * h] = a.ch_task[pk.ch0 + tc.ch0];
-                if (tc.nch > 1) gc[2 * h + 1] = a.ch_task[pk.ch0 + tc.ch0 + 1];
-            }
-        }
-        g.x0 = gc[0] | (gc[1] << 16);
-        g.x1 = gc[2] | (gc[3] << 16);
-    } else {
-        g.x0 = t.ch0 + 2;
-        g.x1 = has ? max(0, t.nch - 2) : 0;
-    }
-    double q = 1.0, z = 1.0;
-#pragma unroll
-    for (int k = 0; k < L; ++k) {
-        const bool real = k < len;
-        const int64_t sl = pk.slot0 + (has ? g.base + int64_t(min(k, len - 1)) * g.w : 0);
-        const double al = a.alpha[sl], f = a.F[sl], dv = a.invd[sl];
-        g.A[k] = real ? al : 0.0;
-        g.D[k] = real ? dv : 0.0;
-        g.F[k] = real ? f : (k == len ? 1.0 : -1.0);
-        if (real) z *= -g.F[k];
-        if (real && k >= 1) q *= -g.F[k];
-    }
-    g.FQ = g.F[0] * q;
-    g.Z = has ? a.tk_Z[pk.tk0 + task] : z;
-    g.fp = 0.0;
-    g.cs = 0.0;
-    g.yl = 0.0;
-    g.xp = 0.0;
-}
-
-// Up round, one level at a time: the children's sum and this branch's
-// contribution to its parent.
-template <int L>
-__device__ __forceinline__ void pass_up(Slot<L>& g, double* sC, const int32_t* s_ch) {
-    double cs = sC[g.c0] + sC[g.c1];
-    for (int q = 0; q < g.x1; ++q) cs += sC[s_ch[g.x0 + q]];
-    g.cs = cs;
-    sC[g.task] = g.fp - g.FQ * cs;
-}
-
-// Up round, two levels at a time (packs of at most binary branch points):
-// each child's contribution formed from its local value and its own
-// children's final contributions, C_c = F_0 P_0(c) - F_0 Q_0(c) sum C_g, so a
-// branch and its children share a round.
-template <int L>
-__device__ __forceinline__ void pass_up2(Slot<L>& g, const double* sF, const double* sQ, double* sC) {
-    const int g00 = g.x0 & 0xffff, g01 = int(unsigned(g.x0) >> 16);
-    const int g10 = g.x1 & 0xffff, g11 = int(unsigned(g.x1) >> 16);
-    const double s0 = sF[g.c0] - sQ[g.c0] * (sC[g00] + sC[g01]);
-    const double s1 = sF[g.c1] - sQ[g.c1] * (sC[g10] + sC[g11]);
-    g.cs = s0 + s1;
-    sC[g.task] = g.fp - g.FQ * g.cs;
-}
-
-// Down round, two levels at a time: the parent's V from the grandparent's
-// (x_p = Y_p + Z_p x_gp, so a branch and its parent can take the same round),
-// then this branch's distal V.
-template <int L>
-__device__ __forceinline__ void pass_down(Slot<L>& g, const double* sY, double* sX) {
-    g.xp = sY[g.ptask] + g.Zp * sX[g.gptask];
-    sX[g.task] = g.yl + g.Z * g.xp;
-}
-
-// End of a round of the tree passes.  A one-wave workgroup needs no
-// barrier and no wait: a wave's LDS operations take effect in issue order,
-// so the next round's loads see this round's stores.
-template <int T>
-__device__ __forceinline__ int block_count(bool pred) {
-    if constexpr (T == 64)
-        return __popcll(__ballot(pred));
-    else
-        return __syncthreads_count(pred);
-}
-
-template <int T>
-__device__ __forceinline__ void round_sync() {
-    if constexpr (T == 64)
-        __builtin_amdgcn_wave_barrier();
-    else
-        __syncthreads();
-}
+using namespace reg;
 
 // Waves per SIMD the registers allow without spilling (built without
 // machine loop-invariant code motion): three for one slot of 8 CVs, two for
 // 16 CVs in all, one otherwise.  G: some pack of the launch keeps its
-// synapse state in HBM (without it, that path is compiled out).
-template <int T, int S, int L, bool G>
-__global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) reg_step_kernel(StepArgs a) {
+// synapse state in HBM (without it, that path is compiled out).  REC: the
+// sim is built for gradients; the steps record their states when a.rec_V
+// is set (the adjoint's recompute), and the gradient forward runs the same
+// code with it unset, so both produce the same trajectory bit for bit (one
+// wave per SIMD fewer than the plain variant: the recording's addresses take
+// the registers).
+template <int T, int S, int L, bool G, bool REC>
+__global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)))
+    reg_step_kernel(StepArgs a) {
     extern __shared__ __align__(16) char lds_raw[];
     const int p = blockIdx.x + a.pack0;
     const PackDesc pk = a.pk[p];
@@ -294,9 +91,12 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
     int32_t* s_ch = reinterpret_cast<int32_t*>(s_nl + pk.nnl);  // children's tasks (other packs)
     int32_t* s_hhs = s_ch + (pk.binary ? 0 : pk.nch);          // per hh instance: its CV's slot
 
+    const bool rec = REC && a.rec_V != nullptr;
     for (int i = tid; i < ns; i += T) {
-        sV[vix(i)] = a.V[pk.slot0 + i];
+        const double v = a.V[pk.slot0 + i];
+        sV[vix(i)] = v;
         sV[vix(i) + kRoff] = a.beta[pk.slot0 + i];
+        if (rec) a.rec_V[pk.slot0 + i] = v;  // row 0: the state before the launch's first step
     }
     if (tid == 0 && pk.spare == ns) {
         sV[vix(ns)] = 0.0;
@@ -455,6 +255,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
                 for (int k = 0; k < d.nsyn; ++k) {
                     const int q = d.syn0 + k;
                     const double gq = sg[q];
+                    if (rec) a.rec_g[int64_t(s) * a.n_syn_total + pk.syn0 + q] = gq;
                     I += gq * (v - s_se[q]);
                     sg[q] = gq * s_sdec[q];
                 }
@@ -572,6 +373,12 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
             store_v<L>(g0, sV, y0);
             if constexpr (S > 1) store_v<L>(g1, sV, y1);
             if constexpr (S > 2) store_v<L>(g2, sV, y2);
+            if (rec) {  // V^{n+1} into row s + 1, from the owners' registers
+                double* row = a.rec_V + int64_t(s + 1) * a.n_slots_total + pk.slot0;
+                record_v<L>(g0, row, y0);
+                if constexpr (S > 1) record_v<L>(g1, row, y1);
+                if constexpr (S > 2) record_v<L>(g2, row, y2);
+            }
         }
         round_sync<T>();
 
@@ -585,11 +392,21 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
                 double al, be;
                 hh_gate_rates(w, sV[s_hhs[q]], al, be);
                 double* x = (w == 0) ? sm : (w == 1) ? sh : sn;
+                if (rec) {  // the gate before its update
+                    double* r = (w == 0) ? a.rec_m : (w == 1) ? a.rec_h : a.rec_n;
+                    r[int64_t(s) * a.n_hh_total + pk.hh0 + q] = x[q];
+                }
                 x[q] = gate_step_pair(x[q], al, be, a.dt);
             }
         } else {
             for (int q = tid; q < pk.nhh; q += T) {
                 const Rates rt = hh_rates(sV[s_hhs[q]]);
+                if (rec) {  // the gates before their update
+                    const int64_t at = int64_t(s) * a.n_hh_total + pk.hh0 + q;
+                    a.rec_m[at] = sm[q];
+                    a.rec_h[at] = sh[q];
+                    a.rec_n[at] = sn[q];
+                }
                 sm[q] = gate_step(sm[q], rt.am, rt.bm, a.dt);
                 sh[q] = gate_step(sh[q], rt.ah, rt.bh, a.dt);
                 sn[q] = gate_step(sn[q], rt.an, rt.bn, a.dt);
@@ -630,16 +447,20 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)) r
 
 template <int T, int S, int L>
 hipError_t launch_reg(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st) {
-    if (cfg.syn_hbm)
-        hipLaunchKernelGGL((reg_step_kernel<T, S, L, true>), dim3(n_packs), dim3(T), cfg.lds_bytes, st, a);
-    else
-        hipLaunchKernelGGL((reg_step_kernel<T, S, L, false>), dim3(n_packs), dim3(T), cfg.lds_bytes, st, a);
+    if (cfg.rec) {  // gradient sims never keep synapse state in HBM
+        if (cfg.syn_hbm) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((reg_step_kernel<T, S, L, false, true>), dim3(n_packs), dim3(T), cfg.lds_bytes, st, a);
+    } else if (cfg.syn_hbm) {
+        hipLaunchKernelGGL((reg_step_kernel<T, S, L, true, false>), dim3(n_packs), dim3(T), cfg.lds_bytes, st, a);
+    } else {
+        hipLaunchKernelGGL((reg_step_kernel<T, S, L, false, false>), dim3(n_packs), dim3(T), cfg.lds_bytes, st, a);
+    }
     return hipGetLastError();
 }
 
-template <int T, int S, int L, bool G>
+template <int T, int S, int L, bool G, bool REC>
 void allow_lds_one(int lds_max) {
-    const void* f = reinterpret_cast<const void*>(&reg_step_kernel<T, S, L, G>);
+    const void* f = reinterpret_cast<const void*>(&reg_step_kernel<T, S, L, G, REC>);
     hipFuncAttributes at{};
     if (hipFuncGetAttributes(&at, f) != hipSuccess) return;
     const int allowed = lds_max - int(at.sharedSizeBytes);
@@ -649,8 +470,9 @@ void allow_lds_one(int lds_max) {
 
 template <int T, int S, int L>
 void allow_lds(int lds_max) {
-    allow_lds_one<T, S, L, false>(lds_max);
-    allow_lds_one<T, S, L, true>(lds_max);
+    allow_lds_one<T, S, L, false, false>(lds_max);
+    allow_lds_one<T, S, L, true, false>(lds_max);
+    allow_lds_one<T, S, L, false, true>(lds_max);
 }
 
 template <int T>

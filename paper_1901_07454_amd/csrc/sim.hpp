@@ -28,6 +28,7 @@ struct Plan {
     int reg_slots = 0, reg_len = 8;
     int64_t fallback_cells_per_pack = 1;  // streamed mode, if the chosen layout fails
     int64_t fallback_lds_budget = 0;
+    int64_t fallback_lds_hard_max = 0;
 };
 Plan choose_plan(const arb_cell* cells, int32_t n_cells, const arb_branch* br, int64_t n_br, const arb_params& p,
                  int64_t lds_max, int n_cu);

@@ -146,7 +146,22 @@ def test_rejects_epoch_longer_than_min_delay():
 def test_rejects_bad_launch_parameters():
     _expect_einval(_ring(), "block_threads", block_threads=96)
     _expect_einval(_ring(), "coef_mode", coef_mode=4)
-    _expect_einval(_ring(), "gradients", coef_mode=3, flags=arbmi.ARB_FLAG_GRADIENTS)
+
+
+def test_gradient_layouts():
+    """Sims built for gradients take the register layout when its packs also
+    fit the adjoint kernel; a cell whose synapses would have to stay in HBM
+    (the adjoint reads them from LDS) falls back to streamed coefficients, or
+    is refused when the register layout was asked for."""
+    G = arbmi.ARB_FLAG_GRADIENTS
+    assert _plan(gen.config4(n_cells=4, n_steps=100), flags=G)["coef_mode"] == 3
+    assert _plan(gen.config2(n_cells=4, n_steps=100), flags=G)["coef_mode"] == 3
+    m = gen.config6(n_cells=4, n_steps=100, n_syn=2000)
+    assert _plan(m)["syn_hbm"] == 1
+    assert _plan(m, flags=G)["coef_mode"] == 2
+    with pytest.raises(arbmi.ArbError) as e:
+        _plan(m, flags=G, coef_mode=3)
+    assert e.value.code == arbmi.ARB_EINVAL
 
 
 @pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")

@@ -9,7 +9,12 @@ from workloads import gen
 pytestmark = pytest.mark.gpu
 
 
-def _setup(n_cells, n_steps):
+# The two adjoint kernels: the register-resident one (the default layout of
+# these cells) and the streamed one (coefficient mode 2).
+LAYOUTS = {"register": ({}, 3), "streamed": ({"coef_mode": 2}, 2)}
+
+
+def _setup(n_cells, n_steps, layout="register", **kw):
     import torch
 
     from paper_1901_07454_amd import grad
@@ -18,9 +23,29 @@ def _setup(n_cells, n_steps):
     th0 = gen.config4_theta(m0)
     ref = oracle.Sim(mh)
     tgt = ref.run(n_steps, probes=oracle.cell_cv_begin(mh)[:-1])
-    gs = grad.GradSim(m0)
+    extra, mode = LAYOUTS[layout]
+    gs = grad.GradSim(m0, **extra, **kw)
+    if "flags" not in kw:
+        assert gs.sim.info["coef_mode"] == mode, gs.sim.info
     theta = torch.tensor(th0, dtype=torch.float64, device="cuda", requires_grad=True)
     return m0, th0, tgt, gs, theta
+
+
+def model_theta(m):
+    """Per-region [gNa, gK, g_pas] of any model (regions: each cell's soma,
+    then its branches), flat [regions, 3]."""
+    out = []
+    b = 0
+    for c, nb in enumerate(m["cell_n_branch"]):
+        out.append((m["soma_gna"][c], m["soma_gk"][c], m["soma_gpas"][c]))
+        for k in range(int(nb)):
+            out.append((m["br_gna"][b + k], m["br_gk"][b + k], m["br_gpas"][b + k]))
+        b += int(nb)
+    return np.array(out, dtype=np.float64)
+
+
+def _oracle_rel(g, og):
+    return np.abs(g - og) / np.maximum(np.abs(og), 1e-3 * np.max(np.abs(og), axis=(1, 2), keepdims=True))
 
 
 def _loss_grad(gs, theta, tgt, n_steps, k):
@@ -34,9 +59,10 @@ def _loss_grad(gs, theta, tgt, n_steps, k):
     return tr.detach().cpu().numpy(), loss.item(), theta.grad.detach().cpu().numpy()
 
 
-def test_adjoint_matches_oracle_adjoint():
+@pytest.mark.parametrize("layout", sorted(LAYOUTS))
+def test_adjoint_matches_oracle_adjoint(layout):
     n_cells, n_steps = 6, 800
-    m0, th0, tgt, gs, theta = _setup(n_cells, n_steps)
+    m0, th0, tgt, gs, theta = _setup(n_cells, n_steps, layout)
     tr, L, g = _loss_grad(gs, theta, tgt, n_steps, 100)
     s = oracle.Sim(m0)
     s.set_params(th0.reshape(-1, 3))
@@ -50,9 +76,10 @@ def test_adjoint_matches_oracle_adjoint():
     gs.close()
 
 
-def test_adjoint_checkpoint_interval_invariant():
+@pytest.mark.parametrize("layout", sorted(LAYOUTS))
+def test_adjoint_checkpoint_interval_invariant(layout):
     n_cells, n_steps = 3, 600
-    m0, th0, tgt, gs, theta = _setup(n_cells, n_steps)
+    m0, th0, tgt, gs, theta = _setup(n_cells, n_steps, layout)
     ref = _loss_grad(gs, theta, tgt, n_steps, 600)[2]
     for k in (1, 37, 100):
         g = _loss_grad(gs, theta, tgt, n_steps, k)[2]
@@ -130,3 +157,61 @@ def test_adjoint_through_network_events():
     g37 = _loss_grad(gs, theta, tgt, n, 37)[2]
     assert np.allclose(g37, g, rtol=1e-12, atol=1e-14 * np.abs(g).max())
     gs.close()
+
+
+def test_autotuned_gradient_sim(tmp_path, monkeypatch):
+    """A gradient sim built with the autotuner, with a cache that already
+    holds the plain sim's choice for the same model: the gradient sim gets
+    its own entry, and its backward matches the oracle's adjoint."""
+    from paper_1901_07454_amd import arbmi
+    monkeypatch.setenv("ARB_AUTOTUNE_CACHE", str(tmp_path / "cache.txt"))
+    n_cells, n_steps = 8, 400
+    m0 = gen.config4(n_cells=n_cells, n_steps=n_steps)
+    plain = arbmi.Simulation(m0, flags=arbmi.ARB_FLAG_AUTOTUNE)
+    plain.close()
+    m0, th0, tgt, gs, theta = _setup(n_cells, n_steps, flags=arbmi.ARB_FLAG_AUTOTUNE)
+    assert len((tmp_path / "cache.txt").read_text().splitlines()) == 2
+    print("gradient sim", gs.sim.info, flush=True)
+    tr, L, g = _loss_grad(gs, theta, tgt, n_steps, 100)
+    s = oracle.Sim(m0)
+    s.set_params(th0.reshape(-1, 3))
+    otr, og = s.adjoint(n_steps, 2.0 * (tr - tgt) / tr.size)
+    assert np.max(np.abs(tr - otr)) <= 1e-8
+    rel = _oracle_rel(g, og.reshape(th0.shape))
+    print(f"max rel |g_gpu - g_oracle| = {rel.max():.3e}", flush=True)
+    assert rel.max() <= 1e-7
+    gs.close()
+
+
+@pytest.mark.parametrize("layout", sorted(LAYOUTS))
+def test_adjoint_of_ring_cells_with_synapses(layout):
+    """Cells of the 8192-cell ring (127 passive branches, hh soma, 10
+    synapses) on a 4-cell ring with the kick: synapse conductances enter
+    dI/dV, several cells share a workgroup, and few hh instances per pack."""
+    import torch
+
+    from paper_1901_07454_amd import arbmi
+    n = 600
+    m0 = gen.config2(n_cells=4, n_steps=n)
+    th = model_theta(m0)
+    sim = arbmi.Simulation(m0, flags=arbmi.ARB_FLAG_GRADIENTS, **LAYOUTS[layout][0])
+    assert sim.info["coef_mode"] == LAYOUTS[layout][1], sim.info
+    sim.set_params(th)
+    cv0 = oracle.cell_cv_begin(m0)
+    tgt = oracle.Sim(m0).run(n, probes=cv0[:-1]) + 1.0
+    trace = torch.empty(4, n, dtype=torch.float64, device="cuda")
+    arbmi.arb_grad_forward(sim.h, n, 100, trace)
+    tr = trace.cpu().numpy()
+    dl = 2.0 * (tr - tgt) / tr.size
+    out = torch.empty(th.size, dtype=torch.float64, device="cuda")
+    arbmi.arb_grad_backward(sim.h, torch.as_tensor(dl, device="cuda"), out)
+    g = out.cpu().numpy().reshape(-1, 3)
+    s = oracle.Sim(m0)
+    s.set_params(th)
+    otr, og = s.adjoint(n, dl)
+    assert np.max(np.abs(tr - otr)) <= 1e-8
+    den = np.maximum(np.abs(og), 1e-3 * np.max(np.abs(og), axis=0, keepdims=True))
+    rel = np.abs(g - og) / den
+    print(f"{layout}: max rel |g_gpu - g_oracle| = {rel.max():.3e}", flush=True)
+    assert rel.max() <= 1e-7
+    sim.close()
