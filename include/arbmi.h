@@ -206,6 +206,16 @@ int arb_step(arb_sim s, int64_t n_steps);
  * first such call and keeps until arb_free. */
 int arb_get_voltages(arb_sim s, double *dst, int64_t n, int dst_on_device);
 
+/* arb_get_voltages into host memory without allocating: for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid it).  Same output as arb_get_voltages with a
+ * host dst (n >= n_cv doubles, user CV order), staged through a fixed 64 MiB
+ * array of static device memory (8,388,608 doubles) that every GPU the
+ * library runs on holds until the process ends.  ARB_EINVAL if the model has
+ * more CVs than that (the call then touches nothing).  All sims on one GPU
+ * share the array: calls that overlap on one GPU race and must not be made. */
+int arb_get_voltages_noalloc(arb_sim s, double *dst, int64_t n);
+
 /* Drain the spikes recorded since the last call into host dst, sorted by
  * (step, gid).  A spike is an upward crossing of the fixed threshold by the
  * soma voltage (Sec. II); spike trains are the second output the paper

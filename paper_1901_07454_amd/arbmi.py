@@ -71,7 +71,7 @@ class arb_info(C.Structure):
 EXPORTS = ["arb_build_cells", "arb_step", "arb_get_voltages", "arb_get_spikes", "arb_set_probes",
            "arb_get_trace", "arb_set_params", "arb_grad_forward", "arb_grad_backward",
            "arb_get_state", "arb_set_state", "arb_get_info", "arb_get_kernel_time", "arb_sync",
-           "arb_free", "arb_last_error", "arb_plan_layout"]
+           "arb_free", "arb_last_error", "arb_plan_layout", "arb_get_voltages_noalloc"]
 
 _lib = None
 
@@ -94,6 +94,7 @@ def load():
             "arb_build_cells": [P, I32, P, I64, P, I64, P, I64, P, I64, P, I32, C.POINTER(arb_params), C.POINTER(P)],
             "arb_step": [P, I64],
             "arb_get_voltages": [P, P, I64, C.c_int],
+            "arb_get_voltages_noalloc": [P, P, I64],
             "arb_get_spikes": [P, P, I64, C.POINTER(I64)],
             "arb_set_probes": [P, P, I32, I64],
             "arb_get_trace": [P, P, I64, C.c_int, C.POINTER(I64)],
@@ -169,6 +170,10 @@ def arb_step(sim, n_steps: int):
 def arb_get_voltages(sim, dst, on_device: bool):
     _check(load().arb_get_voltages(sim, _ptr(dst), int(dst.numel() if hasattr(dst, "numel") else dst.size),
                                    1 if on_device else 0))
+
+
+def arb_get_voltages_noalloc(sim, dst):
+    _check(load().arb_get_voltages_noalloc(sim, _ptr(dst), int(dst.size)))
 
 
 def arb_get_spikes(sim, cap: int):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libarbmi.so")
 SOURCES = ["kernels.hip", "reg_kernels.hip", "reg_adjoint_kernels.hip", "adjoint_kernels.hip", "arbmi.cpp", "lower.cpp",
-           "plan.cpp", "adjoint.cpp", "autotune.cpp"]
+           "plan.cpp", "adjoint.cpp", "autotune.cpp", "noalloc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

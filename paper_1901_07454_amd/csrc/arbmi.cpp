@@ -644,6 +644,9 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
         hipError_t e = hipStreamSynchronize(s->st);
         if (e != hipSuccess) rc = hip_fail(e, "upload");
     }
+    // the no-allocation voltage read's staging buffer on this device (a
+    // failed lookup only disables that call)
+    if (rc == ARB_OK) (void)noalloc_setup(s->device);
     if (rc != ARB_OK) {
         err = g_err;
         destroy_sim(s);  // buffers, streams and events

@@ -167,6 +167,9 @@ void destroy_sim(Sim* s);
 arb_params autotune(const ModelView& m, const arb_params& p, const DeviceLimits& d);
 
 int set_error(int code, const std::string& msg);
+// Look up, once per device (the device current), the static staging buffer of
+// arb_get_voltages_noalloc.
+hipError_t noalloc_setup(int device);
 int set_hip_error(hipError_t e, const char* where);
 
 }  // namespace arbmi
