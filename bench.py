@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -206,20 +208,35 @@ def measured_traffic(path: str, cfg: int, kernel: str, steps_per_launch: float):
         return None
 
 
-def grad_ratio(torch, reps: int = 3):
-    """Config 4: wall time of the forward+adjoint gradient (2000 steps,
-    checkpoints every 100, through the autograd wrapper) over the wall time
-    of the plain forward of the same model on the same GPU, built as the
-    plain benchmark builds it (autotuned launch shape, no gradient flag)."""
+def grad_ratio(torch, reps: int = 3, subset: bool = False):
+    """Wall time of the forward+adjoint gradient (checkpoints every 100 steps,
+    through the autograd wrapper) over the wall time of the plain forward of
+    the same model on the same GPU, built as the plain benchmark builds it
+    (autotuned launch shape, no gradient flag).  Config 4 (256 cells x 200
+    CVs, 2000 steps, loss: soma traces against zero), or with subset the
+    1024-cell subset of the 65536-cell network (800 steps, network input as
+    fixed events, loss: soma traces against -65 mV)."""
     from paper_1901_07454_amd import arbmi, grad
     from workloads import gen
-    n_steps, k = 2000, 100
-    m0 = gen.config4(n_steps=n_steps)
+    k = 100
+    if subset:
+        n_steps = 800
+        m0 = gen.config5_subset(n_steps=n_steps)
+        regions = grad_regions(m0)
+        workload = ("1024-cell subset of the 65536-cell network: 1497 CVs per cell, network input as fixed "
+                    "events, 800 steps (20 ms), checkpoint every 100")
+        v_target = -65.0
+    else:
+        n_steps = 2000
+        m0 = gen.config4(n_steps=n_steps)
+        regions = gen.config4_theta(m0)
+        workload = "config 4: 256 cells x 200 CVs, hh+pas, 2000 steps, checkpoint every 100"
+        v_target = 0.0
     plain = arbmi.Simulation(m0, flags=arbmi.ARB_FLAG_AUTOTUNE)
     plain_state0 = plain.get_state()
     gs = grad.GradSim(m0, flags=arbmi.ARB_FLAG_AUTOTUNE)
-    theta = torch.tensor(gen.config4_theta(m0), dtype=torch.float64, device="cuda", requires_grad=True)
-    target = torch.zeros(gs.n_cells, n_steps, dtype=torch.float64, device="cuda")
+    theta = torch.tensor(regions, dtype=torch.float64, device="cuda", requires_grad=True)
+    target = torch.full((gs.n_cells, n_steps), v_target, dtype=torch.float64, device="cuda")
 
     def fwd():
         plain.set_state(plain_state0)
@@ -249,10 +266,23 @@ def grad_ratio(torch, reps: int = 3):
     gs.close()
     plain.close()
     f, fa = min(t_f), min(t_fa)
-    return {"workload": "config 4: 256 cells x 200 CVs, hh+pas, 2000 steps, checkpoint every 100",
+    return {"workload": workload,
             "fwd_ms": f * 1e3, "fwd_adj_ms": fa * 1e3, "ratio": fa / f, "target_ratio": 4.0,
             "fwd_kernel": kp, "grad_sim_kernel": kg,
             "note": "fwd: the plain benchmark's sim (autotuned, no gradient flag); fwd_adj: the gradient sim"}
+
+
+def grad_regions(m: dict):
+    """Per-region (soma, then branches, per cell) [gNa, gK, g_pas] of a model,
+    flat [regions, 3]."""
+    out = []
+    b = 0
+    for c, nb in enumerate(m["cell_n_branch"]):
+        out.append((m["soma_gna"][c], m["soma_gk"][c], m["soma_gpas"][c]))
+        for q in range(int(nb)):
+            out.append((m["br_gna"][b + q], m["br_gk"][b + q], m["br_gpas"][b + q]))
+        b += int(nb)
+    return np.array(out, dtype=np.float64)
 
 
 def main():
@@ -379,6 +409,8 @@ def main():
     sim.close()
     if not args.no_grad:
         out["grad"] = grad_ratio(torch)
+        if args.config == 5:
+            out["grad_subset"] = grad_ratio(torch, subset=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.config)
     print(json.dumps(out))

@@ -45,27 +45,102 @@ def test_config3_full_size_sampled_cells():
         assert mine == sorted(int(x) for x in st)
 
 
-def test_config5_full_size_light_cone():
-    """65536 cells x 1497 CVs, 400 steps: a sampled cell's inputs within 400
-    steps come only from its sources' spikes before step 201, which depend on
-    nothing but the sources' own background input."""
-    m = gen.config5(n_steps=400)
+def _c5_cell_alone(args):
+    """Oracle run of cell i of the 65536-cell network alone for n steps, its
+    network input replaced by the events its sources' given spikes deliver
+    before step n (each connection has its own synapse, so the conductance
+    sums are the network run's); returns (spike steps, soma trace, final V)."""
+    i, n, spikes, want = args
+    import numpy as np
+
+    import oracle
+    from workloads import gen
+    d = gen.cell_c5(i, 65536, t_ms=20.0)
+    d.ext = [e for e in d.ext if e[1] < n]
+    for (src, ls, delay, w) in d.in_conn:
+        for t in spikes.get(int(src), ()):
+            if t + delay < n:
+                d.ext.append((ls, int(t + delay), w))
+    d.in_conn = []
+    s = oracle.Sim(gen.assemble([d], gids=[i], n_steps=n))
+    tr = s.run(n, probes=[0])[0] if want else (s.run(n), None)[1]
+    _, st, _ = s.spikes()
+    return [int(x) for x in st], tr, (s.state()["V"] if want else None)
+
+
+def _c5_light_cone(m, c, n, pool):
+    """Cell c of the 65536-cell network over n = 800 steps, exactly, from
+    oracle runs of single cells: with delays of at least 200 steps, c's
+    dynamics to step 800 depend on its sources' spikes before 600, theirs on
+    their sources' spikes before 400, and those on spikes before 200, which
+    come from background input alone (no network event arrives before step
+    200).  A cell without any input event before its horizon cannot spike
+    and is not run."""
+    src_of = {}
+    order = np.argsort(m["con_dst"], kind="stable")
+    bounds = np.searchsorted(m["con_dst"][order], np.arange(len(m["cell_n_branch"]) + 1))
+
+    def sources(j):
+        if j not in src_of:
+            src_of[j] = [int(x) for x in m["con_src"][order[bounds[j]:bounds[j + 1]]]]
+        return src_of[j]
+
+    ev_cell = m["syn_cell"][m["ev_syn"]]
+    first_bg = np.full(len(m["cell_n_branch"]), np.iinfo(np.int64).max)
+    np.minimum.at(first_bg, ev_cell, m["ev_step"])
+    s1 = sorted(set(sources(c)))
+    s2 = sorted({x for j in s1 for x in sources(j)})
+    s3 = sorted({x for j in s2 for x in sources(j)})
+    spikes = {}
+    # level 3: spikes before step 200 (background only)
+    run3 = [j for j in s3 if first_bg[j] < 200]
+    for j, (st, _, _) in zip(run3, pool.map(_c5_cell_alone, [(j, 200, {}, False) for j in run3])):
+        spikes[j] = st
+    # level 2 (to step 400), level 1 (to step 600)
+    for level, horizon in ((s2, 400), (s1, 600)):
+        prev = dict(spikes)
+        run = [j for j in level if first_bg[j] < horizon or any(
+            t + 200 <= horizon for x in sources(j) for t in prev.get(x, ()))]
+        res = pool.map(_c5_cell_alone, [(j, horizon, {x: prev[x] for x in sources(j) if x in prev}, False)
+                                        for j in run])
+        spikes = dict(prev)
+        for j, (st, _, _) in zip(run, res):
+            spikes[j] = st
+    print(f"cell {c}: light cone {len(s1)} / {len(s2)} / {len(s3)} cells, "
+          f"{sum(len(v) for v in spikes.values())} spikes", flush=True)
+    return _c5_cell_alone((c, n, {x: spikes[x] for x in sources(c) if x in spikes}, True))
+
+
+@pytest.fixture(scope="module")
+def _c5_full():
+    from paper_1901_07454_amd import arbmi
+    n = 800
+    m = gen.config5(n_steps=n)
     cv0 = oracle.cell_cv_begin(m)
-    samples = [0, 31337, 65535]
-    tr, V, sp, info = _gpu(m, 400, cv0[samples])
+    samples = [0, 65535]
+    tr, V, sp, info = _gpu(m, n, cv0[samples], block_threads=128, coef_mode=3, cells_per_pack=1)
     print("config 5 info", info, "spikes", len(sp), flush=True)
-    for k, c in enumerate(samples):
-        srcs = [int(x[0]) for x in gen.cell_c5(c, 65536, t_ms=10.0).in_conn]
-        cells = [c] + srcs
-        sub = gen.config5(n_cells=65536, cells=cells, n_steps=400)
-        s = oracle.Sim(sub)
-        rtr = s.run(400, probes=[0])[0]
-        err = max(np.max(np.abs(tr[k] - rtr)), np.max(np.abs(V[cv0[c]:cv0[c + 1]] - s.state()["V"][:cv0[c + 1] - cv0[c]])))
-        g, st, _ = s.spikes()
-        mine = sorted(int(x) for x in sp["step"][sp["gid"] == c])
-        print(f"cell {c}: max|dV| = {err:.3e}", flush=True)
-        assert err <= TOL
-        assert mine == sorted(int(x) for x in st[g == 0])
+    assert (info["block_threads"], info["coef_mode"], info["reg_slots"], info["reg_len"]) == (128, 3, 2, 8)
+    assert info["n_packs"] == 65536
+    return m, cv0, samples, tr, V, sp
+
+
+def test_config5_full_size_light_cone(_c5_full):
+    """65536 cells x 1497 CVs, 800 steps (20 ms), in the benchmark's launch
+    shape for this network (reg_step_kernel<128, 2, 8>, one cell per
+    workgroup): sampled cells against the oracle through their light cone
+    (_c5_light_cone)."""
+    import multiprocessing as mp
+    import os
+    m, cv0, samples, tr, V, sp = _c5_full
+    with mp.get_context("spawn").Pool(max(1, min(16, os.cpu_count() or 1))) as pool:
+        for k, c in enumerate(samples):
+            st, rtr, rV = _c5_light_cone(m, c, 800, pool)
+            err = max(np.max(np.abs(tr[k] - rtr)), np.max(np.abs(V[cv0[c]:cv0[c + 1]] - rV)))
+            mine = sorted(int(x) for x in sp["step"][sp["gid"] == c])
+            print(f"cell {c}: max|dV| = {err:.3e}, spikes {mine}", flush=True)
+            assert err <= TOL
+            assert mine == sorted(st)
 
 
 def test_config4_full_size_adjoint_sampled_cells():
@@ -172,3 +247,75 @@ def test_config7_full_size_first_volley():
         print(f"cell {c}: {len(srcs)} sources, max|dV| = {err:.3e}, spikes {mine}", flush=True)
         assert err <= TOL
         assert mine == sorted(int(x) for x in st[g == 0])
+
+
+def _region0(m, c):
+    """Index of cell c's first region (its soma) in the flat region order."""
+    return int(c + np.sum(m["cell_n_branch"][:c]))
+
+
+def test_config5_subset_forward_adjoint():
+    """Forward + adjoint of the 1024-cell subset of the 65536-cell network
+    (1497 CVs per cell, network input as fixed seeded events, background
+    kept), 800 steps (20 ms), checkpoints every 100, in the benchmark's launch
+    shape for this network (128 threads, register layout, one cell per
+    workgroup).  Loss: mean squared distance of every soma trace from -65 mV.
+    Sampled cells' gradients against the oracle's discrete adjoint, and
+    central finite differences of the GPU forward on a few parameters."""
+    import torch
+
+    from paper_1901_07454_amd import arbmi
+    from tests.test_gpu_adjoint import model_theta
+    n, k = 800, 100
+    m = gen.config5_subset(n_steps=n)
+    th = model_theta(m)
+    sim = arbmi.Simulation(m, flags=arbmi.ARB_FLAG_GRADIENTS, block_threads=128, coef_mode=3, cells_per_pack=1)
+    info = sim.info
+    print("config 5 subset gradient sim", info, flush=True)
+    assert (info["block_threads"], info["coef_mode"], info["reg_slots"], info["reg_len"]) == (128, 3, 2, 8)
+    assert info["n_packs"] == 1024
+    state0 = sim.get_state()
+    C = info["n_cells"]
+
+    def forward(theta):
+        sim.set_state(state0)
+        sim.set_params(theta)
+        tr = torch.empty(C, n, dtype=torch.float64, device="cuda")
+        arbmi.arb_grad_forward(sim.h, n, k, tr)
+        return tr
+
+    tr = forward(th)
+    dl = 2.0 * (tr + 65.0) / tr.numel()
+    out = torch.empty(th.size, dtype=torch.float64, device="cuda")
+    arbmi.arb_grad_backward(sim.h, dl.contiguous(), out)
+    g = out.cpu().numpy().reshape(-1, 3)
+    trh, dlh = tr.cpu().numpy(), dl.cpu().numpy()
+    for c in (0, 511, 1023):
+        sub = gen.config5_subset(cells=[c], n_steps=n)
+        r0, r1 = _region0(m, c), _region0(m, c + 1)
+        s = oracle.Sim(sub)
+        s.set_params(th[r0:r1])
+        otr, og = s.adjoint(n, dlh[c][None, :])
+        err = np.max(np.abs(otr[0] - trh[c]))
+        den = np.maximum(np.abs(og), 1e-3 * np.max(np.abs(og), axis=0, keepdims=True))
+        rel = np.abs(g[r0:r1] - og) / den
+        print(f"cell {c}: max|dV| = {err:.3e}, max rel grad err {rel.max():.3e}", flush=True)
+        assert err <= TOL
+        assert rel.max() <= 1e-7
+    # central differences (relative step 1e-5) of the loss; a parameter of
+    # cell c moves only cell c's terms, so only those are summed (the other
+    # cells' terms would add nothing but rounding)
+    h = 1e-5
+    for (c, r, q) in ((0, 0, 0), (0, 0, 1), (0, 40, 2), (511, 1, 2)):
+        j = _region0(m, c) + r
+        vals = []
+        for sgn in (1, -1):
+            t = th.copy()
+            t[j, q] *= 1 + sgn * h
+            trp = forward(t)[c].cpu().numpy()
+            vals.append(float(np.sum((trp + 65.0) ** 2)) / (C * n))
+        fd = (vals[0] - vals[1]) / (2 * h * th[j, q])
+        rel = abs(g[j, q] - fd) / max(abs(fd), 1e-30)
+        print(f"FD cell {c} region {r} param {q}: adjoint {g[j, q]:.6e} fd {fd:.6e} rel {rel:.2e}", flush=True)
+        assert rel <= 1e-5
+    sim.close()

@@ -503,9 +503,11 @@ def test_arbitrary_step_splits_match_one_call():
 
 @pytest.mark.parametrize("target", [0, 1, 4097, 8191])
 def test_config2_full_size_light_cone(target, _full_ring):
-    """Full 8192-cell ring, 4000 steps, in the launch configuration the
-    benchmark uses; each sampled cell is checked against an oracle run of the
-    cells whose spikes can reach it within the run."""
+    """Full 8192-cell ring, 4000 steps, in the launch shape the benchmark's
+    autotuner picks on the MI355X (reg_step_kernel<64, 2, 8>: 64 threads, two
+    register slots of 8 CVs, one cell per one-wave workgroup); each sampled
+    cell is checked against an oracle run of the cells whose spikes can reach
+    it within the run."""
     trace, V, spikes, cv0 = _full_ring
     chain = gen.ring_light_cone(8192, target, 4000)
     sub = gen.config2(n_cells=8192, cells=chain)
@@ -526,6 +528,8 @@ def test_config2_full_size_light_cone(target, _full_ring):
 def _full_ring():
     m = gen.config2()
     cv0 = oracle.cell_cv_begin(m)
-    tr, V, sp, info = gpu_run(m, 4000, cv0[:-1])
+    tr, V, sp, info = gpu_run(m, 4000, cv0[:-1], block_threads=64, coef_mode=3, cells_per_pack=1)
     print("full ring info", info, flush=True)
+    assert (info["block_threads"], info["coef_mode"], info["reg_slots"], info["reg_len"]) == (64, 3, 2, 8)
+    assert info["n_packs"] == 8192 and info["syn_hbm"] == 0
     return tr, V, sp, cv0

@@ -435,6 +435,33 @@ def config5(n_cells: int = 65536, cells=None, n_in: int = 100, n_steps: int = 80
     return assemble([cell_c5(i, n_cells, n_in, t_ms) for i in ids], gids=list(ids), n_steps=n_steps)
 
 
+def cell_c5_fixed_inputs(i: int, n_cells: int = 65536, t_ms: float = 20.0, src_rate_hz: float = 5.0) -> CellDesc:
+    """Cell i of the 65536-cell network with its network input replaced by
+    fixed input events (the gradient workload treats input events as fixed):
+    each incoming connection delivers a seeded Poisson spike train of rate
+    src_rate_hz standing for its source, delayed by the connection's delay
+    and with its weight; the background input is unchanged."""
+    d = cell_c5(i, n_cells, t_ms=t_ms)
+    ss = np.random.SeedSequence(SEED_BASE + 5, spawn_key=(int(i), 1))
+    rng = np.random.Generator(np.random.PCG64(ss))
+    end = int(steps_of(t_ms))
+    for (_, ls, delay, w) in d.in_conn:
+        for st in _poisson_steps(rng, src_rate_hz, t_ms):
+            if int(st) + int(delay) < end:
+                d.ext.append((int(ls), int(st) + int(delay), float(w)))
+    d.in_conn = []
+    return d
+
+
+def config5_subset(n_cells: int = 1024, cells=None, n_steps: int = 800) -> dict:
+    """The first n_cells cells of the 65536-cell network as a gradient
+    workload: morphologies, synapses and background as in the network, the
+    network input as fixed seeded events (cell_c5_fixed_inputs)."""
+    ids = range(n_cells) if cells is None else cells
+    t_ms = n_steps * DT
+    return assemble([cell_c5_fixed_inputs(i, 65536, t_ms) for i in ids], gids=list(ids), n_steps=n_steps)
+
+
 def config6(n_cells: int = 8192, cells=None, kick_all: bool = True, n_steps: int = 4000,
             n_syn: int = 10000) -> dict:
     ids = range(n_cells) if cells is None else cells
