@@ -16,6 +16,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# A build of the same source to load instead (the sanitizer test's
+# instrumented build); unset, the in-tree library above.
+LIB_OVERRIDE = os.environ.get("ORACLE_LIB_OVERRIDE")
 
 _lib = None
 
@@ -32,9 +35,12 @@ def build(threads: bool = False) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        L = C.CDLL(LIB)
+        if LIB_OVERRIDE:
+            L = C.CDLL(LIB_OVERRIDE)
+        else:
+            if not os.path.exists(LIB):
+                build()
+            L = C.CDLL(LIB)
         P = C.c_void_p
         L.orc_build.restype = P
         L.orc_run.restype = C.c_int

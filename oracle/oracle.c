@@ -447,7 +447,7 @@ orc *orc_build(int32_t ncell, const int64_t *cell_branch_begin, const int32_t *c
         orc_event e = {ev_step[k], 1, ev_syn[k], 0xffffffffu, k, ev_w[k]};
         ev_push(s, e);
     }
-    qsort(s->ev, (size_t)s->nev, sizeof(orc_event), ev_cmp);
+    if (s->nev > 1) qsort(s->ev, (size_t)s->nev, sizeof(orc_event), ev_cmp);
 
     /* state (READING: V = v_init; gates at steady state; g = 0) */
     s->V = xcalloc(ncv, sizeof(double));
@@ -547,7 +547,7 @@ static void record_spike(orc *s, uint32_t gid, int64_t step, double t) {
  * spike step + delay (Sec. IV-A) */
 static void exchange(orc *s) {
     int64_t b = s->sp_epoch_begin, e = s->nsp;
-    qsort(s->sp + b, (size_t)(e - b), sizeof(orc_spike), sp_cmp);
+    if (e - b > 1) qsort(s->sp + b, (size_t)(e - b), sizeof(orc_spike), sp_cmp);
     int64_t before = s->nev;
     for (int64_t k = b; k < e; ++k) {
         uint32_t src = s->sp[k].gid;

@@ -48,19 +48,13 @@ struct Part {
 };
 
 std::vector<Part> state_parts(Sim* s) {
-    const Lowered& L = s->L;
-    const int64_t np = int64_t(L.packs.size());
-    const int64_t nhh = int64_t(L.hh_cv.size()), nsyn = int64_t(L.syn_global.size());
-    return {{s->d_V, L.n_slots * 8},   {s->d_hh_m, nhh * 8},  {s->d_hh_h, nhh * 8},
-            {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
-            {s->d_bk_off, s->d_bk_off ? np * (s->K + 1) * 4 : 0},
-            {s->d_bk_nxt, s->d_bk_nxt ? np * (s->K + 1) * 4 : 0},
-            {s->d_bk_q, np * s->bk_cap * 4}, {s->d_bk_w, np * s->bk_cap * 8},
-            {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
-            {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8},
-            {s->d_hist_cnt, int64_t(s->n_hist) * 4},
-            {s->d_hist_gid, int64_t(s->n_hist) * s->hist_cap * 4},
-            {s->d_hist_step, int64_t(s->n_hist) * s->hist_cap * 8}};
+    int64_t bytes[kStateParts];
+    void* ptr[kStateParts];
+    state_part_bytes(s->L, s->state_shape(), bytes);
+    s->state_part_ptrs(ptr);
+    std::vector<Part> out;
+    for (int k = 0; k < kStateParts; ++k) out.push_back({ptr[k], bytes[k]});
+    return out;
 }
 
 // The dynamic state into (save) or out of (load) a checkpoint, in one

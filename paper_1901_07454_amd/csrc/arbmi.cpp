@@ -362,6 +362,24 @@ int Sim::advance(int64_t n, const RecordArgs* rec) {
     return ARB_OK;
 }
 
+StateShape Sim::state_shape() const {
+    StateShape sh;
+    sh.K = K;
+    sh.bk_cap = bk_cap;
+    sh.sp_cap = sp_cap;
+    sh.n_hist = n_hist;
+    sh.hist_cap = hist_cap;
+    sh.net = d_bk_off != nullptr;
+    return sh;
+}
+
+void Sim::state_part_ptrs(void* ptr[kStateParts]) const {
+    void* const v[kStateParts] = {d_V,      d_hh_m,   d_hh_h,    d_hh_n,    d_syn_g,    d_pk_xcur,
+                                  d_bk_off, d_bk_nxt, d_bk_q,    d_bk_w,    d_ctr,      d_sp_gid,
+                                  d_sp_step, d_sp_t,  d_hist_cnt, d_hist_gid, d_hist_step};
+    for (int k = 0; k < kStateParts; ++k) ptr[k] = v[k];
+}
+
 int Sim::check_flags(bool& spikes_lost, bool& events_lost) {
     Counters c{};
     HIP_TRY(hipMemcpyAsync(&c, d_ctr, sizeof c, hipMemcpyDeviceToHost, st));
@@ -967,43 +985,29 @@ int arb_set_params(arb_sim s_, const double* theta, int64_t n) {
     return ARB_OK;
 }
 
-// blob: header, then V, hh m/h/n, syn g, ext cursors, the running epoch's
-// network events, counters, spike buffer, spike history
-struct StateHeader {
-    uint64_t magic;
-    int64_t step, n_slots, n_hh, n_syn, n_packs, n_bk, bk_cap, sp_cap, sp_user;
-};
-static const uint64_t kMagic = 0x41524233535441ull;
-
 int arb_get_state(arb_sim s_, void* blob, int64_t cap, int64_t* n_out) {
     Sim* s = static_cast<Sim*>(s_);
     if (!s || !n_out) return fail(ARB_EINVAL, "null argument");
     const Lowered& L = s->L;
-    const int64_t np = int64_t(L.packs.size()), nbk = np;
-    const int64_t nhh = int64_t(L.hh_cv.size()), nsyn = int64_t(L.syn_global.size());
-    struct Part { const void* d; int64_t bytes; };
-    const Part parts[] = {{s->d_V, L.n_slots * 8},   {s->d_hh_m, nhh * 8},  {s->d_hh_h, nhh * 8},
-                          {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
-                          {s->d_bk_off, s->d_bk_off ? np * (s->K + 1) * 4 : 0},
-                          {s->d_bk_nxt, s->d_bk_nxt ? np * (s->K + 1) * 4 : 0},
-                          {s->d_bk_q, np * s->bk_cap * 4}, {s->d_bk_w, np * s->bk_cap * 8},
-                          {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
-                          {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8},
-                          {s->d_hist_cnt, int64_t(s->n_hist) * 4},
-                          {s->d_hist_gid, int64_t(s->n_hist) * s->hist_cap * 4},
-                          {s->d_hist_step, int64_t(s->n_hist) * s->hist_cap * 8}};
+    const StateShape sh = s->state_shape();
+    int64_t bytes[kStateParts];
+    void* ptr[kStateParts];
+    state_part_bytes(L, sh, bytes);
+    s->state_part_ptrs(ptr);
     int64_t total = sizeof(StateHeader);
-    for (const Part& q : parts) total += q.bytes;
+    for (int k = 0; k < kStateParts; ++k) total += bytes[k];
     *n_out = total;
     if (!blob) return ARB_OK;
     if (cap < total) return fail(ARB_EOVERFLOW, "state blob capacity too small");
-    StateHeader h{kMagic, s->step, L.n_slots, nhh, nsyn, np, nbk, s->bk_cap, s->sp_cap, s->sp_user};
+    const int64_t np = int64_t(L.packs.size());
+    StateHeader h{kStateMagic, s->step, L.n_slots, int64_t(L.hh_cv.size()), int64_t(L.syn_global.size()),
+                  np, np, s->bk_cap, s->sp_cap, s->sp_user};
     char* out = static_cast<char*>(blob);
     std::memcpy(out, &h, sizeof h);
     int64_t at = sizeof h;
-    for (const Part& q : parts) {
-        if (q.bytes) HIP_TRY(hipMemcpyAsync(out + at, q.d, size_t(q.bytes), hipMemcpyDeviceToHost, s->st));
-        at += q.bytes;
+    for (int k = 0; k < kStateParts; ++k) {
+        if (bytes[k]) HIP_TRY(hipMemcpyAsync(out + at, ptr[k], size_t(bytes[k]), hipMemcpyDeviceToHost, s->st));
+        at += bytes[k];
     }
     HIP_TRY(hipStreamSynchronize(s->st));
     return ARB_OK;
@@ -1013,81 +1017,23 @@ int arb_set_state(arb_sim s_, const void* blob, int64_t n) {
     Sim* s = static_cast<Sim*>(s_);
     if (!s || !blob) return fail(ARB_EINVAL, "null argument");
     const Lowered& L = s->L;
-    if (n < int64_t(sizeof(StateHeader))) return fail(ARB_EINVAL, "state blob too small");
+    const StateShape sh = s->state_shape();
+    // every value a kernel indexes with must lie in range before it reaches
+    // the device (the blob is the caller's memory)
+    const std::string bad = check_state_blob(L, sh, blob, n);
+    if (!bad.empty()) return fail(ARB_EINVAL, bad);
     StateHeader h;
     std::memcpy(&h, blob, sizeof h);
-    const int64_t np = int64_t(L.packs.size()), nbk = np;
-    const int64_t nhh = int64_t(L.hh_cv.size()), nsyn = int64_t(L.syn_global.size());
-    if (h.magic != kMagic || h.n_slots != L.n_slots || h.n_hh != nhh || h.n_syn != nsyn || h.n_packs != np ||
-        h.n_bk != nbk || h.bk_cap != s->bk_cap || h.sp_cap != int64_t(s->sp_cap))
-        return fail(ARB_EINVAL, "state blob does not belong to this model");
-    struct Part { void* d; int64_t bytes; };
-    const Part parts[] = {{s->d_V, L.n_slots * 8},   {s->d_hh_m, nhh * 8},  {s->d_hh_h, nhh * 8},
-                          {s->d_hh_n, nhh * 8},      {s->d_syn_g, nsyn * 8}, {s->d_pk_xcur, np * 8},
-                          {s->d_bk_off, s->d_bk_off ? np * (s->K + 1) * 4 : 0},
-                          {s->d_bk_nxt, s->d_bk_nxt ? np * (s->K + 1) * 4 : 0},
-                          {s->d_bk_q, np * s->bk_cap * 4}, {s->d_bk_w, np * s->bk_cap * 8},
-                          {s->d_ctr, int64_t(sizeof(Counters))},          {s->d_sp_gid, int64_t(s->sp_cap) * 4},
-                          {s->d_sp_step, int64_t(s->sp_cap) * 8},         {s->d_sp_t, int64_t(s->sp_cap) * 8},
-                          {s->d_hist_cnt, int64_t(s->n_hist) * 4},
-                          {s->d_hist_gid, int64_t(s->n_hist) * s->hist_cap * 4},
-                          {s->d_hist_step, int64_t(s->n_hist) * s->hist_cap * 8}};
-    int64_t total = sizeof(StateHeader);
-    for (const Part& q : parts) total += q.bytes;
-    if (n < total) return fail(ARB_EINVAL, "state blob truncated");
+    int64_t bytes[kStateParts];
+    void* ptr[kStateParts];
+    state_part_bytes(L, sh, bytes);
+    s->state_part_ptrs(ptr);
     const char* in = static_cast<const char*>(blob);
-    {
-        // every value a kernel indexes with must lie in range before it
-        // reaches the device (the blob is the caller's memory)
-        const char* at_part[sizeof parts / sizeof parts[0]];
-        int64_t off = sizeof h;
-        for (size_t k = 0; k < sizeof parts / sizeof parts[0]; ++k) {
-            at_part[k] = in + off;
-            off += parts[k].bytes;
-        }
-        auto rd32 = [](const char* b, int64_t i) { uint32_t v; std::memcpy(&v, b + 4 * i, 4); return v; };
-        auto rd64 = [](const char* b, int64_t i) { int64_t v; std::memcpy(&v, b + 8 * i, 8); return v; };
-        Counters c;
-        std::memcpy(&c, at_part[10], sizeof c);
-        const uint32_t have = std::min(c.sp_count, s->sp_cap);
-        if (h.step < 0 || h.step >= (int64_t(1) << 31) || h.sp_user < 0 || h.sp_user > int64_t(have) ||
-            c.sp_exch > have)
-            return fail(ARB_EINVAL, "state blob: step or spike counters out of range");
-        for (int64_t p = 0; p < np; ++p) {
-            const int64_t x = rd64(at_part[5], p);
-            if (x < L.packs[p].xe0 || x > L.packs[p].xe1) return fail(ARB_EINVAL, "state blob: event cursor out of range");
-        }
-        for (uint32_t i = 0; i < have; ++i)
-            if (rd32(at_part[11], i) >= uint32_t(L.n_cells)) return fail(ARB_EINVAL, "state blob: spike gid out of range");
-        if (s->d_bk_off) {
-            const int64_t K = s->K;
-            for (int64_t p = 0; p < np; ++p) {
-                uint32_t prev = 0;
-                for (int64_t b = 0; b <= K; ++b) {
-                    const uint32_t o = rd32(at_part[6], p * (K + 1) + b), x = rd32(at_part[7], p * (K + 1) + b);
-                    if (o < prev || o > uint32_t(s->bk_cap) || x > uint32_t(K))
-                        return fail(ARB_EINVAL, "state blob: event bucket offsets out of range");
-                    prev = o;
-                }
-                for (uint32_t i = 0; i < prev; ++i) {
-                    const uint32_t q = rd32(at_part[8], p * int64_t(s->bk_cap) + i);
-                    if (q >= uint32_t(L.packs[p].nsyn)) return fail(ARB_EINVAL, "state blob: event synapse out of range");
-                }
-            }
-            for (int64_t k = 0; k < s->n_hist; ++k) {
-                const uint32_t m = rd32(at_part[14], k);
-                if (m > s->hist_cap) return fail(ARB_EINVAL, "state blob: spike history count out of range");
-                for (uint32_t i = 0; i < m; ++i)
-                    if (rd32(at_part[15], k * int64_t(s->hist_cap) + i) >= uint32_t(L.n_cells))
-                        return fail(ARB_EINVAL, "state blob: spike history gid out of range");
-            }
-        }
-    }
     int64_t at = sizeof h;
     HIP_TRY(hipStreamSynchronize(s->st));
-    for (const Part& q : parts) {
-        if (q.bytes) HIP_TRY(hipMemcpyAsync(q.d, in + at, size_t(q.bytes), hipMemcpyHostToDevice, s->st));
-        at += q.bytes;
+    for (int k = 0; k < kStateParts; ++k) {
+        if (bytes[k]) HIP_TRY(hipMemcpyAsync(ptr[k], in + at, size_t(bytes[k]), hipMemcpyHostToDevice, s->st));
+        at += bytes[k];
     }
     HIP_TRY(hipStreamSynchronize(s->st));
     s->step = h.step;

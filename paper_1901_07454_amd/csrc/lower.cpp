@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <map>
 #include <numeric>
 #include <sstream>
@@ -895,6 +896,79 @@ void recompute_coefficients(Lowered& L) {
         L.hh_gna[q] = gna[L.hh_cv[q]];
         L.hh_gk[q] = gk[L.hh_cv[q]];
     }
+}
+
+void state_part_bytes(const Lowered& L, const StateShape& sh, int64_t b[kStateParts]) {
+    const int64_t np = int64_t(L.packs.size());
+    const int64_t nhh = int64_t(L.hh_cv.size()), nsyn = int64_t(L.syn_global.size());
+    const int64_t nbk = sh.net ? np * (int64_t(sh.K) + 1) * 4 : 0;
+    const int64_t v[kStateParts] = {L.n_slots * 8, nhh * 8, nhh * 8, nhh * 8, nsyn * 8, np * 8, nbk, nbk,
+                                    np * sh.bk_cap * 4, np * sh.bk_cap * 8, int64_t(sizeof(Counters)),
+                                    int64_t(sh.sp_cap) * 4, int64_t(sh.sp_cap) * 8, int64_t(sh.sp_cap) * 8,
+                                    int64_t(sh.n_hist) * 4, int64_t(sh.n_hist) * sh.hist_cap * 4,
+                                    int64_t(sh.n_hist) * sh.hist_cap * 8};
+    for (int k = 0; k < kStateParts; ++k) b[k] = v[k];
+}
+
+std::string check_state_blob(const Lowered& L, const StateShape& sh, const void* blob, int64_t n) {
+    if (!blob) return "null blob";
+    if (n < int64_t(sizeof(StateHeader))) return "state blob too small";
+    StateHeader h;
+    std::memcpy(&h, blob, sizeof h);
+    const int64_t np = int64_t(L.packs.size());
+    const int64_t nhh = int64_t(L.hh_cv.size()), nsyn = int64_t(L.syn_global.size());
+    if (h.magic != kStateMagic || h.n_slots != L.n_slots || h.n_hh != nhh || h.n_syn != nsyn || h.n_packs != np ||
+        h.n_bk != np || h.bk_cap != sh.bk_cap || h.sp_cap != int64_t(sh.sp_cap))
+        return "state blob does not belong to this model";
+    int64_t bytes[kStateParts];
+    state_part_bytes(L, sh, bytes);
+    int64_t total = sizeof(StateHeader);
+    for (int k = 0; k < kStateParts; ++k) total += bytes[k];
+    if (n < total) return "state blob truncated";
+    const char* in = static_cast<const char*>(blob);
+    const char* part[kStateParts];
+    int64_t off = sizeof h;
+    for (int k = 0; k < kStateParts; ++k) {
+        part[k] = in + off;
+        off += bytes[k];
+    }
+    auto rd32 = [](const char* b, int64_t i) { uint32_t v; std::memcpy(&v, b + 4 * i, 4); return v; };
+    auto rd64 = [](const char* b, int64_t i) { int64_t v; std::memcpy(&v, b + 8 * i, 8); return v; };
+    Counters c;
+    std::memcpy(&c, part[10], sizeof c);
+    const uint32_t have = std::min(c.sp_count, sh.sp_cap);
+    if (h.step < 0 || h.step >= (int64_t(1) << 31) || h.sp_user < 0 || h.sp_user > int64_t(have) || c.sp_exch > have)
+        return "state blob: step or spike counters out of range";
+    for (int64_t p = 0; p < np; ++p) {
+        const int64_t x = rd64(part[5], p);
+        if (x < L.packs[p].xe0 || x > L.packs[p].xe1) return "state blob: event cursor out of range";
+    }
+    for (uint32_t i = 0; i < have; ++i)
+        if (rd32(part[11], i) >= uint32_t(L.n_cells)) return "state blob: spike gid out of range";
+    if (sh.net) {
+        const int64_t K = sh.K;
+        for (int64_t p = 0; p < np; ++p) {
+            uint32_t prev = 0;
+            for (int64_t b = 0; b <= K; ++b) {
+                const uint32_t o = rd32(part[6], p * (K + 1) + b), x = rd32(part[7], p * (K + 1) + b);
+                if (o < prev || o > uint32_t(sh.bk_cap) || x > uint32_t(K))
+                    return "state blob: event bucket offsets out of range";
+                prev = o;
+            }
+            for (uint32_t i = 0; i < prev; ++i) {
+                const uint32_t q = rd32(part[8], p * int64_t(sh.bk_cap) + i);
+                if (q >= uint32_t(L.packs[p].nsyn)) return "state blob: event synapse out of range";
+            }
+        }
+        for (int64_t k = 0; k < sh.n_hist; ++k) {
+            const uint32_t m = rd32(part[14], k);
+            if (m > sh.hist_cap) return "state blob: spike history count out of range";
+            for (uint32_t i = 0; i < m; ++i)
+                if (rd32(part[15], k * int64_t(sh.hist_cap) + i) >= uint32_t(L.n_cells))
+                    return "state blob: spike history gid out of range";
+        }
+    }
+    return "";
 }
 
 }  // namespace arbmi

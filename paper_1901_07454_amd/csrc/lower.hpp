@@ -101,6 +101,33 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
 // Check the packed layout's invariants; empty string if all hold.
 std::string verify_layout(const Lowered& lw);
 
+// The dynamic state of a sim as a host blob (arb_get_state / arb_set_state):
+// a header, then kStateParts parts in this order: V, hh m, h, n, synapse g,
+// external-event cursors, the running epoch's network events (offsets,
+// next-step table, synapses, weights), counters, spike buffer (gid, step,
+// time), spike history (counts, gids, steps).
+struct StateShape {
+    int32_t K = 1;            // epoch steps
+    int32_t bk_cap = 0;       // network events per pack and epoch
+    uint32_t sp_cap = 0;      // spike buffer
+    int32_t n_hist = 1;       // history epochs
+    uint32_t hist_cap = 0;    // spikes per history epoch
+    bool net = false;         // the event tables exist
+};
+struct StateHeader {
+    uint64_t magic;
+    int64_t step, n_slots, n_hh, n_syn, n_packs, n_bk, bk_cap, sp_cap, sp_user;
+};
+constexpr uint64_t kStateMagic = 0x41524233535441ull;
+constexpr int kStateParts = 17;
+// Bytes of each part.
+void state_part_bytes(const Lowered& L, const StateShape& sh, int64_t bytes[kStateParts]);
+// Every check arb_set_state makes before any byte reaches the device: the
+// header names this model, and every value a kernel indexes with (step and
+// spike counters, event cursors, spike gids, bucket offsets and synapses,
+// history counts and gids) lies in range.  "" if the blob is acceptable.
+std::string check_state_blob(const Lowered& L, const StateShape& sh, const void* blob, int64_t n);
+
 // Recompute alpha, beta, hh_gna, hh_gk from lw.regions (after a parameter change).
 void recompute_coefficients(Lowered& lw);
 

@@ -135,6 +135,9 @@ struct Sim : arb_sim_ {
     int launch_collect(int64_t epoch, const int64_t* epoch_ptr);  // the epoch's spikes into the history
     int launch_classes(const StepArgs& a);
     int check_flags(bool& spikes_lost, bool& events_lost);
+    // the dynamic state's parts (state_part_bytes order) and their device addresses
+    StateShape state_shape() const;
+    void state_part_ptrs(void* ptr[kStateParts]) const;
 };
 
 struct ModelView {
