@@ -171,8 +171,10 @@ typedef struct {
     int64_t bytes_per_step;   /* algorithmic HBM bytes one step must move (SoA model) */
     int32_t reg_slots;        /* coef_mode 3: branches per thread held in registers */
     int32_t reg_len;          /* coef_mode 3: CVs per branch held in registers */
-    int32_t syn_hbm;          /* coef_mode 3: 1 if some workgroup streams its synapse state from HBM
-                                 each step (too many synapses for LDS), else 0 */
+    int32_t syn_hbm;          /* coef_mode 3: 1 if some workgroup keeps state in HBM: streams its
+                                 synapse state every step (too many synapses for LDS), or reads
+                                 its hh conductances from HBM (a cell too large for LDS
+                                 otherwise); else 0 */
     int32_t reserved;
 } arb_info;
 

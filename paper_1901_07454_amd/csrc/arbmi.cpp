@@ -172,6 +172,8 @@ int Sim::launch_classes(const StepArgs& a0) {
         a.pack0 = classes[c].pack0;
         LaunchCfg lc = cfg;
         lc.lds_bytes = classes[c].lds;
+        lc.syn_hbm = classes[c].hbm;
+        if (cfg.coef_mode == 3) lc.reg_slots = classes[c].slots;
         hipStream_t s_c = (c == 0) ? st : aux[c - 1];
         HIP_TRY(launch_step(a, lc, classes[c].npack, s_c));
     }
@@ -580,7 +582,7 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
     int64_t lds = 0;
     for (const PackDesc& D : s->L.packs) {
         lds = std::max(lds, pack_lds_bytes(D, s->L.coef_mode));
-        if (s->L.coef_mode == 3 && D.syn_global) s->cfg.syn_hbm = 1;
+        if (s->L.coef_mode == 3 && (D.syn_global || D.hh_global)) s->cfg.syn_hbm = 1;
     }
     if (s->cfg.rec && s->cfg.syn_hbm) {  // the lowering keeps gradient sims' synapses in LDS
         delete s;
@@ -593,38 +595,59 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
         return ARB_EINVAL;
     }
     s->cfg.lds_bytes = int(std::max<int64_t>(lds, 8));
-    // classes by workgroups per CU the LDS allows: 1, 2, 3, 4 or more.  Packs
-    // come out of the packer largest first, so each class is a contiguous
-    // range; a class's LDS is its largest pack's.
+    // Classes: runs of packs that need the same kernel variant (register
+    // slots in use, state in HBM) and allow the same number of workgroups
+    // per CU by LDS (1, 2, 3, 4 or more).  The lowering orders the packs so
+    // that each class is a contiguous range; a class's LDS is its largest
+    // pack's, and it runs as its own launch.
     {
+        const Lowered& L = s->L;
         const int64_t lim = d.lds_max - 256;
         auto cat = [&](int64_t b) { return b > lim / 2 ? 1 : b > lim / 3 ? 2 : b > lim / 4 ? 3 : 4; };
-        const int32_t np = int32_t(s->L.packs.size());
+        const int32_t np = int32_t(L.packs.size());
+        auto slots_of = [&](int32_t k) {
+            int used = 1;
+            for (int32_t r = 0; r < L.packs[k].nrd; ++r) used = std::max(used, L.rounds[L.packs[k].rd0 + r].j + 1);
+            return L.coef_mode == 3 ? used : 0;
+        };
+        auto hbm_of = [&](int32_t k) {
+            return (L.coef_mode == 3 && (L.packs[k].syn_global || L.packs[k].hh_global)) ? 1 : 0;
+        };
+        struct Key {
+            int slots, hbm, cat;
+            bool operator==(const Key& o) const { return slots == o.slots && hbm == o.hbm && cat == o.cat; }
+        };
+        auto key_of = [&](int32_t k) {
+            return Key{slots_of(k), hbm_of(k), cat(pack_lds_bytes(L.packs[k], L.coef_mode))};
+        };
         int32_t start = 0;
-        int cur = np ? cat(pack_lds_bytes(s->L.packs[0], s->L.coef_mode)) : 4;
+        Key cur = np ? key_of(0) : Key{0, 0, 0};
         int64_t mx = 0;
         for (int32_t k = 0; k <= np; ++k) {
-            const int64_t b = (k < np) ? pack_lds_bytes(s->L.packs[k], s->L.coef_mode) : 0;
-            const int c = (k < np) ? std::max(cur, cat(b)) : 99;
-            if (c != cur) {
-                s->classes.push_back({start, k - start, int(std::max<int64_t>(mx, 8))});
+            const bool end_run = (k == np) || !(key_of(k) == cur);
+            if (end_run && k > start) {
+                s->classes.push_back({start, k - start, int(std::max<int64_t>(mx, 8)), cur.hbm, cur.slots});
                 start = k;
                 mx = 0;
-                cur = c;
+                if (k < np) cur = key_of(k);
             }
-            mx = std::max(mx, b);
+            if (k < np) mx = std::max(mx, pack_lds_bytes(L.packs[k], L.coef_mode));
         }
         // a class of a few packs is not worth a stream of its own: merge it
-        // into the previous (larger-LDS) class
+        // into the previous class if that uses as many register slots (the
+        // variant that can keep state in HBM also runs packs that keep none)
         std::vector<Sim::Class> merged;
         for (const Sim::Class& c : s->classes) {
-            if (!merged.empty() && c.npack < 2 * d.n_cu) {
+            if (!merged.empty() && c.npack < 2 * d.n_cu && merged.back().slots == c.slots) {
                 merged.back().npack += c.npack;
+                merged.back().lds = std::max(merged.back().lds, c.lds);
+                merged.back().hbm |= c.hbm;
                 continue;
             }
             merged.push_back(c);
         }
         s->classes = merged;
+        if (s->classes.size() == 1 && s->L.coef_mode == 3 && !s->cfg.rec) s->cfg.reg_slots = s->classes[0].slots;
         if (s->classes.size() > 1) {
             for (size_t c = 1; c < s->classes.size(); ++c) {
                 hipStream_t x;
@@ -795,7 +818,7 @@ int arb_plan_layout(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     I.reg_len = L.coef_mode == 3 ? L.reg_len : 0;
     I.syn_hbm = 0;
     for (const PackDesc& D : L.packs)
-        if (L.coef_mode == 3 && D.syn_global) I.syn_hbm = 1;
+        if (L.coef_mode == 3 && (D.syn_global || D.hh_global)) I.syn_hbm = 1;
     *info = I;
     return ARB_OK;
 }

@@ -48,7 +48,8 @@ struct PackDesc {
     int32_t binary;  // 1 if no task of the pack has more than two children
     int32_t syn_global;  // register-resident layout: synapse state stays in HBM
     int32_t syn_uniform; // all synapses of the pack share e_syn and decay (below)
-    int32_t unused;
+    int32_t hh_global;   // register-resident layout: hh conductances and the nonlinear CVs'
+                         // beta stay in HBM (a cell too large for LDS otherwise)
     int64_t xe0, xe1; // external events [xe0, xe1), sorted by (step, syn, input order)
     double syn_e, syn_decay;  // the shared values when syn_uniform
 };
@@ -72,7 +73,9 @@ struct PackDesc {
 constexpr int kSpreadHH = 20;
 
 // A register-resident pack whose synapses would take more LDS than this
-// keeps their state in HBM and streams it every step.
+// keeps their state in HBM and streams it every step.  A pack of one cell
+// too large for LDS otherwise reads its hh conductances and the step-invariant
+// right-hand side of its nonlinear CVs from HBM each step (hh_global).
 constexpr int64_t kSynLdsMax = 16384;
 
 // Incoming connections a pack of several cells may have: one workgroup
@@ -93,8 +96,8 @@ constexpr int vr_block_doubles(int nslot, int spare) {
 inline int64_t pack_lds_bytes(const PackDesc& D, int coef_mode) {
     if (coef_mode == 3) {
         const int64_t dbl = vr_block_doubles(D.nslot, D.spare) + (D.syn_global ? 0 : 3 * int64_t(D.nsyn)) +
-                            5 * int64_t(D.nhh) +
-                            int64_t(D.nnl) + (D.binary ? 3 : 2) * (int64_t(D.ntk) + 2);
+                            (D.hh_global ? 3 : 5) * int64_t(D.nhh) +
+                            (D.hh_global ? 0 : int64_t(D.nnl)) + (D.binary ? 3 : 2) * (int64_t(D.ntk) + 2);
         return 8 * dbl + 16 * int64_t(D.nnl) + (D.binary ? 0 : 4 * int64_t(D.nch)) + 4 * int64_t(D.nhh);
     }
     const bool cl = coef_mode == 1;

@@ -69,6 +69,7 @@ struct PackPlan {
     std::vector<int32_t> cells;
     int64_t nslot = 0;
     int64_t nsyn = 0, nhh = 0, nbr = 0, nic = 0, nin = 0;
+    bool hhg = false;  // hh conductances and nonlinear right-hand sides in HBM
 };
 
 }  // namespace
@@ -343,7 +344,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         for (int32_t b = 0; b < geo[c].nseg(); ++b) nch[geo[c].sparent[b] + 1]++;
         for (int32_t v : nch) max_children[c] = std::max(max_children[c], v);
     }
-    struct Shape { int64_t nslot = 0, nrd = 0; bool ok = true, has_pad = false; };
+    struct Shape { int64_t nslot = 0, nrd = 0; bool ok = true, has_pad = false; int slots = 1; };
     auto plan_shape = [&](const std::vector<int32_t>& cs) -> Shape {
         std::vector<RoundPlan> rps;
         Shape sh;
@@ -351,6 +352,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         for (const RoundPlan& rp : rps) {
             sh.nslot += int64_t(S > 0 ? opt.reg_len : rp.len) * int64_t(rp.items.size());
             for (const Item& it : rp.items) sh.has_pad = sh.has_pad || (S > 0 && it.len < opt.reg_len);
+            sh.slots = std::max(sh.slots, rp.j + 1);
         }
         sh.nrd = int64_t(rps.size());
         return sh;
@@ -376,6 +378,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         int64_t nnl = 0;
         for (int32_t c : pp.cells) nnl += nnl_cell[c];
         D.nnl = int32_t(nnl);
+        D.hh_global = pp.hhg ? 1 : 0;
         if (opt.grads && mode == 3) {
             // the adjoint reads the synapses' recorded conductances from LDS
             if (D.syn_global) return int64_t(1) << 40;
@@ -403,7 +406,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             bool fits = cur.cells.empty() || (int64_t(trial.cells.size()) <= max_cells && trial.nin <= kPackInMax);
             if (fits && !cur.cells.empty()) fits = exact_lds(trial, coef_mode) <= opt.lds_budget;
             if (!fits) {
-                plans.push_back(cur);
+                if (!cur.cells.empty()) plans.push_back(cur);
                 cur = PackPlan();
                 cur.cells.push_back(c);
                 cur.nsyn = nsyn_cell[c];
@@ -414,8 +417,39 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             } else {
                 cur = trial;
             }
+            // a cell too large for the register layout's LDS alone keeps its
+            // hh conductances and nonlinear right-hand sides in HBM
+            if (cur.cells.size() == 1 && S > 0 && !opt.grads && coef_mode == 3 &&
+                exact_lds(cur, coef_mode) > opt.lds_hard_max) {
+                cur.hhg = true;
+                if (exact_lds(cur, coef_mode) > opt.lds_hard_max) cur.hhg = false;
+            }
         }
         if (!cur.cells.empty()) plans.push_back(cur);
+    }
+    if (S > 1) {
+        // Packs that need the same kernel variant (register slots in use,
+        // state in HBM) next to each other, most slots first, each group
+        // largest LDS first: the host launches each run of them as one class
+        // with the registers and LDS it needs.
+        struct Key { int slots, hbm; int64_t lds; };
+        std::vector<Key> key(plans.size());
+        for (size_t k = 0; k < plans.size(); ++k) {
+            const Shape sh = plan_shape(plans[k].cells);
+            key[k] = Key{sh.slots, (plans[k].hhg || 24 * plans[k].nsyn > kSynLdsMax) ? 1 : 0,
+                         exact_lds(plans[k], coef_mode)};
+        }
+        std::vector<size_t> idx(plans.size());
+        std::iota(idx.begin(), idx.end(), size_t(0));
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+            if (key[a].slots != key[b].slots) return key[a].slots > key[b].slots;
+            if (key[a].hbm != key[b].hbm) return key[a].hbm > key[b].hbm;
+            return key[a].lds > key[b].lds;
+        });
+        std::vector<PackPlan> sorted;
+        sorted.reserve(plans.size());
+        for (size_t k : idx) sorted.push_back(std::move(plans[k]));
+        plans.swap(sorted);
     }
     for (const PackPlan& pp : plans)
         if (S > 0 && !plan_shape(pp.cells).ok) {
@@ -481,6 +515,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         D.binary = 1;
         for (int32_t c : pp.cells) D.binary = D.binary && max_children[c] <= 2;
         D.syn_global = (S > 0 && 24 * pp.nsyn > kSynLdsMax) ? 1 : 0;
+        D.hh_global = pp.hhg ? 1 : 0;
         // the register-resident kernel's empty slots write to a slot no CV
         // uses: the first pad row if there is one, else one past the end
         D.spare = D.nslot;

@@ -45,8 +45,9 @@ using namespace reg;
 
 // Waves per SIMD the registers allow without spilling (built without
 // machine loop-invariant code motion): three for one slot of 8 CVs, two for
-// 16 CVs in all, one otherwise.  G: some pack of the launch keeps its
-// synapse state in HBM (without it, that path is compiled out).  REC: the
+// 16 CVs in all, one otherwise.  G: some pack of the launch keeps state in
+// HBM, its synapses' or its hh conductances' (without it, those paths are
+// compiled out).  REC: the
 // sim is built for gradients; the steps record their states when a.rec_V
 // is set (the adjoint's recompute), and the gradient forward runs the same
 // code with it unset, so both produce the same trajectory bit for bit (one
@@ -74,15 +75,18 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
     const double* g_se = a.syn_e + pk.syn0;
     const double* g_sdec = a.syn_decay + pk.syn0;
     double* sgv = syn_hbm ? g_g : sg;                    // where events add to g
+    // hh conductances and the nonlinear CVs' beta in LDS, or in HBM for a
+    // pack too large for LDS otherwise
+    const bool hh_hbm = G && pk.hh_global;
     double* sh = sm + pk.nhh;
     double* sn = sh + pk.nhh;
     double* s_gna = sn + pk.nhh;
-    double* s_gk = s_gna + pk.nhh;
-    double* s_nlb = s_gk + pk.nhh;                             // beta of each nonlinear CV
+    double* s_gk = s_gna + (hh_hbm ? 0 : pk.nhh);
+    double* s_nlb = s_gk + (hh_hbm ? 0 : pk.nhh);              // beta of each nonlinear CV
     // per task, two spare entries (zero, discard) each: contribution, then
     // distal V; contribution with no children, then distal V for a grounded
     // parent; F_0 Q_0 (binary packs)
-    double* sC = s_nlb + pk.nnl;
+    double* sC = s_nlb + (hh_hbm ? 0 : pk.nnl);
     double* sX = sC;
     double* sF = sC + (pk.ntk + 2);
     double* sY = sF;
@@ -116,13 +120,15 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
         sm[i] = a.hh_m[pk.hh0 + i];
         sh[i] = a.hh_h[pk.hh0 + i];
         sn[i] = a.hh_n[pk.hh0 + i];
-        s_gna[i] = a.hh_gna[pk.hh0 + i];
-        s_gk[i] = a.hh_gk[pk.hh0 + i];
+        if (!hh_hbm) {
+            s_gna[i] = a.hh_gna[pk.hh0 + i];
+            s_gk[i] = a.hh_gk[pk.hh0 + i];
+        }
     }
     for (int i = tid; i < pk.nnl; i += T) {
         const NlDesc d = a.nl[pk.nl0 + i];
         s_nl[i] = d;
-        s_nlb[i] = a.beta[pk.slot0 + d.slot];
+        if (!hh_hbm) s_nlb[i] = a.beta[pk.slot0 + d.slot];
         if (d.hh >= 0) s_hhs[d.hh] = vix(d.slot);
     }
     if (!pk.binary)
@@ -242,12 +248,23 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
         for (int j = tid; j < pk.nnl; j += T) {
             const NlDesc d = s_nl[j];
             const double v = sV[vix(d.slot)];
-            double I = 0.0;
-            if (d.hh >= 0) {
-                const int q = d.hh;
-                const double m = sm[q], h = sh[q], x = sn[q];
-                I += s_gna[q] * (m * m * m * h) * (v - kENa);
-                I += s_gk[q] * (x * x * x * x) * (v - kEK);
+            double I = 0.0, bnl;
+            if (hh_hbm) {
+                bnl = a.beta[pk.slot0 + d.slot];
+                if (d.hh >= 0) {
+                    const int q = d.hh;
+                    const double m = sm[q], h = sh[q], x = sn[q];
+                    I += a.hh_gna[pk.hh0 + q] * (m * m * m * h) * (v - kENa);
+                    I += a.hh_gk[pk.hh0 + q] * (x * x * x * x) * (v - kEK);
+                }
+            } else {
+                bnl = s_nlb[j];
+                if (d.hh >= 0) {
+                    const int q = d.hh;
+                    const double m = sm[q], h = sh[q], x = sn[q];
+                    I += s_gna[q] * (m * m * m * h) * (v - kENa);
+                    I += s_gk[q] * (x * x * x * x) * (v - kEK);
+                }
             }
             if (!syn_hbm) {
                 // the decay of phase E is applied here too: g is not read
@@ -297,7 +314,7 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
                     }
                 }
             }
-            sV[vix(d.slot) + kRoff] = s_nlb[j] - I;
+            sV[vix(d.slot) + kRoff] = bnl - I;
         }
         if (soma >= 0) vold = sV[soma];
         if (pk.nic > 0) {

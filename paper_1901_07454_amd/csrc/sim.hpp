@@ -47,6 +47,8 @@ struct Sim : arb_sim_ {
     // kernels, each with the LDS its largest pack needs
     struct Class {
         int32_t pack0, npack, lds;
+        int hbm;    // some pack of the class keeps state in HBM (the kernel variant that can)
+        int slots;  // register slots its packs use (register layout), else 0
     };
     std::vector<Class> classes;
     std::vector<hipStream_t> aux;       // one per class after the first

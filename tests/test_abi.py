@@ -219,6 +219,21 @@ def test_plan_layout_invariants_uneven_and_networks(mode, T):
         assert info["lds_bytes"] <= 160 * 1024 - 256
 
 
+def test_plan_register_layout_holds_the_largest_uneven_cells():
+    """The 4096 uneven cells in the register layout at 256 threads x 3 slots:
+    the largest (up to 4990 CVs) exceed LDS with their hh conductances there,
+    so their packs keep those in HBM (reported as syn_hbm), and every pack
+    fits the device's LDS."""
+    m = gen.config3(n_steps=10)
+    info = _plan(m, coef_mode=3, block_threads=256)
+    assert info["coef_mode"] == 3 and info["reg_slots"] == 3 and info["reg_len"] == 8
+    assert info["syn_hbm"] == 1
+    assert info["lds_bytes"] <= 160 * 1024 - 256
+    assert info["n_cv"] == int(gen.n_cvs(m).sum())
+    small = gen.config3(cells=[0, 1, 2], n_steps=10)
+    assert _plan(small, coef_mode=3, block_threads=256)["syn_hbm"] == 0
+
+
 def test_plan_cuts_long_branches_into_register_segments():
     m = gen.config1()  # 32-CV branches do not fit 16 registers
     assert _plan(m)["coef_mode"] == 2  # the default keeps the streamed layout for them

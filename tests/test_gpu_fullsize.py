@@ -45,6 +45,31 @@ def test_config3_full_size_sampled_cells():
         assert mine == sorted(int(x) for x in st)
 
 
+def test_config3_register_layout_largest_and_smallest_cells():
+    """The register layout at 256 threads x 3 slots on the uneven workload's
+    four largest cells (their packs read hh conductances from HBM) and four
+    small ones, 2000 steps, each cell against the oracle."""
+    from paper_1901_07454_amd import arbmi
+    ncv = np.array([1 + gen.cell_c3(i, 1.0).n_cv.sum() for i in range(4096)])
+    order = np.argsort(-ncv)
+    cells = sorted([int(c) for c in order[:4]] + [int(c) for c in order[-2:]] + [0, 2047])
+    n = 2000
+    m = gen.config3(cells=cells, n_steps=n)
+    cv0 = oracle.cell_cv_begin(m)
+    tr, V, sp, info = _gpu(m, n, cv0[:-1], block_threads=256, coef_mode=3)
+    print("info", info, flush=True)
+    assert info["coef_mode"] == 3 and info["syn_hbm"] == 1
+    for k, c in enumerate(cells):
+        s = oracle.Sim(gen.config3(cells=[c], n_steps=n))
+        rtr = s.run(n, probes=[0])[0]
+        err = max(np.max(np.abs(tr[k] - rtr)), np.max(np.abs(V[cv0[k]:cv0[k + 1]] - s.state()["V"])))
+        g, st, _ = s.spikes()
+        mine = sorted(int(x) for x in sp["step"][sp["gid"] == k])
+        print(f"cell {c} ({ncv[c]} CVs): max|dV| = {err:.3e}, spikes {len(mine)}", flush=True)
+        assert err <= TOL
+        assert mine == sorted(int(x) for x in st)
+
+
 def _c5_cell_alone(args):
     """Oracle run of cell i of the 65536-cell network alone for n steps, its
     network input replaced by the events its sources' given spikes deliver
