@@ -298,6 +298,7 @@ def main():
     ap.add_argument("--epoch-steps", type=int, default=0, help="0 = the minimum delay (or 1000 without a network)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch every epoch's kernels directly")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -314,7 +315,8 @@ def main():
     m, desc = make_model(args.config, args.cells)
     log(f"model built in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    flags = arbmi.ARB_FLAG_TIME_KERNELS
+    # whole epochs (exchange and step kernels) replay from a captured HIP graph
+    flags = arbmi.ARB_FLAG_TIME_KERNELS | (0 if args.no_graph else arbmi.ARB_FLAG_GRAPH)
     if not (args.block_threads or args.coef_mode or args.cells_per_pack):
         flags |= arbmi.ARB_FLAG_AUTOTUNE
     sim = arbmi.Simulation(m, flags=flags, block_threads=args.block_threads, epoch_steps=args.epoch_steps,
@@ -401,7 +403,8 @@ def main():
         "config": {"workload": f"config {args.config}: {desc}", "cells": info["n_cells"], "cvs": n_cv,
                    "dt_ms": float(m["dt"]), "epoch_steps": K,
                    "block_threads": info["block_threads"], "coef_mode": info["coef_mode"],
-                   "packs": info["n_packs"], "lds_bytes": info["lds_bytes"], "spikes": int(len(spikes))},
+                   "packs": info["n_packs"], "lds_bytes": info["lds_bytes"], "launch_classes": info["n_classes"],
+                   "graph": not args.no_graph, "spikes": int(len(spikes))},
         "roofline": roof,
     }
     if info["n_syn"] > 0:

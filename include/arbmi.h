@@ -175,7 +175,9 @@ typedef struct {
                                  synapse state every step (too many synapses for LDS), or reads
                                  its hh conductances from HBM (a cell too large for LDS
                                  otherwise); else 0 */
-    int32_t reserved;
+    int32_t n_classes;        /* launches per step kernel call: classes of workgroups that need
+                                 different kernel variants or LDS, run concurrently (0 in
+                                 arb_plan_layout) */
 } arb_info;
 
 /* Build a simulation from a fully enumerated model (Sec. III-A: cells,

@@ -62,7 +62,7 @@ class arb_info(C.Structure):
                 ("block_threads", C.c_int32), ("coef_mode", C.c_int32), ("lds_bytes", C.c_int32),
                 ("device_bytes", C.c_int64), ("bytes_per_step", C.c_int64),
                 ("reg_slots", C.c_int32), ("reg_len", C.c_int32), ("syn_hbm", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("n_classes", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1093,6 +1093,7 @@ int arb_get_info(arb_sim s_, arb_info* info) {
     I.reg_slots = s->cfg.coef_mode == 3 ? s->cfg.reg_slots : 0;
     I.reg_len = s->cfg.coef_mode == 3 ? s->cfg.reg_len : 0;
     I.syn_hbm = s->cfg.syn_hbm;
+    I.n_classes = int32_t(std::max<size_t>(1, s->classes.size()));
     *info = I;
     return ARB_OK;
 }

@@ -222,6 +222,29 @@ def test_network_exchange_under_graph_replay_and_state_restore():
     b.close()
 
 
+def test_launch_classes_under_graph_replay():
+    """Uneven cells in the register layout at 256 threads (the largest read
+    their hh conductances from HBM, the rest use one or two register slots):
+    several launch classes on forked streams, captured in one graph per
+    epoch and replayed, match direct launches bitwise and the oracle."""
+    from paper_1901_07454_amd import arbmi
+    ncv = np.array([1 + gen.cell_c3(i, 1.0).n_cv.sum() for i in range(4096)])
+    order = np.argsort(-ncv)
+    cells = sorted([int(c) for c in order[:2]] + [int(c) for c in order[1500:1503]] +
+                   [int(c) for c in order[-3:]])
+    n = 2500
+    m = gen.config3(cells=cells, n_steps=n)
+    probes = oracle.cell_cv_begin(m)[:-1]
+    ref = gpu_run(m, n, probes, block_threads=256, coef_mode=3)
+    got = gpu_run(m, n, probes, block_threads=256, coef_mode=3, flags=arbmi.ARB_FLAG_GRAPH)
+    print("info", got[3], flush=True)
+    assert got[3]["syn_hbm"] == 1 and got[3]["n_classes"] >= 2
+    assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1]) and ref[2] == got[2]
+    otr, _, osp = oracle_run(m, n, probes)
+    assert np.max(np.abs(got[0] - otr)) <= TOL
+    assert got[2] == osp
+
+
 def _event_run_model(n_cells=12, n_syn=6, dup=3, delay=120):
     """Every cell wired to every synapse of every other cell `dup` times
     (same delay, different weights), external events on the same synapses
