@@ -40,7 +40,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_model(cfg: int, n_cells: int | None):
+def make_model(cfg: int, n_cells: int | None, ranks: int = 1):
     from workloads import gen
     if cfg == 1:
         return gen.config1(), "1 cell, 129 CVs (hh soma + 4x32 pas), 1 expsyn, 10 input events"
@@ -63,6 +63,12 @@ def make_model(cfg: int, n_cells: int | None):
         n = n_cells or 8192
         return gen.config6(n_cells=n), (f"{n}-cell synapse-dominated ring, random trees of 90-170 CVs (mean 130), "
                                         "hh soma, pas dendrites, 10,000 expsyn/cell (one on the ring), delay 5 ms")
+    if cfg == 7 and ranks > 1:
+        n = n_cells or 8192
+        return gen.config7_dry_run(n_cells=n, ranks=ranks), (
+            f"dry run of the 10k-connectivity model: one rank of {n} cells (the cells of config 6) in {ranks} "
+            f"identical ranks, every synapse wired from a random gid of all {ranks * n} cells (delay 20 ms), "
+            "remote spikes as proxies of the local cells, all cells driven to fire together at 50 Hz")
     if cfg == 7:
         n = n_cells or 8192
         return gen.config7(n_cells=n), (f"{n}-cell 10k-connectivity model: the cells of config 6, every synapse "
@@ -299,6 +305,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch every epoch's kernels directly")
+    ap.add_argument("--dry-run-ranks", type=int, default=1,
+                    help="config 7: emulate this many identical ranks (proxy spikes, Sec. V-E dry run)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -312,7 +320,7 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    m, desc = make_model(args.config, args.cells)
+    m, desc = make_model(args.config, args.cells, args.dry_run_ranks)
     log(f"model built in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
     # whole epochs (exchange and step kernels) replay from a captured HIP graph
@@ -320,6 +328,7 @@ def main():
     if not (args.block_threads or args.coef_mode or args.cells_per_pack):
         flags |= arbmi.ARB_FLAG_AUTOTUNE
     sim = arbmi.Simulation(m, flags=flags, block_threads=args.block_threads, epoch_steps=args.epoch_steps,
+                           dry_run_ranks=args.dry_run_ranks if args.config == 7 else 0,
                            coef_mode=args.coef_mode, cells_per_pack=args.cells_per_pack)
     info = sim.info
     log(f"sim built in {time.perf_counter() - t0:.1f} s: {info}")
@@ -404,7 +413,8 @@ def main():
                    "dt_ms": float(m["dt"]), "epoch_steps": K,
                    "block_threads": info["block_threads"], "coef_mode": info["coef_mode"],
                    "packs": info["n_packs"], "lds_bytes": info["lds_bytes"], "launch_classes": info["n_classes"],
-                   "graph": not args.no_graph, "spikes": int(len(spikes))},
+                   "graph": not args.no_graph, "spikes": int(len(spikes)),
+                   **({"dry_run_ranks": args.dry_run_ranks} if args.config == 7 and args.dry_run_ranks > 1 else {})},
         "roofline": roof,
     }
     if info["n_syn"] > 0:

@@ -96,7 +96,8 @@ typedef struct {
 } arb_synapse;
 
 /* Connection tuple (source, destination, synapse, delay, weight) (Sec. II).
- * syn is an index into the synapse array and must lie on cell dst. */
+ * syn is an index into the synapse array and must lie on cell dst; src is a
+ * cell, or in dry-run mode any gid of the R ranks (arb_params). */
 typedef struct {
     uint32_t src, dst, syn;
     int32_t delay_steps;      /* >= 1 */
@@ -136,10 +137,15 @@ typedef struct {
     int32_t coef_mode;        /* 0 = autotuned, 1 = per-CV coefficients in LDS, 2 = streamed,
                                  3 = held in registers (by default for branches of <= 16 CVs;
                                  on request longer branches are cut into chains of 8-CV
-                                 segments; not with ARB_FLAG_GRADIENTS, which needs the
-                                 states mode 1 or 2 records) */
+                                 segments; with ARB_FLAG_GRADIENTS the packs must also fit
+                                 the register-resident adjoint kernel) */
     int32_t cells_per_pack;   /* most cells one workgroup advances; 0 = autotuned */
-    int32_t reserved;
+    int32_t dry_run_ranks;    /* dry-run mode (Sec. V-E): 0 or 1 = off; R > 1: the model's cells
+                                 are rank 0 of R identical ranks, connection sources may be any
+                                 gid in [0, R n_cells), and the spikes of gid g on another rank
+                                 are proxies: those of local cell g mod n_cells.  Each epoch's
+                                 exchange then indexes R times the local spikes.  At most 2^20
+                                 ranks and R n_cells < 2^31. */
 } arb_params;
 
 #define ARB_FLAG_TIME_KERNELS 1 /* record HIP events around every step kernel */

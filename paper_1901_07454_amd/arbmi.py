@@ -52,7 +52,7 @@ class arb_params(C.Structure):
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
                 ("spike_capacity", C.c_int64), ("event_capacity", C.c_int64),
                 ("block_threads", C.c_int32), ("coef_mode", C.c_int32),
-                ("cells_per_pack", C.c_int32), ("reserved", C.c_int32)]
+                ("cells_per_pack", C.c_int32), ("dry_run_ranks", C.c_int32)]
 
 
 class arb_info(C.Structure):
@@ -282,7 +282,7 @@ class Simulation:
 
     def __init__(self, m: dict, epoch_steps: int = 0, block_threads: int = 0, coef_mode: int = 0,
                  cells_per_pack: int = 0, flags: int = 0, spike_capacity: int = 0, event_capacity: int = 0, stream=None,
-                 use_torch_allocator: bool = True):
+                 use_torch_allocator: bool = True, dry_run_ranks: int = 0):
         import torch
         self._torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -293,6 +293,7 @@ class Simulation:
         p.spike_capacity, p.event_capacity = int(spike_capacity), int(event_capacity)
         p.block_threads, p.coef_mode = int(block_threads), int(coef_mode)
         p.cells_per_pack = int(cells_per_pack)
+        p.dry_run_ranks = int(dry_run_ranks)
         if use_torch_allocator:
             dev = self.stream.device
             st = self.stream

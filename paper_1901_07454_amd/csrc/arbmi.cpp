@@ -187,8 +187,21 @@ int Sim::launch_classes(const StepArgs& a0) {
 // The epoch's network events: index the spike history by source, then every
 // pack pulls its events of the epoch into its bucket.
 int Sim::launch_pull(int64_t epoch, const int64_t* epoch_ptr) {
-    HIP_TRY(launch_index_spikes(d_hist_gid, d_hist_step, d_hist_cnt, hist_cap, n_hist, d_sx_cnt, d_sx_off, d_sx_step,
-                                L.n_cells, st));
+    IndexLaunch ix{};
+    ix.h_gid = d_hist_gid;
+    ix.h_step = d_hist_step;
+    ix.h_cnt = d_hist_cnt;
+    ix.h_cap = hist_cap;
+    ix.n_hist = n_hist;
+    ix.ranks = L.dry_run_ranks;
+    ix.n_cells = L.n_cells;
+    ix.sx_cap = sx_cap;
+    ix.cnt = d_sx_cnt;
+    ix.off = d_sx_off;
+    ix.tile_sum = d_tile_sum;
+    ix.sx_step = d_sx_step;
+    ix.ctr = d_ctr;
+    HIP_TRY(launch_index_spikes(ix, st));
     PullArgs x{};
     x.in_off = d_in_off;
     x.cr_src = d_cr_src;
@@ -197,7 +210,7 @@ int Sim::launch_pull(int64_t epoch, const int64_t* epoch_ptr) {
     x.cr_w = d_cr_w;
     x.sx_off = d_sx_off;
     x.sx_step = d_sx_step;
-    x.n_cells = L.n_cells;
+    x.n_src = L.n_src;
     x.bk_off = d_bk_off;
     x.bk_nxt = d_bk_nxt;
     x.bk_q = d_bk_q;
@@ -244,7 +257,7 @@ int Sim::capture_epoch_graph() {
         (void)hipGraphExecDestroy(graph);
         graph = nullptr;
     }
-    const bool net = !L.out_rank.empty();
+    const bool net = !L.cr_src.empty();
     StepArgs a = step_args();
     a.epoch_ptr = d_epoch;
     a.nsteps = K;
@@ -273,7 +286,7 @@ int Sim::capture_epoch_graph() {
 // each epoch end.  `rec` (optional) records the pre-step state of every step
 // for the adjoint.  With ARB_FLAG_GRAPH, whole epochs replay a captured graph.
 int Sim::advance(int64_t n, const RecordArgs* rec) {
-    const bool net = !L.out_rank.empty();
+    const bool net = !L.cr_src.empty();
     int64_t done = 0;
     while (n > 0) {
         const int64_t e = step / K, pos = step % K;
@@ -481,7 +494,7 @@ int build_device(Sim* s) {
     // network: one event bucket per pack for the running epoch, and the spike
     // history of the epochs whose spikes can still arrive (a spike of epoch
     // e - n_hist + 1 .. e - 1 can deliver into epoch e, none of epoch e)
-    const bool net = !L.out_rank.empty();
+    const bool net = !L.cr_src.empty();
     if (net) {
         int64_t cap = s->p.event_capacity;
         if (cap <= 0) cap = std::max<int64_t>(64, 4 * L.max_in_per_pack);
@@ -507,10 +520,18 @@ int build_device(Sim* s) {
     s->d_hist_step = dalloc<int64_t>(s, nh, rc);
     s->d_hist_cnt = dalloc<uint32_t>(s, size_t(s->n_hist), rc);
     if (rc == ARB_OK) rc = s->fill_zero(s->d_hist_cnt, size_t(s->n_hist) * sizeof(uint32_t));
-    s->d_sx_cnt = dalloc<int32_t>(s, size_t(L.n_cells) + 1, rc);
-    if (rc == ARB_OK) rc = s->fill_zero(s->d_sx_cnt, (size_t(L.n_cells) + 1) * sizeof(int32_t));
-    s->d_sx_off = dalloc<int64_t>(s, size_t(L.n_cells) + 1, rc);
-    s->d_sx_step = dalloc<int64_t>(s, nh, rc);
+    // the source index: one count and offset per source gid (ranks x cells
+    // in a dry run), and the indexed spikes, proxies included (a dry run
+    // holds at most 4 per local cell, history epoch and rank)
+    const size_t nsrc = size_t(std::max<int64_t>(L.n_src, L.n_cells));
+    s->sx_cap = (L.dry_run_ranks > 1) ? int64_t(L.dry_run_ranks) * s->n_hist *
+                                            std::min<int64_t>(s->hist_cap, 4 * int64_t(L.n_cells))
+                                      : int64_t(nh);
+    s->d_sx_cnt = dalloc<int32_t>(s, nsrc + 1, rc);
+    if (rc == ARB_OK) rc = s->fill_zero(s->d_sx_cnt, (nsrc + 1) * sizeof(int32_t));
+    s->d_sx_off = dalloc<int64_t>(s, nsrc + 1, rc);
+    s->d_sx_step = dalloc<int64_t>(s, size_t(std::max<int64_t>(1, s->sx_cap)), rc);
+    s->d_tile_sum = dalloc<int64_t>(s, size_t(std::max<int64_t>(1, index_tiles(int64_t(nsrc)))), rc);
     s->d_epoch = dalloc<int64_t>(s, 1, rc);
     s->d_ctr = dalloc<Counters>(s, 1, rc);
     if (rc == ARB_OK) rc = s->fill_zero(s->d_ctr, sizeof(Counters));
@@ -566,7 +587,7 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
         err = "no HIP device available";
         return ARB_EHIP;
     }
-    const bool net = !s->L.out_rank.empty();
+    const bool net = !s->L.cr_src.empty();
     s->K = p->epoch_steps > 0 ? p->epoch_steps : (net ? std::min(s->L.min_delay, kMaxEpochSteps) : 1000);
     if (net && s->K > kMaxEpochSteps) {
         delete s;
@@ -805,9 +826,9 @@ int arb_plan_layout(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     I.n_slots = L.n_slots;
     I.n_hh = int64_t(L.hh_cv.size());
     I.n_syn = int64_t(L.syn_pack_index.size());  // the model's synapses (pack order may pad)
-    I.n_conn = int64_t(L.out_rank.size());
+    I.n_conn = int64_t(L.cr_src.size());
     I.epoch_steps = p->epoch_steps > 0 ? p->epoch_steps
-                                       : (L.out_rank.empty() ? 1000 : std::min(L.min_delay, kMaxEpochSteps));
+                                       : (L.cr_src.empty() ? 1000 : std::min(L.min_delay, kMaxEpochSteps));
     I.block_threads = L.block_threads;
     I.coef_mode = L.coef_mode;
     int64_t lds = 0;
@@ -888,7 +909,7 @@ int arb_get_spikes(arb_sim s_, arb_spike* dst, int64_t cap, int64_t* n_out) {
     *n_out = n;
     s->sp_user = have;
     // everything returned and (in a network) exchanged: start the buffer over
-    const bool exchanged = s->L.out_rank.empty() || c.sp_exch == have;
+    const bool exchanged = s->L.cr_src.empty() || c.sp_exch == have;
     if (exchanged && have == c.sp_count && (c.flags & kFlagSpikeOverflow) == 0) {
         Counters z = c;
         z.sp_count = 0;
@@ -1078,7 +1099,7 @@ int arb_get_info(arb_sim s_, arb_info* info) {
     I.n_slots = L.n_slots;
     I.n_hh = int64_t(L.hh_cv.size());
     I.n_syn = int64_t(L.syn_pack_index.size());  // the model's synapses (pack order may pad)
-    I.n_conn = int64_t(L.out_rank.size());
+    I.n_conn = int64_t(L.cr_src.size());
     I.step = s->step;
     I.epoch_steps = s->K;
     I.block_threads = s->cfg.block_threads;

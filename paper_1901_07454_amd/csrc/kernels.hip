@@ -340,81 +340,168 @@ __global__ void __launch_bounds__(T) step_kernel(StepArgs a) {
 // incoming connections (ranks in order) against the index, writing its
 // bucket of the epoch already in (step, rank) order.
 
-// One workgroup: the copy is small (an epoch's spikes) and the exchanged
-// mark moves after every thread has read it.
-__global__ void __launch_bounds__(1024) collect_spikes_kernel(Counters* ctr, const uint32_t* sp_gid,
-                                                              const int64_t* sp_step, uint32_t sp_cap,
-                                                              uint32_t* h_gid, int64_t* h_step, uint32_t* h_cnt,
-                                                              uint32_t h_cap, int32_t n_hist, int64_t epoch,
-                                                              const int64_t* epoch_ptr) {
+// The epoch's spikes [sp_exch, sp_count) into history slot epoch % n_hist,
+// over any number of workgroups (every block reads the counters, which only
+// collect_finish_kernel moves, after this kernel).
+__global__ void __launch_bounds__(256) collect_copy_kernel(const Counters* ctr, const uint32_t* sp_gid,
+                                                           const int64_t* sp_step, uint32_t sp_cap, uint32_t* h_gid,
+                                                           int64_t* h_step, uint32_t h_cap, int32_t n_hist,
+                                                           int64_t epoch, const int64_t* epoch_ptr) {
     const int64_t e = epoch_ptr ? *epoch_ptr : epoch;
     const int64_t slot = e % n_hist;
     const uint32_t b = ctr->sp_exch;
     const uint32_t end = ctr->sp_count < sp_cap ? ctr->sp_count : sp_cap;
     const uint32_t n = end > b ? end - b : 0u;
     const uint32_t m = n < h_cap ? n : h_cap;
-    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         h_gid[slot * h_cap + i] = sp_gid[b + i];
         h_step[slot * h_cap + i] = sp_step[b + i];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        h_cnt[slot] = m;
-        if (n > h_cap) atomicOr(&ctr->flags, kFlagEventOverflow);
-        ctr->sp_exch = end;
+}
+
+// The slot's count, the overflow flag, and the exchanged mark.
+__global__ void collect_finish_kernel(Counters* ctr, uint32_t sp_cap, uint32_t* h_cnt, uint32_t h_cap,
+                                      int32_t n_hist, int64_t epoch, const int64_t* epoch_ptr) {
+    const int64_t e = epoch_ptr ? *epoch_ptr : epoch;
+    const uint32_t b = ctr->sp_exch;
+    const uint32_t end = ctr->sp_count < sp_cap ? ctr->sp_count : sp_cap;
+    const uint32_t n = end > b ? end - b : 0u;
+    h_cnt[e % n_hist] = n < h_cap ? n : h_cap;
+    if (n > h_cap) atomicOr(&ctr->flags, kFlagEventOverflow);
+    ctr->sp_exch = end;
+}
+
+// Index the history's spikes by source gid over any number of workgroups:
+// count per gid, an exclusive scan of the counts into off[0, n_src] (tiles
+// of kScanTile gids: scanned per tile, tile totals scanned, tile offsets
+// added), then scatter the steps while counting back down, which leaves the
+// counts at zero for the next epoch.  With R ranks (dry run) every local
+// spike of gid g stands for R spikes, of gids g + k n_cells, k < R; the
+// index holds at most sx_cap of them (in history order, spike by spike),
+// and more flag an event overflow.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+struct IndexArgs {
+    const uint32_t* h_gid;
+    const int64_t* h_step;
+    const uint32_t* h_cnt;
+    uint32_t h_cap;
+    int32_t n_hist;
+    int32_t ranks;      // R
+    int32_t n_cells;    // local cells
+    int64_t n_src;      // R n_cells
+    int64_t sx_cap;
+    int32_t* cnt;       // [n_src]
+    int64_t* off;       // [n_src + 1]
+    int64_t* tile_sum;  // [tiles]
+    int64_t* sx_step;   // [sx_cap]
+    Counters* ctr;
+};
+
+__device__ __forceinline__ int64_t history_spikes(const IndexArgs& a) {
+    int64_t n = 0;
+    for (int32_t h = 0; h < a.n_hist; ++h) n += a.h_cnt[h];
+    return n;
+}
+
+// f(gid, step) for every indexed proxy spike, grid-stride, in history order
+template <class Fn>
+__device__ __forceinline__ void for_each_proxy(const IndexArgs& a, Fn fn) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    int64_t base = 0;  // proxies of the earlier history slots
+    for (int32_t h = 0; h < a.n_hist && base < a.sx_cap; ++h) {
+        const int64_t e_h = int64_t(a.h_cnt[h]) * a.ranks;
+        const int64_t lim = (base + e_h <= a.sx_cap) ? e_h : a.sx_cap - base;
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < lim; i += stride) {
+            const int64_t sp = i / a.ranks, k = i - sp * a.ranks;
+            const int64_t at = int64_t(h) * a.h_cap + sp;
+            fn(int64_t(a.h_gid[at]) + k * a.n_cells, a.h_step[at]);
+        }
+        base += e_h;
     }
 }
 
-// Index the history's spikes by source gid, in one workgroup: count per gid
-// (cnt starts at zero), exclusive scan into off[0, n_cells] (each thread
-// sums a contiguous segment, the segment sums are scanned in LDS), then
-// scatter the steps while counting back down, which leaves cnt at zero for
-// the next epoch.
-__global__ void __launch_bounds__(1024) index_spikes_kernel(const uint32_t* h_gid, const int64_t* h_step,
-                                                            const uint32_t* h_cnt, uint32_t h_cap, int32_t n_hist,
-                                                            int32_t* cnt, int64_t* off, int64_t* sx_step,
-                                                            int32_t n) {
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
-    int64_t any = 0;
-    for (int32_t h = 0; h < n_hist; ++h) any += h_cnt[h];
-    if (any == 0) {  // no spikes: only the total, which the pull checks first
-        if (t == 0) off[n] = 0;
+__global__ void __launch_bounds__(256) index_count_kernel(IndexArgs a) {
+    const int64_t n = history_spikes(a);
+    if (n == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n * a.ranks > a.sx_cap) atomicOr(&a.ctr->flags, kFlagEventOverflow);
+    for_each_proxy(a, [&](int64_t g, int64_t) { atomicAdd(&a.cnt[g], 1); });
+}
+
+// exclusive scan of v over the block (kScanThreads threads); *total gets the sum
+__device__ __forceinline__ int64_t block_scan(int64_t v, int64_t* lds, int64_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        before += (w < wave) ? lds[w] : 0;
+        all += lds[w];
+    }
+    __syncthreads();
+    *total = all;
+    return before + x - v;
+}
+
+// per tile: off[i] = exclusive prefix of cnt within the tile; tile totals
+__global__ void __launch_bounds__(kScanThreads) index_scan_tiles_kernel(IndexArgs a) {
+    __shared__ int64_t lds[kScanThreads / 64];
+    if (history_spikes(a) == 0) return;
+    const int64_t t0 = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+    int32_t c[kScanItems];
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        c[k] = (t0 + k < a.n_src) ? a.cnt[t0 + k] : 0;
+        sum += c[k];
+    }
+    int64_t total;
+    int64_t run = block_scan(sum, lds, &total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (t0 + k < a.n_src) a.off[t0 + k] = run;
+        run += c[k];
+    }
+    if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
+}
+
+// one block: tile totals -> exclusive tile offsets (in place); off[n_src]
+__global__ void __launch_bounds__(kScanThreads) index_scan_totals_kernel(IndexArgs a, int64_t tiles) {
+    __shared__ int64_t lds[kScanThreads / 64];
+    if (history_spikes(a) == 0) {
+        if (threadIdx.x == 0) a.off[a.n_src] = 0;  // the pull checks the total first
         return;
     }
-    for (int32_t h = 0; h < n_hist; ++h) {
-        const uint32_t c = h_cnt[h];
-        for (uint32_t i = t; i < c; i += 1024) atomicAdd(&cnt[h_gid[int64_t(h) * h_cap + i]], 1);
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < tiles; b0 += kScanThreads) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t v = i < tiles ? a.tile_sum[i] : 0;
+        int64_t total;
+        const int64_t x = block_scan(v, lds, &total);
+        if (i < tiles) a.tile_sum[i] = carry + x;
+        carry += total;
     }
-    __threadfence_block();
-    __syncthreads();
-    const int32_t seg = (n + 1023) / 1024;
-    const int32_t i0 = t * seg < n ? t * seg : n, i1 = i0 + seg < n ? i0 + seg : n;
-    int64_t sum = 0;
-    for (int32_t i = i0; i < i1; ++i) sum += cnt[i];
-    part[t] = sum;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int64_t x = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += x;
-        __syncthreads();
-    }
-    int64_t run = part[t] - sum;
-    for (int32_t i = i0; i < i1; ++i) {
-        off[i] = run;
-        run += cnt[i];
-    }
-    if (t == 1023) off[n] = part[1023];
-    __threadfence_block();
-    __syncthreads();
-    for (int32_t h = 0; h < n_hist; ++h) {
-        const uint32_t c = h_cnt[h];
-        for (uint32_t i = t; i < c; i += 1024) {
-            const uint32_t g = h_gid[int64_t(h) * h_cap + i];
-            sx_step[off[g] + atomicSub(&cnt[g], 1) - 1] = h_step[int64_t(h) * h_cap + i];
-        }
-    }
+    if (threadIdx.x == 0) a.off[a.n_src] = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads) index_scan_add_kernel(IndexArgs a) {
+    if (history_spikes(a) == 0) return;
+    const int64_t add = a.tile_sum[blockIdx.x];
+    const int64_t t0 = int64_t(blockIdx.x) * kScanTile;
+    for (int k = threadIdx.x; k < kScanTile; k += kScanThreads)
+        if (t0 + k < a.n_src) a.off[t0 + k] += add;
+}
+
+__global__ void __launch_bounds__(256) index_scatter_kernel(IndexArgs a) {
+    if (history_spikes(a) == 0) return;
+    for_each_proxy(a, [&](int64_t g, int64_t step) { a.sx_step[a.off[g] + atomicSub(&a.cnt[g], 1) - 1] = step; });
 }
 
 __device__ __forceinline__ int wave_min(int v) {
@@ -439,7 +526,7 @@ __global__ void __launch_bounds__(64) pull_events_kernel(PullArgs a) {
     const int K = a.epoch_steps;
     const int64_t lo = e * K;
     const int64_t r0 = a.in_off[p], r1 = a.in_off[p + 1];
-    if (a.sx_off[a.n_cells] == 0) {  // no spikes in the history: no events this epoch
+    if (a.sx_off[a.n_src] == 0) {  // no spikes in the history: no events this epoch
         uint32_t* nxt = a.bk_nxt + int64_t(p) * (K + 1);
         for (int b = lane; b <= K; b += 64) nxt[b] = uint32_t(K);
         return;
@@ -712,16 +799,48 @@ hipError_t launch_advance_epoch(int64_t* epoch, hipStream_t st) {
 hipError_t launch_collect_spikes(Counters* ctr, const uint32_t* sp_gid, const int64_t* sp_step, uint32_t sp_cap,
                                  uint32_t* h_gid, int64_t* h_step, uint32_t* h_cnt, uint32_t h_cap, int32_t n_hist,
                                  int64_t epoch, const int64_t* epoch_ptr, hipStream_t st) {
-    hipLaunchKernelGGL(collect_spikes_kernel, dim3(1), dim3(1024), 0, st, ctr, sp_gid, sp_step, sp_cap, h_gid, h_step,
-                       h_cnt, h_cap, n_hist, epoch, epoch_ptr);
+    const unsigned nb = unsigned(std::min<int64_t>(256, std::max<int64_t>(1, (int64_t(h_cap) + 255) / 256)));
+    hipLaunchKernelGGL(collect_copy_kernel, dim3(nb), dim3(256), 0, st, ctr, sp_gid, sp_step, sp_cap, h_gid, h_step,
+                       h_cap, n_hist, epoch, epoch_ptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(collect_finish_kernel, dim3(1), dim3(1), 0, st, ctr, sp_cap, h_cnt, h_cap, n_hist, epoch,
+                       epoch_ptr);
     return hipGetLastError();
 }
 
-hipError_t launch_index_spikes(const uint32_t* h_gid, const int64_t* h_step, const uint32_t* h_cnt, uint32_t h_cap,
-                               int32_t n_hist, int32_t* sx_cnt, int64_t* sx_off, int64_t* sx_step, int32_t n_cells,
-                               hipStream_t st) {
-    hipLaunchKernelGGL(index_spikes_kernel, dim3(1), dim3(1024), 0, st, h_gid, h_step, h_cnt, h_cap, n_hist, sx_cnt,
-                       sx_off, sx_step, n_cells);
+int64_t index_tiles(int64_t n_src) { return (n_src + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_index_spikes(const IndexLaunch& x, hipStream_t st) {
+    IndexArgs a{};
+    a.h_gid = x.h_gid;
+    a.h_step = x.h_step;
+    a.h_cnt = x.h_cnt;
+    a.h_cap = x.h_cap;
+    a.n_hist = x.n_hist;
+    a.ranks = x.ranks;
+    a.n_cells = x.n_cells;
+    a.n_src = int64_t(x.ranks) * x.n_cells;
+    a.sx_cap = x.sx_cap;
+    a.cnt = x.cnt;
+    a.off = x.off;
+    a.tile_sum = x.tile_sum;
+    a.sx_step = x.sx_step;
+    a.ctr = x.ctr;
+    const int64_t tiles = index_tiles(a.n_src);
+    // proxies per epoch: about R x the spikes of the history; enough blocks
+    // for every CU, more when the dry run multiplies them
+    const unsigned nb = unsigned(std::min<int64_t>(4096, std::max<int64_t>(256, int64_t(x.ranks) * 4)));
+    hipLaunchKernelGGL(index_count_kernel, dim3(nb), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(index_scan_tiles_kernel, dim3(unsigned(tiles)), dim3(kScanThreads), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(index_scan_totals_kernel, dim3(1), dim3(kScanThreads), 0, st, a, tiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(index_scan_add_kernel, dim3(unsigned(tiles)), dim3(kScanThreads), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(index_scatter_kernel, dim3(nb), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -112,12 +112,29 @@ hipError_t launch_advance_epoch(int64_t* epoch, hipStream_t st);
 hipError_t launch_collect_spikes(Counters* ctr, const uint32_t* sp_gid, const int64_t* sp_step, uint32_t sp_cap,
                                  uint32_t* h_gid, int64_t* h_step, uint32_t* h_cnt, uint32_t h_cap, int32_t n_hist,
                                  int64_t epoch, const int64_t* epoch_ptr, hipStream_t st);
-// Epoch start: index the history's spikes by source gid: sx_off[n_cells + 1]
-// (exclusive offsets) and sx_step (their steps); sx_cnt[n_cells] is scratch
-// that must be zero on entry and is zero again on return.
-hipError_t launch_index_spikes(const uint32_t* h_gid, const int64_t* h_step, const uint32_t* h_cnt, uint32_t h_cap,
-                               int32_t n_hist, int32_t* sx_cnt, int64_t* sx_off, int64_t* sx_step, int32_t n_cells,
-                               hipStream_t st);
+// Epoch start: index the history's spikes by source gid: off[n_src + 1]
+// (exclusive offsets, n_src = ranks x n_cells) and sx_step (their steps).
+// With ranks R > 1 (dry run) each local spike of gid g also stands for the
+// spikes of gids g + k n_cells, k < R; at most sx_cap are indexed (more
+// flag an event overflow).  cnt[n_src] is scratch that must be zero on entry
+// and is zero again on return; tile_sum holds index_tiles(n_src) values.
+struct IndexLaunch {
+    const uint32_t* h_gid;
+    const int64_t* h_step;
+    const uint32_t* h_cnt;
+    uint32_t h_cap;
+    int32_t n_hist;
+    int32_t ranks;
+    int32_t n_cells;
+    int64_t sx_cap;
+    int32_t* cnt;
+    int64_t* off;
+    int64_t* tile_sum;
+    int64_t* sx_step;
+    Counters* ctr;
+};
+int64_t index_tiles(int64_t n_src);
+hipError_t launch_index_spikes(const IndexLaunch& x, hipStream_t st);
 // Epoch start, after the index: each pack's network events of the epoch in
 // (step, rank) order, with each step's start, into its bucket.
 struct PullArgs {
@@ -126,10 +143,9 @@ struct PullArgs {
     const int32_t* cr_delay;   // per rank: delay in steps
     const int32_t* cr_syn;     // per rank: pack-local synapse
     const double* cr_w;        // per rank: weight nS
-    const int64_t* sx_off;     // [n_cells + 1]
+    const int64_t* sx_off;     // [n_src + 1]
     const int64_t* sx_step;
-    int32_t n_cells;
-    int32_t pad;
+    int64_t n_src;             // source gids (ranks x cells)
     uint32_t* bk_off;          // [n_packs][epoch_steps + 1]
     uint32_t* bk_nxt;          // [n_packs][epoch_steps + 1]
     int32_t* bk_q;             // [n_packs][bk_cap]

@@ -246,11 +246,18 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         if (ev[q].step < 0 || ev[q].step >= (int64_t(1) << 31)) { err = fmt("event %lld: step out of range", (long long)q); return ARB_EINVAL; }
         if (!std::isfinite(ev[q].w_uS)) { err = fmt("event %lld: weight not finite", (long long)q); return ARB_EINVAL; }
     }
+    if (p.dry_run_ranks < 0 || p.dry_run_ranks > (1 << 20) ||
+        int64_t(std::max(1, p.dry_run_ranks)) * n_cells >= (int64_t(1) << 31)) {
+        err = "dry_run_ranks out of range (at most 2^20, and ranks x cells below 2^31)";
+        return ARB_EINVAL;
+    }
+    L.dry_run_ranks = std::max(1, p.dry_run_ranks);
+    L.n_src = int64_t(L.dry_run_ranks) * n_cells;
     L.min_delay = 0;
     L.max_delay = 0;
     for (int64_t q = 0; q < n_conn; ++q) {
         const arb_connection& K = conn[q];
-        if (K.src >= uint32_t(n_cells) || K.dst >= uint32_t(n_cells)) { err = fmt("connection %lld: cell out of range", (long long)q); return ARB_EINVAL; }
+        if (int64_t(K.src) >= L.n_src || K.dst >= uint32_t(n_cells)) { err = fmt("connection %lld: cell out of range", (long long)q); return ARB_EINVAL; }
         if (int64_t(K.syn) >= n_syn || syn[K.syn].cell != int32_t(K.dst)) {
             err = fmt("connection %lld: synapse not on the destination cell", (long long)q); return ARB_EINVAL;
         }
@@ -760,7 +767,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         }
     }
 
-    // connections: rank by (dst pack, pack synapse, src, index); CSR by source.
+    // connections: rank by (dst pack, pack synapse, src, index).
     // A pack's synapse positions are contiguous and packs follow each other,
     // so ordering by position orders by pack: a counting sort by position
     // (stable, so by index within a position), then by source where several
@@ -786,7 +793,6 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         L.cr_src.resize(n_conn);
         L.cr_w.resize(n_conn);
         std::vector<int64_t> in_per_pack(n_packs, 0);
-        L.out_off.assign(n_cells + 1, 0);
         for (int64_t r = 0; r < n_conn; ++r) {
             const arb_connection& K = conn[idx[r]];
             const int64_t pk = pack_of_cell[K.dst];
@@ -796,18 +802,10 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             L.cr_src[r] = K.src;
             L.cr_w[r] = 1000.0 * K.w_uS;
             in_per_pack[pk]++;
-            L.out_off[K.src + 1]++;
         }
         L.max_in_per_pack = n_packs ? *std::max_element(in_per_pack.begin(), in_per_pack.end()) : 0;
         L.in_off.assign(n_packs + 1, 0);
         for (int64_t pk = 0; pk < n_packs; ++pk) L.in_off[pk + 1] = L.in_off[pk] + in_per_pack[pk];
-        for (int32_t c = 0; c < n_cells; ++c) L.out_off[c + 1] += L.out_off[c];
-        L.out_rank.resize(n_conn);
-        std::vector<int64_t> fill(n_cells, 0);
-        for (int64_t r = 0; r < n_conn; ++r) {
-            const uint32_t src = conn[idx[r]].src;
-            L.out_rank[L.out_off[src] + fill[src]++] = uint32_t(r);
-        }
     }
     return ARB_OK;
 }

@@ -69,12 +69,12 @@ struct Lowered {
     std::vector<int32_t> xe_syn;              // pack-local synapse
     std::vector<double> xe_w;                 // nS
     // connections: ranks sorted by (dst pack, dst pack-local synapse, src, index)
-    std::vector<int64_t> out_off;             // [n_cells + 1] CSR by source gid
-    std::vector<uint32_t> out_rank;
+    int64_t n_src = 0;                        // source gids: n_cells, or R n_cells in dry-run mode
     std::vector<int32_t> cr_pack, cr_syn, cr_delay;
     std::vector<uint32_t> cr_src;             // source gid of each rank
     std::vector<double> cr_w;                 // nS
     std::vector<int64_t> in_off;              // [n_packs + 1] first rank of each pack
+    int32_t dry_run_ranks = 1;                // R: ranks the exchange emulates (1 = none)
     int32_t min_delay = 0, max_delay = 0;
     int64_t max_in_per_pack = 0;              // incoming connections of the busiest pack
     int64_t n_hh_total = 0;

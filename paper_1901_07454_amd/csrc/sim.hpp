@@ -100,7 +100,8 @@ struct Sim : arb_sim_ {
     int64_t* d_hist_step = nullptr;
     uint32_t* d_hist_cnt = nullptr;
     int32_t* d_sx_cnt = nullptr;
-    int64_t *d_sx_off = nullptr, *d_sx_step = nullptr;
+    int64_t *d_sx_off = nullptr, *d_sx_step = nullptr, *d_tile_sum = nullptr;
+    int64_t sx_cap = 0;  // indexed spikes (proxies included) per epoch
     uint32_t* d_sp_gid = nullptr;
     int64_t* d_sp_step = nullptr;
     double* d_sp_t = nullptr;

@@ -91,7 +91,7 @@ int main(int argc, char** argv) {
 
         // state blobs as arb_get_state writes them for this lowering
         StateShape sh;
-        sh.net = !L.out_rank.empty();
+        sh.net = !L.cr_src.empty();
         sh.K = sh.net ? L.min_delay : 1000;
         sh.bk_cap = sh.net ? int32_t(std::max<int64_t>(64, 4 * L.max_in_per_pack)) : 0;
         sh.sp_cap = uint32_t(std::max<int64_t>(1 << 16, int64_t(L.n_cells) * 64));

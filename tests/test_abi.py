@@ -148,6 +148,20 @@ def test_rejects_bad_launch_parameters():
     _expect_einval(_ring(), "coef_mode", coef_mode=4)
 
 
+def test_dry_run_sources_and_limits():
+    """Dry-run mode accepts connection sources among ranks x cells gids
+    only, and at most 2^20 ranks."""
+    m = gen.config7_dry_run(n_cells=6, ranks=4, n_steps=10, n_syn=20)
+    assert int(m["con_src"].max()) >= 6
+    assert _plan(m, dry_run_ranks=4)["n_conn"] == 120
+    with pytest.raises(arbmi.ArbError) as e:
+        _plan(m)  # sources beyond the cells without a dry run
+    assert e.value.code == arbmi.ARB_EINVAL and "connection" in str(e.value)
+    with pytest.raises(arbmi.ArbError) as e:
+        _plan(m, dry_run_ranks=(1 << 20) + 1)
+    assert "dry_run_ranks" in str(e.value)
+
+
 def test_gradient_layouts():
     """Sims built for gradients take the register layout when its packs also
     fit the adjoint kernel; a cell whose synapses would have to stay in HBM

@@ -301,10 +301,12 @@ def cell_c7(i: int, n_cells: int, n_syn: int = 10000, min_delay_ms: float = 20.0
 # assembly of a model from cell descriptions
 
 def assemble(cells: list[CellDesc], gids=None, n_steps: int = 0,
-             dt: float = DT) -> dict:
+             dt: float = DT, remote_sources: bool = False) -> dict:
     """Flatten per-cell descriptions into the column model.  `gids` are the
     global ids the cells had in the full network; connections whose source is
-    not among them are dropped (used for light-cone sub-models)."""
+    not among them are dropped (used for light-cone sub-models), unless
+    remote_sources, which keeps every source gid as it is (the cells are then
+    gids 0 .. n-1, one rank of a larger network)."""
     if gids is None:
         gids = list(range(len(cells)))
     remap = {int(g): k for k, g in enumerate(gids)}
@@ -354,6 +356,10 @@ def assemble(cells: list[CellDesc], gids=None, n_steps: int = 0,
                 continue
             src, ls, dl, w = (np.asarray(x) for x in c.in_conn_arr)
             src = src.astype(np.int64)
+            if remote_sources:
+                parts.append([src.astype(np.uint32), np.full(len(src), ci, np.uint32),
+                              (sb[ci] + ls).astype(np.uint32), dl.astype(np.int32), w.astype(np.float64)])
+                continue
             ok = src < len(lut)
             ok[ok] = lut[src[ok]] >= 0
             parts.append([lut[src[ok]].astype(np.uint32), np.full(int(ok.sum()), ci, np.uint32),
@@ -473,6 +479,27 @@ def config7(n_cells: int = 8192, cells=None, n_steps: int = 4000, n_syn: int = 1
     ids = range(n_cells) if cells is None else cells
     return assemble([cell_c7(i, n_cells, n_syn, min_delay_ms, w_net, n_steps=n_steps) for i in ids],
                     gids=list(ids), n_steps=n_steps)
+
+
+def config7_dry_run(n_cells: int = 8192, ranks: int = 1, n_steps: int = 4000, n_syn: int = 10000,
+                    min_delay_ms: float = 20.0, w_net: float = 2e-6) -> dict:
+    """One rank's share of the 10k-connectivity model on `ranks` identical
+    ranks (the dry run of Sec. V-E): the cells of config 7, every synapse
+    wired from a uniformly drawn other gid of all ranks' ranks x n_cells
+    cells (source gids kept as they are).  Run with dry_run_ranks = ranks, a
+    remote gid g fires as local cell g mod n_cells does."""
+    cells = []
+    n_src = int(ranks) * int(n_cells)
+    for i in range(n_cells):
+        d = cell_c7(i, n_cells, n_syn, min_delay_ms, w_net, n_steps=n_steps)
+        ss = np.random.SeedSequence(SEED_BASE + 7, spawn_key=(int(i), 2))
+        rng = np.random.Generator(np.random.PCG64(ss))
+        src = rng.integers(n_src - 1, size=n_syn) if n_src > 1 else np.zeros(0, np.int64)
+        src = np.where(src >= i, src + 1, src)
+        k = len(src)
+        d.in_conn_arr = (src, np.arange(k), np.full(k, int(round(min_delay_ms / DT))), np.full(k, w_net))
+        cells.append(d)
+    return assemble(cells, n_steps=n_steps, remote_sources=True)
 
 
 def ring_light_cone(n_cells: int, target: int, n_steps: int, delay: int = 200) -> list[int]:
