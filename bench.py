@@ -291,6 +291,45 @@ def grad_regions(m: dict):
     return np.array(out, dtype=np.float64)
 
 
+def dry_run_sweep(m: dict, ranks_list, K: int, epochs: int = 3):
+    """The 10k-connectivity model's rank of cells at each rank count (only
+    the connection sources change): wall time per epoch of direct launches
+    after a warm-up epoch, the step kernel's share from HIP events, and the
+    rest (spike collection, the source index over ranks x cells gids, the
+    event pull, launch gaps) per epoch."""
+    import torch
+
+    from paper_1901_07454_amd import arbmi
+    from workloads import gen
+    n = len(m["cell_n_branch"])
+    n_syn = len(m["con_src"]) // n
+    rows = []
+    for r in ranks_list:
+        mm = dict(m)
+        mm["con_src"] = gen.config7_dry_run_sources(n, r, n_syn)
+        sim = arbmi.Simulation(mm, flags=arbmi.ARB_FLAG_TIME_KERNELS | arbmi.ARB_FLAG_AUTOTUNE, dry_run_ranks=r)
+        sim.step(K)
+        sim.sync()
+        sim.kernel_time()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(epochs * K)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms, _ = sim.kernel_time()
+        sim.sync()
+        sp = len(sim.spikes())
+        info = sim.info
+        sim.close()
+        rows.append({"ranks": r, "source_gids": r * n, "cv_updates_per_s": info["n_cv"] * epochs * K / wall,
+                     "ms_per_epoch": wall * 1e3 / epochs, "step_kernel_ms_per_epoch": kms / epochs,
+                     "exchange_and_gaps_ms_per_epoch": (wall * 1e3 - kms) / epochs,
+                     "local_spikes": sp, "indexed_spikes_per_epoch": sp * r / (epochs + 1)})
+        log(f"dry run, {r} ranks: {rows[-1]}")
+    return {"model": "config 7 rank of %d cells, 10,000 synapses each, sources among ranks x cells gids" % n,
+            "epoch_steps": K, "epochs_timed": epochs, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,8 +344,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch every epoch's kernels directly")
-    ap.add_argument("--dry-run-ranks", type=int, default=1,
-                    help="config 7: emulate this many identical ranks (proxy spikes, Sec. V-E dry run)")
+    ap.add_argument("--dry-run-ranks", default="1",
+                    help="config 7: emulate this many identical ranks (proxy spikes, Sec. V-E dry run); a comma "
+                         "list sweeps them, the first giving the headline line")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -320,6 +360,8 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
+    sweep = [int(x) for x in str(args.dry_run_ranks).split(",")]
+    args.dry_run_ranks = sweep[0]
     m, desc = make_model(args.config, args.cells, args.dry_run_ranks)
     log(f"model built in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
@@ -420,6 +462,8 @@ def main():
     if info["n_syn"] > 0:
         out["synapse_updates_per_s"] = info["n_syn"] * steps / wall
     sim.close()
+    if args.config == 7 and len(sweep) > 1:
+        out["dry_run"] = dry_run_sweep(m, sweep, K)
     if not args.no_grad:
         out["grad"] = grad_ratio(torch)
         if args.config == 5:

@@ -489,17 +489,28 @@ def config7_dry_run(n_cells: int = 8192, ranks: int = 1, n_steps: int = 4000, n_
     cells (source gids kept as they are).  Run with dry_run_ranks = ranks, a
     remote gid g fires as local cell g mod n_cells does."""
     cells = []
-    n_src = int(ranks) * int(n_cells)
     for i in range(n_cells):
         d = cell_c7(i, n_cells, n_syn, min_delay_ms, w_net, n_steps=n_steps)
-        ss = np.random.SeedSequence(SEED_BASE + 7, spawn_key=(int(i), 2))
-        rng = np.random.Generator(np.random.PCG64(ss))
-        src = rng.integers(n_src - 1, size=n_syn) if n_src > 1 else np.zeros(0, np.int64)
-        src = np.where(src >= i, src + 1, src)
+        src = _dry_run_sources(i, n_cells, ranks, n_syn)
         k = len(src)
         d.in_conn_arr = (src, np.arange(k), np.full(k, int(round(min_delay_ms / DT))), np.full(k, w_net))
         cells.append(d)
     return assemble(cells, n_steps=n_steps, remote_sources=True)
+
+
+def _dry_run_sources(i: int, n_cells: int, ranks: int, n_syn: int) -> np.ndarray:
+    ss = np.random.SeedSequence(SEED_BASE + 7, spawn_key=(int(i), 2))
+    rng = np.random.Generator(np.random.PCG64(ss))
+    n_src = int(ranks) * int(n_cells)
+    src = rng.integers(n_src - 1, size=n_syn) if n_src > 1 else np.zeros(0, np.int64)
+    return np.where(src >= i, src + 1, src)
+
+
+def config7_dry_run_sources(n_cells: int, ranks: int, n_syn: int = 10000) -> np.ndarray:
+    """The con_src column of config7_dry_run(n_cells, ranks, ..., n_syn) (the
+    connections of cell 0, then cell 1, ... each in synapse order), drawn
+    alone: the same model at another rank count differs only in it."""
+    return np.concatenate([_dry_run_sources(i, n_cells, ranks, n_syn) for i in range(n_cells)]).astype(np.uint32)
 
 
 def ring_light_cone(n_cells: int, target: int, n_steps: int, delay: int = 200) -> list[int]:
