@@ -59,6 +59,14 @@ def lib():
         L.orc_cv_info.argtypes = [P, P, P, P, P]
         L.orc_membrane_current.argtypes = [P, C.c_int64, P]
         L.orc_set_params.argtypes = [P, P]
+        L.orc_set_varstep.restype = C.c_int
+        L.orc_set_varstep.argtypes = [P, P, C.c_int64, P, P, P, C.c_int64]
+        L.orc_advance_to.restype = C.c_int
+        L.orc_advance_to.argtypes = [P, C.c_int64]
+        L.orc_varstep_steps.restype = C.c_int64
+        L.orc_varstep_steps.argtypes = [P]
+        L.orc_varstep_grid.restype = C.c_int64
+        L.orc_varstep_grid.argtypes = [P]
         L.orc_adjoint.restype = C.c_int
         L.orc_adjoint.argtypes = [P, C.c_int64, P, P, P]
         L.orc_hines_solve.argtypes = [C.c_int64, P, P, P, P]
@@ -168,6 +176,42 @@ class Sim:
         g = np.zeros(max(self.nsyn, 1))
         lib().orc_get_state(self.h, _p(V), _p(mm), _p(hh), _p(nn), _p(g))
         return dict(V=V, m=mm, h=hh, n=nn, g=g[: self.nsyn])
+
+    # variable time step (models with continuous times: con_delay_ms, ev_t)
+    def set_varstep(self, epoch_steps: int | None = None):
+        """Switch to the variable-step mode with the model's continuous
+        delays (con_delay_ms) and event times (ev_t); epochs of epoch_steps
+        grid steps (default: the most within the minimum delay, or 1000
+        without connections)."""
+        m = self.m
+        d = _c(m["con_delay_ms"], np.float64)
+        if epoch_steps is None:
+            epoch_steps = 1000
+            if len(d):
+                epoch_steps = int(np.floor(float(d.min()) / float(m["dt"])))
+                while (epoch_steps + 1) * float(m["dt"]) <= float(d.min()):
+                    epoch_steps += 1
+                while epoch_steps > 1 and epoch_steps * float(m["dt"]) > float(d.min()):
+                    epoch_steps -= 1
+        syn, t, w = _c(m["ev_syn"], np.uint32), _c(m["ev_t"], np.float64), _c(m["ev_w"], np.float64)
+        self._keep_vs = (d, syn, t, w)
+        rc = lib().orc_set_varstep(self.h, _p(d), len(syn), _p(syn), _p(t), _p(w), int(epoch_steps))
+        if rc != 0:
+            raise ValueError("the variable-step mode takes no current clamps, and epochs of at most the "
+                             "minimum delay")
+        return self
+
+    def advance_to(self, k_end: int):
+        """Every cell to grid point k_end (time k_end dt)."""
+        lib().orc_advance_to(self.h, int(k_end))
+
+    @property
+    def varstep_steps(self) -> int:
+        return int(lib().orc_varstep_steps(self.h))
+
+    @property
+    def grid_point(self) -> int:
+        return int(lib().orc_varstep_grid(self.h))
 
     def set_voltage(self, V):
         V = _c(V, np.float64)

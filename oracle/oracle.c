@@ -59,6 +59,17 @@ typedef struct {
     double t;
 } orc_spike;
 
+/* an event of the variable-step mode: continuous time (ms) */
+typedef struct {
+    int32_t cell;
+    double t;
+    int32_t kind; /* 0 = network, 1 = external input */
+    uint32_t syn;
+    uint32_t src;
+    int64_t seq;
+    double w; /* uS */
+} orc_tev;
+
 typedef struct {
     /* sizes */
     int32_t ncell;
@@ -118,6 +129,20 @@ typedef struct {
 
     /* scratch */
     double *d, *rhs, *I;
+
+    /* variable-step mode (orc_set_varstep) */
+    int varstep;
+    int64_t K_ep;          /* epoch length (grid steps) */
+    int64_t k_now;         /* grid point every cell has reached */
+    double *tcell;         /* [ncell] each cell's time */
+    int64_t *kcell;        /* [ncell] its grid interval: k dt <= t < (k+1) dt */
+    double *out_delay_ms;  /* per connection, out_* order */
+    int32_t *syn_cell;     /* [nsyn] */
+    int64_t *csyn_begin, *csyn; /* synapses of each cell */
+    orc_tev *tev;          /* pending events */
+    int64_t ntev, captev;
+    int64_t *tev_begin, *tev_end, *tev_head; /* [ncell] this epoch's events of each cell */
+    int64_t nvsteps;       /* steps taken (all cells) */
 } orc;
 
 /* ------------------------------------------------------------------------ */
@@ -476,7 +501,8 @@ void orc_free(orc *s) {
                   s->reg_gpas, s->reg_epas, s->reg_cell, s->syn_cv, s->syn_tau, s->syn_e,
                   s->out_begin, s->out_syn, s->out_src, s->out_delay, s->out_w, s->out_id,
                   s->ic_cv, s->ic_on, s->ic_off, s->ic_amp, s->V, s->m, s->h, s->n, s->g,
-                  s->ev, s->sp, s->rec, s->d, s->rhs, s->I};
+                  s->ev, s->sp, s->rec, s->d, s->rhs, s->I, s->tcell, s->kcell, s->out_delay_ms, s->syn_cell,
+                  s->csyn_begin, s->csyn, s->tev, s->tev_begin, s->tev_end, s->tev_head};
     for (size_t k = 0; k < sizeof(ps) / sizeof(ps[0]); ++k) free(ps[k]);
     free(s);
 }
@@ -797,3 +823,220 @@ int orc_adjoint(orc *s, int64_t n_steps, const double *dLdtrace, double *grad, d
     free(gdiag);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Variable time step (Sec. II: a spike's arrival changes a synapse's state
+ * at once, so the step is shortened as needed for every such update to fall
+ * at the beginning of a step).  Every cell keeps its own time.  Inputs are
+ * continuous: external event times and connection delays in ms; a spike
+ * carries its threshold crossing time interpolated within the step, and its
+ * events arrive at that time plus the delay.
+ * READING (the paper states the rule, not the procedure): the steps end on
+ * the grid k dt unless an event comes first: from its time t in
+ * [k dt, (k+1) dt) a cell steps to min((k+1) dt, its next event's time),
+ * after applying every event due at or before t, and a full step from k dt
+ * to (k+1) dt has length dt exactly.  An epoch is K steps of the grid (K dt
+ * at most the minimum delay) and its spikes are exchanged at its end, so the
+ * epoch length does not change the run.  The matrix C/dt' + L is assembled
+ * and solved for each step's length dt'; gates and synapses decay over dt'.
+ * Current clamps are not part of this mode. */
+
+static int tev_cmp(const void *a_, const void *b_) {
+    const orc_tev *a = a_, *b = b_;
+#define CMP(x, y) \
+    if ((x) < (y)) return -1; \
+    if ((x) > (y)) return 1;
+    CMP(a->cell, b->cell);
+    CMP(a->t, b->t);
+    CMP(a->kind, b->kind);
+    CMP(a->syn, b->syn);
+    CMP(a->src, b->src);
+    CMP(a->seq, b->seq);
+#undef CMP
+    return 0;
+}
+
+static void tev_push(orc *s, orc_tev e) {
+    if (s->ntev == s->captev) {
+        s->captev = s->captev ? 2 * s->captev : 1024;
+        s->tev = realloc(s->tev, (size_t)s->captev * sizeof(orc_tev));
+    }
+    s->tev[s->ntev++] = e;
+}
+
+/* Switch to the variable-step mode: connection delays (ms, input order),
+ * external events (synapse, time ms, weight uS) replacing the step-indexed
+ * ones, epoch length K_ep (steps).  Every cell starts at time 0.  Returns 0,
+ * -1 if the model has current clamps, -2 if the epoch exceeds a delay. */
+int orc_set_varstep(orc *s, const double *con_delay_ms, int64_t next, const uint32_t *ev_syn,
+                    const double *ev_t, const double *ev_w, int64_t K_ep) {
+    if (s->nic > 0) return -1;
+    for (int64_t k = 0; k < s->ncon; ++k)
+        if (!(con_delay_ms[k] >= (double)K_ep * s->dt)) return -2; /* an epoch is at most the minimum delay */
+    s->varstep = 1;
+    s->K_ep = K_ep;
+    s->k_now = 0;
+    s->tcell = xcalloc((size_t)s->ncell, sizeof(double));
+    s->kcell = xcalloc((size_t)s->ncell, sizeof(int64_t));
+    s->out_delay_ms = xcalloc((size_t)s->ncon, sizeof(double));
+    for (int64_t c = 0; c < s->ncon; ++c) s->out_delay_ms[c] = con_delay_ms[s->out_id[c]];
+    /* the cell of each synapse, and each cell's synapses */
+    s->syn_cell = xcalloc((size_t)s->nsyn, sizeof(int32_t));
+    s->csyn_begin = xcalloc((size_t)s->ncell + 1, sizeof(int64_t));
+    s->csyn = xcalloc((size_t)s->nsyn, sizeof(int64_t));
+    for (int64_t k = 0; k < s->nsyn; ++k) {
+        int32_t c = 0;
+        while (s->cv_begin[c + 1] <= s->syn_cv[k]) ++c;
+        s->syn_cell[k] = c;
+        s->csyn_begin[c + 1]++;
+    }
+    for (int32_t c = 0; c < s->ncell; ++c) s->csyn_begin[c + 1] += s->csyn_begin[c];
+    int64_t *fill = xcalloc((size_t)s->ncell, sizeof(int64_t));
+    for (int64_t k = 0; k < s->nsyn; ++k) {
+        int32_t c = s->syn_cell[k];
+        s->csyn[s->csyn_begin[c] + fill[c]++] = k;
+    }
+    free(fill);
+    s->ntev = 0;
+    for (int64_t k = 0; k < next; ++k) {
+        orc_tev e = {s->syn_cell[ev_syn[k]], ev_t[k], 1, ev_syn[k], 0xffffffffu, k, ev_w[k]};
+        tev_push(s, e);
+    }
+    s->tev_begin = xcalloc((size_t)s->ncell, sizeof(int64_t));
+    s->tev_end = xcalloc((size_t)s->ncell, sizeof(int64_t));
+    s->tev_head = xcalloc((size_t)s->ncell, sizeof(int64_t));
+    return 0;
+}
+
+/* one step of length dt of cell c, from its time t (operator split of
+ * Sec. II with the step's own dt) */
+static void cell_step(orc *s, int32_t c, double t, double dt) {
+    int64_t c0 = s->cv_begin[c], c1 = s->cv_begin[c + 1];
+    for (int64_t i = c0; i < c1; ++i) {
+        double v = s->V[i], I = 0.0;
+        for (int64_t k = s->ct_begin[i]; k < s->ct_begin[i + 1]; ++k) {
+            int64_t r = s->ct_reg[k];
+            double a10 = 10.0 * s->ct_area[k];
+            uint32_t mech = s->reg_mech[r];
+            if (mech & MECH_PAS) I += a10 * s->reg_gpas[r] * (v - s->reg_epas[r]);
+            if (mech & MECH_HH) {
+                double m = s->m[i], h = s->h[i], n = s->n[i];
+                I += a10 * s->reg_gna[r] * m * m * m * h * (v - E_NA);
+                I += a10 * s->reg_gk[r] * n * n * n * n * (v - E_K);
+                I += a10 * s->reg_gl[r] * (v - E_L);
+            }
+        }
+        s->I[i] = I;
+    }
+    for (int64_t q = s->csyn_begin[c]; q < s->csyn_begin[c + 1]; ++q) {
+        int64_t k = s->csyn[q], i = s->syn_cv[k];
+        s->I[i] += s->g[k] * (s->V[i] - s->syn_e[k]);
+    }
+    for (int64_t i = c0; i < c1; ++i) {
+        s->d[i] = s->cap[i] / dt;
+        s->rhs[i] = s->cap[i] / dt * s->V[i] - s->I[i];
+    }
+    for (int64_t i = c0; i < c1; ++i) {
+        int64_t p = s->parent[i];
+        if (p < 0) continue;
+        s->d[i] += s->sig[i];
+        s->d[p] += s->sig[i];
+    }
+    double vs_old = s->V[c0];
+    orc_hines_solve(c1 - c0, s->lpar + c0, s->d + c0, s->uoff + c0, s->rhs + c0);
+    for (int64_t i = c0; i < c1; ++i) s->V[i] = s->rhs[i];
+    double vs_new = s->V[c0];
+    /* READING: the crossing time interpolated linearly within the step */
+    if (vs_old < s->theta && vs_new >= s->theta)
+        record_spike(s, (uint32_t)c, -1, t + dt * (s->theta - vs_old) / (vs_new - vs_old));
+    for (int64_t i = c0; i < c1; ++i) {
+        if (!s->has_hh[i]) continue;
+        double r[6];
+        orc_hh_rates(s->V[i], r);
+        gate_update(&s->m[i], r[0], r[1], dt);
+        gate_update(&s->h[i], r[2], r[3], dt);
+        gate_update(&s->n[i], r[4], r[5], dt);
+    }
+    for (int64_t q = s->csyn_begin[c]; q < s->csyn_begin[c + 1]; ++q) {
+        int64_t k = s->csyn[q];
+        s->g[k] *= exp(-dt / s->syn_tau[k]);
+    }
+    s->nvsteps++;
+}
+
+/* cell c from its time to grid point k_end */
+static void cell_advance(orc *s, int32_t c, int64_t k_end) {
+    while (s->kcell[c] < k_end) {
+        double t = s->tcell[c];
+        int64_t k = s->kcell[c];
+        int64_t *head = &s->tev_head[c];
+        while (*head < s->tev_end[c] && s->tev[*head].t <= t) {
+            orc_tev e = s->tev[(*head)++];
+            s->g[e.syn] += 1000.0 * e.w; /* uS -> nS */
+        }
+        double grid0 = (double)k * s->dt, grid1 = (double)(k + 1) * s->dt;
+        double target = grid1;
+        if (*head < s->tev_end[c] && s->tev[*head].t < target) target = s->tev[*head].t;
+        double h = (t == grid0 && target == grid1) ? s->dt : target - t;
+        cell_step(s, c, t, h);
+        s->tcell[c] = target;
+        if (target == grid1) s->kcell[c] = k + 1;
+    }
+}
+
+/* pending events sorted by (cell, time, kind, synapse, source, index) and
+ * grouped by cell */
+static void tev_group(orc *s) {
+    if (s->ntev > 1) qsort(s->tev, (size_t)s->ntev, sizeof(orc_tev), tev_cmp);
+    int64_t at = 0;
+    for (int32_t c = 0; c < s->ncell; ++c) {
+        s->tev_begin[c] = at;
+        while (at < s->ntev && s->tev[at].cell == c) ++at;
+        s->tev_end[c] = at;
+        s->tev_head[c] = s->tev_begin[c];
+    }
+}
+
+/* the delivered events out; the epoch's spikes (sorted by gid, time) walked
+ * against their sources' connections into events at spike time + delay */
+static void varstep_exchange(orc *s) {
+    int64_t keep = 0;
+    for (int32_t c = 0; c < s->ncell; ++c)
+        for (int64_t k = s->tev_head[c]; k < s->tev_end[c]; ++k) s->tev[keep++] = s->tev[k];
+    s->ntev = keep;
+    int64_t b = s->sp_epoch_begin, e = s->nsp;
+    for (int64_t k = b; k < e; ++k) {
+        uint32_t src = s->sp[k].gid;
+        for (int64_t q = s->out_begin[src]; q < s->out_begin[src + 1]; ++q) {
+            orc_tev ev = {s->syn_cell[s->out_syn[q]], s->sp[k].t + s->out_delay_ms[q], 0, s->out_syn[q], src,
+                          s->out_id[q], s->out_w[q]};
+            tev_push(s, ev);
+        }
+    }
+    s->sp_epoch_begin = s->nsp;
+}
+
+/* every cell from the common grid point to grid point k_end (time
+ * k_end dt), epoch by epoch, spikes exchanged at each epoch end reached */
+int orc_advance_to(orc *s, int64_t k_end) {
+    if (!s->varstep) return -1;
+    while (s->k_now < k_end) {
+        int64_t ke = (s->k_now / s->K_ep + 1) * s->K_ep;
+        int64_t stop = ke < k_end ? ke : k_end;
+        tev_group(s);
+        for (int32_t c = 0; c < s->ncell; ++c) cell_advance(s, c, stop);
+        s->k_now = stop;
+        if (stop == ke) varstep_exchange(s);
+        else { /* partial epoch: drop the delivered events, keep the spikes for the epoch's end */
+            int64_t keep = 0;
+            for (int32_t c = 0; c < s->ncell; ++c)
+                for (int64_t k = s->tev_head[c]; k < s->tev_end[c]; ++k) s->tev[keep++] = s->tev[k];
+            s->ntev = keep;
+        }
+    }
+    return 0;
+}
+
+int64_t orc_varstep_steps(orc *s) { return s->nvsteps; }
+int64_t orc_varstep_grid(orc *s) { return s->k_now; }
+

@@ -513,6 +513,48 @@ def config7_dry_run_sources(n_cells: int, ranks: int, n_syn: int = 10000) -> np.
     return np.concatenate([_dry_run_sources(i, n_cells, ranks, n_syn) for i in range(n_cells)]).astype(np.uint32)
 
 
+def timed(m: dict, con_delay_ms=None, ev_t=None) -> dict:
+    """A model for the variable time step: continuous connection delays
+    (con_delay_ms, ms) and event times (ev_t, ms), by default the step-grid
+    ones (delay_steps x dt, step x dt)."""
+    out = dict(m)
+    out["con_delay_ms"] = (np.asarray(con_delay_ms, np.float64) if con_delay_ms is not None
+                           else m["con_delay"].astype(np.float64) * m["dt"])
+    out["ev_t"] = np.asarray(ev_t, np.float64) if ev_t is not None else m["ev_step"].astype(np.float64) * m["dt"]
+    return out
+
+
+def config2_timed(n_cells: int = 8192, cells=None, t_ms: float = 100.0) -> dict:
+    """The 8192-cell ring for the variable time step: the cells of config 2,
+    ring delays U(5, 5.5) ms and kicks at U(0, 1) ms (off the step grid), and
+    Poisson input at 10 Hz on each dendritic synapse (w 0.01 uS) at
+    continuous times."""
+    ids = list(range(n_cells)) if cells is None else list(cells)
+    m = config2(n_cells=n_cells, cells=ids, n_steps=int(round(t_ms / DT)))
+    delay, ev_syn, ev_t, ev_w = [], [], [], []
+    syn0 = np.concatenate([[0], np.cumsum(np.bincount(m["syn_cell"], minlength=len(ids)))])
+    for k, i in enumerate(ids):
+        ss = np.random.SeedSequence(SEED_BASE + 2, spawn_key=(int(i), 3))
+        rng = np.random.Generator(np.random.PCG64(ss))
+        delay.append(rng.uniform(5.0, 5.5))
+        ev_syn.append(syn0[k])
+        ev_t.append(rng.uniform(0.0, 1.0))
+        ev_w.append(0.05)
+        for q in range(int(syn0[k]) + 1, int(syn0[k + 1])):
+            times = np.sort(rng.uniform(0.0, t_ms, rng.poisson(10.0 * t_ms * 1e-3)))
+            ev_syn.extend([q] * len(times))
+            ev_t.extend(times.tolist())
+            ev_w.extend([0.01] * len(times))
+    # connection j ends on the cell ids[j'] whose ring predecessor fired; the
+    # delay drawn for that destination cell
+    dst_pos = {int(g): k for k, g in enumerate(ids)}
+    d_ms = np.array([delay[dst_pos[int(m["gids"][int(dc)])]] for dc in m["con_dst"]], np.float64)
+    m["ev_syn"] = np.array(ev_syn, np.uint32)
+    m["ev_step"] = np.zeros(len(ev_syn), np.int64)
+    m["ev_w"] = np.array(ev_w, np.float64)
+    return timed(m, con_delay_ms=d_ms, ev_t=np.array(ev_t, np.float64))
+
+
 def ring_light_cone(n_cells: int, target: int, n_steps: int, delay: int = 200) -> list[int]:
     """Cells of the config-2 ring whose spikes can reach `target` within
     n_steps: a spike of cell target-j needs at least j*(delay+1) steps."""
