@@ -197,6 +197,38 @@ int arb_build_cells(const arb_cell *cells, int32_t n_cells, const arb_branch *br
                     int64_t n_ev, const arb_iclamp *stim, int32_t n_stim,
                     const arb_params *p, arb_sim *out);
 
+/* Build a simulation that shortens steps at event times (Sec. II: the
+ * step is cut so that every event falls at the beginning of a step, with
+ * each cell keeping its own time).  The model is as for arb_build_cells
+ * with continuous times in place of step indices: delay_ms[k] (>= dt) is the
+ * delay of conn[k] (its delay_steps is validated but not used) and t_ms[k]
+ * (in [0, 2^31 dt)) the time of ev[k] (its step is not used); either array
+ * may be NULL when its count is 0.  A cell in [k dt, (k+1) dt) takes every
+ * event due at or before its time (network events first), then steps to
+ * (k+1) dt or to its next event's time if that comes first; a step from
+ * k dt to (k+1) dt has length dt exactly.  A spike's time is its threshold
+ * crossing interpolated within its step, and its events arrive at that time
+ * plus the delay.  Epochs are K grid steps with K dt at most the minimum
+ * delay (epoch_steps = 0: the largest such K), so arb_step(n) still advances
+ * every cell by n steps of the grid.  arb_get_spikes reports step = -1 and
+ * the spike time, sorted by (time, gid).
+ * Runs one cell per workgroup in the register-resident layout
+ * (coef_mode and cells_per_pack are set by the library, block_threads is
+ * honoured if given, ARB_FLAG_AUTOTUNE is ignored).  ARB_EINVAL for current
+ * clamps, ARB_FLAG_GRADIENTS, dry_run_ranks > 1, a cell whose synapses do
+ * not fit LDS, and for the state calls (arb_get_state, arb_set_state) and
+ * arb_grad_forward on the sim. */
+int arb_build_cells_timed(const arb_cell *cells, int32_t n_cells, const arb_branch *branches,
+                          int64_t n_branches, const arb_synapse *syn, int64_t n_syn,
+                          const arb_connection *conn, const double *delay_ms, int64_t n_conn,
+                          const arb_event *ev, const double *t_ms, int64_t n_ev,
+                          const arb_params *p, arb_sim *out);
+
+/* Steps taken by all cells since the build into *n_out: with the variable
+ * time step, every cell's full and shortened steps (Sec. II); otherwise the
+ * completed steps times the cell count.  Synchronises the sim's stream. */
+int arb_get_step_count(arb_sim s, int64_t *n_out);
+
 /* Advance every cell by n_steps steps of dt (Sec. II operator splitting:
  * events due at the step start, currents at V(t), implicit Euler + Hines for
  * V(t+dt), states with the new V, threshold test; spike exchange at each

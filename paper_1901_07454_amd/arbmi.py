@@ -71,7 +71,8 @@ class arb_info(C.Structure):
 EXPORTS = ["arb_build_cells", "arb_step", "arb_get_voltages", "arb_get_spikes", "arb_set_probes",
            "arb_get_trace", "arb_set_params", "arb_grad_forward", "arb_grad_backward",
            "arb_get_state", "arb_set_state", "arb_get_info", "arb_get_kernel_time", "arb_sync",
-           "arb_free", "arb_last_error", "arb_plan_layout", "arb_get_voltages_noalloc"]
+           "arb_free", "arb_last_error", "arb_plan_layout", "arb_get_voltages_noalloc", "arb_build_cells_timed",
+           "arb_get_step_count"]
 
 _lib = None
 
@@ -92,6 +93,9 @@ def load():
         P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {
             "arb_build_cells": [P, I32, P, I64, P, I64, P, I64, P, I64, P, I32, C.POINTER(arb_params), C.POINTER(P)],
+            "arb_build_cells_timed": [P, I32, P, I64, P, I64, P, P, I64, P, P, I64, C.POINTER(arb_params),
+                                      C.POINTER(P)],
+            "arb_get_step_count": [P, C.POINTER(I64)],
             "arb_step": [P, I64],
             "arb_get_voltages": [P, P, I64, C.c_int],
             "arb_get_voltages_noalloc": [P, P, I64],
@@ -150,6 +154,27 @@ def arb_build_cells(cells, branches, syn, conn, ev, stim, params: arb_params):
     _check(L.arb_build_cells(_ptr(c), len(c), _ptr(b), len(b), _ptr(s), len(s), _ptr(k), len(k), _ptr(e), len(e),
                              _ptr(i), len(i), C.byref(params), C.byref(out)))
     return out
+
+
+def arb_build_cells_timed(cells, branches, syn, conn, delay_ms, ev, t_ms, params: arb_params):
+    L = load()
+    out = C.c_void_p()
+    arrs = [np.ascontiguousarray(x, dtype=d) for x, d in
+            ((cells, CELL), (branches, BRANCH), (syn, SYNAPSE), (conn, CONNECTION), (ev, EVENT))]
+    c, b, s, k, e = arrs
+    dm = np.ascontiguousarray(delay_ms, dtype=np.float64)
+    tm = np.ascontiguousarray(t_ms, dtype=np.float64)
+    if len(dm) != len(k) or len(tm) != len(e):
+        raise ValueError("one delay per connection and one time per event")
+    _check(L.arb_build_cells_timed(_ptr(c), len(c), _ptr(b), len(b), _ptr(s), len(s), _ptr(k), _ptr(dm), len(k),
+                                   _ptr(e), _ptr(tm), len(e), C.byref(params), C.byref(out)))
+    return out
+
+
+def arb_get_step_count(sim) -> int:
+    n = C.c_int64()
+    _check(load().arb_get_step_count(sim, C.byref(n)))
+    return n.value
 
 
 def arb_plan_layout(cells, branches, syn, conn, ev, stim, params: arb_params) -> dict:
@@ -282,7 +307,10 @@ class Simulation:
 
     def __init__(self, m: dict, epoch_steps: int = 0, block_threads: int = 0, coef_mode: int = 0,
                  cells_per_pack: int = 0, flags: int = 0, spike_capacity: int = 0, event_capacity: int = 0, stream=None,
-                 use_torch_allocator: bool = True, dry_run_ranks: int = 0):
+                 use_torch_allocator: bool = True, dry_run_ranks: int = 0, timed: bool | None = None):
+        """timed: build for the variable time step (arb_build_cells_timed) with
+        the model's continuous delays and event times (con_delay_ms, ev_t);
+        None = when the model has them."""
         import torch
         self._torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -311,7 +339,16 @@ class Simulation:
             p.alloc, p.free = self._cb
         self.params = p
         self.m = m
-        self.h = arb_build_cells(*model_structs(m), p)
+        if timed is None:
+            timed = "con_delay_ms" in m and "ev_t" in m
+        self.timed = bool(timed)
+        cells, br, syn, con, ev, ic = model_structs(m)
+        if self.timed:
+            if len(ic):
+                raise ValueError("the variable time step takes no current clamps")
+            self.h = arb_build_cells_timed(cells, br, syn, con, m["con_delay_ms"], ev, m["ev_t"], p)
+        else:
+            self.h = arb_build_cells(cells, br, syn, con, ev, ic, p)
         self.info = arb_get_info(self.h)
 
     def close(self):
@@ -364,6 +401,9 @@ class Simulation:
 
     def sync(self):
         arb_sync(self.h)
+
+    def step_count(self) -> int:
+        return arb_get_step_count(self.h)
 
     def refresh_info(self):
         self.info = arb_get_info(self.h)

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libarbmi.so")
 SOURCES = ["kernels.hip", "reg_kernels.hip", "reg_adjoint_kernels.hip", "adjoint_kernels.hip", "arbmi.cpp", "lower.cpp",
-           "plan.cpp", "adjoint.cpp", "autotune.cpp", "noalloc.hip"]
+           "plan.cpp", "adjoint.cpp", "autotune.cpp", "noalloc.hip", "var_kernels.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -17,7 +17,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 # a whole launch; hoisting the FP64 exp/expm1 polynomial constants out of the
 # step loop (machine LICM) would pin another ~40 VGPRs and cost occupancy.
 EXTRA = {"reg_kernels.hip": ["-mllvm", "-disable-machine-licm"],
-         "reg_adjoint_kernels.hip": ["-mllvm", "-disable-machine-licm"]}
+         "reg_adjoint_kernels.hip": ["-mllvm", "-disable-machine-licm"],
+         "var_kernels.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
 def build(verbose: bool = False) -> str:

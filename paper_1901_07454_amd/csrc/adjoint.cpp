@@ -206,6 +206,7 @@ int setup(Sim* s, int64_t n, int64_t k) {
 int grad_forward(Sim* s, int64_t n_steps, int32_t ckpt_every, double* trace_dev) {
     if (n_steps <= 0 || ckpt_every <= 0) return set_error(ARB_EINVAL, "n_steps and ckpt_every must be positive");
     if (!trace_dev) return set_error(ARB_EINVAL, "trace_dev is NULL");
+    if (s->timed) return set_error(ARB_EINVAL, "the variable time step has no gradients");
     if (s->step + n_steps >= (int64_t(1) << 31)) return set_error(ARB_EINVAL, "step count beyond 2^31");
     s->grad_valid = false;
     int rc = setup(s, n_steps, std::min<int64_t>(ckpt_every, n_steps));

@@ -155,6 +155,19 @@ StepArgs Sim::step_args() const {
     return a;
 }
 
+VarArgs Sim::var_args() const {
+    VarArgs v{};
+    v.xe_t = d_xe_t;
+    v.bk_t = d_bk_t;
+    v.cap = d_cap;
+    v.gmem = d_gmem;
+    v.sigsum = d_sigsum;
+    v.uoff = d_uoff;
+    v.syn_tau = d_syn_tau;
+    v.pk_steps = d_pk_steps;
+    return v;
+}
+
 // The step kernel over every pack: one launch per class, the first on the
 // sim's stream, the others on auxiliary streams forked from and joined back
 // into it.
@@ -162,7 +175,10 @@ int Sim::launch_classes(const StepArgs& a0) {
     if (classes.size() <= 1) {
         StepArgs a = a0;
         a.pack0 = 0;
-        HIP_TRY(launch_step(a, cfg, int32_t(L.packs.size()), st));
+        if (timed)
+            HIP_TRY(launch_var_step(a, var_args(), cfg, int32_t(L.packs.size()), st));
+        else
+            HIP_TRY(launch_step(a, cfg, int32_t(L.packs.size()), st));
         return ARB_OK;
     }
     HIP_TRY(hipEventRecord(fork_ev[0], st));
@@ -175,7 +191,10 @@ int Sim::launch_classes(const StepArgs& a0) {
         lc.syn_hbm = classes[c].hbm;
         if (cfg.coef_mode == 3) lc.reg_slots = classes[c].slots;
         hipStream_t s_c = (c == 0) ? st : aux[c - 1];
-        HIP_TRY(launch_step(a, lc, classes[c].npack, s_c));
+        if (timed)
+            HIP_TRY(launch_var_step(a, var_args(), lc, classes[c].npack, s_c));
+        else
+            HIP_TRY(launch_step(a, lc, classes[c].npack, s_c));
     }
     for (size_t c = 1; c < classes.size(); ++c) {
         HIP_TRY(hipEventRecord(join_ev[c - 1], aux[c - 1]));
@@ -202,6 +221,29 @@ int Sim::launch_pull(int64_t epoch, const int64_t* epoch_ptr) {
     ix.sx_step = d_sx_step;
     ix.ctr = d_ctr;
     HIP_TRY(launch_index_spikes(ix, st));
+    if (timed) {
+        TimedPullArgs x{};
+        x.in_off = d_in_off;
+        x.cr_src = d_cr_src;
+        x.cr_delay_ms = d_cr_delay_ms;
+        x.cr_syn = d_cr_syn;
+        x.cr_w = d_cr_w;
+        x.sx_off = d_sx_off;
+        x.sx_step = d_sx_step;
+        x.n_src = L.n_src;
+        x.bk_off = d_bk_off;
+        x.bk_q = d_bk_q;
+        x.bk_w = d_bk_w;
+        x.bk_t = d_bk_t;
+        x.ctr = d_ctr;
+        x.epoch_ptr = epoch_ptr;
+        x.epoch = epoch;
+        x.dt = L.dt;
+        x.bk_cap = bk_cap;
+        x.epoch_steps = K;
+        HIP_TRY(launch_pull_timed(x, int32_t(L.packs.size()), st));
+        return ARB_OK;
+    }
     PullArgs x{};
     x.in_off = d_in_off;
     x.cr_src = d_cr_src;
@@ -473,6 +515,16 @@ int build_device(Sim* s) {
     s->d_xe_step = dupload(s, L.xe_step, rc);
     s->d_xe_syn = dupload(s, L.xe_syn, rc);
     s->d_xe_w = dupload(s, L.xe_w, rc);
+    if (s->timed) {
+        s->d_xe_t = dupload(s, L.xe_t, rc);
+        s->d_cr_delay_ms = dupload(s, L.cr_delay_ms, rc);
+        s->d_cap = dupload(s, L.cap, rc);
+        s->d_gmem = dupload(s, L.gmem, rc);
+        s->d_sigsum = dupload(s, L.sigsum, rc);
+        s->d_uoff = dupload(s, L.uoff, rc);
+        s->d_syn_tau = dupload(s, L.syn_tau, rc);
+        s->d_pk_steps = dupload(s, std::vector<int64_t>(np, 0), rc);
+    }
     std::vector<int64_t> xcur(np);
     for (int k = 0; k < np; ++k) xcur[k] = L.packs[k].xe0;
     s->xcur0 = xcur;
@@ -514,6 +566,7 @@ int build_device(Sim* s) {
         if (rc == ARB_OK) rc = s->fill_zero(s->d_bk_nxt, noff * sizeof(uint32_t));
         s->d_bk_q = dalloc<int32_t>(s, size_t(np) * size_t(s->bk_cap), rc);
         s->d_bk_w = dalloc<double>(s, size_t(np) * size_t(s->bk_cap), rc);
+        if (s->timed) s->d_bk_t = dalloc<double>(s, size_t(np) * size_t(s->bk_cap), rc);
     }
     const size_t nh = std::max<size_t>(1, size_t(s->n_hist) * s->hist_cap);
     s->d_hist_gid = dalloc<uint32_t>(s, nh, rc);
@@ -562,10 +615,40 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
     opt.reg_slots = plan.coef_mode == 3 ? plan.reg_slots : 0;
     opt.reg_len = plan.reg_len;
     opt.grads = (p->flags & ARB_FLAG_GRADIENTS) != 0;
-    int rc = lower_model(m.cells, m.n_cells, m.br, m.n_br, m.syn, m.n_syn, m.conn, m.n_conn, m.ev, m.n_ev, m.ic,
+    opt.conn_delay_ms = m.conn_delay_ms;
+    opt.ev_t_ms = m.ev_t_ms;
+    const bool timed = m.conn_delay_ms != nullptr || m.ev_t_ms != nullptr;
+    int rc = ARB_OK;
+    if (timed) {
+        // one cell per workgroup in the register layout; unless the caller
+        // fixed the workgroup size, the smallest one whose register slots
+        // hold every cell
+        opt.coef_mode = 3;
+        opt.max_cells_per_pack = 1;
+        opt.lds_budget = opt.lds_hard_max;
+        for (int T : {64, 128, 256}) {
+            if (p->block_threads && T != p->block_threads) continue;
+            arb_params pt = *p;
+            pt.block_threads = T;
+            pt.coef_mode = 3;
+            pt.cells_per_pack = 1;
+            const Plan pl = choose_plan(m.cells, m.n_cells, m.br, m.n_br, pt, d.lds_max, d.n_cu);
+            opt.block_threads = T;
+            opt.reg_slots = pl.reg_slots;
+            opt.reg_len = pl.reg_len;
+            s->L = Lowered();
+            err.clear();
+            rc = lower_model(m.cells, m.n_cells, m.br, m.n_br, m.syn, m.n_syn, m.conn, m.n_conn, m.ev, m.n_ev, m.ic,
+                             m.n_ic, *p, opt, s->L, err);
+            if (rc == ARB_OK || (err.find("LDS") == std::string::npos && err.find("register") == std::string::npos))
+                break;
+        }
+    } else {
+        rc = lower_model(m.cells, m.n_cells, m.br, m.n_br, m.syn, m.n_syn, m.conn, m.n_conn, m.ev, m.n_ev, m.ic,
                          m.n_ic, *p, opt, s->L, err);
+    }
     const bool auto_mode = p->coef_mode == 0 || (p->flags & ARB_FLAG_AUTOTUNE);
-    if (rc == ARB_EINVAL && auto_mode && opt.coef_mode != 2 &&
+    if (rc == ARB_EINVAL && auto_mode && !timed && opt.coef_mode != 2 &&
         (err.find("LDS") != std::string::npos || err.find("register") != std::string::npos)) {
         // a cell too large for LDS- or register-resident coefficients: stream them
         opt.coef_mode = 2;
@@ -587,6 +670,7 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
         err = "no HIP device available";
         return ARB_EHIP;
     }
+    s->timed = s->L.timed;
     const bool net = !s->L.cr_src.empty();
     s->K = p->epoch_steps > 0 ? p->epoch_steps : (net ? std::min(s->L.min_delay, kMaxEpochSteps) : 1000);
     if (net && s->K > kMaxEpochSteps) {
@@ -696,6 +780,7 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
         }
     }
     hipError_t he = prepare_step_kernels(int(d.lds_max));
+    if (he == hipSuccess && s->timed) he = prepare_var_kernels(int(d.lds_max));
     if (he != hipSuccess) {
         destroy_sim(s);
         err = std::string("prepare_step_kernels: ") + hipGetErrorString(he);
@@ -738,12 +823,12 @@ void destroy_sim(Sim* s) {
 
 }  // namespace arbmi
 
-extern "C" {
+namespace {
 
-int arb_build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* branches, int64_t n_branches,
-                    const arb_synapse* syn, int64_t n_syn, const arb_connection* conn, int64_t n_conn,
-                    const arb_event* ev, int64_t n_ev, const arb_iclamp* stim, int32_t n_stim,
-                    const arb_params* p, arb_sim* out) {
+int build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* branches, int64_t n_branches,
+                const arb_synapse* syn, int64_t n_syn, const arb_connection* conn, int64_t n_conn,
+                const arb_event* ev, int64_t n_ev, const arb_iclamp* stim, int32_t n_stim,
+                const double* conn_delay_ms, const double* ev_t_ms, const arb_params* p, arb_sim* out) {
     g_err.clear();
     if (!out) return fail(ARB_EINVAL, "out is NULL");
     *out = nullptr;
@@ -765,9 +850,12 @@ int arb_build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* br
             d.lds_max = v;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d.dev) == hipSuccess && v > 0) d.n_cu = v;
     }
-    const ModelView m{cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim};
+    ModelView m{cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim};
+    m.conn_delay_ms = conn_delay_ms;
+    m.ev_t_ms = ev_t_ms;
+    const bool timed = conn_delay_ms != nullptr || ev_t_ms != nullptr;
     arb_params q = *p;
-    if ((p->flags & ARB_FLAG_AUTOTUNE) && d.have_dev && p->block_threads == 0 && p->coef_mode == 0 &&
+    if ((p->flags & ARB_FLAG_AUTOTUNE) && d.have_dev && !timed && p->block_threads == 0 && p->coef_mode == 0 &&
         p->cells_per_pack == 0)
         q = autotune(m, *p, d);
     Sim* s = nullptr;
@@ -775,6 +863,50 @@ int arb_build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* br
     const int rc = build_sim(m, q, d, &s, err);
     if (rc != ARB_OK) return fail(rc, err);
     *out = s;
+    return ARB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int arb_build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* branches, int64_t n_branches,
+                    const arb_synapse* syn, int64_t n_syn, const arb_connection* conn, int64_t n_conn,
+                    const arb_event* ev, int64_t n_ev, const arb_iclamp* stim, int32_t n_stim,
+                    const arb_params* p, arb_sim* out) {
+    return build_cells(cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, stim, n_stim,
+                       nullptr, nullptr, p, out);
+}
+
+int arb_build_cells_timed(const arb_cell* cells, int32_t n_cells, const arb_branch* branches, int64_t n_branches,
+                          const arb_synapse* syn, int64_t n_syn, const arb_connection* conn, const double* delay_ms,
+                          int64_t n_conn, const arb_event* ev, const double* t_ms, int64_t n_ev,
+                          const arb_params* p, arb_sim* out) {
+    static const double kNone = 0.0;  // a non-null marker for empty arrays
+    if ((n_conn > 0 && !delay_ms) || (n_ev > 0 && !t_ms)) {
+        g_err.clear();
+        if (out) *out = nullptr;
+        return fail(ARB_EINVAL, "delay_ms and t_ms must be given for every connection and event");
+    }
+    return build_cells(cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, nullptr, 0,
+                       delay_ms ? delay_ms : &kNone, t_ms ? t_ms : &kNone, p, out);
+}
+
+int arb_get_step_count(arb_sim s_, int64_t* n_out) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s || !n_out) return fail(ARB_EINVAL, "null argument");
+    *n_out = 0;
+    const int64_t np = int64_t(s->L.packs.size());
+    if (!s->timed) {  // every cell takes every step of the grid
+        *n_out = s->step * int64_t(s->L.n_cells);
+        return ARB_OK;
+    }
+    std::vector<int64_t> c(size_t(std::max<int64_t>(np, 1)), 0);
+    HIP_TRY(hipStreamSynchronize(s->st));
+    if (np) HIP_TRY(hipMemcpy(c.data(), s->d_pk_steps, size_t(np) * 8, hipMemcpyDeviceToHost));
+    int64_t tot = 0;
+    for (int64_t k = 0; k < np; ++k) tot += c[size_t(k)];
+    *n_out = tot;
     return ARB_OK;
 }
 
@@ -895,14 +1027,20 @@ int arb_get_spikes(arb_sim s_, arb_spike* dst, int64_t cap, int64_t* n_out) {
         HIP_TRY(hipStreamSynchronize(s->st));
         std::vector<int64_t> idx(n);
         for (int64_t i = 0; i < n; ++i) idx[i] = i;
-        std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
-            if (stp[a] != stp[b]) return stp[a] < stp[b];
-            return gid[a] < gid[b];
-        });
+        if (s->timed)  // the step field carries the time's bits: order by time
+            std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+                if (t[a] != t[b]) return t[a] < t[b];
+                return gid[a] < gid[b];
+            });
+        else
+            std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+                if (stp[a] != stp[b]) return stp[a] < stp[b];
+                return gid[a] < gid[b];
+            });
         for (int64_t i = 0; i < n; ++i) {
             dst[i].gid = gid[idx[i]];
             dst[i].reserved = 0;
-            dst[i].step = stp[idx[i]];
+            dst[i].step = s->timed ? -1 : stp[idx[i]];
             dst[i].t_ms = t[idx[i]];
         }
     }
@@ -1023,6 +1161,7 @@ int arb_set_params(arb_sim s_, const double* theta, int64_t n) {
     if (rc == ARB_OK) rc = s->upload(s->d_beta, L.beta.data(), L.beta.size() * 8);
     if (rc == ARB_OK) rc = s->upload(s->d_hh_gna, L.hh_gna.data(), L.hh_gna.size() * 8);
     if (rc == ARB_OK) rc = s->upload(s->d_hh_gk, L.hh_gk.data(), L.hh_gk.size() * 8);
+    if (rc == ARB_OK && s->timed) rc = s->upload(s->d_gmem, L.gmem.data(), L.gmem.size() * 8);
     if (rc != ARB_OK) return rc;
     HIP_TRY(hipStreamSynchronize(s->st));
     s->grad_valid = false;
@@ -1032,6 +1171,7 @@ int arb_set_params(arb_sim s_, const double* theta, int64_t n) {
 int arb_get_state(arb_sim s_, void* blob, int64_t cap, int64_t* n_out) {
     Sim* s = static_cast<Sim*>(s_);
     if (!s || !n_out) return fail(ARB_EINVAL, "null argument");
+    if (s->timed) return fail(ARB_EINVAL, "state blobs are not kept for the variable time step");
     const Lowered& L = s->L;
     const StateShape sh = s->state_shape();
     int64_t bytes[kStateParts];
@@ -1060,6 +1200,7 @@ int arb_get_state(arb_sim s_, void* blob, int64_t cap, int64_t* n_out) {
 int arb_set_state(arb_sim s_, const void* blob, int64_t n) {
     Sim* s = static_cast<Sim*>(s_);
     if (!s || !blob) return fail(ARB_EINVAL, "null argument");
+    if (s->timed) return fail(ARB_EINVAL, "state blobs are not kept for the variable time step");
     const Lowered& L = s->L;
     const StateShape sh = s->state_shape();
     // every value a kernel indexes with must lie in range before it reaches

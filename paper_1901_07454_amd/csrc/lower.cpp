@@ -21,6 +21,7 @@
 #include "lower.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -266,6 +267,37 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         L.min_delay = q == 0 ? K.delay_steps : std::min(L.min_delay, K.delay_steps);
         L.max_delay = std::max(L.max_delay, K.delay_steps);
     }
+    L.timed = opt.conn_delay_ms != nullptr || opt.ev_t_ms != nullptr;
+    if (L.timed) {
+        // the variable step runs one cell per workgroup in the register
+        // layout; clamps, gradients and the dry run are fixed-step features
+        if (n_ic > 0) { err = "the variable time step takes no current clamps"; return ARB_EINVAL; }
+        if (opt.grads) { err = "the variable time step has no gradients"; return ARB_EINVAL; }
+        if (p.dry_run_ranks > 1) { err = "the variable time step has no dry-run mode"; return ARB_EINVAL; }
+        if (opt.coef_mode != 3 || opt.max_cells_per_pack != 1) {
+            err = "the variable time step needs the register layout with one cell per pack"; return ARB_EINVAL;
+        }
+        if ((n_ev && !opt.ev_t_ms) || (n_conn && !opt.conn_delay_ms)) { err = "missing event times or delays"; return ARB_EINVAL; }
+        // continuous times: an epoch of K grid steps must end before any
+        // event of its spikes can arrive (K dt <= the minimum delay)
+        for (int64_t q = 0; q < n_ev; ++q)
+            if (!(opt.ev_t_ms[q] >= 0.0) || !(opt.ev_t_ms[q] < double(int64_t(1) << 31) * dt)) {
+                err = fmt("event %lld: time out of range", (long long)q); return ARB_EINVAL;
+            }
+        for (int64_t q = 0; q < n_conn; ++q) {
+            const double dm = opt.conn_delay_ms[q];
+            if (!(dm >= dt) || !std::isfinite(dm)) { err = fmt("connection %lld: delay_ms must be at least dt", (long long)q); return ARB_EINVAL; }
+            L.min_delay_ms = q == 0 ? dm : std::min(L.min_delay_ms, dm);
+            L.max_delay_ms = std::max(L.max_delay_ms, dm);
+        }
+        if (n_conn) {
+            int64_t k = int64_t(L.min_delay_ms / dt);
+            while (double(k + 1) * dt <= L.min_delay_ms) ++k;
+            while (k > 1 && double(k) * dt > L.min_delay_ms) --k;
+            L.min_delay = int32_t(std::min<int64_t>(k, INT32_MAX));
+            L.max_delay = int32_t(std::min<double>(std::ceil(L.max_delay_ms / dt) + 1.0, double(INT32_MAX)));
+        }
+    }
     if (n_conn && p.epoch_steps > L.min_delay) {
         err = fmt("epoch_steps %d exceeds the minimum delay %d", p.epoch_steps, L.min_delay); return ARB_EINVAL;
     }
@@ -426,7 +458,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             }
             // a cell too large for the register layout's LDS alone keeps its
             // hh conductances and nonlinear right-hand sides in HBM
-            if (cur.cells.size() == 1 && S > 0 && !opt.grads && coef_mode == 3 &&
+            if (cur.cells.size() == 1 && S > 0 && !opt.grads && !L.timed && coef_mode == 3 &&
                 exact_lds(cur, coef_mode) > opt.lds_hard_max) {
                 cur.hhg = true;
                 if (exact_lds(cur, coef_mode) > opt.lds_hard_max) cur.hhg = false;
@@ -523,6 +555,10 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         for (int32_t c : pp.cells) D.binary = D.binary && max_children[c] <= 2;
         D.syn_global = (S > 0 && 24 * pp.nsyn > kSynLdsMax) ? 1 : 0;
         D.hh_global = pp.hhg ? 1 : 0;
+        if (L.timed && D.syn_global) {
+            err = "the variable time step keeps every synapse in LDS: a cell has too many synapses";
+            return ARB_EINVAL;
+        }
         // the register-resident kernel's empty slots write to a slot no CV
         // uses: the first pad row if there is one, else one past the end
         D.spare = D.nslot;
@@ -591,10 +627,14 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
     L.F.assign(L.n_slots, 0.0);
     L.invd.assign(L.n_slots, 0.0);
     L.d_elim.assign(L.n_slots, 0.0);
+    L.sigsum.assign(L.n_slots, 0.0);
+    L.uoff.assign(L.n_slots, 0.0);
     for (int32_t c = 0; c < n_cells; ++c) {
         const CellCV& G = geo[c];
         const int64_t cv0 = L.cell_cv0[c];
         std::vector<double> d(G.ncv);
+        std::vector<double> ss(G.ncv, 0.0);
+        for (int i = 1; i < G.ncv; ++i) { ss[i] += G.sig[i]; ss[G.parent[i]] += G.sig[i]; }
         for (int i = 0; i < G.ncv; ++i) d[i] = G.cap[i] / dt;
         for (int i = 1; i < G.ncv; ++i) { d[i] += G.sig[i]; d[G.parent[i]] += G.sig[i]; }
         std::vector<double> Fl(G.ncv, 0.0);
@@ -606,6 +646,8 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         for (int i = 0; i < G.ncv; ++i) {
             const int64_t s = L.perm[cv0 + i];
             L.cap[s] = G.cap[i];
+            L.sigsum[s] = ss[i];
+            L.uoff[s] = (i == 0) ? 0.0 : -G.sig[i];
             L.F[s] = Fl[i];
             L.d_elim[s] = d[i];
             L.invd[s] = 1.0 / d[i];
@@ -668,6 +710,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             L.syn_global[pos] = q;
             L.syn_e[pos] = syn[q].e_rev_mV;
             L.syn_decay[pos] = std::exp(-dt / syn[q].tau_ms);
+            L.syn_tau[pos] = syn[q].tau_ms;
         };
         const int64_t nhere = int64_t(here.size());
         const int64_t group = D.syn_global ? int64_t(T) : 1;
@@ -680,6 +723,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             L.syn_global.resize(base + len, -1);
             L.syn_e.resize(base + len, 0.0);
             L.syn_decay.resize(base + len, 0.0);
+            L.syn_tau.resize(base + len, 1.0);
             for (int64_t t = 0; t < w; ++t) {
                 NlDesc& N = L.nl[nl_first + u0 + t];
                 N.syn0 = int32_t(base + t - D.syn0);
@@ -728,6 +772,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
     L.hh_gna.assign(L.hh_cv.size(), 0.0);
     L.hh_gk.assign(L.hh_cv.size(), 0.0);
     L.glin_extra.assign(L.n_cv, 0.0);
+    L.gmem.assign(L.n_slots, 0.0);
     recompute_coefficients(L);
     // the register-resident kernel needs only as many slots as the rounds use
     if (L.reg_slots > 0) {
@@ -744,12 +789,14 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
             const int64_t pa = key_pack(a), pb = key_pack(b);
             if (pa != pb) return pa < pb;
+            if (opt.ev_t_ms && opt.ev_t_ms[a] != opt.ev_t_ms[b]) return opt.ev_t_ms[a] < opt.ev_t_ms[b];
             if (ev[a].step != ev[b].step) return ev[a].step < ev[b].step;
             const int64_t sa = L.syn_pack_index[ev[a].syn], sb = L.syn_pack_index[ev[b].syn];
             if (sa != sb) return sa < sb;
             return a < b;
         });
         L.xe_step.resize(n_ev);
+        if (opt.ev_t_ms) L.xe_t.resize(n_ev);
         L.xe_syn.resize(n_ev);
         L.xe_w.resize(n_ev);
         for (auto& D : L.packs) { D.xe0 = 0; D.xe1 = 0; }
@@ -759,6 +806,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             while (at < n_ev && key_pack(idx[at]) == pk) {
                 const int64_t q = idx[at];
                 L.xe_step[at] = ev[q].step;
+                if (opt.ev_t_ms) L.xe_t[at] = opt.ev_t_ms[q];
                 L.xe_syn[at] = int32_t(L.syn_pack_index[ev[q].syn] - L.packs[pk].syn0);
                 L.xe_w[at] = 1000.0 * ev[q].w_uS;  // uS -> nS
                 ++at;
@@ -790,6 +838,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         L.cr_pack.resize(n_conn);
         L.cr_syn.resize(n_conn);
         L.cr_delay.resize(n_conn);
+        if (opt.conn_delay_ms) L.cr_delay_ms.resize(n_conn);
         L.cr_src.resize(n_conn);
         L.cr_w.resize(n_conn);
         std::vector<int64_t> in_per_pack(n_packs, 0);
@@ -799,6 +848,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             L.cr_pack[r] = int32_t(pk);
             L.cr_syn[r] = int32_t(L.syn_pack_index[K.syn] - L.packs[pk].syn0);
             L.cr_delay[r] = K.delay_steps;
+            if (opt.conn_delay_ms) L.cr_delay_ms[r] = opt.conn_delay_ms[idx[r]];
             L.cr_src[r] = K.src;
             L.cr_w[r] = 1000.0 * K.w_uS;
             in_per_pack[pk]++;
@@ -923,6 +973,7 @@ void recompute_coefficients(Lowered& L) {
         const int64_t s = L.perm[i];
         L.alpha[s] = L.cap[s] / dt - G - gl;
         L.beta[s] = GE + gl * kEL;
+        L.gmem[s] = G + gl;
         L.glin_extra[i] = gl;
     }
     for (size_t q = 0; q < L.hh_cv.size(); ++q) {

@@ -41,6 +41,9 @@ struct Lowered {
     std::vector<double> cap;                  // pF (0 in padding)
     std::vector<double> alpha, beta, F, invd; // step coefficients
     std::vector<double> d_elim;               // eliminated diagonal (kept for checks)
+    std::vector<double> sigsum;               // sum of the axial conductances at the CV (nS)
+    std::vector<double> uoff;                 // -sigma to the parent CV (0 at a soma and in padding)
+    std::vector<double> gmem;                 // linear membrane conductance (pas, hh leak; nS)
     std::vector<int64_t> perm;                // user CV -> global slot
     std::vector<int32_t> slot_cell;           // global slot -> gid (-1 padding)
 
@@ -60,21 +63,26 @@ struct Lowered {
     std::vector<int64_t> syn_global;          // pack-order index -> global synapse
     std::vector<int64_t> syn_pack_index;      // global synapse -> pack-order index
     std::vector<double> syn_e, syn_decay;
+    std::vector<double> syn_tau;              // ms (variable step: decay over any step length)
     // clamps, per pack, ordered by (slot, input order)
     std::vector<int32_t> ic_slot;             // pack-local slot
     std::vector<int64_t> ic_on, ic_off;
     std::vector<double> ic_amp;               // pA
     // external events, pack order
     std::vector<int64_t> xe_step;
+    std::vector<double> xe_t;                 // variable step: event times (ms)
     std::vector<int32_t> xe_syn;              // pack-local synapse
     std::vector<double> xe_w;                 // nS
     // connections: ranks sorted by (dst pack, dst pack-local synapse, src, index)
     int64_t n_src = 0;                        // source gids: n_cells, or R n_cells in dry-run mode
     std::vector<int32_t> cr_pack, cr_syn, cr_delay;
+    std::vector<double> cr_delay_ms;          // variable step: delays (ms)
     std::vector<uint32_t> cr_src;             // source gid of each rank
     std::vector<double> cr_w;                 // nS
     std::vector<int64_t> in_off;              // [n_packs + 1] first rank of each pack
     int32_t dry_run_ranks = 1;                // R: ranks the exchange emulates (1 = none)
+    bool timed = false;                       // variable time step (continuous event times)
+    double min_delay_ms = 0, max_delay_ms = 0;
     int32_t min_delay = 0, max_delay = 0;
     int64_t max_in_per_pack = 0;              // incoming connections of the busiest pack
     int64_t n_hh_total = 0;
@@ -90,6 +98,10 @@ struct LowerOptions {
     int32_t reg_len = 8;              // and the longest branch it takes
     bool grads = false;               // packs must also fit the adjoint kernel (register layout:
                                       // its LDS, and synapse state in LDS)
+    // variable time step: continuous connection delays (ms, input order) and
+    // external event times (ms, input order); both null for the fixed step
+    const double* conn_delay_ms = nullptr;
+    const double* ev_t_ms = nullptr;
 };
 
 // Validates and lowers.  Returns ARB_OK or ARB_EINVAL (message in err).

@@ -9,6 +9,7 @@
 #include "../../include/arbmi.h"
 #include "kernels.hpp"
 #include "lower.hpp"
+#include "var_kernels.hpp"
 
 struct arb_sim_ {};
 
@@ -122,6 +123,12 @@ struct Sim : arb_sim_ {
     hipStream_t st_capture = nullptr;  // capture happens here; replays go on st
     bool graph_dirty = true;
     int capture_epoch_graph();
+    // variable time step (continuous event times; arb_build_cells_timed)
+    bool timed = false;
+    double *d_xe_t = nullptr, *d_bk_t = nullptr, *d_cr_delay_ms = nullptr;
+    double *d_cap = nullptr, *d_gmem = nullptr, *d_sigsum = nullptr, *d_uoff = nullptr, *d_syn_tau = nullptr;
+    int64_t* d_pk_steps = nullptr;
+    VarArgs var_args() const;
     // gradients
     GradState* grad = nullptr;
     bool grad_valid = false;
@@ -156,6 +163,9 @@ struct ModelView {
     int64_t n_ev;
     const arb_iclamp* ic;
     int32_t n_ic;
+    // variable time step: connection delays and event times (ms), or null
+    const double* conn_delay_ms = nullptr;
+    const double* ev_t_ms = nullptr;
 };
 
 struct DeviceLimits {

@@ -292,3 +292,53 @@ def test_plan_segments_are_balanced_chains():
     assert info["coef_mode"] == 3 and info["reg_len"] == 8
     assert info["n_cv"] == 101 and info["n_slots"] == 8 * (1 + 13)
     assert _plan(m)["coef_mode"] == 2  # not chosen by default for such branches
+
+
+def _build_timed(m, **kw):
+    cells, br, syn, con, ev, _ = arbmi.model_structs(m)
+    return arbmi.arb_build_cells_timed(cells, br, syn, con, m["con_delay_ms"], ev, m["ev_t"], _params(**kw))
+
+
+def _expect_timed_einval(m, text, **kw):
+    with pytest.raises(arbmi.ArbError) as e:
+        _build_timed(m, **kw)
+    assert e.value.code == arbmi.ARB_EINVAL, str(e.value)
+    assert text in str(e.value)
+
+
+def test_timed_build_validation():
+    """The variable-step build checks its continuous inputs and refuses
+    what it does not run: delays below dt, event times out of range,
+    gradients, the dry run, current clamps (the timed call takes none) and an
+    epoch longer than the shortest delay (K dt <= min delay, in grid steps)."""
+    m = gen.config2_timed(n_cells=3, t_ms=5.0)
+    bad = dict(m, con_delay_ms=m["con_delay_ms"].copy())
+    bad["con_delay_ms"][1] = 0.01
+    _expect_timed_einval(bad, "delay_ms")
+    bad = dict(m, ev_t=m["ev_t"].copy())
+    bad["ev_t"][0] = -1e-9
+    _expect_timed_einval(bad, "time out of range")
+    bad["ev_t"][0] = float("nan")
+    _expect_timed_einval(bad, "time out of range")
+    _expect_timed_einval(m, "gradients", flags=arbmi.ARB_FLAG_GRADIENTS)
+    _expect_timed_einval(m, "dry-run", dry_run_ranks=2)
+    # epochs of at most K grid steps, K dt <= the shortest delay
+    K = int(np.floor(m["con_delay_ms"].min() / gen.DT))
+    while (K + 1) * gen.DT <= m["con_delay_ms"].min():
+        K += 1
+    _expect_timed_einval(m, "minimum delay", epoch_steps=K + 1)
+    with pytest.raises(ValueError):
+        arbmi.arb_build_cells_timed(*arbmi.model_structs(m)[:4], m["con_delay_ms"][:1], arbmi.model_structs(m)[4],
+                                    m["ev_t"], _params())
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")
+def test_timed_build_valid_model_reaches_the_device_step():
+    """A valid timed model passes validation and lowering (one cell per
+    workgroup, register layout) and fails only for want of a device."""
+    with pytest.raises(arbmi.ArbError) as e:
+        _build_timed(gen.config2_timed(n_cells=3, t_ms=5.0))
+    assert e.value.code == arbmi.ARB_EHIP
+    with pytest.raises(arbmi.ArbError) as e:  # block_threads honoured
+        _build_timed(gen.config2_timed(n_cells=3, t_ms=5.0), block_threads=128)
+    assert e.value.code == arbmi.ARB_EHIP
