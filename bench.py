@@ -10,7 +10,11 @@ warm-up epoch.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line.  `--config 3|4|5|1` selects the other workloads,
 `--config 6` the synapse-dominated ring (10,000 expsyn per cell) and
-`--config 7` the 10k-connectivity model.
+`--config 7` the 10k-connectivity model.  `--varstep` runs the ring with the
+variable time step (Sec. II: steps shortened at event times): off-grid ring
+delays U(5, 5.5) ms, kicks at U(0, 1) ms and 10 Hz Poisson input on every
+dendritic synapse at continuous times; its rate counts n_cv CV-updates per
+grid step (the shortened steps taken on top are reported beside it).
 """
 from __future__ import annotations
 
@@ -98,6 +102,13 @@ def _oracle_chunk(args):
     cfg, cells, steps = args
     import oracle
     from workloads import gen
+    if cfg == "2t":  # the timed ring, the oracle's variable step
+        m = gen.config2_timed(cells=cells, t_ms=VARSTEP_T_MS)
+        s = oracle.Sim(m).set_varstep()
+        t0 = time.perf_counter()
+        s.advance_to(steps)
+        dt = time.perf_counter() - t0
+        return int(gen.n_cvs(m).sum()) * steps, dt
     if cfg == 2:
         m = gen.config2(n_cells=8192, cells=cells)
     elif cfg == 3:
@@ -145,11 +156,13 @@ HOST_CORES_PER_GPU = 16
 # single-thread leg.
 CPU_LEGS = {1: ((1, 4000), (1, 4000)), 2: ((8192, 4000), (64, 4000)), 3: ((4096, 8000), (16, 8000)),
             4: ((256, 2000), (64, 2000)), 5: ((65536, 800), (16, 800)), 6: ((8192, 800), (16, 800)),
-            7: ((8192, 800), (16, 800))}
-CPU_BASE_CELLS = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536, 6: 8192, 7: 8192}
+            7: ((8192, 800), (16, 800)), "2t": ((8192, 4000), (64, 4000))}
+CPU_BASE_CELLS = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536, 6: 8192, 7: 8192, "2t": 8192}
+# model time of the timed ring's inputs (the benchmark's steps and warm-up fit)
+VARSTEP_T_MS = 200.0
 
 
-def cpu_baseline(cfg: int):
+def cpu_baseline(cfg):
     """The CPU oracle as it stands (single-threaded C, built -O2 without
     fast-math), timed twice on the same workload as the GPU: on every usable
     host core (up to one GPU's share), as independent processes over disjoint
@@ -188,7 +201,9 @@ def cpu_baseline(cfg: int):
                        f"one GPU's share of the host")}
 
 
-def kernel_name(info: dict) -> str:
+def kernel_name(info: dict, timed: bool = False) -> str:
+    if timed:
+        return f"var_step_kernel<{info['block_threads']}, {info['reg_slots']}, {info['reg_len']}>"
     if info["coef_mode"] == 3:
         return (f"reg_step_kernel<{info['block_threads']}, {info['reg_slots']}, {info['reg_len']}, "
                 f"{'true' if info['syn_hbm'] else 'false'}>")
@@ -348,7 +363,11 @@ def main():
                     help="config 7: emulate this many identical ranks (proxy spikes, Sec. V-E dry run); a comma "
                          "list sweeps them, the first giving the headline line")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.txt"))
+    ap.add_argument("--varstep", action="store_true",
+                    help="the ring (config 2) with the variable time step: steps cut at off-grid event times")
     args = ap.parse_args()
+    if args.varstep and args.config != 2:
+        raise SystemExit("--varstep runs the ring: use it with --config 2")
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         raise SystemExit(2)
@@ -362,12 +381,19 @@ def main():
     t0 = time.perf_counter()
     sweep = [int(x) for x in str(args.dry_run_ranks).split(",")]
     args.dry_run_ranks = sweep[0]
-    m, desc = make_model(args.config, args.cells, args.dry_run_ranks)
+    if args.varstep:
+        n = args.cells or 8192
+        m = gen.config2_timed(n_cells=n, t_ms=VARSTEP_T_MS)
+        desc = (f"{n}-cell ring with the variable time step: depth-6 binary trees x 8 CVs/branch (1017 CVs/cell), "
+                "hh soma, pas dendrites, 10 expsyn/cell, ring delays U(5, 5.5) ms, kicks at U(0, 1) ms, 10 Hz "
+                "Poisson input per dendritic synapse at continuous times")
+    else:
+        m, desc = make_model(args.config, args.cells, args.dry_run_ranks)
     log(f"model built in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
     # whole epochs (exchange and step kernels) replay from a captured HIP graph
     flags = arbmi.ARB_FLAG_TIME_KERNELS | (0 if args.no_graph else arbmi.ARB_FLAG_GRAPH)
-    if not (args.block_threads or args.coef_mode or args.cells_per_pack):
+    if not (args.block_threads or args.coef_mode or args.cells_per_pack or args.varstep):
         flags |= arbmi.ARB_FLAG_AUTOTUNE
     sim = arbmi.Simulation(m, flags=flags, block_threads=args.block_threads, epoch_steps=args.epoch_steps,
                            dry_run_ranks=args.dry_run_ranks if args.config == 7 else 0,
@@ -382,9 +408,12 @@ def main():
     K = info["epoch_steps"]
     warmup = max(1, -(-args.warmup // K)) * K
     steps = max(1, -(-args.steps // K)) * K
+    if args.varstep and (warmup + steps) * float(m["dt"]) > VARSTEP_T_MS:
+        raise SystemExit(f"--varstep: at most {VARSTEP_T_MS} ms of input (warm-up plus timed steps)")
     sim.step(warmup)
     sim.sync()
     sim.kernel_time()  # discard warm-up launches
+    taken0 = sim.step_count()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
@@ -393,6 +422,7 @@ def main():
     kms, nlaunch = sim.kernel_time()
     sim.sync()
     spikes = sim.spikes()
+    taken = sim.step_count() - taken0  # steps of all cells, shortened ones included
     log(f"timed {steps} steps in {wall:.4f} s, {nlaunch} step-kernel launches, {kms:.2f} ms in them, "
         f"{len(spikes)} spikes")
 
@@ -400,10 +430,12 @@ def main():
     steps_per_launch = steps / max(nlaunch, 1)
     avg_launch_s = kms / 1e3 / max(nlaunch, 1)
     flops_per_step = FLOPS_PER_CV * n_cv + FLOPS_PER_HH * info["n_hh"] + FLOPS_PER_SYN * info["n_syn"]
-    tflops = flops_per_step * steps_per_launch / avg_launch_s / 1e12
+    # steps taken per grid step of every cell (1 with the fixed step)
+    taken_ratio = taken / (steps * info["n_cells"])
+    tflops = flops_per_step * taken_ratio * steps_per_launch / avg_launch_s / 1e12
     model_gbps = info["bytes_per_step"] * steps_per_launch / avg_launch_s / 1e9
-    kernel = kernel_name(info)
-    traffic = measured_traffic(args.traffic_json, args.config, kernel, steps_per_launch)
+    kernel = kernel_name(info, args.varstep)
+    traffic = measured_traffic(args.traffic_json, "2t" if args.varstep else args.config, kernel, steps_per_launch)
     traffic_gbps = None if traffic is None else traffic / avg_launch_s / 1e9
     copy_gbps = copy_bandwidth_gbps(torch)
     # The bound: the resource the kernel comes closest to.  The fused kernel
@@ -422,7 +454,7 @@ def main():
         roof = {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": alu_frac, "traffic": traffic,
                 "basis": ("algorithmic FP64 operations per launch (7 per CV, 61 per hh instance, 4 per "
-                          "synapse, per step) / average launch time; peak = MI355X vector FP64")}
+                          "synapse, per step taken) / average launch time; peak = MI355X vector FP64")}
     roof.update({
         "kernel": kernel, "steps_per_launch": steps_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
         "launches": nlaunch, "kernel_ms_total": kms,
@@ -451,11 +483,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"config {args.config}: {desc}", "cells": info["n_cells"], "cvs": n_cv,
+        "config": {"workload": ("variable step: " if args.varstep else f"config {args.config}: ") + desc,
+                   "cells": info["n_cells"], "cvs": n_cv,
                    "dt_ms": float(m["dt"]), "epoch_steps": K,
                    "block_threads": info["block_threads"], "coef_mode": info["coef_mode"],
                    "packs": info["n_packs"], "lds_bytes": info["lds_bytes"], "launch_classes": info["n_classes"],
                    "graph": not args.no_graph, "spikes": int(len(spikes)),
+                   **({"steps_taken": int(taken), "steps_taken_per_grid_step": taken_ratio} if args.varstep else {}),
                    **({"dry_run_ranks": args.dry_run_ranks} if args.config == 7 and args.dry_run_ranks > 1 else {})},
         "roofline": roof,
     }
@@ -469,7 +503,7 @@ def main():
         if args.config == 5:
             out["grad_subset"] = grad_ratio(torch, subset=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.config)
+        out["cpu_baseline"] = cpu_baseline("2t" if args.varstep else args.config)
     print(json.dumps(out))
 
 

@@ -15,12 +15,12 @@
 // A step of length dt runs exactly as the fixed step does, with the
 // factorisation computed once on the host and held in registers.  A
 // shortened step of length h changes the matrix (C/h + the axial
-// conductances): it is eliminated and solved afresh, level by level of the
-// branch tree (the continued fraction d'_k = C_k/h + sum sigma -
-// u_{k+1} F_{k+1} does not split across branches the way the right-hand side
-// does), in LDS with the per-CV constants read from HBM, leaving the
-// registers' step-dt coefficients untouched.  Gates and synapses decay over
-// h.
+// conductances): the branches refactor their registers for h, level by
+// level of the branch tree from the deepest (the continued fraction
+// d'_k = C_k/h + sum sigma - u_{k+1} F_{k+1} does not split across branches
+// the way the right-hand side does), the same split solve runs, and the
+// step-dt coefficients are reloaded afterwards.  Gates and synapses decay
+// over h.
 //
 // The pull (one wave per cell) bins the epoch's network events by grid
 // interval, comparing arrival times with the grid points k dt as the step
@@ -44,66 +44,103 @@ namespace {
 using namespace dev;
 using namespace reg;
 
-// The children's sums of a branch in a shortened step's up sweep: sum of
-// u F (their part of this branch's distal d') and of F rhs' (of its distal
-// rhs').  Binary packs hold grandchildren in x0/x1, so only c0 and c1 are
-// children there.
+// Refactor a branch in its registers for a step of length h.  The step-dt
+// factorisation held there gives what the new one needs, with the branch's
+// capacitances C (read from HBM, every row's load issued at once, at clamped
+// rows for the pads): u_k = F_k / D_k (F = u/d', D = 1/d'), and with dh =
+// 1/h - 1/dt and the distal neighbour's parts c = u F of the eliminated
+// diagonal at dt (c_dt) and at h (c_h),
+//   d'_h = 1/D + c_dt - c_h + C dh,   alpha_h = alpha + C dh,
+// so that d'_h = C/h + sum sigma - c_h, the elimination of the matrix for h
+// (Sec. II, the step's own dt).  cdt and ch are the children's sums at the
+// distal CV; returns the branch's own parts (u_0 F_0 at dt and at h) for its
+// parent.  Pads keep their neutral values.
+template <int L>
+__device__ __forceinline__ void var_refactor(Slot<L>& g, const VarArgs& v, const PackDesc& pk, double ih, double dh,
+                                             double cdt, double ch, double& out_dt, double& out_h) {
+    // the rows' addresses are formed here, at each use: hoisted out of the
+    // time loop they would hold 2 L registers for the whole launch
+    int base = g.base, w = g.w, len = g.len;
+    asm volatile("" : "+v"(base), "+v"(w), "+v"(len));
+    double cap[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) cap[k] = v.cap[pk.slot0 + base + int64_t(min(k, len - 1)) * w];
+    (void)ih;
+#pragma unroll
+    for (int k = L - 1; k >= 0; --k) {
+        if (k < len) {
+            const double u = g.F[k] / g.D[k];
+            const double d = 1.0 / g.D[k] + cdt - ch + cap[k] * dh;
+            const double f = u / d;
+            cdt = g.F[k] * u;
+            ch = f * u;
+            g.A[k] += cap[k] * dh;
+            g.F[k] = f;
+            g.D[k] = 1.0 / d;
+        }
+    }
+    double q = 1.0, z = 1.0;
+#pragma unroll
+    for (int k = 0; k < L; ++k)
+        if (k < len) {
+            z *= -g.F[k];
+            if (k >= 1) q *= -g.F[k];
+        }
+    g.FQ = g.F[0] * q;
+    g.Z = z;
+    out_dt = cdt;
+    out_h = ch;
+}
+
+// The children's sums of a branch's parts in the refactoring pass (binary
+// packs hold grandchildren in x0/x1, so only c0 and c1 are children there).
 template <int L>
 __device__ __forceinline__ void child_sums(const Slot<L>& g, const double* sC, const double* sF, const int32_t* s_ch,
-                                           bool binary, double& cd, double& cr) {
-    cd = sC[g.c0] + sC[g.c1];
-    cr = sF[g.c0] + sF[g.c1];
+                                           bool binary, double& cdt, double& ch) {
+    cdt = sF[g.c0] + sF[g.c1];
+    ch = sC[g.c0] + sC[g.c1];
     if (!binary)
         for (int q = 0; q < g.x1; ++q) {
             const int c = s_ch[g.x0 + q];
-            cd += sC[c];
-            cr += sF[c];
+            cdt += sF[c];
+            ch += sC[c];
         }
 }
 
-// Up sweep of a shortened step (length h) over one branch, distal CV
-// first: d' = C/h + sum sigma - (the distal neighbour's u F), rhs' =
-// (C/h - g_lin) V + R - (its F rhs'), F = u / d'.  Each CV's rhs' goes to its
-// V entry and d' to its R entry; the branch's own (u_0 F_0, F_0 rhs'_0) to sC
-// and sF.  The coefficients come from HBM: the register-held ones are those
-// of dt and stay untouched.
 template <int L>
-__device__ __forceinline__ void cut_up(const Slot<L>& g, double* sV, double* sC, double* sF, const int32_t* s_ch,
-                                       bool binary, const VarArgs& v, const PackDesc& pk, double h) {
-    double cd, cr;
-    child_sums<L>(g, sC, sF, s_ch, binary, cd, cr);
-    for (int k = g.len - 1; k >= 0; --k) {
-        const int i = cv_slot(g, k);
-        const int64_t sl = pk.slot0 + g.base + int64_t(k) * g.w;
-        const double ch = v.cap[sl] / h;
-        const double u = v.uoff[sl];
-        const double d = ch + v.sigsum[sl] - cd;
-        const double r = (ch - v.gmem[sl]) * sV[i] + sV[i + kRoff] - cr;
-        const double f = u / d;
-        sV[i] = r;
-        sV[i + kRoff] = d;
-        cd = f * u;
-        cr = f * r;
-    }
-    sC[g.task] = cd;
-    sF[g.task] = cr;
+__device__ __forceinline__ void refactor_level(Slot<L>& g, int lv, const VarArgs& v, const PackDesc& pk, double ih,
+                                               double dh, double* sC, double* sF, const int32_t* s_ch) {
+    if (g.lev != lv) return;
+    double cdt, ch, odt, oh;
+    child_sums<L>(g, sC, sF, s_ch, pk.binary, cdt, ch);
+    var_refactor<L>(g, v, pk, ih, dh, cdt, ch, odt, oh);
+    sF[g.task] = odt;
+    sC[g.task] = oh;
 }
 
-// Down sweep of a shortened step over one branch, proximal CV first, from
-// its parent's distal V (sX of the parent task; 0 at a soma, whose u is 0):
-// V_k = (rhs'_k - u_k V_{k-1}) / d'_k.  R gets its step-invariant part back.
+// The step-dt coefficients of a branch back from HBM after a shortened
+// step (the branch's position fields are unchanged): every row's loads issued
+// at once, at clamped rows for the pads, as load_slot does.
 template <int L>
-__device__ __forceinline__ void cut_down(const Slot<L>& g, double* sV, double* sX, const VarArgs& v,
-                                         const StepArgs& a, const PackDesc& pk) {
-    double x = sX[g.ptask];
-    for (int k = 0; k < g.len; ++k) {
-        const int i = cv_slot(g, k);
-        const int64_t sl = pk.slot0 + g.base + int64_t(k) * g.w;
-        x = (sV[i] - v.uoff[sl] * x) / sV[i + kRoff];
-        sV[i] = x;
-        sV[i + kRoff] = a.beta[sl];
+__device__ __forceinline__ void restore_coefficients(Slot<L>& g, const StepArgs& a, const PackDesc& pk) {
+    if (g.r < 0) return;
+    int base = g.base, w = g.w, len = g.len;
+    asm volatile("" : "+v"(base), "+v"(w), "+v"(len));
+    double q = 1.0;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const int64_t sl = pk.slot0 + base + int64_t(min(k, len - 1)) * w;
+        const double al = a.alpha[sl], f = a.F[sl], dv = a.invd[sl];
+        if (k < len) {
+            g.A[k] = al;
+            g.F[k] = f;
+            g.D[k] = dv;
+            if (k >= 1) q *= -f;
+        }
     }
-    sX[g.task] = x;
+    g.FQ = g.F[0] * q;
+    g.Z = a.tk_Z[pk.tk0 + g.task];
+    g.Zp = (g.ptask != pk.ntk) ? a.tk_Z[pk.tk0 + g.ptask] : 0.0;
 }
 
 // The cell's time, its event cursors and their next times are the same in
@@ -186,18 +223,30 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1))
     int64_t step0 = a.step0;
     if (a.epoch_ptr) step0 = *a.epoch_ptr * a.nsteps;
     const int64_t estart = step0 - step0 % a.epoch_steps;
-    // network events of the epoch, in time order: the launch starts at the
-    // first one of its grid interval (earlier ones were taken before)
-    const uint32_t* eoff = a.bk_off ? a.bk_off + int64_t(p) * (a.epoch_steps + 1) : nullptr;
-    const int32_t* eq = a.bk_q + int64_t(p) * a.bk_cap;
-    const double* ew = a.bk_w + int64_t(p) * a.bk_cap;
-    const double* et = v.bk_t + int64_t(p) * a.bk_cap;
-    int64_t ncur = uniform(eoff ? int64_t(eoff[step0 - estart]) : int64_t(0));
-    const int64_t nend = uniform(eoff ? int64_t(eoff[a.epoch_steps]) : int64_t(0));
-    int64_t xcur = uniform(a.pk_xcur[p]);
+    // The cell's event cursors, its time and the next decision live in LDS
+    // and are read and written by thread 0, which delivers the events: the
+    // other threads carry only the grid step and the end of the current run
+    // of steps of dt from one decision to the next.  Network events of the
+    // epoch are in time order; the launch starts at the first one of its
+    // grid interval (earlier ones were taken before).
+    __shared__ double cb_t, cb_t0, cb_tn, cb_tx, cb_h;
+    __shared__ int64_t cb_ncur, cb_xcur, cb_nend, cb_kf, cb_nsub;
+    __shared__ int32_t cb_full, cb_on_grid;
     const double kInf = __builtin_inf();
-    double tn = uniform((ncur < nend) ? et[ncur] : kInf);       // next network event
-    double tx = uniform((xcur < pk.xe1) ? v.xe_t[xcur] : kInf);  // next external event
+    if (tid == 0) {
+        const uint32_t* eoff = a.bk_off ? a.bk_off + int64_t(p) * (a.epoch_steps + 1) : nullptr;
+        const double* et = v.bk_t + int64_t(p) * a.bk_cap;
+        const int64_t ncur = eoff ? int64_t(eoff[step0 - estart]) : 0;
+        const int64_t nend = eoff ? int64_t(eoff[a.epoch_steps]) : 0;
+        const int64_t xcur = a.pk_xcur[p];
+        cb_ncur = ncur;
+        cb_nend = nend;
+        cb_xcur = xcur;
+        cb_tn = (ncur < nend) ? et[ncur] : kInf;         // next network event
+        cb_tx = (xcur < pk.xe1) ? v.xe_t[xcur] : kInf;   // next external event
+        cb_t = double(step0) * a.dt;
+        cb_nsub = 0;
+    }
     const int soma = (tid < pk.ncell) ? vix(a.pc_soma[pk.cell0 + tid]) : -1;
     double vold = 0.0;
 
@@ -229,30 +278,112 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1))
 
     const int64_t kend = step0 + a.nsteps;
     int64_t k = step0;
-    double t = double(k) * a.dt;
-    int64_t nsub = 0;
+    int64_t kf = k;  // steps of dt run while k < kf, with no event due
     while (k < kend) {
-        // A: every event due at or before t, network ones first (each
-        // thread walks the cursors; thread 0 adds)
-        if (tn <= t || tx <= t) {
-            while (tn <= t) {
-                if (tid == 0) sg[eq[ncur]] += ew[ncur];
-                ++ncur;
-                tn = uniform((ncur < nend) ? et[ncur] : kInf);
+        bool full = k < kf;
+        double t = double(k) * a.dt, h = a.dt;
+        bool on_grid = true;
+        if (!full) {
+            if (tid == 0) {
+                // A: every event due at or before t, network ones first
+                const double tc = cb_t;
+                double tn = cb_tn, tx = cb_tx;
+                if (tn <= tc || tx <= tc) {
+                    const int32_t* eq = a.bk_q + int64_t(p) * a.bk_cap;
+                    const double* ew = a.bk_w + int64_t(p) * a.bk_cap;
+                    const double* et = v.bk_t + int64_t(p) * a.bk_cap;
+                    int64_t ncur = cb_ncur, xcur = cb_xcur;
+                    const int64_t nend = cb_nend;
+                    while (tn <= tc) {
+                        sg[eq[ncur]] += ew[ncur];
+                        ++ncur;
+                        tn = (ncur < nend) ? et[ncur] : kInf;
+                    }
+                    while (tx <= tc) {
+                        sg[a.xe_syn[xcur]] += a.xe_w[xcur];
+                        ++xcur;
+                        tx = (xcur < pk.xe1) ? v.xe_t[xcur] : kInf;
+                    }
+                    cb_ncur = ncur;
+                    cb_xcur = xcur;
+                    cb_tn = tn;
+                    cb_tx = tx;
+                }
+                const double next = fmin(tn, tx);  // > tc
+                const double grid1 = double(k + 1) * a.dt;
+                if (tc == double(k) * a.dt && !(next < grid1)) {
+                    // on the grid, no event inside the coming interval:
+                    // steps of dt up to the grid point at or before the
+                    // next event
+                    int64_t e = kend;
+                    if (next < double(kend) * a.dt) {
+                        e = int64_t(next / a.dt);
+                        while (e > k + 1 && double(e) * a.dt > next) --e;
+                        while (e + 1 < kend && double(e + 1) * a.dt <= next) ++e;
+                        e = e < k + 1 ? k + 1 : e;
+                    }
+                    cb_full = 1;
+                    cb_kf = e;
+                    cb_t = double(e) * a.dt;
+                    cb_nsub += e - k;
+                } else {
+                    // a step cut at the next event, or ending on the grid
+                    // from an off-grid time
+                    const double target = (next < grid1) ? next : grid1;
+                    cb_full = 0;
+                    cb_t0 = tc;
+                    cb_h = target - tc;
+                    cb_on_grid = !(next < grid1);
+                    cb_t = target;
+                    cb_nsub += 1;
+                }
             }
-            while (tx <= t) {
-                if (tid == 0) sg[a.xe_syn[xcur]] += a.xe_w[xcur];
-                ++xcur;
-                tx = uniform((xcur < pk.xe1) ? v.xe_t[xcur] : kInf);
+            round_sync<T>();
+            full = __builtin_amdgcn_readfirstlane(cb_full) != 0;
+            if (full) {
+                kf = uniform(cb_kf);
+            } else {
+                h = uniform(cb_h);
+                t = uniform(cb_t0);
+                on_grid = __builtin_amdgcn_readfirstlane(cb_on_grid) != 0;
+            }
+            round_sync<T>();  // every thread has read the decision before it changes
+        }
+        if (!full) {  // the branches' coefficients for h, deepest level first
+            const double ih = 1.0 / h, dh = ih - 1.0 / a.dt;
+            for (int lv = pk.nlev - 1; lv >= 0; --lv) {
+                refactor_level<L>(g0, lv, v, pk, ih, dh, sC, sF, s_ch);
+                if constexpr (S > 1) refactor_level<L>(g1, lv, v, pk, ih, dh, sC, sF, s_ch);
+                if constexpr (S > 2) refactor_level<L>(g2, lv, v, pk, ih, dh, sC, sF, s_ch);
+                round_sync<T>();
+            }
+            // each branch's Z for its children, F_0 Q_0 for the up passes
+            if (g0.r >= 0) sF[g0.task] = g0.Z;
+            if constexpr (S > 1) {
+                if (g1.r >= 0) sF[g1.task] = g1.Z;
+            }
+            if constexpr (S > 2) {
+                if (g2.r >= 0) sF[g2.task] = g2.Z;
+            }
+            if (pk.binary) {
+                if (g0.r >= 0) sQ[g0.task] = g0.FQ;
+                if constexpr (S > 1) {
+                    if (g1.r >= 0) sQ[g1.task] = g1.FQ;
+                }
+                if constexpr (S > 2) {
+                    if (g2.r >= 0) sQ[g2.task] = g2.FQ;
+                }
+            }
+            round_sync<T>();
+            if (g0.r >= 0) g0.Zp = sF[g0.ptask];
+            if constexpr (S > 1) {
+                if (g1.r >= 0) g1.Zp = sF[g1.ptask];
+            }
+            if constexpr (S > 2) {
+                if (g2.r >= 0) g2.Zp = sF[g2.ptask];
             }
             round_sync<T>();
         }
-        // the step: to the next grid point, or to the next event before it
-        const double grid0 = double(k) * a.dt, grid1 = double(k + 1) * a.dt;
-        const double next = fmin(tn, tx);
-        const double target = uniform((next < grid1) ? next : grid1);
-        const bool full = (t == grid0 && target == grid1);
-        const double h = uniform(full ? a.dt : target - t);
 
         // B: R = beta - I at the nonlinear CVs (V at t); synapses decay over
         // the step here (g is not read again before the next events)
@@ -266,101 +397,85 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1))
                 I += s_gna[q] * (m * m * m * hg) * (vv - kENa);
                 I += s_gk[q] * (x * x * x * x) * (vv - kEK);
             }
-            for (int c = 0; c < d.nsyn; ++c) {
-                const int q = d.syn0 + c;
-                const double gq = sg[q];
-                I += gq * (vv - s_se[q]);
-                sg[q] = gq * (full ? s_sdec[q] : exp(-h / v.syn_tau[pk.syn0 + q]));
+            if (full) {
+                for (int c = 0; c < d.nsyn; ++c) {
+                    const int q = d.syn0 + c;
+                    const double gq = sg[q];
+                    I += gq * (vv - s_se[q]);
+                    sg[q] = gq * s_sdec[q];
+                }
+            } else {
+                for (int c = 0; c < d.nsyn; ++c) {
+                    const int q = d.syn0 + c;
+                    const double gq = sg[q];
+                    I += gq * (vv - s_se[q]);
+                    sg[q] = gq * exp(-h / v.syn_tau[pk.syn0 + q]);
+                }
             }
             sV[vix(d.slot) + kRoff] = s_nlb[j] - I;
         }
         if (soma >= 0) vold = sV[soma];
         round_sync<T>();
 
-        // C/D: a step of dt, the split Hines solve with the register-held
-        // coefficients; a shortened step, the level-by-level solve of the
-        // matrix for h
-        if (full) {
-            double y0[L], y1[L], y2[L];
-            local_load<L>(g0, sV, y0);
-            if constexpr (S > 1) local_load<L>(g1, sV, y1);
-            if constexpr (S > 2) local_load<L>(g2, sV, y2);
-            local_chain<L>(g0, y0);
-            if constexpr (S > 1) local_chain<L>(g1, y1);
-            if constexpr (S > 2) local_chain<L>(g2, y2);
-            local_store<L>(g0, sC, sF);
-            if constexpr (S > 1) local_store<L>(g1, sC, sF);
-            if constexpr (S > 2) local_store<L>(g2, sC, sF);
-            round_sync<T>();
-            if (pk.binary) {
-                for (int sr = 0; 2 * sr < pk.nlev; ++sr) {
-                    if (((pk.nlev - 1 - g0.lev) >> 1) == sr && g0.c0 != pk.ntk) pass_up2<L>(g0, sF, sQ, sC);
-                    if constexpr (S > 1) {
-                        if (((pk.nlev - 1 - g1.lev) >> 1) == sr && g1.c0 != pk.ntk) pass_up2<L>(g1, sF, sQ, sC);
-                    }
-                    if constexpr (S > 2) {
-                        if (((pk.nlev - 1 - g2.lev) >> 1) == sr && g2.c0 != pk.ntk) pass_up2<L>(g2, sF, sQ, sC);
-                    }
-                    round_sync<T>();
-                }
-            } else {
-                for (int r = 0; r < pk.nrd; ++r) {
-                    if (g0.r == r && g0.c0 != pk.ntk) pass_up<L>(g0, sC, s_ch);
-                    if constexpr (S > 1) {
-                        if (g1.r == r && g1.c0 != pk.ntk) pass_up<L>(g1, sC, s_ch);
-                    }
-                    if constexpr (S > 2) {
-                        if (g2.r == r && g2.c0 != pk.ntk) pass_up<L>(g2, sC, s_ch);
-                    }
-                    round_sync<T>();
-                }
-            }
-            full_chain<L>(g0, y0);
-            if constexpr (S > 1) full_chain<L>(g1, y1);
-            if constexpr (S > 2) full_chain<L>(g2, y2);
-            sY[g0.task] = g0.yl;
-            if constexpr (S > 1) sY[g1.task] = g1.yl;
-            if constexpr (S > 2) sY[g2.task] = g2.yl;
-            round_sync<T>();
+        // C/D: the split Hines solve with the registers' coefficients
+        double y0[L], y1[L], y2[L];
+        local_load<L>(g0, sV, y0);
+        if constexpr (S > 1) local_load<L>(g1, sV, y1);
+        if constexpr (S > 2) local_load<L>(g2, sV, y2);
+        local_chain<L>(g0, y0);
+        if constexpr (S > 1) local_chain<L>(g1, y1);
+        if constexpr (S > 2) local_chain<L>(g2, y2);
+        local_store<L>(g0, sC, sF);
+        if constexpr (S > 1) local_store<L>(g1, sC, sF);
+        if constexpr (S > 2) local_store<L>(g2, sC, sF);
+        round_sync<T>();
+        if (pk.binary) {
             for (int sr = 0; 2 * sr < pk.nlev; ++sr) {
-                if ((g0.lev >> 1) == sr) pass_down<L>(g0, sY, sX);
+                if (((pk.nlev - 1 - g0.lev) >> 1) == sr && g0.c0 != pk.ntk) pass_up2<L>(g0, sF, sQ, sC);
                 if constexpr (S > 1) {
-                    if ((g1.lev >> 1) == sr) pass_down<L>(g1, sY, sX);
+                    if (((pk.nlev - 1 - g1.lev) >> 1) == sr && g1.c0 != pk.ntk) pass_up2<L>(g1, sF, sQ, sC);
                 }
                 if constexpr (S > 2) {
-                    if ((g2.lev >> 1) == sr) pass_down<L>(g2, sY, sX);
+                    if (((pk.nlev - 1 - g2.lev) >> 1) == sr && g2.c0 != pk.ntk) pass_up2<L>(g2, sF, sQ, sC);
                 }
                 round_sync<T>();
             }
-            subst_chain<L>(g0, y0);
-            if constexpr (S > 1) subst_chain<L>(g1, y1);
-            if constexpr (S > 2) subst_chain<L>(g2, y2);
-            store_v<L>(g0, sV, y0);
-            if constexpr (S > 1) store_v<L>(g1, sV, y1);
-            if constexpr (S > 2) store_v<L>(g2, sV, y2);
-            round_sync<T>();
         } else {
-            for (int lv = pk.nlev - 1; lv >= 0; --lv) {
-                if (g0.lev == lv) cut_up<L>(g0, sV, sC, sF, s_ch, pk.binary, v, pk, h);
+            for (int r = 0; r < pk.nrd; ++r) {
+                if (g0.r == r && g0.c0 != pk.ntk) pass_up<L>(g0, sC, s_ch);
                 if constexpr (S > 1) {
-                    if (g1.lev == lv) cut_up<L>(g1, sV, sC, sF, s_ch, pk.binary, v, pk, h);
+                    if (g1.r == r && g1.c0 != pk.ntk) pass_up<L>(g1, sC, s_ch);
                 }
                 if constexpr (S > 2) {
-                    if (g2.lev == lv) cut_up<L>(g2, sV, sC, sF, s_ch, pk.binary, v, pk, h);
-                }
-                round_sync<T>();
-            }
-            for (int lv = 0; lv < pk.nlev; ++lv) {
-                if (g0.lev == lv) cut_down<L>(g0, sV, sX, v, a, pk);
-                if constexpr (S > 1) {
-                    if (g1.lev == lv) cut_down<L>(g1, sV, sX, v, a, pk);
-                }
-                if constexpr (S > 2) {
-                    if (g2.lev == lv) cut_down<L>(g2, sV, sX, v, a, pk);
+                    if (g2.r == r && g2.c0 != pk.ntk) pass_up<L>(g2, sC, s_ch);
                 }
                 round_sync<T>();
             }
         }
+        full_chain<L>(g0, y0);
+        if constexpr (S > 1) full_chain<L>(g1, y1);
+        if constexpr (S > 2) full_chain<L>(g2, y2);
+        sY[g0.task] = g0.yl;
+        if constexpr (S > 1) sY[g1.task] = g1.yl;
+        if constexpr (S > 2) sY[g2.task] = g2.yl;
+        round_sync<T>();
+        for (int sr = 0; 2 * sr < pk.nlev; ++sr) {
+            if ((g0.lev >> 1) == sr) pass_down<L>(g0, sY, sX);
+            if constexpr (S > 1) {
+                if ((g1.lev >> 1) == sr) pass_down<L>(g1, sY, sX);
+            }
+            if constexpr (S > 2) {
+                if ((g2.lev >> 1) == sr) pass_down<L>(g2, sY, sX);
+            }
+            round_sync<T>();
+        }
+        subst_chain<L>(g0, y0);
+        if constexpr (S > 1) subst_chain<L>(g1, y1);
+        if constexpr (S > 2) subst_chain<L>(g2, y2);
+        store_v<L>(g0, sV, y0);
+        if constexpr (S > 1) store_v<L>(g1, sV, y1);
+        if constexpr (S > 2) store_v<L>(g2, sV, y2);
+        round_sync<T>();
 
         // E: gates over h with the new V; threshold, the crossing time
         // interpolated within the step
@@ -394,16 +509,28 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1))
                 }
             }
         }
-        if (target == grid1 && a.trace) {
+        if (on_grid && a.trace) {
             const int64_t col = k - a.trace_step0;
             if (col >= 0 && col < a.trace_cap)
                 for (int j = tid; j < pk.npr; j += T)
                     a.trace[int64_t(a.pr_id[pk.pr0 + j]) * a.trace_cap + col] = sV[vix(a.pr_slot[pk.pr0 + j])];
         }
+        if (!full) {  // the step-dt coefficients back
+            restore_coefficients<L>(g0, a, pk);
+            if constexpr (S > 1) restore_coefficients<L>(g1, a, pk);
+            if constexpr (S > 2) restore_coefficients<L>(g2, a, pk);
+            if (pk.binary) {
+                if (g0.r >= 0) sQ[g0.task] = g0.FQ;
+                if constexpr (S > 1) {
+                    if (g1.r >= 0) sQ[g1.task] = g1.FQ;
+                }
+                if constexpr (S > 2) {
+                    if (g2.r >= 0) sQ[g2.task] = g2.FQ;
+                }
+            }
+        }
         round_sync<T>();
-        t = target;
-        if (target == grid1) ++k;
-        ++nsub;
+        if (full || on_grid) ++k;
     }
 
     for (int i = tid; i < ns; i += T) a.V[pk.slot0 + i] = sV[vix(i)];
@@ -414,8 +541,8 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1))
         a.hh_n[pk.hh0 + i] = sn[i];
     }
     if (tid == 0) {
-        a.pk_xcur[p] = xcur;
-        v.pk_steps[p] += nsub;
+        a.pk_xcur[p] = cb_xcur;
+        v.pk_steps[p] += cb_nsub;
     }
 }
 

@@ -77,10 +77,10 @@ def test_on_grid_times_take_the_fixed_steps():
     tm = gen.timed(m)
     nsp, ng = _compare(tm, [700, n])
     assert ng == len(cells) * n
-    fixed = arbmi.Simulation(m, coef_mode=3, cells_per_pack=1, block_threads=64)
-    fixed.step(n)
-    var = arbmi.Simulation(tm, block_threads=64)
+    var = arbmi.Simulation(tm)
     var.step(n)
+    fixed = arbmi.Simulation(m, coef_mode=3, cells_per_pack=1, block_threads=var.info["block_threads"])
+    fixed.step(n)
     assert fixed.info["reg_slots"] == var.info["reg_slots"]
     assert np.array_equal(fixed.voltages_host(), var.voltages_host())
     fixed.close()
