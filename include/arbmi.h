@@ -119,6 +119,30 @@ typedef struct {
     double amp_nA;
 } arb_iclamp;
 
+/* A generated density mechanism on one region of a cell: the soma or one
+ * branch (the role of the paper's NMODL mechanisms, Sec. III-C
+ * "Mechanisms": each is described once in the description language and
+ * compiled into the kernels).  Its current density, with the instance's
+ * parameters and states, applies to the membrane area of every CV that lies
+ * on the region (as the built-in densities do, eq. 2a).  Several entries may
+ * name one region; their currents add. */
+typedef struct {
+    int32_t cell;
+    int32_t branch;           /* branch index within the cell, -1 = the soma */
+    int32_t mech;             /* index in the catalogue (arb_mechanism_info) */
+    int32_t n_param;          /* param[0 .. n_param) given (in the mechanism's order);
+                                 the rest take their defaults */
+    double param[8];
+} arb_density;
+
+/* One mechanism of the generated catalogue. */
+typedef struct {
+    char name[32];
+    int32_t n_params, n_states;
+    char param_names[8][16];
+    double defaults[8];
+} arb_mech_info;
+
 typedef struct {
     double dt_ms;             /* > 0 */
     double threshold_mV;      /* soma spike threshold (upward crossing) */
@@ -146,6 +170,12 @@ typedef struct {
                                  are proxies: those of local cell g mod n_cells.  Each epoch's
                                  exchange then indexes R times the local spikes.  At most 2^20
                                  ranks and R n_cells < 2^31. */
+    int32_t reserved0;
+    const arb_density *densities; /* generated density mechanisms (read during the build only);
+                                     they run in the register-resident layout (coef_mode 0 or 3,
+                                     ARB_FLAG_AUTOTUNE ignored) and not with ARB_FLAG_GRADIENTS,
+                                     the variable time step or state held in HBM */
+    int64_t n_densities;
 } arb_params;
 
 #define ARB_FLAG_TIME_KERNELS 1 /* record HIP events around every step kernel */
@@ -228,6 +258,12 @@ int arb_build_cells_timed(const arb_cell *cells, int32_t n_cells, const arb_bran
  * time step, every cell's full and shortened steps (Sec. II); otherwise the
  * completed steps times the cell count.  Synchronises the sim's stream. */
 int arb_get_step_count(arb_sim s, int64_t *n_out);
+
+/* The generated mechanism catalogue: the number of mechanisms, and the
+ * name, parameters (names, defaults) and state count of mechanism id
+ * (0 .. count - 1).  ARB_EINVAL for an id out of range. */
+int arb_mechanism_count(void);
+int arb_mechanism_info(int32_t id, arb_mech_info *out);
 
 /* Advance every cell by n_steps steps of dt (Sec. II operator splitting:
  * events due at the step start, currents at V(t), implicit Euler + Hines for

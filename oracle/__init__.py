@@ -72,6 +72,14 @@ def lib():
         L.orc_hines_solve.argtypes = [C.c_int64, P, P, P, P]
         L.orc_hh_rates.argtypes = [C.c_double, P]
         L.orc_hh_rates_dv.argtypes = [C.c_double, P]
+        L.orc_set_densities.restype = C.c_int
+        L.orc_set_densities.argtypes = [P, C.c_int64, P, P, P, P, P]
+        L.orc_gen_states.restype = C.c_int
+        L.orc_gen_states.argtypes = [P, P]
+        L.orc_gen_count.restype = C.c_int64
+        L.orc_gen_count.argtypes = [P]
+        L.orc_gen_defaults.restype = C.c_int
+        L.orc_gen_defaults.argtypes = [C.c_int32, P]
         _lib = L
     return _lib
 
@@ -105,6 +113,12 @@ def hh_rates_dv(v: float) -> np.ndarray:
     r = np.zeros(6)
     lib().orc_hh_rates_dv(float(v), _p(r))
     return r
+
+
+# The further density mechanisms the oracle implements (oracle.c, each
+# written out from its definition): its number and its parameters in order.
+MECHANISMS = {"kdr": (0, ("gbar", "ek")), "hcn": (1, ("gbar", "eh", "vhalf")),
+              "hh_dsl": (2, ("gnabar", "gkbar", "gl", "ena", "ek", "el"))}
 
 
 class Sim:
@@ -143,6 +157,25 @@ class Sim:
         self.h = C.c_void_p(L.orc_build(*args))
         self.ncv = int(L.orc_ncv(self.h))
         self.nsyn = len(m["syn_cell"])
+        dens = m.get("densities") or []
+        if dens:  # (cell, branch, mechanism name, {parameter: value})
+            n = len(dens)
+            cell, branch, mech, npar = (np.zeros(n, np.int32) for _ in range(4))
+            prm = np.zeros((n, 8))
+            for k, (c, b, name, pv) in enumerate(dens):
+                if name not in MECHANISMS:
+                    raise ValueError(f"the oracle has no mechanism {name}")
+                mid, names = MECHANISMS[name]
+                cell[k], branch[k], mech[k] = c, b, mid
+                dflt = np.zeros(8)
+                npar[k] = L.orc_gen_defaults(mid, _p(dflt))
+                prm[k] = dflt
+                for pn, v in (pv or {}).items():
+                    prm[k, names.index(pn)] = float(v)
+            rc = L.orc_set_densities(self.h, n, _p(cell), _p(branch), _p(mech), _p(npar), _p(prm))
+            if rc != 0:
+                raise ValueError("bad density entry")
+        self.ngen = int(L.orc_gen_count(self.h))
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -213,6 +246,12 @@ class Sim:
     def grid_point(self) -> int:
         return int(lib().orc_varstep_grid(self.h))
 
+    def gen_states(self) -> np.ndarray:
+        """States of the further mechanisms' instances, [instance][4]."""
+        st = np.zeros(max(self.ngen, 1) * 4)
+        lib().orc_gen_states(self.h, _p(st))
+        return st[: self.ngen * 4].reshape(self.ngen, 4)
+
     def set_voltage(self, V):
         V = _c(V, np.float64)
         assert V.shape == (self.ncv,)
@@ -246,6 +285,8 @@ class Sim:
         grad = np.zeros((nreg, 3))
         tr = np.zeros((ncell, int(n_steps)))
         rc = lib().orc_adjoint(self.h, int(n_steps), _p(dl), _p(grad), _p(tr))
+        if rc == -3:
+            raise ValueError("the oracle adjoint does not cover the further density mechanisms")
         if rc != 0:
             raise MemoryError("oracle adjoint: out of memory")
         return tr, grad

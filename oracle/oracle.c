@@ -143,6 +143,14 @@ typedef struct {
     int64_t ntev, captev;
     int64_t *tev_begin, *tev_end, *tev_head; /* [ncell] this epoch's events of each cell */
     int64_t nvsteps;       /* steps taken (all cells) */
+
+    /* further density mechanisms (orc_set_densities): instances per CV */
+    int64_t ngen;
+    int64_t *gen_begin;    /* [ncv+1] instances of each CV */
+    int32_t *gen_mech;     /* ORC_GEN_* */
+    double *gen_w;         /* 10 x area (um^2): S/cm^2 -> nS */
+    double *gen_p;         /* [ngen][8] parameters */
+    double *gen_s;         /* [ngen][4] states */
 } orc;
 
 /* ------------------------------------------------------------------------ */
@@ -502,13 +510,18 @@ void orc_free(orc *s) {
                   s->out_begin, s->out_syn, s->out_src, s->out_delay, s->out_w, s->out_id,
                   s->ic_cv, s->ic_on, s->ic_off, s->ic_amp, s->V, s->m, s->h, s->n, s->g,
                   s->ev, s->sp, s->rec, s->d, s->rhs, s->I, s->tcell, s->kcell, s->out_delay_ms, s->syn_cell,
-                  s->csyn_begin, s->csyn, s->tev, s->tev_begin, s->tev_end, s->tev_head};
+                  s->csyn_begin, s->csyn, s->tev, s->tev_begin, s->tev_end, s->tev_head,
+                  s->gen_begin, s->gen_mech, s->gen_w, s->gen_p, s->gen_s};
     for (size_t k = 0; k < sizeof(ps) / sizeof(ps[0]); ++k) free(ps[k]);
     free(s);
 }
 
 /* ------------------------------------------------------------------------ */
 /* one time step                                                             */
+
+/* the further density mechanisms (defined below) */
+static double gen_current(int32_t mech, const double *p, const double *st, double v);
+static void gen_states(int32_t mech, const double *p, double *st, double v, double dt);
 
 /* membrane current I_i (pA, outward positive) of every CV at the present V,
  * gates and synaptic conductances, minus injected current (eq. 2a) */
@@ -528,6 +541,9 @@ static void currents(orc *s, int64_t n_step) {
                 I += a10 * s->reg_gl[r] * (v - E_L);
             }
         }
+        if (s->gen_begin)
+            for (int64_t q = s->gen_begin[i]; q < s->gen_begin[i + 1]; ++q)
+                I += s->gen_w[q] * gen_current(s->gen_mech[q], s->gen_p + q * 8, s->gen_s + q * 4, v);
         s->I[i] = I;
     }
     /* READING: expsyn current g (V - e) */
@@ -557,6 +573,138 @@ static void deliver_events(orc *s, int64_t n_step) {
 static void gate_update(double *x, double a, double b, double dt) {
     double xinf = a / (a + b);
     *x = xinf + (*x - xinf) * exp(-dt * (a + b));
+}
+
+/* ------------------------------------------------------------------------ */
+/* further density mechanisms, each written out from its definition (a gate
+ * with first-order kinetics integrated exactly at fixed V, as the hh gates
+ * are; a current density in S/cm^2 x mV):
+ *   kdr:    n' = a_n (1 - n) - b_n n, a_n = 0.16 exprelr(-(V + 52)/5),
+ *           b_n = 0.5 e^{-(V + 57)/40};  i = gbar n^4 (V - ek)
+ *           parameters gbar 0.01, ek -90
+ *   hcn:    q' = (q_inf - q)/tau_q, q_inf = 1/(1 + e^{(V - vhalf)/6}),
+ *           tau_q = 50 + 200/(1 + e^{(V + 60)/10});  i = gbar q (V - eh)
+ *           parameters gbar 0.0001, eh -30, vhalf -80
+ *   hh_dsl: the Hodgkin-Huxley sodium, potassium and leak currents with
+ *           their own densities and reversal potentials (the textbook rates
+ *           of orc_hh_rates); parameters gnabar 0.12, gkbar 0.036,
+ *           gl 0.0003, ena 50, ek -77, el -54.3 */
+
+enum { ORC_GEN_KDR = 0, ORC_GEN_HCN = 1, ORC_GEN_HHDSL = 2, ORC_GEN_COUNT = 3 };
+
+static double gen_exprelr(double x) { return (1.0 + x == 1.0) ? 1.0 : x / expm1(x); }
+
+static const double gen_defaults[ORC_GEN_COUNT][8] = {
+    {0.01, -90.0},
+    {0.0001, -30.0, -80.0},
+    {0.12, 0.036, 0.0003, 50.0, -77.0, -54.3},
+};
+static const int gen_nparams[ORC_GEN_COUNT] = {2, 3, 6};
+
+static double gen_current(int32_t mech, const double *p, const double *st, double v) {
+    switch (mech) {
+    case ORC_GEN_KDR: {
+        double n = st[0];
+        return p[0] * n * n * n * n * (v - p[1]);
+    }
+    case ORC_GEN_HCN:
+        return p[0] * st[0] * (v - p[1]);
+    case ORC_GEN_HHDSL: {
+        double m = st[0], h = st[1], n = st[2];
+        return p[0] * m * m * m * h * (v - p[3]) + p[1] * n * n * n * n * (v - p[4]) + p[2] * (v - p[5]);
+    }
+    }
+    return 0.0;
+}
+
+static void hcn_inf_tau(const double *p, double v, double *inf, double *tau) {
+    *inf = 1.0 / (1.0 + exp((v - p[2]) / 6.0));
+    *tau = 50.0 + 200.0 / (1.0 + exp((v + 60.0) / 10.0));
+}
+
+/* the states after a step of dt at fixed v (dt = -1: at rest at v) */
+static void gen_states(int32_t mech, const double *p, double *st, double v, double dt) {
+    switch (mech) {
+    case ORC_GEN_KDR: {
+        double a = 0.16 * gen_exprelr(-(v + 52.0) / 5.0), b = 0.5 * exp(-(v + 57.0) / 40.0);
+        if (dt < 0) st[0] = a / (a + b);
+        else gate_update(&st[0], a, b, dt);
+        return;
+    }
+    case ORC_GEN_HCN: {
+        double inf, tau;
+        hcn_inf_tau(p, v, &inf, &tau);
+        st[0] = (dt < 0) ? inf : inf + (st[0] - inf) * exp(-dt / tau);
+        return;
+    }
+    case ORC_GEN_HHDSL: {
+        double r[6];
+        orc_hh_rates(v, r);
+        for (int g = 0; g < 3; ++g) {
+            if (dt < 0) st[g] = r[2 * g] / (r[2 * g] + r[2 * g + 1]);
+            else gate_update(&st[g], r[2 * g], r[2 * g + 1], dt);
+        }
+        return;
+    }
+    }
+}
+
+/* Densities of the further mechanisms on regions (cell, branch; branch -1
+ * = the soma), parameters in the mechanism's order (n_param given, the rest
+ * default).  Every CV piece on such a region gets an instance with the
+ * piece's area, at rest at the CV's present V.  Returns 0, or -1 for a bad
+ * entry. */
+int orc_set_densities(orc *s, int64_t n, const int32_t *cell, const int32_t *branch, const int32_t *mech,
+                      const int32_t *n_param, const double *param) {
+    for (int64_t q = 0; q < n; ++q) {
+        if (cell[q] < 0 || cell[q] >= s->ncell || mech[q] < 0 || mech[q] >= ORC_GEN_COUNT) return -1;
+        if (branch[q] < -1 || s->reg_begin[cell[q]] + 1 + branch[q] >= s->reg_begin[cell[q] + 1]) return -1;
+        if (n_param[q] < 0 || n_param[q] > gen_nparams[mech[q]]) return -1;
+    }
+    s->gen_begin = xcalloc((size_t)s->ncv + 1, sizeof(int64_t));
+    int64_t cnt = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        cnt = 0;
+        for (int64_t i = 0; i < s->ncv; ++i) {
+            if (pass == 1) s->gen_begin[i] = cnt;
+            for (int64_t k = s->ct_begin[i]; k < s->ct_begin[i + 1]; ++k)
+                for (int64_t q = 0; q < n; ++q) {
+                    if (s->reg_begin[cell[q]] + 1 + branch[q] != s->ct_reg[k]) continue;
+                    if (pass == 1) {
+                        s->gen_mech[cnt] = mech[q];
+                        s->gen_w[cnt] = 10.0 * s->ct_area[k];
+                        for (int j = 0; j < 8; ++j)
+                            s->gen_p[cnt * 8 + j] = (j < n_param[q]) ? param[q * 8 + j] : gen_defaults[mech[q]][j];
+                        gen_states(mech[q], s->gen_p + cnt * 8, s->gen_s + cnt * 4, s->V[i], -1.0);
+                    }
+                    ++cnt;
+                }
+        }
+        if (pass == 0) {
+            s->ngen = cnt;
+            s->gen_mech = xcalloc((size_t)cnt + 1, sizeof(int32_t));
+            s->gen_w = xcalloc((size_t)cnt + 1, sizeof(double));
+            s->gen_p = xcalloc((size_t)cnt * 8 + 1, sizeof(double));
+            s->gen_s = xcalloc((size_t)cnt * 4 + 1, sizeof(double));
+        }
+    }
+    s->gen_begin[s->ncv] = cnt;
+    return 0;
+}
+
+/* a further mechanism's defaults; returns its parameter count */
+int orc_gen_defaults(int32_t mech, double *out) {
+    if (mech < 0 || mech >= ORC_GEN_COUNT) return -1;
+    for (int j = 0; j < 8; ++j) out[j] = gen_defaults[mech][j];
+    return gen_nparams[mech];
+}
+
+int64_t orc_gen_count(orc *s) { return s->ngen; }
+
+/* the states of every instance, [ngen][4] (for tests) */
+int orc_gen_states(orc *s, double *st) {
+    for (int64_t q = 0; q < s->ngen * 4; ++q) st[q] = s->gen_s[q];
+    return (int)s->ngen;
 }
 
 static void record_spike(orc *s, uint32_t gid, int64_t step, double t) {
@@ -626,6 +774,10 @@ static void step_once(orc *s) {
         gate_update(&s->h[i], r[2], r[3], dt);
         gate_update(&s->n[i], r[4], r[5], dt);
     }
+    if (s->gen_begin)
+        for (int64_t i = 0; i < s->ncv; ++i)
+            for (int64_t q = s->gen_begin[i]; q < s->gen_begin[i + 1]; ++q)
+                gen_states(s->gen_mech[q], s->gen_p + q * 8, s->gen_s + q * 4, s->V[i], dt);
     for (int64_t k = 0; k < s->nsyn; ++k) s->g[k] *= exp(-dt / s->syn_tau[k]);
     s->step = n + 1;
     if (s->step % s->K == 0) exchange(s);
@@ -705,6 +857,7 @@ void orc_set_params(orc *s, const double *theta) {
  * of the forward run is written to trace[c * n_steps + k] if non-null.
  * Memory: the whole trajectory is kept (meant for small test models). */
 int orc_adjoint(orc *s, int64_t n_steps, const double *dLdtrace, double *grad, double *trace) {
+    if (s->gen_begin) return -3; /* the further mechanisms have no adjoint here */
     int64_t ncv = s->ncv, nsyn = s->nsyn, N = n_steps;
     double dt = s->dt;
     int64_t step0 = s->step;
@@ -871,6 +1024,7 @@ static void tev_push(orc *s, orc_tev e) {
 int orc_set_varstep(orc *s, const double *con_delay_ms, int64_t next, const uint32_t *ev_syn,
                     const double *ev_t, const double *ev_w, int64_t K_ep) {
     if (s->nic > 0) return -1;
+    if (s->gen_begin) return -3; /* the further mechanisms run with the fixed step only */
     for (int64_t k = 0; k < s->ncon; ++k)
         if (!(con_delay_ms[k] >= (double)K_ep * s->dt)) return -2; /* an epoch is at most the minimum delay */
     s->varstep = 1;

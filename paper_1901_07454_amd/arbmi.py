@@ -52,7 +52,18 @@ class arb_params(C.Structure):
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
                 ("spike_capacity", C.c_int64), ("event_capacity", C.c_int64),
                 ("block_threads", C.c_int32), ("coef_mode", C.c_int32),
-                ("cells_per_pack", C.c_int32), ("dry_run_ranks", C.c_int32)]
+                ("cells_per_pack", C.c_int32), ("dry_run_ranks", C.c_int32), ("reserved0", C.c_int32),
+                ("densities", C.c_void_p), ("n_densities", C.c_int64)]
+
+
+class arb_density(C.Structure):
+    _fields_ = [("cell", C.c_int32), ("branch", C.c_int32), ("mech", C.c_int32), ("n_param", C.c_int32),
+                ("param", C.c_double * 8)]
+
+
+class arb_mech_info(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("n_params", C.c_int32), ("n_states", C.c_int32),
+                ("param_names", (C.c_char * 16) * 8), ("defaults", C.c_double * 8)]
 
 
 class arb_info(C.Structure):
@@ -72,7 +83,7 @@ EXPORTS = ["arb_build_cells", "arb_step", "arb_get_voltages", "arb_get_spikes", 
            "arb_get_trace", "arb_set_params", "arb_grad_forward", "arb_grad_backward",
            "arb_get_state", "arb_set_state", "arb_get_info", "arb_get_kernel_time", "arb_sync",
            "arb_free", "arb_last_error", "arb_plan_layout", "arb_get_voltages_noalloc", "arb_build_cells_timed",
-           "arb_get_step_count"]
+           "arb_get_step_count", "arb_mechanism_count", "arb_mechanism_info"]
 
 _lib = None
 
@@ -96,6 +107,8 @@ def load():
             "arb_build_cells_timed": [P, I32, P, I64, P, I64, P, P, I64, P, P, I64, C.POINTER(arb_params),
                                       C.POINTER(P)],
             "arb_get_step_count": [P, C.POINTER(I64)],
+            "arb_mechanism_count": [],
+            "arb_mechanism_info": [I32, C.POINTER(arb_mech_info)],
             "arb_step": [P, I64],
             "arb_get_voltages": [P, P, I64, C.c_int],
             "arb_get_voltages_noalloc": [P, P, I64],
@@ -169,6 +182,43 @@ def arb_build_cells_timed(cells, branches, syn, conn, delay_ms, ev, t_ms, params
     _check(L.arb_build_cells_timed(_ptr(c), len(c), _ptr(b), len(b), _ptr(s), len(s), _ptr(k), _ptr(dm), len(k),
                                    _ptr(e), _ptr(tm), len(e), C.byref(params), C.byref(out)))
     return out
+
+
+def mechanism_catalogue() -> list[dict]:
+    """The generated mechanisms: name, parameter names and defaults, state
+    count, in id order."""
+    L = load()
+    out = []
+    for i in range(L.arb_mechanism_count()):
+        info = arb_mech_info()
+        _check(L.arb_mechanism_info(i, C.byref(info)))
+        names = [info.param_names[k].value.decode() for k in range(info.n_params)]
+        out.append({"id": i, "name": info.name.decode(), "params": names,
+                    "defaults": [info.defaults[k] for k in range(info.n_params)], "n_states": info.n_states})
+    return out
+
+
+def density_structs(dens) -> np.ndarray | None:
+    """(cell, branch, mechanism name, {parameter: value}) tuples as the ABI's
+    arb_density entries (branch -1 = the soma)."""
+    if not dens:
+        return None
+    cat = {m["name"]: m for m in mechanism_catalogue()}
+    arr = (arb_density * len(dens))()
+    for k, (cell, branch, name, prm) in enumerate(dens):
+        if name not in cat:
+            raise ValueError(f"unknown mechanism {name}")
+        m = cat[name]
+        arr[k].cell, arr[k].branch, arr[k].mech = int(cell), int(branch), m["id"]
+        vals = list(m["defaults"])
+        for pn, v in (prm or {}).items():
+            if pn not in m["params"]:
+                raise ValueError(f"{name} has no parameter {pn}")
+            vals[m["params"].index(pn)] = float(v)
+        arr[k].n_param = len(vals)
+        for j, v in enumerate(vals):
+            arr[k].param[j] = v
+    return arr
 
 
 def arb_get_step_count(sim) -> int:
@@ -322,6 +372,10 @@ class Simulation:
         p.block_threads, p.coef_mode = int(block_threads), int(coef_mode)
         p.cells_per_pack = int(cells_per_pack)
         p.dry_run_ranks = int(dry_run_ranks)
+        self._dens = density_structs(m.get("densities"))
+        if self._dens is not None:
+            p.densities = C.cast(self._dens, C.c_void_p)
+            p.n_densities = len(self._dens)
         if use_torch_allocator:
             dev = self.stream.device
             st = self.stream

@@ -23,6 +23,9 @@ EXTRA = {"reg_kernels.hip": ["-mllvm", "-disable-machine-licm"],
 
 def build(verbose: bool = False) -> str:
     from concurrent.futures import ThreadPoolExecutor
+    sys.path.insert(0, HERE)
+    import mechgen
+    mechgen.generate()  # csrc/gen/*.hpp from mechanisms/*.mech
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     jobs = []
     for src in SOURCES:

@@ -13,6 +13,7 @@
 #include "adjoint.hpp"
 #include "kernels.hpp"
 #include "lower.hpp"
+#include "gen/mechanisms_desc.hpp"
 #include "sim.hpp"
 
 using namespace arbmi;
@@ -152,6 +153,13 @@ StepArgs Sim::step_args() const {
     a.n_syn_total = int64_t(L.syn_global.size());
     a.dt = L.dt;
     a.threshold = L.threshold;
+    a.gen_off = d_gen_off;
+    a.gen_pk = d_gen_pk;
+    a.gen_mech = d_gen_mech;
+    a.gen_slot = d_gen_slot;
+    a.gen_w = d_gen_w;
+    a.gen_prm = d_gen_prm;
+    a.gen_st = d_gen_st;
     return a;
 }
 
@@ -433,7 +441,7 @@ StateShape Sim::state_shape() const {
 void Sim::state_part_ptrs(void* ptr[kStateParts]) const {
     void* const v[kStateParts] = {d_V,      d_hh_m,   d_hh_h,    d_hh_n,    d_syn_g,    d_pk_xcur,
                                   d_bk_off, d_bk_nxt, d_bk_q,    d_bk_w,    d_ctr,      d_sp_gid,
-                                  d_sp_step, d_sp_t,  d_hist_cnt, d_hist_gid, d_hist_step};
+                                  d_sp_step, d_sp_t,  d_hist_cnt, d_hist_gid, d_hist_step, d_gen_st};
     for (int k = 0; k < kStateParts; ++k) ptr[k] = v[k];
 }
 
@@ -515,6 +523,15 @@ int build_device(Sim* s) {
     s->d_xe_step = dupload(s, L.xe_step, rc);
     s->d_xe_syn = dupload(s, L.xe_syn, rc);
     s->d_xe_w = dupload(s, L.xe_w, rc);
+    if (!L.gen_mech.empty()) {
+        s->d_gen_off = dupload(s, L.gen_off, rc);
+        s->d_gen_pk = dupload(s, L.gen_pk, rc);
+        s->d_gen_mech = dupload(s, L.gen_mech, rc);
+        s->d_gen_slot = dupload(s, L.gen_slot, rc);
+        s->d_gen_w = dupload(s, L.gen_w, rc);
+        s->d_gen_prm = dupload(s, L.gen_prm, rc);
+        s->d_gen_st = dupload(s, L.gen_st0, rc);
+    }
     if (s->timed) {
         s->d_xe_t = dupload(s, L.xe_t, rc);
         s->d_cr_delay_ms = dupload(s, L.cr_delay_ms, rc);
@@ -684,6 +701,7 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
     s->cfg.reg_len = s->L.reg_len;
     s->cfg.syn_hbm = 0;
     s->cfg.rec = (s->L.coef_mode == 3 && (p->flags & ARB_FLAG_GRADIENTS)) ? 1 : 0;
+    s->cfg.gen = s->L.gen_mech.empty() ? 0 : 1;
     int64_t lds = 0;
     for (const PackDesc& D : s->L.packs) {
         lds = std::max(lds, pack_lds_bytes(D, s->L.coef_mode));
@@ -854,9 +872,11 @@ int build_cells(const arb_cell* cells, int32_t n_cells, const arb_branch* branch
     m.conn_delay_ms = conn_delay_ms;
     m.ev_t_ms = ev_t_ms;
     const bool timed = conn_delay_ms != nullptr || ev_t_ms != nullptr;
+    const bool dens = p->n_densities != 0;
     arb_params q = *p;
-    if ((p->flags & ARB_FLAG_AUTOTUNE) && d.have_dev && !timed && p->block_threads == 0 && p->coef_mode == 0 &&
-        p->cells_per_pack == 0)
+    if (dens && q.coef_mode == 0) q.coef_mode = 3;  // generated mechanisms run in the register layout
+    if ((p->flags & ARB_FLAG_AUTOTUNE) && d.have_dev && !timed && !dens && p->block_threads == 0 &&
+        p->coef_mode == 0 && p->cells_per_pack == 0)
         q = autotune(m, *p, d);
     Sim* s = nullptr;
     std::string err;
@@ -890,6 +910,24 @@ int arb_build_cells_timed(const arb_cell* cells, int32_t n_cells, const arb_bran
     }
     return build_cells(cells, n_cells, branches, n_branches, syn, n_syn, conn, n_conn, ev, n_ev, nullptr, 0,
                        delay_ms ? delay_ms : &kNone, t_ms ? t_ms : &kNone, p, out);
+}
+
+int arb_mechanism_count(void) { return gen::kNumMechs; }
+
+int arb_mechanism_info(int32_t id, arb_mech_info* out) {
+    if (!out) return fail(ARB_EINVAL, "null argument");
+    if (id < 0 || id >= gen::kNumMechs) return fail(ARB_EINVAL, "mechanism id out of range");
+    const gen::MechDesc& M = gen::kMechs[id];
+    arb_mech_info I{};
+    std::snprintf(I.name, sizeof I.name, "%s", M.name);
+    I.n_params = M.n_params;
+    I.n_states = M.n_states;
+    for (int k = 0; k < M.n_params && k < 8; ++k) {
+        std::snprintf(I.param_names[k], sizeof I.param_names[k], "%s", M.param_names[k]);
+        I.defaults[k] = M.defaults[k];
+    }
+    *out = I;
+    return ARB_OK;
 }
 
 int arb_get_step_count(arb_sim s_, int64_t* n_out) {

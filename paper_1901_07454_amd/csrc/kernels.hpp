@@ -84,6 +84,16 @@ struct StepArgs {
     const int64_t* epoch_ptr;
     int32_t pad0;
     int32_t pack0;             // first pack of this launch (block b runs pack pack0 + b)
+    // generated density mechanisms (null when the model has none): the
+    // instances of each nonlinear entry and of each pack, their mechanism,
+    // CV, weight (10 x area, S/cm^2 -> nS), parameters and states
+    const int32_t* gen_off;    // [n_nl + 1]
+    const int32_t* gen_pk;     // [n_packs + 1]
+    const int32_t* gen_mech;
+    const int32_t* gen_slot;   // pack-local slot
+    const double* gen_w;
+    const double* gen_prm;     // [n_inst][kMaxParams]
+    double* gen_st;            // [n_inst][kMaxStates]
 };
 
 // Per-launch configuration chosen by the host.
@@ -95,6 +105,7 @@ struct LaunchCfg {
     int reg_len;        // mode 3: CVs per branch held in registers (8 or 16)
     int syn_hbm;        // mode 3: some pack keeps its synapse state in HBM
     int rec;            // mode 3: the sim is built for gradients (kernels that can record states)
+    int gen;            // mode 3: the model has generated density mechanisms
 };
 
 hipError_t launch_step(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st);

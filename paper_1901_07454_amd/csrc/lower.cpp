@@ -20,6 +20,8 @@
 //   x_i = rhs'_i / d'_i - F_i x_parent(i)  (substitution).
 #include "lower.hpp"
 
+#include "gen/mechanisms_desc.hpp"
+
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -221,6 +223,36 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             geo[c].cap[i - L.cell_cv0[c]] = cap_user[i];
         }
 
+    // ------------------------------------------- generated density mechanisms
+    const int64_t n_den = p.n_densities;
+    if (n_den < 0 || (n_den > 0 && !p.densities)) { err = "densities: bad count or NULL array"; return ARB_EINVAL; }
+    std::vector<std::vector<int64_t>> den_of_reg(n_den ? n_reg : 0);
+    for (int64_t q = 0; q < n_den; ++q) {
+        const arb_density& D = p.densities[q];
+        if (D.cell < 0 || D.cell >= n_cells || D.branch < -1 || D.branch >= cells[D.cell].n_branch) {
+            err = fmt("density %lld: cell or branch out of range", (long long)q); return ARB_EINVAL;
+        }
+        if (D.mech < 0 || D.mech >= gen::kNumMechs) { err = fmt("density %lld: unknown mechanism", (long long)q); return ARB_EINVAL; }
+        if (D.n_param < 0 || D.n_param > gen::kMechs[D.mech].n_params) {
+            err = fmt("density %lld: %s takes at most %d parameters", (long long)q, gen::kMechs[D.mech].name,
+                      gen::kMechs[D.mech].n_params);
+            return ARB_EINVAL;
+        }
+        for (int32_t k = 0; k < D.n_param; ++k)
+            if (!std::isfinite(D.param[k])) { err = fmt("density %lld: parameter not finite", (long long)q); return ARB_EINVAL; }
+        den_of_reg[L.cell_reg0[D.cell] + 1 + D.branch].push_back(q);
+    }
+    if (n_den > 0) {
+        if (opt.grads) { err = "generated mechanisms have no gradients"; return ARB_EINVAL; }
+        if (opt.conn_delay_ms || opt.ev_t_ms) { err = "generated mechanisms do not run with the variable time step"; return ARB_EINVAL; }
+        if (opt.coef_mode != 3) { err = "generated mechanisms need the register layout (coef_mode 3)"; return ARB_EINVAL; }
+    }
+    std::vector<char> has_gen(L.n_cv, 0);
+    if (n_den > 0)
+        for (int64_t i = 0; i < L.n_cv; ++i)
+            for (int64_t k = L.piece_off[i]; k < L.piece_off[i + 1]; ++k)
+                if (!den_of_reg[L.piece_reg[k]].empty()) has_gen[i] = 1;
+
     // ------------------------------------------------ synapses, clamps, events
     std::vector<int64_t> syn_cv(n_syn);
     for (int64_t q = 0; q < n_syn; ++q) {
@@ -399,7 +431,8 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
     // CVs carrying hh or synapses, per cell
     std::vector<int32_t> nnl_cell(n_cells, 0);
     for (int32_t c = 0; c < n_cells; ++c)
-        for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i) nnl_cell[c] += (has_hh[i] || nsyn_cv[i] || nic_cv[i]) ? 1 : 0;
+        for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i)
+            nnl_cell[c] += (has_hh[i] || nsyn_cv[i] || nic_cv[i] || has_gen[i]) ? 1 : 0;
     auto exact_lds = [&](const PackPlan& pp, int mode) -> int64_t {
         const Shape sh = plan_shape(pp.cells);
         if (!sh.ok) return int64_t(1) << 40;  // does not fit the register slots
@@ -681,7 +714,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         for (int32_t k = 0; k < D.ncell; ++k) {
             const int32_t c = L.pc_gid[D.cell0 + k];
             for (int64_t i = L.cell_cv0[c]; i < L.cell_cv0[c + 1]; ++i)
-                if (has_hh[i] || nsyn_cv[i] || nic_cv[i]) here.push_back({L.perm[i], i});
+                if (has_hh[i] || nsyn_cv[i] || nic_cv[i] || has_gen[i]) here.push_back({L.perm[i], i});
         }
         std::sort(here.begin(), here.end());
         if (D.syn_global)  // CVs with similar synapse counts share a group: little padding
@@ -690,6 +723,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                 return syn_at[a.second].size() > syn_at[b.second].size();
             });
         const size_t nl_first = L.nl.size();
+        if (n_den > 0) L.gen_pk.push_back(int32_t(L.gen_mech.size()));
         for (auto& sc : here) {
             const int64_t i = sc.second;
             NlDesc N{};
@@ -698,6 +732,22 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             if (has_hh[i]) { N.hh = int32_t(L.hh_cv.size()) - D.hh0; L.hh_cv.push_back(i); }
             N.nsyn = int32_t(syn_at[i].size());
             L.nl.push_back(N);
+            if (n_den > 0) {  // this CV's instances: its pieces in order, each region's entries in order
+                L.gen_off.push_back(int32_t(L.gen_mech.size()));
+                for (int64_t k = L.piece_off[i]; k < L.piece_off[i + 1]; ++k)
+                    for (int64_t q : den_of_reg[L.piece_reg[k]]) {
+                        const arb_density& E = p.densities[q];
+                        const gen::MechDesc& M = gen::kMechs[E.mech];
+                        double prm[gen::kMaxParams] = {}, st[gen::kMaxStates] = {};
+                        for (int32_t j = 0; j < M.n_params; ++j) prm[j] = (j < E.n_param) ? E.param[j] : M.defaults[j];
+                        gen::steady(E.mech, L.v_init, prm, st);
+                        L.gen_mech.push_back(E.mech);
+                        L.gen_slot.push_back(N.slot);
+                        L.gen_w.push_back(10.0 * L.piece_area[k]);  // S/cm^2 x um^2 -> nS
+                        L.gen_prm.insert(L.gen_prm.end(), prm, prm + gen::kMaxParams);
+                        L.gen_st0.insert(L.gen_st0.end(), st, st + gen::kMaxStates);
+                    }
+            }
         }
         // Synapses in pack order.  In LDS they are contiguous per CV.  A pack
         // that keeps them in HBM interleaves them over the threads that take
@@ -767,6 +817,14 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         D.nic = int32_t(L.ic_on.size()) - D.ic0;
         D.nhh = int32_t(L.hh_cv.size()) - D.hh0;
         D.nsyn = int32_t(L.syn_global.size()) - D.syn0;
+        if (n_den > 0 && (D.syn_global || D.hh_global) && L.gen_pk.back() != int32_t(L.gen_mech.size())) {
+            err = "generated mechanisms do not run on a cell whose state is held in HBM (too large for LDS)";
+            return ARB_EINVAL;
+        }
+    }
+    if (n_den > 0) {
+        L.gen_off.push_back(int32_t(L.gen_mech.size()));
+        L.gen_pk.push_back(int32_t(L.gen_mech.size()));
     }
     L.n_hh_total = int64_t(L.hh_cv.size());
     L.hh_gna.assign(L.hh_cv.size(), 0.0);
@@ -990,7 +1048,7 @@ void state_part_bytes(const Lowered& L, const StateShape& sh, int64_t b[kStatePa
                                     np * sh.bk_cap * 4, np * sh.bk_cap * 8, int64_t(sizeof(Counters)),
                                     int64_t(sh.sp_cap) * 4, int64_t(sh.sp_cap) * 8, int64_t(sh.sp_cap) * 8,
                                     int64_t(sh.n_hist) * 4, int64_t(sh.n_hist) * sh.hist_cap * 4,
-                                    int64_t(sh.n_hist) * sh.hist_cap * 8};
+                                    int64_t(sh.n_hist) * sh.hist_cap * 8, int64_t(L.gen_st0.size()) * 8};
     for (int k = 0; k < kStateParts; ++k) b[k] = v[k];
 }
 

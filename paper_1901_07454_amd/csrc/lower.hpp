@@ -79,6 +79,15 @@ struct Lowered {
     std::vector<double> cr_delay_ms;          // variable step: delays (ms)
     std::vector<uint32_t> cr_src;             // source gid of each rank
     std::vector<double> cr_w;                 // nS
+    // generated density mechanisms: one instance per (CV, density entry on a
+    // region the CV covers); instances are grouped by nonlinear entry
+    std::vector<int32_t> gen_off;             // [n_nl + 1] first instance of each nonlinear entry
+    std::vector<int32_t> gen_pk;              // [n_packs + 1] first instance of each pack
+    std::vector<int32_t> gen_mech;            // per instance: catalogue index
+    std::vector<int32_t> gen_slot;            // per instance: pack-local slot of its CV
+    std::vector<double> gen_w;                // per instance: 10 x its membrane area (um^2): S/cm^2 -> nS
+    std::vector<double> gen_prm;              // [n_inst][gen::kMaxParams]
+    std::vector<double> gen_st0;              // [n_inst][gen::kMaxStates] states at rest at v_init
     std::vector<int64_t> in_off;              // [n_packs + 1] first rank of each pack
     int32_t dry_run_ranks = 1;                // R: ranks the exchange emulates (1 = none)
     bool timed = false;                       // variable time step (continuous event times)
@@ -117,7 +126,7 @@ std::string verify_layout(const Lowered& lw);
 // a header, then kStateParts parts in this order: V, hh m, h, n, synapse g,
 // external-event cursors, the running epoch's network events (offsets,
 // next-step table, synapses, weights), counters, spike buffer (gid, step,
-// time), spike history (counts, gids, steps).
+// time), spike history (counts, gids, steps), generated mechanisms' states.
 struct StateShape {
     int32_t K = 1;            // epoch steps
     int32_t bk_cap = 0;       // network events per pack and epoch
@@ -131,7 +140,7 @@ struct StateHeader {
     int64_t step, n_slots, n_hh, n_syn, n_packs, n_bk, bk_cap, sp_cap, sp_user;
 };
 constexpr uint64_t kStateMagic = 0x41524233535441ull;
-constexpr int kStateParts = 17;
+constexpr int kStateParts = 18;
 // Bytes of each part.
 void state_part_bytes(const Lowered& L, const StateShape& sh, int64_t bytes[kStateParts]);
 // Every check arb_set_state makes before any byte reaches the device: the

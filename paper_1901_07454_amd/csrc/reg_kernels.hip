@@ -32,6 +32,7 @@
 // before their update and the synapse conductances after the step's events.
 #include <hip/hip_runtime.h>
 
+#include "gen/mechanisms.hpp"
 #include "kernel_common.hpp"
 #include "kernels.hpp"
 #include "reg_solve.hpp"
@@ -52,8 +53,10 @@ using namespace reg;
 // is set (the adjoint's recompute), and the gradient forward runs the same
 // code with it unset, so both produce the same trajectory bit for bit (one
 // wave per SIMD fewer than the plain variant: the recording's addresses take
-// the registers).
-template <int T, int S, int L, bool G, bool REC>
+// the registers).  M: the model has generated density mechanisms (their
+// currents join the nonlinear CVs' right-hand sides, their states advance
+// with the gates; parameters and states stay in HBM).
+template <int T, int S, int L, bool G, bool REC, bool M = false>
 __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1)))
     reg_step_kernel(StepArgs a) {
     extern __shared__ __align__(16) char lds_raw[];
@@ -266,6 +269,11 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
                     I += s_gk[q] * (x * x * x * x) * (v - kEK);
                 }
             }
+            if constexpr (M) {
+                for (int q = a.gen_off[pk.nl0 + j]; q < a.gen_off[pk.nl0 + j + 1]; ++q)
+                    I += a.gen_w[q] * gen::current(a.gen_mech[q], v, a.gen_prm + int64_t(q) * gen::kMaxParams,
+                                                   a.gen_st + int64_t(q) * gen::kMaxStates);
+            }
             if (!syn_hbm) {
                 // the decay of phase E is applied here too: g is not read
                 // again before the next step's events
@@ -448,6 +456,12 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
                 for (int j = tid; j < pk.npr; j += T)
                     a.trace[int64_t(a.pr_id[pk.pr0 + j]) * a.trace_cap + col] = sV[vix(a.pr_slot[pk.pr0 + j])];
         }
+        if constexpr (M) {  // generated mechanisms' states with V^{n+1}
+            for (int q = a.gen_pk[p] + tid; q < a.gen_pk[p + 1]; q += T)
+                gen::advance(a.gen_mech[q], sV[vix(a.gen_slot[q])], a.dt, a.gen_prm + int64_t(q) * gen::kMaxParams,
+                             a.gen_st + int64_t(q) * gen::kMaxStates);
+            __threadfence_block();  // before the next step's currents read them
+        }
         if (syn_hbm) __threadfence_block();  // phase B's g stores before the next step's events
         round_sync<T>();
     }
@@ -464,7 +478,11 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
 
 template <int T, int S, int L>
 hipError_t launch_reg(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipStream_t st) {
-    if (cfg.rec) {  // gradient sims never keep synapse state in HBM
+    if (cfg.gen) {  // generated mechanisms: state in LDS, no recording
+        if (cfg.rec || cfg.syn_hbm) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((reg_step_kernel<T, S, L, false, false, true>), dim3(n_packs), dim3(T), cfg.lds_bytes, st,
+                           a);
+    } else if (cfg.rec) {  // gradient sims never keep synapse state in HBM
         if (cfg.syn_hbm) return hipErrorInvalidValue;
         hipLaunchKernelGGL((reg_step_kernel<T, S, L, false, true>), dim3(n_packs), dim3(T), cfg.lds_bytes, st, a);
     } else if (cfg.syn_hbm) {
@@ -475,9 +493,9 @@ hipError_t launch_reg(const StepArgs& a, const LaunchCfg& cfg, int n_packs, hipS
     return hipGetLastError();
 }
 
-template <int T, int S, int L, bool G, bool REC>
+template <int T, int S, int L, bool G, bool REC, bool M = false>
 void allow_lds_one(int lds_max) {
-    const void* f = reinterpret_cast<const void*>(&reg_step_kernel<T, S, L, G, REC>);
+    const void* f = reinterpret_cast<const void*>(&reg_step_kernel<T, S, L, G, REC, M>);
     hipFuncAttributes at{};
     if (hipFuncGetAttributes(&at, f) != hipSuccess) return;
     const int allowed = lds_max - int(at.sharedSizeBytes);
@@ -490,6 +508,7 @@ void allow_lds(int lds_max) {
     allow_lds_one<T, S, L, false, false>(lds_max);
     allow_lds_one<T, S, L, true, false>(lds_max);
     allow_lds_one<T, S, L, false, true>(lds_max);
+    allow_lds_one<T, S, L, false, false, true>(lds_max);
 }
 
 template <int T>

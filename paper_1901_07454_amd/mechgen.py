@@ -1,0 +1,488 @@
+"""Mechanism description language -> HIP code (the role the paper gives its
+NMODL compiler, Sec. III-C "Mechanisms" and Sec. IV-C: mechanisms are
+described once and compiled into the back end's kernels).
+
+A mechanism file describes one density mechanism: ion-channel gates with
+first-order kinetics and the membrane current they carry.  Line by line:
+
+    mechanism <name>
+    parameter <name> = <number>          # a per-instance constant, with its default
+    state <name>                         # a gate, 0..1
+    rate <name> = <expr>                 # an intermediate of v and the parameters
+    gate <state> alpha <expr> beta <expr>   # x' = alpha (1 - x) - beta x
+    gate <state> inf <expr> tau <expr>      # x' = (inf - x) / tau
+    current <expr>                       # outward current density (S/cm^2 x mV)
+
+Expressions use numbers, v (mV), the parameters, the rates defined above
+them, the states (in the current only), + - * /, integer powers x^n
+(n = 1..8) and the functions exp, expm1, exprelr (x / (e^x - 1), 1 at 0),
+log and sqrt.  Comments start with '#'.
+
+The gates are integrated as the built-in hh gates are (Sec. II, the state
+update with the new voltage): exactly at fixed v over the step,
+x <- x_inf + (x - x_inf) exp(-dt / tau), with x_inf = alpha / (alpha + beta)
+and 1/tau = alpha + beta for alpha/beta gates.  A mechanism instance starts
+at its steady state at the initial voltage.
+
+`generate(dir)` writes two headers: `mechanisms_desc.hpp` (plain C++, for
+the host: names, parameter names and defaults, the steady state) and
+`mechanisms.hpp` (HIP device code: the current and the state update of each
+mechanism, dispatched on the mechanism's index).  The library's build runs
+it over `mechanisms/*.mech` before compiling.
+"""
+from __future__ import annotations
+
+import glob
+import os
+import re
+from dataclasses import dataclass, field
+
+MAX_PARAMS = 8
+MAX_STATES = 4
+FUNCTIONS = ("exp", "expm1", "exprelr", "log", "sqrt")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+MECH_DIR = os.path.join(HERE, "mechanisms")
+OUT_DIR = os.path.join(HERE, "csrc", "gen")
+
+
+class MechError(ValueError):
+    pass
+
+
+# ---------------------------------------------------------------- expressions
+
+_TOKEN = re.compile(r"\s*(?:(\d+\.\d*(?:[eE][-+]?\d+)?|\.\d+(?:[eE][-+]?\d+)?|\d+(?:[eE][-+]?\d+)?)|"
+                    r"([A-Za-z_][A-Za-z_0-9]*)|(\*\*|[-+*/^(),]))")
+
+
+def _tokens(text: str, where: str):
+    out, pos = [], 0
+    text = text.rstrip()
+    while pos < len(text):
+        m = _TOKEN.match(text, pos)
+        if not m or m.end() == pos:
+            raise MechError(f"{where}: cannot read '{text[pos:]}'")
+        num, name, op = m.groups()
+        out.append(("num", num) if num else ("name", name) if name else ("op", "^" if op == "**" else op))
+        pos = m.end()
+    return out
+
+
+class _Parser:
+    """Recursive descent: sum := prod (('+'|'-') prod)*; prod := unary
+    (('*'|'/') unary)*; unary := '-' unary | power; power := atom ('^' int)?;
+    atom := number | name | func '(' sum ')' | '(' sum ')'."""
+
+    def __init__(self, toks, where):
+        self.t, self.i, self.where = toks, 0, where
+
+    def peek(self):
+        return self.t[self.i] if self.i < len(self.t) else (None, None)
+
+    def take(self, kind=None, val=None):
+        k, v = self.peek()
+        if k is None or (kind and k != kind) or (val and v != val):
+            raise MechError(f"{self.where}: expected {val or kind}, found {v or 'the end'}")
+        self.i += 1
+        return v
+
+    def parse(self):
+        e = self.sum()
+        if self.i != len(self.t):
+            raise MechError(f"{self.where}: unexpected '{self.peek()[1]}'")
+        return e
+
+    def sum(self):
+        e = self.prod()
+        while self.peek() in (("op", "+"), ("op", "-")):
+            op = self.take()
+            e = ("bin", op, e, self.prod())
+        return e
+
+    def prod(self):
+        e = self.unary()
+        while self.peek() in (("op", "*"), ("op", "/")):
+            op = self.take()
+            e = ("bin", op, e, self.unary())
+        return e
+
+    def unary(self):
+        if self.peek() == ("op", "-"):
+            self.take()
+            return ("neg", self.unary())
+        if self.peek() == ("op", "+"):
+            self.take()
+            return self.unary()
+        return self.power()
+
+    def power(self):
+        e = self.atom()
+        if self.peek() == ("op", "^"):
+            self.take()
+            n = self.take("num")
+            if not re.fullmatch(r"\d+", n) or not 1 <= int(n) <= 8:
+                raise MechError(f"{self.where}: powers take an integer exponent 1..8, not {n}")
+            e = ("pow", e, int(n))
+        return e
+
+    def atom(self):
+        k, v = self.peek()
+        if k == "num":
+            self.take()
+            return ("num", float(v))
+        if k == "name":
+            self.take()
+            if self.peek() == ("op", "("):
+                if v not in FUNCTIONS:
+                    raise MechError(f"{self.where}: unknown function {v}")
+                self.take("op", "(")
+                a = self.sum()
+                self.take("op", ")")
+                return ("call", v, a)
+            return ("var", v)
+        if (k, v) == ("op", "("):
+            self.take()
+            e = self.sum()
+            self.take("op", ")")
+            return e
+        raise MechError(f"{self.where}: expected a value, found {v or 'the end'}")
+
+
+def parse_expr(text: str, where: str = "expression"):
+    return _Parser(_tokens(text, where), where).parse()
+
+
+def _names(e) -> set[str]:
+    k = e[0]
+    if k == "var":
+        return {e[1]}
+    if k == "num":
+        return set()
+    if k in ("neg",):
+        return _names(e[1])
+    if k == "call":
+        return _names(e[2])
+    if k == "pow":
+        return _names(e[1])
+    return _names(e[2]) | _names(e[3])
+
+
+def _num(x: float) -> str:
+    s = repr(float(x))
+    return s if ("." in s or "e" in s or "inf" in s or "nan" in s) else s + ".0"
+
+
+def emit_expr(e) -> str:
+    """C++ for an expression: every operation parenthesised, so the C++
+    evaluates exactly the tree that was written."""
+    k = e[0]
+    if k == "num":
+        return _num(e[1])
+    if k == "var":
+        return e[1]
+    if k == "neg":
+        return f"(-{emit_expr(e[1])})"
+    if k == "call":
+        return f"{'gen_exprelr' if e[1] == 'exprelr' else e[1]}({emit_expr(e[2])})"
+    if k == "pow":
+        b = emit_expr(e[1])
+        return "(" + " * ".join([b] * e[2]) + ")"
+    return f"({emit_expr(e[2])} {e[1]} {emit_expr(e[3])})"
+
+
+# ------------------------------------------------------------------ mechanisms
+
+@dataclass
+class Gate:
+    state: str
+    kind: str  # "alpha_beta" or "inf_tau"
+    a: tuple
+    b: tuple
+
+
+@dataclass
+class Mechanism:
+    name: str
+    params: list = field(default_factory=list)    # [(name, default)]
+    states: list = field(default_factory=list)    # [name]
+    rates: list = field(default_factory=list)     # [(name, expr)]
+    gates: list = field(default_factory=list)     # [Gate]
+    current: tuple | None = None
+    source: str = ""
+
+
+def parse_mechanism(text: str, source: str = "<text>") -> Mechanism:
+    m = None
+    for ln, raw in enumerate(text.splitlines(), 1):
+        line = raw.split("#", 1)[0].strip()
+        if not line:
+            continue
+        where = f"{source}:{ln}"
+        word, _, rest = line.partition(" ")
+        rest = rest.strip()
+        if word == "mechanism":
+            if m is not None:
+                raise MechError(f"{where}: one mechanism per file")
+            if not re.fullmatch(r"[A-Za-z_][A-Za-z_0-9]*", rest):
+                raise MechError(f"{where}: bad mechanism name '{rest}'")
+            m = Mechanism(rest, source=source)
+            continue
+        if m is None:
+            raise MechError(f"{where}: the file must start with 'mechanism <name>'")
+        known = {"v"} | {p for p, _ in m.params} | {r for r, _ in m.rates} | set(m.states)
+        if word == "parameter":
+            nm, eq, val = rest.partition("=")
+            nm = nm.strip()
+            if not eq or not re.fullmatch(r"[A-Za-z_][A-Za-z_0-9]*", nm) or nm in known:
+                raise MechError(f"{where}: bad or repeated parameter")
+            e = parse_expr(val, where)
+            if e[0] == "num":
+                dv = e[1]
+            elif e[0] == "neg" and e[1][0] == "num":
+                dv = -e[1][1]
+            else:
+                raise MechError(f"{where}: a parameter default must be a number")
+            m.params.append((nm, dv))
+        elif word == "state":
+            if not re.fullmatch(r"[A-Za-z_][A-Za-z_0-9]*", rest) or rest in known:
+                raise MechError(f"{where}: bad or repeated state")
+            m.states.append(rest)
+        elif word == "rate":
+            nm, eq, ex = rest.partition("=")
+            nm = nm.strip()
+            if not eq or not re.fullmatch(r"[A-Za-z_][A-Za-z_0-9]*", nm) or nm in known:
+                raise MechError(f"{where}: bad or repeated rate")
+            e = parse_expr(ex, where)
+            bad = _names(e) - ({"v"} | {p for p, _ in m.params} | {r for r, _ in m.rates})
+            if bad:
+                raise MechError(f"{where}: a rate may use v, parameters and earlier rates, not {sorted(bad)}")
+            m.rates.append((nm, e))
+        elif word == "gate":
+            toks = rest.split(None, 1)
+            if len(toks) != 2 or toks[0] not in m.states:
+                raise MechError(f"{where}: 'gate <state> alpha <expr> beta <expr>' or '... inf <expr> tau <expr>'")
+            st, spec = toks
+            if any(g.state == st for g in m.gates):
+                raise MechError(f"{where}: state {st} has two gates")
+            mm = re.fullmatch(r"(alpha|inf)\s+(.+?)\s+(beta|tau)\s+(.+)", spec)
+            if not mm or (mm.group(1), mm.group(3)) not in (("alpha", "beta"), ("inf", "tau")):
+                raise MechError(f"{where}: 'gate <state> alpha <expr> beta <expr>' or '... inf <expr> tau <expr>'")
+            ea, eb = parse_expr(mm.group(2), where), parse_expr(mm.group(4), where)
+            allowed = {"v"} | {p for p, _ in m.params} | {r for r, _ in m.rates}
+            bad = (_names(ea) | _names(eb)) - allowed
+            if bad:
+                raise MechError(f"{where}: gate kinetics may use v, parameters and rates, not {sorted(bad)}")
+            m.gates.append(Gate(st, "alpha_beta" if mm.group(1) == "alpha" else "inf_tau", ea, eb))
+        elif word == "current":
+            if m.current is not None:
+                raise MechError(f"{where}: one current per mechanism")
+            e = parse_expr(rest, where)
+            bad = _names(e) - known
+            if bad:
+                raise MechError(f"{where}: unknown names {sorted(bad)}")
+            m.current = e
+        else:
+            raise MechError(f"{where}: unknown statement '{word}'")
+    if m is None:
+        raise MechError(f"{source}: no mechanism")
+    if m.current is None:
+        raise MechError(f"{source}: no current")
+    if {g.state for g in m.gates} != set(m.states):
+        raise MechError(f"{source}: every state needs exactly one gate")
+    if len(m.params) > MAX_PARAMS or len(m.states) > MAX_STATES:
+        raise MechError(f"{source}: at most {MAX_PARAMS} parameters and {MAX_STATES} states")
+    return m
+
+
+def load_catalogue(mech_dir: str = MECH_DIR) -> list[Mechanism]:
+    """Every mechanism file of the directory, in name order (a mechanism's
+    index in the catalogue is its id in the library)."""
+    out = []
+    for path in sorted(glob.glob(os.path.join(mech_dir, "*.mech"))):
+        out.append(parse_mechanism(open(path).read(), os.path.basename(path)))
+    names = [m.name for m in out]
+    if len(set(names)) != len(names):
+        raise MechError("two mechanism files define the same name")
+    return out
+
+
+# ------------------------------------------------------------------ emission
+
+def _gate_lines(m: Mechanism, target: str) -> list[str]:
+    """State updates (target 'advance') or steady states ('steady')."""
+    out = []
+    for g in m.gates:
+        i = m.states.index(g.state)
+        a, b = emit_expr(g.a), emit_expr(g.b)
+        if g.kind == "alpha_beta":
+            out.append(f"{{ const double ra = {a}, rb = {b}, rs = ra + rb, xinf = ra / rs;")
+            out.append(f"  st[{i}] = xinf + (st[{i}] - xinf) * exp(-dt * rs); }}" if target == "advance"
+                       else f"  st[{i}] = xinf; }}")
+        elif target == "advance":
+            out.append(f"{{ const double xinf = {a}, xtau = {b};")
+            out.append(f"  st[{i}] = xinf + (st[{i}] - xinf) * exp(-dt / xtau); }}")
+        else:
+            out.append(f"st[{i}] = {a};")
+    return out
+
+
+def _used(m: Mechanism, exprs) -> set[str]:
+    need = set()
+    for e in exprs:
+        need |= _names(e)
+    for r, e in reversed(m.rates):
+        if r in need:
+            need |= _names(e)
+    return need
+
+
+def _body(m: Mechanism, kind: str) -> list[str]:
+    if kind == "current":
+        exprs = [m.current]
+    elif kind == "steady":
+        exprs = [g.a for g in m.gates] + [g.b for g in m.gates if g.kind == "alpha_beta"]
+    else:
+        exprs = [g.a for g in m.gates] + [g.b for g in m.gates]
+    need = _used(m, exprs)
+    lines = [f"const double {p} = prm[{i}];" for i, (p, _) in enumerate(m.params) if p in need]
+    lines += [f"const double {r} = {emit_expr(e)};" for r, e in m.rates if r in need]
+    if kind == "current":
+        lines += [f"const double {s} = st[{i}];" for i, s in enumerate(m.states) if s in need]
+        lines.append(f"return {emit_expr(m.current)};")
+    else:
+        lines += _gate_lines(m, kind)
+    return lines
+
+
+def _switch(cat: list[Mechanism], kind: str, indent: str) -> str:
+    out = []
+    for k, m in enumerate(cat):
+        out.append(f"{indent}case {k}: {{  // {m.name}")
+        out += [indent + "    " + ln for ln in _body(m, kind)]
+        if kind != "current":
+            out.append(indent + "    return;")
+        out.append(indent + "}")
+    return "\n".join(out)
+
+
+_HEADER = """// GENERATED by paper_1901_07454_amd/mechgen.py from mechanisms/*.mech -- do not edit.
+"""
+
+
+def render_desc(cat: list[Mechanism]) -> str:
+    rows = []
+    for m in cat:
+        pn = ", ".join(f'"{p}"' for p, _ in m.params) or '""'
+        pd = ", ".join(_num(d) for _, d in m.params) or "0.0"
+        sn = ", ".join(f'"{s}"' for s in m.states)
+        rows.append(f'    {{"{m.name}", {len(m.params)}, {len(m.states)}, {{{pn}}}, {{{pd}}}, {{{sn}}}}},')
+    return _HEADER + f"""// Host side of the generated mechanisms: the catalogue (names, parameters
+// and their defaults, states) and each mechanism's steady state at a voltage.
+#pragma once
+#include <cmath>
+
+namespace arbmi {{
+namespace gen {{
+
+constexpr int kMaxParams = {MAX_PARAMS};
+constexpr int kMaxStates = {MAX_STATES};
+constexpr int kNumMechs = {len(cat)};
+
+struct MechDesc {{
+    const char* name;
+    int n_params, n_states;
+    const char* param_names[kMaxParams];
+    double defaults[kMaxParams];
+    const char* state_names[kMaxStates];
+}};
+
+inline const MechDesc kMechs[kNumMechs > 0 ? kNumMechs : 1] = {{
+{chr(10).join(rows) if rows else '    {"", 0, 0, {""}, {0.0}, {""}},'}
+}};
+
+// x / (e^x - 1), 1 where 1 + x == 1 (its limit at 0)
+inline double gen_exprelr_host(double x) {{ return (1.0 + x == 1.0) ? 1.0 : x / std::expm1(x); }}
+
+// the outward current density of mechanism `id` (the device code's
+// expression, on the host)
+inline double current_host(int id, double v, const double* prm, const double* st) {{
+    using std::exp; using std::expm1; using std::log; using std::sqrt;
+    auto gen_exprelr = gen_exprelr_host;
+    (void)v; (void)prm; (void)st; (void)gen_exprelr;
+    switch (id) {{
+{_switch(cat, "current", "        ")}
+        default:
+            return 0.0;
+    }}
+}}
+
+// the states of mechanism `id` at rest at voltage v
+inline void steady(int id, double v, const double* prm, double* st) {{
+    using std::exp; using std::expm1; using std::log; using std::sqrt;
+    auto gen_exprelr = gen_exprelr_host;
+    (void)v; (void)prm; (void)st; (void)gen_exprelr;
+    switch (id) {{
+{_switch(cat, "steady", "        ")}
+        default:
+            return;
+    }}
+}}
+
+}}  // namespace gen
+}}  // namespace arbmi
+"""
+
+
+def render_device(cat: list[Mechanism]) -> str:
+    return _HEADER + f"""// Device side of the generated mechanisms: each one's outward current
+// density at voltage v (S/cm^2 x mV; times 10 x the instance's area in um^2
+// it is in pA) and its state update over a step of dt at v.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mechanisms_desc.hpp"
+
+namespace arbmi {{
+namespace gen {{
+
+__device__ __forceinline__ double gen_exprelr(double x) {{ return (1.0 + x == 1.0) ? 1.0 : x / expm1(x); }}
+
+__device__ __forceinline__ double current(int id, double v, const double* prm, const double* st) {{
+    switch (id) {{
+{_switch(cat, "current", "        ")}
+        default:
+            return 0.0;
+    }}
+}}
+
+__device__ __forceinline__ void advance(int id, double v, double dt, const double* prm, double* st) {{
+    switch (id) {{
+{_switch(cat, "advance", "        ")}
+        default:
+            return;
+    }}
+}}
+
+}}  // namespace gen
+}}  // namespace arbmi
+"""
+
+
+def generate(out_dir: str = OUT_DIR, mech_dir: str = MECH_DIR) -> list[str]:
+    """Write both headers (only when their text changes); returns the paths."""
+    cat = load_catalogue(mech_dir)
+    os.makedirs(out_dir, exist_ok=True)
+    paths = []
+    for name, text in (("mechanisms_desc.hpp", render_desc(cat)), ("mechanisms.hpp", render_device(cat))):
+        path = os.path.join(out_dir, name)
+        if not os.path.exists(path) or open(path).read() != text:
+            with open(path, "w") as f:
+                f.write(text)
+        paths.append(path)
+    return paths
+
+
+if __name__ == "__main__":
+    for p in generate():
+        print(p)

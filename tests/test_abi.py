@@ -342,3 +342,42 @@ def test_timed_build_valid_model_reaches_the_device_step():
     with pytest.raises(arbmi.ArbError) as e:  # block_threads honoured
         _build_timed(gen.config2_timed(n_cells=3, t_ms=5.0), block_threads=128)
     assert e.value.code == arbmi.ARB_EHIP
+
+
+def test_density_validation():
+    """Generated density mechanisms: entries are checked (cell, branch,
+    mechanism, parameter count, finite values), and refused with gradients,
+    the variable time step and layouts other than the register-resident one."""
+    m = gen.config2_mech(n_cells=2, n_steps=10)
+
+    def expect(mm, text, **kw):
+        with pytest.raises(arbmi.ArbError) as e:
+            _build(mm, **kw)
+        assert e.value.code == arbmi.ARB_EINVAL and text in str(e.value), str(e.value)
+
+    def bad(**change):
+        d = arbmi.density_structs(m["densities"][:1])
+        for k, v in change.items():
+            setattr(d[0], k, v)
+        return d
+
+    def build_with(d, **kw):
+        p = _params(**kw)
+        p.densities = ctypes.cast(d, ctypes.c_void_p)
+        p.n_densities = len(d)
+        return arbmi.arb_build_cells(*arbmi.model_structs(m), p)
+
+    for change, text in (({"cell": 5}, "out of range"), ({"branch": 999}, "out of range"),
+                         ({"mech": 99}, "unknown mechanism"), ({"n_param": 9}, "parameters")):
+        with pytest.raises(arbmi.ArbError) as e:
+            build_with(bad(**change))
+        assert text in str(e.value), str(e.value)
+    d = bad()
+    d[0].param[0] = float("nan")
+    with pytest.raises(arbmi.ArbError) as e:
+        build_with(d)
+    assert "not finite" in str(e.value)
+    for kw, text in (({"flags": arbmi.ARB_FLAG_GRADIENTS}, "gradients"), ({"coef_mode": 1}, "register layout")):
+        with pytest.raises(arbmi.ArbError) as e:
+            build_with(arbmi.density_structs(m["densities"]), **kw)
+        assert text in str(e.value), str(e.value)

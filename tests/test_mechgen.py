@@ -1,0 +1,182 @@
+"""The mechanism description language and its HIP generator (the role of the
+paper's NMODL compiler, Sec. III-C "Mechanisms", Sec. IV-C): the parser's
+checks, the generated headers kept in step with the mechanism files, the
+emitted C++ evaluating the trees that were written (compiled on the host and
+compared with an interpreter of the parsed description), and the oracle's
+hand-written mechanisms agreeing with the descriptions."""
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_07454_amd import mechgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _eval(e, env):
+    """Interpret a parsed expression with Python floats."""
+    k = e[0]
+    if k == "num":
+        return e[1]
+    if k == "var":
+        return env[e[1]]
+    if k == "neg":
+        return -_eval(e[1], env)
+    if k == "pow":
+        return _eval(e[1], env) ** e[2]
+    if k == "call":
+        x = _eval(e[2], env)
+        if e[1] == "exprelr":
+            return 1.0 if 1.0 + x == 1.0 else x / math.expm1(x)
+        return getattr(math, e[1])(x)
+    a, b = _eval(e[2], env), _eval(e[3], env)
+    return {"+": a + b, "-": a - b, "*": a * b, "/": a / b}[e[1]]
+
+
+def _env(m, v, params=None):
+    env = {"v": v}
+    env.update({p: d for p, d in m.params})
+    env.update(params or {})
+    for r, e in m.rates:
+        env[r] = _eval(e, env)
+    return env
+
+
+def steady_of(m, v, params=None):
+    env = _env(m, v, params)
+    out = []
+    for st in m.states:
+        g = next(g for g in m.gates if g.state == st)
+        a = _eval(g.a, env)
+        out.append(a / (a + _eval(g.b, env)) if g.kind == "alpha_beta" else a)
+    return out
+
+
+def current_of(m, v, states, params=None):
+    env = _env(m, v, params)
+    env.update(dict(zip(m.states, states)))
+    return _eval(m.current, env)
+
+
+def test_parser_reads_the_grammar():
+    e = mechgen.parse_expr("-a^3 * b / (c - 2.5e-1) + exprelr(-(v + 40) / 10)")
+    env = {"a": 1.5, "b": 2.0, "c": 0.75, "v": -52.0}
+    ref = -1.5 ** 3 * 2.0 / (0.75 - 0.25) + (-(-52 + 40) / 10) / math.expm1(-(-52 + 40) / 10)
+    assert abs(_eval(e, env) - ref) < 1e-14
+    assert mechgen.emit_expr(mechgen.parse_expr("x^2")) == "(x * x)"
+    assert mechgen.emit_expr(mechgen.parse_expr("2 - 3 - 4")) == "((2.0 - 3.0) - 4.0)"
+
+
+@pytest.mark.parametrize("text,msg", [
+    ("state n\n", "must start"),
+    ("mechanism k\nparameter g = 1\nstate n\ngate n alpha 1 beta 1\n", "no current"),
+    ("mechanism k\nstate n\ncurrent n * v\n", "exactly one gate"),
+    ("mechanism k\nstate n\nrate a = n * 2\ngate n alpha a beta 1\ncurrent n\n", "rate may use"),
+    ("mechanism k\nstate n\ngate n alpha 1 tau 2\ncurrent n\n", "alpha"),
+    ("mechanism k\nstate n\ngate n alpha foo(v) beta 1\ncurrent n\n", "unknown function"),
+    ("mechanism k\nstate n\ngate n alpha 1 beta 1\ncurrent n^9\n", "integer exponent"),
+    ("mechanism k\nstate n\ngate n alpha 1 beta 1\ncurrent n * w\n", "unknown names"),
+    ("mechanism k\nparameter g = 1\nparameter g = 2\nstate n\ngate n alpha 1 beta 1\ncurrent g\n", "repeated"),
+    ("mechanism k\nparameter g = v\nstate n\ngate n alpha 1 beta 1\ncurrent g\n", "must be a number"),
+])
+def test_parser_rejects_bad_descriptions(text, msg):
+    with pytest.raises(mechgen.MechError) as e:
+        mechgen.parse_mechanism(text)
+    assert msg in str(e.value)
+
+
+def test_generated_headers_are_current(tmp_path):
+    """The committed headers are what the mechanism files generate."""
+    paths = mechgen.generate(out_dir=str(tmp_path))
+    for p in paths:
+        committed = os.path.join(mechgen.OUT_DIR, os.path.basename(p))
+        assert open(p).read() == open(committed).read(), f"{committed} is stale: run mechgen.py"
+
+
+def test_emitted_code_computes_the_description(tmp_path):
+    """The generated host functions (the same emitter as the device code),
+    compiled with g++, against the interpreter of the parsed descriptions:
+    steady states and currents at voltages across the physiological range,
+    with the defaults and with changed parameters."""
+    cat = mechgen.load_catalogue()
+    prog = tmp_path / "probe.cpp"
+    prog.write_text(f"""
+#include <cstdio>
+#include "{mechgen.OUT_DIR}/mechanisms_desc.hpp"
+using namespace arbmi::gen;
+int main() {{
+    const double vs[] = {{-100, -80, -65, -52, -40.0000001, -40, -20, 0, 30}};
+    for (int id = 0; id < kNumMechs; ++id)
+        for (int scale = 0; scale < 2; ++scale)
+            for (double v : vs) {{
+                double p[kMaxParams], s[kMaxStates] = {{}};
+                for (int k = 0; k < kMaxParams; ++k) p[k] = kMechs[id].defaults[k] * (scale ? 1.3 : 1.0);
+                steady(id, v, p, s);
+                std::printf("%d %d %.17g", id, scale, v);
+                for (int k = 0; k < kMechs[id].n_states; ++k) std::printf(" %.17g", s[k]);
+                std::printf(" %.17g\\n", current_host(id, v, p, s));
+            }}
+}}
+""")
+    exe = tmp_path / "probe"
+    subprocess.run(["g++", "-std=c++17", "-O0", "-ffp-contract=off", str(prog), "-o", str(exe)], check=True)
+    rows = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    n = 0
+    for row in rows:
+        if not row:
+            continue
+        f = row.split()
+        m = cat[int(f[0])]
+        scale = 1.3 if int(f[1]) else 1.0
+        v = float(f[2])
+        prm = {p: d * scale for p, d in m.params}
+        st = steady_of(m, v, prm)
+        got = [float(x) for x in f[3:3 + len(m.states)]]
+        assert np.allclose(got, st, rtol=1e-14, atol=0), (m.name, v)
+        cur = current_of(m, v, got, prm)
+        assert abs(float(f[-1]) - cur) <= 1e-13 * max(1.0, abs(cur)), (m.name, v)
+        n += 1
+    assert n == len(cat) * 2 * 9
+
+
+def test_library_catalogue_matches_the_files():
+    from paper_1901_07454_amd import arbmi
+    cat = mechgen.load_catalogue()
+    lib = arbmi.mechanism_catalogue()
+    assert [m["name"] for m in lib] == [m.name for m in cat]
+    for a, b in zip(lib, cat):
+        assert a["params"] == [p for p, _ in b.params]
+        assert a["defaults"] == [d for _, d in b.params]
+        assert a["n_states"] == len(b.states)
+
+
+def test_oracle_mechanisms_agree_with_their_descriptions():
+    """The oracle's hand-written kdr, hcn and hh_dsl (oracle.c) against the
+    interpreter of the description files: a one-CV cell carrying only the
+    mechanism starts at the description's steady state and its first-step
+    membrane current is the description's current times the area."""
+    from workloads import gen
+    from tests import models
+    cat = {m.name: m for m in mechgen.load_catalogue()}
+    for name, prm in (("kdr", {"gbar": 0.02, "ek": -85.0}), ("hcn", {"gbar": 0.001, "vhalf": -70.0}),
+                      ("hh_dsl", {"gnabar": 0.1, "gl": 0.0005})):
+        for v0 in (-80.0, -65.0, -40.0, -10.0):
+            d = models.bare_cell([-1], [1], [100.0], [2.0], soma_mech=0, dend_mech=0)
+            m = gen.assemble([d], n_steps=0)
+            m["v_init"] = v0
+            s = oracle.Sim(gen.with_densities(m, [(0, -1, name, prm)]))
+            assert s.ngen == 1
+            mech = cat[name]
+            full = {p: d_ for p, d_ in mech.params}
+            full.update(prm)
+            ref = steady_of(mech, v0, full)
+            assert np.allclose(s.gen_states()[0, :len(ref)], ref, rtol=1e-14, atol=0), (name, v0)
+            # the soma CV: only the density's piece (the soma's area) carries a current
+            I = s.membrane_current(0)
+            cur = 10.0 * float(m["soma_area"][0]) * current_of(mech, v0, ref, full)
+            assert abs(I[0] - cur) <= 1e-12 * max(1.0, abs(cur)), (name, v0, I[0], cur)
+            assert I[1] == 0.0

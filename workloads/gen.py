@@ -555,6 +555,35 @@ def config2_timed(n_cells: int = 8192, cells=None, t_ms: float = 100.0) -> dict:
     return timed(m, con_delay_ms=d_ms, ev_t=np.array(ev_t, np.float64))
 
 
+def with_densities(m: dict, dens) -> dict:
+    """The model with generated density mechanisms: (cell, branch, mechanism
+    name, {parameter: value}) entries, branch -1 = the soma."""
+    out = dict(m)
+    out["densities"] = [(int(c), int(b), str(n), dict(p or {})) for c, b, n, p in dens]
+    return out
+
+
+def config2_mech(n_cells: int = 8, n_steps: int = 2000) -> dict:
+    """The ring's cells with the generated mechanisms on them: hcn on the soma
+    (gbar 3e-4 S/cm^2), kdr on every dendritic branch (gbar 2e-3), and
+    hh_dsl on branch 0 (gnabar 0.04, gkbar 0.012, no leak); every cell is
+    kicked again on its soma synapse every 10 ms (w 0.05 uS), so that it
+    keeps firing."""
+    m = config2(n_cells=n_cells, n_steps=n_steps)
+    syn0 = np.concatenate([[0], np.cumsum(np.bincount(m["syn_cell"], minlength=n_cells))])[:-1]
+    kick = np.arange(400, n_steps, 400, dtype=np.int64)
+    m["ev_syn"] = np.concatenate([m["ev_syn"], np.repeat(syn0.astype(np.uint32), len(kick))])
+    m["ev_step"] = np.concatenate([m["ev_step"], np.tile(kick, n_cells)])
+    m["ev_w"] = np.concatenate([m["ev_w"], np.full(n_cells * len(kick), 0.05)])
+    dens = []
+    for c in range(n_cells):
+        dens.append((c, -1, "hcn", {"gbar": 3e-4}))
+        for b in range(int(m["cell_n_branch"][c])):
+            dens.append((c, b, "kdr", {"gbar": 2e-3}))
+        dens.append((c, 0, "hh_dsl", {"gnabar": 0.04, "gkbar": 0.012, "gl": 0.0}))
+    return with_densities(m, dens)
+
+
 def ring_light_cone(n_cells: int, target: int, n_steps: int, delay: int = 200) -> list[int]:
     """Cells of the config-2 ring whose spikes can reach `target` within
     n_steps: a spike of cell target-j needs at least j*(delay+1) steps."""
