@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -216,17 +217,87 @@ def measured_traffic(path: str, cfg: int, kernel: str, steps_per_launch: float):
     sources unchanged since; else None.  The summary holds a fixed part per
     launch (loading and storing the packs' state) and a part per step, fitted
     from launches of two lengths, so any launch length gets a figure."""
-    import hashlib
     try:
         rec = json.load(open(path))[f"config{cfg}"]
-        h = hashlib.sha256()
-        for p in rec["kernel_sources"]:
-            h.update(open(os.path.join(ROOT, p), "rb").read())
-        if h.hexdigest() != rec["kernel_sha256"] or rec["kernel"] != kernel:
+        if _sources_sha(rec["kernel_sources"]) != rec["kernel_sha256"] or rec["kernel"] != kernel:
             return None
         return rec["fixed_bytes_per_launch"] + rec["bytes_per_step"] * steps_per_launch
     except Exception:
         return None
+
+
+# The sources a step kernel's traffic depends on (a recorded figure holds
+# while their hash is unchanged).
+CSRC = "paper_1901_07454_amd/csrc/"
+KERNEL_SOURCES = {
+    "reg": [CSRC + f for f in ("reg_kernels.hip", "reg_solve.hpp", "kernel_common.hpp", "layout.hpp",
+                               "kernels.hpp", "fastexp.hpp", "gen/mechanisms.hpp", "gen/mechanisms_desc.hpp")],
+    "var": [CSRC + f for f in ("var_kernels.hip", "var_kernels.hpp", "reg_solve.hpp", "kernel_common.hpp",
+                               "layout.hpp", "kernels.hpp", "fastexp.hpp")],
+}
+
+
+def _sources_sha(paths) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()
+
+
+def _counter_rows(path: str):
+    import csv
+    return list(csv.DictReader(open(path)))
+
+
+def fit_traffic(run_dir: str, key: str, kernel: str, family: str, out_path: str) -> dict:
+    """Fit the HBM traffic of one workload's step kernels from rocprofv3
+    counter runs of the benchmark at two epoch lengths.  run_dir holds, per
+    epoch length K, `fetch_K<K>/` and `write_K<K>/` (the `--pmc FETCH_SIZE`
+    and `--pmc WRITE_SIZE` runs, csv output) and `bench_K<K>.json` (the
+    benchmark's line, for the number of epochs run).  Per epoch, the step
+    kernels' dispatches (every launch class) are summed; the counters are
+    scaled by what they read for the benchmark's 2 GiB device copy (FETCH_SIZE
+    and WRITE_SIZE in KiB per dispatch against 2 GiB read and written);
+    bytes per epoch = fixed + per_step K is solved from the two lengths.  The
+    record is written into out_path (JSON) under `key`."""
+    import glob
+    pts, scales = {}, {"FETCH_SIZE": [], "WRITE_SIZE": []}
+    for bj in sorted(glob.glob(os.path.join(run_dir, "bench_K*.json"))):
+        K = int(re.search(r"bench_K(\d+)\.json", bj).group(1))
+        line = json.loads([ln for ln in open(bj).read().splitlines() if ln.startswith("{")][-1])
+        epochs = (line["steps"] + line["warmup"]) // K
+        kib = {}
+        for ctr, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+            rows = _counter_rows(glob.glob(os.path.join(run_dir, f"{sub}_K{K}", "**", "*counter_collection.csv"),
+                                           recursive=True)[0])
+            step = sum(float(r["Counter_Value"]) for r in rows
+                       if r["Counter_Name"] == ctr and "step_kernel" in r["Kernel_Name"])
+            copies = sorted((float(r["Counter_Value"]) for r in rows
+                             if r["Counter_Name"] == ctr and "copyBuffer" in r["Kernel_Name"]), reverse=True)[:10]
+            scales[ctr].append(2097152.0 / float(np.median(copies)))
+            kib[ctr] = step / epochs
+        pts[K] = kib
+    (k1, p1), (k2, p2) = sorted(pts.items())[:2]
+    sf, sw = float(np.median(scales["FETCH_SIZE"])), float(np.median(scales["WRITE_SIZE"]))
+    b1 = 1024.0 * (p1["FETCH_SIZE"] * sf + p1["WRITE_SIZE"] * sw)
+    b2 = 1024.0 * (p2["FETCH_SIZE"] * sf + p2["WRITE_SIZE"] * sw)
+    per_step = (b2 - b1) / (k2 - k1)
+    rec = {"kernel": kernel, "epoch_lengths": [k1, k2],
+           "fetch_kib_per_epoch": [p1["FETCH_SIZE"], p2["FETCH_SIZE"]],
+           "write_kib_per_epoch": [p1["WRITE_SIZE"], p2["WRITE_SIZE"]],
+           "fetch_scale": sf, "write_scale": sw,
+           "fixed_bytes_per_launch": b1 - per_step * k1, "bytes_per_step": per_step,
+           "kernel_sources": KERNEL_SOURCES[family], "kernel_sha256": _sources_sha(KERNEL_SOURCES[family])}
+    try:
+        allrec = json.load(open(out_path))
+    except Exception:
+        allrec = {}
+    allrec[key] = rec
+    with open(out_path, "w") as f:
+        json.dump(allrec, f, indent=1, sort_keys=True)
+        f.write("\n")
+    return rec
 
 
 def grad_ratio(torch, reps: int = 3, subset: bool = False):
@@ -363,11 +434,20 @@ def main():
                     help="config 7: emulate this many identical ranks (proxy spikes, Sec. V-E dry run); a comma "
                          "list sweeps them, the first giving the headline line")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.txt"))
+    ap.add_argument("--fit-traffic", metavar="RUN_DIR", default=None,
+                    help="fit the step kernels' HBM traffic from counter runs in RUN_DIR (see fit_traffic) "
+                         "into --traffic-json for --config (or --varstep), then exit")
+    ap.add_argument("--kernel", default=None, help="with --fit-traffic: the kernel the runs launched")
     ap.add_argument("--varstep", action="store_true",
                     help="the ring (config 2) with the variable time step: steps cut at off-grid event times")
     args = ap.parse_args()
     if args.varstep and args.config != 2:
         raise SystemExit("--varstep runs the ring: use it with --config 2")
+    if args.fit_traffic:
+        key = "config2t" if args.varstep else f"config{args.config}"
+        rec = fit_traffic(args.fit_traffic, key, args.kernel, "var" if args.varstep else "reg", args.traffic_json)
+        print(json.dumps({key: rec}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         raise SystemExit(2)
