@@ -33,33 +33,49 @@ __device__ inline Rates hh_rates(double v) {
     return r;
 }
 
-// The two rates of one gate of hh_rates (w = 0, 1, 2: m, h, n), with the
-// same expressions, for giving each gate its own thread; e^x and e^x - 1 come
-// from exp_pair (a shorter dependency chain than the library's, within 2 ulp
-// of it).  Both candidate forms of alpha (exprelr-based for m and n,
-// exp-based for h) come from the one exp_pair of its argument and one is
-// kept, so every thread runs the same straight-line code; the per-gate
-// constants go through an empty asm so that the compiler does not specialise
-// the code for each constant.
+// 1/d from the hardware's approximate reciprocal and two Newton steps
+// (within an ulp or so of the rounded quotient; d positive and normal).
+__device__ inline double recip(double d) {
+    double y = __builtin_amdgcn_rcp(d);
+    y = fma(y, fma(-d, y, 1.0), y);
+    y = fma(y, fma(-d, y, 1.0), y);
+    return y;
+}
+
+// The per-gate constants go through an empty asm so that the compiler does
+// not specialise the code below for each gate.
 __device__ inline double opaque(double x) {
     asm volatile("" : "+v"(x));
     return x;
 }
-__device__ inline void hh_gate_rates(int w, double v, double& alpha, double& beta) {
+
+// One gate of an hh instance (w = 0, 1, 2: m, h, n) advanced over a step of
+// length dt at fixed V, by the exact update of gate_step with the rates of
+// hh_rates, for giving each gate its own thread.  Each rate is formed as a
+// quotient, alpha = na/da and beta = nb/db (da = e^xa - 1 for the exprelr
+// rates, db = e^xb + 1 for beta_h, 1 otherwise), so alpha + beta = p/q and
+// x_inf = alpha/(alpha + beta) = na db/p with p = na db + nb da, q = da db,
+// and one reciprocal of p q gives both.  e^x and e^x - 1 come from exp_pair
+// (a shorter dependency chain than the library's, within 2 ulp of it); both
+// candidate forms of alpha come from the one exp_pair of its argument, so
+// every thread runs the same straight-line code.
+__device__ inline double hh_gate_advance(int w, double v, double x, double dt) {
     const double xa = -(v + opaque((w == 0) ? 40.0 : (w == 1) ? 65.0 : 55.0)) * opaque((w == 1) ? 0.05 : 0.1);
     const ExpPair pa = exp_pair(xa);
-    const double er = (1.0 + xa == 1.0) ? 1.0 : xa / pa.em1;  // exprelr(xa)
-    alpha = (w == 1) ? 0.07 * pa.e : (w == 2) ? 0.1 * er : er;
     const double xb = -(v + opaque((w == 1) ? 35.0 : 65.0)) *
                       opaque((w == 0) ? (1.0 / 18.0) : (w == 1) ? 0.1 : (1.0 / 80.0));
     const double eb = exp_pair(xb).e;
-    beta = (w == 1) ? 1.0 / (eb + 1.0) : ((w == 0) ? 4.0 : 0.125) * eb;
-}
-
-// gate_step with e^x from exp_pair
-__device__ inline double gate_step_pair(double x, double a, double b, double dt) {
-    const double s = a + b;
-    const double xinf = a / s;
+    const bool h = w == 1;
+    const bool tiny = 1.0 + xa == 1.0;  // exprelr's removable singularity: alpha_m = 1, alpha_n = 0.1
+    const double na = h ? 0.07 * pa.e : (tiny ? 1.0 : xa) * opaque((w == 0) ? 1.0 : 0.1);
+    const double da = (h || tiny) ? 1.0 : pa.em1;
+    const double nb = h ? 1.0 : opaque((w == 0) ? 4.0 : 0.125) * eb;
+    const double db = h ? eb + 1.0 : 1.0;
+    const double p = na * db + nb * da;
+    const double q = da * db;
+    const double r = recip(p * q);
+    const double s = p * (p * r);  // alpha + beta
+    const double xinf = (na * db) * (q * r);
     return xinf + (x - xinf) * exp_pair(-dt * s).e;
 }
 

@@ -349,29 +349,7 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
         if constexpr (S > 1) local_store<L>(g1, sC, sF);
         if constexpr (S > 2) local_store<L>(g2, sC, sF);
         round_sync<T>();
-        if (pk.binary) {  // contributions up, two levels a round, deepest first
-            for (int sr = 0; 2 * sr < pk.nlev; ++sr) {
-                if (((pk.nlev - 1 - g0.lev) >> 1) == sr && g0.c0 != pk.ntk) pass_up2<L>(g0, sF, sQ, sC);
-                if constexpr (S > 1) {
-                    if (((pk.nlev - 1 - g1.lev) >> 1) == sr && g1.c0 != pk.ntk) pass_up2<L>(g1, sF, sQ, sC);
-                }
-                if constexpr (S > 2) {
-                    if (((pk.nlev - 1 - g2.lev) >> 1) == sr && g2.c0 != pk.ntk) pass_up2<L>(g2, sF, sQ, sC);
-                }
-                round_sync<T>();
-            }
-        } else {
-            for (int r = 0; r < pk.nrd; ++r) {  // contributions up, deepest rounds first
-                if (g0.r == r && g0.c0 != pk.ntk) pass_up<L>(g0, sC, s_ch);
-                if constexpr (S > 1) {
-                    if (g1.r == r && g1.c0 != pk.ntk) pass_up<L>(g1, sC, s_ch);
-                }
-                if constexpr (S > 2) {
-                    if (g2.r == r && g2.c0 != pk.ntk) pass_up<L>(g2, sC, s_ch);
-                }
-                round_sync<T>();
-            }
-        }
+        up_pass<T, S, L>(pk, g0, g1, g2, sF, sQ, sC, s_ch);
         {
             full_chain<L>(g0, y0);
             if constexpr (S > 1) full_chain<L>(g1, y1);
@@ -381,16 +359,7 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
             if constexpr (S > 2) sY[g2.task] = g2.yl;
         }
         round_sync<T>();
-        for (int sr = 0; 2 * sr < pk.nlev; ++sr) {  // distal V down, two levels a round, shallowest first
-            if ((g0.lev >> 1) == sr) pass_down<L>(g0, sY, sX);
-            if constexpr (S > 1) {
-                if ((g1.lev >> 1) == sr) pass_down<L>(g1, sY, sX);
-            }
-            if constexpr (S > 2) {
-                if ((g2.lev >> 1) == sr) pass_down<L>(g2, sY, sX);
-            }
-            round_sync<T>();
-        }
+        down_pass<T, S, L>(pk, g0, g1, g2, sY, sX);
         {
             subst_chain<L>(g0, y0);
             if constexpr (S > 1) subst_chain<L>(g1, y1);
@@ -414,14 +383,12 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
         if (pk.nhh <= kSpreadHH) {
             for (int j = tid; j < 3 * pk.nhh; j += T) {
                 const int q = j / 3, w = j - 3 * q;
-                double al, be;
-                hh_gate_rates(w, sV[s_hhs[q]], al, be);
                 double* x = (w == 0) ? sm : (w == 1) ? sh : sn;
                 if (rec) {  // the gate before its update
                     double* r = (w == 0) ? a.rec_m : (w == 1) ? a.rec_h : a.rec_n;
                     r[int64_t(s) * a.n_hh_total + pk.hh0 + q] = x[q];
                 }
-                x[q] = gate_step_pair(x[q], al, be, a.dt);
+                x[q] = hh_gate_advance(w, sV[s_hhs[q]], x[q], a.dt);
             }
         } else {
             for (int q = tid; q < pk.nhh; q += T) {

@@ -219,6 +219,53 @@ __device__ __forceinline__ void pass_down(Slot<L>& g, const double* sY, double* 
     sX[g.task] = g.yl + g.Z * g.xp;
 }
 
+// The same two passes with every slot taking part in every round, so that a
+// round has no branches and issues all of its slots' loads before any
+// arithmetic (one LDS round trip a round instead of one per slot and
+// child).  A branch's inputs are final from the round before its own (its
+// grandchildren's round going up, its grandparent's going down) and nothing
+// reads its entry before the round after its own; so the rounds before its
+// own compute values that are never read, and the rounds after it recompute
+// the same values from the same inputs and store identical bits.  An empty
+// slot reads zero entries and writes the discard entry.  Results equal
+// pass_up2 and pass_down bit for bit.
+struct Up2In {
+    double f0, q0, a0, b0;  // first child: F_0 P_0, F_0 Q_0, its children's contributions
+    double f1, q1, a1, b1;  // second child
+};
+template <int L>
+__device__ __forceinline__ Up2In up2_load(const Slot<L>& g, const double* sF, const double* sQ, const double* sC) {
+    Up2In u;
+    u.f0 = sF[g.c0];
+    u.q0 = sQ[g.c0];
+    u.a0 = sC[g.x0 & 0xffff];
+    u.b0 = sC[int(unsigned(g.x0) >> 16)];
+    u.f1 = sF[g.c1];
+    u.q1 = sQ[g.c1];
+    u.a1 = sC[g.x1 & 0xffff];
+    u.b1 = sC[int(unsigned(g.x1) >> 16)];
+    return u;
+}
+template <int L>
+__device__ __forceinline__ void up2_store(Slot<L>& g, const Up2In& u, double* sC) {
+    const double s0 = u.f0 - u.q0 * (u.a0 + u.b0);
+    const double s1 = u.f1 - u.q1 * (u.a1 + u.b1);
+    g.cs = s0 + s1;
+    sC[g.task] = g.fp - g.FQ * g.cs;
+}
+struct DownIn {
+    double y, x;  // parent's V with a grounded grandparent, grandparent's distal V
+};
+template <int L>
+__device__ __forceinline__ DownIn down_load(const Slot<L>& g, const double* sY, const double* sX) {
+    return DownIn{sY[g.ptask], sX[g.gptask]};
+}
+template <int L>
+__device__ __forceinline__ void down_store(Slot<L>& g, const DownIn& d, double* sX) {
+    g.xp = d.y + g.Zp * d.x;
+    sX[g.task] = g.yl + g.Z * g.xp;
+}
+
 // End of a round of the tree passes.  A one-wave workgroup needs no
 // barrier and no wait: a wave's LDS operations take effect in issue order,
 // so the next round's loads see this round's stores.
@@ -236,6 +283,55 @@ __device__ __forceinline__ void round_sync() {
         __builtin_amdgcn_wave_barrier();
     else
         __syncthreads();
+}
+
+// The upward pass of the split solve over the thread's S slots: packs with
+// at most binary branch points take two tree levels a round with every slot
+// in every round (up2_load, up2_store); other packs one round of the host's
+// schedule at a time, each slot in its own round.
+template <int T, int S, int L>
+__device__ __forceinline__ void up_pass(const PackDesc& pk, Slot<L>& g0, Slot<L>& g1, Slot<L>& g2, const double* sF,
+                                        const double* sQ, double* sC, const int32_t* s_ch) {
+    if (pk.binary) {
+        for (int sr = 0; 2 * sr < pk.nlev; ++sr) {
+            Up2In u0, u1, u2;
+            u0 = up2_load<L>(g0, sF, sQ, sC);
+            if constexpr (S > 1) u1 = up2_load<L>(g1, sF, sQ, sC);
+            if constexpr (S > 2) u2 = up2_load<L>(g2, sF, sQ, sC);
+            up2_store<L>(g0, u0, sC);
+            if constexpr (S > 1) up2_store<L>(g1, u1, sC);
+            if constexpr (S > 2) up2_store<L>(g2, u2, sC);
+            round_sync<T>();
+        }
+    } else {
+        for (int r = 0; r < pk.nrd; ++r) {  // deepest rounds first
+            if (g0.r == r && g0.c0 != pk.ntk) pass_up<L>(g0, sC, s_ch);
+            if constexpr (S > 1) {
+                if (g1.r == r && g1.c0 != pk.ntk) pass_up<L>(g1, sC, s_ch);
+            }
+            if constexpr (S > 2) {
+                if (g2.r == r && g2.c0 != pk.ntk) pass_up<L>(g2, sC, s_ch);
+            }
+            round_sync<T>();
+        }
+    }
+}
+
+// The downward pass: two tree levels a round, shallowest first, every slot
+// in every round (down_load, down_store).
+template <int T, int S, int L>
+__device__ __forceinline__ void down_pass(const PackDesc& pk, Slot<L>& g0, Slot<L>& g1, Slot<L>& g2, const double* sY,
+                                          double* sX) {
+    for (int sr = 0; 2 * sr < pk.nlev; ++sr) {
+        DownIn d0, d1, d2;
+        d0 = down_load<L>(g0, sY, sX);
+        if constexpr (S > 1) d1 = down_load<L>(g1, sY, sX);
+        if constexpr (S > 2) d2 = down_load<L>(g2, sY, sX);
+        down_store<L>(g0, d0, sX);
+        if constexpr (S > 1) down_store<L>(g1, d1, sX);
+        if constexpr (S > 2) down_store<L>(g2, d2, sX);
+        round_sync<T>();
+    }
 }
 
 
