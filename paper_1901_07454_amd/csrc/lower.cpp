@@ -364,14 +364,48 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
         out.clear();
         int maxd = 0;
         for (int32_t c : cs) for (int d : geo[c].sdepth) maxd = std::max(maxd, d);
+        // The items of each level in top-down order: the somas in cell order,
+        // then at each deeper level every parent's first child in the order
+        // of the parents, then every second child, and so on.  Consecutive
+        // threads of a round then read consecutive entries for their
+        // children and grandchildren in the tree passes (no LDS bank
+        // conflicts in a full binary tree); the arithmetic of every branch
+        // is the same in any order.
+        std::vector<std::vector<Item>> lev(maxd + 1);
+        {
+            std::vector<std::vector<int32_t>> pos(cs.size()), rank(cs.size());
+            for (size_t ci = 0; ci < cs.size(); ++ci) {
+                const auto& G = geo[cs[ci]];
+                lev[0].push_back({cs[ci], -1, 1});
+                pos[ci].assign(G.nseg(), -1);
+                rank[ci].assign(G.nseg(), 0);
+                std::vector<int32_t> seen(G.nseg() + 1, 0);  // [0] = soma, [b + 1] = segment b
+                for (int32_t b = 0; b < G.nseg(); ++b) rank[ci][b] = seen[G.sparent[b] + 1]++;
+            }
+            struct Key { int32_t k; int64_t ppos; size_t ci; int32_t b; };
+            std::vector<Key> keys;
+            for (int d = 1; d <= maxd; ++d) {
+                keys.clear();
+                for (size_t ci = 0; ci < cs.size(); ++ci) {
+                    const auto& G = geo[cs[ci]];
+                    for (int32_t b = 0; b < G.nseg(); ++b)
+                        if (G.sdepth[b] == d) {
+                            const int32_t p = G.sparent[b];
+                            keys.push_back({rank[ci][b], p < 0 ? int64_t(ci) : int64_t(pos[ci][p]), ci, b});
+                        }
+                }
+                std::sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
+                    return x.k != y.k ? x.k < y.k : x.ppos < y.ppos;
+                });
+                for (size_t i = 0; i < keys.size(); ++i) {
+                    pos[keys[i].ci][keys[i].b] = int32_t(i);
+                    lev[d].push_back({cs[keys[i].ci], keys[i].b, geo[cs[keys[i].ci]].slen[keys[i].b]});
+                }
+            }
+        }
         std::vector<int> next_free(std::max(S, 1), 0);
         for (int d = maxd; d >= 0; --d) {
-            std::vector<Item> items;
-            for (int32_t c : cs) {
-                if (d == 0) { items.push_back({c, -1, 1}); continue; }
-                for (int32_t b = 0; b < geo[c].nseg(); ++b)
-                    if (geo[c].sdepth[b] == d) items.push_back({c, b, geo[c].slen[b]});
-            }
+            const std::vector<Item>& items = lev[d];
             size_t s0 = 0;
             while (s0 < items.size()) {
                 int jb = 0;
