@@ -223,7 +223,8 @@ __device__ __forceinline__ void pass_down(Slot<L>& g, const double* sY, double* 
 // round has no branches and issues all of its slots' loads before any
 // arithmetic (one LDS round trip a round instead of one per slot and
 // child).  A branch's inputs are final from the round before its own (its
-// grandchildren's round going up, its grandparent's going down) and nothing
+// children's or grandchildren's round going up, its grandparent's going
+// down) and nothing
 // reads its entry before the round after its own; so the rounds before its
 // own compute values that are never read, and the rounds after it recompute
 // the same values from the same inputs and store identical bits.  An empty
@@ -285,14 +286,41 @@ __device__ __forceinline__ void round_sync() {
         __syncthreads();
 }
 
-// The upward pass of the split solve over the thread's S slots: packs with
-// at most binary branch points take two tree levels a round with every slot
-// in every round (up2_load, up2_store); other packs one round of the host's
-// schedule at a time, each slot in its own round.
+// The upward pass of the split solve over the thread's S slots.  Packs with
+// at most binary branch points run every slot in every round: in workgroups
+// of up to two waves one tree level a round (a branch adds its children's
+// contributions: two loads per slot and round), in larger workgroups, where
+// each round costs a barrier across more waves, two levels a round
+// (up2_load, up2_store: eight loads per slot and round, half the rounds).
+// Both store the same contributions bit for bit.  Other packs take one round
+// of the host's schedule at a time, each slot in its own round.
 template <int T, int S, int L>
 __device__ __forceinline__ void up_pass(const PackDesc& pk, Slot<L>& g0, Slot<L>& g1, Slot<L>& g2, const double* sF,
                                         const double* sQ, double* sC, const int32_t* s_ch) {
-    if (pk.binary) {
+    if (T <= 128 && pk.binary) {
+        for (int r = 0; r < pk.nlev; ++r) {
+            double a0 = sC[g0.c0], b0 = sC[g0.c1], a1 = 0.0, b1 = 0.0, a2 = 0.0, b2 = 0.0;
+            if constexpr (S > 1) {
+                a1 = sC[g1.c0];
+                b1 = sC[g1.c1];
+            }
+            if constexpr (S > 2) {
+                a2 = sC[g2.c0];
+                b2 = sC[g2.c1];
+            }
+            g0.cs = a0 + b0;
+            sC[g0.task] = g0.fp - g0.FQ * g0.cs;
+            if constexpr (S > 1) {
+                g1.cs = a1 + b1;
+                sC[g1.task] = g1.fp - g1.FQ * g1.cs;
+            }
+            if constexpr (S > 2) {
+                g2.cs = a2 + b2;
+                sC[g2.task] = g2.fp - g2.FQ * g2.cs;
+            }
+            round_sync<T>();
+        }
+    } else if (pk.binary) {
         for (int sr = 0; 2 * sr < pk.nlev; ++sr) {
             Up2In u0, u1, u2;
             u0 = up2_load<L>(g0, sF, sQ, sC);
