@@ -56,21 +56,36 @@ __device__ inline double opaque(double x) {
 // rates, db = e^xb + 1 for beta_h, 1 otherwise), so alpha + beta = p/q and
 // x_inf = alpha/(alpha + beta) = na db/p with p = na db + nb da, q = da db,
 // and one reciprocal of p q gives both.  e^x and e^x - 1 come from exp_pair
-// (a shorter dependency chain than the library's, within 2 ulp of it); both
-// candidate forms of alpha come from the one exp_pair of its argument, so
-// every thread runs the same straight-line code.
-__device__ inline double hh_gate_advance(int w, double v, double x, double dt) {
-    const double xa = -(v + opaque((w == 0) ? 40.0 : (w == 1) ? 65.0 : 55.0)) * opaque((w == 1) ? 0.05 : 0.1);
+// (a shorter dependency chain than the library's, within 2 ulp of it).
+// The gate's constants are chosen once (hh_gate_consts, kept in registers
+// across steps); every thread runs the same straight-line code.
+struct HHGate {
+    double oa, sa;  // alpha's argument -(v + oa) sa
+    double ob, sb;  // beta's argument -(v + ob) sb
+    double ka, kb;  // factors of alpha and beta
+    bool h;         // the h gate: alpha = ka e^xa, beta = 1/(e^xb + 1)
+};
+__device__ inline HHGate hh_gate_consts(int w) {
+    HHGate c;
+    c.oa = opaque((w == 0) ? 40.0 : (w == 1) ? 65.0 : 55.0);
+    c.sa = opaque((w == 1) ? 0.05 : 0.1);
+    c.ob = opaque((w == 1) ? 35.0 : 65.0);
+    c.sb = opaque((w == 0) ? (1.0 / 18.0) : (w == 1) ? 0.1 : (1.0 / 80.0));
+    c.ka = opaque((w == 0) ? 1.0 : (w == 1) ? 0.07 : 0.1);
+    c.kb = opaque((w == 0) ? 4.0 : 0.125);
+    c.h = w == 1;
+    return c;
+}
+__device__ inline double hh_gate_step(const HHGate& c, double v, double x, double dt) {
+    const double xa = -(v + c.oa) * c.sa;
     const ExpPair pa = exp_pair(xa);
-    const double xb = -(v + opaque((w == 1) ? 35.0 : 65.0)) *
-                      opaque((w == 0) ? (1.0 / 18.0) : (w == 1) ? 0.1 : (1.0 / 80.0));
+    const double xb = -(v + c.ob) * c.sb;
     const double eb = exp_pair(xb).e;
-    const bool h = w == 1;
     const bool tiny = 1.0 + xa == 1.0;  // exprelr's removable singularity: alpha_m = 1, alpha_n = 0.1
-    const double na = h ? 0.07 * pa.e : (tiny ? 1.0 : xa) * opaque((w == 0) ? 1.0 : 0.1);
-    const double da = (h || tiny) ? 1.0 : pa.em1;
-    const double nb = h ? 1.0 : opaque((w == 0) ? 4.0 : 0.125) * eb;
-    const double db = h ? eb + 1.0 : 1.0;
+    const double na = c.ka * (c.h ? pa.e : tiny ? 1.0 : xa);
+    const double da = (c.h || tiny) ? 1.0 : pa.em1;
+    const double nb = c.h ? 1.0 : c.kb * eb;
+    const double db = c.h ? eb + 1.0 : 1.0;
     const double p = na * db + nb * da;
     const double q = da * db;
     const double r = recip(p * q);

@@ -148,6 +148,11 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
     // the next step of the epoch with network events: steps without any
     // load nothing
     const uint32_t* enxt = eoff ? a.bk_nxt + int64_t(p) * (a.epoch_steps + 1) : nullptr;
+    // a pack with at most kSpreadHH hh instances gives each gate a thread:
+    // this thread's instance and gate, and the gate's constants
+    static_assert(3 * kSpreadHH <= T, "one gate per thread");
+    const int hq = tid / 3, hw = tid - 3 * hq;
+    const HHGate hc = hh_gate_consts(hw);
     int32_t eb = eoff ? int32_t(enxt[step0 - estart]) : INT32_MAX;
     int64_t xcur = a.pk_xcur[p];
     int64_t xstep = (xcur < pk.xe1) ? a.xe_step[xcur] : INT64_MAX;
@@ -381,14 +386,13 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
         // thread (which computes that gate's two rates and the update);
         // otherwise a thread takes a whole instance.
         if (pk.nhh <= kSpreadHH) {
-            for (int j = tid; j < 3 * pk.nhh; j += T) {
-                const int q = j / 3, w = j - 3 * q;
-                double* x = (w == 0) ? sm : (w == 1) ? sh : sn;
+            if (tid < 3 * pk.nhh) {
+                double* x = (hw == 0) ? sm : (hw == 1) ? sh : sn;
                 if (rec) {  // the gate before its update
-                    double* r = (w == 0) ? a.rec_m : (w == 1) ? a.rec_h : a.rec_n;
-                    r[int64_t(s) * a.n_hh_total + pk.hh0 + q] = x[q];
+                    double* r = (hw == 0) ? a.rec_m : (hw == 1) ? a.rec_h : a.rec_n;
+                    r[int64_t(s) * a.n_hh_total + pk.hh0 + hq] = x[hq];
                 }
-                x[q] = hh_gate_advance(w, sV[s_hhs[q]], x[q], a.dt);
+                x[hq] = hh_gate_step(hc, sV[s_hhs[hq]], x[hq], a.dt);
             }
         } else {
             for (int q = tid; q < pk.nhh; q += T) {

@@ -248,6 +248,11 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1))
         cb_nsub = 0;
     }
     const int soma = (tid < pk.ncell) ? vix(a.pc_soma[pk.cell0 + tid]) : -1;
+    // a pack with at most kSpreadHH hh instances gives each gate a thread:
+    // this thread's instance and gate, and the gate's constants
+    static_assert(3 * kSpreadHH <= T, "one gate per thread");
+    const int hq = tid / 3, hw = tid - 3 * hq;
+    const HHGate hc = hh_gate_consts(hw);
     double vold = 0.0;
 
     int myr[S];
@@ -449,10 +454,9 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1))
         // E: gates over h with the new V; threshold, the crossing time
         // interpolated within the step
         if (pk.nhh <= kSpreadHH) {
-            for (int j = tid; j < 3 * pk.nhh; j += T) {
-                const int q = j / 3, w = j - 3 * q;
-                double* x = (w == 0) ? sm : (w == 1) ? sh : sn;
-                x[q] = hh_gate_advance(w, sV[s_hhs[q]], x[q], h);
+            if (tid < 3 * pk.nhh) {
+                double* x = (hw == 0) ? sm : (hw == 1) ? sh : sn;
+                x[hq] = hh_gate_step(hc, sV[s_hhs[hq]], x[hq], h);
             }
         } else {
             for (int q = tid; q < pk.nhh; q += T) {
