@@ -91,9 +91,9 @@ __device__ __forceinline__ void full_chain(Slot<L>& g, double* t) {
         t[k] = r * g.D[k];
         acc = r;
     }
-    double x = 0.0;
+    double x = t[0];
 #pragma unroll
-    for (int k = 0; k < L; ++k) x = t[k] - g.F[k] * x;
+    for (int k = 1; k < L; ++k) x = t[k] - g.F[k] * x;
     g.yl = (g.len == L) ? x : -x;
 }
 template <int L>
