@@ -47,7 +47,8 @@ using namespace reg;
 // Refactor a branch in its registers for a step of length h.  The step-dt
 // factorisation held there gives what the new one needs, with the branch's
 // capacitances C (read from HBM, every row's load issued at once, at clamped
-// rows for the pads): u_k = F_k / D_k (F = u/d', D = 1/d'), and with dh =
+// rows for the pads): u_k = F_k / D_k (F = u/d', D = 1/d'; the quotients
+// from refined reciprocals, recip), and with dh =
 // 1/h - 1/dt and the distal neighbour's parts c = u F of the eliminated
 // diagonal at dt (c_dt) and at h (c_h),
 //   d'_h = 1/D + c_dt - c_h + C dh,   alpha_h = alpha + C dh,
@@ -66,18 +67,21 @@ __device__ __forceinline__ void var_refactor(Slot<L>& g, const VarArgs& v, const
 #pragma unroll
     for (int k = 0; k < L; ++k) cap[k] = v.cap[pk.slot0 + base + int64_t(min(k, len - 1)) * w];
     (void)ih;
+    // branch-free over the rows: a pad row (k >= len; D = 0) computes
+    // values that the selects discard
 #pragma unroll
     for (int k = L - 1; k >= 0; --k) {
-        if (k < len) {
-            const double u = g.F[k] / g.D[k];
-            const double d = 1.0 / g.D[k] + cdt - ch + cap[k] * dh;
-            const double f = u / d;
-            cdt = g.F[k] * u;
-            ch = f * u;
-            g.A[k] += cap[k] * dh;
-            g.F[k] = f;
-            g.D[k] = 1.0 / d;
-        }
+        const bool real = k < len;
+        const double id = recip(g.D[k]);  // d' at dt
+        const double u = g.F[k] * id;
+        const double d = id + cdt - ch + cap[k] * dh;
+        const double rd = recip(d);
+        const double f = u * rd;
+        cdt = real ? g.F[k] * u : cdt;
+        ch = real ? f * u : ch;
+        g.A[k] = real ? g.A[k] + cap[k] * dh : g.A[k];
+        g.F[k] = real ? f : g.F[k];
+        g.D[k] = real ? rd : g.D[k];
     }
     double q = 1.0, z = 1.0;
 #pragma unroll
