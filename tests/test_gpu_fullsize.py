@@ -137,35 +137,38 @@ def _c5_light_cone(m, c, n, pool):
 
 
 @pytest.fixture(scope="module")
-def _c5_full():
-    from paper_1901_07454_amd import arbmi
+def _c5_oracle():
+    """The network, its sampled cells and the oracle's results for them
+    through their light cones (_c5_light_cone), computed once."""
+    import multiprocessing as mp
+    import os
     n = 800
     m = gen.config5(n_steps=n)
     cv0 = oracle.cell_cv_begin(m)
     samples = [0, 65535]
-    tr, V, sp, info = _gpu(m, n, cv0[samples], block_threads=128, coef_mode=3, cells_per_pack=1)
-    print("config 5 info", info, "spikes", len(sp), flush=True)
-    assert (info["block_threads"], info["coef_mode"], info["reg_slots"], info["reg_len"]) == (128, 3, 2, 8)
-    assert info["n_packs"] == 65536
-    return m, cv0, samples, tr, V, sp
-
-
-def test_config5_full_size_light_cone(_c5_full):
-    """65536 cells x 1497 CVs, 800 steps (20 ms), in the benchmark's launch
-    shape for this network (reg_step_kernel<128, 2, 8>, one cell per
-    workgroup): sampled cells against the oracle through their light cone
-    (_c5_light_cone)."""
-    import multiprocessing as mp
-    import os
-    m, cv0, samples, tr, V, sp = _c5_full
     with mp.get_context("spawn").Pool(max(1, min(16, os.cpu_count() or 1))) as pool:
-        for k, c in enumerate(samples):
-            st, rtr, rV = _c5_light_cone(m, c, 800, pool)
-            err = max(np.max(np.abs(tr[k] - rtr)), np.max(np.abs(V[cv0[c]:cv0[c + 1]] - rV)))
-            mine = sorted(int(x) for x in sp["step"][sp["gid"] == c])
-            print(f"cell {c}: max|dV| = {err:.3e}, spikes {mine}", flush=True)
-            assert err <= TOL
-            assert mine == sorted(st)
+        ref = [_c5_light_cone(m, c, n, pool) for c in samples]
+    return m, cv0, samples, ref
+
+
+@pytest.mark.parametrize("T,S", [(128, 2), (64, 3)])
+def test_config5_full_size_light_cone(_c5_oracle, T, S):
+    """65536 cells x 1497 CVs, 800 steps (20 ms), in the two launch shapes
+    the benchmark's autotuner chooses between for this network
+    (reg_step_kernel<128, 2, 8> and <64, 3, 8>, one cell per workgroup):
+    sampled cells against the oracle through their light cones."""
+    m, cv0, samples, ref = _c5_oracle
+    tr, V, sp, info = _gpu(m, 800, cv0[samples], block_threads=T, coef_mode=3, cells_per_pack=1)
+    print("config 5 info", info, "spikes", len(sp), flush=True)
+    assert (info["block_threads"], info["coef_mode"], info["reg_slots"], info["reg_len"]) == (T, 3, S, 8)
+    assert info["n_packs"] == 65536
+    for k, c in enumerate(samples):
+        st, rtr, rV = ref[k]
+        err = max(np.max(np.abs(tr[k] - rtr)), np.max(np.abs(V[cv0[c]:cv0[c + 1]] - rV)))
+        mine = sorted(int(x) for x in sp["step"][sp["gid"] == c])
+        print(f"cell {c}: max|dV| = {err:.3e}, spikes {mine}", flush=True)
+        assert err <= TOL
+        assert mine == sorted(st)
 
 
 def test_config4_full_size_adjoint_sampled_cells():
