@@ -300,9 +300,9 @@ __global__ void __launch_bounds__(T, 1) reg_adjoint_kernel(StepArgs a, AdjArgs b
         full_chain<L>(g0, y0);
         if constexpr (S > 1) full_chain<L>(g1, y1);
         if constexpr (S > 2) full_chain<L>(g2, y2);
-        sY[g0.task] = g0.yl;
-        if constexpr (S > 1) sY[g1.task] = g1.yl;
-        if constexpr (S > 2) sY[g2.task] = g2.yl;
+        grounded_store<L>(g0, sY, sX);
+        if constexpr (S > 1) grounded_store<L>(g1, sY, sX);
+        if constexpr (S > 2) grounded_store<L>(g2, sY, sX);
         round_sync<T>();
         down_pass<T, S, L>(pk, g0, g1, g2, sY, sX);
         subst_chain<L>(g0, y0);

@@ -298,7 +298,9 @@ template <int T, int S, int L>
 __device__ __forceinline__ void up_pass(const PackDesc& pk, Slot<L>& g0, Slot<L>& g1, Slot<L>& g2, const double* sF,
                                         const double* sQ, double* sC, const int32_t* s_ch) {
     if (T <= 128 && pk.binary) {
-        for (int r = 0; r < pk.nlev; ++r) {
+        // the deepest level's branches are leaves, final from the local
+        // elimination on: the root is final after nlev - 1 rounds
+        for (int r = 0; r + 1 < pk.nlev; ++r) {
             double a0 = sC[g0.c0], b0 = sC[g0.c1], a1 = 0.0, b1 = 0.0, a2 = 0.0, b2 = 0.0;
             if constexpr (S > 1) {
                 a1 = sC[g1.c0];
@@ -321,7 +323,8 @@ __device__ __forceinline__ void up_pass(const PackDesc& pk, Slot<L>& g0, Slot<L>
             round_sync<T>();
         }
     } else if (pk.binary) {
-        for (int sr = 0; 2 * sr < pk.nlev; ++sr) {
+        // after round r every level from nlev - 3 - 2 r down is final
+        for (int sr = 0; 2 * sr + 1 < pk.nlev; ++sr) {
             Up2In u0, u1, u2;
             u0 = up2_load<L>(g0, sF, sQ, sC);
             if constexpr (S > 1) u1 = up2_load<L>(g1, sF, sQ, sC);
@@ -345,12 +348,23 @@ __device__ __forceinline__ void up_pass(const PackDesc& pk, Slot<L>& g0, Slot<L>
     }
 }
 
+// The values the downward pass starts from, stored after the full
+// elimination: every branch's distal value with a grounded parent (Y) and
+// the same as its distal voltage (X), which is final for the root (its
+// parent's voltage is zero) and rewritten by the rounds for the others.
+template <int L>
+__device__ __forceinline__ void grounded_store(const Slot<L>& g, double* sY, double* sX) {
+    sY[g.task] = g.yl;
+    sX[g.task] = g.yl + g.Z * 0.0;
+}
+
 // The downward pass: two tree levels a round, shallowest first, every slot
-// in every round (down_load, down_store).
+// in every round (down_load, down_store).  With the root final beforehand
+// (grounded_store), after round r every level up to 2 r + 2 is final.
 template <int T, int S, int L>
 __device__ __forceinline__ void down_pass(const PackDesc& pk, Slot<L>& g0, Slot<L>& g1, Slot<L>& g2, const double* sY,
                                           double* sX) {
-    for (int sr = 0; 2 * sr < pk.nlev; ++sr) {
+    for (int sr = 0; 2 * sr + 1 < pk.nlev; ++sr) {
         DownIn d0, d1, d2;
         d0 = down_load<L>(g0, sY, sX);
         if constexpr (S > 1) d1 = down_load<L>(g1, sY, sX);
