@@ -185,6 +185,8 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
         }
     }
     __syncthreads();
+    // the V entry of this thread's gate in the spread update, fixed for the launch
+    const int hv = (pk.nhh <= kSpreadHH && tid < 3 * pk.nhh) ? s_hhs[hq] : 0;
 
     for (int s = 0; s < a.nsteps; ++s) {
         const int64_t n = step0 + s;
@@ -392,7 +394,7 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
                     double* r = (hw == 0) ? a.rec_m : (hw == 1) ? a.rec_h : a.rec_n;
                     r[int64_t(s) * a.n_hh_total + pk.hh0 + hq] = x[hq];
                 }
-                x[hq] = hh_gate_step(hc, sV[s_hhs[hq]], x[hq], a.dt);
+                x[hq] = hh_gate_step(hc, sV[hv], x[hq], a.dt);
             }
         } else {
             for (int q = tid; q < pk.nhh; q += T) {

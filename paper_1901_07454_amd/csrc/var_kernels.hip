@@ -284,6 +284,8 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1))
         }
     }
     __syncthreads();
+    // the V entry of this thread's gate in the spread update, fixed for the launch
+    const int hv = (pk.nhh <= kSpreadHH && tid < 3 * pk.nhh) ? s_hhs[hq] : 0;
 
     const int64_t kend = step0 + a.nsteps;
     int64_t k = step0;
@@ -460,7 +462,7 @@ __global__ void __launch_bounds__(T, (S * L <= 8) ? 3 : (S * L <= 16 ? 2 : 1))
         if (pk.nhh <= kSpreadHH) {
             if (tid < 3 * pk.nhh) {
                 double* x = (hw == 0) ? sm : (hw == 1) ? sh : sn;
-                x[hq] = hh_gate_step(hc, sV[s_hhs[hq]], x[hq], h);
+                x[hq] = hh_gate_step(hc, sV[hv], x[hq], h);
             }
         } else {
             for (int q = tid; q < pk.nhh; q += T) {
