@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -176,9 +177,9 @@ VarArgs Sim::var_args() const {
     return v;
 }
 
-// The step kernel over every pack: one launch per class, the first on the
-// sim's stream, the others on auxiliary streams forked from and joined back
-// into it.
+// The step kernel over every pack: one launch per class, each on the stream
+// the class was given (the sim's stream or an auxiliary one forked from and
+// joined back into it; classes sharing a stream run one after the other).
 int Sim::launch_classes(const StepArgs& a0) {
     if (classes.size() <= 1) {
         StepArgs a = a0;
@@ -190,7 +191,7 @@ int Sim::launch_classes(const StepArgs& a0) {
         return ARB_OK;
     }
     HIP_TRY(hipEventRecord(fork_ev[0], st));
-    for (size_t c = 1; c < classes.size(); ++c) HIP_TRY(hipStreamWaitEvent(aux[c - 1], fork_ev[0], 0));
+    for (hipStream_t x : aux) HIP_TRY(hipStreamWaitEvent(x, fork_ev[0], 0));
     for (size_t c = 0; c < classes.size(); ++c) {
         StepArgs a = a0;
         a.pack0 = classes[c].pack0;
@@ -198,15 +199,15 @@ int Sim::launch_classes(const StepArgs& a0) {
         lc.lds_bytes = classes[c].lds;
         lc.syn_hbm = classes[c].hbm;
         if (cfg.coef_mode == 3) lc.reg_slots = classes[c].slots;
-        hipStream_t s_c = (c == 0) ? st : aux[c - 1];
+        hipStream_t s_c = (classes[c].stream == 0) ? st : aux[classes[c].stream - 1];
         if (timed)
             HIP_TRY(launch_var_step(a, var_args(), lc, classes[c].npack, s_c));
         else
             HIP_TRY(launch_step(a, lc, classes[c].npack, s_c));
     }
-    for (size_t c = 1; c < classes.size(); ++c) {
-        HIP_TRY(hipEventRecord(join_ev[c - 1], aux[c - 1]));
-        HIP_TRY(hipStreamWaitEvent(st, join_ev[c - 1], 0));
+    for (size_t k = 0; k < aux.size(); ++k) {
+        HIP_TRY(hipEventRecord(join_ev[k], aux[k]));
+        HIP_TRY(hipStreamWaitEvent(st, join_ev[k], 0));
     }
     return ARB_OK;
 }
@@ -749,7 +750,7 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
         for (int32_t k = 0; k <= np; ++k) {
             const bool end_run = (k == np) || !(key_of(k) == cur);
             if (end_run && k > start) {
-                s->classes.push_back({start, k - start, int(std::max<int64_t>(mx, 8)), cur.hbm, cur.slots});
+                s->classes.push_back({start, k - start, int(std::max<int64_t>(mx, 8)), cur.hbm, cur.slots, 0});
                 start = k;
                 mx = 0;
                 if (k < np) cur = key_of(k);
@@ -771,8 +772,29 @@ int build_sim(const ModelView& m, const arb_params& pp, const DeviceLimits& d, S
         }
         s->classes = merged;
         if (s->classes.size() == 1 && s->L.coef_mode == 3 && !s->cfg.rec) s->cfg.reg_slots = s->classes[0].slots;
+        // Classes onto at most kClassStreams streams (the device runs a
+        // process's streams on four hardware queues; two busy streams on one
+        // queue run one after the other): longest first, each onto the
+        // stream with the least work so far, a class's work taken as its
+        // packs' CV rows.
+        int n_streams = 1;
         if (s->classes.size() > 1) {
-            for (size_t c = 1; c < s->classes.size(); ++c) {
+            n_streams = int(std::min<size_t>(s->classes.size(), Sim::kClassStreams));
+            std::vector<int64_t> work(s->classes.size(), 0), load(n_streams, 0);
+            for (size_t c = 0; c < s->classes.size(); ++c)
+                for (int32_t k = s->classes[c].pack0; k < s->classes[c].pack0 + s->classes[c].npack; ++k)
+                    work[c] += L.packs[k].nslot;
+            std::vector<size_t> order(s->classes.size());
+            std::iota(order.begin(), order.end(), size_t(0));
+            std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return work[x] > work[y]; });
+            for (size_t c : order) {
+                const int at = int(std::min_element(load.begin(), load.end()) - load.begin());
+                s->classes[c].stream = at;
+                load[at] += work[c];
+            }
+        }
+        if (n_streams > 1) {
+            for (int c = 1; c < n_streams; ++c) {
                 hipStream_t x;
                 hipEvent_t e;
                 if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) {

@@ -46,13 +46,16 @@ struct Sim : arb_sim_ {
     LaunchCfg cfg{};
     // launch classes: contiguous pack ranges run as separate concurrent
     // kernels, each with the LDS its largest pack needs
+    // streams the launch classes run on at most (the sim's and auxiliary ones)
+    static constexpr int kClassStreams = 4;
     struct Class {
         int32_t pack0, npack, lds;
-        int hbm;    // some pack of the class keeps state in HBM (the kernel variant that can)
-        int slots;  // register slots its packs use (register layout), else 0
+        int hbm;     // some pack of the class keeps state in HBM (the kernel variant that can)
+        int slots;   // register slots its packs use (register layout), else 0
+        int stream;  // 0: the sim's stream, k > 0: aux[k - 1]
     };
     std::vector<Class> classes;
-    std::vector<hipStream_t> aux;       // one per class after the first
+    std::vector<hipStream_t> aux;       // the streams besides the sim's that classes run on
     std::vector<hipEvent_t> fork_ev, join_ev;
     int32_t bk_cap = 0;
     int32_t n_hist = 1;     // epochs of spike history the longest delay needs
