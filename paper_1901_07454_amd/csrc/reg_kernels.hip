@@ -286,10 +286,10 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
                 // again before the next step's events
                 for (int k = 0; k < d.nsyn; ++k) {
                     const int q = d.syn0 + k;
-                    const double gq = sg[q];
+                    const double gq = sg[q], eq = s_se[q], dq = s_sdec[q];  // loads issued together
                     if (rec) a.rec_g[int64_t(s) * a.n_syn_total + pk.syn0 + q] = gq;
-                    I += gq * (v - s_se[q]);
-                    sg[q] = gq * s_sdec[q];
+                    I += gq * (v - eq);
+                    sg[q] = gq * dq;
                 }
             } else {
                 // HBM synapses, interleaved over the threads of this group
