@@ -15,14 +15,17 @@
 // children's sum and the local substitution; rounds shallowest first passing
 // the distal V down, two tree levels a round (a branch forms its parent's V
 // from its grandparent's: x_p = Y_p + Z_p x_gp); all branches' substitution
-// with the parent's V.
+// with the parent's V.  In packs with at most binary branch points every
+// register slot takes part in every round (up_pass, down_pass).
 //
 // LDS keeps V and R (the right-hand side) per slot, in blocks of 64 slots
 // (64 V then 64 R): V-only accesses of consecutive slots are 8 bytes apart
 // and R is a fixed offset from V.  R holds beta (the step-invariant part of
 // the right-hand side) minus the point currents.
-// Between the phases of the solve, a branch keeps its intermediate values
-// in its own V entries.  Every branch has L rows in the layout; a shorter
+// Through the solve a row's values stay in its thread's registers; only
+// the per-branch scalars passed between branches go through LDS (the task
+// arrays sC, sF, sQ, with sX and sY reusing sC and sF for the downward
+// pass).  Every branch has L rows in the layout; a shorter
 // branch's spare rows hold pad CVs (alpha = beta = 1/d' = 0) that carry the
 // recurrences through unchanged (F = +1 at the first pad, -1 after it).
 // An empty register slot works on a slot no CV uses (a pad row, or one past
