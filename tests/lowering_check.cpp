@@ -35,6 +35,38 @@ void expect(bool ok, const std::string& what) {
     }
 }
 
+// The lowering's order of branches within a depth level: every parent's
+// first child in the parents' task order, then every second child, and so
+// on, each level numbered in that order (so consecutive threads of a round
+// find their children at consecutive task entries).
+bool level_order_ok(const Lowered& L) {
+    for (const PackDesc& D : L.packs) {
+        std::vector<std::vector<int32_t>> by_lev;
+        for (int32_t t = 0; t < D.ntk; ++t) {
+            const int32_t lev = L.tk_lev[D.tk0 + t];
+            if (lev < 0) return false;
+            if (size_t(lev) >= by_lev.size()) by_lev.resize(size_t(lev) + 1);
+            by_lev[size_t(lev)].push_back(t);
+        }
+        for (const std::vector<int32_t>& ts : by_lev) {
+            int32_t prev = -1;
+            for (int32_t k = 0;; ++k) {
+                bool any = false;
+                for (int32_t t : ts) {
+                    const TaskDesc& T = L.tasks[D.tk0 + t];
+                    if (T.nch <= k) continue;
+                    const int32_t c = L.ch_task[D.ch0 + T.ch0 + k];
+                    if (c <= prev) return false;
+                    prev = c;
+                    any = true;
+                }
+                if (!any) break;
+            }
+        }
+    }
+    return true;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -87,6 +119,7 @@ int main(int argc, char** argv) {
         }
         ++lowered;
         expect(verify_layout(L).empty(), "layout invariants: " + verify_layout(L));
+        expect(level_order_ok(L), "branch order within depth levels");
         recompute_coefficients(L);
 
         // state blobs as arb_get_state writes them for this lowering
