@@ -123,6 +123,26 @@ def test_edge_morphologies():
     check(m, 1200, probes=np.arange(int(gen.n_cvs(m).sum())), coef_mode=3, block_threads=128)
 
 
+@pytest.mark.parametrize("T", [64, 128, 256])
+def test_shallow_trees_in_packs_of_their_own(T):
+    """Cells of one to three depth levels, each alone in its pack, in the
+    register layout: a soma-only pack runs no tree rounds at all, one level
+    of branches one round each way, two levels the one-level upward rounds
+    (up to 128 threads) or a single two-level round (256 threads), so the
+    passes' round counts are exercised at their smallest."""
+    cells = [
+        models.bare_cell([], [], [], [], soma_mech=gen.MECH_HH | gen.MECH_PAS),   # soma only
+        models.bare_cell([-1], [4], [120.0], [1.2]),                               # one branch
+        models.bare_cell([-1, -1], [3, 8], [80.0, 200.0], [1.0, 2.0]),             # two roots
+        models.bare_cell(gen.full_binary_parents(1), [5, 2, 8], [90.0, 60.0, 150.0], [1.5, 0.8, 1.1],
+                         soma_mech=gen.MECH_HH | gen.MECH_PAS, dend_mech=gen.MECH_HH),  # two branch levels
+    ]
+    for k, d in enumerate(cells):
+        d.clamps.append((-1, 0, 20, 700, 0.25 + 0.05 * k))
+    m = gen.assemble(cells, n_steps=900)
+    check(m, 900, probes=np.arange(int(gen.n_cvs(m).sum())), coef_mode=3, block_threads=T, cells_per_pack=1)
+
+
 @pytest.mark.parametrize("coef_mode", [1, 2, 3])
 def test_clamps_on_passive_dendrites(coef_mode):
     """Clamps on dendritic CVs without channels or synapses (inside a branch,
