@@ -99,6 +99,27 @@ def test_ring_with_off_grid_events_matches_oracle(T):
     assert nsp >= 16 and ng > 16 * 1600
 
 
+@pytest.mark.parametrize("T", [64, 256])
+def test_shallow_cells_take_shortened_steps(T):
+    """A soma-only cell and a one-branch cell, each alone in its pack, with
+    synaptic events at off-grid times: the shortened steps' refactoring and
+    the tree passes at their smallest (no tree round for the soma, one for
+    the branch), voltages, spikes and step counts against the oracle."""
+    cells = [models.bare_cell([], [], [], [], soma_mech=gen.MECH_HH | gen.MECH_PAS),
+             models.bare_cell([-1], [5], [150.0], [1.3])]
+    for d in cells:
+        d.syn.append((-1, 0, 2.0, 0.0))
+    m = gen.assemble(cells, n_steps=0)
+    times = [[0.0131, 0.5006, 2.71, 2.7125, 9.9], [0.0249, 1.0001, 3.333, 7.5]]
+    ws = [[0.06, 0.02, 0.05, 0.05, 0.08], [0.09, 0.01, 0.07, 0.04]]
+    m["ev_syn"] = np.array([c for c in range(2) for _ in times[c]], np.uint32)
+    m["ev_step"] = np.zeros(len(m["ev_syn"]), np.int64)
+    m["ev_w"] = np.array([w for c in range(2) for w in ws[c]], np.float64)
+    tm = gen.timed(m, ev_t=np.array([t for c in range(2) for t in times[c]], np.float64))
+    nsp, ng = _compare(tm, [150, 500], block_threads=T, cells_per_pack=1)
+    assert nsp >= 2 and ng > 2 * 500
+
+
 def test_uneven_steps_decay_a_passive_cell_exactly():
     """The closed form the oracle is pinned to, on the GPU: zero-weight
     events at off-grid times only cut steps; each step of length h scales
