@@ -70,3 +70,41 @@ def test_generated_hh_reproduces_the_built_in_hh():
     print(f"built-in vs generated hh: max|dV| {err:.3e} mV, spikes {len(sp_a)}", flush=True)
     assert err <= 1e-9
     assert sp_a["step"].tolist() == sp_b["step"].tolist() and len(sp_a) >= 2
+
+
+def _uneven_with_mechanisms(n):
+    """Fourteen Yule-tree cells of the uneven workload (56-548 CVs, hh on a
+    quarter of the branches, 10 Hz Poisson input), with hcn on every soma
+    and kdr on every other branch, each instance with its own parameters
+    drawn from a seeded generator."""
+    cells = [3, 4, 5, 8, 11, 15, 20, 23, 33, 34, 35, 38, 0, 12]
+    m = gen.config3(cells=cells, n_steps=n)
+    rng = np.random.default_rng(1901)
+    dens = []
+    for c in range(len(cells)):
+        dens.append((c, -1, "hcn", {"gbar": float(rng.uniform(1e-4, 5e-4)), "vhalf": float(rng.uniform(-80, -65))}))
+        for b in range(0, int(m["cell_n_branch"][c]), 2):
+            dens.append((c, b, "kdr", {"gbar": float(rng.uniform(1e-3, 4e-3))}))
+    return gen.with_densities(m, dens)
+
+
+@pytest.mark.parametrize("T", [64, 128, 256])
+def test_generated_mechanisms_on_uneven_trees_match_oracle(T):
+    """Generated mechanisms in packs of several irregular trees (the
+    general tree rounds, not the binary ones), with per-instance
+    parameters: 1600 steps, soma traces, final voltages and spike steps
+    against the oracle."""
+    n = 1600
+    m = _uneven_with_mechanisms(n)
+    cv0 = oracle.cell_cv_begin(m)
+    tr, V, sp, info = _gpu(m, n, cv0[:-1], block_threads=T, coef_mode=3)
+    s = oracle.Sim(m)
+    assert s.ngen > 1000
+    rtr = s.run(n, probes=cv0[:-1])
+    err = max(np.max(np.abs(tr - rtr)), np.max(np.abs(V - s.state()["V"])))
+    g, st, _ = s.spikes()
+    print(f"T={T}: max|dV| {err:.3e} mV, spikes {len(sp)} (oracle {len(g)}), packs {info['n_packs']}", flush=True)
+    assert info["coef_mode"] == 3 and info["n_packs"] < len(cv0) - 1
+    assert err <= TOL
+    assert sorted(zip(sp["step"].tolist(), sp["gid"].tolist())) == sorted(zip(st.tolist(), g.tolist()))
+    assert len(g) >= 5
