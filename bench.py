@@ -15,6 +15,9 @@ variable time step (Sec. II: steps shortened at event times): off-grid ring
 delays U(5, 5.5) ms, kicks at U(0, 1) ms and 10 Hz Poisson input on every
 dendritic synapse at continuous times; its rate counts n_cv CV-updates per
 grid step (the shortened steps taken on top are reported beside it).
+`--mech` runs the ring's cells with generated density mechanisms (Sec.
+III-C): hcn on every soma, kdr on every dendritic branch, the generated hh on
+branch 0, each soma kicked every 10 ms.
 """
 from __future__ import annotations
 
@@ -110,7 +113,9 @@ def _oracle_chunk(args):
         s.advance_to(steps)
         dt = time.perf_counter() - t0
         return int(gen.n_cvs(m).sum()) * steps, dt
-    if cfg == 2:
+    if cfg == "2m":
+        m = gen.config2_mech(n_cells=8192, cells=cells, n_steps=steps + 1)
+    elif cfg == 2:
         m = gen.config2(n_cells=8192, cells=cells)
     elif cfg == 3:
         m = gen.config3(cells=cells)
@@ -157,8 +162,8 @@ HOST_CORES_PER_GPU = 16
 # single-thread leg.
 CPU_LEGS = {1: ((1, 4000), (1, 4000)), 2: ((8192, 4000), (64, 4000)), 3: ((4096, 8000), (16, 8000)),
             4: ((256, 2000), (64, 2000)), 5: ((65536, 800), (16, 800)), 6: ((8192, 800), (16, 800)),
-            7: ((8192, 800), (16, 800)), "2t": ((8192, 4000), (64, 4000))}
-CPU_BASE_CELLS = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536, 6: 8192, 7: 8192, "2t": 8192}
+            7: ((8192, 800), (16, 800)), "2t": ((8192, 4000), (64, 4000)), "2m": ((8192, 800), (16, 800))}
+CPU_BASE_CELLS = {1: 1, 2: 8192, 3: 4096, 4: 256, 5: 65536, 6: 8192, 7: 8192, "2t": 8192, "2m": 8192}
 # model time of the timed ring's inputs (the benchmark's steps and warm-up fit)
 VARSTEP_T_MS = 200.0
 
@@ -202,9 +207,11 @@ def cpu_baseline(cfg):
                        f"one GPU's share of the host")}
 
 
-def kernel_name(info: dict, timed: bool = False) -> str:
+def kernel_name(info: dict, timed: bool = False, generated: bool = False) -> str:
     if timed:
         return f"var_step_kernel<{info['block_threads']}, {info['reg_slots']}, {info['reg_len']}>"
+    if generated:  # the variant with generated mechanisms (state in LDS, no recording)
+        return f"reg_step_kernel<{info['block_threads']}, {info['reg_slots']}, {info['reg_len']}, false, false, true>"
     if info["coef_mode"] == 3:
         return (f"reg_step_kernel<{info['block_threads']}, {info['reg_slots']}, {info['reg_len']}, "
                 f"{'true' if info['syn_hbm'] else 'false'}>")
@@ -440,11 +447,16 @@ def main():
     ap.add_argument("--kernel", default=None, help="with --fit-traffic: the kernel the runs launched")
     ap.add_argument("--varstep", action="store_true",
                     help="the ring (config 2) with the variable time step: steps cut at off-grid event times")
+    ap.add_argument("--mech", action="store_true",
+                    help="the ring's cells (config 2) with generated density mechanisms (hcn, kdr, generated hh)")
     args = ap.parse_args()
-    if args.varstep and args.config != 2:
-        raise SystemExit("--varstep runs the ring: use it with --config 2")
+    if (args.varstep or args.mech) and args.config != 2:
+        raise SystemExit("--varstep and --mech run the ring: use them with --config 2")
+    if args.varstep and args.mech:
+        raise SystemExit("the variable time step does not run generated mechanisms")
+    leg = "2t" if args.varstep else "2m" if args.mech else args.config
     if args.fit_traffic:
-        key = "config2t" if args.varstep else f"config{args.config}"
+        key = f"config{leg}"
         rec = fit_traffic(args.fit_traffic, key, args.kernel, "var" if args.varstep else "reg", args.traffic_json)
         print(json.dumps({key: rec}))
         return
@@ -467,6 +479,14 @@ def main():
         desc = (f"{n}-cell ring with the variable time step: depth-6 binary trees x 8 CVs/branch (1017 CVs/cell), "
                 "hh soma, pas dendrites, 10 expsyn/cell, ring delays U(5, 5.5) ms, kicks at U(0, 1) ms, 10 Hz "
                 "Poisson input per dendritic synapse at continuous times")
+    elif args.mech:
+        n = args.cells or 8192
+        # kicks every 400 steps through the warm-up and the timed steps (both
+        # rounded up to whole epochs of at most 200 steps)
+        m = gen.config2_mech(n_cells=n, n_steps=args.warmup + args.steps + 400)
+        desc = (f"{n}-cell ring with generated mechanisms: depth-6 binary trees x 8 CVs/branch (1017 CVs/cell), "
+                "built-in hh soma, pas dendrites, 10 expsyn/cell, delay 5 ms; generated hcn on the soma, kdr on "
+                "every branch, hh on branch 0; every soma kicked each 10 ms")
     else:
         m, desc = make_model(args.config, args.cells, args.dry_run_ranks)
     log(f"model built in {time.perf_counter() - t0:.1f} s")
@@ -510,12 +530,18 @@ def main():
     steps_per_launch = steps / max(nlaunch, 1)
     avg_launch_s = kms / 1e3 / max(nlaunch, 1)
     flops_per_step = FLOPS_PER_CV * n_cv + FLOPS_PER_HH * info["n_hh"] + FLOPS_PER_SYN * info["n_syn"]
+    gen_instances = {}
+    if args.mech:  # each generated instance's operations, counted from its description
+        from paper_1901_07454_amd import mechgen
+        ops = {m_.name: mechgen.op_count(m_) for m_ in mechgen.load_catalogue()}
+        gen_instances = sim.mechanism_instances()
+        flops_per_step += sum(ops[k] * v for k, v in gen_instances.items())
     # steps taken per grid step of every cell (1 with the fixed step)
     taken_ratio = taken / (steps * info["n_cells"])
     tflops = flops_per_step * taken_ratio * steps_per_launch / avg_launch_s / 1e12
     model_gbps = info["bytes_per_step"] * steps_per_launch / avg_launch_s / 1e9
-    kernel = kernel_name(info, args.varstep)
-    traffic = measured_traffic(args.traffic_json, "2t" if args.varstep else args.config, kernel, steps_per_launch)
+    kernel = kernel_name(info, args.varstep, args.mech)
+    traffic = measured_traffic(args.traffic_json, leg, kernel, steps_per_launch)
     traffic_gbps = None if traffic is None else traffic / avg_launch_s / 1e9
     copy_gbps = copy_bandwidth_gbps(torch)
     # The bound: the resource the kernel comes closest to.  The fused kernel
@@ -537,7 +563,9 @@ def main():
         roof = {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": alu_frac, "traffic": traffic,
                 "basis": ("algorithmic FP64 operations per launch (7 per CV, 61 per hh instance, 4 per "
-                          "synapse, per step taken) / average launch time; peak = MI355X vector FP64")}
+                          "synapse" + (", each generated mechanism instance the count of its description"
+                                       if args.mech else "") +
+                          ", per step taken) / average launch time; peak = MI355X vector FP64")}
     roof.update({
         "kernel": kernel, "steps_per_launch": steps_per_launch, "avg_launch_ms": avg_launch_s * 1e3,
         "launches": nlaunch, "kernel_ms_total": kms,
@@ -566,14 +594,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": ("variable step: " if args.varstep else f"config {args.config}: ") + desc,
+        "config": {"workload": ("variable step: " if args.varstep else "generated mechanisms: " if args.mech
+                                else f"config {args.config}: ") + desc,
                    "cells": info["n_cells"], "cvs": n_cv,
                    "dt_ms": float(m["dt"]), "epoch_steps": K,
                    "block_threads": info["block_threads"], "coef_mode": info["coef_mode"],
                    "packs": info["n_packs"], "lds_bytes": info["lds_bytes"], "launch_classes": info["n_classes"],
                    "graph": not args.no_graph, "spikes": int(len(spikes)),
                    **({"steps_taken": int(taken), "steps_taken_per_grid_step": taken_ratio} if args.varstep else {}),
-                   **({"dry_run_ranks": args.dry_run_ranks} if args.config == 7 and args.dry_run_ranks > 1 else {})},
+                   **({"dry_run_ranks": args.dry_run_ranks} if args.config == 7 and args.dry_run_ranks > 1 else {}),
+                   **({"mechanism_instances": gen_instances} if args.mech else {})},
         "roofline": roof,
     }
     if info["n_syn"] > 0:
@@ -586,7 +616,7 @@ def main():
         if args.config == 5:
             out["grad_subset"] = grad_ratio(torch, subset=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline("2t" if args.varstep else args.config)
+        out["cpu_baseline"] = cpu_baseline(leg)
     print(json.dumps(out))
 
 

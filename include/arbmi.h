@@ -265,6 +265,13 @@ int arb_get_step_count(arb_sim s, int64_t *n_out);
 int arb_mechanism_count(void);
 int arb_mechanism_info(int32_t id, arb_mech_info *out);
 
+/* Instances of each generated mechanism in the sim (Sec. III-C: a density
+ * mechanism acts on every CV that its region covers, one instance per CV
+ * and density entry) into counts[id], id = 0 .. n - 1 (zero past the
+ * catalogue).  counts is host memory owned by the caller; ARB_EINVAL for a
+ * null argument or n < arb_mechanism_count(). */
+int arb_get_mechanism_instances(arb_sim s, int64_t *counts, int32_t n);
+
 /* Advance every cell by n_steps steps of dt (Sec. II operator splitting:
  * events due at the step start, currents at V(t), implicit Euler + Hines for
  * V(t+dt), states with the new V, threshold test; spike exchange at each

@@ -83,7 +83,7 @@ EXPORTS = ["arb_build_cells", "arb_step", "arb_get_voltages", "arb_get_spikes", 
            "arb_get_trace", "arb_set_params", "arb_grad_forward", "arb_grad_backward",
            "arb_get_state", "arb_set_state", "arb_get_info", "arb_get_kernel_time", "arb_sync",
            "arb_free", "arb_last_error", "arb_plan_layout", "arb_get_voltages_noalloc", "arb_build_cells_timed",
-           "arb_get_step_count", "arb_mechanism_count", "arb_mechanism_info"]
+           "arb_get_step_count", "arb_mechanism_count", "arb_mechanism_info", "arb_get_mechanism_instances"]
 
 _lib = None
 
@@ -109,6 +109,7 @@ def load():
             "arb_get_step_count": [P, C.POINTER(I64)],
             "arb_mechanism_count": [],
             "arb_mechanism_info": [I32, C.POINTER(arb_mech_info)],
+            "arb_get_mechanism_instances": [P, C.POINTER(I64), I32],
             "arb_step": [P, I64],
             "arb_get_voltages": [P, P, I64, C.c_int],
             "arb_get_voltages_noalloc": [P, P, I64],
@@ -458,6 +459,13 @@ class Simulation:
 
     def step_count(self) -> int:
         return arb_get_step_count(self.h)
+
+    def mechanism_instances(self) -> dict:
+        """Instances of each generated mechanism in the sim, by name."""
+        cat = mechanism_catalogue()
+        counts = (C.c_int64 * max(len(cat), 1))()
+        _check(load().arb_get_mechanism_instances(self.h, counts, len(cat)))
+        return {m["name"]: int(counts[m["id"]]) for m in cat}
 
     def refresh_info(self):
         self.info = arb_get_info(self.h)

@@ -156,11 +156,13 @@ StepArgs Sim::step_args() const {
     a.threshold = L.threshold;
     a.gen_off = d_gen_off;
     a.gen_pk = d_gen_pk;
-    a.gen_mech = d_gen_mech;
+    a.gen_row = d_gen_row;
     a.gen_slot = d_gen_slot;
     a.gen_w = d_gen_w;
+    a.gen_rmech = d_gen_rmech;
     a.gen_prm = d_gen_prm;
     a.gen_st = d_gen_st;
+    a.gen_n = int64_t(L.gen_mech.size());
     return a;
 }
 
@@ -527,7 +529,8 @@ int build_device(Sim* s) {
     if (!L.gen_mech.empty()) {
         s->d_gen_off = dupload(s, L.gen_off, rc);
         s->d_gen_pk = dupload(s, L.gen_pk, rc);
-        s->d_gen_mech = dupload(s, L.gen_mech, rc);
+        s->d_gen_row = dupload(s, L.gen_row, rc);
+        s->d_gen_rmech = dupload(s, L.gen_rmech, rc);
         s->d_gen_slot = dupload(s, L.gen_slot, rc);
         s->d_gen_w = dupload(s, L.gen_w, rc);
         s->d_gen_prm = dupload(s, L.gen_prm, rc);
@@ -949,6 +952,15 @@ int arb_mechanism_info(int32_t id, arb_mech_info* out) {
         I.defaults[k] = M.defaults[k];
     }
     *out = I;
+    return ARB_OK;
+}
+
+int arb_get_mechanism_instances(arb_sim s_, int64_t* counts, int32_t n) {
+    Sim* s = static_cast<Sim*>(s_);
+    if (!s || !counts) return fail(ARB_EINVAL, "null argument");
+    if (n < gen::kNumMechs) return fail(ARB_EINVAL, "counts smaller than the catalogue");
+    for (int32_t k = 0; k < n; ++k) counts[k] = 0;
+    for (int32_t id : s->L.gen_mech) counts[id]++;
     return ARB_OK;
 }
 

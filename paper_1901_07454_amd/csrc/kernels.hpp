@@ -89,11 +89,13 @@ struct StepArgs {
     // CV, weight (10 x area, S/cm^2 -> nS), parameters and states
     const int32_t* gen_off;    // [n_nl + 1]
     const int32_t* gen_pk;     // [n_packs + 1]
-    const int32_t* gen_mech;
+    const int32_t* gen_row;    // per instance: its parameter row
     const int32_t* gen_slot;   // pack-local slot
     const double* gen_w;
-    const double* gen_prm;     // [n_inst][kMaxParams]
-    double* gen_st;            // [n_inst][kMaxStates]
+    const int32_t* gen_rmech;  // per parameter row: catalogue index
+    const double* gen_prm;     // [n_rows][kMaxParams]
+    double* gen_st;            // [kMaxStates][n_inst], state-major
+    int64_t gen_n;             // instances (the state-major stride)
 };
 
 // Per-launch configuration chosen by the host.

@@ -227,6 +227,7 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
     const int64_t n_den = p.n_densities;
     if (n_den < 0 || (n_den > 0 && !p.densities)) { err = "densities: bad count or NULL array"; return ARB_EINVAL; }
     std::vector<std::vector<int64_t>> den_of_reg(n_den ? n_reg : 0);
+    std::map<std::vector<double>, int32_t> gen_row_of;  // (parameters, mechanism) -> parameter row
     for (int64_t q = 0; q < n_den; ++q) {
         const arb_density& D = p.densities[q];
         if (D.cell < 0 || D.cell >= n_cells || D.branch < -1 || D.branch >= cells[D.cell].n_branch) {
@@ -758,6 +759,8 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
             });
         const size_t nl_first = L.nl.size();
         if (n_den > 0) L.gen_pk.push_back(int32_t(L.gen_mech.size()));
+        // (the instances' states are gathered instance-major in gen_st0 and
+        // made state-major after the last pack)
         for (auto& sc : here) {
             const int64_t i = sc.second;
             NlDesc N{};
@@ -775,10 +778,18 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                         double prm[gen::kMaxParams] = {}, st[gen::kMaxStates] = {};
                         for (int32_t j = 0; j < M.n_params; ++j) prm[j] = (j < E.n_param) ? E.param[j] : M.defaults[j];
                         gen::steady(E.mech, L.v_init, prm, st);
+                        std::vector<double> key(prm, prm + gen::kMaxParams);
+                        key.push_back(double(E.mech));
+                        auto row = gen_row_of.find(key);
+                        if (row == gen_row_of.end()) {
+                            row = gen_row_of.emplace(key, int32_t(L.gen_rmech.size())).first;
+                            L.gen_rmech.push_back(E.mech);
+                            L.gen_prm.insert(L.gen_prm.end(), prm, prm + gen::kMaxParams);
+                        }
                         L.gen_mech.push_back(E.mech);
+                        L.gen_row.push_back(row->second);
                         L.gen_slot.push_back(N.slot);
                         L.gen_w.push_back(10.0 * L.piece_area[k]);  // S/cm^2 x um^2 -> nS
-                        L.gen_prm.insert(L.gen_prm.end(), prm, prm + gen::kMaxParams);
                         L.gen_st0.insert(L.gen_st0.end(), st, st + gen::kMaxStates);
                     }
             }
@@ -859,6 +870,11 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
     if (n_den > 0) {
         L.gen_off.push_back(int32_t(L.gen_mech.size()));
         L.gen_pk.push_back(int32_t(L.gen_mech.size()));
+        const size_t ni = L.gen_mech.size();
+        std::vector<double> sm(L.gen_st0.size());
+        for (size_t q = 0; q < ni; ++q)
+            for (int k = 0; k < gen::kMaxStates; ++k) sm[size_t(k) * ni + q] = L.gen_st0[q * gen::kMaxStates + k];
+        L.gen_st0.swap(sm);
     }
     L.n_hh_total = int64_t(L.hh_cv.size());
     L.hh_gna.assign(L.hh_cv.size(), 0.0);

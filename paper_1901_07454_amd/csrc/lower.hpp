@@ -83,11 +83,15 @@ struct Lowered {
     // region the CV covers); instances are grouped by nonlinear entry
     std::vector<int32_t> gen_off;             // [n_nl + 1] first instance of each nonlinear entry
     std::vector<int32_t> gen_pk;              // [n_packs + 1] first instance of each pack
-    std::vector<int32_t> gen_mech;            // per instance: catalogue index
+    std::vector<int32_t> gen_mech;            // per instance: catalogue index (host side only)
+    std::vector<int32_t> gen_row;             // per instance: its parameter row
     std::vector<int32_t> gen_slot;            // per instance: pack-local slot of its CV
     std::vector<double> gen_w;                // per instance: 10 x its membrane area (um^2): S/cm^2 -> nS
-    std::vector<double> gen_prm;              // [n_inst][gen::kMaxParams]
-    std::vector<double> gen_st0;              // [n_inst][gen::kMaxStates] states at rest at v_init
+    std::vector<int32_t> gen_rmech;           // per parameter row: catalogue index
+    std::vector<double> gen_prm;              // [n_rows][gen::kMaxParams], one row per distinct
+                                              // (mechanism, parameters) pair
+    std::vector<double> gen_st0;              // [gen::kMaxStates][n_inst] states at rest at v_init,
+                                              // state-major (a state of consecutive instances is contiguous)
     std::vector<int64_t> in_off;              // [n_packs + 1] first rank of each pack
     int32_t dry_run_ranks = 1;                // R: ranks the exchange emulates (1 = none)
     bool timed = false;                       // variable time step (continuous event times)

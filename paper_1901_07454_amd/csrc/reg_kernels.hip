@@ -280,9 +280,11 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
                 }
             }
             if constexpr (M) {
-                for (int q = a.gen_off[pk.nl0 + j]; q < a.gen_off[pk.nl0 + j + 1]; ++q)
-                    I += a.gen_w[q] * gen::current(a.gen_mech[q], v, a.gen_prm + int64_t(q) * gen::kMaxParams,
-                                                   a.gen_st + int64_t(q) * gen::kMaxStates);
+                for (int q = a.gen_off[pk.nl0 + j]; q < a.gen_off[pk.nl0 + j + 1]; ++q) {
+                    const int r = a.gen_row[q];  // shared parameter rows stay in cache
+                    I += a.gen_w[q] * gen::current(a.gen_rmech[r], v, a.gen_prm + int64_t(r) * gen::kMaxParams,
+                                                   a.gen_st + q, a.gen_n);
+                }
             }
             if (!syn_hbm) {
                 // the decay of phase E is applied here too: g is not read
@@ -433,9 +435,11 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
                     a.trace[int64_t(a.pr_id[pk.pr0 + j]) * a.trace_cap + col] = sV[vix(a.pr_slot[pk.pr0 + j])];
         }
         if constexpr (M) {  // generated mechanisms' states with V^{n+1}
-            for (int q = a.gen_pk[p] + tid; q < a.gen_pk[p + 1]; q += T)
-                gen::advance(a.gen_mech[q], sV[vix(a.gen_slot[q])], a.dt, a.gen_prm + int64_t(q) * gen::kMaxParams,
-                             a.gen_st + int64_t(q) * gen::kMaxStates);
+            for (int q = a.gen_pk[p] + tid; q < a.gen_pk[p + 1]; q += T) {
+                const int r = a.gen_row[q];
+                gen::advance(a.gen_rmech[r], sV[vix(a.gen_slot[q])], a.dt, a.gen_prm + int64_t(r) * gen::kMaxParams,
+                             a.gen_st + q, a.gen_n);
+            }
             __threadfence_block();  // before the next step's currents read them
         }
         if (syn_hbm) __threadfence_block();  // phase B's g stores before the next step's events

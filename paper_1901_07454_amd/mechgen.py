@@ -309,21 +309,27 @@ def load_catalogue(mech_dir: str = MECH_DIR) -> list[Mechanism]:
 
 # ------------------------------------------------------------------ emission
 
-def _gate_lines(m: Mechanism, target: str) -> list[str]:
+def _st(i: int, strided: bool) -> str:
+    """State i of the instance: contiguous (host), or state-major with the
+    instance count ss as the stride (device)."""
+    return f"st[{i} * ss]" if strided else f"st[{i}]"
+
+
+def _gate_lines(m: Mechanism, target: str, strided: bool = False) -> list[str]:
     """State updates (target 'advance') or steady states ('steady')."""
     out = []
     for g in m.gates:
-        i = m.states.index(g.state)
+        x = _st(m.states.index(g.state), strided)
         a, b = emit_expr(g.a), emit_expr(g.b)
         if g.kind == "alpha_beta":
             out.append(f"{{ const double ra = {a}, rb = {b}, rs = ra + rb, xinf = ra / rs;")
-            out.append(f"  st[{i}] = xinf + (st[{i}] - xinf) * exp(-dt * rs); }}" if target == "advance"
-                       else f"  st[{i}] = xinf; }}")
+            out.append(f"  {x} = xinf + ({x} - xinf) * exp(-dt * rs); }}" if target == "advance"
+                       else f"  {x} = xinf; }}")
         elif target == "advance":
             out.append(f"{{ const double xinf = {a}, xtau = {b};")
-            out.append(f"  st[{i}] = xinf + (st[{i}] - xinf) * exp(-dt / xtau); }}")
+            out.append(f"  {x} = xinf + ({x} - xinf) * exp(-dt / xtau); }}")
         else:
-            out.append(f"st[{i}] = {a};")
+            out.append(f"{x} = {a};")
     return out
 
 
@@ -337,7 +343,42 @@ def _used(m: Mechanism, exprs) -> set[str]:
     return need
 
 
-def _body(m: Mechanism, kind: str) -> list[str]:
+def _ops(e) -> int:
+    """FP64 operations the emitted code of an expression takes per
+    evaluation: one per arithmetic operation, transcendental or division
+    (exprelr, a quotient of an expm1, takes two), integer powers as products,
+    negations folded into the operation they feed, and constant subtrees
+    folded by the compiler."""
+    if not _names(e):
+        return 0
+    k = e[0]
+    if k == "var":
+        return 0
+    if k == "neg":
+        return _ops(e[1])
+    if k == "pow":
+        return _ops(e[1]) + e[2] - 1
+    if k == "call":
+        return _ops(e[2]) + (2 if e[1] == "exprelr" else 1)
+    return 1 + _ops(e[2]) + _ops(e[3])
+
+
+def op_count(m: Mechanism) -> int:
+    """FP64 operations one instance takes per step, counted like the
+    built-in mechanisms: the current with the rates it uses, weighted by the
+    instance's area and added to its CV's current (two more), and the state
+    update with the rates it uses (each recomputed at the new V): an
+    alpha/beta gate's exact update takes 7 besides its rates (sum,
+    quotient, exponent, exp and the update's three), an inf/tau gate's 5."""
+    def with_rates(exprs):
+        need = _used(m, exprs)
+        return sum(_ops(e) for r, e in m.rates if r in need) + sum(_ops(e) for e in exprs)
+    current = with_rates([m.current]) + 2
+    advance = with_rates([g.a for g in m.gates] + [g.b for g in m.gates])
+    return current + advance + sum(7 if g.kind == "alpha_beta" else 5 for g in m.gates)
+
+
+def _body(m: Mechanism, kind: str, strided: bool = False) -> list[str]:
     if kind == "current":
         exprs = [m.current]
     elif kind == "steady":
@@ -348,18 +389,18 @@ def _body(m: Mechanism, kind: str) -> list[str]:
     lines = [f"const double {p} = prm[{i}];" for i, (p, _) in enumerate(m.params) if p in need]
     lines += [f"const double {r} = {emit_expr(e)};" for r, e in m.rates if r in need]
     if kind == "current":
-        lines += [f"const double {s} = st[{i}];" for i, s in enumerate(m.states) if s in need]
+        lines += [f"const double {s} = {_st(i, strided)};" for i, s in enumerate(m.states) if s in need]
         lines.append(f"return {emit_expr(m.current)};")
     else:
-        lines += _gate_lines(m, kind)
+        lines += _gate_lines(m, kind, strided)
     return lines
 
 
-def _switch(cat: list[Mechanism], kind: str, indent: str) -> str:
+def _switch(cat: list[Mechanism], kind: str, indent: str, strided: bool = False) -> str:
     out = []
     for k, m in enumerate(cat):
         out.append(f"{indent}case {k}: {{  // {m.name}")
-        out += [indent + "    " + ln for ln in _body(m, kind)]
+        out += [indent + "    " + ln for ln in _body(m, kind, strided)]
         if kind != "current":
             out.append(indent + "    return;")
         out.append(indent + "}")
@@ -437,7 +478,8 @@ inline void steady(int id, double v, const double* prm, double* st) {{
 def render_device(cat: list[Mechanism]) -> str:
     return _HEADER + f"""// Device side of the generated mechanisms: each one's outward current
 // density at voltage v (S/cm^2 x mV; times 10 x the instance's area in um^2
-// it is in pA) and its state update over a step of dt at v.
+// it is in pA) and its state update over a step of dt at v.  An instance's
+// state k is st[k * ss] (states stored state-major, ss the instance count).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -448,17 +490,17 @@ namespace gen {{
 
 __device__ __forceinline__ double gen_exprelr(double x) {{ return (1.0 + x == 1.0) ? 1.0 : x / expm1(x); }}
 
-__device__ __forceinline__ double current(int id, double v, const double* prm, const double* st) {{
+__device__ __forceinline__ double current(int id, double v, const double* prm, const double* st, int64_t ss) {{
     switch (id) {{
-{_switch(cat, "current", "        ")}
+{_switch(cat, "current", "        ", True)}
         default:
             return 0.0;
     }}
 }}
 
-__device__ __forceinline__ void advance(int id, double v, double dt, const double* prm, double* st) {{
+__device__ __forceinline__ void advance(int id, double v, double dt, const double* prm, double* st, int64_t ss) {{
     switch (id) {{
-{_switch(cat, "advance", "        ")}
+{_switch(cat, "advance", "        ", True)}
         default:
             return;
     }}

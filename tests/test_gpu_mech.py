@@ -108,3 +108,18 @@ def test_generated_mechanisms_on_uneven_trees_match_oracle(T):
     assert err <= TOL
     assert sorted(zip(sp["step"].tolist(), sp["gid"].tolist())) == sorted(zip(st.tolist(), g.tolist()))
     assert len(g) >= 5
+
+
+def test_instance_counts():
+    """arb_get_mechanism_instances on three ring cells: one instance per CV
+    and density entry whose region the CV covers, a branch's region being
+    covered by its 8 CVs and by its parent's node CV, which holds its first
+    half-segment: hcn (soma) 1 per cell, hh_dsl (branch 0) 9, kdr (127
+    branches) 1143; the total is the oracle's."""
+    from paper_1901_07454_amd import arbmi
+    m = gen.config2_mech(n_cells=3, n_steps=10)
+    sim = arbmi.Simulation(m)
+    counts = sim.mechanism_instances()
+    sim.close()
+    assert counts == {"hcn": 3, "hh_dsl": 3 * 9, "kdr": 3 * 127 * 9}
+    assert sum(counts.values()) == oracle.Sim(m).ngen

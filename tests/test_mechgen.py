@@ -180,3 +180,20 @@ def test_oracle_mechanisms_agree_with_their_descriptions():
             cur = 10.0 * float(m["soma_area"][0]) * current_of(mech, v0, ref, full)
             assert abs(I[0] - cur) <= 1e-12 * max(1.0, abs(cur)), (name, v0, I[0], cur)
             assert I[1] == 0.0
+
+
+def test_operation_counts():
+    """Operations per instance and step, as the benchmark's roofline counts
+    them: the generated hh takes the built-in hh's 61 (current 14, six rates
+    26, three exact gate updates 21) plus its explicit leak term (difference,
+    product and the sum into the current: 3) and the instance weight (1);
+    kdr and hcn counted by hand from their descriptions."""
+    cat = {m.name: m for m in mechgen.load_catalogue()}
+    assert mechgen.op_count(cat["hh_dsl"]) == 61 + 3 + 1
+    # kdr: current gbar n^4 (v - ek) 6 + 2; an 5 (sum, quotient, exprelr 2,
+    # product), bn 4; the update 7
+    assert mechgen.op_count(cat["kdr"]) == 8 + 5 + 4 + 7
+    # hcn: current gbar q (v - eh) 3 + 2; qinf 5, qtau 6; the update 5
+    assert mechgen.op_count(cat["hcn"]) == 5 + 5 + 6 + 5
+    # constant subtrees are folded, negations are free, powers are products
+    assert mechgen._ops(mechgen.parse_expr("-(v + 1) * (1 / 18) + x^4")) == 2 + 3 + 1

@@ -563,20 +563,21 @@ def with_densities(m: dict, dens) -> dict:
     return out
 
 
-def config2_mech(n_cells: int = 8, n_steps: int = 2000) -> dict:
+def config2_mech(n_cells: int = 8, n_steps: int = 2000, cells=None) -> dict:
     """The ring's cells with the generated mechanisms on them: hcn on the soma
     (gbar 3e-4 S/cm^2), kdr on every dendritic branch (gbar 2e-3), and
     hh_dsl on branch 0 (gnabar 0.04, gkbar 0.012, no leak); every cell is
     kicked again on its soma synapse every 10 ms (w 0.05 uS), so that it
-    keeps firing."""
-    m = config2(n_cells=n_cells, n_steps=n_steps)
-    syn0 = np.concatenate([[0], np.cumsum(np.bincount(m["syn_cell"], minlength=n_cells))])[:-1]
+    keeps firing.  `cells` picks a subset of the n_cells ring's cells."""
+    m = config2(n_cells=n_cells, cells=cells, n_steps=n_steps)
+    nc = len(m["cell_n_branch"])
+    syn0 = np.concatenate([[0], np.cumsum(np.bincount(m["syn_cell"], minlength=nc))])[:-1]
     kick = np.arange(400, n_steps, 400, dtype=np.int64)
     m["ev_syn"] = np.concatenate([m["ev_syn"], np.repeat(syn0.astype(np.uint32), len(kick))])
-    m["ev_step"] = np.concatenate([m["ev_step"], np.tile(kick, n_cells)])
-    m["ev_w"] = np.concatenate([m["ev_w"], np.full(n_cells * len(kick), 0.05)])
+    m["ev_step"] = np.concatenate([m["ev_step"], np.tile(kick, nc)])
+    m["ev_w"] = np.concatenate([m["ev_w"], np.full(nc * len(kick), 0.05)])
     dens = []
-    for c in range(n_cells):
+    for c in range(nc):
         dens.append((c, -1, "hcn", {"gbar": 3e-4}))
         for b in range(int(m["cell_n_branch"][c])):
             dens.append((c, b, "kdr", {"gbar": 2e-3}))
