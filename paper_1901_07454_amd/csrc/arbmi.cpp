@@ -159,7 +159,6 @@ StepArgs Sim::step_args() const {
     a.gen_row = d_gen_row;
     a.gen_slot = d_gen_slot;
     a.gen_w = d_gen_w;
-    a.gen_rmech = d_gen_rmech;
     a.gen_prm = d_gen_prm;
     a.gen_st = d_gen_st;
     a.gen_n = int64_t(L.gen_mech.size());
@@ -530,7 +529,6 @@ int build_device(Sim* s) {
         s->d_gen_off = dupload(s, L.gen_off, rc);
         s->d_gen_pk = dupload(s, L.gen_pk, rc);
         s->d_gen_row = dupload(s, L.gen_row, rc);
-        s->d_gen_rmech = dupload(s, L.gen_rmech, rc);
         s->d_gen_slot = dupload(s, L.gen_slot, rc);
         s->d_gen_w = dupload(s, L.gen_w, rc);
         s->d_gen_prm = dupload(s, L.gen_prm, rc);

@@ -89,10 +89,9 @@ struct StepArgs {
     // CV, weight (10 x area, S/cm^2 -> nS), parameters and states
     const int32_t* gen_off;    // [n_nl + 1]
     const int32_t* gen_pk;     // [n_packs + 1]
-    const int32_t* gen_row;    // per instance: its parameter row
+    const int32_t* gen_row;    // per instance: parameter row | catalogue index << 24
     const int32_t* gen_slot;   // pack-local slot
     const double* gen_w;
-    const int32_t* gen_rmech;  // per parameter row: catalogue index
     const double* gen_prm;     // [n_rows][kMaxParams]
     double* gen_st;            // [kMaxStates][n_inst], state-major
     int64_t gen_n;             // instances (the state-major stride)

@@ -782,12 +782,17 @@ int lower_model(const arb_cell* cells, int32_t n_cells, const arb_branch* br, in
                         key.push_back(double(E.mech));
                         auto row = gen_row_of.find(key);
                         if (row == gen_row_of.end()) {
+                            static_assert(gen::kNumMechs <= 127, "a catalogue index fits the row word's high bits");
+                            if (L.gen_rmech.size() >= (size_t(1) << 24)) {
+                                err = "more than 2^24 distinct generated-mechanism parameter sets";
+                                return ARB_EINVAL;
+                            }
                             row = gen_row_of.emplace(key, int32_t(L.gen_rmech.size())).first;
                             L.gen_rmech.push_back(E.mech);
                             L.gen_prm.insert(L.gen_prm.end(), prm, prm + gen::kMaxParams);
                         }
                         L.gen_mech.push_back(E.mech);
-                        L.gen_row.push_back(row->second);
+                        L.gen_row.push_back(row->second | (E.mech << 24));  // the mechanism rides along
                         L.gen_slot.push_back(N.slot);
                         L.gen_w.push_back(10.0 * L.piece_area[k]);  // S/cm^2 x um^2 -> nS
                         L.gen_st0.insert(L.gen_st0.end(), st, st + gen::kMaxStates);

@@ -84,10 +84,11 @@ struct Lowered {
     std::vector<int32_t> gen_off;             // [n_nl + 1] first instance of each nonlinear entry
     std::vector<int32_t> gen_pk;              // [n_packs + 1] first instance of each pack
     std::vector<int32_t> gen_mech;            // per instance: catalogue index (host side only)
-    std::vector<int32_t> gen_row;             // per instance: its parameter row
+    std::vector<int32_t> gen_row;             // per instance: its parameter row (low 24 bits) and
+                                              // catalogue index (high bits)
     std::vector<int32_t> gen_slot;            // per instance: pack-local slot of its CV
     std::vector<double> gen_w;                // per instance: 10 x its membrane area (um^2): S/cm^2 -> nS
-    std::vector<int32_t> gen_rmech;           // per parameter row: catalogue index
+    std::vector<int32_t> gen_rmech;           // per parameter row: catalogue index (host side only)
     std::vector<double> gen_prm;              // [n_rows][gen::kMaxParams], one row per distinct
                                               // (mechanism, parameters) pair
     std::vector<double> gen_st0;              // [gen::kMaxStates][n_inst] states at rest at v_init,

@@ -281,8 +281,10 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
             }
             if constexpr (M) {
                 for (int q = a.gen_off[pk.nl0 + j]; q < a.gen_off[pk.nl0 + j + 1]; ++q) {
-                    const int r = a.gen_row[q];  // shared parameter rows stay in cache
-                    I += a.gen_w[q] * gen::current(a.gen_rmech[r], v, a.gen_prm + int64_t(r) * gen::kMaxParams,
+                    // shared parameter rows stay in cache; the mechanism
+                    // comes with the row index (one dependent load less)
+                    const int rr = a.gen_row[q], r = rr & 0xffffff;
+                    I += a.gen_w[q] * gen::current(rr >> 24, v, a.gen_prm + int64_t(r) * gen::kMaxParams,
                                                    a.gen_st + q, a.gen_n);
                 }
             }
@@ -436,8 +438,8 @@ __global__ void __launch_bounds__(T, REC ? ((S * L <= 8) ? 2 : 1) : ((S * L <= 8
         }
         if constexpr (M) {  // generated mechanisms' states with V^{n+1}
             for (int q = a.gen_pk[p] + tid; q < a.gen_pk[p + 1]; q += T) {
-                const int r = a.gen_row[q];
-                gen::advance(a.gen_rmech[r], sV[vix(a.gen_slot[q])], a.dt, a.gen_prm + int64_t(r) * gen::kMaxParams,
+                const int rr = a.gen_row[q], r = rr & 0xffffff;
+                gen::advance(rr >> 24, sV[vix(a.gen_slot[q])], a.dt, a.gen_prm + int64_t(r) * gen::kMaxParams,
                              a.gen_st + q, a.gen_n);
             }
             __threadfence_block();  // before the next step's currents read them

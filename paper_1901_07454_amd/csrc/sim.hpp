@@ -132,8 +132,7 @@ struct Sim : arb_sim_ {
     double *d_cap = nullptr, *d_gmem = nullptr, *d_sigsum = nullptr, *d_uoff = nullptr, *d_syn_tau = nullptr;
     int64_t* d_pk_steps = nullptr;
     // generated density mechanisms (StepArgs.gen_*)
-    int32_t *d_gen_off = nullptr, *d_gen_pk = nullptr, *d_gen_row = nullptr, *d_gen_slot = nullptr,
-            *d_gen_rmech = nullptr;
+    int32_t *d_gen_off = nullptr, *d_gen_pk = nullptr, *d_gen_row = nullptr, *d_gen_slot = nullptr;
     double *d_gen_w = nullptr, *d_gen_prm = nullptr, *d_gen_st = nullptr;
     VarArgs var_args() const;
     // gradients
